@@ -1,0 +1,158 @@
+"""Encode (fit) and decode of NeuralVDB's lower tree levels (oracle).
+
+Encoding trains each network on its own samples (Sec. 3.2.1, 3.3.1):
+  * voxel-value regressor: active voxels only, target v/band for a
+    narrow-band SDF (scaled into [-1,1]) and v for a fog volume (Sec. 3.2);
+  * level-0 mask classifier: every voxel slot of the existing leaves
+    ("performed within level-1's children nodes"), label = active bit;
+  * level-1 node classifier: every leaf slot of the existing level-1 nodes at
+    the leaf centre, label = child (0) / active tile (1) / inactive tile (2).
+Decoding (Sec. 3.5, offline sequential access) evaluates the networks over all
+slots: mask bit = logit > 0, node class = argmax with ties to the lowest index,
+value = y * band (SDF) or y (fog).  The error report follows the quality
+measures of Sec. 4 (IoU of the interior for level sets, RMSE for fog) plus max
+error and the classifier false positives / negatives.
+"""
+import numpy as np
+
+from . import mlp, sampler, tree as T
+
+NET_STREAM = {"regressor": sampler.STREAM_REGRESSOR, "l0": sampler.STREAM_L0, "l1": sampler.STREAM_L1}
+NET_LOSS = {"regressor": "mse", "l0": "bce", "l1": "ce"}
+
+
+def population(tr, net):
+    if net == "regressor":
+        return len(tr["values"])
+    if net == "l0":
+        return 512 * len(tr["leaf_origin"])
+    if net == "l1":
+        return 4096 * len(tr["l1_origin"])
+    raise ValueError(net)
+
+
+def net_inputs(tr, net, idx, lo, D, kind, band):
+    """Normalised coordinates and targets of samples idx of network `net`."""
+    idx = np.asarray(idx, dtype=np.int64)
+    if net == "regressor":
+        x = mlp.normalize_voxel(tr["ijk"][idx], lo, D)
+        v = tr["values"][idx]
+        t = v / band if kind == T.SDF else v
+    elif net == "l0":
+        leaf, n0 = idx >> 9, idx & 511
+        p = tr["leaf_origin"][leaf].astype(np.int64) + T.n0_to_offset(n0)
+        x = mlp.normalize_voxel(p, lo, D)
+        t = T.mask_bits(tr["leaf_mask"], leaf, n0).astype(np.float64)
+    elif net == "l1":
+        node, n1 = idx >> 12, idx & 4095
+        o = tr["l1_origin"][node].astype(np.int64) + T.n1_to_offset(n1)
+        x = mlp.normalize_leaf_slot(o, lo, D)
+        child = T.mask_bits(tr["l1_child"], node, n1)
+        active = T.mask_bits(tr["l1_active"], node, n1)
+        t = np.where(child == 1, 0, np.where(active == 1, 1, 2))
+    else:
+        raise ValueError(net)
+    return x, t
+
+
+def step_grad(theta, shapes, B, x, t, net):
+    """Loss and flat gradient of one batch."""
+    params = mlp.unflatten(theta, shapes)
+    y, cache = mlp.forward(params, mlp.encode(x, B))
+    kind = NET_LOSS[net]
+    gy = mlp.output_grad(kind, y, t)
+    return mlp.loss(kind, y, t), mlp.flatten(mlp.backward(params, cache, gy))
+
+
+def param_grad(theta, shapes, B, x, gy):
+    """Gradient of sum(gy * f(x)) with respect to the parameters (vector-Jacobian product)."""
+    params = mlp.unflatten(theta, shapes)
+    _, cache = mlp.forward(params, mlp.encode(x, B))
+    return mlp.flatten(mlp.backward(params, cache, np.asarray(gy, np.float64).reshape(len(x), -1)))
+
+
+def train(theta0, shapes, B, tr, net, lo, D, kind, band, steps, batch, seed=0, lr0=1e-3,
+          decay=0.975, interval=100, idx_batches=None, step0=0, m0=None, v0=None):
+    """Adam fit of one network.  Batch indices come from the SplitMix64 sampler
+    (stream of the network, step counted from step0) unless idx_batches is given."""
+    theta = np.array(theta0, dtype=np.float64)
+    m = np.zeros_like(theta) if m0 is None else np.array(m0, np.float64)
+    v = np.zeros_like(theta) if v0 is None else np.array(v0, np.float64)
+    pop = population(tr, net)
+    losses = []
+    for k in range(steps):
+        s = step0 + k + 1
+        if idx_batches is not None:
+            idx = idx_batches[k]
+        else:
+            idx = sampler.iid_indices(seed, NET_STREAM[net], s - 1, batch, pop)
+        x, t = net_inputs(tr, net, idx, lo, D, kind, band)
+        L, g = step_grad(theta, shapes, B, x, t, net)
+        losses.append(L)
+        theta, m, v = mlp.adam_step(theta, g, m, v, s, mlp.lr_at(s, lr0, decay, interval))
+    return theta, m, v, np.array(losses)
+
+
+def _batched_predict(theta, shapes, B, x, chunk=1 << 15):
+    params = mlp.unflatten(theta, shapes)
+    out = []
+    for i in range(0, len(x), chunk):
+        y, _ = mlp.forward(params, mlp.encode(x[i:i + chunk], B))
+        out.append(y)
+    return np.concatenate(out) if out else np.zeros((0, shapes[-1][0]))
+
+
+def decode_values(theta, shapes, B, tr, lo, D, kind, band, idx=None):
+    """Regressor decode at the true active voxels (all, or the subset idx)."""
+    idx = np.arange(len(tr["values"])) if idx is None else np.asarray(idx)
+    x = mlp.normalize_voxel(tr["ijk"][idx], lo, D)
+    y = _batched_predict(theta, shapes, B, x)[:, 0]
+    return y * band if kind == T.SDF else y
+
+
+def decode_l0(theta, shapes, B, tr, lo, D, slots=None):
+    """Level-0 classifier logits at leaf slots (all 512 L, or the subset `slots`)."""
+    slots = np.arange(population(tr, "l0")) if slots is None else np.asarray(slots)
+    x, _ = net_inputs(tr, "l0", slots, lo, D, T.SDF, 1.0)
+    return _batched_predict(theta, shapes, B, x)[:, 0]
+
+
+def decode_l1(theta, shapes, B, tr, lo, D, slots=None):
+    """Level-1 classifier logits at leaf slots of the L1 nodes."""
+    slots = np.arange(population(tr, "l1")) if slots is None else np.asarray(slots)
+    x, _ = net_inputs(tr, "l1", slots, lo, D, T.SDF, 1.0)
+    return _batched_predict(theta, shapes, B, x)
+
+
+def mask_from_logits(logits, n_leaves):
+    """Predicted leaf masks (L, 8) uint64 from slot logits in leaf-major order."""
+    bits = (np.asarray(logits).reshape(n_leaves, 512) > 0)
+    words = np.zeros((n_leaves, 8), dtype=np.uint64)
+    for n in range(512):          # bit n -> word n >> 6, position n & 63
+        words[:, n >> 6] |= bits[:, n].astype(np.uint64) << np.uint64(n & 63)
+    return words
+
+
+def l1_classes(logits):
+    """argmax over the three classes, ties resolved to the lowest index."""
+    return np.argmax(np.asarray(logits), axis=1)
+
+
+def errors(tr, vhat, kind, pred_mask=None):
+    """Error report: max |v^ - v| and RMS over the true active voxels (value
+    units), IoU of the interior {v <= 0} over the active set for level sets,
+    and level-0 mask false positives / negatives when predicted masks are given."""
+    v = tr["values"]
+    d = np.asarray(vhat, np.float64) - v
+    rep = dict(n=len(v), max_abs=float(np.max(np.abs(d))) if len(v) else 0.0,
+               rms=float(np.sqrt(np.mean(d * d))) if len(v) else 0.0)
+    if kind == T.SDF:
+        a, b = v <= 0, np.asarray(vhat) <= 0
+        union = int(np.sum(a | b))
+        rep["iou"] = float(np.sum(a & b) / union) if union else 1.0
+    if pred_mask is not None:
+        truth = tr["leaf_mask"]
+        fp = sum(bin(int(w)).count("1") for w in np.bitwise_and(pred_mask, ~truth).reshape(-1))
+        fn = sum(bin(int(w)).count("1") for w in np.bitwise_and(~pred_mask, truth).reshape(-1))
+        rep["fp"], rep["fn"] = int(fp), int(fn)
+    return rep

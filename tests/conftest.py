@@ -1,0 +1,27 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+
+
+def pytest_collection_modifyitems(config, items):
+    # GPU tests run last so that a GPU failure cannot hide the CPU results.
+    items.sort(key=lambda it: 1 if it.get_closest_marker("gpu") else 0)
+
+
+@pytest.fixture(scope="session")
+def gpu_lib():
+    """The HIP library binding; GPU tests fail loudly if it is not built."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU in this environment")
+    from paper_2208_04448_amd import nvdb
+    return nvdb

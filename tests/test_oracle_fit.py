@@ -1,0 +1,82 @@
+"""Pins of the oracle fit/decode/error path: sample construction, an Adam
+fit that lowers the loss, and the error report on known cases."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import fit as F, mlp, tree as T
+
+
+@pytest.fixture(scope="module")
+def sphere():
+    v = workloads.sphere_sdf().numpy()
+    ijk, vals = T.active_set_dense(v, (0, 0, 0), T.SDF, 3.0)
+    return T.build(ijk, vals)
+
+
+def test_net_inputs(sphere):
+    tr = sphere
+    # regressor: voxel centres and scaled targets
+    x, t = F.net_inputs(tr, "regressor", [0, 5, 43877], (0, 0, 0), 64, T.SDF, 3.0)
+    assert np.allclose(x, (tr["ijk"][[0, 5, 43877]] + 0.5) / 64)
+    assert np.allclose(t, tr["values"][[0, 5, 43877]] / 3.0)
+    assert np.all(np.abs(t) <= 1.0)
+    # level-0 slots of active voxels are labelled 1, and the labels sum to N
+    slots = np.arange(F.population(tr, "l0"))
+    _, lab = F.net_inputs(tr, "l0", slots, (0, 0, 0), 64, T.SDF, 3.0)
+    assert lab.sum() == len(tr["values"])
+    s = tr["vox_leaf"] * 512 + tr["vox_n0"]
+    assert np.all(lab[s] == 1)
+    x, _ = F.net_inputs(tr, "l0", s[:10], (0, 0, 0), 64, T.SDF, 3.0)
+    assert np.allclose(x, (tr["ijk"][:10] + 0.5) / 64)
+    # level-1 slots: one class-0 label per leaf, the rest inactive tiles
+    slots = np.arange(F.population(tr, "l1"))
+    x, c = F.net_inputs(tr, "l1", slots, (0, 0, 0), 64, T.SDF, 3.0)
+    assert (c == 0).sum() == len(tr["leaf_origin"]) and (c == 1).sum() == 0
+    assert np.allclose(x[0], [4 / 64, 4 / 64, 4 / 64])
+
+
+def test_fit_lowers_loss(sphere):
+    shapes = mlp.layer_shapes(36, 64, 3, 1)
+    th0 = workloads.init_params(36, 64, 3, 1, seed=0).astype(np.float64)
+    B = mlp.pe_matrix(6)
+    th, m, v, losses = F.train(th0, shapes, B, sphere, "regressor", (0, 0, 0), 64, T.SDF, 3.0,
+                               steps=100, batch=1024, seed=0, lr0=1e-3)
+    assert losses[-5:].mean() < 0.25 * losses[:3].mean()
+    _, _, _, lc = F.train(th0, shapes, B, sphere, "l0", (0, 0, 0), 64, T.SDF, 3.0,
+                          steps=100, batch=1024, seed=0, lr0=1e-3)
+    assert lc[-5:].mean() < 0.85 * lc[:3].mean()
+
+
+def test_train_resume_is_exact(sphere):
+    shapes = mlp.layer_shapes(36, 64, 3, 1)
+    th0 = workloads.init_params(36, 64, 3, 1, seed=1).astype(np.float64)
+    B = mlp.pe_matrix(6)
+    a = F.train(th0, shapes, B, sphere, "regressor", (0, 0, 0), 64, T.SDF, 3.0, steps=6, batch=256)
+    b1 = F.train(th0, shapes, B, sphere, "regressor", (0, 0, 0), 64, T.SDF, 3.0, steps=3, batch=256)
+    b2 = F.train(b1[0], shapes, B, sphere, "regressor", (0, 0, 0), 64, T.SDF, 3.0, steps=3, batch=256,
+                 step0=3, m0=b1[1], v0=b1[2])
+    assert np.array_equal(a[0], b2[0])
+
+
+def test_errors_known_cases(sphere):
+    tr = sphere
+    rep = F.errors(tr, tr["values"].copy(), T.SDF, pred_mask=tr["leaf_mask"].copy())
+    assert rep["max_abs"] == 0.0 and rep["rms"] == 0.0 and rep["iou"] == 1.0
+    assert rep["fp"] == 0 and rep["fn"] == 0
+    vh = tr["values"].copy(); vh[7] += 0.5; vh[9] -= 2.0
+    pm = tr["leaf_mask"].copy()
+    pm[0, 0] ^= np.uint64(0b101)    # flip two slots of leaf 0
+    rep = F.errors(tr, vh, T.SDF, pred_mask=pm)
+    assert rep["max_abs"] == 2.0
+    assert np.isclose(rep["rms"], np.sqrt((0.25 + 4.0) / len(vh)))
+    truth = [(int(tr["leaf_mask"][0, 0]) >> b) & 1 for b in (0, 2)]
+    assert rep["fp"] == truth.count(0) and rep["fn"] == truth.count(1)
+
+
+def test_mask_from_logits_and_classes():
+    logits = -np.ones(2 * 512); logits[[0, 63, 64, 511, 512 + 100]] = 1.0
+    w = F.mask_from_logits(logits, 2)
+    assert int(w[0, 0]) == 1 | (1 << 63) and int(w[0, 1]) == 1 and int(w[0, 7]) == 1 << 63
+    assert int(w[1, 1]) == 1 << 36
+    assert F.l1_classes(np.array([[1.0, 1.0, 0.0], [0.0, 2.0, 2.0], [0, 0, 3.0]])).tolist() == [0, 1, 2]

@@ -1,0 +1,146 @@
+"""Pins of the oracle tree build (Sec. 3.1 VDB, Tab. memory_cost) against
+brute force, invariants and the paper's printed byte accounting."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import tree as T
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_figures.json")))
+
+
+def brute_build(ijk):
+    """Dictionary-based reference using Python floor division (an independent route)."""
+    leaves = {}
+    for p in map(tuple, ijk):
+        lo = tuple((c // 8) * 8 for c in p)
+        n0 = ((p[0] - lo[0]) << 6) | ((p[1] - lo[1]) << 3) | (p[2] - lo[2])
+        leaves.setdefault(lo, set()).add(n0)
+
+    def key(lo):
+        l2 = tuple((c // 4096) * 4096 for c in lo)
+        n2 = (((lo[0] - l2[0]) // 128) << 10) | (((lo[1] - l2[1]) // 128) << 5) | ((lo[2] - l2[2]) // 128)
+        l1 = tuple((c // 128) * 128 for c in lo)
+        n1 = (((lo[0] - l1[0]) // 8) << 8) | (((lo[1] - l1[1]) // 8) << 4) | ((lo[2] - l1[2]) // 8)
+        return l2 + (n2, n1)
+
+    order = sorted(leaves, key=key)
+    return order, leaves
+
+
+def random_sparse(rng, n, spread):
+    pts = set()
+    centres = [rng.integers(-spread, spread, 3) for _ in range(4)]
+    while len(pts) < n:
+        c = centres[rng.integers(0, 4)]
+        pts.add(tuple(int(v) for v in c + rng.integers(-20, 20, 3)))
+    ijk = np.array(sorted(pts), dtype=np.int32)
+    rng.shuffle(ijk)
+    return ijk
+
+
+@pytest.mark.parametrize("seed,spread", [(0, 50), (1, 5000), (2, 9000)])
+def test_tree_matches_brute_force(seed, spread):
+    rng = np.random.default_rng(seed)
+    ijk = random_sparse(rng, 3000, spread)
+    vals = rng.standard_normal(len(ijk))
+    tr = T.build(ijk, vals)
+    order, leaves = brute_build(ijk)
+    assert [tuple(o) for o in tr["leaf_origin"]] == order
+    for li, lo in enumerate(order):
+        n0s = sorted(leaves[lo])
+        a, b = tr["leaf_off"][li], tr["leaf_off"][li + 1]
+        assert b - a == len(n0s)
+        got = tr["ijk"][a:b] - np.array(lo)
+        assert [((x << 6) | (y << 3) | z) for x, y, z in got] == n0s
+        bits = [n for n in range(512) if (int(tr["leaf_mask"][li, n >> 6]) >> (n & 63)) & 1]
+        assert bits == n0s
+    # values travel with their coordinates
+    lookup = {tuple(p): v for p, v in zip(ijk, vals)}
+    assert np.array_equal(tr["values"], np.array([lookup[tuple(p)] for p in tr["ijk"]]))
+
+
+def test_tree_invariants():
+    rng = np.random.default_rng(5)
+    ijk = random_sparse(rng, 5000, 6000)
+    tr = T.build(ijk, np.zeros(len(ijk)))
+    N, L = len(ijk), len(tr["leaf_origin"])
+    assert int(T.popcount64(tr["leaf_mask"]).sum()) == N
+    assert np.all(tr["leaf_origin"] % 8 == 0)
+    assert np.all(tr["l1_origin"] % 128 == 0)
+    assert np.all(tr["l2_origin"] % 4096 == 0)
+    assert np.all(np.diff(tr["leaf_off"]) > 0) and tr["leaf_off"][-1] == N
+    # (leaf, n0) <-> p is a bijection
+    p = tr["leaf_origin"][tr["vox_leaf"]].astype(np.int64) + T.n0_to_offset(tr["vox_n0"])
+    assert np.array_equal(p, tr["ijk"].astype(np.int64))
+    assert len({tuple(q) for q in p}) == N
+    # L1 child bits are exactly the existing leaves
+    assert int(T.popcount64(tr["l1_child"]).sum()) == L
+    for li in range(L):
+        node = tr["leaf_l1"][li]
+        o = tr["leaf_origin"][li] - tr["l1_origin"][node]
+        n1 = ((o[0] // 8) << 8) | ((o[1] // 8) << 4) | (o[2] // 8)
+        assert T.mask_bits(tr["l1_child"], [node], [n1])[0] == 1
+    assert int(T.popcount64(tr["l2_child"]).sum()) == len(tr["l1_origin"])
+
+
+def test_negative_coordinates_floor():
+    d = T.decompose(np.array([[-1, -8, -9], [4095, 4096, -4097]], dtype=np.int32))
+    assert d["leaf_origin"].tolist() == [[-8, -8, -16], [4088, 4096, -4104]]
+    assert d["l1_origin"].tolist() == [[-128, -128, -128], [3968, 4096, -4224]]
+    assert d["l2_origin"].tolist() == [[-4096, -4096, -4096], [0, 4096, -8192]]
+    assert d["n0"].tolist() == [(7 << 6) | (0 << 3) | 7, (7 << 6) | (0 << 3) | 7]
+
+
+def test_duplicates_rejected():
+    with pytest.raises(ValueError):
+        T.build(np.array([[1, 2, 3], [1, 2, 3]]), np.zeros(2))
+
+
+def test_sphere_active_count_two_ways():
+    """phi = |p - (32,32,32)| - 24 on [0,63]^3 with |phi| <= 3: 43,878 voxels."""
+    count = 0
+    for x in range(64):
+        for y in range(64):
+            for z in range(64):
+                r = math.sqrt((x - 32) ** 2 + (y - 32) ** 2 + (z - 32) ** 2)
+                count += abs(r - 24.0) <= 3.0
+    # second route: integer squared radii, 21^2 <= r^2 <= 27^2
+    g = np.indices((64, 64, 64)) - 32
+    r2 = (g ** 2).sum(0)
+    assert count == int(((r2 >= 21 ** 2) & (r2 <= 27 ** 2)).sum()) == 43878
+    shell = 4.0 / 3.0 * math.pi * (27 ** 3 - 21 ** 3)
+    assert abs(count - shell) / shell < 0.01
+
+
+def test_sphere_tree_shape():
+    import workloads
+    v = workloads.sphere_sdf().numpy()
+    ijk, vals = T.active_set_dense(v, (0, 0, 0), T.SDF, 3.0)
+    tr = T.build(ijk, vals)
+    assert len(vals) == 43878
+    assert len(tr["leaf_origin"]) == 257 and len(tr["l1_origin"]) == 1 and len(tr["l2_origin"]) == 1
+
+
+def test_byte_accounting_matches_paper():
+    g = GOLDEN["memory_cost"]
+    b = T.explicit_bytes(g["leaf_nodes"], g["l1_nodes"], g["l2_nodes"])
+    assert b["l2"] == g["l2_bytes"]
+    assert b["l1"] == g["l1_bytes"]
+    assert b["leaf_mask"] == g["leaf_mask_bytes"]
+    assert g["leaf_nodes"] * T.VOXELS_PER_LEAF == g["voxels"]
+    assert b["voxels"] == g["voxel_bytes"]
+    assert sum(b.values()) == g["total_bytes"]
+    # [Hash,5,4,NN(3)]: voxels replaced by 4-byte parameters
+    nn3 = b["l2"] + b["l1"] + b["leaf_mask"] + 4 * g["nn3_voxel_params"]
+    assert 4 * g["nn3_voxel_params"] == g["nn3_voxel_bytes"] and nn3 == g["nn3_total_bytes"]
+    assert round(100.0 * nn3 / g["total_bytes"], 3) == g["nn3_percent"]
+    # [Hash,5,NN(4),NN(3)]: level-0 masks become parameters plus 12-byte coordinate patches
+    assert 4 * g["nn4_l0_params"] + 12 * g["nn4_l0_patches"] == g["nn4_l0_bytes"]
+    assert 4 * g["nn4_voxel_params"] == g["nn4_voxel_bytes"]
+    total = g["l2_bytes"] + g["nn4_l1_bytes"] + g["nn4_l0_bytes"] + g["nn4_voxel_bytes"]
+    assert total == g["nn4_total_bytes"]
+    assert round(100.0 * total / g["total_bytes"], 3) == g["nn4_percent"]
