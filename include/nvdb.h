@@ -1,0 +1,225 @@
+/*
+ * libnvdb -- MI355X (gfx950) implementation of the coordinate-MLP encode/decode
+ * of NeuralVDB (Kim et al., "NeuralVDB: High-resolution Sparse Volume
+ * Representation using Hierarchical Neural Networks", arXiv 2208.04448).
+ *
+ * The calls follow the paper's problem statement: a VDB tree is built from a
+ * sparse grid (Sec. 3.1), neural networks are fitted to its lower levels
+ * ("encoding", Sec. 3.2-3.3), and the grid is reconstructed by inference
+ * ("decoding", Sec. 3.5), with the quality measures of Sec. 4.
+ *
+ * Conventions for every entry point
+ *   - Return value: NVDB_OK (0) or a negative nvdb_status; on failure
+ *     nvdb_last_error() returns a message for the calling thread.  No C++
+ *     exception and no abort crosses this boundary.
+ *   - Pointers named *_dev are device (HBM) pointers; all others are host.
+ *     The caller owns every pointer it passes; the library copies inputs it
+ *     keeps.  Output buffers are caller-allocated, sized from the *_info /
+ *     *_param_count calls.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls returning
+ *     results in host memory synchronise that stream; calls writing only
+ *     device buffers are asynchronous on it.
+ *   - Tree handles are immutable after creation and may be shared between
+ *     threads; a model handle must not be used by two threads at once.
+ */
+#ifndef NVDB_H
+#define NVDB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nvdb_status;
+enum {
+  NVDB_OK = 0,
+  NVDB_E_INVALID = -1,      /* bad argument, shape or input value                  */
+  NVDB_E_NOMEM = -2,        /* device or host allocation failed                    */
+  NVDB_E_DEVICE = -3,       /* a HIP runtime call failed                           */
+  NVDB_E_NUMERIC = -4,      /* non-finite loss during a fit                        */
+  NVDB_E_STATE = -5,        /* handle not in a state that allows the call          */
+  NVDB_E_UNSUPPORTED = -6   /* network shape or precision without a kernel         */
+};
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* nvdb_last_error(void);
+/* ABI version of this header (increments on incompatible changes). */
+int32_t nvdb_abi_version(void);
+
+typedef struct nvdb_tree nvdb_tree;
+typedef struct nvdb_model nvdb_model;
+
+/* ------------------------------------------------------------------ trees */
+/* Active-voxel rule (Sec. 3.2.1): a narrow-band level set keeps |v| <= band
+ * (closed interval), a fog volume keeps v > threshold. */
+enum { NVDB_SDF = 0, NVDB_FOG = 1 };
+typedef struct {
+  int32_t kind;             /* NVDB_SDF or NVDB_FOG */
+  float band_or_threshold;  /* SDF half-width in voxels, or fog threshold */
+} nvdb_active_rule;
+
+typedef struct {
+  int64_t n_voxels;         /* active voxels N                              */
+  int64_t n_leaves;         /* level-0 nodes L (8^3 voxels)                 */
+  int64_t n_l1;             /* level-1 nodes (16^3 leaf slots)              */
+  int64_t n_l2;             /* level-2 nodes (32^3 level-1 slots)           */
+  int32_t grid_origin[3];   /* index-space origin of the source grid        */
+  int32_t grid_dims[3];     /* extent of the source grid                    */
+  int64_t bytes_l2, bytes_l1, bytes_leaf_masks, bytes_voxels; /* Tab. memory_cost accounting */
+} nvdb_tree_info;
+
+/* Build the [Hash,5,4,3] tree (Sec. 3.1) of a dense grid resident in HBM.
+ * grid_dev: float32, dims[0]*dims[1]*dims[2] values, x-major (z fastest);
+ * voxel (i,j,k) of the grid has index-space coordinate origin + (i,j,k).
+ * Coordinates are decomposed bit-exactly: leaf origin p & ~7, slot
+ * n0 = (x&7)<<6|(y&7)<<3|(z&7); level-1 origin p & ~127, slot
+ * n1 = ((x>>3)&15)<<8|((y>>3)&15)<<4|((z>>3)&15); level-2 origin p & ~4095.
+ * Leaves are ordered by (level-2 origin x,y,z, level-1 slot, leaf slot),
+ * voxels inside a leaf by n0; leaf masks keep bit n in word n>>6 at n&63.
+ * Errors: E_INVALID for non-positive dims, a grid beyond 2^31 voxels or
+ * coordinates beyond int32, NaN/Inf among the active voxels, or an unknown
+ * rule; E_NOMEM / E_DEVICE from HIP.  The call synchronises `stream`. */
+nvdb_status nvdb_tree_build_dense(const float* grid_dev, const int32_t dims[3], const int32_t origin[3],
+                                  const nvdb_active_rule* rule, void* stream, nvdb_tree** out);
+/* Counts, bounding grid and byte accounting of a tree. */
+nvdb_status nvdb_tree_get_info(const nvdb_tree* tree, nvdb_tree_info* info);
+/* Copy the canonical arrays to host buffers (any may be NULL):
+ * leaf_origin int32[L][3], leaf_mask uint64[L][8], leaf_off uint32[L+1]
+ * (exclusive prefix of active counts), values float32[N] (leaf-major, n0
+ * ascending), l1_origin int32[n_l1][3], l1_child uint64[n_l1][64]. */
+nvdb_status nvdb_tree_export(const nvdb_tree* tree, int32_t* leaf_origin, uint64_t* leaf_mask,
+                             uint32_t* leaf_off, float* values, int32_t* l1_origin, uint64_t* l1_child);
+void nvdb_tree_free(nvdb_tree* tree);
+
+/* ----------------------------------------------------------------- models */
+/* Networks of a NeuralVDB (Sec. 3.2, 3.3.1): the voxel-value regressor
+ * (MSE, eq. mse), the level-0 active-mask classifier (binary cross-entropy)
+ * and the level-1 node classifier (three-class cross-entropy: child, active
+ * tile, inactive tile). */
+enum { NVDB_NET_REGRESSOR = 0, NVDB_NET_L0 = 1, NVDB_NET_L1 = 2, NVDB_MAX_NETS = 3 };
+/* Arithmetic of the matrix products: FP32 (fp32 MFMA), or BF16 operands with
+ * FP32 accumulation.  Master weights, moments and losses are FP32 in both. */
+enum { NVDB_FP32 = 0, NVDB_BF16 = 1 };
+
+/* An H x W MLP after the feature mapping gamma(x) = [cos 2 pi B x ; sin 2 pi B x]
+ * (eq. fm) with B of shape (n_freq, 3): K = 2 n_freq inputs, H hidden ReLU
+ * layers of width W, an identity head with n_out outputs.  Parameter count
+ * P = K W + W + (H-1)(W^2+W) + W n_out + n_out, canonical flat layout
+ * W1, b1, W2, b2, ..., W_{H+1}, b_{H+1} with each W row-major [out][in].
+ * Kernels exist for W in {64, 128}, H in {2, 3, 4}, 2 n_freq <= 128,
+ * n_out in {1, 3}. */
+typedef struct {
+  int32_t width;
+  int32_t hidden;
+  int32_t n_freq;
+  int32_t n_out;
+} nvdb_net_desc;
+
+typedef struct {
+  int32_t precision;            /* NVDB_FP32 or NVDB_BF16                                   */
+  int32_t has_net[NVDB_MAX_NETS];
+  nvdb_net_desc net[NVDB_MAX_NETS];
+  /* Normalisation box (Sec. 3.4): x = (p - domain_lo + 1/2) / domain_size for a
+   * voxel p, (o - domain_lo + 4) / domain_size for the centre of the leaf at o. */
+  int32_t domain_lo[3];
+  int32_t domain_size;
+  /* Regression targets (Sec. 3.2): v / value_scale; for a level set value_scale
+   * is the band half-width, which maps the band onto [-1, 1]; 1 for fog. */
+  float value_scale;
+} nvdb_model_desc;
+
+nvdb_status nvdb_model_create(const nvdb_model_desc* desc, nvdb_model** out);
+nvdb_status nvdb_model_param_count(const nvdb_model* model, int32_t net, int64_t* n);
+/* Parameters in the canonical flat layout, float32, host memory. */
+nvdb_status nvdb_model_set_params(nvdb_model* model, int32_t net, const float* params, int64_t n);
+nvdb_status nvdb_model_get_params(const nvdb_model* model, int32_t net, float* params, int64_t n);
+/* Feature-mapping matrix B, float32 [n_freq][3] row-major, host memory. */
+nvdb_status nvdb_model_set_encoding(nvdb_model* model, int32_t net, const float* B, int32_t n_freq);
+/* Adam state (checkpoint): first and second moments (canonical layout) and
+ * the number of steps taken. */
+nvdb_status nvdb_model_get_opt_state(const nvdb_model* model, int32_t net, float* m, float* v, int64_t n,
+                                     int64_t* step);
+nvdb_status nvdb_model_set_opt_state(nvdb_model* model, int32_t net, const float* m, const float* v,
+                                     int64_t n, int64_t step);
+void nvdb_model_free(nvdb_model* model);
+
+/* ------------------------------------------------------------------- fit */
+/* Training schedule (Sec. 3.2; Tab. hyperparameters): Adam (beta1 0.9,
+ * beta2 0.999, eps 1e-8) with lr_s = lr * lr_decay^floor((s-1)/lr_interval)
+ * for the s-th step of each network.  Samples of a step are drawn i.i.d. by
+ * the counter-based SplitMix64 sampler (stream = network id) over the
+ * network's population -- active voxels (regressor), all voxel slots of the
+ * leaves (level-0 classifier), all leaf slots of the level-1 nodes (level-1
+ * classifier) -- or, when idx_dev[net] is given, taken in order from that
+ * device array of idx_count[net] population indices, `batch` per step with a
+ * shorter final step (one pass = one epoch).  The loss of a step is the mean
+ * over its samples. */
+typedef struct {
+  int32_t steps;                 /* steps to run (per trained network)                   */
+  int32_t batch;                 /* samples per step, 1 .. 2^24                          */
+  uint64_t seed;
+  float lr, lr_decay;
+  int32_t lr_interval;
+  int32_t nets_mask;             /* bit n trains network n                               */
+  const uint32_t* idx_dev[NVDB_MAX_NETS];  /* optional explicit sample order             */
+  int64_t idx_count[NVDB_MAX_NETS];
+} nvdb_fit_desc;
+
+/* Run `steps` steps continuing from the model's step counters.  loss_host, if
+ * not NULL, receives float[NVDB_MAX_NETS][steps] batch losses (untrained
+ * networks left untouched); the call then synchronises `stream`.
+ * Errors: E_INVALID (bad schedule, empty population), E_STATE (parameters or
+ * encoding not set), E_NUMERIC (non-finite loss; checked when losses are
+ * returned). */
+nvdb_status nvdb_fit(nvdb_model* model, const nvdb_tree* tree, const nvdb_fit_desc* fit, float* loss_host,
+                     void* stream);
+
+/* ---------------------------------------------------------------- decode */
+/* Offline sequential decode (Sec. 3.5) over the tree's topology:
+ * values_dev (float32[N], leaf-major) receives the regressor output at every
+ * active voxel scaled back to value units (y * value_scale); pred_mask_dev
+ * (uint64[L][8], may be NULL) the level-0 classifier's masks, bit set iff the
+ * logit is > 0.  Asynchronous on `stream`. */
+nvdb_status nvdb_decode(const nvdb_model* model, const nvdb_tree* tree, float* values_dev, uint64_t* pred_mask_dev,
+                        void* stream);
+/* Level-1 classifier over every leaf slot of the tree's level-1 nodes
+ * (4096 per node, leaf centres): classes_dev uint8[n_l1][4096], class = argmax
+ * of the three logits (0 child, 1 active tile, 2 inactive tile), ties to the
+ * lowest index.  Asynchronous. */
+nvdb_status nvdb_decode_l1(const nvdb_model* model, const nvdb_tree* tree, uint8_t* classes_dev, void* stream);
+
+/* Error report (Sec. 4): max |v^ - v| and RMS over the true active voxels in
+ * value units; IoU of the interiors {v <= 0} over the active set (level sets);
+ * level-0 false positives / negatives against the true masks when
+ * pred_mask_dev is given.  Synchronises `stream`. */
+typedef struct {
+  int64_t n;
+  double max_abs;
+  double rms;
+  double iou;
+  int64_t fp, fn;
+} nvdb_error_report;
+nvdb_status nvdb_errors(const nvdb_tree* tree, const float* values_dev, const uint64_t* pred_mask_dev,
+                        nvdb_error_report* out, void* stream);
+
+/* ------------------------------------------------- device-pointer calls */
+/* Used by the autograd binding; no allocation beyond the model's workspace,
+ * no synchronisation.
+ * nvdb_forward_dev: y_dev[n][n_out] = f(x) for normalised coordinates
+ *   x_dev float32[n][3].
+ * nvdb_backward_dev: grad_dev[P] (canonical layout) = sum_i gy_dev[i] . df(x_i)/dtheta,
+ *   recomputing the forward activations inside the fused kernel.
+ * nvdb_sample_indices_dev: the sampler's indices idx_dev[j] = floor(h * n_pop / 2^64),
+ *   h = SplitMix64 hash of (seed, stream_id, step, j), j < batch. */
+nvdb_status nvdb_forward_dev(const nvdb_model* model, int32_t net, const float* x_dev, int64_t n, float* y_dev,
+                             void* stream);
+nvdb_status nvdb_backward_dev(nvdb_model* model, int32_t net, const float* x_dev, const float* gy_dev, int64_t n,
+                              float* grad_dev, void* stream);
+nvdb_status nvdb_sample_indices_dev(uint64_t seed, int32_t stream_id, int64_t step, int64_t n_pop, int64_t batch,
+                                    uint32_t* idx_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NVDB_H */

@@ -1,0 +1,592 @@
+// C-ABI of libnvdb: argument checking, object lifetime and launch sequencing.
+// The arithmetic lives in mlp.hip (networks) and tree.hip (tree build, errors).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "nvdb_internal.h"
+
+namespace nvdb {
+
+constexpr int MAX_G = 256;        // work-groups (partial gradient rows) per network
+constexpr int TRAIN_TILE = 128;   // samples per work-group iteration
+
+struct Net {
+  bool present = false;
+  nvdb_net_desc d{};
+  NetShape s{};
+  KernelSet ks{};
+  int prec = NVDB_BF16;
+  DevBuf<float> theta, m, v, grad;
+  DevBuf<float> partial, loss_partial, losses;
+  DevBuf<char> wrow, wcol, w1frag;
+  DevBuf<float> bias, whead, bhead, benc;
+  int64_t step = 0;
+  bool params_set = false, enc_set = false;
+};
+
+}  // namespace nvdb
+
+struct nvdb_tree : nvdb::Tree {};
+struct nvdb_model {
+  nvdb_model_desc d{};
+  nvdb::Net nets[NVDB_MAX_NETS];
+};
+
+using namespace nvdb;
+
+static thread_local std::string g_err;
+
+template <class F>
+static nvdb_status guarded(F&& f) {
+  try {
+    f();
+    g_err.clear();
+    return NVDB_OK;
+  } catch (const Error& e) {
+    g_err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return NVDB_E_NOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return NVDB_E_INVALID;
+  } catch (...) {
+    g_err = "unknown error";
+    return NVDB_E_INVALID;
+  }
+}
+
+static TreeView tree_view(const Tree* t) {
+  TreeView v{};
+  if (!t) return v;
+  v.leaf_o = t->leaf_o.p;
+  v.leaf_mask = t->leaf_mask.p;
+  v.vox_key = t->vox_key.p;
+  v.values = t->values.p;
+  v.l1_o = t->l1_o.p;
+  v.l1_child = t->l1_child.p;
+  v.l1_active = t->l1_active.p;
+  return v;
+}
+
+static NetView net_view(const Net& n) {
+  NetView v{};
+  v.s = n.s;
+  v.wrow = n.wrow.p;
+  v.wcol = n.wcol.p;
+  v.w1frag = n.w1frag.p;
+  v.bias = n.bias.p;
+  v.whead = n.whead.p;
+  v.bhead = n.bhead.p;
+  v.benc = n.benc.p;
+  v.nfreq = n.d.n_freq;
+  return v;
+}
+
+static AdamNet adam_view(Net& n) {
+  AdamNet a{};
+  a.s = n.s;
+  a.theta = n.theta.p;
+  a.m = n.m.p;
+  a.v = n.v.p;
+  a.prec = n.prec;
+  a.wrow = n.wrow.p;
+  a.wcol = n.wcol.p;
+  a.w1frag = n.w1frag.p;
+  a.bias = n.bias.p;
+  a.whead = n.whead.p;
+  a.bhead = n.bhead.p;
+  return a;
+}
+
+static void base_spec(const nvdb_model* m, SampleSpec* sp) {
+  std::memset(sp, 0, sizeof(*sp));
+  for (int d = 0; d < 3; ++d) sp->lo[d] = m->d.domain_lo[d];
+  sp->inv_d = 1.f / (float)m->d.domain_size;
+  sp->tscale = 1.f / m->d.value_scale;
+}
+
+static Net& net_of(nvdb_model* m, int32_t net) {
+  NVDB_REQUIRE(m != nullptr, NVDB_E_INVALID, "model is null");
+  NVDB_REQUIRE(net >= 0 && net < NVDB_MAX_NETS && m->nets[net].present, NVDB_E_INVALID, "network not in model");
+  return m->nets[net];
+}
+static const Net& net_of(const nvdb_model* m, int32_t net) { return net_of(const_cast<nvdb_model*>(m), net); }
+
+static void ensure_partials(Net& n, int G) {
+  n.partial.ensure((size_t)G * n.s.nparams());
+  n.loss_partial.ensure(G);
+}
+
+extern "C" {
+
+const char* nvdb_last_error(void) { return g_err.c_str(); }
+int32_t nvdb_abi_version(void) { return 1; }
+
+// ------------------------------------------------------------------ trees
+nvdb_status nvdb_tree_build_dense(const float* grid_dev, const int32_t dims[3], const int32_t origin[3],
+                                  const nvdb_active_rule* rule, void* stream, nvdb_tree** out) {
+  return guarded([&] {
+    NVDB_REQUIRE(out && dims && origin && rule, NVDB_E_INVALID, "null argument");
+    *out = nullptr;
+    Tree* t = build_tree_dense(grid_dev, dims, origin, *rule, (hipStream_t)stream);
+    *out = static_cast<nvdb_tree*>(t);
+  });
+}
+
+nvdb_status nvdb_tree_get_info(const nvdb_tree* t, nvdb_tree_info* info) {
+  return guarded([&] {
+    NVDB_REQUIRE(t && info, NVDB_E_INVALID, "null argument");
+    std::memset(info, 0, sizeof(*info));
+    info->n_voxels = t->n_vox;
+    info->n_leaves = t->n_leaf;
+    info->n_l1 = t->n_l1;
+    info->n_l2 = t->n_l2;
+    for (int d = 0; d < 3; ++d) {
+      info->grid_origin[d] = t->origin[d];
+      info->grid_dims[d] = t->dims[d];
+    }
+    // Tab. memory_cost accounting of the explicit tree
+    info->bytes_l2 = t->n_l2 * (2 * (32768 / 8) + 32768 * 1 + 12);
+    info->bytes_l1 = t->n_l1 * (2 * (4096 / 8) + 4096 * 4 + 12);
+    info->bytes_leaf_masks = t->n_leaf * (512 / 8 + 12);
+    info->bytes_voxels = t->n_leaf * 512 * 4;
+  });
+}
+
+nvdb_status nvdb_tree_export(const nvdb_tree* t, int32_t* leaf_origin, uint64_t* leaf_mask, uint32_t* leaf_off,
+                             float* values, int32_t* l1_origin, uint64_t* l1_child) {
+  return guarded([&] {
+    NVDB_REQUIRE(t, NVDB_E_INVALID, "null tree");
+    if (leaf_origin && t->n_leaf) {
+      std::vector<int4> o(t->n_leaf);
+      NVDB_HIP(hipMemcpy(o.data(), t->leaf_o.p, t->n_leaf * sizeof(int4), hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < t->n_leaf; ++i) {
+        leaf_origin[3 * i] = o[i].x;
+        leaf_origin[3 * i + 1] = o[i].y;
+        leaf_origin[3 * i + 2] = o[i].z;
+      }
+    }
+    if (leaf_mask && t->n_leaf)
+      NVDB_HIP(hipMemcpy(leaf_mask, t->leaf_mask.p, t->n_leaf * 8 * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    if (leaf_off) NVDB_HIP(hipMemcpy(leaf_off, t->leaf_off.p, (t->n_leaf + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (values && t->n_vox) NVDB_HIP(hipMemcpy(values, t->values.p, t->n_vox * sizeof(float), hipMemcpyDeviceToHost));
+    if (l1_origin && t->n_l1) {
+      std::vector<int4> o(t->n_l1);
+      NVDB_HIP(hipMemcpy(o.data(), t->l1_o.p, t->n_l1 * sizeof(int4), hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < t->n_l1; ++i) {
+        l1_origin[3 * i] = o[i].x;
+        l1_origin[3 * i + 1] = o[i].y;
+        l1_origin[3 * i + 2] = o[i].z;
+      }
+    }
+    if (l1_child && t->n_l1)
+      NVDB_HIP(hipMemcpy(l1_child, t->l1_child.p, t->n_l1 * 64 * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  });
+}
+
+void nvdb_tree_free(nvdb_tree* t) { delete t; }
+
+// ------------------------------------------------------------------ models
+nvdb_status nvdb_model_create(const nvdb_model_desc* desc, nvdb_model** out) {
+  return guarded([&] {
+    NVDB_REQUIRE(desc && out, NVDB_E_INVALID, "null argument");
+    *out = nullptr;
+    NVDB_REQUIRE(desc->precision == NVDB_FP32 || desc->precision == NVDB_BF16, NVDB_E_INVALID, "unknown precision");
+    NVDB_REQUIRE(desc->domain_size > 0, NVDB_E_INVALID, "domain_size must be positive");
+    NVDB_REQUIRE(std::isfinite(desc->value_scale) && desc->value_scale > 0.f, NVDB_E_INVALID,
+                 "value_scale must be positive");
+    nvdb_model* m = new nvdb_model();
+    try {
+      m->d = *desc;
+      bool any = false;
+      for (int k = 0; k < NVDB_MAX_NETS; ++k) {
+        if (!desc->has_net[k]) continue;
+        any = true;
+        Net& n = m->nets[k];
+        const nvdb_net_desc& d = desc->net[k];
+        NVDB_REQUIRE(d.n_freq > 0 && 2 * d.n_freq <= 128, NVDB_E_UNSUPPORTED, "n_freq must be in 1..64");
+        NVDB_REQUIRE(d.n_out == 1 || d.n_out == 3, NVDB_E_UNSUPPORTED, "n_out must be 1 or 3");
+        NVDB_REQUIRE(k != NVDB_NET_L1 || d.n_out == 3, NVDB_E_INVALID, "the level-1 classifier has 3 outputs");
+        NVDB_REQUIRE(k == NVDB_NET_L1 || d.n_out == 1, NVDB_E_INVALID, "regressor and level-0 classifier have 1 output");
+        n.present = true;
+        n.d = d;
+        n.prec = desc->precision;
+        n.s.K = 2 * d.n_freq;
+        n.s.KP = std::max(64, ((n.s.K + 31) / 32) * 32);
+        n.s.W = d.width;
+        n.s.H = d.hidden;
+        n.s.C = d.n_out;
+        NVDB_REQUIRE(find_kernels(n.prec, d.width, d.hidden, n.s.KP, d.n_out, &n.ks), NVDB_E_UNSUPPORTED,
+                     "no kernel for this network shape (width " + std::to_string(d.width) + ", hidden " +
+                         std::to_string(d.hidden) + ", inputs " + std::to_string(n.s.KP) + ", outputs " +
+                         std::to_string(d.n_out) + ")");
+        const int64_t P = n.s.nparams();
+        n.theta.alloc(P);
+        n.m.alloc(P);
+        n.v.alloc(P);
+        n.grad.alloc(P);
+        NVDB_HIP(hipMemset(n.m.p, 0, P * 4));
+        NVDB_HIP(hipMemset(n.v.p, 0, P * 4));
+        const int W = n.s.W, H = n.s.H, KP = n.s.KP;
+        if (n.prec == NVDB_BF16) {
+          n.wrow.alloc((size_t)H * W * ROW_ELEMS * 2);
+          n.w1frag.alloc((size_t)W * KP * 2);
+          NVDB_HIP(hipMemset(n.wrow.p, 0, n.wrow.n));
+          NVDB_HIP(hipMemset(n.w1frag.p, 0, n.w1frag.n));
+        } else {
+          const size_t elems = (size_t)KP * W + (size_t)(H - 1) * W * W;
+          n.wrow.alloc(elems * 4);
+          n.wcol.alloc(elems * 4);
+          NVDB_HIP(hipMemset(n.wrow.p, 0, n.wrow.n));
+          NVDB_HIP(hipMemset(n.wcol.p, 0, n.wcol.n));
+        }
+        n.bias.alloc((size_t)H * W);
+        n.whead.alloc((size_t)n.s.C * W);
+        n.bhead.alloc(4);
+        n.benc.alloc((size_t)3 * (KP / 2));
+        NVDB_HIP(hipMemset(n.bhead.p, 0, 16));
+        NVDB_HIP(hipMemset(n.benc.p, 0, n.benc.n * 4));
+      }
+      NVDB_REQUIRE(any, NVDB_E_INVALID, "model has no networks");
+    } catch (...) {
+      delete m;
+      throw;
+    }
+    *out = m;
+  });
+}
+
+nvdb_status nvdb_model_param_count(const nvdb_model* m, int32_t net, int64_t* n) {
+  return guarded([&] {
+    NVDB_REQUIRE(n, NVDB_E_INVALID, "null argument");
+    *n = net_of(m, net).s.nparams();
+  });
+}
+
+nvdb_status nvdb_model_set_params(nvdb_model* m, int32_t net, const float* params, int64_t n) {
+  return guarded([&] {
+    Net& N = net_of(m, net);
+    NVDB_REQUIRE(params && n == N.s.nparams(), NVDB_E_INVALID, "parameter count mismatch");
+    for (int64_t i = 0; i < n; ++i) NVDB_REQUIRE(std::isfinite(params[i]), NVDB_E_INVALID, "non-finite parameter");
+    NVDB_HIP(hipMemcpy(N.theta.p, params, n * 4, hipMemcpyHostToDevice));
+    launch_write_shadow(adam_view(N), nullptr);
+    NVDB_HIP(hipDeviceSynchronize());
+    N.params_set = true;
+  });
+}
+
+nvdb_status nvdb_model_get_params(const nvdb_model* m, int32_t net, float* params, int64_t n) {
+  return guarded([&] {
+    const Net& N = net_of(m, net);
+    NVDB_REQUIRE(params && n == N.s.nparams(), NVDB_E_INVALID, "parameter count mismatch");
+    NVDB_HIP(hipDeviceSynchronize());
+    NVDB_HIP(hipMemcpy(params, N.theta.p, n * 4, hipMemcpyDeviceToHost));
+  });
+}
+
+nvdb_status nvdb_model_set_encoding(nvdb_model* m, int32_t net, const float* B, int32_t n_freq) {
+  return guarded([&] {
+    Net& N = net_of(m, net);
+    NVDB_REQUIRE(B && n_freq == N.d.n_freq, NVDB_E_INVALID, "n_freq mismatch");
+    std::vector<float> h((size_t)3 * (N.s.KP / 2), 0.f);
+    for (int i = 0; i < 3 * n_freq; ++i) {
+      NVDB_REQUIRE(std::isfinite(B[i]), NVDB_E_INVALID, "non-finite encoding matrix");
+      h[i] = B[i];
+    }
+    NVDB_HIP(hipMemcpy(N.benc.p, h.data(), h.size() * 4, hipMemcpyHostToDevice));
+    N.enc_set = true;
+  });
+}
+
+nvdb_status nvdb_model_get_opt_state(const nvdb_model* m, int32_t net, float* mm, float* vv, int64_t n,
+                                     int64_t* step) {
+  return guarded([&] {
+    const Net& N = net_of(m, net);
+    NVDB_REQUIRE(n == N.s.nparams(), NVDB_E_INVALID, "parameter count mismatch");
+    NVDB_HIP(hipDeviceSynchronize());
+    if (mm) NVDB_HIP(hipMemcpy(mm, N.m.p, n * 4, hipMemcpyDeviceToHost));
+    if (vv) NVDB_HIP(hipMemcpy(vv, N.v.p, n * 4, hipMemcpyDeviceToHost));
+    if (step) *step = N.step;
+  });
+}
+
+nvdb_status nvdb_model_set_opt_state(nvdb_model* m, int32_t net, const float* mm, const float* vv, int64_t n,
+                                     int64_t step) {
+  return guarded([&] {
+    Net& N = net_of(m, net);
+    NVDB_REQUIRE(mm && vv && n == N.s.nparams() && step >= 0, NVDB_E_INVALID, "bad optimiser state");
+    NVDB_HIP(hipMemcpy(N.m.p, mm, n * 4, hipMemcpyHostToDevice));
+    NVDB_HIP(hipMemcpy(N.v.p, vv, n * 4, hipMemcpyHostToDevice));
+    N.step = step;
+  });
+}
+
+void nvdb_model_free(nvdb_model* m) { delete m; }
+
+// ------------------------------------------------------------------ fit
+static int population_src(int net, const Tree* t, int64_t* pop) {
+  if (net == NVDB_NET_REGRESSOR) {
+    *pop = t->n_vox;
+    return SRC_VOXELS;
+  }
+  if (net == NVDB_NET_L0) {
+    *pop = 512 * t->n_leaf;
+    return SRC_LEAF_SLOTS;
+  }
+  *pop = 4096 * t->n_l1;
+  return SRC_L1_SLOTS;
+}
+
+nvdb_status nvdb_fit(nvdb_model* m, const nvdb_tree* tree, const nvdb_fit_desc* fit, float* loss_host, void* stream) {
+  return guarded([&] {
+    NVDB_REQUIRE(m && tree && fit, NVDB_E_INVALID, "null argument");
+    NVDB_REQUIRE(fit->steps >= 0 && fit->batch >= 1 && fit->batch <= (1 << 24), NVDB_E_INVALID, "bad steps/batch");
+    NVDB_REQUIRE(std::isfinite(fit->lr) && fit->lr >= 0.f && std::isfinite(fit->lr_decay) && fit->lr_decay > 0.f &&
+                     fit->lr_interval >= 1,
+                 NVDB_E_INVALID, "bad learning-rate schedule");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int> nets;
+    for (int k = 0; k < NVDB_MAX_NETS; ++k) {
+      if (!(fit->nets_mask & (1 << k))) continue;
+      Net& N = net_of(m, k);
+      NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "parameters or encoding not set");
+      int64_t pop;
+      population_src(k, tree, &pop);
+      NVDB_REQUIRE(pop > 0 && pop < (1ll << 32), NVDB_E_INVALID, "empty or oversized population");
+      if (fit->idx_dev[k]) {
+        NVDB_REQUIRE(fit->idx_count[k] > (int64_t)(fit->steps - 1) * fit->batch, NVDB_E_INVALID,
+                     "explicit index list shorter than the schedule");
+      }
+      nets.push_back(k);
+    }
+    NVDB_REQUIRE(!nets.empty(), NVDB_E_INVALID, "no network selected");
+    const TreeView tv = tree_view(tree);
+    for (int k : nets) m->nets[k].losses.ensure(std::max(fit->steps, 1));
+
+    // group networks that share a kernel into one launch
+    std::vector<std::vector<int>> groups;
+    for (int k : nets) {
+      bool put = false;
+      for (auto& g : groups)
+        if (m->nets[g[0]].ks.train == m->nets[k].ks.train) {
+          g.push_back(k);
+          put = true;
+        }
+      if (!put) groups.push_back({k});
+    }
+
+    for (int step = 0; step < fit->steps; ++step) {
+      AdamLaunch AL{};
+      int na = 0;
+      int64_t maxP = 0;
+      for (auto& grp : groups) {
+        TrainLaunch L{};
+        L.tree = tv;
+        int G = 1;
+        int slot = 0;
+        for (int k : grp) {
+          Net& N = m->nets[k];
+          TrainNet& tn = L.nets[slot++];
+          tn.net = net_view(N);
+          base_spec(m, &tn.spec);
+          int64_t pop;
+          tn.spec.src = population_src(k, tree, &pop);
+          tn.spec.loss = k == NVDB_NET_REGRESSOR ? LOSS_MSE : (k == NVDB_NET_L0 ? LOSS_BCE : LOSS_CE);
+          tn.spec.npop = (uint32_t)pop;
+          int64_t n = fit->batch;
+          if (fit->idx_dev[k]) {
+            const int64_t off = (int64_t)step * fit->batch;
+            n = std::min<int64_t>(fit->batch, fit->idx_count[k] - off);
+            tn.spec.idx = fit->idx_dev[k] + off;
+          } else {
+            tn.spec.step_seed = step_seed(fit->seed, k, N.step);
+          }
+          tn.spec.n = n;
+          tn.spec.inv_n = 1.f / (float)n;
+          G = std::max<int>(G, (int)std::min<int64_t>(MAX_G, (n + TRAIN_TILE - 1) / TRAIN_TILE));
+        }
+        slot = 0;
+        for (int k : grp) {
+          Net& N = m->nets[k];
+          ensure_partials(N, G);
+          TrainNet& tn = L.nets[slot++];
+          tn.partial = N.partial.p;
+          tn.loss_partial = N.loss_partial.p;
+          if (N.ks.train_needs_zeroed_partial)
+            NVDB_HIP(hipMemsetAsync(N.partial.p, 0, (size_t)G * N.s.nparams() * 4, st));
+          // optimiser step for this network
+          const int64_t s = N.step + 1;
+          AdamNet a = adam_view(N);
+          a.partial = N.partial.p;
+          a.loss_partial = N.loss_partial.p;
+          a.G = G;
+          a.loss_out = N.losses.p + step;
+          a.loss_scale = tn.spec.inv_n;
+          a.lr = (float)((double)fit->lr * std::pow((double)fit->lr_decay, (double)((s - 1) / fit->lr_interval)));
+          a.bc1 = (float)(1.0 - std::pow(0.9, (double)s));
+          a.bc2 = (float)(1.0 - std::pow(0.999, (double)s));
+          AL.nets[na++] = a;
+          maxP = std::max(maxP, N.s.nparams());
+        }
+        L.G = G;
+        launch_train(m->nets[grp[0]].ks, L, (int)grp.size(), st);
+      }
+      launch_reduce_adam(AL, maxP, na, st);
+      for (int k : nets) m->nets[k].step += 1;
+    }
+    if (loss_host) {
+      std::vector<float> h(std::max(fit->steps, 1));
+      bool finite = true;
+      for (int k : nets) {
+        if (fit->steps == 0) break;
+        NVDB_HIP(hipMemcpyAsync(h.data(), m->nets[k].losses.p, fit->steps * 4, hipMemcpyDeviceToHost, st));
+        NVDB_HIP(hipStreamSynchronize(st));
+        for (int i = 0; i < fit->steps; ++i) {
+          loss_host[k * fit->steps + i] = h[i];
+          finite = finite && std::isfinite(h[i]);
+        }
+      }
+      NVDB_REQUIRE(finite, NVDB_E_NUMERIC, "non-finite loss during fit");
+    }
+  });
+}
+
+// ------------------------------------------------------------------ decode
+static int infer_grid(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 512)); }
+
+nvdb_status nvdb_decode(const nvdb_model* m, const nvdb_tree* tree, float* values_dev, uint64_t* pred_mask_dev,
+                        void* stream) {
+  return guarded([&] {
+    NVDB_REQUIRE(m && tree, NVDB_E_INVALID, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    const TreeView tv = tree_view(tree);
+    if (values_dev && tree->n_vox > 0) {
+      const Net& N = net_of(m, NVDB_NET_REGRESSOR);
+      NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "regressor parameters or encoding not set");
+      InferLaunch I{};
+      I.net = net_view(N);
+      base_spec(m, &I.spec);
+      I.spec.src = SRC_VOXELS;
+      I.spec.direct = 1;
+      I.spec.n = tree->n_vox;
+      I.tree = tv;
+      I.out_kind = OUT_VALUES;
+      I.out_scale = m->d.value_scale;
+      I.y = values_dev;
+      launch_infer(N.ks, I, infer_grid(I.spec.n), st);
+    }
+    if (pred_mask_dev && tree->n_leaf > 0) {
+      const Net& N = net_of(m, NVDB_NET_L0);
+      NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "classifier parameters or encoding not set");
+      InferLaunch I{};
+      I.net = net_view(N);
+      base_spec(m, &I.spec);
+      I.spec.src = SRC_LEAF_SLOTS;
+      I.spec.direct = 1;
+      I.spec.n = 512 * tree->n_leaf;
+      I.tree = tv;
+      I.out_kind = OUT_MASK;
+      I.mask = pred_mask_dev;
+      launch_infer(N.ks, I, infer_grid(I.spec.n), st);
+    }
+  });
+}
+
+nvdb_status nvdb_decode_l1(const nvdb_model* m, const nvdb_tree* tree, uint8_t* classes_dev, void* stream) {
+  return guarded([&] {
+    NVDB_REQUIRE(m && tree && classes_dev, NVDB_E_INVALID, "null argument");
+    const Net& N = net_of(m, NVDB_NET_L1);
+    NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "level-1 classifier parameters or encoding not set");
+    if (tree->n_l1 == 0) return;
+    InferLaunch I{};
+    I.net = net_view(N);
+    base_spec(m, &I.spec);
+    I.spec.src = SRC_L1_SLOTS;
+    I.spec.direct = 1;
+    I.spec.n = 4096 * tree->n_l1;
+    I.tree = tree_view(tree);
+    I.out_kind = OUT_CLASS;
+    I.cls = classes_dev;
+    launch_infer(N.ks, I, infer_grid(I.spec.n), (hipStream_t)stream);
+  });
+}
+
+nvdb_status nvdb_errors(const nvdb_tree* tree, const float* values_dev, const uint64_t* pred_mask_dev,
+                        nvdb_error_report* out, void* stream) {
+  return guarded([&] {
+    NVDB_REQUIRE(tree && values_dev && out, NVDB_E_INVALID, "null argument");
+    error_report(*tree, values_dev, pred_mask_dev, out, (hipStream_t)stream);
+  });
+}
+
+// ------------------------------------------------------------------ device-pointer calls
+nvdb_status nvdb_forward_dev(const nvdb_model* m, int32_t net, const float* x_dev, int64_t n, float* y_dev,
+                             void* stream) {
+  return guarded([&] {
+    const Net& N = net_of(m, net);
+    NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "parameters or encoding not set");
+    NVDB_REQUIRE(n >= 0 && (n == 0 || (x_dev && y_dev)), NVDB_E_INVALID, "bad buffers");
+    if (n == 0) return;
+    InferLaunch I{};
+    I.net = net_view(N);
+    base_spec(m, &I.spec);
+    I.spec.src = SRC_COORDS;
+    I.spec.direct = 1;
+    I.spec.coords = x_dev;
+    I.spec.n = n;
+    I.out_kind = OUT_Y;
+    I.y = y_dev;
+    launch_infer(N.ks, I, infer_grid(n), (hipStream_t)stream);
+  });
+}
+
+nvdb_status nvdb_backward_dev(nvdb_model* m, int32_t net, const float* x_dev, const float* gy_dev, int64_t n,
+                              float* grad_dev, void* stream) {
+  return guarded([&] {
+    Net& N = net_of(m, net);
+    NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "parameters or encoding not set");
+    NVDB_REQUIRE(n >= 1 && x_dev && gy_dev && grad_dev, NVDB_E_INVALID, "bad buffers");
+    hipStream_t st = (hipStream_t)stream;
+    const int G = (int)std::min<int64_t>(MAX_G, (n + TRAIN_TILE - 1) / TRAIN_TILE);
+    ensure_partials(N, G);
+    if (N.ks.train_needs_zeroed_partial)
+      NVDB_HIP(hipMemsetAsync(N.partial.p, 0, (size_t)G * N.s.nparams() * 4, st));
+    TrainLaunch L{};
+    L.G = G;
+    TrainNet& tn = L.nets[0];
+    tn.net = net_view(N);
+    base_spec(m, &tn.spec);
+    tn.spec.src = SRC_COORDS;
+    tn.spec.loss = LOSS_EXTERNAL;
+    tn.spec.coords = x_dev;
+    tn.spec.gy = gy_dev;
+    tn.spec.n = n;
+    tn.spec.inv_n = 1.f;
+    tn.partial = N.partial.p;
+    tn.loss_partial = N.loss_partial.p;
+    launch_train(N.ks, L, 1, st);
+    AdamLaunch AL{};
+    AL.nets[0] = adam_view(N);
+    AL.nets[0].partial = N.partial.p;
+    AL.nets[0].loss_partial = N.loss_partial.p;
+    AL.nets[0].G = G;
+    AL.nets[0].grad_out = grad_dev;
+    launch_reduce_adam(AL, N.s.nparams(), 1, st);
+  });
+}
+
+nvdb_status nvdb_sample_indices_dev(uint64_t seed, int32_t stream_id, int64_t step, int64_t n_pop, int64_t batch,
+                                    uint32_t* idx_dev, void* stream) {
+  return guarded([&] {
+    NVDB_REQUIRE(n_pop > 0 && n_pop < (1ll << 32) && batch >= 0 && step >= 0 && stream_id >= 0, NVDB_E_INVALID,
+                 "bad sampler arguments");
+    NVDB_REQUIRE(batch == 0 || idx_dev, NVDB_E_INVALID, "null output");
+    launch_sample(step_seed(seed, stream_id, step), (uint32_t)n_pop, batch, idx_dev, (hipStream_t)stream);
+  });
+}
+
+}  // extern "C"

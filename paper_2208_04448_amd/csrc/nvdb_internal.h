@@ -1,0 +1,242 @@
+// Internal definitions shared by the HIP sources of libnvdb (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/nvdb.h"
+
+namespace nvdb {
+
+// ------------------------------------------------------------------ errors
+struct Error : std::runtime_error {
+  nvdb_status code;
+  Error(nvdb_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+#define NVDB_HIP(call)                                                                             \
+  do {                                                                                             \
+    hipError_t e_ = (call);                                                                        \
+    if (e_ != hipSuccess)                                                                          \
+      throw ::nvdb::Error(e_ == hipErrorOutOfMemory ? NVDB_E_NOMEM : NVDB_E_DEVICE,               \
+                          std::string(#call) + ": " + hipGetErrorString(e_));                     \
+  } while (0)
+#define NVDB_REQUIRE(cond, code, msg)                                                              \
+  do {                                                                                             \
+    if (!(cond)) throw ::nvdb::Error(code, msg);                                                   \
+  } while (0)
+
+// ------------------------------------------------------------- vector types
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// --------------------------------------------------------- device buffers
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    release();
+    if (count == 0) return;
+    NVDB_HIP(hipMalloc(&p, count * sizeof(T)));
+    n = count;
+  }
+  void ensure(size_t count) {
+    if (count > n) alloc(count);
+  }
+};
+
+// ----------------------------------------------------------------- trees
+struct Tree {
+  int32_t origin[3], dims[3];
+  int32_t kind = NVDB_SDF;     // active rule the tree was built with
+  int64_t n_vox = 0, n_leaf = 0, n_l1 = 0, n_l2 = 0;
+  DevBuf<int4> leaf_o;         // leaf origins (w unused)
+  DevBuf<uint64_t> leaf_mask;  // [L][8]
+  DevBuf<uint32_t> leaf_off;   // [L+1]
+  DevBuf<float> values;        // [N] leaf-major
+  DevBuf<uint32_t> vox_key;    // [N] leaf << 9 | n0
+  DevBuf<int4> l1_o;           // [n_l1]
+  DevBuf<uint64_t> l1_child;   // [n_l1][64]
+  DevBuf<uint64_t> l1_active;  // [n_l1][64] (all zero for trees built from voxels)
+  std::vector<int32_t> l2_origin;  // host, [n_l2][3]
+};
+
+// ------------------------------------------------------------- sampling
+enum SampleSource : int32_t { SRC_VOXELS = 0, SRC_LEAF_SLOTS = 1, SRC_L1_SLOTS = 2, SRC_COORDS = 3 };
+enum LossKind : int32_t { LOSS_MSE = 0, LOSS_BCE = 1, LOSS_CE = 2, LOSS_EXTERNAL = 3 };
+
+constexpr uint64_t SM_GOLDEN = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t SM_M1 = 0xBF58476D1CE4E5B9ull;
+constexpr uint64_t SM_M2 = 0x94D049BB133111EBull;
+
+// SplitMix64 output function (Steele, Lea, Flood 2014).
+__host__ __device__ inline uint64_t sm_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * SM_M1;
+  z = (z ^ (z >> 27)) * SM_M2;
+  return z ^ (z >> 31);
+}
+// Seed of the per-step generator: output (step+1) of the generator seeded by
+// output (stream+1) of SplitMix64(seed).  Sample j of the step is output j+1
+// of SplitMix64(step_seed).
+inline uint64_t step_seed(uint64_t seed, int64_t stream, int64_t step) {
+  uint64_t s1 = sm_mix(seed + SM_GOLDEN * (uint64_t)(stream + 1));
+  return sm_mix(s1 + SM_GOLDEN * (uint64_t)(step + 1));
+}
+
+// Everything a kernel needs to turn a sample index into coordinates and targets.
+struct TreeView {
+  const int4* leaf_o;
+  const uint64_t* leaf_mask;
+  const uint32_t* vox_key;
+  const float* values;
+  const int4* l1_o;
+  const uint64_t* l1_child;
+  const uint64_t* l1_active;
+};
+
+struct SampleSpec {
+  int32_t src;            // SampleSource
+  int32_t direct;         // sample j is population index j (decode)
+  int32_t loss;           // LossKind
+  uint32_t npop;          // population size for the i.i.d. sampler
+  uint64_t step_seed;     // per-step SplitMix64 seed
+  const uint32_t* idx;    // explicit population indices (or null)
+  int64_t n;              // samples in this step / call
+  float inv_n;            // 1 / n for batch-mean losses
+  float tscale;           // regression target = value * tscale
+  int32_t lo[3];          // normalisation box origin
+  float inv_d;            // 1 / box size
+  const float* coords;    // SRC_COORDS: [n][3]
+  const float* gy;        // LOSS_EXTERNAL: [n][n_out]
+};
+
+// ----------------------------------------------------------- net layout
+// Canonical parameter offsets of an H x W MLP with K inputs and C outputs.
+struct NetShape {
+  int32_t K, KP, W, H, C;  // KP = K rounded up to 32
+  __host__ __device__ int64_t woff(int l) const {  // l = 0 .. H (H = head)
+    if (l == 0) return 0;
+    return (int64_t)W * K + W + (int64_t)(l - 1) * ((int64_t)W * W + W);
+  }
+  __host__ __device__ int64_t boff(int l) const {
+    if (l == 0) return (int64_t)W * K;
+    if (l == H) return woff(H) + (int64_t)C * W;
+    return woff(l) + (int64_t)W * W;
+  }
+  __host__ __device__ int64_t nparams() const { return woff(H) + (int64_t)C * W + C; }
+  __host__ __device__ int win(int l) const { return l == 0 ? K : W; }
+};
+
+// Device-side view of one network: FP32 master parameters are canonical; the
+// kernels read "shadow" copies in their own layouts, rewritten after every
+// optimiser step.
+struct NetView {
+  NetShape s;
+  const void* wrow;      // layers 0..H-1: [W rows][256 bytes] (bf16, swizzled) or [W][Win] (fp32)
+  const void* wcol;      // fp32 only: layers 0..H-1 transposed, [Win][W]
+  const void* w1frag;    // bf16 only: layer 0 in MFMA A-fragment order
+  const float* bias;     // [H][W]
+  const float* whead;    // [C][W]
+  const float* bhead;    // [C]
+  const float* benc;     // feature-mapping matrix [KP/2][3], zero rows beyond n_freq
+  int32_t nfreq;
+};
+
+// bf16 weight rows in LDS / HBM: 256 bytes per row (128 bf16), 8-byte chunks
+// permuted by an XOR swizzle so that both the row-wise fragment reads of the
+// forward product and the transposing reads of the backward product hit
+// distinct LDS banks.
+__host__ __device__ inline int swz(int row) { return ((row & 3) << 3) | ((row >> 2) & 7); }
+__host__ __device__ inline int swz_elem(int row, int col) {  // element offset inside the row
+  return (((col >> 2) ^ swz(row)) << 2) | (col & 3);
+}
+constexpr int ROW_ELEMS = 128;  // bf16 elements per stored row
+
+
+// ----------------------------------------------------------- launch records
+struct TrainNet {
+  NetView net;
+  SampleSpec spec;
+  float* partial;       // [G][P]
+  float* loss_partial;  // [G]
+};
+struct TrainLaunch {
+  TrainNet nets[NVDB_MAX_NETS];
+  TreeView tree;
+  int32_t G;
+};
+enum InferOut : int32_t { OUT_Y = 0, OUT_VALUES = 1, OUT_MASK = 2, OUT_CLASS = 3 };
+struct InferLaunch {
+  NetView net;
+  SampleSpec spec;  // spec.idx null, sample j is population index j (or coordinate j)
+  TreeView tree;
+  int32_t out_kind;
+  float out_scale;
+  float* y;           // OUT_Y: [n][C]; OUT_VALUES: [n]
+  uint64_t* mask;     // OUT_MASK: [n/64]
+  uint8_t* cls;       // OUT_CLASS: [n]
+};
+struct AdamNet {
+  NetShape s;
+  const float* partial;  // [G][P]
+  const float* loss_partial;
+  int32_t G;
+  float* theta;          // FP32 master parameters, canonical
+  float* m;
+  float* v;
+  float* grad_out;       // if non-null: write the reduced gradient and skip the update
+  float* loss_out;       // if non-null: loss of this step (mean)
+  float loss_scale;
+  float lr, bc1, bc2;    // learning rate, 1 - beta1^s, 1 - beta2^s
+  // shadow copies
+  int32_t prec;
+  void* wrow;
+  void* wcol;
+  void* w1frag;
+  float* bias;
+  float* whead;
+  float* bhead;
+};
+struct AdamLaunch {
+  AdamNet nets[NVDB_MAX_NETS];
+};
+struct KernelSet {
+  void (*train)(TrainLaunch);
+  void (*infer)(InferLaunch);
+  int train_lds, infer_lds;
+  bool train_needs_zeroed_partial;
+};
+
+// mlp.hip
+bool find_kernels(int prec, int W, int H, int KP, int C, KernelSet* out);
+void launch_train(const KernelSet& ks, const TrainLaunch& L, int n_nets, hipStream_t st);
+void launch_infer(const KernelSet& ks, const InferLaunch& I, int grid, hipStream_t st);
+void launch_reduce_adam(const AdamLaunch& A, int64_t max_p, int n_nets, hipStream_t st);
+void launch_write_shadow(const AdamNet& A, hipStream_t st);
+void launch_sample(uint64_t sseed, uint32_t npop, int64_t n, uint32_t* out, hipStream_t st);
+// tree.hip
+Tree* build_tree_dense(const float* grid, const int32_t dims[3], const int32_t origin[3], const nvdb_active_rule& rule,
+                       hipStream_t st);
+void error_report(const Tree& t, const float* values, const uint64_t* pred_mask, nvdb_error_report* rep,
+                  hipStream_t st);
+
+}  // namespace nvdb

@@ -1,0 +1,286 @@
+"""Thin ctypes binding of libnvdb (include/nvdb.h).
+
+Argument marshalling only: every step of the encode/decode path runs in the
+HIP kernels of libnvdb.so.  Torch provides device memory and the current
+stream.  Importing this module fails loudly if the library has not been built.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnvdb.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libnvdb.so is not built; run paper_2208_04448_amd/build.py (or __graft_entry__.build())")
+_lib = C.CDLL(LIB_PATH)
+
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_NUMERIC, E_STATE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+SDF, FOG = 0, 1
+NET_REGRESSOR, NET_L0, NET_L1, MAX_NETS = 0, 1, 2, 3
+FP32, BF16 = 0, 1
+
+
+class NvdbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("nvdb error %d: %s" % (code, msg))
+        self.code = code
+
+
+class ActiveRule(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("band_or_threshold", C.c_float)]
+
+
+class TreeInfo(C.Structure):
+    _fields_ = [("n_voxels", C.c_int64), ("n_leaves", C.c_int64), ("n_l1", C.c_int64), ("n_l2", C.c_int64),
+                ("grid_origin", C.c_int32 * 3), ("grid_dims", C.c_int32 * 3),
+                ("bytes_l2", C.c_int64), ("bytes_l1", C.c_int64), ("bytes_leaf_masks", C.c_int64),
+                ("bytes_voxels", C.c_int64)]
+
+
+class NetDesc(C.Structure):
+    _fields_ = [("width", C.c_int32), ("hidden", C.c_int32), ("n_freq", C.c_int32), ("n_out", C.c_int32)]
+
+
+class ModelDesc(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("has_net", C.c_int32 * 3), ("net", NetDesc * 3),
+                ("domain_lo", C.c_int32 * 3), ("domain_size", C.c_int32), ("value_scale", C.c_float)]
+
+
+class FitDesc(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("batch", C.c_int32), ("seed", C.c_uint64), ("lr", C.c_float),
+                ("lr_decay", C.c_float), ("lr_interval", C.c_int32), ("nets_mask", C.c_int32),
+                ("idx_dev", C.c_void_p * 3), ("idx_count", C.c_int64 * 3)]
+
+
+class ErrorReport(C.Structure):
+    _fields_ = [("n", C.c_int64), ("max_abs", C.c_double), ("rms", C.c_double), ("iou", C.c_double),
+                ("fp", C.c_int64), ("fn", C.c_int64)]
+
+
+_P = C.c_void_p
+_SIGS = {
+    "nvdb_last_error": (C.c_char_p, []),
+    "nvdb_abi_version": (C.c_int32, []),
+    "nvdb_tree_build_dense": (C.c_int32, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(ActiveRule), _P,
+                                          C.POINTER(_P)]),
+    "nvdb_tree_get_info": (C.c_int32, [_P, C.POINTER(TreeInfo)]),
+    "nvdb_tree_export": (C.c_int32, [_P, _P, _P, _P, _P, _P, _P]),
+    "nvdb_tree_free": (None, [_P]),
+    "nvdb_model_create": (C.c_int32, [C.POINTER(ModelDesc), C.POINTER(_P)]),
+    "nvdb_model_param_count": (C.c_int32, [_P, C.c_int32, C.POINTER(C.c_int64)]),
+    "nvdb_model_set_params": (C.c_int32, [_P, C.c_int32, _P, C.c_int64]),
+    "nvdb_model_get_params": (C.c_int32, [_P, C.c_int32, _P, C.c_int64]),
+    "nvdb_model_set_encoding": (C.c_int32, [_P, C.c_int32, _P, C.c_int32]),
+    "nvdb_model_get_opt_state": (C.c_int32, [_P, C.c_int32, _P, _P, C.c_int64, C.POINTER(C.c_int64)]),
+    "nvdb_model_set_opt_state": (C.c_int32, [_P, C.c_int32, _P, _P, C.c_int64, C.c_int64]),
+    "nvdb_model_free": (None, [_P]),
+    "nvdb_fit": (C.c_int32, [_P, _P, C.POINTER(FitDesc), _P, _P]),
+    "nvdb_decode": (C.c_int32, [_P, _P, _P, _P, _P]),
+    "nvdb_decode_l1": (C.c_int32, [_P, _P, _P, _P]),
+    "nvdb_errors": (C.c_int32, [_P, _P, _P, C.POINTER(ErrorReport), _P]),
+    "nvdb_forward_dev": (C.c_int32, [_P, C.c_int32, _P, C.c_int64, _P, _P]),
+    "nvdb_backward_dev": (C.c_int32, [_P, C.c_int32, _P, _P, C.c_int64, _P, _P]),
+    "nvdb_sample_indices_dev": (C.c_int32, [C.c_uint64, C.c_int32, C.c_int64, C.c_int64, C.c_int64, _P, _P]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_SIGS)
+
+
+def _check(code):
+    if code != OK:
+        raise NvdbError(code, _lib.nvdb_last_error().decode())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _i3(v):
+    return (C.c_int32 * 3)(*[int(a) for a in v])
+
+
+# ---------------------------------------------------------------------------- trees
+class Tree:
+    """Handle of a tree built on the device from a dense float32 grid (x-major)."""
+
+    def __init__(self, grid, origin=(0, 0, 0), kind=SDF, band_or_threshold=3.0):
+        import torch
+        assert grid.is_cuda and grid.dtype == torch.float32 and grid.dim() == 3
+        grid = grid.contiguous()
+        h = C.c_void_p()
+        rule = ActiveRule(kind, band_or_threshold)
+        _check(_lib.nvdb_tree_build_dense(_ptr(grid), _i3(grid.shape), _i3(origin), C.byref(rule), _stream(),
+                                          C.byref(h)))
+        self.h = h
+        self.kind = kind
+
+    def info(self):
+        i = TreeInfo()
+        _check(_lib.nvdb_tree_get_info(self.h, C.byref(i)))
+        return i
+
+    def export(self):
+        i = self.info()
+        L, N, L1 = i.n_leaves, i.n_voxels, i.n_l1
+        out = dict(leaf_origin=np.zeros((L, 3), np.int32), leaf_mask=np.zeros((L, 8), np.uint64),
+                   leaf_off=np.zeros(L + 1, np.uint32), values=np.zeros(N, np.float32),
+                   l1_origin=np.zeros((L1, 3), np.int32), l1_child=np.zeros((L1, 64), np.uint64))
+        _check(_lib.nvdb_tree_export(self.h, *[o.ctypes.data_as(C.c_void_p) for o in
+                                               (out["leaf_origin"], out["leaf_mask"], out["leaf_off"], out["values"],
+                                                out["l1_origin"], out["l1_child"])]))
+        return out
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _lib.nvdb_tree_free(self.h)
+            self.h = None
+
+
+# ---------------------------------------------------------------------------- models
+class Model:
+    """Handle of a set of NeuralVDB networks (regressor, level-0, level-1)."""
+
+    def __init__(self, nets, precision=BF16, domain_lo=(0, 0, 0), domain_size=64, value_scale=1.0):
+        """nets: {net_id: (width, hidden, n_freq, n_out)}"""
+        d = ModelDesc()
+        d.precision = precision
+        for k, (w, hh, m, c) in nets.items():
+            d.has_net[k] = 1
+            d.net[k] = NetDesc(w, hh, m, c)
+        d.domain_lo = _i3(domain_lo)
+        d.domain_size = int(domain_size)
+        d.value_scale = float(value_scale)
+        h = C.c_void_p()
+        _check(_lib.nvdb_model_create(C.byref(d), C.byref(h)))
+        self.h = h
+        self.nets = dict(nets)
+        self.precision = precision
+
+    def param_count(self, net):
+        n = C.c_int64()
+        _check(_lib.nvdb_model_param_count(self.h, net, C.byref(n)))
+        return n.value
+
+    def set_params(self, net, theta):
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        _check(_lib.nvdb_model_set_params(self.h, net, a.ctypes.data_as(C.c_void_p), a.size))
+
+    def get_params(self, net):
+        a = np.zeros(self.param_count(net), np.float32)
+        _check(_lib.nvdb_model_get_params(self.h, net, a.ctypes.data_as(C.c_void_p), a.size))
+        return a
+
+    def set_encoding(self, net, B):
+        a = np.ascontiguousarray(B, dtype=np.float32)
+        _check(_lib.nvdb_model_set_encoding(self.h, net, a.ctypes.data_as(C.c_void_p), a.shape[0]))
+
+    def get_opt_state(self, net):
+        n = self.param_count(net)
+        m, v, s = np.zeros(n, np.float32), np.zeros(n, np.float32), C.c_int64()
+        _check(_lib.nvdb_model_get_opt_state(self.h, net, m.ctypes.data_as(C.c_void_p), v.ctypes.data_as(C.c_void_p),
+                                             n, C.byref(s)))
+        return m, v, s.value
+
+    def set_opt_state(self, net, m, v, step):
+        m = np.ascontiguousarray(m, np.float32)
+        v = np.ascontiguousarray(v, np.float32)
+        _check(_lib.nvdb_model_set_opt_state(self.h, net, m.ctypes.data_as(C.c_void_p),
+                                             v.ctypes.data_as(C.c_void_p), m.size, int(step)))
+
+    def fit(self, tree, steps, batch, nets_mask, seed=0, lr=1e-3, lr_decay=0.975, lr_interval=100, idx=None,
+            return_losses=True):
+        """Run `steps` Adam steps.  idx: optional {net: int32/uint32 device tensor} of sample indices."""
+        f = FitDesc()
+        f.steps, f.batch, f.seed = steps, batch, seed
+        f.lr, f.lr_decay, f.lr_interval, f.nets_mask = lr, lr_decay, lr_interval, nets_mask
+        keep = []
+        for k, t in (idx or {}).items():
+            keep.append(t)
+            f.idx_dev[k] = t.data_ptr()
+            f.idx_count[k] = t.numel()
+        losses = np.zeros((MAX_NETS, max(steps, 1)), np.float32) if return_losses else None
+        _check(_lib.nvdb_fit(self.h, tree.h, C.byref(f),
+                             losses.ctypes.data_as(C.c_void_p) if return_losses else None, _stream()))
+        return losses[:, :steps] if return_losses else None
+
+    def decode(self, tree, values=True, masks=True):
+        import torch
+        i = tree.info()
+        v = torch.empty(i.n_voxels, dtype=torch.float32, device="cuda") if values else None
+        mk = torch.empty((i.n_leaves, 8), dtype=torch.int64, device="cuda") if masks else None
+        _check(_lib.nvdb_decode(self.h, tree.h, _ptr(v), _ptr(mk), _stream()))
+        return v, mk
+
+    def decode_l1(self, tree):
+        import torch
+        i = tree.info()
+        out = torch.empty((i.n_l1, 4096), dtype=torch.uint8, device="cuda")
+        _check(_lib.nvdb_decode_l1(self.h, tree.h, _ptr(out), _stream()))
+        return out
+
+    def forward(self, net, x):
+        import torch
+        x = x.contiguous()
+        y = torch.empty((x.shape[0], self.nets[net][3]), dtype=torch.float32, device=x.device)
+        _check(_lib.nvdb_forward_dev(self.h, net, _ptr(x), x.shape[0], _ptr(y), _stream()))
+        return y
+
+    def backward(self, net, x, gy):
+        import torch
+        x, gy = x.contiguous(), gy.contiguous()
+        g = torch.empty(self.param_count(net), dtype=torch.float32, device=x.device)
+        _check(_lib.nvdb_backward_dev(self.h, net, _ptr(x), _ptr(gy), x.shape[0], _ptr(g), _stream()))
+        return g
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _lib.nvdb_model_free(self.h)
+            self.h = None
+
+
+def errors(tree, values, pred_mask=None):
+    r = ErrorReport()
+    _check(_lib.nvdb_errors(tree.h, _ptr(values), _ptr(pred_mask), C.byref(r), _stream()))
+    return dict(n=r.n, max_abs=r.max_abs, rms=r.rms, iou=r.iou, fp=r.fp, fn=r.fn)
+
+
+def sample_indices(seed, stream_id, step, n_pop, batch):
+    import torch
+    out = torch.empty(batch, dtype=torch.int32, device="cuda")
+    _check(_lib.nvdb_sample_indices_dev(seed, stream_id, step, n_pop, batch, _ptr(out), _stream()))
+    return out
+
+
+# ---------------------------------------------------------------------------- autograd
+def mlp_function():
+    """torch.autograd.Function whose forward and backward are the fused HIP kernels.
+
+    apply(model, net, x, theta_placeholder) -> y; the gradient arrives in
+    theta_placeholder.grad (canonical layout).  The backward recomputes the
+    forward activations inside the fused kernel instead of storing them."""
+    import torch
+
+    class NvdbMLP(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, model, net, x, theta):
+            ctx.model, ctx.net = model, net
+            ctx.save_for_backward(x)
+            return model.forward(net, x)
+
+        @staticmethod
+        def backward(ctx, gy):
+            (x,) = ctx.saved_tensors
+            g = ctx.model.backward(ctx.net, x, gy.float())
+            return None, None, None, g
+
+    return NvdbMLP
