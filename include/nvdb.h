@@ -78,8 +78,8 @@ typedef struct {
  * Leaves are ordered by (level-2 origin x,y,z, level-1 slot, leaf slot),
  * voxels inside a leaf by n0; leaf masks keep bit n in word n>>6 at n&63.
  * Errors: E_INVALID for non-positive dims, a grid beyond 2^31 voxels or
- * coordinates beyond int32, NaN/Inf among the active voxels, or an unknown
- * rule; E_NOMEM / E_DEVICE from HIP.  The call synchronises `stream`. */
+ * coordinates beyond int32, any NaN/Inf in the grid, or an unknown rule;
+ * E_NOMEM / E_DEVICE from HIP.  The call synchronises `stream`. */
 nvdb_status nvdb_tree_build_dense(const float* grid_dev, const int32_t dims[3], const int32_t origin[3],
                                   const nvdb_active_rule* rule, void* stream, nvdb_tree** out);
 /* Counts, bounding grid and byte accounting of a tree. */
@@ -164,6 +164,10 @@ typedef struct {
   int32_t nets_mask;             /* bit n trains network n                               */
   const uint32_t* idx_dev[NVDB_MAX_NETS];  /* optional explicit sample order             */
   int64_t idx_count[NVDB_MAX_NETS];
+  /* Optional host output: summed duration in ms of the training-kernel launches,
+   * measured with HIP events recorded on `stream` around each launch (the call
+   * then synchronises `stream`).  NULL disables the timing. */
+  float* train_kernel_ms;
 } nvdb_fit_desc;
 
 /* Run `steps` steps continuing from the model's step counters.  loss_host, if

@@ -379,6 +379,13 @@ nvdb_status nvdb_fit(nvdb_model* m, const nvdb_tree* tree, const nvdb_fit_desc* 
       if (!put) groups.push_back({k});
     }
 
+    // optional timing of the training-kernel launches with HIP events on `stream`
+    std::vector<hipEvent_t> ev;
+    if (fit->train_kernel_ms) {
+      ev.resize(2 * (size_t)fit->steps * groups.size());
+      for (auto& e : ev) NVDB_HIP(hipEventCreate(&e));
+    }
+    size_t evi = 0;
     for (int step = 0; step < fit->steps; ++step) {
       AdamLaunch AL{};
       int na = 0;
@@ -416,8 +423,6 @@ nvdb_status nvdb_fit(nvdb_model* m, const nvdb_tree* tree, const nvdb_fit_desc* 
           TrainNet& tn = L.nets[slot++];
           tn.partial = N.partial.p;
           tn.loss_partial = N.loss_partial.p;
-          if (N.ks.train_needs_zeroed_partial)
-            NVDB_HIP(hipMemsetAsync(N.partial.p, 0, (size_t)G * N.s.nparams() * 4, st));
           // optimiser step for this network
           const int64_t s = N.step + 1;
           AdamNet a = adam_view(N);
@@ -433,10 +438,23 @@ nvdb_status nvdb_fit(nvdb_model* m, const nvdb_tree* tree, const nvdb_fit_desc* 
           maxP = std::max(maxP, N.s.nparams());
         }
         L.G = G;
+        if (!ev.empty()) NVDB_HIP(hipEventRecord(ev[evi++], st));
         launch_train(m->nets[grp[0]].ks, L, (int)grp.size(), st);
+        if (!ev.empty()) NVDB_HIP(hipEventRecord(ev[evi++], st));
       }
       launch_reduce_adam(AL, maxP, na, st);
       for (int k : nets) m->nets[k].step += 1;
+    }
+    if (!ev.empty()) {
+      NVDB_HIP(hipEventSynchronize(ev.back()));
+      double tot = 0.0;
+      for (size_t i = 0; i + 1 < ev.size(); i += 2) {
+        float ms = 0.f;
+        NVDB_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+        tot += ms;
+      }
+      for (auto& e : ev) (void)hipEventDestroy(e);
+      *fit->train_kernel_ms = (float)tot;
     }
     if (loss_host) {
       std::vector<float> h(std::max(fit->steps, 1));
@@ -553,8 +571,6 @@ nvdb_status nvdb_backward_dev(nvdb_model* m, int32_t net, const float* x_dev, co
     hipStream_t st = (hipStream_t)stream;
     const int G = (int)std::min<int64_t>(MAX_G, (n + TRAIN_TILE - 1) / TRAIN_TILE);
     ensure_partials(N, G);
-    if (N.ks.train_needs_zeroed_partial)
-      NVDB_HIP(hipMemsetAsync(N.partial.p, 0, (size_t)G * N.s.nparams() * 4, st));
     TrainLaunch L{};
     L.G = G;
     TrainNet& tn = L.nets[0];

@@ -215,54 +215,88 @@ __device__ __forceinline__ void encode_S(const Smp& s, const float* benc, int m,
   }
 }
 
-// ------------------------------------------------------------ fragment loads
-// bf16 weight rows are stored with 128 elements per row and swizzled 8-byte chunks.
-__device__ __forceinline__ bf16x8 frag_rows_bf16(const __bf16* rows, int row, int col) {
-  // elements [col, col+4) and [col+8, col+12) of `row` (col multiple of 4)
-  const __bf16* base = rows + row * ROW_ELEMS;
-  u32x2 a = *(const u32x2*)(base + swz_elem(row, col));
-  u32x2 b = *(const u32x2*)(base + swz_elem(row, col + 8));
+// ------------------------------------------------------------ LDS addressing
+// bf16 rows (weights and exchanged activations) are 256 bytes long; the 8-byte
+// chunk c of row r is stored at chunk c ^ swz(r).  Every access pattern below
+// splits into a compile-time part and a lane part whose bits are disjoint, so
+// the swizzled byte offset is (CT << 3) ^ lane_constant plus an immediate:
+//   row-wise reads and row writes:  lane constant s*256 + ((swz(s) ^ h) << 3), s = lane & 31;
+//   transposing reads (4 rows x 32 columns per 16-lane group):
+//     lane constant (4h + (k>>2))*256 + ((((4gg + (k&3)) ^ (8(k>>2) + h))) << 3).
+struct LaneK {
+  uint32_t fwd, tr;
+  int h, fl;
+};
+__device__ __forceinline__ LaneK lane_consts() {
+  const int l = lane_id(), h = l >> 5, fl = l & 31, k = l & 15, gg = (l >> 4) & 1;
+  LaneK K;
+  K.h = h;
+  K.fl = fl;
+  K.fwd = (uint32_t)fl * 256u + ((uint32_t)(swz(fl) ^ h) << 3);
+  const uint32_t lanebits = (uint32_t)((4 * gg + (k & 3)) ^ (8 * (k >> 2) + h));
+  K.tr = (uint32_t)(4 * h + (k >> 2)) * 256u + (lanebits << 3);
+  return K;
+}
+
+// A fragment of the forward product from LDS rows: output block ob (32 rows),
+// k-step kk of input block t.  Elements [c0, c0+4) and [c0+8, c0+12) of row
+// 32 ob + i, c0 = 32t + 16kk + 4h.
+__device__ __forceinline__ bf16x8 frag_fwd(const char* rows, const LaneK& K, int ob, int t, int kk) {
+  const char* base = rows + ob * 32 * 256;
+  const uint32_t o0 = ((uint32_t)(8 * t + 4 * kk) << 3) ^ K.fwd;
+  const uint32_t o1 = ((uint32_t)(8 * t + 4 * kk + 2) << 3) ^ K.fwd;
+  u32x2 a = *(const u32x2*)(base + o0);
+  u32x2 b = *(const u32x2*)(base + o1);
   u32x4 v = {a[0], a[1], b[0], b[1]};
   return __builtin_bit_cast(bf16x8, v);
 }
-// Transposing read: lane (i, h) receives rows rbase + 8p + 4h + e (p, e) of column cbase + i.
-__device__ __forceinline__ bf16x8 frag_cols_bf16(const __bf16* rows, int rbase, int cbase) {
-  const int l = lane_id(), g = l >> 4, k = l & 15, h = g >> 1, gg = g & 1;
-  const int col = cbase + 16 * gg + 4 * (k & 3);
-  const int r0 = rbase + 4 * h + (k >> 2);
-  u32x2 a = lds_tr(rows + r0 * ROW_ELEMS + swz_elem(r0, col));
-  u32x2 b = lds_tr(rows + (r0 + 8) * ROW_ELEMS + swz_elem(r0 + 8, col));
+// Transposing read: lane (i, h) receives rows rbase + 8p + 4h + e (e < 4, p < 2) of
+// column 32 cb + i, as 8 values ordered (p, e).  rbase is a multiple of 16.
+__device__ __forceinline__ bf16x8 frag_tr(const char* rows, const LaneK& K, int rbase, int cb) {
+  const int kb = (rbase >> 4) & 1;
+  const char* base = rows + rbase * 256;
+  const uint32_t o0 = ((uint32_t)(8 * cb + 4 * kb) << 3) ^ K.tr;
+  const uint32_t o1 = ((uint32_t)(8 * cb + 4 * kb + 2) << 3) ^ K.tr;
+  u32x2 a = lds_tr((const __bf16*)(base + o0));
+  u32x2 b = lds_tr((const __bf16*)(base + 8 * 256 + o1));
   u32x4 v = {a[0], a[1], b[0], b[1]};
   return __builtin_bit_cast(bf16x8, v);
 }
-// Write the lane's S-layout blocks of one sample as a row of bf16 (swizzled).
+// The lane's S-layout blocks of one sample as a swizzled bf16 row.
 template <int NIB>
-__device__ __forceinline__ void write_rows_bf16(__bf16* rows, const uint32_t (&S)[NIB][8]) {
-  const int s = lane_id() & 31, h = lane_id() >> 5;
-  __bf16* base = rows + s * ROW_ELEMS;
+__device__ __forceinline__ void write_rows_bf16(char* rows, const LaneK& K, const uint32_t (&S)[NIB][8]) {
 #pragma unroll
   for (int t = 0; t < NIB; ++t)
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       u32x2 v = {S[t][2 * a], S[t][2 * a + 1]};
-      *(u32x2*)(base + swz_elem(s, 32 * t + 8 * a + 4 * h)) = v;
+      *(u32x2*)(rows + ((((uint32_t)(8 * t + 2 * a)) << 3) ^ K.fwd)) = v;
     }
 }
 template <int NIB>
-__device__ __forceinline__ void write_rows_f32(float* rows, int pitch, const uint32_t (&S)[NIB][16]) {
-  const int s = lane_id() & 31, h = lane_id() >> 5;
-  float* base = rows + s * pitch;
+__device__ __forceinline__ void write_rows_f32(float* rows, int pitch, const LaneK& K, const uint32_t (&S)[NIB][16]) {
+  float* base = rows + K.fl * pitch + 4 * K.h;
 #pragma unroll
   for (int t = 0; t < NIB; ++t)
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       floatx4 v = {__uint_as_float(S[t][4 * a]), __uint_as_float(S[t][4 * a + 1]), __uint_as_float(S[t][4 * a + 2]),
                    __uint_as_float(S[t][4 * a + 3])};
-      *(floatx4*)(base + 32 * t + 8 * a + 4 * h) = v;
+      *(floatx4*)(base + 32 * t + 8 * a) = v;
     }
 }
-__device__ __forceinline__ float row_elem_bf16(const __bf16* rows, int s, int f) {
-  return (float)rows[s * ROW_ELEMS + swz_elem(s, f)];
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+// sum of the 8 bf16 values of a fragment, accumulated in fp32 (plain unpack and add:
+// the bf16 dot-product builtin was observed to read one source register four times
+// when fed elements of a bit-cast vector)
+__device__ __forceinline__ float frag_sum(bf16x8 f, float acc) {
+  const u32x4 u = __builtin_bit_cast(u32x4, f);
+  const float s0 = bf16_lo(u[0]) + bf16_hi(u[0]);
+  const float s1 = bf16_lo(u[1]) + bf16_hi(u[1]);
+  const float s2 = bf16_lo(u[2]) + bf16_hi(u[2]);
+  const float s3 = bf16_lo(u[3]) + bf16_hi(u[3]);
+  return acc + ((s0 + s1) + (s2 + s3));
 }
 
 // ------------------------------------------------------------ per-layer weights
@@ -270,19 +304,17 @@ __device__ __forceinline__ float row_elem_bf16(const __bf16* rows, int s, int f)
 // k-step kk of input block t.
 template <int PREC, int W, int KP>
 struct WFwd {
-  const __bf16* lds;       // bf16 rows (layers >= 1 staged in LDS)
+  const char* lds;         // bf16 rows of this layer in LDS
   const u32x4* gfrag;      // bf16 layer-0 fragments in HBM
-  const float* gcol;       // fp32: layer transposed [Win][W] in HBM
-  int layer;
+  const float* gcol;       // fp32: this layer transposed [Win][W] in HBM
+  bool global0;            // bf16: read the layer-0 fragments from HBM
+  const LaneK* K;
   __device__ __forceinline__ typename PR<PREC>::Frag operator()(int ob, int t, int kk) const {
     if constexpr (PREC == NVDB_BF16) {
-      if (layer == 0) {
-        return __builtin_bit_cast(bf16x8, gfrag[((ob * (KP / 32) + t) * 2 + kk) * 64 + lane_id()]);
-      }
-      return frag_rows_bf16(lds, 32 * ob + (lane_id() & 31), 32 * t + 16 * kk + 4 * (lane_id() >> 5));
+      if (global0) return __builtin_bit_cast(bf16x8, gfrag[((ob * (KP / 32) + t) * 2 + kk) * 64 + lane_id()]);
+      return frag_fwd(lds, *K, ob, t, kk);
     } else {
-      const int h = lane_id() >> 5;
-      return gcol[(size_t)sfeat(t, kk, h) * W + 32 * ob + (lane_id() & 31)];
+      return gcol[(size_t)sfeat(t, kk, K->h) * W + 32 * ob + K->fl];
     }
   }
 };
@@ -290,23 +322,38 @@ struct WFwd {
 // k-step kk of output block t.
 template <int PREC, int W>
 struct WBwd {
-  const __bf16* lds;
+  const char* lds;
   const float* grow;  // fp32: [W][W] row-major
+  const LaneK* K;
   __device__ __forceinline__ typename PR<PREC>::Frag operator()(int ib, int t, int kk) const {
     if constexpr (PREC == NVDB_BF16) {
-      return frag_cols_bf16(lds, 32 * t + 16 * kk, 32 * ib);
+      return frag_tr(lds, *K, 32 * t + 16 * kk, ib);
     } else {
-      const int h = lane_id() >> 5;
-      return grow[(size_t)sfeat(t, kk, h) * W + 32 * ib + (lane_id() & 31)];
+      return grow[(size_t)sfeat(t, kk, K->h) * W + 32 * ib + K->fl];
     }
   }
 };
 
-// One output block of a layer: sum over input blocks and k-steps.
+// Accumulator initialised with the bias of the lane's 16 output features.
+__device__ __forceinline__ floatx16 bias_acc(const float* bias, const LaneK& K, int ob) {
+  const floatx4* b = (const floatx4*)(bias + 32 * ob + 4 * K.h);
+  floatx16 a;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    floatx4 v = b[2 * q];
+    a[4 * q] = v[0];
+    a[4 * q + 1] = v[1];
+    a[4 * q + 2] = v[2];
+    a[4 * q + 3] = v[3];
+  }
+  return a;
+}
+
+// One output block of a layer: sum over input blocks and k-steps, starting from acc.
 template <int PREC, int NIB, class AF>
-__device__ __forceinline__ floatx16 layer_block(const AF& af, int ob, const uint32_t (&X)[NIB][PR<PREC>::SR]) {
+__device__ __forceinline__ floatx16 layer_block(const AF& af, int ob, const uint32_t (&X)[NIB][PR<PREC>::SR],
+                                                floatx16 acc) {
   using P = PR<PREC>;
-  floatx16 acc = {};
 #pragma unroll
   for (int t = 0; t < NIB; ++t)
 #pragma unroll
@@ -314,13 +361,25 @@ __device__ __forceinline__ floatx16 layer_block(const AF& af, int ob, const uint
   return acc;
 }
 
-__device__ __forceinline__ void bias_relu(floatx16& a, const float* bias, int ob) {
-  const int h = lane_id() >> 5;
+// Two output blocks sharing each B operand: two independent accumulator chains keep
+// the MFMA pipe busy while each chain waits on its previous result.
+template <int PREC, int NIB, class AF>
+__device__ __forceinline__ void layer_block2(const AF& af, int ob, const uint32_t (&X)[NIB][PR<PREC>::SR],
+                                             floatx16& acc0, floatx16& acc1) {
+  using P = PR<PREC>;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    float v = a[r] + bias[sfeat(ob, r, h)];
-    a[r] = v > 0.f ? v : 0.f;
-  }
+  for (int t = 0; t < NIB; ++t)
+#pragma unroll
+    for (int kk = 0; kk < P::KS; ++kk) {
+      const auto b = P::sfrag(X[t], kk);
+      acc0 = P::mma(af(ob, t, kk), b, acc0);
+      acc1 = P::mma(af(ob + 1, t, kk), b, acc1);
+    }
+}
+
+__device__ __forceinline__ void relu16(floatx16& a) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) a[r] = fmaxf(a[r], 0.f);
 }
 
 // Loss value and dL/dy of one sample (batch-mean losses).
@@ -369,6 +428,13 @@ __device__ __forceinline__ float loss_grad(const SampleSpec& sp, const Smp& s, i
   return L;
 }
 
+// Value of S-layout register r of a block (bf16 or fp32 storage).
+template <int PREC>
+__device__ __forceinline__ float sval(const uint32_t* s, int r) {
+  if constexpr (PREC == NVDB_BF16) return (r & 1) ? bf16_hi(s[r >> 1]) : bf16_lo(s[r >> 1]);
+  else return __uint_as_float(s[r]);
+}
+
 // ============================================================== training kernel
 template <int PREC, int W, int H, int KP, int C>
 struct TrainCfg {
@@ -376,49 +442,56 @@ struct TrainCfg {
   // Layers whose dW stays in registers for the whole step (BF16 form); the others
   // fold each iteration's contribution into the work-group's partial row in HBM.
   static constexpr bool DWREG = (PREC == NVDB_BF16);
-  static constexpr int DWREG_FROM = (W >= 128) ? 1 : 0;
+  static constexpr int DWREG_FROM = (W >= 128) ? 2 : 0;
   static constexpr bool reg_layer(int l) { return DWREG && l >= DWREG_FROM; }
   static constexpr bool any_rmw = !DWREG || DWREG_FROM > 0;
-  static constexpr int FPW = W / 4;                   // bias/head features owned per wave
   static constexpr int RB = (PREC == NVDB_BF16) ? 0 : (KP > W ? KP : W) + 4;  // fp32 row pitch (floats)
-  static constexpr int ROWS_BYTES = (PREC == NVDB_BF16) ? 32 * ROW_ELEMS * 2 : 32 * RB * 4;
-  static constexpr int SLOT_BYTES = 2 * ROWS_BYTES + 32 * C * 4;
-  static constexpr int WL_BYTES = (PREC == NVDB_BF16) ? (H - 1) * W * ROW_ELEMS * 2 : 0;
+  static constexpr int ROWS_BYTES = (PREC == NVDB_BF16) ? 32 * 256 : 32 * RB * 4;
+  // slot: G rows, input-activation rows, last-hidden-layer rows (head), gy [C][32].
+  // The FP32 form keeps the last hidden layer's rows in a private buffer per wave
+  // instead (written right after the forward pass) to free its registers.
+  static constexpr bool HH_PRIVATE = (PREC != NVDB_BF16);
+  static constexpr int SLOT_BYTES = (HH_PRIVATE ? 2 : 3) * ROWS_BYTES + 32 * C * 4;
+  static constexpr int HH_BYTES = HH_PRIVATE ? 4 * ROWS_BYTES : 0;
+  static constexpr int WL_BYTES = (PREC == NVDB_BF16) ? (H - 1) * W * 256 : 0;
   static constexpr int SMALL_FLOATS = H * W + C * W + 4 + 3 * (KP / 2) + 8;
-  static constexpr int LDS_BYTES = WL_BYTES + NSLOT * SLOT_BYTES + SMALL_FLOATS * 4;
+  static constexpr int LDS_BYTES = WL_BYTES + NSLOT * SLOT_BYTES + HH_BYTES + SMALL_FLOATS * 4;
   // dW blocks owned by a wave: waves form a 2 x 2 grid over (output, input) blocks.
   static constexpr int OBW = NB / 2;
   static constexpr int IBW0 = NIB0 / 2, IBW = NB / 2;
   static constexpr int IBWMAX = IBW0 > IBW ? IBW0 : IBW;
+  // the wave that sums the bias gradient of its output block a (spread over the two
+  // waves of a row of the 2 x 2 grid when each owns two output blocks)
+  static __device__ __forceinline__ bool bias_owner(int a, int wi) { return OBW == 1 ? wi == 0 : a == wi; }
 };
-
 
 template <int PREC, int W, int H, int KP, int C>
 __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) k_train(TrainLaunch L) {
   using P = PR<PREC>;
   using CF = TrainCfg<PREC, W, H, KP, C>;
-  constexpr int NB = CF::NB, NIB0 = CF::NIB0, SR = P::SR, OBW = CF::OBW, FPW = CF::FPW;
+  constexpr int NB = CF::NB, NIB0 = CF::NIB0, SR = P::SR, OBW = CF::OBW;
   constexpr bool BF = (PREC == NVDB_BF16);
   __shared__ __attribute__((aligned(16))) char smem[CF::LDS_BYTES];
 
   const TrainNet& TN = L.nets[blockIdx.y];
   const NetView& nv = TN.net;
   const SampleSpec& sp = TN.spec;
-  const int lane = lane_id(), wave = wave_id(), h = lane >> 5, fl = lane & 31;
+  const int wave = wave_id();
   const int64_t P_ = nv.s.nparams();
 
   // ---- LDS carve-up
-  __bf16* wl0 = (__bf16*)smem;                                   // bf16 layers 1..H-1
-  char* slots = smem + CF::WL_BYTES;
-  float* sm_bias0 = (float*)(slots + CF::NSLOT * CF::SLOT_BYTES);  // [H][W]
-  float* sm_whead0 = sm_bias0 + H * W;                             // [C][W]
-  float* sm_bhead0 = sm_whead0 + C * W;                            // [C] (padded to 4)
-  float* sm_benc0 = sm_bhead0 + 4;                                 // [KP/2][3]
-  float* sm_red = sm_benc0 + 3 * (KP / 2);                         // [8] reductions
+  char* wl0 = smem;                                                // bf16 layers 1..H-1
+  char* slots0 = smem + CF::WL_BYTES;
+  char* hh0 = slots0 + CF::NSLOT * CF::SLOT_BYTES;                  // FP32: per-wave rows of a_H
+  float* sm_bias0 = (float*)(hh0 + CF::HH_BYTES);                    // [H][W]
+  float* sm_whead0 = sm_bias0 + H * W;                              // [C][W]
+  float* sm_bhead0 = sm_whead0 + C * W;                             // [C] (padded to 4)
+  float* sm_benc0 = sm_bhead0 + 4;                                  // [KP/2][3]
+  float* sm_red = sm_benc0 + 3 * (KP / 2);                          // [8] reductions
 
   // ---- stage parameters
   if constexpr (BF) {
-    const u32x4* src = (const u32x4*)((const __bf16*)nv.wrow + (size_t)W * ROW_ELEMS);  // skip layer 0
+    const u32x4* src = (const u32x4*)((const char*)nv.wrow + (size_t)W * 256);  // skip layer 0
     u32x4* dst = (u32x4*)wl0;
     for (int i = threadIdx.x; i < CF::WL_BYTES / 16; i += blockDim.x) dst[i] = src[i];
   }
@@ -436,9 +509,11 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
     for (int a = 0; a < OBW; ++a)
 #pragma unroll
       for (int b = 0; b < CF::IBWMAX; ++b) dacc[l][a][b] = floatx16{};
-  float dbias[H];
+  float dbias[H][OBW];
 #pragma unroll
-  for (int l = 0; l < H; ++l) dbias[l] = 0.f;
+  for (int l = 0; l < H; ++l)
+#pragma unroll
+    for (int a = 0; a < OBW; ++a) dbias[l][a] = 0.f;
   float dwh[C], dbh[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) dwh[c] = dbh[c] = 0.f;
@@ -448,39 +523,48 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
   const int64_t n_iter = (sp.n + 127) / 128;
   float* partial = TN.partial + (size_t)blockIdx.x * P_;
 
-
   for (int64_t it = blockIdx.x; it < n_iter; it += L.G) {
+    const LaneK K = lane_consts();
+    const int h = K.h, fl = K.fl;
     const int z = opaque_zero();
     const float* sm_bias = sm_bias0 + z;
     const float* sm_whead = sm_whead0 + z;
     const float* sm_bhead = sm_bhead0 + z;
     const float* sm_benc = sm_benc0 + z;
-    __bf16* wl = wl0 + z;
+    const char* wl = wl0 + z;
+    char* slots = slots0 + z;
+    const bool first = (it == (int64_t)blockIdx.x);  // first iteration stores into the partial row
     const int64_t j = it * 128 + wave * 32 + fl;
     const Smp smp = fetch_sample(sp, L.tree, j);
 
     // ================= forward
     uint32_t Hs[H][NB][SR];  // Hs[l] = a_{l+1} (S layout), l = 0..H-1
     {
-      WFwd<PREC, W, KP> wf0{nullptr, (const u32x4*)nv.w1frag + z, (const float*)nv.wcol + z, 0};
       uint32_t X0[NIB0][SR];
       encode_S<PREC, NIB0>(smp, sm_benc, nv.nfreq, X0);
+      WFwd<PREC, W, KP> wf0{nullptr, (const u32x4*)nv.w1frag + z, (const float*)nv.wcol + z, true, &K};
 #pragma unroll
-      for (int ob = 0; ob < NB; ++ob) {
-        floatx16 a = layer_block<PREC, NIB0>(wf0, ob, X0);
-        bias_relu(a, sm_bias, ob);
-        P::store(a, Hs[0][ob]);
+      for (int ob = 0; ob < NB; ob += 2) {
+        floatx16 a0 = bias_acc(sm_bias, K, ob), a1 = bias_acc(sm_bias, K, ob + 1);
+        layer_block2<PREC, NIB0>(wf0, ob, X0, a0, a1);
+        relu16(a0);
+        relu16(a1);
+        P::store(a0, Hs[0][ob]);
+        P::store(a1, Hs[0][ob + 1]);
       }
     }
     static_for<1, H>([&](auto lc) {
       constexpr int l = decltype(lc)::value;
-      WFwd<PREC, W, KP> wf{wl + (size_t)(l - 1) * W * ROW_ELEMS, nullptr,
-                           (const float*)nv.wcol + z + (size_t)KP * W + (size_t)(l - 1) * W * W, l};
+      WFwd<PREC, W, KP> wf{wl + (size_t)(l - 1) * W * 256, nullptr,
+                           (const float*)nv.wcol + z + (size_t)KP * W + (size_t)(l - 1) * W * W, false, &K};
 #pragma unroll
-      for (int ob = 0; ob < NB; ++ob) {
-        floatx16 a = layer_block<PREC, NB>(wf, ob, Hs[l - 1]);
-        bias_relu(a, sm_bias + l * W, ob);
-        P::store(a, Hs[l][ob]);
+      for (int ob = 0; ob < NB; ob += 2) {
+        floatx16 a0 = bias_acc(sm_bias + l * W, K, ob), a1 = bias_acc(sm_bias + l * W, K, ob + 1);
+        layer_block2<PREC, NB>(wf, ob, Hs[l - 1], a0, a1);
+        relu16(a0);
+        relu16(a1);
+        P::store(a0, Hs[l][ob]);
+        P::store(a1, Hs[l][ob + 1]);
       }
     });
     // head (VALU): y_c = sum_f Wh[c][f] a_H[f] + bh[c]
@@ -491,15 +575,10 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
 #pragma unroll
       for (int ob = 0; ob < NB; ++ob)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          float av;
-          if constexpr (BF) {
-            uint32_t w = Hs[H - 1][ob][r >> 1];
-            av = __uint_as_float((r & 1) ? (w & 0xffff0000u) : (w << 16));
-          } else {
-            av = __uint_as_float(Hs[H - 1][ob][r]);
-          }
-          acc = fmaf(sm_whead[c * W + sfeat(ob, r, h)], av, acc);
+        for (int q = 0; q < 4; ++q) {
+          const floatx4 w4 = *(const floatx4*)(sm_whead + c * W + 32 * ob + 8 * q + 4 * h);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc = fmaf(w4[e], sval<PREC>(Hs[H - 1][ob], 4 * q + e), acc);
         }
       y[c] = acc + shfl_xor32(acc) + sm_bhead[c];
     }
@@ -512,57 +591,21 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
     for (int ob = 0; ob < NB; ++ob) {
       floatx16 g;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        float v = 0.f;
+      for (int q = 0; q < 4; ++q) {
+        floatx4 v = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int c = 0; c < C; ++c) v = fmaf(sm_whead[c * W + sfeat(ob, r, h)], gy[c], v);
-        g[r] = P::positive(Hs[H - 1][ob], r) ? v : 0.f;
+        for (int c = 0; c < C; ++c) {
+          const floatx4 w4 = *(const floatx4*)(sm_whead + c * W + 32 * ob + 8 * q + 4 * h);
+          v += w4 * gy[c];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) g[4 * q + e] = P::positive(Hs[H - 1][ob], 4 * q + e) ? v[e] : 0.f;
       }
       P::store(g, Gc[ob]);
     }
-
-    // ================= head gradients (rows of a_H and gy exchanged through LDS)
-#pragma unroll
-    for (int round = 0; round < 4 / CF::NSLOT; ++round) {
-      const int my_slot = wave - round * CF::NSLOT;
-      if (my_slot >= 0 && my_slot < CF::NSLOT) {
-        char* sl = slots + my_slot * CF::SLOT_BYTES;
-        if constexpr (BF) write_rows_bf16<NB>((__bf16*)(sl + CF::ROWS_BYTES), Hs[H - 1]);
-        else write_rows_f32<NB>((float*)(sl + CF::ROWS_BYTES), CF::RB, Hs[H - 1]);
-        if (h == 0) {
-          float* gyr = (float*)(sl + 2 * CF::ROWS_BYTES);
-#pragma unroll
-          for (int c = 0; c < C; ++c) gyr[fl * C + c] = gy[c];
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int sl_i = 0; sl_i < CF::NSLOT; ++sl_i) {
-        const char* sl = slots + sl_i * CF::SLOT_BYTES;
-        const float* gyr = (const float*)(sl + 2 * CF::ROWS_BYTES);
-        if (fl < FPW) {
-          const int f = FPW * wave + fl;
-#pragma unroll 4
-          for (int s = h; s < 32; s += 2) {
-            float av;
-            if constexpr (BF) av = row_elem_bf16((const __bf16*)(sl + CF::ROWS_BYTES), s, f);
-            else av = ((const float*)(sl + CF::ROWS_BYTES))[s * CF::RB + f];
-#pragma unroll
-            for (int c = 0; c < C; ++c) dwh[c] = fmaf(gyr[s * C + c], av, dwh[c]);
-          }
-        }
-        if (wave == 0) {
-#pragma unroll
-          for (int c = 0; c < C; ++c) {
-            if (fl == c) {
-              float acc = 0.f;
-              for (int s = h; s < 32; s += 2) acc += gyr[s * C + c];
-              dbh[c] += acc;
-            }
-          }
-        }
-      }
-      __syncthreads();
+    if constexpr (CF::HH_PRIVATE) {
+      // the previous iteration's readers of this buffer finished before its last barrier
+      write_rows_f32<NB>((float*)(hh0 + z + wave * CF::ROWS_BYTES), CF::RB, K, Hs[H - 1]);
     }
 
     // ================= backward through the hidden layers
@@ -570,6 +613,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
       constexpr int l = H - 1 - decltype(kc)::value;
       constexpr int NIBl = (l == 0) ? NIB0 : NB;
       constexpr int IBWl = NIBl / 2;
+      constexpr bool HEAD = (l == H - 1);
       // input activations a_l of layer l as rows (gamma recomputed for l = 0)
       uint32_t X0[NIB0][SR];
       if constexpr (l == 0) encode_S<PREC, NIB0>(smp, sm_benc, nv.nfreq, X0);
@@ -580,13 +624,21 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
         if (my_slot >= 0 && my_slot < CF::NSLOT) {
           char* sl = slots + my_slot * CF::SLOT_BYTES;
           if constexpr (BF) {
-            write_rows_bf16<NB>((__bf16*)sl, Gc);
-            if constexpr (l == 0) write_rows_bf16<NIB0>((__bf16*)(sl + CF::ROWS_BYTES), X0);
-            else write_rows_bf16<NB>((__bf16*)(sl + CF::ROWS_BYTES), Hs[l - 1 < 0 ? 0 : l - 1]);
+            write_rows_bf16<NB>(sl, K, Gc);
+            if constexpr (l == 0) write_rows_bf16<NIB0>(sl + CF::ROWS_BYTES, K, X0);
+            else write_rows_bf16<NB>(sl + CF::ROWS_BYTES, K, Hs[l - 1 < 0 ? 0 : l - 1]);
+            if constexpr (HEAD) write_rows_bf16<NB>(sl + 2 * CF::ROWS_BYTES, K, Hs[H - 1]);
           } else {
-            write_rows_f32<NB>((float*)sl, CF::RB, Gc);
-            if constexpr (l == 0) write_rows_f32<NIB0>((float*)(sl + CF::ROWS_BYTES), CF::RB, X0);
-            else write_rows_f32<NB>((float*)(sl + CF::ROWS_BYTES), CF::RB, Hs[l - 1 < 0 ? 0 : l - 1]);
+            write_rows_f32<NB>((float*)sl, CF::RB, K, Gc);
+            if constexpr (l == 0) write_rows_f32<NIB0>((float*)(sl + CF::ROWS_BYTES), CF::RB, K, X0);
+            else write_rows_f32<NB>((float*)(sl + CF::ROWS_BYTES), CF::RB, K, Hs[l - 1 < 0 ? 0 : l - 1]);
+          }
+          if constexpr (HEAD) {
+            if (h == 0) {
+              float* gyr = (float*)(sl + (CF::HH_PRIVATE ? 2 : 3) * CF::ROWS_BYTES);
+#pragma unroll
+              for (int c = 0; c < C; ++c) gyr[c * 32 + fl] = gy[c];
+            }
           }
         }
         __syncthreads();
@@ -599,14 +651,18 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
 #pragma unroll
             for (int a = 0; a < OBW; ++a) {
               const int ob = wo * OBW + a;
-              if constexpr (BF) ga[a] = frag_cols_bf16((const __bf16*)sl, 16 * kk, 32 * ob);
+              if constexpr (BF) ga[a] = frag_tr(sl, K, 16 * kk, ob);
               else ga[a] = ((const float*)sl)[(2 * kk + h) * CF::RB + 32 * ob + fl];
+              if (CF::bias_owner(a, wi)) {  // bias gradient: column sums of g over the samples
+                if constexpr (BF) dbias[l][a] = frag_sum(ga[a], dbias[l][a]);
+                else dbias[l][a] += ga[a];
+              }
             }
 #pragma unroll
             for (int b = 0; b < CF::IBWMAX; ++b) {
               if (b < IBWl) {
                 const int ib = wi * IBWl + b;
-                if constexpr (BF) hb[b] = frag_cols_bf16((const __bf16*)(sl + CF::ROWS_BYTES), 16 * kk, 32 * ib);
+                if constexpr (BF) hb[b] = frag_tr(sl + CF::ROWS_BYTES, K, 16 * kk, ib);
                 else hb[b] = ((const float*)(sl + CF::ROWS_BYTES))[(2 * kk + h) * CF::RB + 32 * ib + fl];
               }
             }
@@ -615,17 +671,41 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
 #pragma unroll
               for (int b = 0; b < CF::IBWMAX; ++b)
                 if (b < IBWl) dacc[l][a][b] = P::mma(ga[a], hb[b], dacc[l][a][b]);
-          }
-          // bias gradient: column sums of the g rows
-          if (fl < FPW) {
-            const int f = FPW * wave + fl;
-            float acc = 0.f;
-#pragma unroll 4
-            for (int s = h; s < 32; s += 2) {
-              if constexpr (BF) acc += row_elem_bf16((const __bf16*)sl, s, f);
-              else acc += ((const float*)sl)[s * CF::RB + f];
+            if constexpr (HEAD) {
+              // head weights and bias: wave w owns the head's input block w (if it exists)
+              const float* gyr = (const float*)(sl + (CF::HH_PRIVATE ? 2 : 3) * CF::ROWS_BYTES);
+              if (wave < NB) {
+                if constexpr (BF) {
+                  const bf16x8 hh = frag_tr(sl + 2 * CF::ROWS_BYTES, K, 16 * kk, wave);
+                  const u32x4 u = __builtin_bit_cast(u32x4, hh);
+#pragma unroll
+                  for (int c = 0; c < C; ++c) {
+                    const floatx4 g0 = *(const floatx4*)(gyr + c * 32 + 16 * kk + 4 * h);
+                    const floatx4 g1 = *(const floatx4*)(gyr + c * 32 + 16 * kk + 8 + 4 * h);
+                    float acc = dwh[c];
+                    acc = fmaf(g0[0], bf16_lo(u[0]), acc);
+                    acc = fmaf(g0[1], bf16_hi(u[0]), acc);
+                    acc = fmaf(g0[2], bf16_lo(u[1]), acc);
+                    acc = fmaf(g0[3], bf16_hi(u[1]), acc);
+                    acc = fmaf(g1[0], bf16_lo(u[2]), acc);
+                    acc = fmaf(g1[1], bf16_hi(u[2]), acc);
+                    acc = fmaf(g1[2], bf16_lo(u[3]), acc);
+                    acc = fmaf(g1[3], bf16_hi(u[3]), acc);
+                    dwh[c] = acc;
+                    if (wave == 0) dbh[c] += ((g0[0] + g0[1]) + (g0[2] + g0[3])) + ((g1[0] + g1[1]) + (g1[2] + g1[3]));
+                  }
+                } else {
+                  const float* hhr = (const float*)(hh0 + z + (round * CF::NSLOT + sl_i) * CF::ROWS_BYTES);
+                  const float hv = hhr[(2 * kk + h) * CF::RB + 32 * wave + fl];
+#pragma unroll
+                  for (int c = 0; c < C; ++c) {
+                    const float g = gyr[c * 32 + 2 * kk + h];
+                    dwh[c] = fmaf(g, hv, dwh[c]);
+                    if (wave == 0) dbh[c] += g;
+                  }
+                }
+              }
             }
-            dbias[l] += acc;
           }
         }
         __syncthreads();
@@ -646,7 +726,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
                 for (int r = 0; r < 16; ++r) {
                   const int o = sfeat(ob, r, h);
                   float* p = partial + nv.s.woff(l) + (size_t)o * win + i;
-                  *p += dacc[l][a][b][r];
+                  *p = first ? dacc[l][a][b][r] : *p + dacc[l][a][b][r];
                 }
               }
               dacc[l][a][b] = floatx16{};
@@ -656,15 +736,20 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
 
       if constexpr (l > 0) {
         // g_l = (W_l^T g_{l+1}) * 1[a_l > 0]
-        WBwd<PREC, W> wb{wl + (size_t)(l - 1) * W * ROW_ELEMS,
-                         (const float*)nv.wrow + z + (size_t)W * KP + (size_t)(l - 1) * W * W};
+        WBwd<PREC, W> wb{wl + (size_t)(l - 1) * W * 256,
+                         (const float*)nv.wrow + z + (size_t)W * KP + (size_t)(l - 1) * W * W, &K};
         uint32_t Gn[NB][SR];
 #pragma unroll
-        for (int ib = 0; ib < NB; ++ib) {
-          floatx16 a = layer_block<PREC, NB>(wb, ib, Gc);
+        for (int ib = 0; ib < NB; ib += 2) {
+          floatx16 a0 = floatx16{}, a1 = floatx16{};
+          layer_block2<PREC, NB>(wb, ib, Gc, a0, a1);
 #pragma unroll
-          for (int r = 0; r < 16; ++r) a[r] = P::positive(Hs[l - 1][ib], r) ? a[r] : 0.f;
-          P::store(a, Gn[ib]);
+          for (int r = 0; r < 16; ++r) {
+            a0[r] = P::positive(Hs[l - 1][ib], r) ? a0[r] : 0.f;
+            a1[r] = P::positive(Hs[l - 1][ib + 1], r) ? a1[r] : 0.f;
+          }
+          P::store(a0, Gn[ib]);
+          P::store(a1, Gn[ib + 1]);
         }
 #pragma unroll
         for (int ib = 0; ib < NB; ++ib)
@@ -675,6 +760,19 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
   }
 
   // ---- write this work-group's partial gradient row
+  const int h = lane_id() >> 5, fl = lane_id() & 31;
+  if constexpr (CF::any_rmw) {
+    // a work-group without iterations still owes zeros in the rows it would have accumulated
+    if ((int64_t)blockIdx.x >= n_iter) {
+      static_for<0, H>([&](auto lc) {
+        constexpr int l = decltype(lc)::value;
+        if constexpr (!CF::reg_layer(l)) {
+          const int64_t n_el = (int64_t)W * nv.s.win(l);
+          for (int64_t q = threadIdx.x; q < n_el; q += blockDim.x) partial[nv.s.woff(l) + q] = 0.f;
+        }
+      });
+    }
+  }
   if constexpr (CF::DWREG) {
     static_for<0, H>([&](auto lc) {
       constexpr int l = decltype(lc)::value;
@@ -700,37 +798,38 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
         }
     });
   }
-  // biases and head: combine the two lane halves, lanes of the low half write
+  // biases (waves of the first input column own them) and head: combine the lane halves
 #pragma unroll
-  for (int l = 0; l < H; ++l) {
-    float v = dbias[l] + shfl_xor32(dbias[l]);
-    if (h == 0 && fl < FPW) partial[nv.s.boff(l) + FPW * wave + fl] = v;
-  }
+  for (int l = 0; l < H; ++l)
+#pragma unroll
+    for (int a = 0; a < OBW; ++a) {
+      const float v = dbias[l][a] + shfl_xor32(dbias[l][a]);
+      if (CF::bias_owner(a, wi) && h == 0) partial[nv.s.boff(l) + 32 * (wo * OBW + a) + fl] = v;
+    }
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    float v = dwh[c] + shfl_xor32(dwh[c]);
-    if (h == 0 && fl < FPW) partial[nv.s.woff(H) + (size_t)c * W + FPW * wave + fl] = v;
-    float b = dbh[c] + shfl_xor32(dbh[c]);
-    if (wave == 0 && h == 0 && fl == c) partial[nv.s.boff(H) + c] = b;
+    const float v = dwh[c] + shfl_xor32(dwh[c]);
+    if (wave < NB && h == 0) partial[nv.s.woff(H) + (size_t)c * W + 32 * wave + fl] = v;
+    const float b = dbh[c] + shfl_xor32(dbh[c]);
+    if (wave == 0 && lane_id() == 0) partial[nv.s.boff(H) + c] = b;
   }
   // loss: fixed-order reduction over the wave, then over the four waves
   float v = loss_acc;
 #pragma unroll
   for (int off = 16; off >= 1; off >>= 1) {
-    int src = (lane ^ off) << 2;
+    int src = (lane_id() ^ off) << 2;
     v += __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(v)));
   }
-  if (lane == 0) sm_red[wave] = v;
+  if (lane_id() == 0) sm_red[wave] = v;
   __syncthreads();
   if (threadIdx.x == 0) TN.loss_partial[blockIdx.x] = ((sm_red[0] + sm_red[1]) + sm_red[2]) + sm_red[3];
 }
 
 // ============================================================== inference kernel
-
 template <int PREC, int W, int H, int KP, int C>
 struct InferCfg {
   static constexpr int NT = (PREC == NVDB_BF16) ? 2 : 1;  // 32-sample tiles per wave sharing each weight fragment
-  static constexpr int WL_BYTES = (PREC == NVDB_BF16) ? H * W * ROW_ELEMS * 2 : 0;
+  static constexpr int WL_BYTES = (PREC == NVDB_BF16) ? H * W * 256 : 0;
   static constexpr int SMALL_FLOATS = H * W + C * W + 4 + 3 * (KP / 2);
   static constexpr int LDS_BYTES = WL_BYTES + SMALL_FLOATS * 4;
 };
@@ -740,13 +839,14 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
   using P = PR<PREC>;
   using CF = InferCfg<PREC, W, H, KP, C>;
   constexpr int NB = W / 32, NIB0 = KP / 32, SR = P::SR, NT = CF::NT;
+  constexpr int NA = NB > NIB0 ? NB : NIB0;
   constexpr bool BF = (PREC == NVDB_BF16);
   __shared__ __attribute__((aligned(16))) char smem[CF::LDS_BYTES];
   const NetView& nv = I.net;
   const SampleSpec& sp = I.spec;
-  const int lane = lane_id(), wave = wave_id(), h = lane >> 5, fl = lane & 31;
+  const int wave = wave_id();
 
-  __bf16* wl0 = (__bf16*)smem;
+  char* wl0 = smem;
   float* sm_bias0 = (float*)(smem + CF::WL_BYTES);
   float* sm_whead0 = sm_bias0 + H * W;
   float* sm_bhead0 = sm_whead0 + C * W;
@@ -765,19 +865,20 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
   const int64_t per_wave = 32 * NT;
   const int64_t stride = (int64_t)gridDim.x * 4 * per_wave;
   for (int64_t base = ((int64_t)blockIdx.x * 4 + wave) * per_wave; base < sp.n; base += stride) {
+    const LaneK K = lane_consts();
+    const int h = K.h, fl = K.fl;
     const int z = opaque_zero();
     const float* sm_bias = sm_bias0 + z;
     const float* sm_whead = sm_whead0 + z;
     const float* sm_bhead = sm_bhead0 + z;
     const float* sm_benc = sm_benc0 + z;
-    __bf16* wl = wl0 + z;
-    uint32_t A[NT][NB > NIB0 ? NB : NIB0][SR];
-    Smp smp[NT];
+    const char* wl = wl0 + z;
+    uint32_t A[NT][NA][SR];
 #pragma unroll
     for (int u = 0; u < NT; ++u) {
-      smp[u] = fetch_sample(sp, I.tree, base + 32 * u + fl);
+      const Smp smp = fetch_sample(sp, I.tree, base + 32 * u + fl);
       uint32_t X0[NIB0][SR];
-      encode_S<PREC, NIB0>(smp[u], sm_benc, nv.nfreq, X0);
+      encode_S<PREC, NIB0>(smp, sm_benc, nv.nfreq, X0);
 #pragma unroll
       for (int t = 0; t < NIB0; ++t)
 #pragma unroll
@@ -786,28 +887,27 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
     static_for<0, H>([&](auto lc) {
       constexpr int l = decltype(lc)::value;
       constexpr int NIBl = (l == 0) ? NIB0 : NB;
-      WFwd<PREC, W, KP> wf{wl + (size_t)l * W * ROW_ELEMS, (const u32x4*)nv.w1frag + z,
-                           (const float*)nv.wcol + z + (l == 0 ? 0 : (size_t)KP * W + (size_t)(l - 1) * W * W), BF ? 1 : l};
+      WFwd<PREC, W, KP> wf{wl + (size_t)l * W * 256, nullptr,
+                           (const float*)nv.wcol + z + (l == 0 ? 0 : (size_t)KP * W + (size_t)(l - 1) * W * W), false, &K};
       uint32_t Bn[NT][NB][SR];
 #pragma unroll
       for (int ob = 0; ob < NB; ++ob) {
         floatx16 acc[NT];
+        const floatx16 b0 = bias_acc(sm_bias + l * W, K, ob);
 #pragma unroll
-        for (int u = 0; u < NT; ++u) acc[u] = floatx16{};
+        for (int u = 0; u < NT; ++u) acc[u] = b0;
 #pragma unroll
-        for (int t = 0; t < (NB > NIB0 ? NB : NIB0); ++t) {
-          if (t < NIBl) {
+        for (int t = 0; t < NIBl; ++t) {
 #pragma unroll
-            for (int kk = 0; kk < P::KS; ++kk) {
-              typename P::Frag af = wf(ob, t, kk);
+          for (int kk = 0; kk < P::KS; ++kk) {
+            typename P::Frag af = wf(ob, t, kk);
 #pragma unroll
-              for (int u = 0; u < NT; ++u) acc[u] = P::mma(af, P::sfrag(A[u][t], kk), acc[u]);
-            }
+            for (int u = 0; u < NT; ++u) acc[u] = P::mma(af, P::sfrag(A[u][t], kk), acc[u]);
           }
         }
 #pragma unroll
         for (int u = 0; u < NT; ++u) {
-          bias_relu(acc[u], sm_bias + l * W, ob);
+          relu16(acc[u]);
           P::store(acc[u], Bn[u][ob]);
         }
       }
@@ -828,23 +928,21 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
 #pragma unroll
         for (int ob = 0; ob < NB; ++ob)
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            float av;
-            if constexpr (BF) {
-              uint32_t w = A[u][ob][r >> 1];
-              av = __uint_as_float((r & 1) ? (w & 0xffff0000u) : (w << 16));
-            } else {
-              av = __uint_as_float(A[u][ob][r]);
-            }
-            acc = fmaf(sm_whead[c * W + sfeat(ob, r, h)], av, acc);
+          for (int q = 0; q < 4; ++q) {
+            const floatx4 w4 = *(const floatx4*)(sm_whead + c * W + 32 * ob + 8 * q + 4 * h);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc = fmaf(w4[e], sval<PREC>(A[u][ob], 4 * q + e), acc);
           }
         y[u][c] = acc + shfl_xor32(acc) + sm_bhead[c];
       }
     // outputs
     if (I.out_kind == OUT_MASK) {
-      uint64_t b0 = __ballot(y[0][0] > 0.f) & 0xffffffffull;
-      uint64_t b1 = __ballot((NT > 1 ? y[NT - 1][0] : 0.f) > 0.f) & 0xffffffffull;
-      if (lane == 0 && base < sp.n) I.mask[base >> 6] = b0 | (b1 << 32);
+      // one 32-bit word per 32-slot tile (the mask words are little-endian uint64)
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        const uint32_t bits = (uint32_t)(__ballot(y[u][0] > 0.f) & 0xffffffffull);
+        if (lane_id() == 0 && base + 32 * u < sp.n) ((uint32_t*)I.mask)[(base + 32 * u) >> 5] = bits;
+      }
     } else {
 #pragma unroll
       for (int u = 0; u < NT; ++u) {
@@ -857,7 +955,10 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
             float bv = y[u][0];
 #pragma unroll
             for (int c = 1; c < C; ++c)
-              if (y[u][c] > bv) { bv = y[u][c]; best = c; }
+              if (y[u][c] > bv) {
+                bv = y[u][c];
+                best = c;
+              }
             I.cls[j] = (uint8_t)best;
           } else {
 #pragma unroll
@@ -945,8 +1046,7 @@ __global__ void k_sample(uint64_t sseed, uint32_t npop, int64_t n, uint32_t* out
 template <int PREC, int W, int H, int KP, int C>
 KernelSet make_set() {
   return KernelSet{k_train<PREC, W, H, KP, C>, k_infer<PREC, W, H, KP, C>,
-                   TrainCfg<PREC, W, H, KP, C>::LDS_BYTES, InferCfg<PREC, W, H, KP, C>::LDS_BYTES,
-                   TrainCfg<PREC, W, H, KP, C>::any_rmw};
+                   TrainCfg<PREC, W, H, KP, C>::LDS_BYTES, InferCfg<PREC, W, H, KP, C>::LDS_BYTES};
 }
 
 // Shapes with compiled kernels: (W, H, KP, C).

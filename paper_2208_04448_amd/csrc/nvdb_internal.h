@@ -223,7 +223,6 @@ struct KernelSet {
   void (*train)(TrainLaunch);
   void (*infer)(InferLaunch);
   int train_lds, infer_lds;
-  bool train_needs_zeroed_partial;
 };
 
 // mlp.hip

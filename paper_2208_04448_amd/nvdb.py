@@ -50,7 +50,7 @@ class ModelDesc(C.Structure):
 class FitDesc(C.Structure):
     _fields_ = [("steps", C.c_int32), ("batch", C.c_int32), ("seed", C.c_uint64), ("lr", C.c_float),
                 ("lr_decay", C.c_float), ("lr_interval", C.c_int32), ("nets_mask", C.c_int32),
-                ("idx_dev", C.c_void_p * 3), ("idx_count", C.c_int64 * 3)]
+                ("idx_dev", C.c_void_p * 3), ("idx_count", C.c_int64 * 3), ("train_kernel_ms", C.c_void_p)]
 
 
 class ErrorReport(C.Structure):
@@ -141,7 +141,7 @@ class Tree:
         return out
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and _lib is not None:
             _lib.nvdb_tree_free(self.h)
             self.h = None
 
@@ -198,9 +198,13 @@ class Model:
                                              v.ctypes.data_as(C.c_void_p), m.size, int(step)))
 
     def fit(self, tree, steps, batch, nets_mask, seed=0, lr=1e-3, lr_decay=0.975, lr_interval=100, idx=None,
-            return_losses=True):
-        """Run `steps` Adam steps.  idx: optional {net: int32/uint32 device tensor} of sample indices."""
+            return_losses=True, kernel_times=None):
+        """Run `steps` Adam steps.  idx: optional {net: int32/uint32 device tensor} of sample indices.
+        kernel_times: optional dict that receives 'train_kernel_ms' (HIP events around the launches)."""
         f = FitDesc()
+        tk = C.c_float(0.0)
+        if kernel_times is not None:
+            f.train_kernel_ms = C.cast(C.pointer(tk), C.c_void_p)
         f.steps, f.batch, f.seed = steps, batch, seed
         f.lr, f.lr_decay, f.lr_interval, f.nets_mask = lr, lr_decay, lr_interval, nets_mask
         keep = []
@@ -211,6 +215,8 @@ class Model:
         losses = np.zeros((MAX_NETS, max(steps, 1)), np.float32) if return_losses else None
         _check(_lib.nvdb_fit(self.h, tree.h, C.byref(f),
                              losses.ctypes.data_as(C.c_void_p) if return_losses else None, _stream()))
+        if kernel_times is not None:
+            kernel_times["train_kernel_ms"] = tk.value
         return losses[:, :steps] if return_losses else None
 
     def decode(self, tree, values=True, masks=True):
@@ -243,7 +249,7 @@ class Model:
         return g
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and _lib is not None:
             _lib.nvdb_model_free(self.h)
             self.h = None
 

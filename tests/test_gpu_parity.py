@@ -1,0 +1,406 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Tolerances (derived in DESIGN.md, section "Tolerances"):
+  * integer work (tree arrays, sample indices, mask bits away from the decision
+    boundary): bit-exact;
+  * FP32 form: forward |dy| <= 1e-5 (1 + |y|); gradients <= 1e-5 relative (L2)
+    per layer; values after a short fit <= 1e-3 relative (Adam amplifies the
+    last-bit differences of near-zero gradients);
+  * BF16 form: forward |dy| <= 2e-2 (outputs are in normalised units, |y| <~ 1);
+    gradients <= 0.2 relative per layer with cosine >= 0.98 (an FP64 computation
+    that rounds the same operands to bf16 lands at 0.06-0.09 on these cases).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import fit as F, mlp, sampler as S, tree as T
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+SHAPES = [  # (W, H, n_freq, n_out, net id)
+    (64, 3, 18, 1, 0),
+    (128, 4, 64, 1, 0),
+    (128, 3, 64, 1, 1),
+    (64, 4, 64, 3, 2),
+]
+
+
+def enc_matrix(m, seed):
+    return workloads.pe_matrix(6) if m == 18 else workloads.ffm_matrix(m, 10.0, seed=seed)
+
+
+def model_for(nvdb, shape, prec, domain=64, seed=1):
+    W, H, m, c, net = shape
+    K = 2 * m
+    theta = workloads.init_params(K, W, H, c, seed=seed)
+    B = enc_matrix(m, seed + 1)
+    model = nvdb.Model({net: (W, H, m, c)}, precision=prec, domain_size=domain, value_scale=3.0)
+    model.set_params(net, theta)
+    model.set_encoding(net, B)
+    return model, theta.astype(np.float64), B.astype(np.float64), mlp.layer_shapes(K, W, H, c)
+
+
+def layer_rel_errors(g, go, shapes):
+    offs = np.cumsum([0] + [o * i + o for o, i in shapes])
+    return [float(np.linalg.norm(g[a:b] - go[a:b]) / max(np.linalg.norm(go[a:b]), 1e-30))
+            for a, b in zip(offs[:-1], offs[1:])]
+
+
+# --------------------------------------------------------------------------- sampler
+@pytest.mark.parametrize("seed,stream,step,npop,batch", [
+    (0, 0, 0, 43878, 4096), (12345, 1, 77, 131584, 10000), (9, 2, 5, 2 ** 31 + 7, 3000), (0, 0, 1999, 5_000_000, 1 << 18),
+    (7, 1, 3, 1, 65), (0, 0, 0, 43878, 1 << 22)])
+def test_sampler_bit_exact(gpu_lib, seed, stream, step, npop, batch):
+    g = gpu_lib.sample_indices(seed, stream, step, npop, batch).cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    assert np.array_equal(g, S.iid_indices(seed, stream, step, batch, npop))
+
+
+# --------------------------------------------------------------------------- tree
+TREE_CASES = [
+    ("sphere64", lambda: workloads.sphere_sdf(), (0, 0, 0), T.SDF, 3.0),
+    ("fog_negative_origin", lambda: torch.randn(40, 23, 70, generator=torch.Generator().manual_seed(0)),
+     (4090, -130, 100), T.FOG, 1.2),
+    ("ragged_sdf", lambda: workloads.sphere_sdf(n=37, center=(10.0, 30.0, 5.0), radius=17.0)[:, :29, :31].contiguous(),
+     (-4100, 4093, -7), T.SDF, 2.0),
+    ("empty", lambda: torch.full((9, 10, 11), 50.0), (0, 0, 0), T.SDF, 3.0),
+    ("single_voxel", lambda: torch.where(torch.arange(5 * 6 * 7).reshape(5, 6, 7) == 101, 0.0, 9.0), (-1, -1, -1),
+     T.SDF, 1.0),
+]
+
+
+@pytest.mark.parametrize("name,make,origin,kind,thr", TREE_CASES, ids=[c[0] for c in TREE_CASES])
+def test_tree_bit_exact(gpu_lib, name, make, origin, kind, thr):
+    grid = make().float()
+    tr = gpu_lib.Tree(grid.to(DEV), origin, kind, thr)
+    ex = tr.export()
+    ijk, vals = T.active_set_dense(grid.numpy(), origin, kind, thr)
+    ot = T.build(ijk, vals)
+    info = tr.info()
+    assert (info.n_voxels, info.n_leaves, info.n_l1, info.n_l2) == (
+        len(ot["values"]), len(ot["leaf_origin"]), len(ot["l1_origin"]), len(ot["l2_origin"]))
+    assert np.array_equal(ex["leaf_origin"], ot["leaf_origin"])
+    assert np.array_equal(ex["leaf_mask"], ot["leaf_mask"])
+    assert np.array_equal(ex["leaf_off"].astype(np.int64), ot["leaf_off"])
+    assert np.array_equal(ex["values"].astype(np.float64), ot["values"])
+    assert np.array_equal(ex["l1_origin"], ot["l1_origin"])
+    assert np.array_equal(ex["l1_child"], ot["l1_child"])
+    b = T.explicit_bytes(info.n_leaves, info.n_l1, info.n_l2)
+    assert (info.bytes_l2, info.bytes_l1, info.bytes_leaf_masks, info.bytes_voxels) == (
+        b["l2"], b["l1"], b["leaf_mask"], b["voxels"])
+
+
+def test_tree_rejects_nan(gpu_lib):
+    g = workloads.sphere_sdf(n=16, center=(8.0, 8.0, 8.0), radius=5.0)
+    g[3, 4, 5] = float("nan")
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        gpu_lib.Tree(g.to(DEV), (0, 0, 0), T.SDF, 3.0)
+    assert e.value.code == gpu_lib.E_INVALID
+
+
+# --------------------------------------------------------------------------- forward / backward
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("shape", SHAPES, ids=["%dx%d_m%d_c%d" % s[:4] for s in SHAPES])
+@pytest.mark.parametrize("n", [1, 33, 1000, 4097])
+def test_forward_parity(gpu_lib, prec, shape, n):
+    p = gpu_lib.FP32 if prec == "fp32" else gpu_lib.BF16
+    model, theta, B, shapes = model_for(gpu_lib, shape, p)
+    x = np.random.default_rng(n).random((n, 3)).astype(np.float32)
+    y = model.forward(shape[4], torch.from_numpy(x).to(DEV)).cpu().numpy()
+    yo = mlp.predict(mlp.unflatten(theta, shapes), x.astype(np.float64), B)
+    if p == gpu_lib.FP32:
+        assert np.all(np.abs(y - yo) <= 1e-5 * (1 + np.abs(yo)))
+    else:
+        assert np.max(np.abs(y - yo)) <= 2e-2
+
+
+def away_from_kinks(theta, shapes, B, x, margin):
+    """Rows of x whose hidden pre-activations all satisfy |z| > margin.  A ReLU whose
+    input lies within rounding of zero may switch between the FP32 kernel and the FP64
+    oracle, which changes the gradient by a whole term; such inputs are excluded."""
+    _, cache = mlp.forward(mlp.unflatten(theta, shapes), mlp.encode(x.astype(np.float64), B))
+    zmin = np.min(np.stack([np.abs(cache[i]).min(axis=1) for i in range(1, len(cache), 2)]), axis=0)
+    return x[zmin > margin]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("shape", SHAPES, ids=["%dx%d_m%d_c%d" % s[:4] for s in SHAPES])
+@pytest.mark.parametrize("n", [77, 3000])
+def test_backward_parity(gpu_lib, prec, shape, n):
+    p = gpu_lib.FP32 if prec == "fp32" else gpu_lib.BF16
+    model, theta, B, shapes = model_for(gpu_lib, shape, p)
+    rng = np.random.default_rng(n + 5)
+    x = rng.random((2 * n, 3)).astype(np.float32)
+    if p == gpu_lib.FP32:
+        x = away_from_kinks(theta, shapes, B, x, 1e-5)
+    x = x[:n]
+    assert len(x) == n
+    gy = rng.standard_normal((n, shape[3])).astype(np.float32)
+    g = model.backward(shape[4], torch.from_numpy(x).to(DEV), torch.from_numpy(gy).to(DEV)).cpu().numpy()
+    go = F.param_grad(theta, shapes, B, x.astype(np.float64), gy.astype(np.float64))
+    errs = layer_rel_errors(g.astype(np.float64), go, shapes)
+    if p == gpu_lib.FP32:
+        assert max(errs) <= 1e-5, errs
+    else:
+        assert max(errs) <= 0.2, errs
+        cos = float(g @ go / (np.linalg.norm(g) * np.linalg.norm(go)))
+        assert cos >= 0.98
+
+
+def test_backward_deterministic(gpu_lib):
+    model, theta, B, shapes = model_for(gpu_lib, SHAPES[1], gpu_lib.BF16)
+    x = torch.rand(50000, 3, device=DEV, generator=torch.Generator(DEV).manual_seed(3))
+    gy = torch.randn(50000, 1, device=DEV, generator=torch.Generator(DEV).manual_seed(4))
+    a = model.backward(0, x, gy)
+    b = model.backward(0, x, gy)
+    assert torch.equal(a, b)
+
+
+# --------------------------------------------------------------------------- fit, decode, errors (C1)
+@pytest.fixture(scope="module")
+def sphere(gpu_lib):
+    v = workloads.sphere_sdf()
+    tr = gpu_lib.Tree(v.to(DEV), (0, 0, 0), T.SDF, 3.0)
+    ijk, vals = T.active_set_dense(v.numpy(), (0, 0, 0), T.SDF, 3.0)
+    return tr, T.build(ijk, vals)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_fit_one_epoch_parity(gpu_lib, sphere, prec):
+    """C1: one pass over a seeded permutation at batch 4096 (11 regressor steps, the
+    last of 2,918 samples; 33 level-0 classifier steps), then full decode."""
+    tr, ot = sphere
+    p = gpu_lib.FP32 if prec == "fp32" else gpu_lib.BF16
+    shapes = mlp.layer_shapes(36, 64, 3, 1)
+    B = workloads.pe_matrix(6)
+    th0 = {0: workloads.init_params(36, 64, 3, 1, seed=0), 1: workloads.init_params(36, 64, 3, 1, seed=1)}
+    perm = {0: workloads.epoch_permutation(43878, seed=5), 1: workloads.epoch_permutation(512 * 257, seed=6)}
+    model = gpu_lib.Model({0: (64, 3, 18, 1), 1: (64, 3, 18, 1)}, precision=p, domain_size=64, value_scale=3.0)
+    steps = {0: 11, 1: 33}
+    losses = {}
+    for k in (0, 1):
+        model.set_params(k, th0[k])
+        model.set_encoding(k, B)
+        idx = torch.from_numpy(perm[k].astype(np.int32)).to(DEV)
+        losses[k] = model.fit(tr, steps=steps[k], batch=4096, nets_mask=1 << k, idx={k: idx})[k]
+    for k, net in ((0, "regressor"), (1, "l0")):
+        chunks = [perm[k][i:i + 4096] for i in range(0, len(perm[k]), 4096)]
+        assert len(chunks) == steps[k]
+        tho, _, _, lo = F.train(th0[k].astype(np.float64), shapes, B.astype(np.float64), ot, net, (0, 0, 0), 64,
+                                T.SDF, 3.0, steps=steps[k], batch=4096, idx_batches=chunks)
+        thg = model.get_params(k).astype(np.float64)
+        rel_loss = np.abs(losses[k] - lo) / np.abs(lo)
+        rel_theta = np.linalg.norm(thg - tho) / np.linalg.norm(tho - th0[k])
+        if p == gpu_lib.FP32:
+            # Adam steps a parameter whose gradient is zero up to rounding by up to +-lr
+            # either way, so the parameters are compared in aggregate; the loss
+            # trajectory is the sharp check.
+            assert rel_loss.max() <= 1e-5, rel_loss
+            assert rel_theta <= 2e-2, rel_theta
+        else:
+            assert rel_loss.max() <= 2e-2, rel_loss
+            assert rel_theta <= 0.3, rel_theta
+    # decode with the fitted weights against the oracle evaluated at the same weights
+    values, masks = model.decode(tr)
+    th_r = model.get_params(0).astype(np.float64)
+    vo = F.decode_values(th_r, shapes, B.astype(np.float64), ot, (0, 0, 0), 64, T.SDF, 3.0)
+    vtol = 3e-5 if p == gpu_lib.FP32 else 6e-2      # value units: band 3 x output tolerance
+    assert np.max(np.abs(values.cpu().numpy() - vo)) <= vtol
+    logits = F.decode_l0(model.get_params(1).astype(np.float64), shapes, B.astype(np.float64), ot, (0, 0, 0), 64)
+    mo = F.mask_from_logits(logits, len(ot["leaf_origin"]))
+    mg = masks.cpu().numpy().view(np.uint64)
+    diff = np.unpackbits((mg ^ mo).view(np.uint8), bitorder="little").astype(bool)
+    near = np.abs(logits.reshape(-1, 512)) <= (1e-5 if p == gpu_lib.FP32 else 2e-2)
+    near_bits = np.zeros_like(diff)
+    near_bits[:near.size] = near.reshape(-1)
+    assert not np.any(diff & ~near_bits)
+    # error report against the oracle's report on the same decoded values
+    rep = gpu_lib.errors(tr, values, masks)
+    orep = F.errors(ot, values.cpu().numpy().astype(np.float64), T.SDF, pred_mask=mg)
+    assert rep["n"] == orep["n"] and rep["fp"] == orep["fp"] and rep["fn"] == orep["fn"]
+    assert abs(rep["max_abs"] - orep["max_abs"]) <= 1e-6 * max(1.0, orep["max_abs"])
+    assert abs(rep["rms"] - orep["rms"]) <= 1e-9 * max(1.0, orep["rms"])
+    assert rep["iou"] == pytest.approx(orep["iou"], abs=1e-12)
+
+
+def test_fit_iid_matches_oracle_and_resumes(gpu_lib, sphere):
+    """i.i.d. SplitMix64 batches: 6 steps in one call equal 3 + 3 across a checkpoint."""
+    tr, ot = sphere
+    shapes = mlp.layer_shapes(36, 64, 3, 1)
+    B = workloads.pe_matrix(6)
+    th0 = workloads.init_params(36, 64, 3, 1, seed=3)
+    mk = lambda: gpu_lib.Model({0: (64, 3, 18, 1)}, precision=gpu_lib.FP32, domain_size=64, value_scale=3.0)
+    a = mk()
+    a.set_params(0, th0); a.set_encoding(0, B)
+    la = a.fit(tr, steps=6, batch=2048, nets_mask=1, seed=17)[0]
+    b = mk()
+    b.set_params(0, th0); b.set_encoding(0, B)
+    b.fit(tr, steps=3, batch=2048, nets_mask=1, seed=17)
+    m, v, s = b.get_opt_state(0)
+    c = mk()
+    c.set_params(0, b.get_params(0)); c.set_encoding(0, B); c.set_opt_state(0, m, v, s)
+    lc = c.fit(tr, steps=3, batch=2048, nets_mask=1, seed=17)[0]
+    assert np.array_equal(a.get_params(0), c.get_params(0))
+    assert np.array_equal(la[3:], lc)
+    _, _, _, lo = F.train(th0.astype(np.float64), shapes, B.astype(np.float64), ot, "regressor", (0, 0, 0), 64, T.SDF,
+                          3.0, steps=6, batch=2048, seed=17)
+    assert np.max(np.abs(la - lo) / lo) <= 1e-5
+
+
+def test_fit_state_and_input_errors(gpu_lib, sphere):
+    tr, _ = sphere
+    m = gpu_lib.Model({0: (64, 3, 18, 1)}, precision=gpu_lib.BF16, domain_size=64, value_scale=3.0)
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        m.fit(tr, steps=1, batch=16, nets_mask=1)
+    assert e.value.code == gpu_lib.E_STATE
+    m.set_params(0, workloads.init_params(36, 64, 3, 1, seed=0))
+    m.set_encoding(0, workloads.pe_matrix(6))
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        m.fit(tr, steps=1, batch=16, nets_mask=2)       # level-0 network not in the model
+    assert e.value.code == gpu_lib.E_INVALID
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        m.set_params(0, np.zeros(5, np.float32))
+    assert e.value.code == gpu_lib.E_INVALID
+    empty = gpu_lib.Tree(torch.full((8, 8, 8), 50.0, device=DEV), (0, 0, 0), T.SDF, 3.0)
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        m.fit(empty, steps=1, batch=16, nets_mask=1)
+    assert e.value.code == gpu_lib.E_INVALID
+
+
+def test_fit_divergence_is_reported(gpu_lib, sphere):
+    tr, _ = sphere
+    m = gpu_lib.Model({0: (64, 3, 18, 1)}, precision=gpu_lib.FP32, domain_size=64, value_scale=3.0)
+    m.set_params(0, workloads.init_params(36, 64, 3, 1, seed=0))
+    m.set_encoding(0, workloads.pe_matrix(6))
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        m.fit(tr, steps=40, batch=1024, nets_mask=1, lr=1e30)
+    assert e.value.code == gpu_lib.E_NUMERIC
+
+
+# --------------------------------------------------------------------------- level-1 classifier
+def test_l1_classifier_fit_and_decode(gpu_lib):
+    """Three-class node classifier over the leaf slots of the level-1 nodes (4x64, 3 logits)."""
+    v = workloads.sphere_sdf(n=200, center=(100.0, 90.0, 110.0), radius=70.0)
+    tr = gpu_lib.Tree(v.to(DEV), (0, 0, 0), T.SDF, 3.0)
+    ijk, vals = T.active_set_dense(v.numpy(), (0, 0, 0), T.SDF, 3.0)
+    ot = T.build(ijk, vals)
+    shapes = mlp.layer_shapes(128, 64, 4, 3)
+    B = workloads.ffm_matrix(64, 3.0, seed=4)
+    th0 = workloads.init_params(128, 64, 4, 3, seed=9)
+    for p, ltol in ((gpu_lib.FP32, 1e-5), (gpu_lib.BF16, 2e-2)):
+        m = gpu_lib.Model({2: (64, 4, 64, 3)}, precision=p, domain_size=256, value_scale=3.0)
+        m.set_params(2, th0)
+        m.set_encoding(2, B)
+        L = m.fit(tr, steps=4, batch=3000, nets_mask=4, seed=2)[2]
+        _, _, _, lo = F.train(th0.astype(np.float64), shapes, B.astype(np.float64), ot, "l1", (0, 0, 0), 256,
+                              T.SDF, 3.0, steps=4, batch=3000, seed=2)
+        assert np.max(np.abs(L - lo) / lo) <= ltol
+        cls = m.decode_l1(tr).cpu().numpy().reshape(-1)
+        lg = F.decode_l1(m.get_params(2).astype(np.float64), shapes, B.astype(np.float64), ot, (0, 0, 0), 256)
+        oc = F.l1_classes(lg)
+        srt = np.sort(lg, axis=1)
+        margin = srt[:, -1] - srt[:, -2]
+        ok = (cls == oc) | (margin <= (1e-5 if p == gpu_lib.FP32 else 3e-2))
+        assert ok.all()
+
+
+# --------------------------------------------------------------------------- full size (512^3)
+@pytest.fixture(scope="module")
+def c2(gpu_lib):
+    grid = workloads.noise_sphere_sdf(512, center=(256.0, 256.0, 256.0), radius=200.0, amplitude=20.0, octaves=4,
+                                      scale=64.0, seed=0, device=DEV)
+    ijk, vals = T.active_set_dense(grid.cpu().numpy(), (0, 0, 0), T.SDF, 3.0)
+    return grid, gpu_lib.Tree(grid, (0, 0, 0), T.SDF, 3.0), T.build(ijk, vals)
+
+
+def test_c2_tree_sampled_leaves(gpu_lib, c2):
+    """512^3 level set: counts and 64 sampled leaves against an oracle build of the
+    same active set; global invariants of the whole export."""
+    grid, tr, ot = c2
+    ex = tr.export()
+    info = tr.info()
+    assert info.n_voxels == len(ot["values"]) and info.n_leaves == len(ot["leaf_origin"]) and info.n_l1 == len(ot["l1_origin"])
+    rng = np.random.default_rng(0)
+    for li in rng.choice(info.n_leaves, 64, replace=False):
+        assert np.array_equal(ex["leaf_origin"][li], ot["leaf_origin"][li])
+        assert np.array_equal(ex["leaf_mask"][li], ot["leaf_mask"][li])
+        a, b = int(ot["leaf_off"][li]), int(ot["leaf_off"][li + 1])
+        assert int(ex["leaf_off"][li]) == a
+        assert np.array_equal(ex["values"][a:b].astype(np.float64), ot["values"][a:b])
+    assert np.array_equal(ex["l1_child"], ot["l1_child"])
+    assert int(ex["leaf_off"][-1]) == info.n_voxels
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_c2_decode_sampled(gpu_lib, c2, prec):
+    """Full decode at 512^3 in the launch configuration the benchmark times, checked
+    on 4096 sampled voxels and 64 sampled leaves' masks."""
+    grid, tr, ot = c2
+    p = gpu_lib.FP32 if prec == "fp32" else gpu_lib.BF16
+    W, H, m, c = 128, 4, 64, 1
+    shapes = mlp.layer_shapes(128, W, H, c)
+    B = {0: workloads.ffm_matrix(m, 10.0, seed=11), 1: workloads.ffm_matrix(m, 10.0, seed=12)}
+    th = {0: workloads.init_params(128, W, H, c, seed=21), 1: workloads.init_params(128, W, H, c, seed=22)}
+    model = gpu_lib.Model({0: (W, H, m, c), 1: (W, H, m, c)}, precision=p, domain_size=512, value_scale=3.0)
+    for k in (0, 1):
+        model.set_params(k, th[k])
+        model.set_encoding(k, B[k])
+    values, masks = model.decode(tr)
+    ex = tr.export()
+    rng = np.random.default_rng(1)
+    info = tr.info()
+    sel = rng.choice(info.n_voxels, 4096, replace=False)
+    # oracle coordinates of the sampled voxels come from the oracle's own tree
+    vo = F.decode_values(th[0].astype(np.float64), shapes, B[0].astype(np.float64), ot, (0, 0, 0), 512, T.SDF, 3.0,
+                         idx=sel)
+    tol = 3e-5 if p == gpu_lib.FP32 else 6e-2
+    assert np.max(np.abs(values.cpu().numpy()[sel] - vo)) <= tol
+    leaves = rng.choice(info.n_leaves, 64, replace=False)
+    slots = (leaves[:, None] * 512 + np.arange(512)[None, :]).reshape(-1)
+    lg = F.decode_l0(th[1].astype(np.float64), shapes, B[1].astype(np.float64), ot, (0, 0, 0), 512, slots=slots)
+    mg = masks.cpu().numpy().view(np.uint64)[leaves]
+    bits = np.unpackbits(mg.view(np.uint8), bitorder="little").reshape(64, 512).astype(bool)
+    want = (lg > 0).reshape(64, 512)
+    near = np.abs(lg).reshape(64, 512) <= (1e-5 if p == gpu_lib.FP32 else 2e-2)
+    assert not np.any((bits != want) & ~near)
+    _ = ex
+
+
+# --------------------------------------------------------------------------- C4 gradient check
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_c4_gradient_batch_2_22(gpu_lib, sphere, prec):
+    """Fused backward behind torch.autograd.Function at batch 2^22 (i.i.d. voxel samples
+    of the C1 volume, MSE loss) against the oracle's analytic gradient."""
+    tr, ot = sphere
+    p = gpu_lib.FP32 if prec == "fp32" else gpu_lib.BF16
+    shapes = mlp.layer_shapes(36, 64, 3, 1)
+    B = workloads.pe_matrix(6)
+    th = workloads.init_params(36, 64, 3, 1, seed=0)
+    model = gpu_lib.Model({0: (64, 3, 18, 1)}, precision=p, domain_size=64, value_scale=3.0)
+    model.set_params(0, th)
+    model.set_encoding(0, B)
+    n = 1 << 22
+    idx = S.iid_indices(0, 0, 0, n, len(ot["values"]))
+    x, t = F.net_inputs(ot, "regressor", idx, (0, 0, 0), 64, T.SDF, 3.0)
+    xd = torch.from_numpy(x.astype(np.float32)).to(DEV)
+    td = torch.from_numpy(t.astype(np.float32)).to(DEV)
+    Fn = gpu_lib.mlp_function()
+    theta = torch.zeros(len(th), device=DEV, requires_grad=True)
+    y = Fn.apply(model, 0, xd, theta)
+    loss = ((y[:, 0] - td) ** 2).mean()
+    loss.backward()
+    g = theta.grad.cpu().numpy().astype(np.float64)
+    # oracle: the same gradient in FP64, accumulated over chunks
+    thd = th.astype(np.float64)
+    go = np.zeros_like(thd)
+    params = mlp.unflatten(thd, shapes)
+    for i in range(0, n, 1 << 18):
+        xi, ti = x[i:i + (1 << 18)], t[i:i + (1 << 18)]
+        yo, cache = mlp.forward(params, mlp.encode(xi, B.astype(np.float64)))
+        gy = 2.0 * (yo[:, 0] - ti)[:, None] / n
+        go += mlp.flatten(mlp.backward(params, cache, gy))
+    errs = layer_rel_errors(g, go, shapes)
+    assert max(errs) <= (1e-4 if p == gpu_lib.FP32 else 5e-2), errs
