@@ -179,6 +179,39 @@ typedef struct {
 nvdb_status nvdb_fit(nvdb_model* model, const nvdb_tree* tree, const nvdb_fit_desc* fit, float* loss_host,
                      void* stream);
 
+/* Temporally coherent warm-start encoder for an animated sequence (Sec. 3.6).
+ * Frame 0 is fitted from the model's current parameters with `cold` (the
+ * target learning rate), then fitted again with `warm` (a rate up to 100x
+ * smaller).  Every later frame starts from the previous frame's converged
+ * weights and runs at most warm->steps steps of `warm`, ending early once a
+ * step's batch loss falls below the final loss of frame 0's second pass; the
+ * test is taken on the device before each step, per network, so the host never
+ * waits inside the sequence.  Each pass starts from a fresh optimiser state
+ * (zero moments, step counter 1) and draws i.i.d. batches with seed
+ * cold->seed (frame 0, first pass) or warm->seed + f (frame f's warm pass).
+ * cold and warm must select the same networks, have >= 1 step and no explicit
+ * index lists.  use_graph != 0 captures the whole sequence (every step of every
+ * frame) into one HIP graph and launches it once on `stream`.
+ * Outputs (each may be NULL):
+ *   reports[n_frames]  steps run per network (frame 0 counts both passes) and
+ *                      the loss of the frame's last step that ran;
+ *   loss_host          float[NVDB_MAX_NETS][T], T = cold->steps + n_frames *
+ *                      warm->steps, batch losses in schedule order; a skipped
+ *                      step repeats the loss that stopped the frame;
+ *   frame_params_dev   device float[n_frames][sum of the trained networks'
+ *                      parameter counts, ascending network id], the weights
+ *                      after each frame in the canonical flat layout.
+ * The model keeps the last frame's weights and optimiser state.  Synchronises
+ * `stream`.  Errors as nvdb_fit; E_NUMERIC for a non-finite loss. */
+typedef struct {
+  int32_t steps_run[NVDB_MAX_NETS];
+  float final_loss[NVDB_MAX_NETS];
+} nvdb_frame_report;
+nvdb_status nvdb_fit_sequence(nvdb_model* model, const nvdb_tree* const* frames, int32_t n_frames,
+                              const nvdb_fit_desc* cold, const nvdb_fit_desc* warm, int32_t use_graph,
+                              nvdb_frame_report* reports, float* loss_host, float* frame_params_dev,
+                              void* stream);
+
 /* ---------------------------------------------------------------- decode */
 /* Offline sequential decode (Sec. 3.5) over the tree's topology:
  * values_dev (float32[N], leaf-major) receives the regressor output at every

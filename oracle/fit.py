@@ -72,15 +72,20 @@ def param_grad(theta, shapes, B, x, gy):
 
 
 def train(theta0, shapes, B, tr, net, lo, D, kind, band, steps, batch, seed=0, lr0=1e-3,
-          decay=0.975, interval=100, idx_batches=None, step0=0, m0=None, v0=None):
+          decay=0.975, interval=100, idx_batches=None, step0=0, m0=None, v0=None, stop_below=None):
     """Adam fit of one network.  Batch indices come from the SplitMix64 sampler
-    (stream of the network, step counted from step0) unless idx_batches is given."""
+    (stream of the network, step counted from step0) unless idx_batches is given.
+    With stop_below, no further step is taken once a step's batch loss is below
+    it (the warm-start stopping rule of Sec. 3.6); the returned losses then hold
+    only the steps that ran."""
     theta = np.array(theta0, dtype=np.float64)
     m = np.zeros_like(theta) if m0 is None else np.array(m0, np.float64)
     v = np.zeros_like(theta) if v0 is None else np.array(v0, np.float64)
     pop = population(tr, net)
     losses = []
     for k in range(steps):
+        if stop_below is not None and losses and losses[-1] < stop_below:
+            break
         s = step0 + k + 1
         if idx_batches is not None:
             idx = idx_batches[k]
@@ -91,6 +96,34 @@ def train(theta0, shapes, B, tr, net, lo, D, kind, band, steps, batch, seed=0, l
         losses.append(L)
         theta, m, v = mlp.adam_step(theta, g, m, v, s, mlp.lr_at(s, lr0, decay, interval))
     return theta, m, v, np.array(losses)
+
+
+def train_sequence(theta0, shapes, B, frames, net, lo, D, kind, band, cold, warm):
+    """Warm-start encoder of an animated sequence (Sec. 3.6) for one network.
+
+    Frame 0 is fitted twice from theta0: `cold` (the target learning rate), then
+    `warm` (the smaller refinement rate).  The final batch loss of that second
+    pass is the target every later frame aims for: frame f >= 1 starts from the
+    weights of frame f-1 and runs up to warm['steps'] steps, stopping as soon as
+    a step's loss is below the target.  Each pass has its own Adam state (zero
+    moments, step count from 1); pass seeds are cold['seed'] for the first pass
+    and warm['seed'] + f for frame f's warm pass.
+    cold / warm: dicts with steps, batch, seed, lr, lr_decay, lr_interval.
+    Returns (thetas per frame, steps run per frame, losses per frame)."""
+    def run(theta, tree, d, seed, stop):
+        th, _, _, L = train(theta, shapes, B, tree, net, lo, D, kind, band, d["steps"], d["batch"], seed=seed,
+                            lr0=d["lr"], decay=d["lr_decay"], interval=d["lr_interval"], stop_below=stop)
+        return th, L
+    th, La = run(theta0, frames[0], cold, cold["seed"], None)
+    th, Lb = run(th, frames[0], warm, warm["seed"], None)
+    target = Lb[-1]
+    thetas, runs, losses = [th], [len(La) + len(Lb)], [np.concatenate([La, Lb])]
+    for f in range(1, len(frames)):
+        th, L = run(th, frames[f], warm, warm["seed"] + f, target)
+        thetas.append(th)
+        runs.append(len(L))
+        losses.append(L)
+    return thetas, runs, losses
 
 
 def _batched_predict(theta, shapes, B, x, chunk=1 << 15):

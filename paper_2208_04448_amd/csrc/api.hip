@@ -20,6 +20,8 @@ struct Net {
   int prec = NVDB_BF16;
   DevBuf<float> theta, m, v, grad;
   DevBuf<float> partial, loss_partial, losses;
+  DevBuf<int32_t> ran;  // per step of a sequence fit: 1 when the step ran
+  DevBuf<floatx4> xt;  // gathered samples of the current step
   DevBuf<char> wrow, wcol, w1frag;
   DevBuf<float> bias, whead, bhead, benc;
   int64_t step = 0;
@@ -247,7 +249,7 @@ nvdb_status nvdb_model_create(const nvdb_model_desc* desc, nvdb_model** out) {
         n.bias.alloc((size_t)H * W);
         n.whead.alloc((size_t)n.s.C * W);
         n.bhead.alloc(4);
-        n.benc.alloc((size_t)3 * (KP / 2));
+        n.benc.alloc((size_t)4 * (KP / 2));
         NVDB_HIP(hipMemset(n.bhead.p, 0, 16));
         NVDB_HIP(hipMemset(n.benc.p, 0, n.benc.n * 4));
       }
@@ -292,11 +294,12 @@ nvdb_status nvdb_model_set_encoding(nvdb_model* m, int32_t net, const float* B, 
   return guarded([&] {
     Net& N = net_of(m, net);
     NVDB_REQUIRE(B && n_freq == N.d.n_freq, NVDB_E_INVALID, "n_freq mismatch");
-    std::vector<float> h((size_t)3 * (N.s.KP / 2), 0.f);
-    for (int i = 0; i < 3 * n_freq; ++i) {
-      NVDB_REQUIRE(std::isfinite(B[i]), NVDB_E_INVALID, "non-finite encoding matrix");
-      h[i] = B[i];
-    }
+    std::vector<float> h((size_t)4 * (N.s.KP / 2), 0.f);  // rows (bx, by, bz, 0)
+    for (int i = 0; i < n_freq; ++i)
+      for (int d = 0; d < 3; ++d) {
+        NVDB_REQUIRE(std::isfinite(B[3 * i + d]), NVDB_E_INVALID, "non-finite encoding matrix");
+        h[4 * i + d] = B[3 * i + d];
+      }
     NVDB_HIP(hipMemcpy(N.benc.p, h.data(), h.size() * 4, hipMemcpyHostToDevice));
     N.enc_set = true;
   });
@@ -341,43 +344,166 @@ static int population_src(int net, const Tree* t, int64_t* pop) {
   return SRC_L1_SLOTS;
 }
 
+}  // extern "C"
+
+// Schedule of one run of consecutive optimiser steps.
+struct Phase {
+  int32_t batch;
+  uint64_t seed;
+  float lr, lr_decay;
+  int32_t lr_interval;
+  const nvdb_fit_desc* idx;  // explicit index lists (idx_dev / idx_count) or null for i.i.d. draws
+};
+
+// Per-step device pointers: where each network's batch loss goes and the
+// optional stop test of warm-started frames.
+struct StepHooks {
+  float* loss_out[NVDB_MAX_NETS] = {};
+  const float* prev_loss[NVDB_MAX_NETS] = {};
+  const float* stop_below[NVDB_MAX_NETS] = {};
+  int32_t* ran[NVDB_MAX_NETS] = {};
+};
+
+static int train_grid(int64_t n) { return (int)std::min<int64_t>(MAX_G, (n + TRAIN_TILE - 1) / TRAIN_TILE); }
+
+// Networks that share a kernel go into one launch (gridDim.y = network).
+static std::vector<std::vector<int>> kernel_groups(const nvdb_model* m, const std::vector<int>& nets) {
+  std::vector<std::vector<int>> groups;
+  for (int k : nets) {
+    bool put = false;
+    for (auto& g : groups)
+      if (m->nets[g[0]].ks.train == m->nets[k].ks.train) {
+        g.push_back(k);
+        put = true;
+        break;
+      }
+    if (!put) groups.push_back({k});
+  }
+  return groups;
+}
+
+// Checks that every selected network is ready and has a non-empty population on `tree`.
+static std::vector<int> fit_nets(nvdb_model* m, const Tree* tree, int32_t mask) {
+  std::vector<int> nets;
+  for (int k = 0; k < NVDB_MAX_NETS; ++k) {
+    if (!(mask & (1 << k))) continue;
+    Net& N = net_of(m, k);
+    NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "parameters or encoding not set");
+    int64_t pop;
+    population_src(k, tree, &pop);
+    NVDB_REQUIRE(pop > 0 && pop < (1ll << 32), NVDB_E_INVALID, "empty or oversized population");
+    nets.push_back(k);
+  }
+  NVDB_REQUIRE(!nets.empty(), NVDB_E_INVALID, "no network selected");
+  return nets;
+}
+
+static void check_schedule(const nvdb_fit_desc* f) {
+  NVDB_REQUIRE(f->steps >= 0 && f->batch >= 1 && f->batch <= (1 << 24), NVDB_E_INVALID, "bad steps/batch");
+  NVDB_REQUIRE(std::isfinite(f->lr) && f->lr >= 0.f && std::isfinite(f->lr_decay) && f->lr_decay > 0.f &&
+                   f->lr_interval >= 1,
+               NVDB_E_INVALID, "bad learning-rate schedule");
+}
+
+// Workspace for steps of `batch` samples; allocates, so never called under capture.
+static void reserve_step(Net& N, int32_t batch, int32_t n_steps) {
+  const int G = std::max(1, train_grid(batch));
+  ensure_partials(N, G);
+  N.xt.ensure(std::max<int64_t>(batch, 1));
+  N.losses.ensure(std::max(n_steps, 1));
+  N.ran.ensure(std::max(n_steps, 1));
+}
+
+// Enqueues optimiser step `step` (0-based within the phase) of every network in
+// `groups` on `tree`: a gather per network, one fused train launch per group,
+// one reduce + Adam launch for all.  Workspace must be reserved beforehand.
+// `ev`, if non-null, holds two events per group around its train launch.
+static void enqueue_step(nvdb_model* m, const Tree* tree, const std::vector<std::vector<int>>& groups,
+                         const Phase& ph, int step, const StepHooks& hk, hipEvent_t* ev, hipStream_t st) {
+  const TreeView tv = tree_view(tree);
+  AdamLaunch AL{};
+  int na = 0;
+  int64_t maxP = 0;
+  size_t evi = 0;
+  for (auto& grp : groups) {
+    TrainLaunch L{};
+    L.tree = tv;
+    int G = 1;
+    int slot = 0;
+    for (int k : grp) {
+      Net& N = m->nets[k];
+      TrainNet& tn = L.nets[slot++];
+      tn.net = net_view(N);
+      base_spec(m, &tn.spec);
+      int64_t pop;
+      tn.spec.src = population_src(k, tree, &pop);
+      tn.spec.loss = k == NVDB_NET_REGRESSOR ? LOSS_MSE : (k == NVDB_NET_L0 ? LOSS_BCE : LOSS_CE);
+      tn.spec.npop = (uint32_t)pop;
+      int64_t n = ph.batch;
+      if (ph.idx && ph.idx->idx_dev[k]) {
+        const int64_t off = (int64_t)step * ph.batch;
+        n = std::min<int64_t>(ph.batch, ph.idx->idx_count[k] - off);
+        tn.spec.idx = ph.idx->idx_dev[k] + off;
+      } else {
+        tn.spec.step_seed = step_seed(ph.seed, k, N.step);
+      }
+      tn.spec.n = n;
+      tn.spec.inv_n = 1.f / (float)n;
+      tn.prev_loss = hk.prev_loss[k];
+      tn.stop_below = hk.stop_below[k];
+      G = std::max(G, train_grid(n));
+    }
+    slot = 0;
+    for (int k : grp) {
+      Net& N = m->nets[k];
+      NVDB_REQUIRE(N.partial.n >= (size_t)G * N.s.nparams() && N.xt.n >= (size_t)L.nets[slot].spec.n,
+                   NVDB_E_STATE, "training workspace not reserved");
+      TrainNet& tn = L.nets[slot++];
+      tn.partial = N.partial.p;
+      tn.loss_partial = N.loss_partial.p;
+      launch_gather(tn.spec, tv, N.xt.p, st);
+      tn.xt = N.xt.p;
+      const int64_t s = N.step + 1;
+      AdamNet a = adam_view(N);
+      a.partial = N.partial.p;
+      a.loss_partial = N.loss_partial.p;
+      a.G = G;
+      a.loss_out = hk.loss_out[k];
+      a.loss_scale = tn.spec.inv_n;
+      a.lr = (float)((double)ph.lr * std::pow((double)ph.lr_decay, (double)((s - 1) / ph.lr_interval)));
+      a.bc1 = (float)(1.0 - std::pow(0.9, (double)s));
+      a.bc2 = (float)(1.0 - std::pow(0.999, (double)s));
+      a.prev_loss = hk.prev_loss[k];
+      a.stop_below = hk.stop_below[k];
+      a.ran = hk.ran[k];
+      AL.nets[na++] = a;
+      maxP = std::max(maxP, N.s.nparams());
+    }
+    L.G = G;
+    if (ev) NVDB_HIP(hipEventRecord(ev[evi++], st));
+    launch_train(m->nets[grp[0]].ks, L, (int)grp.size(), st);
+    if (ev) NVDB_HIP(hipEventRecord(ev[evi++], st));
+  }
+  launch_reduce_adam(AL, maxP, na, st);
+  for (auto& grp : groups)
+    for (int k : grp) m->nets[k].step += 1;
+}
+
+extern "C" {
+
 nvdb_status nvdb_fit(nvdb_model* m, const nvdb_tree* tree, const nvdb_fit_desc* fit, float* loss_host, void* stream) {
   return guarded([&] {
     NVDB_REQUIRE(m && tree && fit, NVDB_E_INVALID, "null argument");
-    NVDB_REQUIRE(fit->steps >= 0 && fit->batch >= 1 && fit->batch <= (1 << 24), NVDB_E_INVALID, "bad steps/batch");
-    NVDB_REQUIRE(std::isfinite(fit->lr) && fit->lr >= 0.f && std::isfinite(fit->lr_decay) && fit->lr_decay > 0.f &&
-                     fit->lr_interval >= 1,
-                 NVDB_E_INVALID, "bad learning-rate schedule");
+    check_schedule(fit);
     hipStream_t st = (hipStream_t)stream;
-    std::vector<int> nets;
-    for (int k = 0; k < NVDB_MAX_NETS; ++k) {
-      if (!(fit->nets_mask & (1 << k))) continue;
-      Net& N = net_of(m, k);
-      NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "parameters or encoding not set");
-      int64_t pop;
-      population_src(k, tree, &pop);
-      NVDB_REQUIRE(pop > 0 && pop < (1ll << 32), NVDB_E_INVALID, "empty or oversized population");
-      if (fit->idx_dev[k]) {
+    const std::vector<int> nets = fit_nets(m, tree, fit->nets_mask);
+    for (int k : nets)
+      if (fit->idx_dev[k])
         NVDB_REQUIRE(fit->idx_count[k] > (int64_t)(fit->steps - 1) * fit->batch, NVDB_E_INVALID,
                      "explicit index list shorter than the schedule");
-      }
-      nets.push_back(k);
-    }
-    NVDB_REQUIRE(!nets.empty(), NVDB_E_INVALID, "no network selected");
-    const TreeView tv = tree_view(tree);
-    for (int k : nets) m->nets[k].losses.ensure(std::max(fit->steps, 1));
-
-    // group networks that share a kernel into one launch
-    std::vector<std::vector<int>> groups;
-    for (int k : nets) {
-      bool put = false;
-      for (auto& g : groups)
-        if (m->nets[g[0]].ks.train == m->nets[k].ks.train) {
-          g.push_back(k);
-          put = true;
-        }
-      if (!put) groups.push_back({k});
-    }
+    for (int k : nets) reserve_step(m->nets[k], fit->batch, fit->steps);
+    const auto groups = kernel_groups(m, nets);
+    const Phase ph{fit->batch, fit->seed, fit->lr, fit->lr_decay, fit->lr_interval, fit};
 
     // optional timing of the training-kernel launches with HIP events on `stream`
     std::vector<hipEvent_t> ev;
@@ -385,65 +511,10 @@ nvdb_status nvdb_fit(nvdb_model* m, const nvdb_tree* tree, const nvdb_fit_desc* 
       ev.resize(2 * (size_t)fit->steps * groups.size());
       for (auto& e : ev) NVDB_HIP(hipEventCreate(&e));
     }
-    size_t evi = 0;
     for (int step = 0; step < fit->steps; ++step) {
-      AdamLaunch AL{};
-      int na = 0;
-      int64_t maxP = 0;
-      for (auto& grp : groups) {
-        TrainLaunch L{};
-        L.tree = tv;
-        int G = 1;
-        int slot = 0;
-        for (int k : grp) {
-          Net& N = m->nets[k];
-          TrainNet& tn = L.nets[slot++];
-          tn.net = net_view(N);
-          base_spec(m, &tn.spec);
-          int64_t pop;
-          tn.spec.src = population_src(k, tree, &pop);
-          tn.spec.loss = k == NVDB_NET_REGRESSOR ? LOSS_MSE : (k == NVDB_NET_L0 ? LOSS_BCE : LOSS_CE);
-          tn.spec.npop = (uint32_t)pop;
-          int64_t n = fit->batch;
-          if (fit->idx_dev[k]) {
-            const int64_t off = (int64_t)step * fit->batch;
-            n = std::min<int64_t>(fit->batch, fit->idx_count[k] - off);
-            tn.spec.idx = fit->idx_dev[k] + off;
-          } else {
-            tn.spec.step_seed = step_seed(fit->seed, k, N.step);
-          }
-          tn.spec.n = n;
-          tn.spec.inv_n = 1.f / (float)n;
-          G = std::max<int>(G, (int)std::min<int64_t>(MAX_G, (n + TRAIN_TILE - 1) / TRAIN_TILE));
-        }
-        slot = 0;
-        for (int k : grp) {
-          Net& N = m->nets[k];
-          ensure_partials(N, G);
-          TrainNet& tn = L.nets[slot++];
-          tn.partial = N.partial.p;
-          tn.loss_partial = N.loss_partial.p;
-          // optimiser step for this network
-          const int64_t s = N.step + 1;
-          AdamNet a = adam_view(N);
-          a.partial = N.partial.p;
-          a.loss_partial = N.loss_partial.p;
-          a.G = G;
-          a.loss_out = N.losses.p + step;
-          a.loss_scale = tn.spec.inv_n;
-          a.lr = (float)((double)fit->lr * std::pow((double)fit->lr_decay, (double)((s - 1) / fit->lr_interval)));
-          a.bc1 = (float)(1.0 - std::pow(0.9, (double)s));
-          a.bc2 = (float)(1.0 - std::pow(0.999, (double)s));
-          AL.nets[na++] = a;
-          maxP = std::max(maxP, N.s.nparams());
-        }
-        L.G = G;
-        if (!ev.empty()) NVDB_HIP(hipEventRecord(ev[evi++], st));
-        launch_train(m->nets[grp[0]].ks, L, (int)grp.size(), st);
-        if (!ev.empty()) NVDB_HIP(hipEventRecord(ev[evi++], st));
-      }
-      launch_reduce_adam(AL, maxP, na, st);
-      for (int k : nets) m->nets[k].step += 1;
+      StepHooks hk;
+      for (int k : nets) hk.loss_out[k] = m->nets[k].losses.p + step;
+      enqueue_step(m, tree, groups, ph, step, hk, ev.empty() ? nullptr : ev.data() + 2 * groups.size() * step, st);
     }
     if (!ev.empty()) {
       NVDB_HIP(hipEventSynchronize(ev.back()));
@@ -470,6 +541,147 @@ nvdb_status nvdb_fit(nvdb_model* m, const nvdb_tree* tree, const nvdb_fit_desc* 
       }
       NVDB_REQUIRE(finite, NVDB_E_NUMERIC, "non-finite loss during fit");
     }
+  });
+}
+
+}  // extern "C"
+
+// Ends a stream capture that an exception interrupted and releases the graph objects.
+struct CaptureGuard {
+  hipStream_t cs = nullptr;
+  bool capturing = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~CaptureGuard() {
+    if (capturing) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(cs, &g);
+      if (g) (void)hipGraphDestroy(g);
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+};
+
+extern "C" {
+
+nvdb_status nvdb_fit_sequence(nvdb_model* m, const nvdb_tree* const* frames, int32_t n_frames,
+                              const nvdb_fit_desc* cold, const nvdb_fit_desc* warm, int32_t use_graph,
+                              nvdb_frame_report* reports, float* loss_host, float* frame_params_dev,
+                              void* stream) {
+  return guarded([&] {
+    NVDB_REQUIRE(m && frames && cold && warm && n_frames >= 1, NVDB_E_INVALID, "null argument or no frames");
+    check_schedule(cold);
+    check_schedule(warm);
+    NVDB_REQUIRE(cold->steps >= 1 && warm->steps >= 1, NVDB_E_INVALID, "cold and warm passes need >= 1 step");
+    NVDB_REQUIRE(cold->nets_mask == warm->nets_mask, NVDB_E_INVALID, "cold and warm passes select other networks");
+    for (int k = 0; k < NVDB_MAX_NETS; ++k)
+      NVDB_REQUIRE(!cold->idx_dev[k] && !warm->idx_dev[k], NVDB_E_INVALID,
+                   "sequences draw i.i.d. batches; explicit index lists are not accepted");
+    std::vector<int> nets;
+    for (int32_t f = 0; f < n_frames; ++f) {
+      NVDB_REQUIRE(frames[f], NVDB_E_INVALID, "null frame");
+      nets = fit_nets(m, frames[f], cold->nets_mask);
+    }
+    const int64_t total = (int64_t)cold->steps + (int64_t)n_frames * warm->steps;
+    NVDB_REQUIRE(total < (1ll << 30), NVDB_E_INVALID, "schedule too long");
+    for (int k : nets) {
+      Net& N = m->nets[k];
+      reserve_step(N, std::max(cold->batch, warm->batch), (int32_t)total);
+    }
+    const auto groups = kernel_groups(m, nets);
+    hipStream_t st = (hipStream_t)stream;
+
+    CaptureGuard cap;
+    hipStream_t q = st;
+    if (use_graph) {
+      NVDB_HIP(hipStreamCreateWithFlags(&cap.cs, hipStreamNonBlocking));
+      NVDB_HIP(hipStreamBeginCapture(cap.cs, hipStreamCaptureModeThreadLocal));
+      cap.capturing = true;
+      q = cap.cs;
+    }
+    int64_t frame_stride = 0;
+    for (int k : nets) frame_stride += m->nets[k].s.nparams();
+    int64_t g = 0;  // global step index into each network's loss / ran arrays
+    // A pass starts from a fresh optimiser state: zero moments, step count 0.
+    auto run_pass = [&](const Tree* tree, const nvdb_fit_desc* d, uint64_t seed, bool stop_test) {
+      for (int k : nets) {
+        Net& N = m->nets[k];
+        launch_fill(N.m.p, N.s.nparams(), 0.f, q);
+        launch_fill(N.v.p, N.s.nparams(), 0.f, q);
+        N.step = 0;
+      }
+      const Phase ph{d->batch, seed, d->lr, d->lr_decay, d->lr_interval, nullptr};
+      for (int j = 0; j < d->steps; ++j, ++g) {
+        StepHooks hk;
+        for (int k : nets) {
+          Net& N = m->nets[k];
+          hk.loss_out[k] = N.losses.p + g;
+          hk.ran[k] = N.ran.p + g;
+          if (stop_test && j > 0) {
+            hk.prev_loss[k] = N.losses.p + g - 1;
+            hk.stop_below[k] = N.losses.p + (cold->steps + warm->steps - 1);
+          }
+        }
+        enqueue_step(m, tree, groups, ph, j, hk, nullptr, q);
+      }
+    };
+    auto save_frame = [&](int32_t f) {
+      if (!frame_params_dev) return;
+      int64_t off = (int64_t)f * frame_stride;
+      for (int k : nets) {
+        Net& N = m->nets[k];
+        NVDB_HIP(hipMemcpyAsync(frame_params_dev + off, N.theta.p, N.s.nparams() * 4, hipMemcpyDeviceToDevice, q));
+        off += N.s.nparams();
+      }
+    };
+    // frame 0: cold pass at the target rate, then a refit at the warm rate (Sec. 3.6)
+    run_pass(frames[0], cold, cold->seed, false);
+    run_pass(frames[0], warm, warm->seed, false);
+    save_frame(0);
+    // later frames: warm start from the previous frame's weights, stopping once the
+    // batch loss falls below frame 0's final loss
+    for (int32_t f = 1; f < n_frames; ++f) {
+      run_pass(frames[f], warm, warm->seed + (uint64_t)f, true);
+      save_frame(f);
+    }
+    if (use_graph) {
+      cap.capturing = false;
+      NVDB_HIP(hipStreamEndCapture(cap.cs, &cap.graph));
+      NVDB_HIP(hipGraphInstantiate(&cap.exec, cap.graph, nullptr, nullptr, 0));
+      NVDB_HIP(hipGraphLaunch(cap.exec, st));
+    }
+    NVDB_HIP(hipStreamSynchronize(st));
+
+    // per-frame report; the host step counters follow the steps that actually ran
+    bool finite = true;
+    std::vector<float> lh(total);
+    std::vector<int32_t> rh(total);
+    if (reports) std::memset(reports, 0, sizeof(nvdb_frame_report) * n_frames);
+    for (int k : nets) {
+      Net& N = m->nets[k];
+      NVDB_HIP(hipMemcpy(lh.data(), N.losses.p, total * 4, hipMemcpyDeviceToHost));
+      NVDB_HIP(hipMemcpy(rh.data(), N.ran.p, total * 4, hipMemcpyDeviceToHost));
+      int64_t i = 0;
+      int32_t last_run = 0;
+      for (int32_t f = 0; f < n_frames; ++f) {
+        const int64_t len = f == 0 ? (int64_t)cold->steps + warm->steps : warm->steps;
+        int32_t run = 0;
+        for (int64_t j = 0; j < len; ++j, ++i) {
+          run += rh[i];
+          finite = finite && std::isfinite(lh[i]);
+        }
+        if (reports) {
+          reports[f].steps_run[k] = run;
+          reports[f].final_loss[k] = lh[i - 1];
+        }
+        last_run = f == 0 ? run - cold->steps : run;
+      }
+      N.step = last_run;
+      if (loss_host) std::memcpy(loss_host + (int64_t)k * total, lh.data(), total * 4);
+    }
+    NVDB_REQUIRE(finite, NVDB_E_NUMERIC, "non-finite loss during the sequence fit");
   });
 }
 
@@ -584,6 +796,9 @@ nvdb_status nvdb_backward_dev(nvdb_model* m, int32_t net, const float* x_dev, co
     tn.spec.inv_n = 1.f;
     tn.partial = N.partial.p;
     tn.loss_partial = N.loss_partial.p;
+    N.xt.ensure(n);
+    launch_gather(tn.spec, TreeView{}, N.xt.p, st);
+    tn.xt = N.xt.p;
     launch_train(N.ks, L, 1, st);
     AdamLaunch AL{};
     AL.nets[0] = adam_view(N);

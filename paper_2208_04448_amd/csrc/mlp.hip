@@ -111,6 +111,44 @@ struct PR<NVDB_FP32> {
   static __device__ __forceinline__ bool positive(const uint32_t* s, int r) { return __uint_as_float(s[r]) > 0.f; }
 };
 
+typedef short short2v __attribute__((ext_vector_type(2)));
+typedef unsigned short ushort2v __attribute__((ext_vector_type(2)));
+// ReLU of two packed bf16 values: read as int16, negative bf16 values are negative.
+__device__ __forceinline__ uint32_t relu_pk(uint32_t w) {
+  short2v v = __builtin_bit_cast(short2v, w);
+  v = __builtin_elementwise_max(v, short2v{0, 0});
+  return __builtin_bit_cast(uint32_t, v);
+}
+// Zero the halves of g whose matching half of a (a ReLU output, so >= +0) is zero.
+__device__ __forceinline__ uint32_t mask_pk(uint32_t g, uint32_t a) {
+  ushort2v t = __builtin_elementwise_min(__builtin_bit_cast(ushort2v, a), ushort2v{1, 1});
+  ushort2v m = ushort2v{0, 0} - t;
+  return g & __builtin_bit_cast(uint32_t, m);
+}
+template <int PREC>
+__device__ __forceinline__ void store_relu(floatx16 a, uint32_t* s) {
+  if constexpr (PREC == NVDB_BF16) {
+    PR<PREC>::store(a, s);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s[i] = relu_pk(s[i]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) s[i] = __float_as_uint(a[i] > 0.f ? a[i] : 0.f);
+  }
+}
+// Store a gradient block masked by the ReLU derivative of the activation block act.
+template <int PREC>
+__device__ __forceinline__ void store_masked(floatx16 a, uint32_t* s, const uint32_t* act) {
+  if constexpr (PREC == NVDB_BF16) {
+    PR<PREC>::store(a, s);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s[i] = mask_pk(s[i], act[i]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) s[i] = __uint_as_float(act[i]) > 0.f ? __float_as_uint(a[i]) : 0u;
+  }
+}
+
 // Feature held in accumulator register r (0..15) of block t by lane half h.
 __device__ __forceinline__ int sfeat(int t, int r, int h) { return 32 * t + 8 * (r >> 2) + 4 * h + (r & 3); }
 
@@ -188,30 +226,49 @@ __device__ __forceinline__ Smp fetch_sample(const SampleSpec& sp, const TreeView
 // m <= f < 2m is sin(2 pi b_{f-m}.x), f >= 2m is zero padding.  The hardware sine
 // takes revolutions; the phase is reduced with fract first.  The FP32 form forms the
 // phase in double precision so the feature is accurate to the sine's own error.
+// benc holds b_f as float4 rows (x, y, z, 0).
+template <int PREC>
+__device__ __forceinline__ float phase(const floatx4& b, const Smp& s, float shift) {
+  if constexpr (PREC == NVDB_FP32) {
+    double u = (double)b[0] * s.x[0] + (double)b[1] * s.x[1] + (double)b[2] * s.x[2] + (double)shift;
+    return (float)(u - floor(u));
+  } else {
+    return __builtin_amdgcn_fractf(fmaf(b[0], s.x[0], fmaf(b[1], s.x[1], fmaf(b[2], s.x[2], shift))));
+  }
+}
 template <int PREC, int NIB>
 __device__ __forceinline__ void encode_S(const Smp& s, const float* benc, int m, uint32_t (&X)[NIB][PR<PREC>::SR]) {
   const int h = lane_id() >> 5;
+  if (2 * m == 32 * NIB) {
+    // cos features fill the first half of the blocks and the sin features of the same
+    // frequencies the second half, in the same registers: one phase per pair
 #pragma unroll
-  for (int t = 0; t < NIB; ++t) {
-    floatx16 v;
+    for (int t = 0; t < NIB / 2; ++t) {
+      floatx16 vc, vs;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      int f = sfeat(t, r, h);
-      int fi = f < m ? f : f - m;
-      fi = fi < m ? fi : 0;
-      float b0 = benc[3 * fi], b1 = benc[3 * fi + 1], b2 = benc[3 * fi + 2];
-      float ph;
-      if constexpr (PREC == NVDB_FP32) {
-        double u = (double)b0 * s.x[0] + (double)b1 * s.x[1] + (double)b2 * s.x[2] + (f < m ? 0.25 : 0.0);
-        ph = (float)(u - floor(u));
-      } else {
-        float u = fmaf(b0, s.x[0], fmaf(b1, s.x[1], b2 * s.x[2])) + (f < m ? 0.25f : 0.f);
-        ph = __builtin_amdgcn_fractf(u);
+      for (int r = 0; r < 16; ++r) {
+        const floatx4 b = *(const floatx4*)(benc + 4 * sfeat(t, r, h));
+        vc[r] = __builtin_amdgcn_sinf(phase<PREC>(b, s, 0.25f));
+        vs[r] = __builtin_amdgcn_sinf(phase<PREC>(b, s, 0.f));
       }
-      float val = __builtin_amdgcn_sinf(ph);
-      v[r] = (f < 2 * m) ? val : 0.f;
+      PR<PREC>::store(vc, X[t]);
+      PR<PREC>::store(vs, X[t + NIB / 2]);
     }
-    PR<PREC>::store(v, X[t]);
+  } else {
+#pragma unroll
+    for (int t = 0; t < NIB; ++t) {
+      floatx16 v;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int f = sfeat(t, r, h);
+        int fi = f < m ? f : f - m;
+        fi = fi < m ? fi : 0;
+        const floatx4 b = *(const floatx4*)(benc + 4 * fi);
+        const float val = __builtin_amdgcn_sinf(phase<PREC>(b, s, f < m ? 0.25f : 0.f));
+        v[r] = (f < 2 * m) ? val : 0.f;
+      }
+      PR<PREC>::store(v, X[t]);
+    }
   }
 }
 
@@ -287,16 +344,15 @@ __device__ __forceinline__ void write_rows_f32(float* rows, int pitch, const Lan
 }
 __device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
-// sum of the 8 bf16 values of a fragment, accumulated in fp32 (plain unpack and add:
-// the bf16 dot-product builtin was observed to read one source register four times
-// when fed elements of a bit-cast vector)
+// Sum of the 8 bf16 values of a fragment, accumulated in fp32 with the bf16 dot
+// product against (1, 1).  Written as inline assembly: the compiler builtin was seen
+// reading one source register four times when fed elements of a bit-cast vector.
 __device__ __forceinline__ float frag_sum(bf16x8 f, float acc) {
   const u32x4 u = __builtin_bit_cast(u32x4, f);
-  const float s0 = bf16_lo(u[0]) + bf16_hi(u[0]);
-  const float s1 = bf16_lo(u[1]) + bf16_hi(u[1]);
-  const float s2 = bf16_lo(u[2]) + bf16_hi(u[2]);
-  const float s3 = bf16_lo(u[3]) + bf16_hi(u[3]);
-  return acc + ((s0 + s1) + (s2 + s3));
+  const uint32_t ones = 0x3f803f80u;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) asm("v_dot2c_f32_bf16 %0, %1, %2" : "+v"(acc) : "v"(ones), "v"(u[q]));
+  return acc;
 }
 
 // ------------------------------------------------------------ per-layer weights
@@ -454,7 +510,7 @@ struct TrainCfg {
   static constexpr int SLOT_BYTES = (HH_PRIVATE ? 2 : 3) * ROWS_BYTES + 32 * C * 4;
   static constexpr int HH_BYTES = HH_PRIVATE ? 4 * ROWS_BYTES : 0;
   static constexpr int WL_BYTES = (PREC == NVDB_BF16) ? (H - 1) * W * 256 : 0;
-  static constexpr int SMALL_FLOATS = H * W + C * W + 4 + 3 * (KP / 2) + 8;
+  static constexpr int SMALL_FLOATS = H * W + C * W + 4 + 4 * (KP / 2) + 8;
   static constexpr int LDS_BYTES = WL_BYTES + NSLOT * SLOT_BYTES + HH_BYTES + SMALL_FLOATS * 4;
   // dW blocks owned by a wave: waves form a 2 x 2 grid over (output, input) blocks.
   static constexpr int OBW = NB / 2;
@@ -474,6 +530,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
   __shared__ __attribute__((aligned(16))) char smem[CF::LDS_BYTES];
 
   const TrainNet& TN = L.nets[blockIdx.y];
+  if (TN.prev_loss && *TN.prev_loss < *TN.stop_below) return;  // uniform: this network has converged
   const NetView& nv = TN.net;
   const SampleSpec& sp = TN.spec;
   const int wave = wave_id();
@@ -486,8 +543,8 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
   float* sm_bias0 = (float*)(hh0 + CF::HH_BYTES);                    // [H][W]
   float* sm_whead0 = sm_bias0 + H * W;                              // [C][W]
   float* sm_bhead0 = sm_whead0 + C * W;                             // [C] (padded to 4)
-  float* sm_benc0 = sm_bhead0 + 4;                                  // [KP/2][3]
-  float* sm_red = sm_benc0 + 3 * (KP / 2);                          // [8] reductions
+  float* sm_benc0 = sm_bhead0 + 4;                                  // [KP/2][4]
+  float* sm_red = sm_benc0 + 4 * (KP / 2);                          // [8] reductions
 
   // ---- stage parameters
   if constexpr (BF) {
@@ -498,7 +555,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
   for (int i = threadIdx.x; i < H * W; i += blockDim.x) sm_bias0[i] = nv.bias[i];
   for (int i = threadIdx.x; i < C * W; i += blockDim.x) sm_whead0[i] = nv.whead[i];
   if (threadIdx.x < C) sm_bhead0[threadIdx.x] = nv.bhead[threadIdx.x];
-  for (int i = threadIdx.x; i < 3 * (KP / 2); i += blockDim.x) sm_benc0[i] = nv.benc[i];
+  for (int i = threadIdx.x; i < 4 * (KP / 2); i += blockDim.x) sm_benc0[i] = nv.benc[i];
   __syncthreads();
 
   // ---- per-wave accumulators kept across iterations
@@ -523,7 +580,17 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
   const int64_t n_iter = (sp.n + 127) / 128;
   float* partial = TN.partial + (size_t)blockIdx.x * P_;
 
+  floatx4 xt_next = floatx4{0.f, 0.f, 0.f, 0.f};
+  {
+    const int64_t j0 = (int64_t)blockIdx.x * 128 + wave * 32 + (lane_id() & 31);
+    if (j0 < sp.n) xt_next = TN.xt[j0];
+  }
   for (int64_t it = blockIdx.x; it < n_iter; it += L.G) {
+    const floatx4 xt_cur = xt_next;
+    {
+      const int64_t jn = (it + L.G) * 128 + wave * 32 + (lane_id() & 31);
+      if (jn < sp.n) xt_next = TN.xt[jn];
+    }
     const LaneK K = lane_consts();
     const int h = K.h, fl = K.fl;
     const int z = opaque_zero();
@@ -535,7 +602,13 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
     char* slots = slots0 + z;
     const bool first = (it == (int64_t)blockIdx.x);  // first iteration stores into the partial row
     const int64_t j = it * 128 + wave * 32 + fl;
-    const Smp smp = fetch_sample(sp, L.tree, j);
+    Smp smp;
+    smp.valid = j < sp.n;
+    smp.x[0] = xt_cur[0];
+    smp.x[1] = xt_cur[1];
+    smp.x[2] = xt_cur[2];
+    smp.t = xt_cur[3];
+    smp.cls = (int)xt_cur[3];
 
     // ================= forward
     uint32_t Hs[H][NB][SR];  // Hs[l] = a_{l+1} (S layout), l = 0..H-1
@@ -547,10 +620,8 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
       for (int ob = 0; ob < NB; ob += 2) {
         floatx16 a0 = bias_acc(sm_bias, K, ob), a1 = bias_acc(sm_bias, K, ob + 1);
         layer_block2<PREC, NIB0>(wf0, ob, X0, a0, a1);
-        relu16(a0);
-        relu16(a1);
-        P::store(a0, Hs[0][ob]);
-        P::store(a1, Hs[0][ob + 1]);
+        store_relu<PREC>(a0, Hs[0][ob]);
+        store_relu<PREC>(a1, Hs[0][ob + 1]);
       }
     }
     static_for<1, H>([&](auto lc) {
@@ -561,10 +632,8 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
       for (int ob = 0; ob < NB; ob += 2) {
         floatx16 a0 = bias_acc(sm_bias + l * W, K, ob), a1 = bias_acc(sm_bias + l * W, K, ob + 1);
         layer_block2<PREC, NB>(wf, ob, Hs[l - 1], a0, a1);
-        relu16(a0);
-        relu16(a1);
-        P::store(a0, Hs[l][ob]);
-        P::store(a1, Hs[l][ob + 1]);
+        store_relu<PREC>(a0, Hs[l][ob]);
+        store_relu<PREC>(a1, Hs[l][ob + 1]);
       }
     });
     // head (VALU): y_c = sum_f Wh[c][f] a_H[f] + bh[c]
@@ -599,9 +668,9 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
           v += w4 * gy[c];
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) g[4 * q + e] = P::positive(Hs[H - 1][ob], 4 * q + e) ? v[e] : 0.f;
+        for (int e = 0; e < 4; ++e) g[4 * q + e] = v[e];
       }
-      P::store(g, Gc[ob]);
+      store_masked<PREC>(g, Gc[ob], Hs[H - 1][ob]);
     }
     if constexpr (CF::HH_PRIVATE) {
       // the previous iteration's readers of this buffer finished before its last barrier
@@ -617,6 +686,25 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
       // input activations a_l of layer l as rows (gamma recomputed for l = 0)
       uint32_t X0[NIB0][SR];
       if constexpr (l == 0) encode_S<PREC, NIB0>(smp, sm_benc, nv.nfreq, X0);
+      // layers folded into the partial row: fetch the running sums now so that the
+      // loads complete under the exchange below
+      constexpr bool PREFETCH = !CF::reg_layer(l) && l == 0;  // registers are free only at layer 0
+      float prev[PREFETCH ? OBW : 1][PREFETCH ? CF::IBWMAX : 1][16];
+      if constexpr (PREFETCH) {
+        if (!first) {
+          const int win = nv.s.win(l);
+#pragma unroll
+          for (int a = 0; a < OBW; ++a)
+#pragma unroll
+            for (int b = 0; b < CF::IBWMAX; ++b)
+              if (b < IBWl) {
+                const int ob = wo * OBW + a, ib = wi * IBWl + b, i = 32 * ib + fl;
+                const float* p0 = partial + nv.s.woff(l) + (size_t)(32 * ob + 4 * h) * win + i;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) prev[a][b][r] = (i < win) ? p0[(size_t)(8 * (r >> 2) + (r & 3)) * win] : 0.f;
+              }
+        }
+      }
 
 #pragma unroll
       for (int round = 0; round < 4 / CF::NSLOT; ++round) {
@@ -713,20 +801,22 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
 
       if constexpr (!CF::reg_layer(l)) {
         // fold this iteration's blocks into the work-group's partial row
+        const int win = nv.s.win(l);
 #pragma unroll
         for (int a = 0; a < OBW; ++a)
 #pragma unroll
           for (int b = 0; b < CF::IBWMAX; ++b) {
             if (b < IBWl) {
-              const int ob = wo * OBW + a, ib = wi * IBWl + b;
-              const int win = nv.s.win(l);
-              const int i = 32 * ib + fl;
+              const int ob = wo * OBW + a, ib = wi * IBWl + b, i = 32 * ib + fl;
+              float* p0 = partial + nv.s.woff(l) + (size_t)(32 * ob + 4 * h) * win + i;
               if (i < win) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                  const int o = sfeat(ob, r, h);
-                  float* p = partial + nv.s.woff(l) + (size_t)o * win + i;
-                  *p = first ? dacc[l][a][b][r] : *p + dacc[l][a][b][r];
+                  float* q = p0 + (size_t)(8 * (r >> 2) + (r & 3)) * win;
+                  float old_v;
+                  if constexpr (PREFETCH) old_v = prev[a][b][r];
+                  else old_v = first ? 0.f : *q;
+                  *q = first ? dacc[l][a][b][r] : old_v + dacc[l][a][b][r];
                 }
               }
               dacc[l][a][b] = floatx16{};
@@ -743,13 +833,8 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
         for (int ib = 0; ib < NB; ib += 2) {
           floatx16 a0 = floatx16{}, a1 = floatx16{};
           layer_block2<PREC, NB>(wb, ib, Gc, a0, a1);
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            a0[r] = P::positive(Hs[l - 1][ib], r) ? a0[r] : 0.f;
-            a1[r] = P::positive(Hs[l - 1][ib + 1], r) ? a1[r] : 0.f;
-          }
-          P::store(a0, Gn[ib]);
-          P::store(a1, Gn[ib + 1]);
+          store_masked<PREC>(a0, Gn[ib], Hs[l - 1][ib]);
+          store_masked<PREC>(a1, Gn[ib + 1], Hs[l - 1][ib + 1]);
         }
 #pragma unroll
         for (int ib = 0; ib < NB; ++ib)
@@ -830,7 +915,7 @@ template <int PREC, int W, int H, int KP, int C>
 struct InferCfg {
   static constexpr int NT = (PREC == NVDB_BF16) ? 2 : 1;  // 32-sample tiles per wave sharing each weight fragment
   static constexpr int WL_BYTES = (PREC == NVDB_BF16) ? H * W * 256 : 0;
-  static constexpr int SMALL_FLOATS = H * W + C * W + 4 + 3 * (KP / 2);
+  static constexpr int SMALL_FLOATS = H * W + C * W + 4 + 4 * (KP / 2);
   static constexpr int LDS_BYTES = WL_BYTES + SMALL_FLOATS * 4;
 };
 
@@ -859,7 +944,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
   for (int i = threadIdx.x; i < H * W; i += blockDim.x) sm_bias0[i] = nv.bias[i];
   for (int i = threadIdx.x; i < C * W; i += blockDim.x) sm_whead0[i] = nv.whead[i];
   if (threadIdx.x < C) sm_bhead0[threadIdx.x] = nv.bhead[threadIdx.x];
-  for (int i = threadIdx.x; i < 3 * (KP / 2); i += blockDim.x) sm_benc0[i] = nv.benc[i];
+  for (int i = threadIdx.x; i < 4 * (KP / 2); i += blockDim.x) sm_benc0[i] = nv.benc[i];
   __syncthreads();
 
   const int64_t per_wave = 32 * NT;
@@ -906,10 +991,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
           }
         }
 #pragma unroll
-        for (int u = 0; u < NT; ++u) {
-          relu16(acc[u]);
-          P::store(acc[u], Bn[u][ob]);
-        }
+        for (int u = 0; u < NT; ++u) store_relu<PREC>(acc[u], Bn[u][ob]);
       }
 #pragma unroll
       for (int u = 0; u < NT; ++u)
@@ -1008,6 +1090,14 @@ __global__ void __launch_bounds__(256) k_reduce_adam(AdamLaunch AL) {
   const AdamNet& A = AL.nets[blockIdx.y];
   const int64_t P = A.s.nparams();
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (A.prev_loss && *A.prev_loss < *A.stop_below) {  // skipped step: carry the loss forward
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (A.loss_out) *A.loss_out = *A.prev_loss;
+      if (A.ran) *A.ran = 0;
+    }
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && A.ran) *A.ran = 1;
   if (blockIdx.x == 0 && threadIdx.x == 0 && A.loss_out) {
     float L = 0.f;
     for (int g = 0; g < A.G; ++g) L += A.loss_partial[g];
@@ -1034,6 +1124,20 @@ __global__ void __launch_bounds__(256) k_reduce_adam(AdamLaunch AL) {
 __global__ void k_write_shadow(AdamNet A) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p < A.s.nparams()) write_shadow(A, p, A.theta[p]);
+}
+
+// Samples of one step, gathered once into (x, y, z, target or class) so that the
+// fused kernel reads one coalesced 16-byte record per sample.
+__global__ void __launch_bounds__(256) k_gather(SampleSpec sp, TreeView tv, floatx4* out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= sp.n) return;
+  const Smp s = fetch_sample(sp, tv, j);
+  out[j] = floatx4{s.x[0], s.x[1], s.x[2], sp.src == SRC_L1_SLOTS ? (float)s.cls : s.t};
+}
+
+__global__ void k_fill(float* p, int64_t n, float v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 __global__ void k_sample(uint64_t sseed, uint32_t npop, int64_t n, uint32_t* out) {
@@ -1081,6 +1185,16 @@ void launch_reduce_adam(const AdamLaunch& A, int64_t max_p, int n_nets, hipStrea
 }
 void launch_write_shadow(const AdamNet& A, hipStream_t st) {
   hipLaunchKernelGGL(k_write_shadow, dim3((unsigned)((A.s.nparams() + 255) / 256)), dim3(256), 0, st, A);
+  NVDB_HIP(hipGetLastError());
+}
+void launch_gather(const SampleSpec& sp, const TreeView& tv, floatx4* out, hipStream_t st) {
+  if (sp.n <= 0) return;
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)((sp.n + 255) / 256)), dim3(256), 0, st, sp, tv, out);
+  NVDB_HIP(hipGetLastError());
+}
+void launch_fill(float* p, int64_t n, float v, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
   NVDB_HIP(hipGetLastError());
 }
 void launch_sample(uint64_t sseed, uint32_t npop, int64_t n, uint32_t* out, hipStream_t st) {

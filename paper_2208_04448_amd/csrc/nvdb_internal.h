@@ -157,7 +157,7 @@ struct NetView {
   const float* bias;     // [H][W]
   const float* whead;    // [C][W]
   const float* bhead;    // [C]
-  const float* benc;     // feature-mapping matrix [KP/2][3], zero rows beyond n_freq
+  const float* benc;     // feature-mapping matrix [KP/2][4] rows (bx, by, bz, 0), zero beyond n_freq
   int32_t nfreq;
 };
 
@@ -176,8 +176,13 @@ constexpr int ROW_ELEMS = 128;  // bf16 elements per stored row
 struct TrainNet {
   NetView net;
   SampleSpec spec;
+  const floatx4* xt;    // gathered samples of this step: (x, y, z, target or class)
   float* partial;       // [G][P]
   float* loss_partial;  // [G]
+  // Device-side stop test (warm-started sequences): the step is skipped when
+  // *prev_loss < *stop_below (both device pointers; null disables the test).
+  const float* prev_loss;
+  const float* stop_below;
 };
 struct TrainLaunch {
   TrainNet nets[NVDB_MAX_NETS];
@@ -207,6 +212,9 @@ struct AdamNet {
   float* loss_out;       // if non-null: loss of this step (mean)
   float loss_scale;
   float lr, bc1, bc2;    // learning rate, 1 - beta1^s, 1 - beta2^s
+  const float* prev_loss;   // stop test, as in TrainNet; a skipped step carries the loss forward
+  const float* stop_below;
+  int32_t* ran;             // if non-null: 1 when the step ran, 0 when skipped
   // shadow copies
   int32_t prec;
   void* wrow;
@@ -232,6 +240,8 @@ void launch_infer(const KernelSet& ks, const InferLaunch& I, int grid, hipStream
 void launch_reduce_adam(const AdamLaunch& A, int64_t max_p, int n_nets, hipStream_t st);
 void launch_write_shadow(const AdamNet& A, hipStream_t st);
 void launch_sample(uint64_t sseed, uint32_t npop, int64_t n, uint32_t* out, hipStream_t st);
+void launch_gather(const SampleSpec& sp, const TreeView& tv, floatx4* out, hipStream_t st);
+void launch_fill(float* p, int64_t n, float v, hipStream_t st);
 // tree.hip
 Tree* build_tree_dense(const float* grid, const int32_t dims[3], const int32_t origin[3], const nvdb_active_rule& rule,
                        hipStream_t st);

@@ -53,6 +53,10 @@ class FitDesc(C.Structure):
                 ("idx_dev", C.c_void_p * 3), ("idx_count", C.c_int64 * 3), ("train_kernel_ms", C.c_void_p)]
 
 
+class FrameReport(C.Structure):
+    _fields_ = [("steps_run", C.c_int32 * 3), ("final_loss", C.c_float * 3)]
+
+
 class ErrorReport(C.Structure):
     _fields_ = [("n", C.c_int64), ("max_abs", C.c_double), ("rms", C.c_double), ("iou", C.c_double),
                 ("fp", C.c_int64), ("fn", C.c_int64)]
@@ -76,6 +80,8 @@ _SIGS = {
     "nvdb_model_set_opt_state": (C.c_int32, [_P, C.c_int32, _P, _P, C.c_int64, C.c_int64]),
     "nvdb_model_free": (None, [_P]),
     "nvdb_fit": (C.c_int32, [_P, _P, C.POINTER(FitDesc), _P, _P]),
+    "nvdb_fit_sequence": (C.c_int32, [_P, _P, C.c_int32, C.POINTER(FitDesc), C.POINTER(FitDesc), C.c_int32, _P, _P,
+                                      _P, _P]),
     "nvdb_decode": (C.c_int32, [_P, _P, _P, _P, _P]),
     "nvdb_decode_l1": (C.c_int32, [_P, _P, _P, _P]),
     "nvdb_errors": (C.c_int32, [_P, _P, _P, C.POINTER(ErrorReport), _P]),
@@ -218,6 +224,34 @@ class Model:
         if kernel_times is not None:
             kernel_times["train_kernel_ms"] = tk.value
         return losses[:, :steps] if return_losses else None
+
+    def fit_sequence(self, frames, cold, warm, nets_mask, use_graph=True, frame_params=True):
+        """Warm-started fit of an animated sequence (one tree per frame).
+        cold / warm: dicts with steps, batch, seed, lr and optionally lr_decay, lr_interval.
+        Returns (reports: list of (steps_run[3], final_loss[3]) per frame,
+        losses: float32[3][T], frame_params: device float32[n_frames][sum P] or None)."""
+        import torch
+
+        def desc(d):
+            f = FitDesc()
+            f.steps, f.batch, f.seed = d["steps"], d["batch"], d.get("seed", 0)
+            f.lr, f.lr_decay, f.lr_interval = d["lr"], d.get("lr_decay", 0.975), d.get("lr_interval", 100)
+            f.nets_mask = nets_mask
+            return f
+        fc, fw = desc(cold), desc(warm)
+        n = len(frames)
+        hs = (C.c_void_p * n)(*[t.h for t in frames])
+        reps = (FrameReport * n)()
+        T = cold["steps"] + n * warm["steps"]
+        losses = np.zeros((MAX_NETS, T), np.float32)
+        fp = None
+        if frame_params:
+            tot = sum(self.param_count(k) for k in range(MAX_NETS) if nets_mask & (1 << k))
+            fp = torch.empty((n, tot), dtype=torch.float32, device="cuda")
+        _check(_lib.nvdb_fit_sequence(self.h, hs, n, C.byref(fc), C.byref(fw), int(bool(use_graph)), reps,
+                                      losses.ctypes.data_as(C.c_void_p), _ptr(fp), _stream()))
+        out = [(list(r.steps_run), list(r.final_loss)) for r in reps]
+        return out, losses, fp
 
     def decode(self, tree, values=True, masks=True):
         import torch

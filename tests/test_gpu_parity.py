@@ -404,3 +404,84 @@ def test_c4_gradient_batch_2_22(gpu_lib, sphere, prec):
         go += mlp.flatten(mlp.backward(params, cache, gy))
     errs = layer_rel_errors(g, go, shapes)
     assert max(errs) <= (1e-4 if p == gpu_lib.FP32 else 5e-2), errs
+
+
+# --------------------------------------------------------------------------- warm-start sequence (Sec. 3.6)
+def test_fit_sequence_matches_oracle(gpu_lib):
+    """Four frames of a sphere moving 0.28 voxel per frame, regressor + level-0
+    classifier (64x3, PE-6, FP32): frame 0 cold then refit, frames 1-3 warm-started with the
+    device-side stop test.  Graph and stream launches agree bit for bit; the stop
+    decisions follow the library's own losses exactly; losses, step counts and
+    per-frame weights match the FP64 oracle's sequence."""
+    centers = [(32.0 + 0.25 * i, 32.0, 32.0 - 0.125 * i) for i in range(4)]
+    vols = [workloads.sphere_sdf(center=c, radius=22.0) for c in centers]
+    trees = [gpu_lib.Tree(v.to(DEV), (0, 0, 0), T.SDF, 3.0) for v in vols]
+    otrees = [T.build(*T.active_set_dense(v.numpy(), (0, 0, 0), T.SDF, 3.0)) for v in vols]
+    B = workloads.pe_matrix(6)
+    shapes = mlp.layer_shapes(36, 64, 3, 1)
+    th0 = {0: workloads.init_params(36, 64, 3, 1, seed=30), 1: workloads.init_params(36, 64, 3, 1, seed=31)}
+    cold = dict(steps=100, batch=2048, seed=3, lr=3e-3, lr_decay=0.975, lr_interval=100)
+    warm = dict(steps=20, batch=2048, seed=11, lr=5e-4, lr_decay=0.975, lr_interval=100)
+    S = warm["steps"]
+    # Over 120 steps the FP32 trajectory drifts from the FP64 one by more than in
+    # the short fits: losses are compared to 2e-3 relative.
+    LTOL = 2e-3
+
+    def run(use_graph):
+        m = gpu_lib.Model({0: (64, 3, 18, 1), 1: (64, 3, 18, 1)}, precision=gpu_lib.FP32, domain_size=64,
+                          value_scale=3.0)
+        for k in (0, 1):
+            m.set_params(k, th0[k])
+            m.set_encoding(k, B)
+        reps, L, fp = m.fit_sequence(trees, cold, warm, nets_mask=3, use_graph=use_graph)
+        return m, reps, L, fp.cpu().numpy()
+
+    mg, reps, L, fp = run(True)
+    _, reps2, L2, fp2 = run(False)
+    assert reps == reps2 and np.array_equal(L, L2) and np.array_equal(fp, fp2)
+    P = mlp.param_count(36, 64, 3, 1)
+    assert fp.shape == (4, 2 * P)
+    assert np.array_equal(fp[3, :P], mg.get_params(0)) and np.array_equal(fp[3, P:], mg.get_params(1))
+
+    c0 = cold["steps"] + warm["steps"]
+    for k, net in ((0, "regressor"), (1, "l0")):
+        target = L[k, c0 - 1]
+        assert reps[0][0][k] == c0
+        # stop rule against the library's own losses
+        for f in range(1, 4):
+            seg = L[k, c0 + (f - 1) * S: c0 + f * S]
+            below = np.nonzero(seg < target)[0]
+            want = below[0] + 1 if len(below) else S
+            assert reps[f][0][k] == want, (k, f, seg, target)
+            assert np.all(seg[want:] == seg[want - 1])
+            assert reps[f][1][k] == seg[-1]
+        # the FP64 oracle's sequence
+        ths, runs, lo = F.train_sequence(th0[k].astype(np.float64), shapes, B.astype(np.float64), otrees, net,
+                                         (0, 0, 0), 64, T.SDF, 3.0, cold, warm)
+        assert np.max(np.abs(L[k, :c0] - lo[0]) / lo[0]) <= LTOL
+        rel = np.linalg.norm(fp[0, k * P:(k + 1) * P] - ths[0]) / np.linalg.norm(ths[0] - th0[k])
+        assert rel <= 2e-2, rel
+        for f in range(1, 4):
+            r = reps[f][0][k]
+            seg = L[k, c0 + (f - 1) * S: c0 + (f - 1) * S + r]
+            if r != runs[f]:
+                # a different stop is acceptable only where the oracle's deciding
+                # loss sits at the target to within the FP32 agreement
+                j = min(r, runs[f]) - 1
+                assert abs(lo[f][j] - lo[0][-1]) <= 2 * LTOL * lo[0][-1], (k, f, r, runs[f])
+                break
+            assert np.max(np.abs(seg - lo[f]) / lo[f]) <= LTOL
+            rel = np.linalg.norm(fp[f, k * P:(k + 1) * P] - ths[f]) / np.linalg.norm(ths[f] - th0[k])
+            assert rel <= 2e-2, (k, f, rel)
+
+
+def test_fit_sequence_rejects_bad_schedules(gpu_lib, sphere):
+    tr, _ = sphere
+    m = gpu_lib.Model({0: (64, 3, 18, 1)}, precision=gpu_lib.FP32, domain_size=64, value_scale=3.0)
+    m.set_params(0, workloads.init_params(36, 64, 3, 1, seed=0))
+    m.set_encoding(0, workloads.pe_matrix(6))
+    ok = dict(steps=2, batch=256, seed=0, lr=1e-3)
+    for cold, warm, mask in ((dict(ok, steps=0), ok, 1), (ok, dict(ok, lr=float("nan")), 1), (ok, ok, 2)):
+        with pytest.raises(gpu_lib.NvdbError) as e:
+            m.fit_sequence([tr, tr], cold, warm, nets_mask=mask)
+        assert e.value.code == gpu_lib.E_INVALID

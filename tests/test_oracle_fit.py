@@ -80,3 +80,83 @@ def test_mask_from_logits_and_classes():
     assert int(w[0, 0]) == 1 | (1 << 63) and int(w[0, 1]) == 1 and int(w[0, 7]) == 1 << 63
     assert int(w[1, 1]) == 1 << 36
     assert F.l1_classes(np.array([[1.0, 1.0, 0.0], [0.0, 2.0, 2.0], [0, 0, 3.0]])).tolist() == [0, 1, 2]
+
+
+# ---------------------------------------------------------------- warm-start sequence (Sec. 3.6)
+_SEQ_SHAPES = mlp.layer_shapes(36, 16, 2, 1)
+_SEQ_B = mlp.pe_matrix(6)
+
+
+def _seq_frames(centers, radius=20.0):
+    out = []
+    for c in centers:
+        v = workloads.sphere_sdf(center=c, radius=radius).numpy()
+        ijk, vals = T.active_set_dense(v, (0, 0, 0), T.SDF, 3.0)
+        out.append(T.build(ijk, vals))
+    return out
+
+
+def _sched(steps, lr, seed, batch=256):
+    return dict(steps=steps, batch=batch, seed=seed, lr=lr, lr_decay=0.975, lr_interval=100)
+
+
+def test_sequence_single_frame_is_cold_then_refit(sphere):
+    th0 = workloads.init_params(36, 16, 2, 1, seed=3).astype(np.float64)
+    cold, warm = _sched(6, 1e-2, 5), _sched(4, 1e-3, 9)
+    ths, runs, L = F.train_sequence(th0, _SEQ_SHAPES, _SEQ_B, [sphere], "regressor", (0, 0, 0), 64, T.SDF, 3.0,
+                                    cold, warm)
+    a, _, _, La = F.train(th0, _SEQ_SHAPES, _SEQ_B, sphere, "regressor", (0, 0, 0), 64, T.SDF, 3.0, 6, 256,
+                          seed=5, lr0=1e-2)
+    # the refit starts from a fresh Adam state: its first update is -lr g / (|g| + eps)
+    b, _, _, Lb = F.train(a, _SEQ_SHAPES, _SEQ_B, sphere, "regressor", (0, 0, 0), 64, T.SDF, 3.0, 1, 256,
+                          seed=9, lr0=1e-3)
+    g = F.step_grad(a, _SEQ_SHAPES, _SEQ_B,
+                    *F.net_inputs(sphere, "regressor", F.sampler.iid_indices(9, F.NET_STREAM["regressor"], 0, 256,
+                                                                             len(sphere["values"])),
+                                  (0, 0, 0), 64, T.SDF, 3.0), "regressor")[1]
+    assert np.allclose(b - a, -1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-9, atol=1e-15)
+    assert runs == [10]
+    assert np.allclose(L[0][:6], La, rtol=0, atol=0)
+    assert L[0][6] == Lb[0]
+
+
+def test_sequence_stop_rule_brute_force():
+    """With a zero warm rate the weights never move after frame 0, so every
+    frame's batch losses are losses of one fixed network; the number of steps a
+    frame runs must be one past the first batch whose loss is below frame 0's
+    final loss (or the cap), found here by evaluating the batches directly."""
+    frames = _seq_frames([(32.0, 32.0, 32.0), (32.5, 32.0, 31.5), (33.0, 32.0, 31.0)])
+    th0 = workloads.init_params(36, 16, 2, 1, seed=4).astype(np.float64)
+    cold, warm = _sched(40, 1e-2, 1), _sched(12, 0.0, 7)
+    ths, runs, L = F.train_sequence(th0, _SEQ_SHAPES, _SEQ_B, frames, "regressor", (0, 0, 0), 64, T.SDF, 3.0,
+                                    cold, warm)
+    target = L[0][-1]
+    params = mlp.unflatten(ths[0], _SEQ_SHAPES)
+    for f in (1, 2):
+        assert np.array_equal(ths[f], ths[0])
+        tr = frames[f]
+        batch_losses = []
+        for j in range(12):
+            idx = F.sampler.iid_indices(7 + f, F.NET_STREAM["regressor"], j, 256, len(tr["values"]))
+            x = (tr["ijk"][idx] + 0.5) / 64.0
+            t = tr["values"][idx] / 3.0
+            y, _ = mlp.forward(params, mlp.encode(x, _SEQ_B))
+            batch_losses.append(np.mean((y[:, 0] - t) ** 2))
+        below = [j for j, l in enumerate(batch_losses) if l < target]
+        expect = below[0] + 1 if below else 12
+        assert runs[f] == expect
+        assert np.allclose(L[f], batch_losses[:expect], rtol=1e-12, atol=0)
+    assert min(runs[1:]) < 12, "the case should exercise an early stop"
+
+
+def test_sequence_warm_start_needs_fewer_steps():
+    """The point of the warm start: later frames of a slowly moving sphere reach
+    frame 0's final loss within the cap, well before a cold fit would."""
+    frames = _seq_frames([(32.0, 32.0, 32.0), (32.25, 32.0, 32.0), (32.5, 32.0, 32.0)])
+    th0 = workloads.init_params(36, 16, 2, 1, seed=4).astype(np.float64)
+    cold, warm = _sched(60, 1e-2, 1), _sched(30, 1e-3, 7)
+    ths, runs, L = F.train_sequence(th0, _SEQ_SHAPES, _SEQ_B, frames, "regressor", (0, 0, 0), 64, T.SDF, 3.0,
+                                    cold, warm)
+    assert runs[0] == 90
+    assert all(r < 30 for r in runs[1:]), runs
+    assert all(l[-1] < L[0][-1] for l in L[1:])
