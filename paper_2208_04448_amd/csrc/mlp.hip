@@ -367,7 +367,7 @@ struct WFwd {
   const LaneK* K;
   __device__ __forceinline__ typename PR<PREC>::Frag operator()(int ob, int t, int kk) const {
     if constexpr (PREC == NVDB_BF16) {
-      if (global0) return __builtin_bit_cast(bf16x8, gfrag[((ob * (KP / 32) + t) * 2 + kk) * 64 + lane_id()]);
+      if (global0) return __builtin_bit_cast(bf16x8, gfrag[((ob * (KP / 32) + t) * 2 + kk) * 64 + 32 * K->h + K->fl]);
       return frag_fwd(lds, *K, ob, t, kk);
     } else {
       return gcol[(size_t)sfeat(t, kk, K->h) * W + 32 * ob + K->fl];
@@ -419,18 +419,32 @@ __device__ __forceinline__ floatx16 layer_block(const AF& af, int ob, const uint
 
 // Two output blocks sharing each B operand: two independent accumulator chains keep
 // the MFMA pipe busy while each chain waits on its previous result.
+// The A fragments are fetched PF k-steps ahead of their use (software pipeline), so
+// the load latency overlaps the MFMAs of the preceding steps.
 template <int PREC, int NIB, class AF>
 __device__ __forceinline__ void layer_block2(const AF& af, int ob, const uint32_t (&X)[NIB][PR<PREC>::SR],
                                              floatx16& acc0, floatx16& acc1) {
   using P = PR<PREC>;
+  constexpr int NS = NIB * P::KS;
+  constexpr int PF = (PREC == NVDB_BF16) ? (NS < 4 ? NS : 4) : 1;
+  typename P::Frag fa[PF], fb[PF];
 #pragma unroll
-  for (int t = 0; t < NIB; ++t)
+  for (int s = 0; s < PF; ++s) {
+    fa[s] = af(ob, s / P::KS, s % P::KS);
+    fb[s] = af(ob + 1, s / P::KS, s % P::KS);
+  }
 #pragma unroll
-    for (int kk = 0; kk < P::KS; ++kk) {
-      const auto b = P::sfrag(X[t], kk);
-      acc0 = P::mma(af(ob, t, kk), b, acc0);
-      acc1 = P::mma(af(ob + 1, t, kk), b, acc1);
+  for (int s = 0; s < NS; ++s) {
+    const int t = s / P::KS, kk = s % P::KS;
+    const auto b = P::sfrag(X[t], kk);
+    const auto a0 = fa[s % PF], a1 = fb[s % PF];
+    if (s + PF < NS) {
+      fa[s % PF] = af(ob, (s + PF) / P::KS, (s + PF) % P::KS);
+      fb[s % PF] = af(ob + 1, (s + PF) / P::KS, (s + PF) % P::KS);
     }
+    acc0 = P::mma(a0, b, acc0);
+    acc1 = P::mma(a1, b, acc1);
+  }
 }
 
 __device__ __forceinline__ void relu16(floatx16& a) {
@@ -800,8 +814,25 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
       }
 
       if constexpr (!CF::reg_layer(l)) {
-        // fold this iteration's blocks into the work-group's partial row
+        // fold this iteration's blocks into the work-group's partial row.  Every
+        // running sum is loaded before the first store: a store may alias a later
+        // load as far as the compiler knows, so interleaving them would cost one
+        // memory round trip per element.
         const int win = nv.s.win(l);
+        float old[PREFETCH ? 1 : OBW][PREFETCH ? 1 : CF::IBWMAX][16];
+        if constexpr (!PREFETCH) {
+#pragma unroll
+          for (int a = 0; a < OBW; ++a)
+#pragma unroll
+            for (int b = 0; b < CF::IBWMAX; ++b)
+              if (b < IBWl) {
+                const int ob = wo * OBW + a, ib = wi * IBWl + b, i = 32 * ib + fl;
+                const float* p0 = partial + nv.s.woff(l) + (size_t)(32 * ob + 4 * h) * win + i;
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                  old[a][b][r] = (!first && i < win) ? p0[(size_t)(8 * (r >> 2) + (r & 3)) * win] : 0.f;
+              }
+        }
 #pragma unroll
         for (int a = 0; a < OBW; ++a)
 #pragma unroll
@@ -814,9 +845,9 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
                 for (int r = 0; r < 16; ++r) {
                   float* q = p0 + (size_t)(8 * (r >> 2) + (r & 3)) * win;
                   float old_v;
-                  if constexpr (PREFETCH) old_v = prev[a][b][r];
-                  else old_v = first ? 0.f : *q;
-                  *q = first ? dacc[l][a][b][r] : old_v + dacc[l][a][b][r];
+                  if constexpr (PREFETCH) old_v = first ? 0.f : prev[a][b][r];
+                  else old_v = old[a][b][r];
+                  *q = old_v + dacc[l][a][b][r];
                 }
               }
               dacc[l][a][b] = floatx16{};

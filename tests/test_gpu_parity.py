@@ -412,7 +412,7 @@ def test_fit_sequence_matches_oracle(gpu_lib):
     classifier (64x3, PE-6, FP32): frame 0 cold then refit, frames 1-3 warm-started with the
     device-side stop test.  Graph and stream launches agree bit for bit; the stop
     decisions follow the library's own losses exactly; losses, step counts and
-    per-frame weights match the FP64 oracle's sequence."""
+    per-frame weights match the FP64 oracle replaying each frame."""
     centers = [(32.0 + 0.25 * i, 32.0, 32.0 - 0.125 * i) for i in range(4)]
     vols = [workloads.sphere_sdf(center=c, radius=22.0) for c in centers]
     trees = [gpu_lib.Tree(v.to(DEV), (0, 0, 0), T.SDF, 3.0) for v in vols]
@@ -423,9 +423,7 @@ def test_fit_sequence_matches_oracle(gpu_lib):
     cold = dict(steps=100, batch=2048, seed=3, lr=3e-3, lr_decay=0.975, lr_interval=100)
     warm = dict(steps=20, batch=2048, seed=11, lr=5e-4, lr_decay=0.975, lr_interval=100)
     S = warm["steps"]
-    # Over 120 steps the FP32 trajectory drifts from the FP64 one by more than in
-    # the short fits: losses are compared to 2e-3 relative.
-    LTOL = 2e-3
+    LTOL = 5e-4  # loss agreement over a replayed frame of <= 20 steps
 
     def run(use_graph):
         m = gpu_lib.Model({0: (64, 3, 18, 1), 1: (64, 3, 18, 1)}, precision=gpu_lib.FP32, domain_size=64,
@@ -455,23 +453,30 @@ def test_fit_sequence_matches_oracle(gpu_lib):
             assert reps[f][0][k] == want, (k, f, seg, target)
             assert np.all(seg[want:] == seg[want - 1])
             assert reps[f][1][k] == seg[-1]
-        # the FP64 oracle's sequence
-        ths, runs, lo = F.train_sequence(th0[k].astype(np.float64), shapes, B.astype(np.float64), otrees, net,
-                                         (0, 0, 0), 64, T.SDF, 3.0, cold, warm)
-        assert np.max(np.abs(L[k, :c0] - lo[0]) / lo[0]) <= LTOL
-        rel = np.linalg.norm(fp[0, k * P:(k + 1) * P] - ths[0]) / np.linalg.norm(ths[0] - th0[k])
-        assert rel <= 2e-2, rel
+        # The FP64 oracle.  Over 120 steps at these rates the FP32 and FP64
+        # trajectories drift apart (Adam turns last-bit differences of near-zero
+        # gradients into +-lr steps), so the cold pass is compared over its first
+        # 10 steps and every later frame is replayed by the oracle from the
+        # library's own weights at the start of that frame.
+        _, _, _, lc = F.train(th0[k].astype(np.float64), shapes, B.astype(np.float64), otrees[0], net, (0, 0, 0),
+                              64, T.SDF, 3.0, 10, cold["batch"], seed=cold["seed"], lr0=cold["lr"])
+        assert np.max(np.abs(L[k, :10] - lc) / lc) <= 1e-4
         for f in range(1, 4):
+            start = fp[f - 1, k * P:(k + 1) * P].astype(np.float64)
+            tho, _, _, lo = F.train(start, shapes, B.astype(np.float64), otrees[f], net, (0, 0, 0), 64, T.SDF, 3.0,
+                                    S, warm["batch"], seed=warm["seed"] + f, lr0=warm["lr"],
+                                    stop_below=float(target))
             r = reps[f][0][k]
             seg = L[k, c0 + (f - 1) * S: c0 + (f - 1) * S + r]
-            if r != runs[f]:
-                # a different stop is acceptable only where the oracle's deciding
-                # loss sits at the target to within the FP32 agreement
-                j = min(r, runs[f]) - 1
-                assert abs(lo[f][j] - lo[0][-1]) <= 2 * LTOL * lo[0][-1], (k, f, r, runs[f])
-                break
-            assert np.max(np.abs(seg - lo[f]) / lo[f]) <= LTOL
-            rel = np.linalg.norm(fp[f, k * P:(k + 1) * P] - ths[f]) / np.linalg.norm(ths[f] - th0[k])
+            n = min(r, len(lo))
+            assert np.max(np.abs(seg[:n] - lo[:n]) / lo[:n]) <= LTOL, (k, f)
+            if r != len(lo):
+                # a different stop only where the deciding loss sits at the target
+                # to within the FP32 agreement
+                assert abs(lo[n - 1] - target) <= 2 * LTOL * target, (k, f, r, len(lo))
+                continue
+            upd = np.linalg.norm(tho - start)
+            rel = np.linalg.norm(fp[f, k * P:(k + 1) * P] - tho) / max(upd, 1e-30)
             assert rel <= 2e-2, (k, f, rel)
 
 
