@@ -190,8 +190,10 @@ nvdb_status nvdb_fit(nvdb_model* model, const nvdb_tree* tree, const nvdb_fit_de
  * (zero moments, step counter 1) and draws i.i.d. batches with seed
  * cold->seed (frame 0, first pass) or warm->seed + f (frame f's warm pass).
  * cold and warm must select the same networks, have >= 1 step and no explicit
- * index lists.  use_graph != 0 captures the whole sequence (every step of every
- * frame) into one HIP graph and launches it once on `stream`.
+ * index lists.  use_graph != 0 records the schedule as HIP graphs of up to 512
+ * steps each (fills, steps and per-frame copies; the stop test lives in the
+ * kernels, so the graphs hold no host decision) and launches them in order on
+ * `stream`.
  * Outputs (each may be NULL):
  *   reports[n_frames]  steps run per network (frame 0 counts both passes) and
  *                      the loss of the frame's last step that ran;

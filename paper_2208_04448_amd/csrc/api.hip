@@ -546,20 +546,54 @@ nvdb_status nvdb_fit(nvdb_model* m, const nvdb_tree* tree, const nvdb_fit_desc* 
 
 }  // extern "C"
 
-// Ends a stream capture that an exception interrupted and releases the graph objects.
-struct CaptureGuard {
-  hipStream_t cs = nullptr;
-  bool capturing = false;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  ~CaptureGuard() {
+// Records a long run of launches as a series of HIP graphs of at most
+// MAX_STEPS optimiser steps each, launched in order on the caller's stream.
+// Graphs are kept to a few thousand nodes: the whole schedule of a long
+// sequence (tens of thousands of steps, four launches each) recorded as one
+// graph made the host runtime crash, while graphs of ~10^4 nodes ran.  Every
+// executable graph stays alive until the caller has synchronised.
+struct GraphChunks {
+  static constexpr int MAX_STEPS = 512;
+  hipStream_t main = nullptr, cs = nullptr;
+  bool on = false, capturing = false;
+  int steps = 0;
+  std::vector<hipGraphExec_t> execs;
+  GraphChunks(hipStream_t st, bool use) : main(st), on(use) {
+    if (on) NVDB_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  }
+  // stream on which the next operation is to be enqueued
+  hipStream_t q() {
+    if (!on) return main;
+    if (!capturing) {
+      NVDB_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      capturing = true;
+    }
+    return cs;
+  }
+  void step_done() {
+    if (on && ++steps >= MAX_STEPS) flush();
+  }
+  void flush() {
+    if (!capturing) return;
+    capturing = false;
+    steps = 0;
+    hipGraph_t g = nullptr;
+    NVDB_HIP(hipStreamEndCapture(cs, &g));
+    hipGraphExec_t e = nullptr;
+    const hipError_t r = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    NVDB_HIP(r);
+    execs.push_back(e);
+    NVDB_HIP(hipGraphLaunch(e, main));
+  }
+  ~GraphChunks() {
     if (capturing) {
       hipGraph_t g = nullptr;
       (void)hipStreamEndCapture(cs, &g);
       if (g) (void)hipGraphDestroy(g);
     }
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    if (!execs.empty()) (void)hipStreamSynchronize(main);
+    for (auto e : execs) (void)hipGraphExecDestroy(e);
     if (cs) (void)hipStreamDestroy(cs);
   }
 };
@@ -593,14 +627,7 @@ nvdb_status nvdb_fit_sequence(nvdb_model* m, const nvdb_tree* const* frames, int
     const auto groups = kernel_groups(m, nets);
     hipStream_t st = (hipStream_t)stream;
 
-    CaptureGuard cap;
-    hipStream_t q = st;
-    if (use_graph) {
-      NVDB_HIP(hipStreamCreateWithFlags(&cap.cs, hipStreamNonBlocking));
-      NVDB_HIP(hipStreamBeginCapture(cap.cs, hipStreamCaptureModeThreadLocal));
-      cap.capturing = true;
-      q = cap.cs;
-    }
+    GraphChunks cap(st, use_graph != 0);
     int64_t frame_stride = 0;
     for (int k : nets) frame_stride += m->nets[k].s.nparams();
     int64_t g = 0;  // global step index into each network's loss / ran arrays
@@ -608,8 +635,8 @@ nvdb_status nvdb_fit_sequence(nvdb_model* m, const nvdb_tree* const* frames, int
     auto run_pass = [&](const Tree* tree, const nvdb_fit_desc* d, uint64_t seed, bool stop_test) {
       for (int k : nets) {
         Net& N = m->nets[k];
-        launch_fill(N.m.p, N.s.nparams(), 0.f, q);
-        launch_fill(N.v.p, N.s.nparams(), 0.f, q);
+        launch_fill(N.m.p, N.s.nparams(), 0.f, cap.q());
+        launch_fill(N.v.p, N.s.nparams(), 0.f, cap.q());
         N.step = 0;
       }
       const Phase ph{d->batch, seed, d->lr, d->lr_decay, d->lr_interval, nullptr};
@@ -624,7 +651,8 @@ nvdb_status nvdb_fit_sequence(nvdb_model* m, const nvdb_tree* const* frames, int
             hk.stop_below[k] = N.losses.p + (cold->steps + warm->steps - 1);
           }
         }
-        enqueue_step(m, tree, groups, ph, j, hk, nullptr, q);
+        enqueue_step(m, tree, groups, ph, j, hk, nullptr, cap.q());
+        cap.step_done();
       }
     };
     auto save_frame = [&](int32_t f) {
@@ -632,7 +660,8 @@ nvdb_status nvdb_fit_sequence(nvdb_model* m, const nvdb_tree* const* frames, int
       int64_t off = (int64_t)f * frame_stride;
       for (int k : nets) {
         Net& N = m->nets[k];
-        NVDB_HIP(hipMemcpyAsync(frame_params_dev + off, N.theta.p, N.s.nparams() * 4, hipMemcpyDeviceToDevice, q));
+        NVDB_HIP(hipMemcpyAsync(frame_params_dev + off, N.theta.p, N.s.nparams() * 4, hipMemcpyDeviceToDevice,
+                                cap.q()));
         off += N.s.nparams();
       }
     };
@@ -646,12 +675,7 @@ nvdb_status nvdb_fit_sequence(nvdb_model* m, const nvdb_tree* const* frames, int
       run_pass(frames[f], warm, warm->seed + (uint64_t)f, true);
       save_frame(f);
     }
-    if (use_graph) {
-      cap.capturing = false;
-      NVDB_HIP(hipStreamEndCapture(cap.cs, &cap.graph));
-      NVDB_HIP(hipGraphInstantiate(&cap.exec, cap.graph, nullptr, nullptr, 0));
-      NVDB_HIP(hipGraphLaunch(cap.exec, st));
-    }
+    cap.flush();
     NVDB_HIP(hipStreamSynchronize(st));
 
     // per-frame report; the host step counters follow the steps that actually ran

@@ -706,7 +706,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
       float prev[PREFETCH ? OBW : 1][PREFETCH ? CF::IBWMAX : 1][16];
       if constexpr (PREFETCH) {
         if (!first) {
-          const int win = nv.s.win(l);
+          const int win = (l == 0) ? nv.s.win(0) : W;  // compile-time above layer 0
 #pragma unroll
           for (int a = 0; a < OBW; ++a)
 #pragma unroll
@@ -818,7 +818,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
         // running sum is loaded before the first store: a store may alias a later
         // load as far as the compiler knows, so interleaving them would cost one
         // memory round trip per element.
-        const int win = nv.s.win(l);
+        const int win = (l == 0) ? nv.s.win(0) : W;
         float old[PREFETCH ? 1 : OBW][PREFETCH ? 1 : CF::IBWMAX][16];
         if constexpr (!PREFETCH) {
 #pragma unroll
@@ -1117,10 +1117,16 @@ __device__ __forceinline__ void write_shadow(const AdamNet& A, int64_t p, float 
   }
 }
 
+// One work-group per 64 parameters: its four waves each sum a quarter of the
+// work-group partial rows (four interleaved running sums per lane keep eight
+// loads in flight), then wave 0 combines the quarters in a fixed order, so the
+// result is the same on every run.
+constexpr int RED_P = 64;
 __global__ void __launch_bounds__(256) k_reduce_adam(AdamLaunch AL) {
   const AdamNet& A = AL.nets[blockIdx.y];
   const int64_t P = A.s.nparams();
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int64_t p = (int64_t)blockIdx.x * RED_P + lane;
   if (A.prev_loss && *A.prev_loss < *A.stop_below) {  // skipped step: carry the loss forward
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       if (A.loss_out) *A.loss_out = *A.prev_loss;
@@ -1128,15 +1134,35 @@ __global__ void __launch_bounds__(256) k_reduce_adam(AdamLaunch AL) {
     }
     return;
   }
+  if ((int64_t)blockIdx.x * RED_P >= P) return;  // uniform per work-group
   if (blockIdx.x == 0 && threadIdx.x == 0 && A.ran) *A.ran = 1;
   if (blockIdx.x == 0 && threadIdx.x == 0 && A.loss_out) {
     float L = 0.f;
     for (int g = 0; g < A.G; ++g) L += A.loss_partial[g];
     *A.loss_out = L * A.loss_scale;
   }
-  if (p >= P) return;
-  float g = 0.f;
-  for (int w = 0; w < A.G; ++w) g += A.partial[(size_t)w * P + p];
+  __shared__ float red[4][RED_P];
+  const int per = (A.G + 3) / 4;
+  const int g0 = q * per, g1 = min(A.G, g0 + per);
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  if (p < P) {
+    const float* col = A.partial + p;
+    int g = g0;
+    for (; g + 8 <= g1; g += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = col[(size_t)(g + u) * P];
+      s0 += v[0] + v[4];
+      s1 += v[1] + v[5];
+      s2 += v[2] + v[6];
+      s3 += v[3] + v[7];
+    }
+    for (; g < g1; ++g) s0 += col[(size_t)g * P];
+  }
+  red[q][lane] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  if (q != 0 || p >= P) return;
+  const float g = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
   if (A.grad_out) {
     A.grad_out[p] = g;
     return;
@@ -1211,7 +1237,7 @@ void launch_infer(const KernelSet& ks, const InferLaunch& I, int grid, hipStream
   NVDB_HIP(hipGetLastError());
 }
 void launch_reduce_adam(const AdamLaunch& A, int64_t max_p, int n_nets, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_adam, dim3((unsigned)((max_p + 255) / 256), n_nets), dim3(256), 0, st, A);
+  hipLaunchKernelGGL(k_reduce_adam, dim3((unsigned)((max_p + RED_P - 1) / RED_P), n_nets), dim3(256), 0, st, A);
   NVDB_HIP(hipGetLastError());
 }
 void launch_write_shadow(const AdamNet& A, hipStream_t st) {

@@ -480,6 +480,25 @@ def test_fit_sequence_matches_oracle(gpu_lib):
             assert rel <= 2e-2, (k, f, rel)
 
 
+def test_fit_sequence_graph_chunks(gpu_lib, sphere):
+    """A schedule of 1,500 steps is recorded as several graphs (512 steps each);
+    the result equals the stream-launched sequence bit for bit."""
+    tr, _ = sphere
+    cold = dict(steps=600, batch=256, seed=5, lr=1e-3)
+    warm = dict(steps=300, batch=256, seed=6, lr=1e-4)
+
+    def run(use_graph):
+        m = gpu_lib.Model({0: (64, 3, 18, 1)}, precision=gpu_lib.BF16, domain_size=64, value_scale=3.0)
+        m.set_params(0, workloads.init_params(36, 64, 3, 1, seed=2))
+        m.set_encoding(0, workloads.pe_matrix(6))
+        reps, L, fp = m.fit_sequence([tr, tr, tr], cold, warm, nets_mask=1, use_graph=use_graph)
+        return reps, L, fp.cpu().numpy()
+
+    a, b = run(True), run(False)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    assert a[0][0][0][0] == 900 and all(1 <= r[0][0] <= 300 for r in a[0][1:])
+
+
 def test_fit_sequence_rejects_bad_schedules(gpu_lib, sphere):
     tr, _ = sphere
     m = gpu_lib.Model({0: (64, 3, 18, 1)}, precision=gpu_lib.FP32, domain_size=64, value_scale=3.0)
