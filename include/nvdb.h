@@ -179,6 +179,29 @@ typedef struct {
 nvdb_status nvdb_fit(nvdb_model* model, const nvdb_tree* tree, const nvdb_fit_desc* fit, float* loss_host,
                      void* stream);
 
+/* Launch-shape autotuner.  The training step splits each network's batch over
+ * G work-groups (tiles of 128 samples, one partial gradient row per work-group,
+ * reduced in a fixed order before Adam); G trades the reduction's traffic
+ * against filling the 256 compute units.  nvdb_autotune times reps training
+ * steps of `batch` samples on `tree` (the gradient is computed and discarded:
+ * parameters, optimiser state and step counters are left as they were) for each
+ * candidate G in {32, 64, 128, 192, 256, 320, 384, 512} not above the tile count,
+ * plus the tile count itself, and keeps the fastest for later nvdb_fit,
+ * nvdb_fit_sequence and nvdb_backward_dev calls on this model.  Results for a
+ * given G are deterministic; another G sums the same gradient in another order.
+ * nvdb_model_set_train_groups sets G directly (0 restores the default, 256).
+ * Synchronises `stream`.  Errors: E_INVALID, E_STATE as nvdb_fit. */
+#define NVDB_TUNE_MAX 16
+typedef struct {
+  int32_t chosen_g;
+  int32_t n_candidates;
+  int32_t g[NVDB_TUNE_MAX];
+  float ms_per_step[NVDB_TUNE_MAX];  /* train + reduce launches of one step */
+} nvdb_tune_report;
+nvdb_status nvdb_autotune(nvdb_model* model, const nvdb_tree* tree, int32_t nets_mask, int32_t batch, int32_t reps,
+                          nvdb_tune_report* report, void* stream);
+nvdb_status nvdb_model_set_train_groups(nvdb_model* model, int32_t g);
+
 /* Temporally coherent warm-start encoder for an animated sequence (Sec. 3.6).
  * Frame 0 is fitted from the model's current parameters with `cold` (the
  * target learning rate), then fitted again with `warm` (a rate up to 100x

@@ -9,7 +9,8 @@
 
 namespace nvdb {
 
-constexpr int MAX_G = 256;        // work-groups (partial gradient rows) per network
+constexpr int MAX_G = 512;        // work-groups (partial gradient rows) per network
+constexpr int DEFAULT_G = 256;    // used until nvdb_autotune picks another
 constexpr int TRAIN_TILE = 128;   // samples per work-group iteration
 
 struct Net {
@@ -34,6 +35,7 @@ struct nvdb_tree : nvdb::Tree {};
 struct nvdb_model {
   nvdb_model_desc d{};
   nvdb::Net nets[NVDB_MAX_NETS];
+  int train_g = 0;  // work-groups per network chosen by nvdb_autotune (0: default)
 };
 
 using namespace nvdb;
@@ -358,13 +360,16 @@ struct Phase {
 // Per-step device pointers: where each network's batch loss goes and the
 // optional stop test of warm-started frames.
 struct StepHooks {
+  float* grad_out[NVDB_MAX_NETS] = {};  // non-null: write the summed gradient there, no Adam step
   float* loss_out[NVDB_MAX_NETS] = {};
   const float* prev_loss[NVDB_MAX_NETS] = {};
   const float* stop_below[NVDB_MAX_NETS] = {};
   int32_t* ran[NVDB_MAX_NETS] = {};
 };
 
-static int train_grid(int64_t n) { return (int)std::min<int64_t>(MAX_G, (n + TRAIN_TILE - 1) / TRAIN_TILE); }
+static int train_grid(int64_t n, int g = DEFAULT_G) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, (n + TRAIN_TILE - 1) / TRAIN_TILE));
+}
 
 // Networks that share a kernel go into one launch (gridDim.y = network).
 static std::vector<std::vector<int>> kernel_groups(const nvdb_model* m, const std::vector<int>& nets) {
@@ -406,8 +411,8 @@ static void check_schedule(const nvdb_fit_desc* f) {
 }
 
 // Workspace for steps of `batch` samples; allocates, so never called under capture.
-static void reserve_step(Net& N, int32_t batch, int32_t n_steps) {
-  const int G = std::max(1, train_grid(batch));
+static void reserve_step(Net& N, int32_t batch, int32_t n_steps, int g) {
+  const int G = train_grid(batch, g);
   ensure_partials(N, G);
   N.xt.ensure(std::max<int64_t>(batch, 1));
   N.losses.ensure(std::max(n_steps, 1));
@@ -451,7 +456,7 @@ static void enqueue_step(nvdb_model* m, const Tree* tree, const std::vector<std:
       tn.spec.inv_n = 1.f / (float)n;
       tn.prev_loss = hk.prev_loss[k];
       tn.stop_below = hk.stop_below[k];
-      G = std::max(G, train_grid(n));
+      G = std::max(G, train_grid(n, m->train_g > 0 ? m->train_g : DEFAULT_G));
     }
     slot = 0;
     for (int k : grp) {
@@ -476,6 +481,7 @@ static void enqueue_step(nvdb_model* m, const Tree* tree, const std::vector<std:
       a.prev_loss = hk.prev_loss[k];
       a.stop_below = hk.stop_below[k];
       a.ran = hk.ran[k];
+      a.grad_out = hk.grad_out[k];
       AL.nets[na++] = a;
       maxP = std::max(maxP, N.s.nparams());
     }
@@ -486,7 +492,8 @@ static void enqueue_step(nvdb_model* m, const Tree* tree, const std::vector<std:
   }
   launch_reduce_adam(AL, maxP, na, st);
   for (auto& grp : groups)
-    for (int k : grp) m->nets[k].step += 1;
+    for (int k : grp)
+      if (!hk.grad_out[k]) m->nets[k].step += 1;
 }
 
 extern "C" {
@@ -501,7 +508,7 @@ nvdb_status nvdb_fit(nvdb_model* m, const nvdb_tree* tree, const nvdb_fit_desc* 
       if (fit->idx_dev[k])
         NVDB_REQUIRE(fit->idx_count[k] > (int64_t)(fit->steps - 1) * fit->batch, NVDB_E_INVALID,
                      "explicit index list shorter than the schedule");
-    for (int k : nets) reserve_step(m->nets[k], fit->batch, fit->steps);
+    for (int k : nets) reserve_step(m->nets[k], fit->batch, fit->steps, m->train_g > 0 ? m->train_g : DEFAULT_G);
     const auto groups = kernel_groups(m, nets);
     const Phase ph{fit->batch, fit->seed, fit->lr, fit->lr_decay, fit->lr_interval, fit};
 
@@ -541,6 +548,84 @@ nvdb_status nvdb_fit(nvdb_model* m, const nvdb_tree* tree, const nvdb_fit_desc* 
       }
       NVDB_REQUIRE(finite, NVDB_E_NUMERIC, "non-finite loss during fit");
     }
+  });
+}
+
+nvdb_status nvdb_autotune(nvdb_model* m, const nvdb_tree* tree, int32_t nets_mask, int32_t batch, int32_t reps,
+                          nvdb_tune_report* report, void* stream) {
+  return guarded([&] {
+    NVDB_REQUIRE(m && tree && batch >= 1 && batch <= (1 << 24) && reps >= 1 && reps <= 1000, NVDB_E_INVALID,
+                 "bad autotune arguments");
+    hipStream_t st = (hipStream_t)stream;
+    const std::vector<int> nets = fit_nets(m, tree, nets_mask);
+    const auto groups = kernel_groups(m, nets);
+    const int tiles = (int)std::min<int64_t>(MAX_G, ((int64_t)batch + TRAIN_TILE - 1) / TRAIN_TILE);
+    static const int cand_all[] = {32, 64, 128, 192, 256, 320, 384, 512};
+    std::vector<int> cands;
+    for (int g : cand_all)
+      if (g <= tiles) cands.push_back(g);
+    if (cands.empty() || cands.back() != tiles) cands.push_back(tiles);
+    NVDB_REQUIRE((int)cands.size() <= NVDB_TUNE_MAX, NVDB_E_INVALID, "too many candidates");
+    std::vector<DevBuf<float>> grads(NVDB_MAX_NETS);
+    for (int k : nets) {
+      reserve_step(m->nets[k], batch, 1, MAX_G);
+      grads[k].alloc(m->nets[k].s.nparams());
+    }
+    const int saved_g = m->train_g;
+    std::vector<int64_t> saved_step(NVDB_MAX_NETS);
+    for (int k : nets) saved_step[k] = m->nets[k].step;
+    hipEvent_t e0, e1;
+    NVDB_HIP(hipEventCreate(&e0));
+    NVDB_HIP(hipEventCreate(&e1));
+    int best = cands[0];
+    float best_ms = 0.f;
+    std::vector<float> times;
+    try {
+      const Phase ph{batch, 0x5eedull, 0.f, 1.f, 1, nullptr};
+      StepHooks hk;
+      for (int k : nets) hk.grad_out[k] = grads[k].p;
+      for (size_t c = 0; c < cands.size(); ++c) {
+        m->train_g = cands[c];
+        enqueue_step(m, tree, groups, ph, 0, hk, nullptr, st);  // warm-up
+        NVDB_HIP(hipEventRecord(e0, st));
+        for (int r = 0; r < reps; ++r) enqueue_step(m, tree, groups, ph, 0, hk, nullptr, st);
+        NVDB_HIP(hipEventRecord(e1, st));
+        NVDB_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        NVDB_HIP(hipEventElapsedTime(&ms, e0, e1));
+        ms /= (float)reps;
+        times.push_back(ms);
+        if (c == 0 || ms < best_ms) {
+          best_ms = ms;
+          best = cands[c];
+        }
+      }
+    } catch (...) {
+      m->train_g = saved_g;
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (int k : nets) m->nets[k].step = saved_step[k];
+    m->train_g = best;
+    if (report) {
+      std::memset(report, 0, sizeof(*report));
+      report->chosen_g = best;
+      report->n_candidates = (int32_t)cands.size();
+      for (size_t c = 0; c < cands.size(); ++c) {
+        report->g[c] = cands[c];
+        report->ms_per_step[c] = times[c];
+      }
+    }
+  });
+}
+
+nvdb_status nvdb_model_set_train_groups(nvdb_model* m, int32_t g) {
+  return guarded([&] {
+    NVDB_REQUIRE(m && g >= 0 && g <= MAX_G, NVDB_E_INVALID, "work-groups per network must be in 0..512");
+    m->train_g = g;
   });
 }
 
@@ -622,7 +707,7 @@ nvdb_status nvdb_fit_sequence(nvdb_model* m, const nvdb_tree* const* frames, int
     NVDB_REQUIRE(total < (1ll << 30), NVDB_E_INVALID, "schedule too long");
     for (int k : nets) {
       Net& N = m->nets[k];
-      reserve_step(N, std::max(cold->batch, warm->batch), (int32_t)total);
+      reserve_step(N, std::max(cold->batch, warm->batch), (int32_t)total, m->train_g > 0 ? m->train_g : DEFAULT_G);
     }
     const auto groups = kernel_groups(m, nets);
     hipStream_t st = (hipStream_t)stream;
@@ -805,7 +890,7 @@ nvdb_status nvdb_backward_dev(nvdb_model* m, int32_t net, const float* x_dev, co
     NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "parameters or encoding not set");
     NVDB_REQUIRE(n >= 1 && x_dev && gy_dev && grad_dev, NVDB_E_INVALID, "bad buffers");
     hipStream_t st = (hipStream_t)stream;
-    const int G = (int)std::min<int64_t>(MAX_G, (n + TRAIN_TILE - 1) / TRAIN_TILE);
+    const int G = train_grid(n, m->train_g > 0 ? m->train_g : DEFAULT_G);
     ensure_partials(N, G);
     TrainLaunch L{};
     L.G = G;

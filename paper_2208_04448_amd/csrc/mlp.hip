@@ -444,6 +444,8 @@ __device__ __forceinline__ void layer_block2(const AF& af, int ob, const uint32_
     }
     acc0 = P::mma(a0, b, acc0);
     acc1 = P::mma(a1, b, acc1);
+    // keep the scheduler from sinking the prefetch back next to its use
+    if constexpr (PREC == NVDB_BF16) __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -702,7 +704,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
       if constexpr (l == 0) encode_S<PREC, NIB0>(smp, sm_benc, nv.nfreq, X0);
       // layers folded into the partial row: fetch the running sums now so that the
       // loads complete under the exchange below
-      constexpr bool PREFETCH = !CF::reg_layer(l) && l == 0;  // registers are free only at layer 0
+      constexpr bool PREFETCH = !CF::reg_layer(l) && (BF || l == 0);  // FP32: registers allow layer 0 only
       float prev[PREFETCH ? OBW : 1][PREFETCH ? CF::IBWMAX : 1][16];
       if constexpr (PREFETCH) {
         if (!first) {

@@ -57,6 +57,11 @@ class FrameReport(C.Structure):
     _fields_ = [("steps_run", C.c_int32 * 3), ("final_loss", C.c_float * 3)]
 
 
+class TuneReport(C.Structure):
+    _fields_ = [("chosen_g", C.c_int32), ("n_candidates", C.c_int32), ("g", C.c_int32 * 16),
+                ("ms_per_step", C.c_float * 16)]
+
+
 class ErrorReport(C.Structure):
     _fields_ = [("n", C.c_int64), ("max_abs", C.c_double), ("rms", C.c_double), ("iou", C.c_double),
                 ("fp", C.c_int64), ("fn", C.c_int64)]
@@ -82,6 +87,8 @@ _SIGS = {
     "nvdb_fit": (C.c_int32, [_P, _P, C.POINTER(FitDesc), _P, _P]),
     "nvdb_fit_sequence": (C.c_int32, [_P, _P, C.c_int32, C.POINTER(FitDesc), C.POINTER(FitDesc), C.c_int32, _P, _P,
                                       _P, _P]),
+    "nvdb_autotune": (C.c_int32, [_P, _P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(TuneReport), _P]),
+    "nvdb_model_set_train_groups": (C.c_int32, [_P, C.c_int32]),
     "nvdb_decode": (C.c_int32, [_P, _P, _P, _P, _P]),
     "nvdb_decode_l1": (C.c_int32, [_P, _P, _P, _P]),
     "nvdb_errors": (C.c_int32, [_P, _P, _P, C.POINTER(ErrorReport), _P]),
@@ -224,6 +231,16 @@ class Model:
         if kernel_times is not None:
             kernel_times["train_kernel_ms"] = tk.value
         return losses[:, :steps] if return_losses else None
+
+    def autotune(self, tree, nets_mask, batch, reps=5):
+        """Pick the work-groups per network for training steps of `batch` samples;
+        returns (chosen G, {G: ms per step})."""
+        r = TuneReport()
+        _check(_lib.nvdb_autotune(self.h, tree.h, nets_mask, batch, reps, C.byref(r), _stream()))
+        return r.chosen_g, {r.g[i]: r.ms_per_step[i] for i in range(r.n_candidates)}
+
+    def set_train_groups(self, g):
+        _check(_lib.nvdb_model_set_train_groups(self.h, int(g)))
 
     def fit_sequence(self, frames, cold, warm, nets_mask, use_graph=True, frame_params=True):
         """Warm-started fit of an animated sequence (one tree per frame).

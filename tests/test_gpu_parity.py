@@ -509,3 +509,37 @@ def test_fit_sequence_rejects_bad_schedules(gpu_lib, sphere):
         with pytest.raises(gpu_lib.NvdbError) as e:
             m.fit_sequence([tr, tr], cold, warm, nets_mask=mask)
         assert e.value.code == gpu_lib.E_INVALID
+
+
+# --------------------------------------------------------------------------- launch-shape autotuner
+def test_autotune_leaves_state_and_fits_match(gpu_lib, sphere):
+    """The autotuner picks one of its candidates, leaves parameters, moments and
+    step counters untouched, and fits with any work-group count agree with the
+    FP64 oracle; a given count is deterministic."""
+    tr, ot = sphere
+    shapes = mlp.layer_shapes(36, 64, 3, 1)
+    B = workloads.pe_matrix(6)
+    th0 = workloads.init_params(36, 64, 3, 1, seed=8)
+    m = gpu_lib.Model({0: (64, 3, 18, 1)}, precision=gpu_lib.FP32, domain_size=64, value_scale=3.0)
+    m.set_params(0, th0)
+    m.set_encoding(0, B)
+    m.fit(tr, steps=2, batch=4096, nets_mask=1, seed=1)
+    before = (m.get_params(0), m.get_opt_state(0))
+    g, times = m.autotune(tr, nets_mask=1, batch=1 << 14, reps=2)
+    assert g in times and set(times) <= {32, 64, 128, 192, 256, 320, 384, 512, 128}
+    assert times[g] == min(times.values()) and all(t > 0 for t in times.values())
+    after = (m.get_params(0), m.get_opt_state(0))
+    assert np.array_equal(before[0], after[0])
+    assert all(np.array_equal(a, b) for a, b in zip(before[1][:2], after[1][:2])) and before[1][2] == after[1][2]
+    _, _, _, lo = F.train(th0.astype(np.float64), shapes, B.astype(np.float64), ot, "regressor", (0, 0, 0), 64,
+                          T.SDF, 3.0, steps=4, batch=1 << 14, seed=9)
+    res = {}
+    for gg in (32, 128, g):
+        for rep in range(2):
+            m.set_params(0, th0)
+            m.set_opt_state(0, np.zeros_like(th0), np.zeros_like(th0), 0)
+            m.set_train_groups(gg)
+            L = m.fit(tr, steps=4, batch=1 << 14, nets_mask=1, seed=9)[0]
+            res.setdefault(gg, []).append((L, m.get_params(0)))
+        assert np.array_equal(res[gg][0][1], res[gg][1][1]) and np.array_equal(res[gg][0][0], res[gg][1][0])
+        assert np.max(np.abs(res[gg][0][0] - lo) / lo) <= 1e-5
