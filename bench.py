@@ -11,9 +11,15 @@ Workload (one "step" = one pass of the whole hot path over the volume):
     full decode (regressor at every active voxel, classifier at every voxel slot
     of every leaf) and the error report.
 value = training samples (fwd+bwd, both networks) per second of whole-step time.
-The same job runs once in the plain FP32 form for the equal-error comparison;
-the FP64 oracle is timed on a bounded sample of the same workload on the host.
+The launch shape (work-groups per network) comes from the library's autotuner,
+run once before the timed region.  The same job runs once in the plain FP32
+form for the equal-error comparison; the FP64 oracle is timed on a bounded
+sample of the same workload on the host.  Two further legs are reported beside
+the headline (not in `value`): the warm-started sequence fit of 16 frames of an
+advected water surface (1024 x 256 x 1024) and the two-level fog-volume decode
+of a 1024^3 fBm cloud.
 """
+import hashlib
 import argparse
 import json
 import os
@@ -52,6 +58,10 @@ def main():
     ap.add_argument("--fit-steps", type=int, default=2000)
     ap.add_argument("--skip-fp32", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-sequence", action="store_true")
+    ap.add_argument("--skip-cloud", action="store_true")
+    ap.add_argument("--seq-frames", type=int, default=16)
+    ap.add_argument("--seq-cap", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (N=%d requested)" % args.gpus,
@@ -105,6 +115,12 @@ def main():
         return tree, values, masks, rep, losses
 
     bf = make_model(nvdb.BF16)
+    tune_tree = nvdb.Tree(grid, (0, 0, 0), nvdb.SDF, BAND)
+    for k in (0, 1):
+        bf.set_params(k, theta0[k])
+    tuned_g, tune_ms = bf.autotune(tune_tree, nets_mask=3, batch=BATCH, reps=3)
+    del tune_tree
+    print("autotune: G=%d %s" % (tuned_g, {g: round(t, 4) for g, t in tune_ms.items()}), file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         job(bf, args.fit_steps)
     torch.cuda.synchronize()
@@ -154,15 +170,21 @@ def main():
         "bf16": {"max_abs_err_voxels": rep["max_abs"], "rms_err_voxels": rep["rms"], "iou": rep["iou"],
                  "l0_fp": rep["fp"], "l0_fn": rep["fn"], "final_loss": [float(losses[0, -1]), float(losses[1, -1])]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_BF16_TFLOPS, "traffic": measured_traffic(),
                      "kernel": "k_train<bf16,128,4,128,1> (both networks per launch)",
                      "flops_per_launch": launch_flops, "avg_launch_ms": train_launch_s * 1e3},
+        "autotune": {"work_groups_per_network": tuned_g, "ms_per_step": {str(g): t for g, t in tune_ms.items()}},
     }
     print("bf16 jobs: %s s" % ["%.3f" % t for t in times], file=sys.stderr, flush=True)
 
     if not args.skip_fp32:
         print("fp32 form job (%d steps) ..." % args.fit_steps, file=sys.stderr, flush=True)
         fp = make_model(nvdb.FP32)
+        for k in (0, 1):
+            fp.set_params(k, theta0[k])
+        tt = nvdb.Tree(grid, (0, 0, 0), nvdb.SDF, BAND)
+        g32, _ = fp.autotune(tt, nets_mask=3, batch=BATCH, reps=2)
+        del tt
         t32 = {}
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -176,7 +198,8 @@ def main():
             "max_abs_err_voxels": rep32["max_abs"], "rms_err_voxels": rep32["rms"], "iou": rep32["iou"],
             "l0_fp": rep32["fp"], "l0_fn": rep32["fn"],
             "final_loss": [float(losses32[0, -1]), float(losses32[1, -1])],
-            "train_tflops": a32, "train_frac_of_fp32_peak": a32 / PEAK_FP32_TFLOPS}
+            "train_tflops": a32, "train_frac_of_fp32_peak": a32 / PEAK_FP32_TFLOPS,
+            "work_groups_per_network": g32}
         out["bf16_vs_fp32"] = {"speedup_whole_step": out["value"] / out["fp32_form"]["train_samples_per_s"],
                                "bf16_reaches_fp32_max_err": rep["max_abs"] <= rep32["max_abs"],
                                "equal_steps": args.fit_steps}
@@ -185,8 +208,149 @@ def main():
     if not args.skip_cpu:
         print("cpu baseline (FP64 oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(grid)
+    del grid, bf
+    torch.cuda.empty_cache()
+    if not args.skip_sequence:
+        print("sequence leg ...", file=sys.stderr, flush=True)
+        out["sequence"] = sequence_leg(args.seq_frames, args.seq_cap, tuned_g)
+        torch.cuda.empty_cache()
+    if not args.skip_cloud:
+        print("cloud leg ...", file=sys.stderr, flush=True)
+        out["cloud"] = cloud_leg(args.fit_steps, tuned_g)
 
     print(json.dumps(out), flush=True)
+
+
+def measured_traffic():
+    """HBM bytes per launch of the timed train kernel from the committed rocprofv3
+    counter summary, or None when the kernel source has changed since."""
+    path = os.path.join(ROOT, "profiles", "k_train_bf16_4x128_sphere512_traffic.json")
+    src = os.path.join(ROOT, "paper_2208_04448_amd", "csrc", "mlp.hip")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
+def sequence_leg(n_frames, cap, tuned_g):
+    """Warm-started fit of an animated sequence: frame 0 cold (2000 steps, lr 1e-3)
+    then refit at 1e-4, later frames warm-started at 1e-4 until the batch loss is
+    below frame 0's final loss (at most `cap` steps); then the last frame fitted
+    cold for 2000 steps for comparison at an equal step budget."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2208_04448_amd import nvdb
+    t = time.perf_counter()
+    trees, counts = [], []
+    for f in range(n_frames):
+        g = workloads.water_frame(f, n_frames=n_frames, device="cuda")
+        trees.append(nvdb.Tree(g, (0, 0, 0), nvdb.SDF, BAND))
+        counts.append(int(trees[-1].info().n_voxels))
+        del g
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t
+    K = 2 * M
+    th0 = {k: workloads.init_params(K, W, H, C, seed=31 + k) for k in (0, 1)}
+    mdl = nvdb.Model({0: (W, H, M, C), 1: (W, H, M, C)}, precision=nvdb.BF16, domain_lo=(0, 0, 0),
+                     domain_size=1024, value_scale=BAND)
+    mdl.set_train_groups(tuned_g)
+    for k in (0, 1):
+        mdl.set_encoding(k, workloads.ffm_matrix(M, 10.0, seed=41 + k))
+        mdl.set_params(k, th0[k])
+    cold = dict(steps=2000, batch=BATCH, seed=0, lr=1e-3)
+    warm = dict(steps=cap, batch=BATCH, seed=1, lr=1e-4)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    reps, _, fp = mdl.fit_sequence(trees, cold, warm, nets_mask=3, use_graph=True)
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - t
+    steps = [int(max(r[0][:2])) for r in reps]
+    P = mdl.param_count(0)
+    frames = []
+    for f in range(n_frames):
+        for k in (0, 1):
+            mdl.set_params(k, fp[f, k * P:(k + 1) * P].cpu().numpy())
+        v, mk = mdl.decode(trees[f])
+        e = nvdb.errors(trees[f], v, mk)
+        frames.append({"voxels": counts[f], "steps": [int(reps[f][0][0]), int(reps[f][0][1])],
+                       "max_abs": e["max_abs"], "rms": e["rms"], "iou": e["iou"], "l0_fp": e["fp"], "l0_fn": e["fn"]})
+    # the last frame from scratch, 2000 steps at the cold rate
+    last = n_frames - 1
+    for k in (0, 1):
+        mdl.set_params(k, th0[k])
+        mdl.set_opt_state(k, np.zeros(P, np.float32), np.zeros(P, np.float32), 0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    mdl.fit(trees[last], steps=2000, batch=BATCH, nets_mask=3, seed=7, lr=1e-3, return_losses=False)
+    torch.cuda.synchronize()
+    cold_s = time.perf_counter() - t
+    v, mk = mdl.decode(trees[last])
+    e = nvdb.errors(trees[last], v, mk)
+    total_steps = sum(steps)
+    return {"workload": "advected noisy water surface 1024x256x1024, %d frames, band +-3; regressor + level-0 "
+                        "classifier 4x128, FFM m=64 sigma=10, BF16, 2^18 samples per network per step" % n_frames,
+            "frame_voxels_min_max": [min(counts), max(counts)], "frames_generated_s": gen_s,
+            "cold": {"steps": 2000, "lr": 1e-3}, "warm": {"cap": cap, "lr": 1e-4},
+            "sequence_s": seq_s, "steps_total": total_steps,
+            "train_samples_per_s": 2 * BATCH * total_steps / seq_s,
+            "warm_frames_hitting_cap": sum(1 for s_ in steps[1:] if s_ >= cap),
+            "frames": frames,
+            "last_frame_cold_2000": {"s": cold_s, "max_abs": e["max_abs"], "rms": e["rms"], "iou": e["iou"],
+                                     "l0_fp": e["fp"], "l0_fn": e["fn"]}}
+
+
+def cloud_leg(fit_steps, tuned_g):
+    """Fog volume: 1024^3 fBm cloud (6 octaves), active where the density exceeds
+    0.55; voxel regressor 4x128 and level-1 node classifier 4x64 (3 classes) fitted
+    for fit_steps steps, then the full decode of every active voxel and every
+    leaf slot of the level-1 nodes."""
+    import torch
+
+    import workloads
+    from paper_2208_04448_amd import nvdb
+    t = time.perf_counter()
+    g = workloads.fbm_cloud(1024, device="cuda")
+    tree = nvdb.Tree(g, (0, 0, 0), nvdb.FOG, 0.55)
+    del g
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t
+    info = tree.info()
+    mdl = nvdb.Model({0: (W, H, M, C), 2: (64, 4, M, 3)}, precision=nvdb.BF16, domain_lo=(0, 0, 0),
+                     domain_size=1024, value_scale=1.0)
+    mdl.set_train_groups(tuned_g)
+    mdl.set_encoding(0, workloads.ffm_matrix(M, 10.0, seed=51))
+    mdl.set_encoding(2, workloads.ffm_matrix(M, 10.0, seed=52))
+    mdl.set_params(0, workloads.init_params(2 * M, W, H, C, seed=53))
+    mdl.set_params(2, workloads.init_params(2 * M, 64, 4, 3, seed=54))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    mdl.fit(tree, steps=fit_steps, batch=BATCH, nets_mask=0b101, seed=0, lr=1e-3, return_losses=False)
+    torch.cuda.synchronize()
+    fit_s = time.perf_counter() - t
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    values, _ = mdl.decode(tree, values=True, masks=False)
+    e1.record()
+    classes = mdl.decode_l1(tree)
+    e2.record()
+    torch.cuda.synchronize()
+    dec_s, l1_s = e0.elapsed_time(e1) / 1e3, e1.elapsed_time(e2) / 1e3
+    rep = nvdb.errors(tree, values)
+    r1 = nvdb.errors_l1(tree, classes)
+    N, L1 = int(info.n_voxels), int(info.n_l1)
+    return {"workload": "fBm cloud 1024^3 (6 octaves, lacunarity 2, gain 0.5), active where density > 0.55; "
+                        "voxel regressor 4x128 + level-1 classifier 4x64 (3 classes), FFM m=64 sigma=10, BF16; "
+                        "%d steps x 2^18 samples per network" % fit_steps,
+            "n_voxels": N, "n_leaves": int(info.n_leaves), "n_l1": L1, "generated_s": gen_s, "fit_s": fit_s,
+            "decoded_voxels_per_s": N / dec_s, "decode_ms": dec_s * 1e3,
+            "decode_tflops": N * flops_fwd(2 * M, W, H, C) / dec_s / 1e12,
+            "l1_slots_per_s": 4096 * L1 / l1_s, "l1_decode_ms": l1_s * 1e3,
+            "rms_err": rep["rms"], "max_abs_err": rep["max_abs"],
+            "l1": {"n_slots": r1["n_slots"], "fp": r1["fp"], "fn": r1["fn"], "mismatch": r1["mismatch"]}}
 
 
 def cpu_baseline(grid):

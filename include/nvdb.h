@@ -264,6 +264,17 @@ typedef struct {
 } nvdb_error_report;
 nvdb_status nvdb_errors(const nvdb_tree* tree, const float* values_dev, const uint64_t* pred_mask_dev,
                         nvdb_error_report* out, void* stream);
+/* Level-1 classifier report (Sec. 3.3.1, Sec. 4) over the 4096 leaf slots of
+ * every level-1 node: classes_dev is uint8[n_l1][4096] as written by
+ * nvdb_decode_l1; the true class of a slot is 0 when it has a child leaf, else
+ * 1 when it is an active tile, else 2.  fp counts slots predicted as child
+ * leaves that are not, fn child leaves predicted as anything else, mismatch
+ * every slot whose class differs.  Synchronises `stream`. */
+typedef struct {
+  int64_t n_slots;
+  int64_t fp, fn, mismatch;
+} nvdb_l1_report;
+nvdb_status nvdb_errors_l1(const nvdb_tree* tree, const uint8_t* classes_dev, nvdb_l1_report* out, void* stream);
 
 /* ------------------------------------------------- device-pointer calls */
 /* Used by the autograd binding; no allocation beyond the model's workspace,

@@ -171,6 +171,18 @@ def l1_classes(logits):
     return np.argmax(np.asarray(logits), axis=1)
 
 
+def errors_l1(tr, classes):
+    """Level-1 classifier report over every leaf slot of the level-1 nodes:
+    false positives (predicted child leaf, none there), false negatives (child
+    leaf predicted as a tile) and class mismatches."""
+    n = 4096 * len(tr["l1_origin"])
+    _, truth = net_inputs(tr, "l1", np.arange(n), (0, 0, 0), 1, T.SDF, 1.0)
+    truth = truth.astype(np.int64)
+    c = np.asarray(classes, np.int64).reshape(-1)
+    return dict(n_slots=n, fp=int(np.sum((c == 0) & (truth != 0))), fn=int(np.sum((c != 0) & (truth == 0))),
+                mismatch=int(np.sum(c != truth)))
+
+
 def errors(tr, vhat, kind, pred_mask=None):
     """Error report: max |v^ - v| and RMS over the true active voxels (value
     units), IoU of the interior {v <= 0} over the active set for level sets,

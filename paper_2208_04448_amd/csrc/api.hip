@@ -862,6 +862,13 @@ nvdb_status nvdb_errors(const nvdb_tree* tree, const float* values_dev, const ui
   });
 }
 
+nvdb_status nvdb_errors_l1(const nvdb_tree* tree, const uint8_t* classes_dev, nvdb_l1_report* out, void* stream) {
+  return guarded([&] {
+    NVDB_REQUIRE(tree && out && (classes_dev || tree->n_l1 == 0), NVDB_E_INVALID, "null argument");
+    error_report_l1(*tree, classes_dev, out, (hipStream_t)stream);
+  });
+}
+
 // ------------------------------------------------------------------ device-pointer calls
 nvdb_status nvdb_forward_dev(const nvdb_model* m, int32_t net, const float* x_dev, int64_t n, float* y_dev,
                              void* stream) {

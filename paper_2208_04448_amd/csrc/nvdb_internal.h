@@ -247,5 +247,6 @@ Tree* build_tree_dense(const float* grid, const int32_t dims[3], const int32_t o
                        hipStream_t st);
 void error_report(const Tree& t, const float* values, const uint64_t* pred_mask, nvdb_error_report* rep,
                   hipStream_t st);
+void error_report_l1(const Tree& t, const uint8_t* classes, nvdb_l1_report* rep, hipStream_t st);
 
 }  // namespace nvdb

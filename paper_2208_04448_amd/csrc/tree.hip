@@ -456,4 +456,57 @@ void error_report(const Tree& t, const float* values, const uint64_t* pred_mask,
   rep->fn = (int64_t)fn;
 }
 
+// Level-1 classifier against the truth: class 0 (child leaf) iff the child bit
+// is set, else 1 (active tile) iff the tile-active bit is set, else 2.
+struct ErrL1Partial {
+  uint64_t fp, fn, mismatch;
+};
+__global__ void __launch_bounds__(256) k_err_l1(const uint64_t* child, const uint64_t* active, const uint8_t* cls,
+                                                int64_t n_slots, ErrL1Partial* out) {
+  __shared__ uint64_t s_fp[256], s_fn[256], s_mm[256];
+  uint64_t fp = 0, fn = 0, mm = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n_slots; i += (int64_t)gridDim.x * 256) {
+    const bool c = (child[i >> 6] >> (i & 63)) & 1ull;
+    const bool a = (active[i >> 6] >> (i & 63)) & 1ull;
+    const int t = c ? 0 : (a ? 1 : 2);
+    const int p = cls[i];
+    fp += (p == 0 && t != 0);
+    fn += (p != 0 && t == 0);
+    mm += (p != t);
+  }
+  s_fp[threadIdx.x] = fp;
+  s_fn[threadIdx.x] = fn;
+  s_mm[threadIdx.x] = mm;
+  __syncthreads();
+  for (int off = 128; off >= 1; off >>= 1) {
+    if (threadIdx.x < off) {
+      s_fp[threadIdx.x] += s_fp[threadIdx.x + off];
+      s_fn[threadIdx.x] += s_fn[threadIdx.x + off];
+      s_mm[threadIdx.x] += s_mm[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = ErrL1Partial{s_fp[0], s_fn[0], s_mm[0]};
+}
+
+void error_report_l1(const Tree& t, const uint8_t* classes, nvdb_l1_report* rep, hipStream_t st) {
+  const int nblk = 256;
+  rep->n_slots = 4096 * t.n_l1;
+  rep->fp = rep->fn = rep->mismatch = 0;
+  if (t.n_l1 == 0) return;
+  DevBuf<ErrL1Partial> part;
+  part.alloc(nblk);
+  hipLaunchKernelGGL(k_err_l1, dim3(nblk), dim3(256), 0, st, t.l1_child.p, t.l1_active.p, classes, 4096 * t.n_l1,
+                     part.p);
+  NVDB_HIP(hipGetLastError());
+  std::vector<ErrL1Partial> h(nblk);
+  NVDB_HIP(hipMemcpyAsync(h.data(), part.p, nblk * sizeof(ErrL1Partial), hipMemcpyDeviceToHost, st));
+  NVDB_HIP(hipStreamSynchronize(st));
+  for (const auto& e : h) {
+    rep->fp += (int64_t)e.fp;
+    rep->fn += (int64_t)e.fn;
+    rep->mismatch += (int64_t)e.mismatch;
+  }
+}
+
 }  // namespace nvdb

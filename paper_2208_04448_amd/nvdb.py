@@ -57,6 +57,10 @@ class FrameReport(C.Structure):
     _fields_ = [("steps_run", C.c_int32 * 3), ("final_loss", C.c_float * 3)]
 
 
+class L1Report(C.Structure):
+    _fields_ = [("n_slots", C.c_int64), ("fp", C.c_int64), ("fn", C.c_int64), ("mismatch", C.c_int64)]
+
+
 class TuneReport(C.Structure):
     _fields_ = [("chosen_g", C.c_int32), ("n_candidates", C.c_int32), ("g", C.c_int32 * 16),
                 ("ms_per_step", C.c_float * 16)]
@@ -92,6 +96,7 @@ _SIGS = {
     "nvdb_decode": (C.c_int32, [_P, _P, _P, _P, _P]),
     "nvdb_decode_l1": (C.c_int32, [_P, _P, _P, _P]),
     "nvdb_errors": (C.c_int32, [_P, _P, _P, C.POINTER(ErrorReport), _P]),
+    "nvdb_errors_l1": (C.c_int32, [_P, _P, C.POINTER(L1Report), _P]),
     "nvdb_forward_dev": (C.c_int32, [_P, C.c_int32, _P, C.c_int64, _P, _P]),
     "nvdb_backward_dev": (C.c_int32, [_P, C.c_int32, _P, _P, C.c_int64, _P, _P]),
     "nvdb_sample_indices_dev": (C.c_int32, [C.c_uint64, C.c_int32, C.c_int64, C.c_int64, C.c_int64, _P, _P]),
@@ -309,6 +314,12 @@ def errors(tree, values, pred_mask=None):
     r = ErrorReport()
     _check(_lib.nvdb_errors(tree.h, _ptr(values), _ptr(pred_mask), C.byref(r), _stream()))
     return dict(n=r.n, max_abs=r.max_abs, rms=r.rms, iou=r.iou, fp=r.fp, fn=r.fn)
+
+
+def errors_l1(tree, classes):
+    r = L1Report()
+    _check(_lib.nvdb_errors_l1(tree.h, _ptr(classes), C.byref(r), _stream()))
+    return dict(n_slots=r.n_slots, fp=r.fp, fn=r.fn, mismatch=r.mismatch)
 
 
 def sample_indices(seed, stream_id, step, n_pop, batch):

@@ -305,6 +305,9 @@ def test_l1_classifier_fit_and_decode(gpu_lib):
         margin = srt[:, -1] - srt[:, -2]
         ok = (cls == oc) | (margin <= (1e-5 if p == gpu_lib.FP32 else 3e-2))
         assert ok.all()
+        # level-1 error report of the library's own classes against the oracle's count
+        rep = gpu_lib.errors_l1(tr, m.decode_l1(tr))
+        assert rep == F.errors_l1(ot, cls)
 
 
 # --------------------------------------------------------------------------- full size (512^3)

@@ -160,3 +160,21 @@ def test_sequence_warm_start_needs_fewer_steps():
     assert runs[0] == 90
     assert all(r < 30 for r in runs[1:]), runs
     assert all(l[-1] < L[0][-1] for l in L[1:])
+
+
+def test_errors_l1_counts(sphere):
+    """Level-1 report: the truth has exactly one child-leaf slot per leaf; a
+    perfect prediction has no errors; planted mistakes are counted exactly."""
+    tr = sphere
+    n = 4096 * len(tr["l1_origin"])
+    _, truth = F.net_inputs(tr, "l1", np.arange(n), (0, 0, 0), 64, T.SDF, 3.0)
+    assert int(np.sum(truth == 0)) == len(tr["leaf_origin"])
+    rep = F.errors_l1(tr, truth)
+    assert rep == dict(n_slots=n, fp=0, fn=0, mismatch=0)
+    c = truth.copy()
+    child = np.nonzero(truth == 0)[0]
+    other = np.nonzero(truth == 2)[0]
+    c[child[:3]] = 2          # 3 false negatives
+    c[other[:5]] = 0          # 5 false positives
+    c[other[5:7]] = 1         # 2 plain mismatches
+    assert F.errors_l1(tr, c) == dict(n_slots=n, fp=5, fn=3, mismatch=10)
