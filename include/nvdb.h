@@ -250,6 +250,18 @@ nvdb_status nvdb_decode(const nvdb_model* model, const nvdb_tree* tree, float* v
  * of the three logits (0 child, 1 active tile, 2 inactive tile), ties to the
  * lowest index.  Asynchronous. */
 nvdb_status nvdb_decode_l1(const nvdb_model* model, const nvdb_tree* tree, uint8_t* classes_dev, void* stream);
+/* The same two decodes in the FP8 form: every hidden layer multiplies e4m3
+ * weights (one scale per layer, 448 / max|W|) by e4m3 inputs (one scale per
+ * sample, 448 / max |h|) on the FP8 matrix cores with FP32 accumulation, then
+ * divides by both scales, adds the bias and applies ReLU; the head runs in
+ * FP32.  Conversions round to nearest even after clamping to +-448.  The e4m3
+ * weights are rebuilt from the FP32 master parameters on every call (the
+ * paper stores 16-bit networks, Sec. 4, and leaves lower-precision inference to
+ * future work, Sec. 7; this form is that direction).  Asynchronous;
+ * E_UNSUPPORTED when the network shape has no FP8 kernel. */
+nvdb_status nvdb_decode_fp8(const nvdb_model* model, const nvdb_tree* tree, float* values_dev, uint64_t* pred_mask_dev,
+                            void* stream);
+nvdb_status nvdb_decode_l1_fp8(const nvdb_model* model, const nvdb_tree* tree, uint8_t* classes_dev, void* stream);
 
 /* Error report (Sec. 4): max |v^ - v| and RMS over the true active voxels in
  * value units; IoU of the interiors {v <= 0} over the active set (level sets);

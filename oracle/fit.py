@@ -15,7 +15,7 @@ error and the classifier false positives / negatives.
 """
 import numpy as np
 
-from . import mlp, sampler, tree as T
+from . import fp8 as fp8_form, mlp, sampler, tree as T
 
 NET_STREAM = {"regressor": sampler.STREAM_REGRESSOR, "l0": sampler.STREAM_L0, "l1": sampler.STREAM_L1}
 NET_LOSS = {"regressor": "mse", "l0": "bce", "l1": "ce"}
@@ -126,35 +126,37 @@ def train_sequence(theta0, shapes, B, frames, net, lo, D, kind, band, cold, warm
     return thetas, runs, losses
 
 
-def _batched_predict(theta, shapes, B, x, chunk=1 << 15):
+def _batched_predict(theta, shapes, B, x, chunk=1 << 15, fp8=False):
     params = mlp.unflatten(theta, shapes)
     out = []
     for i in range(0, len(x), chunk):
-        y, _ = mlp.forward(params, mlp.encode(x[i:i + chunk], B))
+        z0 = mlp.encode(x[i:i + chunk], B)
+        y = fp8_form.forward_fp8(params, z0) if fp8 else mlp.forward(params, z0)[0]
         out.append(y)
     return np.concatenate(out) if out else np.zeros((0, shapes[-1][0]))
 
 
-def decode_values(theta, shapes, B, tr, lo, D, kind, band, idx=None):
-    """Regressor decode at the true active voxels (all, or the subset idx)."""
+def decode_values(theta, shapes, B, tr, lo, D, kind, band, idx=None, fp8=False):
+    """Regressor decode at the true active voxels (all, or the subset idx); fp8
+    selects the FP8 form of the forward pass."""
     idx = np.arange(len(tr["values"])) if idx is None else np.asarray(idx)
     x = mlp.normalize_voxel(tr["ijk"][idx], lo, D)
-    y = _batched_predict(theta, shapes, B, x)[:, 0]
+    y = _batched_predict(theta, shapes, B, x, fp8=fp8)[:, 0]
     return y * band if kind == T.SDF else y
 
 
-def decode_l0(theta, shapes, B, tr, lo, D, slots=None):
+def decode_l0(theta, shapes, B, tr, lo, D, slots=None, fp8=False):
     """Level-0 classifier logits at leaf slots (all 512 L, or the subset `slots`)."""
     slots = np.arange(population(tr, "l0")) if slots is None else np.asarray(slots)
     x, _ = net_inputs(tr, "l0", slots, lo, D, T.SDF, 1.0)
-    return _batched_predict(theta, shapes, B, x)[:, 0]
+    return _batched_predict(theta, shapes, B, x, fp8=fp8)[:, 0]
 
 
-def decode_l1(theta, shapes, B, tr, lo, D, slots=None):
+def decode_l1(theta, shapes, B, tr, lo, D, slots=None, fp8=False):
     """Level-1 classifier logits at leaf slots of the L1 nodes."""
     slots = np.arange(population(tr, "l1")) if slots is None else np.asarray(slots)
     x, _ = net_inputs(tr, "l1", slots, lo, D, T.SDF, 1.0)
-    return _batched_predict(theta, shapes, B, x)
+    return _batched_predict(theta, shapes, B, x, fp8=fp8)
 
 
 def mask_from_logits(logits, n_leaves):

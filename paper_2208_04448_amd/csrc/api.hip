@@ -24,6 +24,9 @@ struct Net {
   DevBuf<int32_t> ran;  // per step of a sequence fit: 1 when the step ran
   DevBuf<floatx4> xt;  // gathered samples of the current step
   DevBuf<char> wrow, wcol, w1frag;
+  // FP8 form: e4m3 fragments and per-layer scales, rebuilt from theta by every FP8 decode
+  mutable DevBuf<char> w8;
+  mutable DevBuf<float> w8inv;
   DevBuf<float> bias, whead, bhead, benc;
   int64_t step = 0;
   bool params_set = false, enc_set = false;
@@ -797,61 +800,82 @@ nvdb_status nvdb_fit_sequence(nvdb_model* m, const nvdb_tree* const* frames, int
 // ------------------------------------------------------------------ decode
 static int infer_grid(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 512)); }
 
+}  // extern "C"
+
+// Launches the forward pass of network N over one population of `tree`; the FP8
+// form first requantises the weights from the master copy.
+static void run_infer(const nvdb_model* m, const Net& N, const Tree* tree, int src, int64_t n, InferLaunch I, bool fp8,
+                      hipStream_t st) {
+  I.net = net_view(N);
+  base_spec(m, &I.spec);
+  I.spec.src = src;
+  I.spec.direct = 1;
+  I.spec.n = n;
+  I.tree = tree_view(tree);
+  if (fp8) {
+    NVDB_REQUIRE(N.ks.infer8 != nullptr, NVDB_E_UNSUPPORTED, "no FP8 kernel for this network shape");
+    N.w8.ensure((size_t)fp8_weight_bytes(N.s));
+    N.w8inv.ensure(2 * (size_t)N.s.H);
+    launch_quant_fp8(N.s, N.theta.p, N.w8.p, N.w8inv.p, st);
+    I.w8 = N.w8.p;
+    I.w8inv = N.w8inv.p;
+    launch_infer8(N.ks, I, infer_grid(n), st);
+  } else {
+    launch_infer(N.ks, I, infer_grid(n), st);
+  }
+}
+
+static void decode_impl(const nvdb_model* m, const nvdb_tree* tree, float* values_dev, uint64_t* pred_mask_dev,
+                        bool fp8, hipStream_t st) {
+  NVDB_REQUIRE(m && tree, NVDB_E_INVALID, "null argument");
+  if (values_dev && tree->n_vox > 0) {
+    const Net& N = net_of(m, NVDB_NET_REGRESSOR);
+    NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "regressor parameters or encoding not set");
+    InferLaunch I{};
+    I.out_kind = OUT_VALUES;
+    I.out_scale = m->d.value_scale;
+    I.y = values_dev;
+    run_infer(m, N, tree, SRC_VOXELS, tree->n_vox, I, fp8, st);
+  }
+  if (pred_mask_dev && tree->n_leaf > 0) {
+    const Net& N = net_of(m, NVDB_NET_L0);
+    NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "classifier parameters or encoding not set");
+    InferLaunch I{};
+    I.out_kind = OUT_MASK;
+    I.mask = pred_mask_dev;
+    run_infer(m, N, tree, SRC_LEAF_SLOTS, 512 * tree->n_leaf, I, fp8, st);
+  }
+}
+
+static void decode_l1_impl(const nvdb_model* m, const nvdb_tree* tree, uint8_t* classes_dev, bool fp8, hipStream_t st) {
+  NVDB_REQUIRE(m && tree && classes_dev, NVDB_E_INVALID, "null argument");
+  const Net& N = net_of(m, NVDB_NET_L1);
+  NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "level-1 classifier parameters or encoding not set");
+  if (tree->n_l1 == 0) return;
+  InferLaunch I{};
+  I.out_kind = OUT_CLASS;
+  I.cls = classes_dev;
+  run_infer(m, N, tree, SRC_L1_SLOTS, 4096 * tree->n_l1, I, fp8, st);
+}
+
+extern "C" {
+
 nvdb_status nvdb_decode(const nvdb_model* m, const nvdb_tree* tree, float* values_dev, uint64_t* pred_mask_dev,
                         void* stream) {
-  return guarded([&] {
-    NVDB_REQUIRE(m && tree, NVDB_E_INVALID, "null argument");
-    hipStream_t st = (hipStream_t)stream;
-    const TreeView tv = tree_view(tree);
-    if (values_dev && tree->n_vox > 0) {
-      const Net& N = net_of(m, NVDB_NET_REGRESSOR);
-      NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "regressor parameters or encoding not set");
-      InferLaunch I{};
-      I.net = net_view(N);
-      base_spec(m, &I.spec);
-      I.spec.src = SRC_VOXELS;
-      I.spec.direct = 1;
-      I.spec.n = tree->n_vox;
-      I.tree = tv;
-      I.out_kind = OUT_VALUES;
-      I.out_scale = m->d.value_scale;
-      I.y = values_dev;
-      launch_infer(N.ks, I, infer_grid(I.spec.n), st);
-    }
-    if (pred_mask_dev && tree->n_leaf > 0) {
-      const Net& N = net_of(m, NVDB_NET_L0);
-      NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "classifier parameters or encoding not set");
-      InferLaunch I{};
-      I.net = net_view(N);
-      base_spec(m, &I.spec);
-      I.spec.src = SRC_LEAF_SLOTS;
-      I.spec.direct = 1;
-      I.spec.n = 512 * tree->n_leaf;
-      I.tree = tv;
-      I.out_kind = OUT_MASK;
-      I.mask = pred_mask_dev;
-      launch_infer(N.ks, I, infer_grid(I.spec.n), st);
-    }
-  });
+  return guarded([&] { decode_impl(m, tree, values_dev, pred_mask_dev, false, (hipStream_t)stream); });
+}
+
+nvdb_status nvdb_decode_fp8(const nvdb_model* m, const nvdb_tree* tree, float* values_dev, uint64_t* pred_mask_dev,
+                            void* stream) {
+  return guarded([&] { decode_impl(m, tree, values_dev, pred_mask_dev, true, (hipStream_t)stream); });
 }
 
 nvdb_status nvdb_decode_l1(const nvdb_model* m, const nvdb_tree* tree, uint8_t* classes_dev, void* stream) {
-  return guarded([&] {
-    NVDB_REQUIRE(m && tree && classes_dev, NVDB_E_INVALID, "null argument");
-    const Net& N = net_of(m, NVDB_NET_L1);
-    NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "level-1 classifier parameters or encoding not set");
-    if (tree->n_l1 == 0) return;
-    InferLaunch I{};
-    I.net = net_view(N);
-    base_spec(m, &I.spec);
-    I.spec.src = SRC_L1_SLOTS;
-    I.spec.direct = 1;
-    I.spec.n = 4096 * tree->n_l1;
-    I.tree = tree_view(tree);
-    I.out_kind = OUT_CLASS;
-    I.cls = classes_dev;
-    launch_infer(N.ks, I, infer_grid(I.spec.n), (hipStream_t)stream);
-  });
+  return guarded([&] { decode_l1_impl(m, tree, classes_dev, false, (hipStream_t)stream); });
+}
+
+nvdb_status nvdb_decode_l1_fp8(const nvdb_model* m, const nvdb_tree* tree, uint8_t* classes_dev, void* stream) {
+  return guarded([&] { decode_l1_impl(m, tree, classes_dev, true, (hipStream_t)stream); });
 }
 
 nvdb_status nvdb_errors(const nvdb_tree* tree, const float* values_dev, const uint64_t* pred_mask_dev,

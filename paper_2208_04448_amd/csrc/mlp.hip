@@ -59,6 +59,7 @@ __device__ __forceinline__ int opaque_zero() {
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef int intx8 __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
   bf16x2 v = {(__bf16)a, (__bf16)b};
   return __builtin_bit_cast(uint32_t, v);
@@ -1085,6 +1086,273 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
   }
 }
 
+// ============================================================== FP8 (e4m3) forward
+// The FP8 form of the forward pass (decoding): every hidden layer multiplies
+// e4m3 weights, quantised per layer with s_w = 448 / max|W|, by e4m3 inputs,
+// quantised per sample with s_a = 448 / max_f |h_f|, on the gfx950
+// 32x32x64 FP8 MFMA with FP32 accumulation; z = acc / (s_w s_a) + b, ReLU; the
+// head runs on the FP32 activations.  Values are clamped to +-448 before the
+// conversion, which rounds to nearest even.
+//
+// Operand layout of the 32x32x64 FP8 MFMA: lane (i, g) of A holds row i, bytes
+// s = 0..31 of k-group g; lane (j, g) of B holds column j with the same k
+// assignment, so a k index is any (g, s) pair used consistently by A and B.
+// The B operand of k-step kk is the pair of S-layout blocks 2kk, 2kk+1 of the
+// lane's sample, 16 bytes each, so byte s of lane half g carries feature
+//   f(kk, g, s) = 32 (2kk + s/16) + 8 ((s mod 16) / 4) + 4 g + s mod 4,
+// and the weight fragments are stored with the same assignment:
+//   [layer][ob][kk][plane p][lane][16 bytes], bytes 16p .. 16p+15 of the lane.
+__device__ __forceinline__ int fp8_feature(int kk, int g, int s) {
+  return 32 * (2 * kk + (s >> 4)) + 8 * ((s & 15) >> 2) + 4 * g + (s & 3);
+}
+__device__ __forceinline__ uint32_t pack4_fp8(float a, float b, float c, float d) {
+  const float m = 448.f;
+  a = fminf(fmaxf(a, -m), m);
+  b = fminf(fmaxf(b, -m), m);
+  c = fminf(fmaxf(c, -m), m);
+  d = fminf(fmaxf(d, -m), m);
+  uint32_t w = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(c, d, (int)w, true);
+}
+
+// Per-layer scales: one work-group per hidden layer.
+__global__ void __launch_bounds__(256) k_fp8_scales(NetShape s, const float* theta, float* w8inv, float* w8scale) {
+  const int l = blockIdx.x;
+  const int64_t n = (int64_t)s.W * s.win(l);
+  const float* w = theta + s.woff(l);
+  float mx = 0.f;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) mx = fmaxf(mx, fabsf(w[i]));
+  __shared__ float red[256];
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int off = 128; off >= 1; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const float sc = red[0] > 0.f ? 448.f / red[0] : 1.f;
+    w8scale[l] = sc;
+    w8inv[l] = 1.f / sc;
+  }
+}
+// One thread per 4 fragment bytes.
+__global__ void __launch_bounds__(256) k_fp8_pack(NetShape s, const float* theta, const float* w8scale, char* w8) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // dword index
+  const int64_t total = fp8_weight_bytes(s) / 4;
+  if (q >= total) return;
+  // locate the layer
+  int64_t off = q * 4;
+  int l = 0;
+  int64_t lbytes = (int64_t)s.W * s.KP;
+  while (off >= lbytes) {
+    off -= lbytes;
+    ++l;
+    lbytes = (int64_t)s.W * s.W;
+  }
+  const int winp = (l == 0) ? s.KP : s.W, win = s.win(l), ks = winp / 64;
+  const int frag = (int)(off / 2048), rem = (int)(off % 2048);
+  const int ob = frag / ks, kk = frag % ks;
+  const int p = rem / 1024, lane = (rem % 1024) / 16, s0 = 16 * p + (rem % 16);
+  const int i = 32 * ob + (lane & 31), g = lane >> 5;
+  const float sc = w8scale[l];
+  float v[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int f = fp8_feature(kk, g, s0 + e);
+    v[e] = f < win ? theta[s.woff(l) + (int64_t)i * win + f] * sc : 0.f;
+  }
+  ((uint32_t*)w8)[q] = pack4_fp8(v[0], v[1], v[2], v[3]);
+}
+
+template <int W, int H, int KP, int C>
+struct Infer8Cfg {
+  static constexpr int NT = 2;
+  static constexpr int WL_BYTES = W * KP + (H - 1) * W * W;
+  static constexpr int SMALL_FLOATS = H * W + C * W + 4 + 4 * (KP / 2) + 4;
+  static constexpr int LDS_BYTES = WL_BYTES + SMALL_FLOATS * 4;
+};
+
+// gamma(x) in S layout, FP32 values (any m <= 16 NIB).
+template <int NIB>
+__device__ __forceinline__ void encode_f32(const Smp& s, const float* benc, int m, float (&X)[NIB][16]) {
+  const int h = lane_id() >> 5;
+#pragma unroll
+  for (int t = 0; t < NIB; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int f = sfeat(t, r, h);
+      int fi = f < m ? f : f - m;
+      fi = fi < m ? fi : 0;
+      const floatx4 b = *(const floatx4*)(benc + 4 * fi);
+      const float val = __builtin_amdgcn_sinf(phase<NVDB_BF16>(b, s, f < m ? 0.25f : 0.f));
+      X[t][r] = (f < 2 * m) ? val : 0.f;
+    }
+}
+
+template <int C, int NT>
+__device__ __forceinline__ void write_outputs(const InferLaunch& I, const float (&y)[NT][C], int64_t base, int fl,
+                                              int h) {
+  const SampleSpec& sp = I.spec;
+  if (I.out_kind == OUT_MASK) {
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      const uint32_t bits = (uint32_t)(__ballot(y[u][0] > 0.f) & 0xffffffffull);
+      if (lane_id() == 0 && base + 32 * u < sp.n) ((uint32_t*)I.mask)[(base + 32 * u) >> 5] = bits;
+    }
+    return;
+  }
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    const int64_t j = base + 32 * u + fl;
+    if (h == 0 && j < sp.n) {
+      if (I.out_kind == OUT_VALUES) {
+        I.y[j] = y[u][0] * I.out_scale;
+      } else if (I.out_kind == OUT_CLASS) {
+        int best = 0;
+        float bv = y[u][0];
+#pragma unroll
+        for (int c = 1; c < C; ++c)
+          if (y[u][c] > bv) {
+            bv = y[u][c];
+            best = c;
+          }
+        I.cls[j] = (uint8_t)best;
+      } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) I.y[(size_t)j * C + c] = y[u][c];
+      }
+    }
+  }
+}
+
+template <int W, int H, int KP, int C>
+__global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) k_infer_fp8(InferLaunch I) {
+  using CF = Infer8Cfg<W, H, KP, C>;
+  constexpr int NB = W / 32, NIB0 = KP / 32, NT = CF::NT;
+  constexpr int NA = NB > NIB0 ? NB : NIB0;
+  __shared__ __attribute__((aligned(16))) char smem[CF::LDS_BYTES];
+  const NetView& nv = I.net;
+  const SampleSpec& sp = I.spec;
+  const int wave = wave_id();
+
+  char* wl0 = smem;
+  float* sm_bias0 = (float*)(smem + CF::WL_BYTES);
+  float* sm_whead0 = sm_bias0 + H * W;
+  float* sm_bhead0 = sm_whead0 + C * W;
+  float* sm_benc0 = sm_bhead0 + 4;
+  float* sm_winv0 = sm_benc0 + 4 * (KP / 2);
+  {
+    const u32x4* src = (const u32x4*)I.w8;
+    u32x4* dst = (u32x4*)wl0;
+    for (int i = threadIdx.x; i < CF::WL_BYTES / 16; i += blockDim.x) dst[i] = src[i];
+  }
+  for (int i = threadIdx.x; i < H * W; i += blockDim.x) sm_bias0[i] = nv.bias[i];
+  for (int i = threadIdx.x; i < C * W; i += blockDim.x) sm_whead0[i] = nv.whead[i];
+  if (threadIdx.x < C) sm_bhead0[threadIdx.x] = nv.bhead[threadIdx.x];
+  for (int i = threadIdx.x; i < 4 * (KP / 2); i += blockDim.x) sm_benc0[i] = nv.benc[i];
+  if (threadIdx.x < H) sm_winv0[threadIdx.x] = I.w8inv[threadIdx.x];
+  __syncthreads();
+
+  const int64_t per_wave = 32 * NT;
+  const int64_t stride = (int64_t)gridDim.x * 4 * per_wave;
+  for (int64_t base = ((int64_t)blockIdx.x * 4 + wave) * per_wave; base < sp.n; base += stride) {
+    const int lane = lane_id();
+    const int h = lane >> 5, fl = lane & 31;
+    const int z = opaque_zero();
+    const float* sm_bias = sm_bias0 + z;
+    const float* sm_whead = sm_whead0 + z;
+    const float* sm_bhead = sm_bhead0 + z;
+    const float* sm_benc = sm_benc0 + z;
+    const float* sm_winv = sm_winv0 + z;
+    const char* wl = wl0 + z;
+    const LaneK K = lane_consts();
+    float Z[NT][NA][16];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      const Smp smp = fetch_sample(sp, I.tree, base + 32 * u + fl);
+      float X0[NIB0][16];
+      encode_f32<NIB0>(smp, sm_benc, nv.nfreq, X0);
+#pragma unroll
+      for (int t = 0; t < NIB0; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) Z[u][t][r] = X0[t][r];
+    }
+    static_for<0, H>([&](auto lc) {
+      constexpr int l = decltype(lc)::value;
+      constexpr int NIBl = (l == 0) ? NIB0 : NB;
+      constexpr int KSl = NIBl / 2;
+      constexpr int LOFF = (l == 0) ? 0 : W * KP + (l - 1) * W * W;
+      // per-sample quantisation of the layer input
+      uint32_t Bq[NT][NIBl][4];
+      float inv_sa[NT];
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        float mx = 0.f;
+#pragma unroll
+        for (int t = 0; t < NIBl; ++t)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) mx = fmaxf(mx, fabsf(Z[u][t][r]));
+        mx = fmaxf(mx, shfl_xor32(mx));
+        const float sa = mx > 0.f ? 448.f / mx : 1.f;
+        inv_sa[u] = 1.f / sa;
+#pragma unroll
+        for (int t = 0; t < NIBl; ++t)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            Bq[u][t][q] = pack4_fp8(Z[u][t][4 * q] * sa, Z[u][t][4 * q + 1] * sa, Z[u][t][4 * q + 2] * sa,
+                                    Z[u][t][4 * q + 3] * sa);
+      }
+      const float winv = sm_winv[l];
+#pragma unroll
+      for (int ob = 0; ob < NB; ++ob) {
+        floatx16 acc[NT];
+#pragma unroll
+        for (int u = 0; u < NT; ++u) acc[u] = floatx16{};
+#pragma unroll
+        for (int kk = 0; kk < KSl; ++kk) {
+          const char* fr = wl + LOFF + (ob * KSl + kk) * 2048 + lane * 16;
+          const u32x4 a0 = *(const u32x4*)fr;
+          const u32x4 a1 = *(const u32x4*)(fr + 1024);
+          const intx8 A = {(int)a0[0], (int)a0[1], (int)a0[2], (int)a0[3],
+                           (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
+#pragma unroll
+          for (int u = 0; u < NT; ++u) {
+            const intx8 Bv = {(int)Bq[u][2 * kk][0], (int)Bq[u][2 * kk][1], (int)Bq[u][2 * kk][2], (int)Bq[u][2 * kk][3],
+                              (int)Bq[u][2 * kk + 1][0], (int)Bq[u][2 * kk + 1][1], (int)Bq[u][2 * kk + 1][2],
+                              (int)Bq[u][2 * kk + 1][3]};
+            acc[u] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A, Bv, acc[u], 0, 0, 0, 0, 0, 0);
+          }
+        }
+        const floatx16 b0 = bias_acc(sm_bias + l * W, K, ob);
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          const float d = winv * inv_sa[u];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) Z[u][ob][r] = fmaxf(fmaf(acc[u][r], d, b0[r]), 0.f);
+        }
+      }
+    });
+    // head on the FP32 activations
+    float y[NT][C];
+#pragma unroll
+    for (int u = 0; u < NT; ++u)
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        float acc = 0.f;
+#pragma unroll
+        for (int ob = 0; ob < NB; ++ob)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const floatx4 w4 = *(const floatx4*)(sm_whead + c * W + 32 * ob + 8 * q + 4 * h);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc = fmaf(w4[e], Z[u][ob][4 * q + e], acc);
+          }
+        y[u][c] = acc + shfl_xor32(acc) + sm_bhead[c];
+      }
+    write_outputs<C, NT>(I, y, base, fl, h);
+  }
+}
+
 // ============================================================== reduce + Adam
 
 __device__ __forceinline__ void write_shadow(const AdamNet& A, int64_t p, float th) {
@@ -1208,8 +1476,10 @@ __global__ void k_sample(uint64_t sseed, uint32_t npop, int64_t n, uint32_t* out
 
 template <int PREC, int W, int H, int KP, int C>
 KernelSet make_set() {
+  static_assert(KP % 64 == 0, "the FP8 form takes k-steps of 64 features");
   return KernelSet{k_train<PREC, W, H, KP, C>, k_infer<PREC, W, H, KP, C>,
-                   TrainCfg<PREC, W, H, KP, C>::LDS_BYTES, InferCfg<PREC, W, H, KP, C>::LDS_BYTES};
+                   TrainCfg<PREC, W, H, KP, C>::LDS_BYTES, InferCfg<PREC, W, H, KP, C>::LDS_BYTES,
+                   k_infer_fp8<W, H, KP, C>};
 }
 
 // Shapes with compiled kernels: (W, H, KP, C).
@@ -1249,6 +1519,18 @@ void launch_write_shadow(const AdamNet& A, hipStream_t st) {
 void launch_gather(const SampleSpec& sp, const TreeView& tv, floatx4* out, hipStream_t st) {
   if (sp.n <= 0) return;
   hipLaunchKernelGGL(k_gather, dim3((unsigned)((sp.n + 255) / 256)), dim3(256), 0, st, sp, tv, out);
+  NVDB_HIP(hipGetLastError());
+}
+void launch_quant_fp8(const NetShape& s, const float* theta, char* w8, float* w8inv, hipStream_t st) {
+  float* scale = w8inv + s.H;  // the caller's buffer holds 2 H floats: 1/s_w, then s_w
+  hipLaunchKernelGGL(k_fp8_scales, dim3(s.H), dim3(256), 0, st, s, theta, w8inv, scale);
+  NVDB_HIP(hipGetLastError());
+  const int64_t dw = fp8_weight_bytes(s) / 4;
+  hipLaunchKernelGGL(k_fp8_pack, dim3((unsigned)((dw + 255) / 256)), dim3(256), 0, st, s, theta, (const float*)scale, w8);
+  NVDB_HIP(hipGetLastError());
+}
+void launch_infer8(const KernelSet& ks, const InferLaunch& I, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(ks.infer8, dim3(grid), dim3(256), 0, st, I);
   NVDB_HIP(hipGetLastError());
 }
 void launch_fill(float* p, int64_t n, float v, hipStream_t st) {

@@ -199,6 +199,9 @@ struct InferLaunch {
   float* y;           // OUT_Y: [n][C]; OUT_VALUES: [n]
   uint64_t* mask;     // OUT_MASK: [n/64]
   uint8_t* cls;       // OUT_CLASS: [n]
+  // FP8 form only: e4m3 weight fragments of every hidden layer and 1/s_w per layer
+  const char* w8;
+  const float* w8inv;
 };
 struct AdamNet {
   NetShape s;
@@ -231,10 +234,15 @@ struct KernelSet {
   void (*train)(TrainLaunch);
   void (*infer)(InferLaunch);
   int train_lds, infer_lds;
+  void (*infer8)(InferLaunch);  // FP8 form of the forward pass
 };
+// Bytes of the e4m3 weight fragments of all hidden layers (the FP8 form).
+__host__ __device__ inline int64_t fp8_weight_bytes(const NetShape& s) { return (int64_t)s.W * s.KP + (int64_t)(s.H - 1) * s.W * s.W; }
 
 // mlp.hip
 bool find_kernels(int prec, int W, int H, int KP, int C, KernelSet* out);
+void launch_quant_fp8(const NetShape& s, const float* theta, char* w8, float* w8inv, hipStream_t st);
+void launch_infer8(const KernelSet& ks, const InferLaunch& I, int grid, hipStream_t st);
 void launch_train(const KernelSet& ks, const TrainLaunch& L, int n_nets, hipStream_t st);
 void launch_infer(const KernelSet& ks, const InferLaunch& I, int grid, hipStream_t st);
 void launch_reduce_adam(const AdamLaunch& A, int64_t max_p, int n_nets, hipStream_t st);

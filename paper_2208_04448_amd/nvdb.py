@@ -95,6 +95,8 @@ _SIGS = {
     "nvdb_model_set_train_groups": (C.c_int32, [_P, C.c_int32]),
     "nvdb_decode": (C.c_int32, [_P, _P, _P, _P, _P]),
     "nvdb_decode_l1": (C.c_int32, [_P, _P, _P, _P]),
+    "nvdb_decode_fp8": (C.c_int32, [_P, _P, _P, _P, _P]),
+    "nvdb_decode_l1_fp8": (C.c_int32, [_P, _P, _P, _P]),
     "nvdb_errors": (C.c_int32, [_P, _P, _P, C.POINTER(ErrorReport), _P]),
     "nvdb_errors_l1": (C.c_int32, [_P, _P, C.POINTER(L1Report), _P]),
     "nvdb_forward_dev": (C.c_int32, [_P, C.c_int32, _P, C.c_int64, _P, _P]),
@@ -275,19 +277,21 @@ class Model:
         out = [(list(r.steps_run), list(r.final_loss)) for r in reps]
         return out, losses, fp
 
-    def decode(self, tree, values=True, masks=True):
+    def decode(self, tree, values=True, masks=True, fp8=False):
         import torch
         i = tree.info()
         v = torch.empty(i.n_voxels, dtype=torch.float32, device="cuda") if values else None
         mk = torch.empty((i.n_leaves, 8), dtype=torch.int64, device="cuda") if masks else None
-        _check(_lib.nvdb_decode(self.h, tree.h, _ptr(v), _ptr(mk), _stream()))
+        f = _lib.nvdb_decode_fp8 if fp8 else _lib.nvdb_decode
+        _check(f(self.h, tree.h, _ptr(v), _ptr(mk), _stream()))
         return v, mk
 
-    def decode_l1(self, tree):
+    def decode_l1(self, tree, fp8=False):
         import torch
         i = tree.info()
         out = torch.empty((i.n_l1, 4096), dtype=torch.uint8, device="cuda")
-        _check(_lib.nvdb_decode_l1(self.h, tree.h, _ptr(out), _stream()))
+        f = _lib.nvdb_decode_l1_fp8 if fp8 else _lib.nvdb_decode_l1
+        _check(f(self.h, tree.h, _ptr(out), _stream()))
         return out
 
     def forward(self, net, x):

@@ -546,3 +546,46 @@ def test_autotune_leaves_state_and_fits_match(gpu_lib, sphere):
             res.setdefault(gg, []).append((L, m.get_params(0)))
         assert np.array_equal(res[gg][0][1], res[gg][1][1]) and np.array_equal(res[gg][0][0], res[gg][1][0])
         assert np.max(np.abs(res[gg][0][0] - lo) / lo) <= 1e-5
+
+
+# --------------------------------------------------------------------------- FP8 form of the decode
+@pytest.mark.parametrize("shape", [(64, 3, 18, 1, 0), (128, 4, 64, 1, 0), (128, 3, 64, 1, 1), (64, 4, 64, 3, 2)],
+                         ids=["64x3_pe", "128x4", "128x3_l0", "64x4_l1"])
+def test_fp8_decode_parity(gpu_lib, shape):
+    """FP8 decode against the FP64 oracle of the same FP8 form on the same weights
+    (fitted a few steps, so the activations are not those of the initialisation).
+    The weight codes are decided in float32 on both sides and agree; activation
+    codes can flip where the FP32 and FP64 activations straddle a rounding
+    boundary, one e4m3 step (2^-3 relative) of one input, which bounds the output
+    difference far below the tolerance 3e-2 (normalised units)."""
+    W, H, m, c, net = shape
+    v = workloads.sphere_sdf(n=96, center=(47.0, 50.0, 45.0), radius=30.0)
+    tr = gpu_lib.Tree(v.to(DEV), (0, 0, 0), T.SDF, 3.0)
+    ot = T.build(*T.active_set_dense(v.numpy(), (0, 0, 0), T.SDF, 3.0))
+    model, theta, B, shapes = model_for(gpu_lib, shape, gpu_lib.BF16, domain=128, seed=5)
+    model.fit(tr, steps=5, batch=2048, nets_mask=1 << net, seed=3, lr=3e-3)
+    th = model.get_params(net).astype(np.float64)
+    if net == 0:
+        vals, _ = model.decode(tr, values=True, masks=False, fp8=True)
+        got = vals.cpu().numpy() / 3.0
+        want = F.decode_values(th, shapes, B, ot, (0, 0, 0), 128, T.SDF, 3.0, fp8=True) / 3.0
+        exact = F.decode_values(th, shapes, B, ot, (0, 0, 0), 128, T.SDF, 3.0) / 3.0
+        d = np.abs(got - want)
+        assert d.max() <= 3e-2, d.max()
+        print("fp8 vs fp8 oracle: max %.3g median %.3g; fp8 oracle vs exact: max %.3g"
+              % (d.max(), np.median(d), np.abs(want - exact).max()))
+    elif net == 1:
+        _, mk = model.decode(tr, values=False, masks=True, fp8=True)
+        lg = F.decode_l0(th, shapes, B, ot, (0, 0, 0), 128, fp8=True)
+        mo = F.mask_from_logits(lg, len(ot["leaf_origin"]))
+        mg = mk.cpu().numpy().view(np.uint64)
+        diff = np.unpackbits((mg ^ mo).view(np.uint8), bitorder="little").astype(bool)
+        near = np.zeros_like(diff)
+        near[:lg.size] = np.abs(lg) <= 3e-2
+        assert not np.any(diff & ~near)
+    else:
+        cls = model.decode_l1(tr, fp8=True).cpu().numpy().reshape(-1)
+        lg = F.decode_l1(th, shapes, B, ot, (0, 0, 0), 128, fp8=True)
+        srt = np.sort(lg, axis=1)
+        ok = (cls == F.l1_classes(lg)) | (srt[:, -1] - srt[:, -2] <= 6e-2)
+        assert ok.all()
