@@ -176,6 +176,21 @@ def main():
         "autotune": {"work_groups_per_network": tuned_g, "ms_per_step": {str(g): t for g, t in tune_ms.items()}},
     }
     print("bf16 jobs: %s s" % ["%.3f" % t for t in times], file=sys.stderr, flush=True)
+    # FP8 form of the decode with the same (BF16-trained) weights
+    bf.decode(tree, fp8=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    v8, m8 = bf.decode(tree, fp8=True)
+    e1.record()
+    torch.cuda.synchronize()
+    d8 = e0.elapsed_time(e1) / 1e3
+    rep8 = nvdb.errors(tree, v8, m8)
+    out["fp8_decode"] = {"decoded_voxels_per_s": N / d8, "decode_ms": d8 * 1e3, "decode_tflops": dec_flops / d8 / 1e12,
+                         "max_abs_err_voxels": rep8["max_abs"], "rms_err_voxels": rep8["rms"], "iou": rep8["iou"],
+                         "l0_fp": rep8["fp"], "l0_fn": rep8["fn"],
+                         "note": "e4m3 weights (per layer) and activations (per sample), FP32 accumulate; "
+                                 "includes requantising the weights"}
 
     if not args.skip_fp32:
         print("fp32 form job (%d steps) ..." % args.fit_steps, file=sys.stderr, flush=True)
@@ -341,6 +356,17 @@ def cloud_leg(fit_steps, tuned_g):
     dec_s, l1_s = e0.elapsed_time(e1) / 1e3, e1.elapsed_time(e2) / 1e3
     rep = nvdb.errors(tree, values)
     r1 = nvdb.errors_l1(tree, classes)
+    mdl.decode(tree, values=True, masks=False, fp8=True)
+    torch.cuda.synchronize()
+    e0.record()
+    values8, _ = mdl.decode(tree, values=True, masks=False, fp8=True)
+    e1.record()
+    classes8 = mdl.decode_l1(tree, fp8=True)
+    e2.record()
+    torch.cuda.synchronize()
+    dec8_s, l18_s = e0.elapsed_time(e1) / 1e3, e1.elapsed_time(e2) / 1e3
+    rep8 = nvdb.errors(tree, values8)
+    r18 = nvdb.errors_l1(tree, classes8)
     N, L1 = int(info.n_voxels), int(info.n_l1)
     return {"workload": "fBm cloud 1024^3 (6 octaves, lacunarity 2, gain 0.5), active where density > 0.55; "
                         "voxel regressor 4x128 + level-1 classifier 4x64 (3 classes), FFM m=64 sigma=10, BF16; "
@@ -350,7 +376,12 @@ def cloud_leg(fit_steps, tuned_g):
             "decode_tflops": N * flops_fwd(2 * M, W, H, C) / dec_s / 1e12,
             "l1_slots_per_s": 4096 * L1 / l1_s, "l1_decode_ms": l1_s * 1e3,
             "rms_err": rep["rms"], "max_abs_err": rep["max_abs"],
-            "l1": {"n_slots": r1["n_slots"], "fp": r1["fp"], "fn": r1["fn"], "mismatch": r1["mismatch"]}}
+            "l1": {"n_slots": r1["n_slots"], "fp": r1["fp"], "fn": r1["fn"], "mismatch": r1["mismatch"]},
+            "fp8": {"decoded_voxels_per_s": N / dec8_s, "decode_ms": dec8_s * 1e3,
+                    "decode_tflops": N * flops_fwd(2 * M, W, H, C) / dec8_s / 1e12,
+                    "frac_of_fp8_peak": N * flops_fwd(2 * M, W, H, C) / dec8_s / 1e12 / 5000.0,
+                    "l1_slots_per_s": 4096 * L1 / l18_s, "rms_err": rep8["rms"], "max_abs_err": rep8["max_abs"],
+                    "l1": {"fp": r18["fp"], "fn": r18["fn"], "mismatch": r18["mismatch"]}}}
 
 
 def cpu_baseline(grid):

@@ -1105,12 +1105,11 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
 __device__ __forceinline__ int fp8_feature(int kk, int g, int s) {
   return 32 * (2 * kk + (s >> 4)) + 8 * ((s & 15) >> 2) + 4 * g + (s & 3);
 }
+// Four values to e4m3 (round to nearest even).  Callers scale by 448 / max|x|,
+// so no value exceeds 448 by more than a rounding of the product, far below the
+// first value the conversion does not saturate (464): the clamp of the
+// definition never acts and is not executed.
 __device__ __forceinline__ uint32_t pack4_fp8(float a, float b, float c, float d) {
-  const float m = 448.f;
-  a = fminf(fmaxf(a, -m), m);
-  b = fminf(fmaxf(b, -m), m);
-  c = fminf(fmaxf(c, -m), m);
-  d = fminf(fmaxf(d, -m), m);
   uint32_t w = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
   return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(c, d, (int)w, true);
 }
@@ -1176,6 +1175,19 @@ struct Infer8Cfg {
 template <int NIB>
 __device__ __forceinline__ void encode_f32(const Smp& s, const float* benc, int m, float (&X)[NIB][16]) {
   const int h = lane_id() >> 5;
+  if (2 * m == 32 * NIB) {
+    // cos and sin of the same frequency sit in blocks t and t + NIB/2, same register
+#pragma unroll
+    for (int t = 0; t < NIB / 2; ++t)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const floatx4 b = *(const floatx4*)(benc + 4 * sfeat(t, r, h));
+        const float u = fmaf(b[0], s.x[0], fmaf(b[1], s.x[1], b[2] * s.x[2]));
+        X[t][r] = __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(u + 0.25f));
+        X[t + NIB / 2][r] = __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(u));
+      }
+    return;
+  }
 #pragma unroll
   for (int t = 0; t < NIB; ++t)
 #pragma unroll
@@ -1267,8 +1279,10 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
     const char* wl = wl0 + z;
     const LaneK K = lane_consts();
     float Z[NT][NA][16];
+    float zmax[NT];  // per-sample max of the current activations (lane's half)
 #pragma unroll
     for (int u = 0; u < NT; ++u) {
+      zmax[u] = 0.f;
       const Smp smp = fetch_sample(sp, I.tree, base + 32 * u + fl);
       float X0[NIB0][16];
       encode_f32<NIB0>(smp, sm_benc, nv.nfreq, X0);
@@ -1287,11 +1301,13 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
       float inv_sa[NT];
 #pragma unroll
       for (int u = 0; u < NT; ++u) {
-        float mx = 0.f;
+        float mx = zmax[u];
+        if constexpr (l == 0) {
 #pragma unroll
-        for (int t = 0; t < NIBl; ++t)
+          for (int t = 0; t < NIBl; ++t)
 #pragma unroll
-          for (int r = 0; r < 16; ++r) mx = fmaxf(mx, fabsf(Z[u][t][r]));
+            for (int r = 0; r < 16; ++r) mx = fmaxf(mx, fabsf(Z[u][t][r]));
+        }
         mx = fmaxf(mx, shfl_xor32(mx));
         const float sa = mx > 0.f ? 448.f / mx : 1.f;
         inv_sa[u] = 1.f / sa;
@@ -1303,6 +1319,8 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
                                     Z[u][t][4 * q + 3] * sa);
       }
       const float winv = sm_winv[l];
+#pragma unroll
+      for (int u = 0; u < NT; ++u) zmax[u] = 0.f;
 #pragma unroll
       for (int ob = 0; ob < NB; ++ob) {
         floatx16 acc[NT];
@@ -1328,7 +1346,10 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
         for (int u = 0; u < NT; ++u) {
           const float d = winv * inv_sa[u];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) Z[u][ob][r] = fmaxf(fmaf(acc[u][r], d, b0[r]), 0.f);
+          for (int r = 0; r < 16; ++r) {
+            Z[u][ob][r] = fmaxf(fmaf(acc[u][r], d, b0[r]), 0.f);
+            zmax[u] = fmaxf(zmax[u], Z[u][ob][r]);  // ReLU outputs: |z| = z
+          }
         }
       }
     });
