@@ -62,6 +62,8 @@ def main():
     ap.add_argument("--skip-cloud", action="store_true")
     ap.add_argument("--seq-frames", type=int, default=16)
     ap.add_argument("--seq-cap", type=int, default=2000)
+    ap.add_argument("--train-groups", type=int, default=0,
+                    help="work-groups per network; 0 runs the autotuner (profiling runs pin it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (N=%d requested)" % args.gpus,
@@ -118,7 +120,11 @@ def main():
     tune_tree = nvdb.Tree(grid, (0, 0, 0), nvdb.SDF, BAND)
     for k in (0, 1):
         bf.set_params(k, theta0[k])
-    tuned_g, tune_ms = bf.autotune(tune_tree, nets_mask=3, batch=BATCH, reps=3)
+    if args.train_groups > 0:
+        tuned_g, tune_ms = args.train_groups, {}
+        bf.set_train_groups(tuned_g)
+    else:
+        tuned_g, tune_ms = bf.autotune(tune_tree, nets_mask=3, batch=BATCH, reps=3)
     del tune_tree
     print("autotune: G=%d %s" % (tuned_g, {g: round(t, 4) for g, t in tune_ms.items()}), file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -198,7 +204,11 @@ def main():
         for k in (0, 1):
             fp.set_params(k, theta0[k])
         tt = nvdb.Tree(grid, (0, 0, 0), nvdb.SDF, BAND)
-        g32, _ = fp.autotune(tt, nets_mask=3, batch=BATCH, reps=2)
+        if args.train_groups > 0:
+            g32 = args.train_groups
+            fp.set_train_groups(g32)
+        else:
+            g32, _ = fp.autotune(tt, nets_mask=3, batch=BATCH, reps=2)
         del tt
         t32 = {}
         torch.cuda.synchronize()
