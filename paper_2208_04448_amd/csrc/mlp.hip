@@ -25,6 +25,26 @@
 // then feeds Adam, which also rewrites the weight copies the kernels read.
 #include "nvdb_internal.h"
 
+// Waves per decode work-group: eight waves (two per SIMD) share one LDS copy of
+// the weights, so one wave's conversions overlap the other's matrix products.
+#ifndef NVDB_INFER_WAVES
+#define NVDB_INFER_WAVES 8
+#endif
+#ifndef NVDB_INFER_NT
+#define NVDB_INFER_NT 2
+#endif
+// FP8 decode: the e4m3 weights take 64 KiB of LDS, so two work-groups of eight
+// single-tile waves fit on a CU (four waves per SIMD).
+#ifndef NVDB_INFER8_WAVES
+#define NVDB_INFER8_WAVES 8
+#endif
+#ifndef NVDB_INFER8_NT
+#define NVDB_INFER8_NT 1
+#endif
+#ifndef NVDB_INFER8_WGS
+#define NVDB_INFER8_WGS 2
+#endif
+
 namespace nvdb {
 
 // Lane index, opaque to the optimiser: swizzled LDS addresses are functions of the
@@ -947,14 +967,16 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
 // ============================================================== inference kernel
 template <int PREC, int W, int H, int KP, int C>
 struct InferCfg {
-  static constexpr int NT = (PREC == NVDB_BF16) ? 2 : 1;  // 32-sample tiles per wave sharing each weight fragment
+  static constexpr int NT = (PREC == NVDB_BF16) ? NVDB_INFER_NT : 1;  // 32-sample tiles per wave sharing each weight fragment
+  static constexpr int WAVES = NVDB_INFER_WAVES;          // waves per work-group (one LDS copy of the weights)
   static constexpr int WL_BYTES = (PREC == NVDB_BF16) ? H * W * 256 : 0;
   static constexpr int SMALL_FLOATS = H * W + C * W + 4 + 4 * (KP / 2);
   static constexpr int LDS_BYTES = WL_BYTES + SMALL_FLOATS * 4;
 };
 
 template <int PREC, int W, int H, int KP, int C>
-__global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) k_infer(InferLaunch I) {
+__global__ void __launch_bounds__(64 * NVDB_INFER_WAVES, 1)
+    __attribute__((amdgpu_waves_per_eu(NVDB_INFER_WAVES / 4, NVDB_INFER_WAVES / 4))) k_infer(InferLaunch I) {
   using P = PR<PREC>;
   using CF = InferCfg<PREC, W, H, KP, C>;
   constexpr int NB = W / 32, NIB0 = KP / 32, SR = P::SR, NT = CF::NT;
@@ -982,8 +1004,8 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
   __syncthreads();
 
   const int64_t per_wave = 32 * NT;
-  const int64_t stride = (int64_t)gridDim.x * 4 * per_wave;
-  for (int64_t base = ((int64_t)blockIdx.x * 4 + wave) * per_wave; base < sp.n; base += stride) {
+  const int64_t stride = (int64_t)gridDim.x * CF::WAVES * per_wave;
+  for (int64_t base = ((int64_t)blockIdx.x * CF::WAVES + wave) * per_wave; base < sp.n; base += stride) {
     const LaneK K = lane_consts();
     const int h = K.h, fl = K.fl;
     const int z = opaque_zero();
@@ -1165,7 +1187,8 @@ __global__ void __launch_bounds__(256) k_fp8_pack(NetShape s, const float* theta
 
 template <int W, int H, int KP, int C>
 struct Infer8Cfg {
-  static constexpr int NT = 2;
+  static constexpr int NT = NVDB_INFER8_NT;
+  static constexpr int WAVES = NVDB_INFER8_WAVES;
   static constexpr int WL_BYTES = W * KP + (H - 1) * W * W;
   static constexpr int SMALL_FLOATS = H * W + C * W + 4 + 4 * (KP / 2) + 4;
   static constexpr int LDS_BYTES = WL_BYTES + SMALL_FLOATS * 4;
@@ -1238,7 +1261,9 @@ __device__ __forceinline__ void write_outputs(const InferLaunch& I, const float 
 }
 
 template <int W, int H, int KP, int C>
-__global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) k_infer_fp8(InferLaunch I) {
+__global__ void __launch_bounds__(64 * NVDB_INFER8_WAVES, NVDB_INFER8_WGS)
+    __attribute__((amdgpu_waves_per_eu(NVDB_INFER8_WAVES / 4 * NVDB_INFER8_WGS, NVDB_INFER8_WAVES / 4 * NVDB_INFER8_WGS)))
+    k_infer_fp8(InferLaunch I) {
   using CF = Infer8Cfg<W, H, KP, C>;
   constexpr int NB = W / 32, NIB0 = KP / 32, NT = CF::NT;
   constexpr int NA = NB > NIB0 ? NB : NIB0;
@@ -1266,8 +1291,8 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
   __syncthreads();
 
   const int64_t per_wave = 32 * NT;
-  const int64_t stride = (int64_t)gridDim.x * 4 * per_wave;
-  for (int64_t base = ((int64_t)blockIdx.x * 4 + wave) * per_wave; base < sp.n; base += stride) {
+  const int64_t stride = (int64_t)gridDim.x * CF::WAVES * per_wave;
+  for (int64_t base = ((int64_t)blockIdx.x * CF::WAVES + wave) * per_wave; base < sp.n; base += stride) {
     const int lane = lane_id();
     const int h = lane >> 5, fl = lane & 31;
     const int z = opaque_zero();
@@ -1526,7 +1551,7 @@ void launch_train(const KernelSet& ks, const TrainLaunch& L, int n_nets, hipStre
   NVDB_HIP(hipGetLastError());
 }
 void launch_infer(const KernelSet& ks, const InferLaunch& I, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(ks.infer, dim3(grid), dim3(256), 0, st, I);
+  hipLaunchKernelGGL(ks.infer, dim3(grid), dim3(64 * NVDB_INFER_WAVES), 0, st, I);
   NVDB_HIP(hipGetLastError());
 }
 void launch_reduce_adam(const AdamLaunch& A, int64_t max_p, int n_nets, hipStream_t st) {
@@ -1551,7 +1576,7 @@ void launch_quant_fp8(const NetShape& s, const float* theta, char* w8, float* w8
   NVDB_HIP(hipGetLastError());
 }
 void launch_infer8(const KernelSet& ks, const InferLaunch& I, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(ks.infer8, dim3(grid), dim3(256), 0, st, I);
+  hipLaunchKernelGGL(ks.infer8, dim3(grid), dim3(64 * NVDB_INFER8_WAVES), 0, st, I);
   NVDB_HIP(hipGetLastError());
 }
 void launch_fill(float* p, int64_t n, float v, hipStream_t st) {
