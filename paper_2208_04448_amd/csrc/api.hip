@@ -23,7 +23,7 @@ struct Net {
   DevBuf<float> partial, loss_partial, losses;
   DevBuf<int32_t> ran;  // per step of a sequence fit: 1 when the step ran
   DevBuf<floatx4> xt;  // gathered samples of the current step
-  DevBuf<char> wrow, wcol, w1frag;
+  DevBuf<char> wrow, wcol, wfrag, wtfrag;
   // FP8 form: e4m3 fragments and per-layer scales, rebuilt from theta by every FP8 decode
   mutable DevBuf<char> w8;
   mutable DevBuf<float> w8inv;
@@ -84,7 +84,8 @@ static NetView net_view(const Net& n) {
   v.s = n.s;
   v.wrow = n.wrow.p;
   v.wcol = n.wcol.p;
-  v.w1frag = n.w1frag.p;
+  v.wfrag = n.wfrag.p;
+  v.wtfrag = n.wtfrag.p;
   v.bias = n.bias.p;
   v.whead = n.whead.p;
   v.bhead = n.bhead.p;
@@ -102,7 +103,8 @@ static AdamNet adam_view(Net& n) {
   a.prec = n.prec;
   a.wrow = n.wrow.p;
   a.wcol = n.wcol.p;
-  a.w1frag = n.w1frag.p;
+  a.wfrag = n.wfrag.p;
+  a.wtfrag = n.wtfrag.p;
   a.bias = n.bias.p;
   a.whead = n.whead.p;
   a.bhead = n.bhead.p;
@@ -241,9 +243,11 @@ nvdb_status nvdb_model_create(const nvdb_model_desc* desc, nvdb_model** out) {
         const int W = n.s.W, H = n.s.H, KP = n.s.KP;
         if (n.prec == NVDB_BF16) {
           n.wrow.alloc((size_t)H * W * ROW_ELEMS * 2);
-          n.w1frag.alloc((size_t)W * KP * 2);
+          n.wfrag.alloc((size_t)wfrag_elems(n.s) * 2);
+          n.wtfrag.alloc((size_t)std::max<int64_t>(1, wtfrag_elems(n.s)) * 2);
           NVDB_HIP(hipMemset(n.wrow.p, 0, n.wrow.n));
-          NVDB_HIP(hipMemset(n.w1frag.p, 0, n.w1frag.n));
+          NVDB_HIP(hipMemset(n.wfrag.p, 0, n.wfrag.n));
+          NVDB_HIP(hipMemset(n.wtfrag.p, 0, n.wtfrag.n));
         } else {
           const size_t elems = (size_t)KP * W + (size_t)(H - 1) * W * W;
           n.wrow.alloc(elems * 4);

@@ -27,6 +27,19 @@
 
 // Waves per decode work-group: eight waves (two per SIMD) share one LDS copy of
 // the weights, so one wave's conversions overlap the other's matrix products.
+// Training forward products read their BF16 weight fragments from HBM (L2/L1
+// resident) rather than from the LDS copy: measured 5 % faster per step; the
+// input-gradient products keep the transposing LDS reads (from HBM they were
+// 45 % slower).
+#ifndef NVDB_TRAIN_FWD_GLOBAL
+#define NVDB_TRAIN_FWD_GLOBAL 1
+#endif
+#ifndef NVDB_INFER_GLOBAL
+#define NVDB_INFER_GLOBAL 0
+#endif
+#ifndef NVDB_TRAIN_DX_GLOBAL
+#define NVDB_TRAIN_DX_GLOBAL 0
+#endif
 #ifndef NVDB_INFER_WAVES
 #define NVDB_INFER_WAVES 8
 #endif
@@ -379,16 +392,16 @@ __device__ __forceinline__ float frag_sum(bf16x8 f, float acc) {
 // ------------------------------------------------------------ per-layer weights
 // A fragment of W_l for the forward product: rows = output features of block ob,
 // k-step kk of input block t.
-template <int PREC, int W, int KP>
+template <int PREC, int W, int NIBL>
 struct WFwd {
   const char* lds;         // bf16 rows of this layer in LDS
-  const u32x4* gfrag;      // bf16 layer-0 fragments in HBM
+  const u32x4* gfrag;      // bf16 fragments of this layer in HBM
   const float* gcol;       // fp32: this layer transposed [Win][W] in HBM
-  bool global0;            // bf16: read the layer-0 fragments from HBM
+  bool global;             // bf16: read the fragments from HBM instead of LDS
   const LaneK* K;
   __device__ __forceinline__ typename PR<PREC>::Frag operator()(int ob, int t, int kk) const {
     if constexpr (PREC == NVDB_BF16) {
-      if (global0) return __builtin_bit_cast(bf16x8, gfrag[((ob * (KP / 32) + t) * 2 + kk) * 64 + 32 * K->h + K->fl]);
+      if (global) return __builtin_bit_cast(bf16x8, gfrag[((ob * NIBL + t) * 2 + kk) * 64 + 32 * K->h + K->fl]);
       return frag_fwd(lds, *K, ob, t, kk);
     } else {
       return gcol[(size_t)sfeat(t, kk, K->h) * W + 32 * ob + K->fl];
@@ -400,10 +413,13 @@ struct WFwd {
 template <int PREC, int W>
 struct WBwd {
   const char* lds;
-  const float* grow;  // fp32: [W][W] row-major
+  const float* grow;    // fp32: [W][W] row-major
+  const u32x4* gtfrag;  // bf16: transposed fragments of this layer in HBM
+  bool global;          // bf16: read them from HBM instead of transposing from LDS
   const LaneK* K;
   __device__ __forceinline__ typename PR<PREC>::Frag operator()(int ib, int t, int kk) const {
     if constexpr (PREC == NVDB_BF16) {
+      if (global) return __builtin_bit_cast(bf16x8, gtfrag[((ib * (W / 32) + t) * 2 + kk) * 64 + 32 * K->h + K->fl]);
       return frag_tr(lds, *K, 32 * t + 16 * kk, ib);
     } else {
       return grow[(size_t)sfeat(t, kk, K->h) * W + 32 * ib + K->fl];
@@ -535,6 +551,9 @@ struct TrainCfg {
   // Layers whose dW stays in registers for the whole step (BF16 form); the others
   // fold each iteration's contribution into the work-group's partial row in HBM.
   static constexpr bool DWREG = (PREC == NVDB_BF16);
+  // BF16: where the weight fragments of layers 1..H-1 come from (HBM/L2 or the LDS copy)
+  static constexpr bool FWD_GLOBAL = NVDB_TRAIN_FWD_GLOBAL != 0;
+  static constexpr bool DX_GLOBAL = NVDB_TRAIN_DX_GLOBAL != 0;
   static constexpr int DWREG_FROM = (W >= 128) ? 2 : 0;
   static constexpr bool reg_layer(int l) { return DWREG && l >= DWREG_FROM; }
   static constexpr bool any_rmw = !DWREG || DWREG_FROM > 0;
@@ -652,7 +671,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
     {
       uint32_t X0[NIB0][SR];
       encode_S<PREC, NIB0>(smp, sm_benc, nv.nfreq, X0);
-      WFwd<PREC, W, KP> wf0{nullptr, (const u32x4*)nv.w1frag + z, (const float*)nv.wcol + z, true, &K};
+      WFwd<PREC, W, NIB0> wf0{nullptr, (const u32x4*)nv.wfrag + z, (const float*)nv.wcol + z, true, &K};
 #pragma unroll
       for (int ob = 0; ob < NB; ob += 2) {
         floatx16 a0 = bias_acc(sm_bias, K, ob), a1 = bias_acc(sm_bias, K, ob + 1);
@@ -663,8 +682,9 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
     }
     static_for<1, H>([&](auto lc) {
       constexpr int l = decltype(lc)::value;
-      WFwd<PREC, W, KP> wf{wl + (size_t)(l - 1) * W * 256, nullptr,
-                           (const float*)nv.wcol + z + (size_t)KP * W + (size_t)(l - 1) * W * W, false, &K};
+      WFwd<PREC, W, NB> wf{wl + (size_t)(l - 1) * W * 256,
+                           (const u32x4*)((const __bf16*)nv.wfrag + (size_t)W * KP + (size_t)(l - 1) * W * W) + z,
+                           (const float*)nv.wcol + z + (size_t)KP * W + (size_t)(l - 1) * W * W, CF::FWD_GLOBAL, &K};
 #pragma unroll
       for (int ob = 0; ob < NB; ob += 2) {
         floatx16 a0 = bias_acc(sm_bias + l * W, K, ob), a1 = bias_acc(sm_bias + l * W, K, ob + 1);
@@ -881,7 +901,8 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
       if constexpr (l > 0) {
         // g_l = (W_l^T g_{l+1}) * 1[a_l > 0]
         WBwd<PREC, W> wb{wl + (size_t)(l - 1) * W * 256,
-                         (const float*)nv.wrow + z + (size_t)W * KP + (size_t)(l - 1) * W * W, &K};
+                         (const float*)nv.wrow + z + (size_t)W * KP + (size_t)(l - 1) * W * W,
+                         (const u32x4*)((const __bf16*)nv.wtfrag + (size_t)(l - 1) * W * W) + z, CF::DX_GLOBAL, &K};
         uint32_t Gn[NB][SR];
 #pragma unroll
         for (int ib = 0; ib < NB; ib += 2) {
@@ -969,7 +990,8 @@ template <int PREC, int W, int H, int KP, int C>
 struct InferCfg {
   static constexpr int NT = (PREC == NVDB_BF16) ? NVDB_INFER_NT : 1;  // 32-sample tiles per wave sharing each weight fragment
   static constexpr int WAVES = NVDB_INFER_WAVES;          // waves per work-group (one LDS copy of the weights)
-  static constexpr int WL_BYTES = (PREC == NVDB_BF16) ? H * W * 256 : 0;
+  static constexpr bool GLOBAL = (PREC == NVDB_BF16) && NVDB_INFER_GLOBAL != 0;  // fragments from HBM, no LDS copy
+  static constexpr int WL_BYTES = (PREC == NVDB_BF16 && !GLOBAL) ? H * W * 256 : 0;
   static constexpr int SMALL_FLOATS = H * W + C * W + 4 + 4 * (KP / 2);
   static constexpr int LDS_BYTES = WL_BYTES + SMALL_FLOATS * 4;
 };
@@ -1028,8 +1050,10 @@ __global__ void __launch_bounds__(64 * NVDB_INFER_WAVES, 1)
     static_for<0, H>([&](auto lc) {
       constexpr int l = decltype(lc)::value;
       constexpr int NIBl = (l == 0) ? NIB0 : NB;
-      WFwd<PREC, W, KP> wf{wl + (size_t)l * W * 256, nullptr,
-                           (const float*)nv.wcol + z + (l == 0 ? 0 : (size_t)KP * W + (size_t)(l - 1) * W * W), false, &K};
+      WFwd<PREC, W, NIBl> wf{wl + (size_t)l * W * 256,
+                             (const u32x4*)((const __bf16*)nv.wfrag + (l == 0 ? 0 : (size_t)W * KP + (size_t)(l - 1) * W * W)) + z,
+                             (const float*)nv.wcol + z + (l == 0 ? 0 : (size_t)KP * W + (size_t)(l - 1) * W * W), CF::GLOBAL,
+                             &K};
       uint32_t Bn[NT][NB][SR];
 #pragma unroll
       for (int ob = 0; ob < NB; ++ob) {
@@ -1420,11 +1444,25 @@ __device__ __forceinline__ void write_shadow(const AdamNet& A, int64_t p, float 
   if (A.prec == NVDB_BF16) {
     __bf16* rows = (__bf16*)A.wrow + (size_t)l * s.W * ROW_ELEMS;
     rows[(size_t)o * ROW_ELEMS + swz_elem(o, i)] = (__bf16)th;
-    if (l == 0) {
+    {
+      // forward A fragment (ob, t, kk): lane (r, g) element e holds
+      // W[32 ob + r][32 t + 16 kk + 8 (e >> 2) + 4 g + (e & 3)]
+      const int nib = (l == 0 ? s.KP : s.W) / 32;
+      const size_t lbase = (l == 0) ? 0 : (size_t)s.W * s.KP + (size_t)(l - 1) * s.W * s.W;
       const int ob = o >> 5, ii = o & 31, t = i >> 5, rem = i & 31, kk = rem >> 4, rr = rem & 15;
       const int e = ((rr >> 3) << 2) | (rr & 3), hh = (rr >> 2) & 1;
       const int lane = ii + 32 * hh;
-      ((__bf16*)A.w1frag)[((((size_t)ob * (s.KP / 32) + t) * 2 + kk) * 64 + lane) * 8 + e] = (__bf16)th;
+      ((__bf16*)A.wfrag)[lbase + ((((size_t)ob * nib + t) * 2 + kk) * 64 + lane) * 8 + e] = (__bf16)th;
+    }
+    if (l > 0) {
+      // transposed fragment (ib, t, kk) of the input-gradient product: lane (r, g)
+      // element q holds W[32 t + 16 kk + 8 (q >> 2) + 4 g + (q & 3)][32 ib + r]
+      const int nb = s.W / 32;
+      const size_t lbase = (size_t)(l - 1) * s.W * s.W;
+      const int ib = i >> 5, ii = i & 31, t = o >> 5, rem = o & 31, kk = rem >> 4, rr = rem & 15;
+      const int q = ((rr >> 3) << 2) | (rr & 3), hh = (rr >> 2) & 1;
+      const int lane = ii + 32 * hh;
+      ((__bf16*)A.wtfrag)[lbase + ((((size_t)ib * nb + t) * 2 + kk) * 64 + lane) * 8 + q] = (__bf16)th;
     }
   } else {
     const size_t loff = (l == 0) ? 0 : (size_t)s.KP * s.W + (size_t)(l - 1) * s.W * s.W;

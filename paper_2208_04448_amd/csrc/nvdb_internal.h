@@ -153,7 +153,8 @@ struct NetView {
   NetShape s;
   const void* wrow;      // layers 0..H-1: [W rows][256 bytes] (bf16, swizzled) or [W][Win] (fp32)
   const void* wcol;      // fp32 only: layers 0..H-1 transposed, [Win][W]
-  const void* w1frag;    // bf16 only: layer 0 in MFMA A-fragment order
+  const void* wfrag;     // bf16 only: every layer in MFMA A-fragment order (forward products)
+  const void* wtfrag;    // bf16 only: layers 1..H-1 transposed, in MFMA A-fragment order (input gradients)
   const float* bias;     // [H][W]
   const float* whead;    // [C][W]
   const float* bhead;    // [C]
@@ -222,7 +223,8 @@ struct AdamNet {
   int32_t prec;
   void* wrow;
   void* wcol;
-  void* w1frag;
+  void* wfrag;
+  void* wtfrag;
   float* bias;
   float* whead;
   float* bhead;
@@ -237,6 +239,9 @@ struct KernelSet {
   void (*infer8)(InferLaunch);  // FP8 form of the forward pass
 };
 // Bytes of the e4m3 weight fragments of all hidden layers (the FP8 form).
+// Elements of the bf16 fragment copies: all layers (forward), layers 1..H-1 (transposed).
+__host__ __device__ inline int64_t wfrag_elems(const NetShape& s) { return (int64_t)s.W * s.KP + (int64_t)(s.H - 1) * s.W * s.W; }
+__host__ __device__ inline int64_t wtfrag_elems(const NetShape& s) { return (int64_t)(s.H - 1) * s.W * s.W; }
 __host__ __device__ inline int64_t fp8_weight_bytes(const NetShape& s) { return (int64_t)s.W * s.KP + (int64_t)(s.H - 1) * s.W * s.W; }
 
 // mlp.hip
