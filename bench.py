@@ -377,7 +377,23 @@ def cloud_leg(fit_steps, tuned_g):
     dec8_s, l18_s = e0.elapsed_time(e1) / 1e3, e1.elapsed_time(e2) / 1e3
     rep8 = nvdb.errors(tree, values8)
     r18 = nvdb.errors_l1(tree, classes8)
+    # full decode of the lower levels: level-1 classes -> leaves -> regressor with the active rule
     N, L1 = int(info.n_voxels), int(info.n_l1)
+    topo = {}
+    for name, f8 in (("bf16", False), ("fp8", True)):
+        mdl.decode_topology(tree, fp8=f8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pred = mdl.decode_topology(tree, fp8=f8)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rt = nvdb.errors_topology(tree, pred)
+        pi = pred.info()
+        topo[name] = {"s": dt, "predicted_leaves": int(pi.n_leaves), "predicted_voxels": int(pi.n_voxels),
+                      "slots_evaluated_per_s": (4096 * L1 + 512 * int(pi.n_leaves)) / dt,
+                      "fp": rt["fp"], "fn": rt["fn"], "n_common": rt["n_common"], "rms_err_common": rt["rms"],
+                      "max_abs_err_common": rt["max_abs"]}
+        del pred
     return {"workload": "fBm cloud 1024^3 (6 octaves, lacunarity 2, gain 0.5), active where density > 0.55; "
                         "voxel regressor 4x128 + level-1 classifier 4x64 (3 classes), FFM m=64 sigma=10, BF16; "
                         "%d steps x 2^18 samples per network" % fit_steps,
@@ -387,6 +403,7 @@ def cloud_leg(fit_steps, tuned_g):
             "l1_slots_per_s": 4096 * L1 / l1_s, "l1_decode_ms": l1_s * 1e3,
             "rms_err": rep["rms"], "max_abs_err": rep["max_abs"],
             "l1": {"n_slots": r1["n_slots"], "fp": r1["fp"], "fn": r1["fn"], "mismatch": r1["mismatch"]},
+            "topology_decode": topo,
             "fp8": {"decoded_voxels_per_s": N / dec8_s, "decode_ms": dec8_s * 1e3,
                     "decode_tflops": N * flops_fwd(2 * M, W, H, C) / dec8_s / 1e12,
                     "frac_of_fp8_peak": N * flops_fwd(2 * M, W, H, C) / dec8_s / 1e12 / 5000.0,

@@ -276,6 +276,31 @@ typedef struct {
 } nvdb_error_report;
 nvdb_status nvdb_errors(const nvdb_tree* tree, const float* values_dev, const uint64_t* pred_mask_dev,
                         nvdb_error_report* out, void* stream);
+/* Full decode of the lower tree levels (Sec. 3.3, 3.5): the level-1 classifier
+ * predicts, for every leaf slot of the level-1 nodes of `upper` (whose upper
+ * levels are stored explicitly), which slots hold a leaf; inside every
+ * predicted leaf the level-0 classifier predicts the active voxels (logit > 0)
+ * or, when the model has no level-0 classifier, the regressor's value at every
+ * voxel slot is tested with the volume's active rule (SDF |v| <= band, fog
+ * v > threshold, as `upper` was built); the regressor then gives each predicted
+ * voxel its value.  The result is a new tree (free with nvdb_tree_free) with
+ * the predicted leaves in canonical order, their masks, voxel values and the
+ * predicted level-1 child / tile masks; it keeps every level-1 node of
+ * `upper`.  fp8 != 0 runs the networks in the FP8 form.  Synchronises `stream`.
+ * Errors: E_STATE (a needed network missing or unset), E_INVALID. */
+nvdb_status nvdb_decode_topology(const nvdb_model* model, const nvdb_tree* upper, int32_t fp8, nvdb_tree** out,
+                                 void* stream);
+/* Voxel-level comparison of a decoded tree with the truth it was decoded from
+ * (same level-1 nodes): n_true / n_pred voxels, fp = predicted voxels that are
+ * not active, fn = active voxels not predicted, and over the n_common voxels in
+ * both, max |v^ - v| and RMS.  Synchronises `stream`. */
+typedef struct {
+  int64_t n_true, n_pred, fp, fn, n_common;
+  double max_abs, rms;
+} nvdb_topology_report;
+nvdb_status nvdb_errors_topology(const nvdb_tree* truth, const nvdb_tree* pred, nvdb_topology_report* out,
+                                 void* stream);
+
 /* Level-1 classifier report (Sec. 3.3.1, Sec. 4) over the 4096 leaf slots of
  * every level-1 node: classes_dev is uint8[n_l1][4096] as written by
  * nvdb_decode_l1; the true class of a slot is 0 when it has a child leaf, else

@@ -185,6 +185,68 @@ def errors_l1(tr, classes):
                 mismatch=int(np.sum(c != truth)))
 
 
+def topology_from_decisions(tr, classes, active_fn, value_fn):
+    """Lower tree levels rebuilt from per-slot decisions (Sec. 3.3, 3.5).
+
+    classes: level-1 class of every leaf slot of tr's level-1 nodes (0 = leaf);
+    active_fn(p) -> bool per voxel coordinate of the predicted leaves' slots;
+    value_fn(p, active) -> values of the active voxels.  Returns the predicted
+    leaf origins, voxel coordinates and values in canonical order."""
+    slots = np.nonzero(np.asarray(classes).reshape(-1) == 0)[0]
+    node, n1 = slots >> 12, slots & 4095
+    leaf_o = tr["l1_origin"][node].astype(np.int64) + T.n1_to_offset(n1)
+    p = (leaf_o[:, None, :] + T.n0_to_offset(np.arange(512))[None, :, :]).reshape(-1, 3)
+    act = np.asarray(active_fn(p), bool) if len(p) else np.zeros(0, bool)
+    ijk = p[act]
+    values = np.asarray(value_fn(p, act), np.float64) if len(ijk) else np.zeros(0)
+    return dict(leaf_origin=leaf_o, ijk=ijk, values=values)
+
+
+def decode_topology(tr, lo, D, kind, thr, value_scale, l1, reg, l0=None, fp8=False):
+    """Full decode with the networks: level-1 classes at every leaf slot, then the
+    level-0 classifier (logit > 0) or, without one, the regressor's value tested
+    with the volume's active rule (SDF |v| <= band, fog v > threshold), then the
+    regressor's values.  l1, reg, l0: (theta, shapes, B)."""
+    cls = l1_classes(decode_l1(*l1, tr, lo, D, fp8=fp8))
+
+    def reg_values(p):
+        return _batched_predict(*reg, mlp.normalize_voxel(p, lo, D), fp8=fp8)[:, 0] * value_scale
+
+    if l0 is not None:
+        def active(p):
+            return _batched_predict(*l0, mlp.normalize_voxel(p, lo, D), fp8=fp8)[:, 0] > 0
+
+        def values(p, act):
+            return reg_values(p[act])
+    else:
+        cache = {}
+
+        def active(p):
+            v = reg_values(p)
+            cache["v"] = v
+            return np.abs(v) <= thr if kind == T.SDF else v > thr
+
+        def values(p, act):
+            return cache["v"][act]
+    return topology_from_decisions(tr, cls, active, values)
+
+
+def _voxel_keys(ijk):
+    ijk = np.asarray(ijk, np.int64) + (1 << 20)
+    return (ijk[:, 0] << 42) | (ijk[:, 1] << 21) | ijk[:, 2]
+
+
+def errors_topology(true_ijk, true_values, pred_ijk, pred_values):
+    """Voxel-level comparison: predicted voxels that are not active (fp), active
+    voxels not predicted (fn), and max / RMS value error over the voxels in both."""
+    kt, kp = _voxel_keys(true_ijk), _voxel_keys(pred_ijk)
+    common, it, ip = np.intersect1d(kt, kp, assume_unique=True, return_indices=True)
+    d = np.asarray(pred_values, np.float64)[ip] - np.asarray(true_values, np.float64)[it]
+    return dict(n_true=len(kt), n_pred=len(kp), fp=len(kp) - len(common), fn=len(kt) - len(common),
+                n_common=len(common), max_abs=float(np.max(np.abs(d))) if len(d) else 0.0,
+                rms=float(np.sqrt(np.mean(d * d))) if len(d) else 0.0)
+
+
 def errors(tr, vhat, kind, pred_mask=None):
     """Error report: max |v^ - v| and RMS over the true active voxels (value
     units), IoU of the interior {v <= 0} over the active set for level sets,

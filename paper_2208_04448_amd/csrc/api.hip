@@ -890,6 +890,97 @@ nvdb_status nvdb_errors(const nvdb_tree* tree, const float* values_dev, const ui
   });
 }
 
+nvdb_status nvdb_decode_topology(const nvdb_model* m, const nvdb_tree* upper, int32_t fp8, nvdb_tree** out,
+                                 void* stream) {
+  return guarded([&] {
+    NVDB_REQUIRE(m && upper && out, NVDB_E_INVALID, "null argument");
+    *out = nullptr;
+    hipStream_t st = (hipStream_t)stream;
+    const bool use_fp8 = fp8 != 0;
+    const Net& R = net_of(m, NVDB_NET_REGRESSOR);
+    NVDB_REQUIRE(R.params_set && R.enc_set, NVDB_E_STATE, "regressor parameters or encoding not set");
+    const bool has_l0 = m->nets[NVDB_NET_L0].present;
+    if (has_l0)
+      NVDB_REQUIRE(m->nets[NVDB_NET_L0].params_set && m->nets[NVDB_NET_L0].enc_set, NVDB_E_STATE,
+                   "level-0 classifier parameters or encoding not set");
+    nvdb_tree* t = new nvdb_tree();
+    try {
+      for (int d = 0; d < 3; ++d) {
+        t->origin[d] = upper->origin[d];
+        t->dims[d] = upper->dims[d];
+      }
+      t->kind = upper->kind;
+      t->thr = upper->thr;
+      t->n_l1 = upper->n_l1;
+      t->n_l2 = upper->n_l2;
+      t->l2_origin = upper->l2_origin;
+      const int64_t nl1 = std::max<int64_t>(t->n_l1, 1);
+      t->l1_o.alloc(nl1);
+      t->l1_child.alloc(nl1 * 64);
+      t->l1_active.alloc(nl1 * 64);
+      if (t->n_l1 > 0)
+        NVDB_HIP(hipMemcpyAsync(t->l1_o.p, upper->l1_o.p, t->n_l1 * sizeof(int4), hipMemcpyDeviceToDevice, st));
+      // level 1: classes of every leaf slot, predicted leaves
+      const int64_t n_slots = 4096 * t->n_l1;
+      DevBuf<uint8_t> cls;
+      DevBuf<uint64_t> flag, prefix;
+      cls.alloc(std::max<int64_t>(n_slots, 1));
+      flag.alloc(std::max<int64_t>(n_slots, 1));
+      prefix.alloc(std::max<int64_t>(n_slots, 1));
+      if (n_slots > 0) {
+        decode_l1_impl(m, upper, cls.p, use_fp8, st);
+        pred_flags(cls.p, n_slots, flag.p, st);
+      }
+      const uint64_t nleaf = scan_u64(flag.p, n_slots, prefix.p, st);
+      t->n_leaf = (int64_t)nleaf;
+      t->leaf_o.alloc(std::max<int64_t>(t->n_leaf, 1));
+      t->leaf_mask.alloc(std::max<int64_t>(t->n_leaf, 1) * 8);
+      t->leaf_off.alloc(t->n_leaf + 1);
+      if (n_slots > 0) pred_leaves(cls.p, prefix.p, t->l1_o.p, n_slots, t->leaf_o.p, t->l1_child.p, t->l1_active.p, st);
+      // level 0: voxel masks
+      DevBuf<float> slot_y;
+      if (t->n_leaf > 0) {
+        if (has_l0) {
+          InferLaunch I{};
+          I.out_kind = OUT_MASK;
+          I.mask = t->leaf_mask.p;
+          run_infer(m, m->nets[NVDB_NET_L0], t, SRC_LEAF_SLOTS, 512 * t->n_leaf, I, use_fp8, st);
+        } else {
+          slot_y.alloc(512 * t->n_leaf);
+          InferLaunch I{};
+          I.out_kind = OUT_Y;
+          I.y = slot_y.p;
+          run_infer(m, R, t, SRC_LEAF_SLOTS, 512 * t->n_leaf, I, use_fp8, st);
+          mask_from_values(slot_y.p, t->n_leaf, m->d.value_scale, t->kind, t->thr, t->leaf_mask.p, st);
+        }
+      }
+      pred_voxels(t->leaf_mask.p, t->n_leaf, t, has_l0 ? nullptr : slot_y.p, m->d.value_scale, st);
+      // values at the predicted voxels
+      if (has_l0 && t->n_vox > 0) {
+        InferLaunch I{};
+        I.out_kind = OUT_VALUES;
+        I.out_scale = m->d.value_scale;
+        I.y = t->values.p;
+        run_infer(m, R, t, SRC_VOXELS, t->n_vox, I, use_fp8, st);
+      }
+      NVDB_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+      delete t;
+      throw;
+    }
+    *out = t;
+  });
+}
+
+nvdb_status nvdb_errors_topology(const nvdb_tree* truth, const nvdb_tree* pred, nvdb_topology_report* out,
+                                 void* stream) {
+  return guarded([&] {
+    NVDB_REQUIRE(truth && pred && out, NVDB_E_INVALID, "null argument");
+    NVDB_REQUIRE(truth->n_l1 == pred->n_l1, NVDB_E_INVALID, "trees do not share their level-1 nodes");
+    error_report_topology(*truth, *pred, out, (hipStream_t)stream);
+  });
+}
+
 nvdb_status nvdb_errors_l1(const nvdb_tree* tree, const uint8_t* classes_dev, nvdb_l1_report* out, void* stream) {
   return guarded([&] {
     NVDB_REQUIRE(tree && out && (classes_dev || tree->n_l1 == 0), NVDB_E_INVALID, "null argument");

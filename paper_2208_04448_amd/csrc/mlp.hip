@@ -231,14 +231,14 @@ __device__ __forceinline__ Smp fetch_sample(const SampleSpec& sp, const TreeView
     px = o.x + (int)(n0 >> 6);
     py = o.y + (int)((n0 >> 3) & 7u);
     pz = o.z + (int)(n0 & 7u);
-    s.t = tv.values[g] * sp.tscale;
+    if (!sp.direct) s.t = tv.values[g] * sp.tscale;  // decoding needs no target
   } else if (sp.src == SRC_LEAF_SLOTS) {
     uint32_t leaf = g >> 9, n0 = g & 511u;
     int4 o = tv.leaf_o[leaf];
     px = o.x + (int)(n0 >> 6);
     py = o.y + (int)((n0 >> 3) & 7u);
     pz = o.z + (int)(n0 & 7u);
-    s.t = (float)((tv.leaf_mask[(size_t)leaf * 8 + (n0 >> 6)] >> (n0 & 63u)) & 1ull);
+    if (!sp.direct) s.t = (float)((tv.leaf_mask[(size_t)leaf * 8 + (n0 >> 6)] >> (n0 & 63u)) & 1ull);
   } else {  // SRC_L1_SLOTS: leaf centres of every slot of the level-1 nodes
     uint32_t node = g >> 12, n1 = g & 4095u;
     int4 o = tv.l1_o[node];
@@ -246,9 +246,11 @@ __device__ __forceinline__ Smp fetch_sample(const SampleSpec& sp, const TreeView
     py = o.y + 8 * (int)((n1 >> 4) & 15u);
     pz = o.z + 8 * (int)(n1 & 15u);
     half = 4.f;
-    uint64_t c = (tv.l1_child[(size_t)node * 64 + (n1 >> 6)] >> (n1 & 63u)) & 1ull;
-    uint64_t a = (tv.l1_active[(size_t)node * 64 + (n1 >> 6)] >> (n1 & 63u)) & 1ull;
-    s.cls = c ? 0 : (a ? 1 : 2);
+    if (!sp.direct) {
+      const uint64_t c = (tv.l1_child[(size_t)node * 64 + (n1 >> 6)] >> (n1 & 63u)) & 1ull;
+      const uint64_t a = (tv.l1_active[(size_t)node * 64 + (n1 >> 6)] >> (n1 & 63u)) & 1ull;
+      s.cls = c ? 0 : (a ? 1 : 2);
+    }
   }
   s.x[0] = ((float)(px - sp.lo[0]) + half) * sp.inv_d;
   s.x[1] = ((float)(py - sp.lo[1]) + half) * sp.inv_d;

@@ -68,6 +68,7 @@ struct DevBuf {
 struct Tree {
   int32_t origin[3], dims[3];
   int32_t kind = NVDB_SDF;     // active rule the tree was built with
+  float thr = 0.f;             // its band (SDF) or threshold (fog)
   int64_t n_vox = 0, n_leaf = 0, n_l1 = 0, n_l2 = 0;
   DevBuf<int4> leaf_o;         // leaf origins (w unused)
   DevBuf<uint64_t> leaf_mask;  // [L][8]
@@ -261,5 +262,12 @@ Tree* build_tree_dense(const float* grid, const int32_t dims[3], const int32_t o
 void error_report(const Tree& t, const float* values, const uint64_t* pred_mask, nvdb_error_report* rep,
                   hipStream_t st);
 void error_report_l1(const Tree& t, const uint8_t* classes, nvdb_l1_report* rep, hipStream_t st);
+uint64_t scan_u64(const uint64_t* in, int64_t n, uint64_t* out, hipStream_t st);  // exclusive; returns the total
+void pred_flags(const uint8_t* cls, int64_t n, uint64_t* flag, hipStream_t st);
+void pred_leaves(const uint8_t* cls, const uint64_t* prefix, const int4* l1_o, int64_t n, int4* leaf_o, uint64_t* child,
+                 uint64_t* active, hipStream_t st);
+void mask_from_values(const float* y, int64_t n_leaf, float scale, int kind, float thr, uint64_t* mask, hipStream_t st);
+uint64_t pred_voxels(const uint64_t* mask, int64_t n_leaf, Tree* t, const float* slot_y, float scale, hipStream_t st);
+void error_report_topology(const Tree& truth, const Tree& pred, nvdb_topology_report* rep, hipStream_t st);
 
 }  // namespace nvdb

@@ -291,6 +291,7 @@ Tree* build_tree_dense(const float* grid, const int32_t dims[3], const int32_t o
       t->dims[d] = dims[d];
     }
     t->kind = rule.kind;
+    t->thr = rule.band_or_threshold;
     t->n_leaf = (int64_t)(tot >> 32);
     t->n_vox = (int64_t)(tot & 0xffffffffull);
     // keep the level-1 nodes that own leaves
@@ -454,6 +455,266 @@ void error_report(const Tree& t, const float* values, const uint64_t* pred_mask,
   if (t.kind != NVDB_SDF) rep->iou = -1.0;
   rep->fp = (int64_t)fp;
   rep->fn = (int64_t)fn;
+}
+
+// ----------------------------------------------------------------- predicted topology
+uint64_t scan_u64(const uint64_t* in, int64_t n, uint64_t* out, hipStream_t st) {
+  if (n == 0) return 0;
+  const int64_t nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
+  DevBuf<uint64_t> sums, total;
+  sums.alloc(nb);
+  total.alloc(1);
+  hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(256), 0, st, in, n, sums.p);
+  hipLaunchKernelGGL(k_scan_sums_serial, dim3(1), dim3(64), 0, st, sums.p, nb, total.p);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, st, in, n, sums.p, out);
+  NVDB_HIP(hipGetLastError());
+  uint64_t tot = 0;
+  NVDB_HIP(hipMemcpyAsync(&tot, total.p, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+  NVDB_HIP(hipStreamSynchronize(st));
+  return tot;
+}
+
+__global__ void k_pred_flags(const uint8_t* cls, int64_t n, uint64_t* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flag[i] = cls[i] == 0 ? 1ull : 0ull;
+}
+// Leaf origins of the slots predicted as child leaves, in slot order (canonical
+// order, since the level-1 nodes are), and the level-1 child / tile bit masks.
+__global__ void k_pred_leaves(const uint8_t* cls, const uint64_t* prefix, const int4* l1_o, int64_t n, int4* leaf_o) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || cls[i] != 0) return;
+  const int4 o = l1_o[i >> 12];
+  const int n1 = (int)(i & 4095);
+  leaf_o[prefix[i]] = make_int4(o.x + 8 * (n1 >> 8), o.y + 8 * ((n1 >> 4) & 15), o.z + 8 * (n1 & 15), 0);
+}
+__global__ void k_pred_l1_bits(const uint8_t* cls, int64_t n_words, uint64_t* child, uint64_t* active) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= n_words) return;
+  uint64_t c = 0, a = 0;
+  for (int b = 0; b < 64; ++b) {
+    const uint8_t k = cls[w * 64 + b];
+    c |= (uint64_t)(k == 0) << b;
+    a |= (uint64_t)(k == 1) << b;
+  }
+  child[w] = c;
+  active[w] = a;
+}
+// Voxel masks from the regressor's value at every slot, by the volume's active rule.
+__global__ void k_mask_from_values(const float* y, int64_t n_words, float scale, int kind, float thr, uint64_t* mask) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= n_words) return;
+  uint64_t m = 0;
+  for (int b = 0; b < 64; ++b) {
+    const float v = y[w * 64 + b] * scale;
+    const bool act = kind == NVDB_SDF ? fabsf(v) <= thr : v > thr;
+    m |= (uint64_t)act << b;
+  }
+  mask[w] = m;
+}
+__global__ void k_leaf_counts(const uint64_t* mask, int64_t n_leaf, uint64_t* cnt) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= n_leaf) return;
+  uint64_t c = 0;
+  for (int w = 0; w < 8; ++w) c += __popcll(mask[l * 8 + w]);
+  cnt[l] = c;
+}
+// One thread per (leaf, mask word): voxel keys (and values from slot_y, if given) of
+// the word's set bits, in ascending n0.
+__global__ void k_pred_voxels(const uint64_t* mask, const uint64_t* prefix, int64_t n_leaf, uint32_t* leaf_off,
+                              uint32_t* vox_key, const float* slot_y, float scale, float* values) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_leaf * 8) return;
+  const int64_t l = t >> 3;
+  const int w = (int)(t & 7);
+  uint64_t pos = prefix[l];
+  for (int q = 0; q < w; ++q) pos += __popcll(mask[l * 8 + q]);
+  if (w == 0) leaf_off[l] = (uint32_t)prefix[l];
+  uint64_t m = mask[l * 8 + w];
+  while (m) {
+    const int b = __builtin_ctzll(m);
+    m &= m - 1;
+    const uint32_t n0 = (uint32_t)(w * 64 + b);
+    vox_key[pos] = (uint32_t)(l << 9) | n0;
+    if (slot_y) values[pos] = slot_y[l * 512 + n0] * scale;
+    ++pos;
+  }
+}
+
+void pred_flags(const uint8_t* cls, int64_t n, uint64_t* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_pred_flags, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, cls, n, flag);
+  NVDB_HIP(hipGetLastError());
+}
+void pred_leaves(const uint8_t* cls, const uint64_t* prefix, const int4* l1_o, int64_t n, int4* leaf_o, uint64_t* child,
+                 uint64_t* active, hipStream_t st) {
+  hipLaunchKernelGGL(k_pred_leaves, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, cls, prefix, l1_o, n, leaf_o);
+  hipLaunchKernelGGL(k_pred_l1_bits, dim3((unsigned)((n / 64 + 255) / 256)), dim3(256), 0, st, cls, n / 64, child,
+                     active);
+  NVDB_HIP(hipGetLastError());
+}
+void mask_from_values(const float* y, int64_t n_leaf, float scale, int kind, float thr, uint64_t* mask, hipStream_t st) {
+  const int64_t nw = n_leaf * 8;
+  hipLaunchKernelGGL(k_mask_from_values, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st, y, nw, scale, kind, thr,
+                     mask);
+  NVDB_HIP(hipGetLastError());
+}
+uint64_t pred_voxels(const uint64_t* mask, int64_t n_leaf, Tree* t, const float* slot_y, float scale, hipStream_t st) {
+  if (n_leaf == 0) {
+    t->n_vox = 0;
+    t->values.alloc(1);
+    t->vox_key.alloc(1);
+    const uint32_t zero = 0;
+    NVDB_HIP(hipMemcpyAsync(t->leaf_off.p, &zero, sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    NVDB_HIP(hipStreamSynchronize(st));
+    return 0;
+  }
+  DevBuf<uint64_t> cnt, prefix;
+  cnt.alloc(std::max<int64_t>(n_leaf, 1));
+  prefix.alloc(std::max<int64_t>(n_leaf, 1));
+  hipLaunchKernelGGL(k_leaf_counts, dim3((unsigned)((n_leaf + 255) / 256)), dim3(256), 0, st, mask, n_leaf, cnt.p);
+  NVDB_HIP(hipGetLastError());
+  const uint64_t nv = scan_u64(cnt.p, n_leaf, prefix.p, st);
+  NVDB_REQUIRE(nv < (1ull << 32), NVDB_E_INVALID, "too many predicted voxels");
+  t->n_vox = (int64_t)nv;
+  t->values.alloc(std::max<int64_t>(t->n_vox, 1));
+  t->vox_key.alloc(std::max<int64_t>(t->n_vox, 1));
+  const uint32_t nv32 = (uint32_t)nv;
+  NVDB_HIP(hipMemcpyAsync(t->leaf_off.p + n_leaf, &nv32, sizeof(uint32_t), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_pred_voxels, dim3((unsigned)((n_leaf * 8 + 255) / 256)), dim3(256), 0, st, mask, prefix.p,
+                     n_leaf, t->leaf_off.p, t->vox_key.p, slot_y, scale, t->values.p);
+  NVDB_HIP(hipGetLastError());
+  NVDB_HIP(hipStreamSynchronize(st));
+  return nv;
+}
+
+// Voxel-level comparison of a predicted tree with the truth; both share the
+// level-1 nodes.  One wave per level-1 slot.
+struct TopoPartial {
+  uint64_t fp, fn, common;
+  double sq;
+  float max_abs;
+};
+__global__ void k_node_counts(const uint64_t* child, int64_t n_l1, uint64_t* cnt) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_l1) return;
+  uint64_t c = 0;
+  for (int w = 0; w < 64; ++w) c += __popcll(child[k * 64 + w]);
+  cnt[k] = c;
+}
+struct TopoSide {
+  const uint64_t* child;      // [n_l1][64]
+  const uint64_t* node_base;  // [n_l1] first leaf of each node
+  const uint64_t* mask;       // [L][8]
+  const uint32_t* leaf_off;
+  const float* values;
+};
+__device__ __forceinline__ int64_t side_leaf(const TopoSide& S, int64_t node, int n1, int lane) {
+  // leaf index of slot n1: node base + child bits before n1 (lane w counts word w)
+  const uint64_t word = S.child[node * 64 + lane];
+  const int wsel = n1 >> 6;
+  int c = lane < wsel ? __popcll(word) : (lane == wsel ? __popcll(word & ((1ull << (n1 & 63)) - 1ull)) : 0);
+  for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
+  return (int64_t)S.node_base[node] + c;
+}
+__global__ void __launch_bounds__(256) k_err_topology(TopoSide T, TopoSide P, int64_t n_slots, TopoPartial* out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint64_t fp = 0, fn = 0, common = 0;
+  double sq = 0.0;
+  float mx = 0.f;
+  for (int64_t s = (int64_t)blockIdx.x * 4 + wv; s < n_slots; s += (int64_t)gridDim.x * 4) {
+    const int64_t node = s >> 12;
+    const int n1 = (int)(s & 4095);
+    const bool tb = (T.child[node * 64 + (n1 >> 6)] >> (n1 & 63)) & 1ull;
+    const bool pb = (P.child[node * 64 + (n1 >> 6)] >> (n1 & 63)) & 1ull;
+    if (!tb && !pb) continue;
+    const int64_t tl = tb ? side_leaf(T, node, n1, lane) : -1;
+    const int64_t pl = pb ? side_leaf(P, node, n1, lane) : -1;
+    // lane handles voxel slots 8 lane .. 8 lane + 7 (one byte of the mask)
+    const int w = lane >> 3, sh = (lane & 7) * 8;
+    const uint64_t tw = tb ? T.mask[tl * 8 + w] : 0ull, pw = pb ? P.mask[pl * 8 + w] : 0ull;
+    const uint32_t tm = (uint32_t)((tw >> sh) & 255ull), pm = (uint32_t)((pw >> sh) & 255ull);
+    fp += __popc(pm & ~tm);
+    fn += __popc(tm & ~pm);
+    const uint32_t both = tm & pm;
+    if (__ballot(both != 0) == 0ull) continue;
+    // ranks of the lane's first bit among the leaf's voxels
+    uint32_t trank = 0, prank = 0;
+    for (int q = 0; q < w; ++q) {
+      if (tb) trank += __popcll(T.mask[tl * 8 + q]);
+      if (pb) prank += __popcll(P.mask[pl * 8 + q]);
+    }
+    trank += __popcll(tw & ((1ull << sh) - 1ull));
+    prank += __popcll(pw & ((1ull << sh) - 1ull));
+    for (int b = 0; b < 8; ++b) {
+      const bool tbit = (tm >> b) & 1u, pbit = (pm >> b) & 1u;
+      if (tbit && pbit) {
+        const float d = P.values[P.leaf_off[pl] + prank] - T.values[T.leaf_off[tl] + trank];
+        sq += (double)d * (double)d;
+        mx = fmaxf(mx, fabsf(d));
+        if (isnan(d)) mx = INFINITY;
+        ++common;
+      }
+      trank += tbit;
+      prank += pbit;
+    }
+  }
+  __shared__ double s_sq[256];
+  __shared__ float s_mx[256];
+  __shared__ uint64_t s_fp[256], s_fn[256], s_c[256];
+  s_sq[threadIdx.x] = sq;
+  s_mx[threadIdx.x] = mx;
+  s_fp[threadIdx.x] = fp;
+  s_fn[threadIdx.x] = fn;
+  s_c[threadIdx.x] = common;
+  __syncthreads();
+  for (int off = 128; off >= 1; off >>= 1) {
+    if (threadIdx.x < off) {
+      s_sq[threadIdx.x] += s_sq[threadIdx.x + off];
+      s_mx[threadIdx.x] = fmaxf(s_mx[threadIdx.x], s_mx[threadIdx.x + off]);
+      s_fp[threadIdx.x] += s_fp[threadIdx.x + off];
+      s_fn[threadIdx.x] += s_fn[threadIdx.x + off];
+      s_c[threadIdx.x] += s_c[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = TopoPartial{s_fp[0], s_fn[0], s_c[0], s_sq[0], s_mx[0]};
+}
+
+void error_report_topology(const Tree& truth, const Tree& pred, nvdb_topology_report* rep, hipStream_t st) {
+  std::memset(rep, 0, sizeof(*rep));
+  rep->n_true = truth.n_vox;
+  rep->n_pred = pred.n_vox;
+  const int64_t n_l1 = truth.n_l1;
+  if (n_l1 == 0) return;
+  DevBuf<uint64_t> tc, pc, tb, pb;
+  tc.alloc(n_l1);
+  pc.alloc(n_l1);
+  tb.alloc(n_l1);
+  pb.alloc(n_l1);
+  hipLaunchKernelGGL(k_node_counts, dim3((unsigned)((n_l1 + 255) / 256)), dim3(256), 0, st, truth.l1_child.p, n_l1, tc.p);
+  hipLaunchKernelGGL(k_node_counts, dim3((unsigned)((n_l1 + 255) / 256)), dim3(256), 0, st, pred.l1_child.p, n_l1, pc.p);
+  NVDB_HIP(hipGetLastError());
+  scan_u64(tc.p, n_l1, tb.p, st);
+  scan_u64(pc.p, n_l1, pb.p, st);
+  TopoSide T{truth.l1_child.p, tb.p, truth.leaf_mask.p, truth.leaf_off.p, truth.values.p};
+  TopoSide P{pred.l1_child.p, pb.p, pred.leaf_mask.p, pred.leaf_off.p, pred.values.p};
+  const int nblk = 512;
+  DevBuf<TopoPartial> part;
+  part.alloc(nblk);
+  hipLaunchKernelGGL(k_err_topology, dim3(nblk), dim3(256), 0, st, T, P, 4096 * n_l1, part.p);
+  NVDB_HIP(hipGetLastError());
+  std::vector<TopoPartial> h(nblk);
+  NVDB_HIP(hipMemcpyAsync(h.data(), part.p, nblk * sizeof(TopoPartial), hipMemcpyDeviceToHost, st));
+  NVDB_HIP(hipStreamSynchronize(st));
+  double sq = 0.0, mx = 0.0;
+  for (const auto& e : h) {
+    rep->fp += (int64_t)e.fp;
+    rep->fn += (int64_t)e.fn;
+    rep->n_common += (int64_t)e.common;
+    sq += e.sq;
+    mx = std::max(mx, (double)e.max_abs);
+  }
+  rep->max_abs = mx;
+  rep->rms = rep->n_common > 0 ? std::sqrt(sq / (double)rep->n_common) : 0.0;
 }
 
 // Level-1 classifier against the truth: class 0 (child leaf) iff the child bit

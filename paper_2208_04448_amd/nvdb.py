@@ -61,6 +61,11 @@ class L1Report(C.Structure):
     _fields_ = [("n_slots", C.c_int64), ("fp", C.c_int64), ("fn", C.c_int64), ("mismatch", C.c_int64)]
 
 
+class TopologyReport(C.Structure):
+    _fields_ = [("n_true", C.c_int64), ("n_pred", C.c_int64), ("fp", C.c_int64), ("fn", C.c_int64),
+                ("n_common", C.c_int64), ("max_abs", C.c_double), ("rms", C.c_double)]
+
+
 class TuneReport(C.Structure):
     _fields_ = [("chosen_g", C.c_int32), ("n_candidates", C.c_int32), ("g", C.c_int32 * 16),
                 ("ms_per_step", C.c_float * 16)]
@@ -99,6 +104,8 @@ _SIGS = {
     "nvdb_decode_l1_fp8": (C.c_int32, [_P, _P, _P, _P]),
     "nvdb_errors": (C.c_int32, [_P, _P, _P, C.POINTER(ErrorReport), _P]),
     "nvdb_errors_l1": (C.c_int32, [_P, _P, C.POINTER(L1Report), _P]),
+    "nvdb_decode_topology": (C.c_int32, [_P, _P, C.c_int32, C.POINTER(_P), _P]),
+    "nvdb_errors_topology": (C.c_int32, [_P, _P, C.POINTER(TopologyReport), _P]),
     "nvdb_forward_dev": (C.c_int32, [_P, C.c_int32, _P, C.c_int64, _P, _P]),
     "nvdb_backward_dev": (C.c_int32, [_P, C.c_int32, _P, _P, C.c_int64, _P, _P]),
     "nvdb_sample_indices_dev": (C.c_int32, [C.c_uint64, C.c_int32, C.c_int64, C.c_int64, C.c_int64, _P, _P]),
@@ -294,6 +301,15 @@ class Model:
         _check(f(self.h, tree.h, _ptr(out), _stream()))
         return out
 
+    def decode_topology(self, upper, fp8=False):
+        """Decode the lower tree levels below the level-1 nodes of `upper`; returns a new Tree."""
+        h = C.c_void_p()
+        _check(_lib.nvdb_decode_topology(self.h, upper.h, int(bool(fp8)), C.byref(h), _stream()))
+        t = Tree.__new__(Tree)
+        t.h = h
+        t.kind = upper.kind
+        return t
+
     def forward(self, net, x):
         import torch
         x = x.contiguous()
@@ -324,6 +340,13 @@ def errors_l1(tree, classes):
     r = L1Report()
     _check(_lib.nvdb_errors_l1(tree.h, _ptr(classes), C.byref(r), _stream()))
     return dict(n_slots=r.n_slots, fp=r.fp, fn=r.fn, mismatch=r.mismatch)
+
+
+def errors_topology(truth, pred):
+    r = TopologyReport()
+    _check(_lib.nvdb_errors_topology(truth.h, pred.h, C.byref(r), _stream()))
+    return dict(n_true=r.n_true, n_pred=r.n_pred, fp=r.fp, fn=r.fn, n_common=r.n_common, max_abs=r.max_abs,
+                rms=r.rms)
 
 
 def sample_indices(seed, stream_id, step, n_pop, batch):

@@ -589,3 +589,87 @@ def test_fp8_decode_parity(gpu_lib, shape):
         srt = np.sort(lg, axis=1)
         ok = (cls == F.l1_classes(lg)) | (srt[:, -1] - srt[:, -2] <= 6e-2)
         assert ok.all()
+
+
+# --------------------------------------------------------------------------- full decode of the lower levels
+def _tree_voxels(ex):
+    L = len(ex["leaf_origin"])
+    bits = np.unpackbits(ex["leaf_mask"].reshape(L, 8).view(np.uint8), bitorder="little").reshape(L, 512).astype(bool)
+    p = ex["leaf_origin"][:, None, :].astype(np.int64) + T.n0_to_offset(np.arange(512))[None, :, :]
+    return p[bits], ex["values"]
+
+
+@pytest.mark.parametrize("with_l0", [True, False])
+def test_decode_topology_matches_oracle(gpu_lib, with_l0):
+    """Level-1 classes -> predicted leaves -> level-0 classifier (or the regressor
+    with the active rule) -> regressor values, FP32, against the oracle's full
+    decode with the same weights.  Leaves and voxels may differ only where the
+    deciding logit or value is within FP32 rounding of its threshold."""
+    v = workloads.sphere_sdf(n=200, center=(100.0, 90.0, 110.0), radius=70.0)
+    tr = gpu_lib.Tree(v.to(DEV), (0, 0, 0), T.SDF, 3.0)
+    ot = T.build(*T.active_set_dense(v.numpy(), (0, 0, 0), T.SDF, 3.0))
+    nets = {2: (64, 4, 64, 3), 0: (64, 3, 18, 1)}
+    if with_l0:
+        nets[1] = (64, 3, 18, 1)
+    m = gpu_lib.Model(nets, precision=gpu_lib.FP32, domain_size=256, value_scale=3.0)
+    Bs = {2: workloads.ffm_matrix(64, 3.0, seed=4), 0: workloads.pe_matrix(6), 1: workloads.pe_matrix(6)}
+    for k, (W_, H_, m_, c_) in nets.items():
+        m.set_params(k, workloads.init_params(2 * m_, W_, H_, c_, seed=40 + k))
+        m.set_encoding(k, Bs[k])
+    m.fit(tr, steps=150, batch=4096, nets_mask=sum(1 << k for k in nets), seed=1, lr=3e-3)
+    pred = m.decode_topology(tr)
+    ex = pred.export()
+    g_ijk, g_val = _tree_voxels(ex)
+
+    def net(k):
+        W_, H_, m_, c_ = nets[k]
+        return (m.get_params(k).astype(np.float64), mlp.layer_shapes(2 * m_, W_, H_, c_), Bs[k].astype(np.float64))
+    o = F.decode_topology(ot, (0, 0, 0), 256, T.SDF, 3.0, 3.0, net(2), net(0), net(1) if with_l0 else None)
+    # leaves: differences only at near-tie level-1 slots
+    lg = F.decode_l1(*net(2), ot, (0, 0, 0), 256)
+    srt = np.sort(lg, axis=1)
+    tie = (srt[:, -1] - srt[:, -2]) <= 1e-4
+    kg, ko = F._voxel_keys(ex["leaf_origin"]), F._voxel_keys(o["leaf_origin"])
+    diff = np.setxor1d(kg, ko)
+    slot_o = F._voxel_keys(ot["l1_origin"][np.arange(len(lg)) >> 12] + T.n1_to_offset(np.arange(len(lg)) & 4095))
+    assert np.isin(diff, slot_o[tie]).all(), len(diff)
+    assert len(ex["leaf_origin"]) > 0 and len(g_ijk) > 0
+    # voxels inside leaves both sides predicted: differences only near the threshold
+    both_leaf = np.intersect1d(kg, ko)
+    leaf_of = lambda p: F._voxel_keys(p & ~7)
+    ing, ino = np.isin(leaf_of(g_ijk), both_leaf), np.isin(leaf_of(o["ijk"]), both_leaf)
+    vg, vo = F._voxel_keys(g_ijk[ing]), F._voxel_keys(o["ijk"][ino])
+    dv = np.setxor1d(vg, vo)
+    assert len(dv) <= max(3, 1e-3 * len(vo)), (len(dv), len(vo))
+    # values on the voxels both predicted
+    common, ig, io = np.intersect1d(vg, vo, return_indices=True)
+    d = np.abs(g_val[ing][ig] - o["values"][ino][io])
+    assert d.max() <= 3e-4, d.max()
+    # the topology error report of the library against the oracle's on the same decoded tree
+    rep = gpu_lib.errors_topology(tr, pred)
+    orep = F.errors_topology(ot["ijk"], ot["values"], g_ijk, g_val)
+    for key in ("n_true", "n_pred", "fp", "fn", "n_common"):
+        assert rep[key] == orep[key], key
+    assert abs(rep["max_abs"] - orep["max_abs"]) <= 1e-6 and abs(rep["rms"] - orep["rms"]) <= 1e-9 * max(1, orep["rms"])
+    # the FP8 form decodes the same topology up to its own rounding
+    p8 = m.decode_topology(tr, fp8=True)
+    n8 = p8.info().n_voxels
+    assert abs(n8 - len(g_ijk)) <= 0.05 * len(g_ijk)
+
+
+def test_decode_topology_empty_prediction(gpu_lib, sphere):
+    """A level-1 classifier that predicts no leaf gives an empty decoded tree, and
+    every true voxel counts as a false negative."""
+    tr, ot = sphere
+    m = gpu_lib.Model({2: (64, 4, 64, 3), 0: (64, 3, 18, 1)}, precision=gpu_lib.BF16, domain_size=64, value_scale=3.0)
+    th = workloads.init_params(128, 64, 4, 3, seed=1)
+    th[-3:] = [-100.0, -100.0, 100.0]  # head biases: always "inactive tile"
+    m.set_params(2, th)
+    m.set_encoding(2, workloads.ffm_matrix(64, 3.0, seed=4))
+    m.set_params(0, workloads.init_params(36, 64, 3, 1, seed=2))
+    m.set_encoding(0, workloads.pe_matrix(6))
+    pred = m.decode_topology(tr)
+    i = pred.info()
+    assert (i.n_leaves, i.n_voxels, i.n_l1) == (0, 0, len(ot["l1_origin"]))
+    rep = gpu_lib.errors_topology(tr, pred)
+    assert rep["fn"] == len(ot["values"]) and rep["fp"] == 0 and rep["n_common"] == 0

@@ -178,3 +178,29 @@ def test_errors_l1_counts(sphere):
     c[other[:5]] = 0          # 5 false positives
     c[other[5:7]] = 1         # 2 plain mismatches
     assert F.errors_l1(tr, c) == dict(n_slots=n, fp=5, fn=3, mismatch=10)
+
+
+def test_topology_from_true_decisions_is_the_tree(sphere):
+    """Rebuilding the lower levels from the true classes, masks and values gives
+    back the tree exactly; planted voxel mistakes are counted exactly."""
+    tr = sphere
+    n = 4096 * len(tr["l1_origin"])
+    _, truth = F.net_inputs(tr, "l1", np.arange(n), (0, 0, 0), 64, T.SDF, 3.0)
+    keys = set(map(tuple, tr["ijk"].tolist()))
+    lut = {k: v for k, v in zip(map(tuple, tr["ijk"].tolist()), tr["values"])}
+    active = lambda p: np.array([tuple(q) in keys for q in p.tolist()])
+    values = lambda p, a: np.array([lut[tuple(q)] for q in p[a].tolist()])
+    pred = F.topology_from_decisions(tr, truth, active, values)
+    assert np.array_equal(pred["leaf_origin"], tr["leaf_origin"])
+    assert np.array_equal(pred["ijk"], tr["ijk"]) and np.array_equal(pred["values"], tr["values"])
+    rep = F.errors_topology(tr["ijk"], tr["values"], pred["ijk"], pred["values"])
+    assert rep == dict(n_true=len(tr["values"]), n_pred=len(tr["values"]), fp=0, fn=0, n_common=len(tr["values"]),
+                       max_abs=0.0, rms=0.0)
+    # drop 5 voxels, add 3 outside the band, perturb one value by 0.5
+    ijk = np.concatenate([pred["ijk"][5:], [[0, 0, 0], [0, 0, 1], [1, 0, 0]]])
+    val = np.concatenate([pred["values"][5:], [9.0, 9.0, 9.0]])
+    val[0] += 0.5
+    rep = F.errors_topology(tr["ijk"], tr["values"], ijk, val)
+    N = len(tr["values"])
+    assert (rep["n_pred"], rep["fp"], rep["fn"], rep["n_common"]) == (N - 2, 3, 5, N - 5)
+    assert rep["max_abs"] == 0.5 and np.isclose(rep["rms"], np.sqrt(0.25 / (N - 5)))
