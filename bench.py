@@ -62,6 +62,8 @@ def main():
     ap.add_argument("--skip-cloud", action="store_true")
     ap.add_argument("--seq-frames", type=int, default=16)
     ap.add_argument("--seq-cap", type=int, default=2000)
+    ap.add_argument("--seq-full-width", action="store_true",
+                    help="sequence leg with the wet region at full width in every frame (no growth)")
     ap.add_argument("--train-groups", type=int, default=0,
                     help="work-groups per network; 0 runs the autotuner (profiling runs pin it)")
     args = ap.parse_args()
@@ -237,7 +239,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.skip_sequence:
         print("sequence leg ...", file=sys.stderr, flush=True)
-        out["sequence"] = sequence_leg(args.seq_frames, args.seq_cap, tuned_g)
+        out["sequence"] = sequence_leg(args.seq_frames, args.seq_cap, tuned_g, args.seq_full_width)
         torch.cuda.empty_cache()
     if not args.skip_cloud:
         print("cloud leg ...", file=sys.stderr, flush=True)
@@ -259,7 +261,7 @@ def measured_traffic():
     return rec["traffic_bytes_per_launch"]
 
 
-def sequence_leg(n_frames, cap, tuned_g):
+def sequence_leg(n_frames, cap, tuned_g, full_width=False):
     """Warm-started fit of an animated sequence: frame 0 cold (2000 steps, lr 1e-3)
     then refit at 1e-4, later frames warm-started at 1e-4 until the batch loss is
     below frame 0's final loss (at most `cap` steps); then the last frame fitted
@@ -272,7 +274,7 @@ def sequence_leg(n_frames, cap, tuned_g):
     t = time.perf_counter()
     trees, counts = [], []
     for f in range(n_frames):
-        g = workloads.water_frame(f, n_frames=n_frames, device="cuda")
+        g = workloads.water_frame(f, n_frames=n_frames, device="cuda", **({"wet0": 1024.0} if full_width else {}))
         trees.append(nvdb.Tree(g, (0, 0, 0), nvdb.SDF, BAND))
         counts.append(int(trees[-1].info().n_voxels))
         del g
@@ -316,8 +318,9 @@ def sequence_leg(n_frames, cap, tuned_g):
     v, mk = mdl.decode(trees[last])
     e = nvdb.errors(trees[last], v, mk)
     total_steps = sum(steps)
-    return {"workload": "advected noisy water surface 1024x256x1024, %d frames, band +-3; regressor + level-0 "
-                        "classifier 4x128, FFM m=64 sigma=10, BF16, 2^18 samples per network per step" % n_frames,
+    return {"workload": "advected noisy water surface 1024x256x1024, %d frames, band +-3, wet region %s; regressor + "
+                        "level-0 classifier 4x128, FFM m=64 sigma=10, BF16, 2^18 samples per network per step"
+                        % (n_frames, "at full width" if full_width else "growing from x < 288 to full width"),
             "frame_voxels_min_max": [min(counts), max(counts)], "frames_generated_s": gen_s,
             "cold": {"steps": 2000, "lr": 1e-3}, "warm": {"cap": cap, "lr": 1e-4},
             "sequence_s": seq_s, "steps_total": total_steps,

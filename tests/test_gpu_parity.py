@@ -673,3 +673,23 @@ def test_decode_topology_empty_prediction(gpu_lib, sphere):
     assert (i.n_leaves, i.n_voxels, i.n_l1) == (0, 0, len(ot["l1_origin"]))
     rep = gpu_lib.errors_topology(tr, pred)
     assert rep["fn"] == len(ot["values"]) and rep["fp"] == 0 and rep["n_common"] == 0
+
+
+def test_new_entry_points_reject_bad_arguments(gpu_lib, sphere):
+    tr, _ = sphere
+    m = gpu_lib.Model({0: (64, 3, 18, 1)}, precision=gpu_lib.BF16, domain_size=64, value_scale=3.0)
+    with pytest.raises(gpu_lib.NvdbError) as e:      # parameters not set
+        m.autotune(tr, nets_mask=1, batch=1024, reps=1)
+    assert e.value.code == gpu_lib.E_STATE
+    m.set_params(0, workloads.init_params(36, 64, 3, 1, seed=0))
+    m.set_encoding(0, workloads.pe_matrix(6))
+    for bad in (dict(batch=0, reps=1), dict(batch=1024, reps=0)):
+        with pytest.raises(gpu_lib.NvdbError) as e:
+            m.autotune(tr, nets_mask=1, **bad)
+        assert e.value.code == gpu_lib.E_INVALID
+    with pytest.raises(gpu_lib.NvdbError) as e:      # no level-1 classifier in the model
+        m.decode_topology(tr)
+    assert e.value.code == gpu_lib.E_INVALID
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        m.set_train_groups(513)
+    assert e.value.code == gpu_lib.E_INVALID
