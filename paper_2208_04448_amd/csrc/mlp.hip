@@ -334,8 +334,11 @@ __device__ __forceinline__ LaneK lane_consts() {
 // A fragment of the forward product from LDS rows: output block ob (32 rows),
 // k-step kk of input block t.  Elements [c0, c0+4) and [c0+8, c0+12) of row
 // 32 ob + i, c0 = 32t + 16kk + 4h.
-__device__ __forceinline__ bf16x8 frag_fwd(const char* rows, const LaneK& K, int ob, int t, int kk) {
-  const char* base = rows + ob * 32 * 256;
+// Rows of consecutive 32-row blocks lie `bstride` bytes apart (8192, or more where a
+// block is padded so that the same lane's reads of two blocks do not share banks).
+__device__ __forceinline__ bf16x8 frag_fwd(const char* rows, const LaneK& K, int ob, int t, int kk,
+                                           int bstride = 32 * 256) {
+  const char* base = rows + ob * bstride;
   const uint32_t o0 = ((uint32_t)(8 * t + 4 * kk) << 3) ^ K.fwd;
   const uint32_t o1 = ((uint32_t)(8 * t + 4 * kk + 2) << 3) ^ K.fwd;
   u32x2 a = *(const u32x2*)(base + o0);
@@ -401,10 +404,11 @@ struct WFwd {
   const float* gcol;       // fp32: this layer transposed [Win][W] in HBM
   bool global;             // bf16: read the fragments from HBM instead of LDS
   const LaneK* K;
+  int bstride = 32 * 256;  // bytes between 32-row blocks of the LDS copy
   __device__ __forceinline__ typename PR<PREC>::Frag operator()(int ob, int t, int kk) const {
     if constexpr (PREC == NVDB_BF16) {
       if (global) return __builtin_bit_cast(bf16x8, gfrag[((ob * NIBL + t) * 2 + kk) * 64 + 32 * K->h + K->fl]);
-      return frag_fwd(lds, *K, ob, t, kk);
+      return frag_fwd(lds, *K, ob, t, kk, bstride);
     } else {
       return gcol[(size_t)sfeat(t, kk, K->h) * W + 32 * ob + K->fl];
     }
@@ -993,7 +997,10 @@ struct InferCfg {
   static constexpr int NT = (PREC == NVDB_BF16) ? NVDB_INFER_NT : 1;  // 32-sample tiles per wave sharing each weight fragment
   static constexpr int WAVES = NVDB_INFER_WAVES;          // waves per work-group (one LDS copy of the weights)
   static constexpr bool GLOBAL = (PREC == NVDB_BF16) && NVDB_INFER_GLOBAL != 0;  // fragments from HBM, no LDS copy
-  static constexpr int WL_BYTES = (PREC == NVDB_BF16 && !GLOBAL) ? H * W * 256 : 0;
+  // Each 32-row block of the weight copy is followed by 64 pad bytes: a lane's reads of
+  // two blocks 8192 bytes apart would hit the same banks when fetched together.
+  static constexpr int BSTRIDE = 32 * 256 + 64;
+  static constexpr int WL_BYTES = (PREC == NVDB_BF16 && !GLOBAL) ? H * (W / 32) * BSTRIDE : 0;
   static constexpr int SMALL_FLOATS = H * W + C * W + 4 + 4 * (KP / 2);
   static constexpr int LDS_BYTES = WL_BYTES + SMALL_FLOATS * 4;
 };
@@ -1016,10 +1023,12 @@ __global__ void __launch_bounds__(64 * NVDB_INFER_WAVES, 1)
   float* sm_whead0 = sm_bias0 + H * W;
   float* sm_bhead0 = sm_whead0 + C * W;
   float* sm_benc0 = sm_bhead0 + 4;
-  if constexpr (BF) {
+  if constexpr (BF && !CF::GLOBAL) {
     const u32x4* src = (const u32x4*)nv.wrow;
-    u32x4* dst = (u32x4*)wl0;
-    for (int i = threadIdx.x; i < CF::WL_BYTES / 16; i += blockDim.x) dst[i] = src[i];
+    for (int i = threadIdx.x; i < H * W * 16; i += blockDim.x) {  // 16-byte pieces of the 256-byte rows
+      const int row = i >> 4, blk = row >> 5;
+      *(u32x4*)(wl0 + blk * CF::BSTRIDE + (row & 31) * 256 + (i & 15) * 16) = src[i];
+    }
   }
   for (int i = threadIdx.x; i < H * W; i += blockDim.x) sm_bias0[i] = nv.bias[i];
   for (int i = threadIdx.x; i < C * W; i += blockDim.x) sm_whead0[i] = nv.whead[i];
@@ -1052,10 +1061,10 @@ __global__ void __launch_bounds__(64 * NVDB_INFER_WAVES, 1)
     static_for<0, H>([&](auto lc) {
       constexpr int l = decltype(lc)::value;
       constexpr int NIBl = (l == 0) ? NIB0 : NB;
-      WFwd<PREC, W, NIBl> wf{wl + (size_t)l * W * 256,
+      WFwd<PREC, W, NIBl> wf{wl + (size_t)l * (W / 32) * CF::BSTRIDE,
                              (const u32x4*)((const __bf16*)nv.wfrag + (l == 0 ? 0 : (size_t)W * KP + (size_t)(l - 1) * W * W)) + z,
                              (const float*)nv.wcol + z + (l == 0 ? 0 : (size_t)KP * W + (size_t)(l - 1) * W * W), CF::GLOBAL,
-                             &K};
+                             &K, CF::BSTRIDE};
       uint32_t Bn[NT][NB][SR];
 #pragma unroll
       for (int ob = 0; ob < NB; ++ob) {
