@@ -308,6 +308,52 @@ __device__ __forceinline__ void encode_S(const Smp& s, const float* benc, int m,
   }
 }
 
+// Phases u_f = b_f . x of the 2m = 32 NIB fast path on the FP32 matrix cores:
+// 32x32x2 products with A = (b_f components) and B = (x components) put u for
+// frequency 32 tb + 8 (r / 4) + 4 h + r mod 4 of the lane's sample in register r,
+// which is the S layout of the cos block tb and the sin block tb + NIB/2.
+// The k index is the coordinate component: lane half h carries components h and
+// 2 + h (the fourth component of every row of B is zero).
+template <int NIB>
+struct PhaseA {
+  float a[NIB / 2][2];
+  __device__ __forceinline__ void load(const float* benc) {
+    const int l = lane_id(), h = l >> 5, fl = l & 31;
+#pragma unroll
+    for (int tb = 0; tb < NIB / 2; ++tb) {
+      a[tb][0] = benc[4 * (32 * tb + fl) + h];
+      a[tb][1] = benc[4 * (32 * tb + fl) + 2 + h];
+    }
+  }
+};
+template <int NIB>
+__device__ __forceinline__ void phases_mfma(const PhaseA<NIB>& A, const Smp& s, floatx16 (&u)[NIB / 2]) {
+  const int h = lane_id() >> 5;
+  const float b0 = h ? s.x[1] : s.x[0], b1 = h ? 0.f : s.x[2];
+#pragma unroll
+  for (int tb = 0; tb < NIB / 2; ++tb) {
+    u[tb] = __builtin_amdgcn_mfma_f32_32x32x2f32(A.a[tb][0], b0, floatx16{}, 0, 0, 0);
+    u[tb] = __builtin_amdgcn_mfma_f32_32x32x2f32(A.a[tb][1], b1, u[tb], 0, 0, 0);
+  }
+}
+// gamma(x) of the fast path from MFMA phases, BF16 S-layout blocks.
+template <int NIB>
+__device__ __forceinline__ void encode_bf16_mfma(const PhaseA<NIB>& A, const Smp& s, uint32_t (&X)[NIB][8]) {
+  floatx16 u[NIB / 2];
+  phases_mfma<NIB>(A, s, u);
+#pragma unroll
+  for (int tb = 0; tb < NIB / 2; ++tb) {
+    floatx16 vc, vs;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      vc[r] = __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(u[tb][r] + 0.25f));
+      vs[r] = __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(u[tb][r]));
+    }
+    PR<NVDB_BF16>::store(vc, X[tb]);
+    PR<NVDB_BF16>::store(vs, X[tb + NIB / 2]);
+  }
+}
+
 // ------------------------------------------------------------ LDS addressing
 // bf16 rows (weights and exchanged activations) are 256 bytes long; the 8-byte
 // chunk c of row r is stored at chunk c ^ swz(r).  Every access pattern below
@@ -642,6 +688,9 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
   const int64_t n_iter = (sp.n + 127) / 128;
   float* partial = TN.partial + (size_t)blockIdx.x * P_;
 
+  PhaseA<NIB0> pa;
+  const bool fastenc = BF && 2 * nv.nfreq == 32 * NIB0;
+  if (fastenc) pa.load(sm_benc0);
   floatx4 xt_next = floatx4{0.f, 0.f, 0.f, 0.f};
   {
     const int64_t j0 = (int64_t)blockIdx.x * 128 + wave * 32 + (lane_id() & 31);
@@ -676,7 +725,12 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
     uint32_t Hs[H][NB][SR];  // Hs[l] = a_{l+1} (S layout), l = 0..H-1
     {
       uint32_t X0[NIB0][SR];
-      encode_S<PREC, NIB0>(smp, sm_benc, nv.nfreq, X0);
+      if constexpr (BF) {
+        if (fastenc) encode_bf16_mfma<NIB0>(pa, smp, X0);
+        else encode_S<PREC, NIB0>(smp, sm_benc, nv.nfreq, X0);
+      } else {
+        encode_S<PREC, NIB0>(smp, sm_benc, nv.nfreq, X0);
+      }
       WFwd<PREC, W, NIB0> wf0{nullptr, (const u32x4*)nv.wfrag + z, (const float*)nv.wcol + z, true, &K};
 #pragma unroll
       for (int ob = 0; ob < NB; ob += 2) {
@@ -748,7 +802,14 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
       constexpr bool HEAD = (l == H - 1);
       // input activations a_l of layer l as rows (gamma recomputed for l = 0)
       uint32_t X0[NIB0][SR];
-      if constexpr (l == 0) encode_S<PREC, NIB0>(smp, sm_benc, nv.nfreq, X0);
+      if constexpr (l == 0) {
+        if constexpr (BF) {
+          if (fastenc) encode_bf16_mfma<NIB0>(pa, smp, X0);
+          else encode_S<PREC, NIB0>(smp, sm_benc, nv.nfreq, X0);
+        } else {
+          encode_S<PREC, NIB0>(smp, sm_benc, nv.nfreq, X0);
+        }
+      }
       // layers folded into the partial row: fetch the running sums now so that the
       // loads complete under the exchange below
       constexpr bool PREFETCH = !CF::reg_layer(l) && (BF || l == 0);  // FP32: registers allow layer 0 only
@@ -1036,6 +1097,9 @@ __global__ void __launch_bounds__(64 * NVDB_INFER_WAVES, 1)
   for (int i = threadIdx.x; i < 4 * (KP / 2); i += blockDim.x) sm_benc0[i] = nv.benc[i];
   __syncthreads();
 
+  PhaseA<NIB0> pa;
+  const bool fastenc = BF && 2 * nv.nfreq == 32 * NIB0;
+  if (fastenc) pa.load(sm_benc0);
   const int64_t per_wave = 32 * NT;
   const int64_t stride = (int64_t)gridDim.x * CF::WAVES * per_wave;
   for (int64_t base = ((int64_t)blockIdx.x * CF::WAVES + wave) * per_wave; base < sp.n; base += stride) {
@@ -1052,7 +1116,12 @@ __global__ void __launch_bounds__(64 * NVDB_INFER_WAVES, 1)
     for (int u = 0; u < NT; ++u) {
       const Smp smp = fetch_sample(sp, I.tree, base + 32 * u + fl);
       uint32_t X0[NIB0][SR];
-      encode_S<PREC, NIB0>(smp, sm_benc, nv.nfreq, X0);
+      if constexpr (BF) {
+        if (fastenc) encode_bf16_mfma<NIB0>(pa, smp, X0);
+        else encode_S<PREC, NIB0>(smp, sm_benc, nv.nfreq, X0);
+      } else {
+        encode_S<PREC, NIB0>(smp, sm_benc, nv.nfreq, X0);
+      }
 #pragma unroll
       for (int t = 0; t < NIB0; ++t)
 #pragma unroll
@@ -1325,6 +1394,9 @@ __global__ void __launch_bounds__(64 * NVDB_INFER8_WAVES, NVDB_INFER8_WGS)
   if (threadIdx.x < H) sm_winv0[threadIdx.x] = I.w8inv[threadIdx.x];
   __syncthreads();
 
+  PhaseA<NIB0> pa;
+  const bool fastenc = 2 * nv.nfreq == 32 * NIB0;
+  if (fastenc) pa.load(sm_benc0);
   const int64_t per_wave = 32 * NT;
   const int64_t stride = (int64_t)gridDim.x * CF::WAVES * per_wave;
   for (int64_t base = ((int64_t)blockIdx.x * CF::WAVES + wave) * per_wave; base < sp.n; base += stride) {
@@ -1345,7 +1417,19 @@ __global__ void __launch_bounds__(64 * NVDB_INFER8_WAVES, NVDB_INFER8_WGS)
       zmax[u] = 0.f;
       const Smp smp = fetch_sample(sp, I.tree, base + 32 * u + fl);
       float X0[NIB0][16];
-      encode_f32<NIB0>(smp, sm_benc, nv.nfreq, X0);
+      if (fastenc) {
+        floatx16 ph[NIB0 / 2];
+        phases_mfma<NIB0>(pa, smp, ph);
+#pragma unroll
+        for (int tb = 0; tb < NIB0 / 2; ++tb)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            X0[tb][r] = __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(ph[tb][r] + 0.25f));
+            X0[tb + NIB0 / 2][r] = __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(ph[tb][r]));
+          }
+      } else {
+        encode_f32<NIB0>(smp, sm_benc, nv.nfreq, X0);
+      }
 #pragma unroll
       for (int t = 0; t < NIB0; ++t)
 #pragma unroll
