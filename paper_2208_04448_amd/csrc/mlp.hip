@@ -515,7 +515,7 @@ __device__ __forceinline__ void layer_block2(const AF& af, int ob, const uint32_
                                              floatx16& acc0, floatx16& acc1) {
   using P = PR<PREC>;
   constexpr int NS = NIB * P::KS;
-  constexpr int PF = (PREC == NVDB_BF16) ? (NS < 4 ? NS : 4) : 1;
+  constexpr int PF = (PREC == NVDB_BF16) ? (NS < 8 ? NS : 8) : 1;
   typename P::Frag fa[PF], fb[PF];
 #pragma unroll
   for (int s = 0; s < PF; ++s) {
@@ -606,7 +606,9 @@ struct TrainCfg {
   // BF16: where the weight fragments of layers 1..H-1 come from (HBM/L2 or the LDS copy)
   static constexpr bool FWD_GLOBAL = NVDB_TRAIN_FWD_GLOBAL != 0;
   static constexpr bool DX_GLOBAL = NVDB_TRAIN_DX_GLOBAL != 0;
-  static constexpr int DWREG_FROM = (W >= 128) ? 2 : 0;
+  // (measured on the 4x128 network: keeping only the top layer's dW resident frees the
+  // registers whose spills cost more than folding one more layer per tile)
+  static constexpr int DWREG_FROM = (W >= 128) ? 3 : 0;
   static constexpr bool reg_layer(int l) { return DWREG && l >= DWREG_FROM; }
   static constexpr bool any_rmw = !DWREG || DWREG_FROM > 0;
   static constexpr int RB = (PREC == NVDB_BF16) ? 0 : (KP > W ? KP : W) + 4;  // fp32 row pitch (floats)
@@ -812,7 +814,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
       }
       // layers folded into the partial row: fetch the running sums now so that the
       // loads complete under the exchange below
-      constexpr bool PREFETCH = !CF::reg_layer(l) && (BF || l == 0);  // FP32: registers allow layer 0 only
+      constexpr bool PREFETCH = !CF::reg_layer(l) && (BF ? l <= 1 : l == 0);  // where registers allow
       float prev[PREFETCH ? OBW : 1][PREFETCH ? CF::IBWMAX : 1][16];
       if constexpr (PREFETCH) {
         if (!first) {
