@@ -82,6 +82,20 @@ typedef struct {
  * E_NOMEM / E_DEVICE from HIP.  The call synchronises `stream`. */
 nvdb_status nvdb_tree_build_dense(const float* grid_dev, const int32_t dims[3], const int32_t origin[3],
                                   const nvdb_active_rule* rule, void* stream, nvdb_tree** out);
+/* Build the same tree from a sparse voxel list resident in HBM: ijk_dev
+ * int32[n][3] index-space coordinates, values_dev float32[n], in any order.
+ * The active rule keeps the voxels it accepts (as for a dense grid); the tree
+ * arrays are those nvdb_tree_build_dense produces for the same active set.
+ * grid_origin / grid_dims of the tree are the bounding box of all n input
+ * voxels (zero for n = 0).  Coordinates must lie in [-2^20, 2^20) (level-2
+ * node index in 9 signed bits: the voxels are put in canonical order by a
+ * radix sort of a 63-bit key).
+ * Errors: E_INVALID for n outside [0, 2^31), null arrays with n > 0, NaN/Inf
+ * values, coordinates out of range, duplicate coordinates (active or not),
+ * more than 2^23 leaves, or an unknown rule; E_NOMEM / E_DEVICE from HIP.
+ * Synchronises `stream`. */
+nvdb_status nvdb_tree_build_sparse(const int32_t* ijk_dev, const float* values_dev, int64_t n,
+                                   const nvdb_active_rule* rule, void* stream, nvdb_tree** out);
 /* Counts, bounding grid and byte accounting of a tree. */
 nvdb_status nvdb_tree_get_info(const nvdb_tree* tree, nvdb_tree_info* info);
 /* Copy the canonical arrays to host buffers (any may be NULL):
@@ -90,6 +104,11 @@ nvdb_status nvdb_tree_get_info(const nvdb_tree* tree, nvdb_tree_info* info);
  * ascending), l1_origin int32[n_l1][3], l1_child uint64[n_l1][64]. */
 nvdb_status nvdb_tree_export(const nvdb_tree* tree, int32_t* leaf_origin, uint64_t* leaf_mask,
                              uint32_t* leaf_off, float* values, int32_t* l1_origin, uint64_t* l1_child);
+/* Upper levels (Sec. 3.1): l2_origin int32[n_l2][3] (the root's keys, in
+ * canonical order) and l2_child uint64[n_l2][512], bit n2 set for every
+ * level-1 node of the level-2 node (n2 = ((x>>7)&31)<<10|((y>>7)&31)<<5|((z>>7)&31)
+ * of the level-1 origin).  Either may be NULL. */
+nvdb_status nvdb_tree_export_l2(const nvdb_tree* tree, int32_t* l2_origin, uint64_t* l2_child);
 void nvdb_tree_free(nvdb_tree* tree);
 
 /* ----------------------------------------------------------------- models */

@@ -49,6 +49,21 @@ def active_set_dense(v, origin, kind, band_or_threshold):
     return ijk.astype(np.int32), v[idx].astype(np.float64)
 
 
+def active_set_sparse(ijk, v, kind, band_or_threshold):
+    """The same active rule applied to a sparse voxel list: keeps the rows of
+    (ijk, v) that the rule accepts, in the given order.  The comparison is made
+    in the precision of v."""
+    ijk = np.asarray(ijk, dtype=np.int32).reshape(-1, 3)
+    v = np.asarray(v).reshape(-1)
+    if kind == SDF:
+        act = np.abs(v) <= v.dtype.type(band_or_threshold)
+    elif kind == FOG:
+        act = v > v.dtype.type(band_or_threshold)
+    else:
+        raise ValueError("kind must be SDF or FOG")
+    return ijk[act], v[act].astype(np.float64)
+
+
 def decompose(ijk):
     """Per-voxel decomposition into leaf/L1/L2 origins and slot indices."""
     p = np.asarray(ijk, dtype=np.int32)

@@ -146,6 +146,16 @@ nvdb_status nvdb_tree_build_dense(const float* grid_dev, const int32_t dims[3], 
   });
 }
 
+nvdb_status nvdb_tree_build_sparse(const int32_t* ijk_dev, const float* values_dev, int64_t n,
+                                   const nvdb_active_rule* rule, void* stream, nvdb_tree** out) {
+  return guarded([&] {
+    NVDB_REQUIRE(out && rule, NVDB_E_INVALID, "null argument");
+    *out = nullptr;
+    Tree* t = build_tree_sparse(ijk_dev, values_dev, n, *rule, (hipStream_t)stream);
+    *out = static_cast<nvdb_tree*>(t);
+  });
+}
+
 nvdb_status nvdb_tree_get_info(const nvdb_tree* t, nvdb_tree_info* info) {
   return guarded([&] {
     NVDB_REQUIRE(t && info, NVDB_E_INVALID, "null argument");
@@ -194,6 +204,30 @@ nvdb_status nvdb_tree_export(const nvdb_tree* t, int32_t* leaf_origin, uint64_t*
     }
     if (l1_child && t->n_l1)
       NVDB_HIP(hipMemcpy(l1_child, t->l1_child.p, t->n_l1 * 64 * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  });
+}
+
+nvdb_status nvdb_tree_export_l2(const nvdb_tree* t, int32_t* l2_origin, uint64_t* l2_child) {
+  return guarded([&] {
+    NVDB_REQUIRE(t, NVDB_E_INVALID, "null tree");
+    if (l2_origin && t->n_l2) std::memcpy(l2_origin, t->l2_origin.data(), t->n_l2 * 3 * sizeof(int32_t));
+    if (l2_child && t->n_l2) {
+      std::memset(l2_child, 0, t->n_l2 * 512 * sizeof(uint64_t));
+      std::vector<int4> o(t->n_l1);
+      if (t->n_l1) NVDB_HIP(hipMemcpy(o.data(), t->l1_o.p, t->n_l1 * sizeof(int4), hipMemcpyDeviceToHost));
+      int64_t node = -1;
+      int32_t cur[3] = {0, 0, 0};
+      for (const int4& q : o) {  // level-1 nodes are grouped by level-2 node, in canonical order
+        const int32_t l2[3] = {q.x & ~4095, q.y & ~4095, q.z & ~4095};
+        if (node < 0 || l2[0] != cur[0] || l2[1] != cur[1] || l2[2] != cur[2]) {
+          ++node;
+          std::memcpy(cur, l2, sizeof(cur));
+        }
+        NVDB_REQUIRE(node < t->n_l2, NVDB_E_STATE, "level-1 nodes out of canonical order");
+        const int n2 = (((q.x >> 7) & 31) << 10) | (((q.y >> 7) & 31) << 5) | ((q.z >> 7) & 31);
+        l2_child[node * 512 + (n2 >> 6)] |= 1ull << (n2 & 63);
+      }
+    }
   });
 }
 

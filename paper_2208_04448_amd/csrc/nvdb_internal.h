@@ -259,6 +259,8 @@ void launch_fill(float* p, int64_t n, float v, hipStream_t st);
 // tree.hip
 Tree* build_tree_dense(const float* grid, const int32_t dims[3], const int32_t origin[3], const nvdb_active_rule& rule,
                        hipStream_t st);
+// sparse.hip
+Tree* build_tree_sparse(const int32_t* ijk, const float* v, int64_t n, const nvdb_active_rule& rule, hipStream_t st);
 void error_report(const Tree& t, const float* values, const uint64_t* pred_mask, nvdb_error_report* rep,
                   hipStream_t st);
 void error_report_l1(const Tree& t, const uint8_t* classes, nvdb_l1_report* rep, hipStream_t st);

@@ -82,7 +82,9 @@ _SIGS = {
     "nvdb_abi_version": (C.c_int32, []),
     "nvdb_tree_build_dense": (C.c_int32, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(ActiveRule), _P,
                                           C.POINTER(_P)]),
+    "nvdb_tree_build_sparse": (C.c_int32, [_P, _P, C.c_int64, C.POINTER(ActiveRule), _P, C.POINTER(_P)]),
     "nvdb_tree_get_info": (C.c_int32, [_P, C.POINTER(TreeInfo)]),
+    "nvdb_tree_export_l2": (C.c_int32, [_P, _P, _P]),
     "nvdb_tree_export": (C.c_int32, [_P, _P, _P, _P, _P, _P, _P]),
     "nvdb_tree_free": (None, [_P]),
     "nvdb_model_create": (C.c_int32, [C.POINTER(ModelDesc), C.POINTER(_P)]),
@@ -150,6 +152,30 @@ class Tree:
                                           C.byref(h)))
         self.h = h
         self.kind = kind
+
+    @classmethod
+    def from_sparse(cls, ijk, values, kind=SDF, band_or_threshold=3.0):
+        """Tree of a sparse voxel list: ijk int32 [n, 3] and values float32 [n], device tensors."""
+        import torch
+        assert ijk.is_cuda and values.is_cuda and ijk.dtype == torch.int32 and values.dtype == torch.float32
+        ijk = ijk.contiguous().reshape(-1, 3)
+        values = values.contiguous().reshape(-1)
+        assert ijk.shape[0] == values.shape[0]
+        h = C.c_void_p()
+        rule = ActiveRule(kind, band_or_threshold)
+        _check(_lib.nvdb_tree_build_sparse(_ptr(ijk), _ptr(values), values.numel(), C.byref(rule), _stream(),
+                                           C.byref(h)))
+        t = cls.__new__(cls)
+        t.h = h
+        t.kind = kind
+        return t
+
+    def export_l2(self):
+        """Level-2 origins int32 [n_l2, 3] and child masks uint64 [n_l2, 512]."""
+        n = self.info().n_l2
+        o, c = np.zeros((n, 3), np.int32), np.zeros((n, 512), np.uint64)
+        _check(_lib.nvdb_tree_export_l2(self.h, o.ctypes.data_as(C.c_void_p), c.ctypes.data_as(C.c_void_p)))
+        return o, c
 
     def info(self):
         i = TreeInfo()

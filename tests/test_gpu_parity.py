@@ -88,9 +88,104 @@ def test_tree_bit_exact(gpu_lib, name, make, origin, kind, thr):
     assert np.array_equal(ex["values"].astype(np.float64), ot["values"])
     assert np.array_equal(ex["l1_origin"], ot["l1_origin"])
     assert np.array_equal(ex["l1_child"], ot["l1_child"])
+    l2o, l2c = tr.export_l2()
+    assert np.array_equal(l2o, ot["l2_origin"]) and np.array_equal(l2c, ot["l2_child"])
     b = T.explicit_bytes(info.n_leaves, info.n_l1, info.n_l2)
     assert (info.bytes_l2, info.bytes_l1, info.bytes_leaf_masks, info.bytes_voxels) == (
         b["l2"], b["l1"], b["leaf_mask"], b["voxels"])
+
+
+def _tree_arrays(tr):
+    ex = tr.export()
+    ex["l2_origin"], ex["l2_child"] = tr.export_l2()
+    i = tr.info()
+    ex["info"] = (i.n_voxels, i.n_leaves, i.n_l1, i.n_l2, tuple(i.grid_origin), tuple(i.grid_dims), i.bytes_l2,
+                  i.bytes_l1, i.bytes_leaf_masks, i.bytes_voxels)
+    return ex
+
+
+def _assert_same_tree(a, b):
+    assert a["info"] == b["info"]
+    for k in ("leaf_origin", "leaf_mask", "leaf_off", "l1_origin", "l1_child", "l2_origin", "l2_child"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(a["values"].view(np.uint32), b["values"].view(np.uint32))
+
+
+def _sparse_case(seed, n, spread, roots):
+    """Distinct random coordinates around a few centres anywhere in [-2^20, 2^20)
+    (several level-2 nodes, negative coordinates), the eight extreme corners of
+    the range, shuffled; values N(0, 2^2)."""
+    rng = np.random.default_rng(seed)
+    centres = rng.integers(-(1 << 20) + spread, (1 << 20) - spread, size=(roots, 3))
+    pts = centres[rng.integers(0, roots, n)] + rng.integers(-spread, spread + 1, size=(n, 3))
+    lo, hi = -(1 << 20), (1 << 20) - 1
+    corners = np.array([[a, b, c] for a in (lo, hi) for b in (lo, hi) for c in (lo, hi)])
+    pts = np.unique(np.concatenate([pts, corners]), axis=0)
+    rng.shuffle(pts)
+    return pts.astype(np.int32), rng.normal(0.0, 2.0, len(pts)).astype(np.float32)
+
+
+SPARSE_CASES = [(0, 1, 3, 1, T.SDF, 1.5), (1, 2000, 12, 1, T.SDF, 1.5), (2, 60000, 200, 3, T.FOG, 0.5),
+                (3, 300000, 4000, 5, T.SDF, 2.0)]
+
+
+@pytest.mark.parametrize("seed,n,spread,roots,kind,thr", SPARSE_CASES)
+def test_tree_sparse_matches_oracle(gpu_lib, seed, n, spread, roots, kind, thr):
+    """Sparse-list build (radix sort of canonical keys) against the oracle build of
+    the same active set, byte for byte, including the level-2 arrays."""
+    pts, vals = _sparse_case(seed, n, spread, roots)
+    tr = gpu_lib.Tree.from_sparse(torch.from_numpy(pts).to(DEV), torch.from_numpy(vals).to(DEV), kind, thr)
+    ex = _tree_arrays(tr)
+    ijk, v = T.active_set_sparse(pts, vals, kind, thr)
+    ot = T.build(ijk, v)
+    assert ex["info"][:4] == (len(ot["values"]), len(ot["leaf_origin"]), len(ot["l1_origin"]), len(ot["l2_origin"]))
+    assert ex["info"][4] == tuple(int(a) for a in pts.min(0))
+    assert ex["info"][5] == tuple(int(a) for a in pts.max(0) - pts.min(0) + 1)
+    assert np.array_equal(ex["leaf_origin"], ot["leaf_origin"])
+    assert np.array_equal(ex["leaf_mask"], ot["leaf_mask"])
+    assert np.array_equal(ex["leaf_off"].astype(np.int64), ot["leaf_off"])
+    assert np.array_equal(ex["values"].astype(np.float64), ot["values"])
+    assert np.array_equal(ex["l1_origin"], ot["l1_origin"]) and np.array_equal(ex["l1_child"], ot["l1_child"])
+    assert np.array_equal(ex["l2_origin"], ot["l2_origin"]) and np.array_equal(ex["l2_child"], ot["l2_child"])
+
+
+@pytest.mark.parametrize("name,make,origin,kind,thr", TREE_CASES, ids=[c[0] for c in TREE_CASES])
+def test_tree_sparse_equals_dense(gpu_lib, name, make, origin, kind, thr):
+    """Every voxel of a dense grid, shuffled, as a sparse list: the same tree as the
+    dense build (the bounding box of the list is the grid)."""
+    grid = make().float()
+    dense = _tree_arrays(gpu_lib.Tree(grid.to(DEV), origin, kind, thr))
+    ijk = np.stack(np.meshgrid(*[np.arange(d) for d in grid.shape], indexing="ij"), -1).reshape(-1, 3)
+    perm = np.random.default_rng(5).permutation(len(ijk))
+    pts = (ijk[perm] + np.asarray(origin)).astype(np.int32)
+    vals = grid.numpy().reshape(-1)[perm]
+    sparse = _tree_arrays(gpu_lib.Tree.from_sparse(torch.from_numpy(pts).to(DEV), torch.from_numpy(vals).to(DEV),
+                                                   kind, thr))
+    _assert_same_tree(sparse, dense)
+
+
+def test_tree_sparse_edge_cases(gpu_lib):
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    empty = gpu_lib.Tree.from_sparse(torch.zeros((0, 3), dtype=torch.int32, device=DEV),
+                                     torch.zeros(0, device=DEV), T.SDF, 3.0)
+    i = empty.info()
+    assert (i.n_voxels, i.n_leaves, i.n_l1, i.n_l2, tuple(i.grid_dims)) == (0, 0, 0, 0, (0, 0, 0))
+    assert empty.export()["leaf_off"].tolist() == [0]
+    pts = np.array([[5, 6, 7], [-9, 4, 4000], [5, 6, 7]], np.int32)
+    for vals in ([0.0, 1.0, 0.5], [0.0, 1.0, 99.0]):  # duplicate active, duplicate inactive
+        with pytest.raises(gpu_lib.NvdbError) as e:
+            gpu_lib.Tree.from_sparse(dev(pts), dev(np.array(vals, np.float32)), T.SDF, 3.0)
+        assert e.value.code == gpu_lib.E_INVALID and "duplicate" in str(e.value)
+    ok = np.array([[5, 6, 7], [-9, 4, 4000]], np.int32)
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        gpu_lib.Tree.from_sparse(dev(ok), dev(np.array([0.0, np.nan], np.float32)), T.SDF, 3.0)
+    assert e.value.code == gpu_lib.E_INVALID
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        gpu_lib.Tree.from_sparse(dev(np.array([[0, 1 << 20, 0]], np.int32)), dev(np.zeros(1, np.float32)), T.SDF, 3.0)
+    assert e.value.code == gpu_lib.E_INVALID
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        gpu_lib.Tree.from_sparse(dev(ok), dev(np.zeros(2, np.float32)), 7, 3.0)
+    assert e.value.code == gpu_lib.E_INVALID
 
 
 def test_tree_rejects_nan(gpu_lib):
@@ -335,6 +430,23 @@ def test_c2_tree_sampled_leaves(gpu_lib, c2):
         assert np.array_equal(ex["values"][a:b].astype(np.float64), ot["values"][a:b])
     assert np.array_equal(ex["l1_child"], ot["l1_child"])
     assert int(ex["leaf_off"][-1]) == info.n_voxels
+
+
+def test_c2_tree_sparse_equals_dense(gpu_lib, c2):
+    """512^3 level set: the voxels within 6 of the surface (twice the band), shuffled,
+    as a sparse list give the dense build's tree with the band-3 rule; the list
+    spans thousands of radix-sort tiles."""
+    grid, tr, _ = c2
+    sel = torch.nonzero(grid.abs() <= 6.0).to(torch.int32)
+    perm = torch.randperm(sel.shape[0], generator=torch.Generator().manual_seed(3)).to(DEV)
+    pts = sel[perm].contiguous()
+    vals = grid[pts[:, 0].long(), pts[:, 1].long(), pts[:, 2].long()].contiguous()
+    sp = gpu_lib.Tree.from_sparse(pts, vals, T.SDF, 3.0)
+    a, b = _tree_arrays(sp), _tree_arrays(tr)
+    assert a["info"][:4] == b["info"][:4] and a["info"][6:] == b["info"][6:]
+    for k in ("leaf_origin", "leaf_mask", "leaf_off", "l1_origin", "l1_child", "l2_origin", "l2_child"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(a["values"].view(np.uint32), b["values"].view(np.uint32))
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])

@@ -144,3 +144,23 @@ def test_byte_accounting_matches_paper():
     total = g["l2_bytes"] + g["nn4_l1_bytes"] + g["nn4_l0_bytes"] + g["nn4_voxel_bytes"]
     assert total == g["nn4_total_bytes"]
     assert round(100.0 * total / g["total_bytes"], 3) == g["nn4_percent"]
+
+
+def test_active_set_sparse_rule_and_order():
+    """Closed interval for level sets, strict threshold for fog; rows kept in input
+    order; on a dense grid listed voxel by voxel it selects what the dense rule
+    selects (brute force over a random grid)."""
+    ijk = np.array([[0, 0, 0], [1, 2, 3], [-5, 7, 9], [4, 4, 4]], np.int32)
+    v = np.array([3.0, -3.0, 3.0001, 0.5], np.float32)
+    a, va = T.active_set_sparse(ijk, v, T.SDF, 3.0)
+    assert a.tolist() == [[0, 0, 0], [1, 2, 3], [4, 4, 4]] and va.tolist() == [3.0, -3.0, 0.5]
+    b, vb = T.active_set_sparse(ijk, v, T.FOG, 3.0)
+    assert b.tolist() == [[-5, 7, 9]]
+    rng = np.random.default_rng(4)
+    grid = rng.normal(0, 2, (6, 5, 7)).astype(np.float32)
+    org = (-3, 10, 4)
+    for kind, thr in ((T.SDF, 1.0), (T.FOG, 0.7)):
+        ref = set(map(tuple, T.active_set_dense(grid, org, kind, thr)[0].tolist()))
+        pts = np.array([[i + org[0], j + org[1], k + org[2]] for i in range(6) for j in range(5) for k in range(7)])
+        got, _ = T.active_set_sparse(pts, grid.reshape(-1), kind, thr)
+        assert set(map(tuple, got.tolist())) == ref
