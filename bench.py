@@ -60,6 +60,7 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-sequence", action="store_true")
     ap.add_argument("--skip-cloud", action="store_true")
+    ap.add_argument("--skip-small", action="store_true")
     ap.add_argument("--seq-frames", type=int, default=16)
     ap.add_argument("--seq-cap", type=int, default=2000)
     ap.add_argument("--seq-full-width", action="store_true",
@@ -266,6 +267,10 @@ def main():
     if not args.skip_cloud:
         print("cloud leg ...", file=sys.stderr, flush=True)
         out["cloud"] = cloud_leg(args.fit_steps, tuned_g)
+        torch.cuda.empty_cache()
+    if not args.skip_small:
+        print("small-network leg ...", file=sys.stderr, flush=True)
+        out["small"] = small_leg()
 
     print(json.dumps(out), flush=True)
 
@@ -436,6 +441,86 @@ def cloud_leg(fit_steps, tuned_g):
                     "l1": {"fp": r18["fp"], "fn": r18["fn"], "mismatch": r18["mismatch"]}}}
 
 
+def small_leg(reps=5):
+    """The 64^3 sphere with the 3x64 PE-6 networks: latency of the one-epoch job
+    (tree build, 11 regressor + 33 level-0 classifier steps of 4096 samples over
+    seeded permutations, full decode, error report), and fwd+bwd throughput at
+    batch 2^22 through the autograd function (forward, then the fused backward
+    that recomputes the activations), median of `reps` after one warm-up."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2208_04448_amd import nvdb
+
+    grid = workloads.sphere_sdf(device="cuda")
+    B = workloads.pe_matrix(6)
+    th0 = {0: workloads.init_params(36, 64, 3, 1, seed=0), 1: workloads.init_params(36, 64, 3, 1, seed=1)}
+    perm = {0: workloads.epoch_permutation(43878, seed=5), 1: workloads.epoch_permutation(512 * 257, seed=6)}
+    idx = {k: torch.from_numpy(perm[k].astype(np.int32)).cuda() for k in (0, 1)}
+    steps = {0: 11, 1: 33}
+    zeros = np.zeros(len(th0[0]), np.float32)
+    res = {"workload": "64^3 sphere SDF (r 24, band +-3, 43,878 voxels, 257 leaves); regressor + level-0 "
+                       "classifier 3x64, PE-6 (K 36)"}
+    for name, prec in (("fp32", nvdb.FP32), ("bf16", nvdb.BF16)):
+        model = nvdb.Model({0: (64, 3, 18, 1), 1: (64, 3, 18, 1)}, precision=prec, domain_size=64, value_scale=BAND)
+        for k in (0, 1):
+            model.set_encoding(k, B)
+
+        def one_epoch():
+            tree = nvdb.Tree(grid, (0, 0, 0), nvdb.SDF, BAND)
+            for k in (0, 1):
+                model.set_params(k, th0[k])
+                model.set_opt_state(k, zeros, zeros, 0)
+                model.fit(tree, steps=steps[k], batch=4096, nets_mask=1 << k, idx={k: idx[k]}, return_losses=False)
+            v, m = model.decode(tree)
+            return nvdb.errors(tree, v, m)
+
+        one_epoch()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rep = one_epoch()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        # C4: batch 2^22 i.i.d. voxel samples, MSE against the targets
+        n = 1 << 22
+        tree = nvdb.Tree(grid, (0, 0, 0), nvdb.SDF, BAND)
+        ii = nvdb.sample_indices(0, 0, 0, 43878, n).long()
+        ex = tree.export()
+        offs = np.repeat(np.arange(len(ex["leaf_origin"])), np.diff(ex["leaf_off"].astype(np.int64)))
+        mask_bits = np.unpackbits(ex["leaf_mask"].view(np.uint8), bitorder="little").reshape(-1, 512)
+        n0 = np.concatenate([np.nonzero(r)[0] for r in mask_bits])
+        p = ex["leaf_origin"][offs] + np.stack([(n0 >> 6) & 7, (n0 >> 3) & 7, n0 & 7], 1)
+        xs = torch.from_numpy(((p + 0.5) / 64.0).astype(np.float32)).cuda()[ii].contiguous()
+        ts_ = torch.from_numpy(ex["values"] / BAND).cuda()[ii].contiguous()
+        model.set_params(0, th0[0])
+        Fn = nvdb.mlp_function()
+        theta = torch.zeros(len(th0[0]), device="cuda", requires_grad=True)
+
+        def fwd_bwd():
+            theta.grad = None
+            y = Fn.apply(model, 0, xs, theta)
+            ((y[:, 0] - ts_) ** 2).mean().backward()
+
+        fwd_bwd()
+        tb = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fwd_bwd()
+            torch.cuda.synchronize()
+            tb.append(time.perf_counter() - t)
+        med = float(np.median(tb))
+        res[name] = {"one_epoch_job_ms": float(np.median(ts)) * 1e3, "max_abs_err_voxels": rep["max_abs"],
+                     "rms_err_voxels": rep["rms"], "iou": rep["iou"],
+                     "batch_2_22_fwd_bwd_ms": med * 1e3, "batch_2_22_samples_per_s": n / med,
+                     "batch_2_22_tflops": n * flops_fwd_bwd(36, 64, 3, 1) / med / 1e12}
+        del model
+    return res
+
+
 def cpu_baseline(grid):
     """The FP64 oracle on the host: 3 Adam steps of the regressor at 2^14 samples
     on the same volume, after building the oracle's own tree from the grid."""
@@ -458,10 +543,17 @@ def cpu_baseline(grid):
     t = time.perf_counter()
     F.train(th, shapes, B, tr, "regressor", (0, 0, 0), N_GRID, T.SDF, BAND, steps=steps, batch=batch, seed=0)
     fit_s = time.perf_counter() - t
+    nd = 1 << 17
+    sel = np.random.default_rng(0).choice(len(vals), nd, replace=False)
+    t = time.perf_counter()
+    F.decode_values(th, shapes, B, tr, (0, 0, 0), N_GRID, T.SDF, BAND, idx=sel)
+    dec_s = time.perf_counter() - t
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     return {"value": steps * batch / fit_s, "unit": "train samples/s", "cores": int(threads), "kind": "oracle",
             "sample": "3 Adam steps x 2^14 samples of the 4x128 regressor on the same 512^3 volume, FP64 numpy "
-                      "(oracle tree build of %d voxels took %.1f s, not counted)" % (len(vals), build_s)}
+                      "(oracle tree build of %d voxels took %.1f s, not counted); decode of 2^17 sampled voxels "
+                      "for decode_voxels_per_s" % (len(vals), build_s),
+            "decode_voxels_per_s": nd / dec_s}
 
 
 if __name__ == "__main__":
