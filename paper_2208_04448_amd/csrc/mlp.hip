@@ -37,6 +37,12 @@
 #ifndef NVDB_INFER_GLOBAL
 #define NVDB_INFER_GLOBAL 0
 #endif
+#ifndef NVDB_DWREG_FROM
+#define NVDB_DWREG_FROM 1
+#endif
+#ifndef NVDB_TRAIN_FWD_CHAIN
+#define NVDB_TRAIN_FWD_CHAIN 1
+#endif
 #ifndef NVDB_TRAIN_DX_GLOBAL
 #define NVDB_TRAIN_DX_GLOBAL 0
 #endif
@@ -153,11 +159,17 @@ __device__ __forceinline__ uint32_t relu_pk(uint32_t w) {
   v = __builtin_elementwise_max(v, short2v{0, 0});
   return __builtin_bit_cast(uint32_t, v);
 }
-// Zero the halves of g whose matching half of a (a ReLU output, so >= +0) is zero.
+// Zero the halves of g whose matching half of a (a ReLU output, so >= +0) is zero:
+// t = min(a, 1) per 16-bit half is 1 where a > 0 and 0 where a == 0, and the
+// 16-bit product g * t keeps or clears each half.  Written as two packed 16-bit
+// integer instructions (the compiler otherwise splits the halves into compares
+// and selects).
 __device__ __forceinline__ uint32_t mask_pk(uint32_t g, uint32_t a) {
-  ushort2v t = __builtin_elementwise_min(__builtin_bit_cast(ushort2v, a), ushort2v{1, 1});
-  ushort2v m = ushort2v{0, 0} - t;
-  return g & __builtin_bit_cast(uint32_t, m);
+  const uint32_t ones = 0x00010001u;
+  uint32_t t, r;
+  asm("v_pk_min_u16 %0, %1, %2" : "=v"(t) : "v"(a), "s"(ones));
+  asm("v_pk_mul_lo_u16 %0, %1, %2" : "=v"(r) : "v"(g), "v"(t));
+  return r;
 }
 template <int PREC>
 __device__ __forceinline__ void store_relu(floatx16 a, uint32_t* s) {
@@ -538,6 +550,102 @@ __device__ __forceinline__ void layer_block2(const AF& af, int ob, const uint32_
   }
 }
 
+// Step schedule of the BF16 forward chain: layer l has NB/2 block pairs of
+// nsl(l) k-steps each; steps are numbered through all layers.
+template <int NIB0, int NB, int H>
+struct FwdSteps {
+  static constexpr int KS = PR<NVDB_BF16>::KS;
+  static constexpr int nsl(int l) { return (l == 0 ? NIB0 : NB) * KS; }
+  static constexpr int per_layer(int l) { return (NB / 2) * nsl(l); }
+  static constexpr int total() {
+    int t = 0;
+    for (int l = 0; l < H; ++l) t += per_layer(l);
+    return t;
+  }
+  static constexpr int layer(int g) {
+    int l = 0;
+    while (g >= per_layer(l)) g -= per_layer(l++);
+    return l;
+  }
+  static constexpr int local(int g) {
+    int l = 0;
+    while (g >= per_layer(l)) g -= per_layer(l++);
+    return g;
+  }
+  static constexpr int pair(int g) { return local(g) / nsl(layer(g)); }  // within the layer
+  static constexpr int step(int g) { return local(g) % nsl(layer(g)); }
+  static constexpr int gpair(int g) { return layer(g) * (NB / 2) + pair(g); }
+  static constexpr int DEFER = 2;  // steps of the next pair that run before a pair's epilogue
+  // The epilogue of the pair ending at step g may wait until step DEFER-1 of the
+  // next pair if that pair's first DEFER steps do not read this pair's outputs.
+  static constexpr bool deferred(int g) {
+    if (g + 1 >= total()) return false;
+    if (layer(g + 1) == layer(g)) return true;
+    return (DEFER - 1) / KS < 2 * pair(g);
+  }
+};
+
+// All hidden layers of the BF16 forward pass in one software pipeline: weight
+// fragments (independent of the data) are fetched PF steps ahead through block
+// pairs and layers, and the bias/ReLU/convert epilogue of a block pair overlaps
+// the next pair's first products (two accumulator sets alternate).
+template <int W, int H, int NIB0, class F0, class FL>
+__device__ __forceinline__ void forward_chain_bf16(const F0& wf0, const FL& wfl, const uint32_t (&X0)[NIB0][8],
+                                                   uint32_t (&Hs)[H][W / 32][8], const float* sm_bias,
+                                                   const LaneK& K) {
+  using P = PR<NVDB_BF16>;
+  constexpr int NB = W / 32, KS = P::KS;
+  using S = FwdSteps<NIB0, NB, H>;
+  constexpr int T = S::total();
+  constexpr int PF = 8;
+  P::Frag fa[PF], fb[PF];
+  floatx16 acc[2][2];
+  auto fetch = [&](auto gc, P::Frag& x, P::Frag& y) {
+    constexpr int g = decltype(gc)::value;
+    constexpr int l = S::layer(g), ob = 2 * S::pair(g), t = S::step(g) / KS, kk = S::step(g) % KS;
+    if constexpr (l == 0) {
+      x = wf0(ob, t, kk);
+      y = wf0(ob + 1, t, kk);
+    } else {
+      const auto wf = wfl(IC<l>{});
+      x = wf(ob, t, kk);
+      y = wf(ob + 1, t, kk);
+    }
+  };
+  static_for<0, PF>([&](auto gc) {
+    constexpr int g = decltype(gc)::value;
+    if constexpr (g < T) fetch(gc, fa[g], fb[g]);
+  });
+  static_for<0, T>([&](auto gc) {
+    constexpr int g = decltype(gc)::value;
+    constexpr int l = S::layer(g), p = S::pair(g), s = S::step(g), buf = S::gpair(g) & 1;
+    if constexpr (s == 0) {
+      acc[buf][0] = bias_acc(sm_bias + l * W, K, 2 * p);
+      acc[buf][1] = bias_acc(sm_bias + l * W, K, 2 * p + 1);
+    }
+    const P::Frag a0 = fa[g % PF], a1 = fb[g % PF];
+    if constexpr (g + PF < T) fetch(IC<g + PF>{}, fa[g % PF], fb[g % PF]);
+    P::Frag b;
+    if constexpr (l == 0) b = P::sfrag(X0[s / KS], s % KS);
+    else b = P::sfrag(Hs[l - 1][s / KS], s % KS);
+    acc[buf][0] = P::mma(a0, b, acc[buf][0]);
+    acc[buf][1] = P::mma(a1, b, acc[buf][1]);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (s == S::DEFER - 1 && S::gpair(g) > 0) {
+      constexpr int ge = g - S::DEFER;  // last step of the previous pair
+      if constexpr (S::deferred(ge)) {
+        constexpr int le = S::layer(ge), pe = S::pair(ge);
+        store_relu<NVDB_BF16>(acc[buf ^ 1][0], Hs[le][2 * pe]);
+        store_relu<NVDB_BF16>(acc[buf ^ 1][1], Hs[le][2 * pe + 1]);
+      }
+    }
+    if constexpr (s == S::nsl(l) - 1 && !S::deferred(g)) {
+      store_relu<NVDB_BF16>(acc[buf][0], Hs[l][2 * p]);
+      store_relu<NVDB_BF16>(acc[buf][1], Hs[l][2 * p + 1]);
+    }
+  });
+}
+
 __device__ __forceinline__ void relu16(floatx16& a) {
 #pragma unroll
   for (int r = 0; r < 16; ++r) a[r] = fmaxf(a[r], 0.f);
@@ -606,9 +714,13 @@ struct TrainCfg {
   // BF16: where the weight fragments of layers 1..H-1 come from (HBM/L2 or the LDS copy)
   static constexpr bool FWD_GLOBAL = NVDB_TRAIN_FWD_GLOBAL != 0;
   static constexpr bool DX_GLOBAL = NVDB_TRAIN_DX_GLOBAL != 0;
-  // (measured on the 4x128 network: keeping only the top layer's dW resident frees the
-  // registers whose spills cost more than folding one more layer per tile)
-  static constexpr int DWREG_FROM = (W >= 128) ? 3 : 0;
+  // BF16: the forward pass as one software pipeline over all layers (two block
+  // pairs per layer or more)
+  static constexpr bool FWD_CHAIN = (PREC == NVDB_BF16) && NVDB_TRAIN_FWD_CHAIN != 0 && W >= 128;
+  // (measured on the 4x128 network: all but layer 0 resident is fastest; its few
+  // spills cost less than folding another layer per tile, while holding layer 0
+  // as well spills far more)
+  static constexpr int DWREG_FROM = (W >= 128) ? NVDB_DWREG_FROM : 0;
   static constexpr bool reg_layer(int l) { return DWREG && l >= DWREG_FROM; }
   static constexpr bool any_rmw = !DWREG || DWREG_FROM > 0;
   static constexpr int RB = (PREC == NVDB_BF16) ? 0 : (KP > W ? KP : W) + 4;  // fp32 row pitch (floats)
@@ -734,27 +846,36 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
         encode_S<PREC, NIB0>(smp, sm_benc, nv.nfreq, X0);
       }
       WFwd<PREC, W, NIB0> wf0{nullptr, (const u32x4*)nv.wfrag + z, (const float*)nv.wcol + z, true, &K};
+      auto wfl = [&](auto lc) {
+        constexpr int l = decltype(lc)::value;
+        return WFwd<PREC, W, NB>{wl + (size_t)(l - 1) * W * 256,
+                                 (const u32x4*)((const __bf16*)nv.wfrag + (size_t)W * KP + (size_t)(l - 1) * W * W) + z,
+                                 (const float*)nv.wcol + z + (size_t)KP * W + (size_t)(l - 1) * W * W, CF::FWD_GLOBAL,
+                                 &K};
+      };
+      if constexpr (CF::FWD_CHAIN) {
+        forward_chain_bf16<W, H, NIB0>(wf0, wfl, X0, Hs, sm_bias, K);
+      } else {
 #pragma unroll
-      for (int ob = 0; ob < NB; ob += 2) {
-        floatx16 a0 = bias_acc(sm_bias, K, ob), a1 = bias_acc(sm_bias, K, ob + 1);
-        layer_block2<PREC, NIB0>(wf0, ob, X0, a0, a1);
-        store_relu<PREC>(a0, Hs[0][ob]);
-        store_relu<PREC>(a1, Hs[0][ob + 1]);
+        for (int ob = 0; ob < NB; ob += 2) {
+          floatx16 a0 = bias_acc(sm_bias, K, ob), a1 = bias_acc(sm_bias, K, ob + 1);
+          layer_block2<PREC, NIB0>(wf0, ob, X0, a0, a1);
+          store_relu<PREC>(a0, Hs[0][ob]);
+          store_relu<PREC>(a1, Hs[0][ob + 1]);
+        }
+        static_for<1, H>([&](auto lc) {
+          constexpr int l = decltype(lc)::value;
+          const auto wf = wfl(lc);
+#pragma unroll
+          for (int ob = 0; ob < NB; ob += 2) {
+            floatx16 a0 = bias_acc(sm_bias + l * W, K, ob), a1 = bias_acc(sm_bias + l * W, K, ob + 1);
+            layer_block2<PREC, NB>(wf, ob, Hs[l - 1], a0, a1);
+            store_relu<PREC>(a0, Hs[l][ob]);
+            store_relu<PREC>(a1, Hs[l][ob + 1]);
+          }
+        });
       }
     }
-    static_for<1, H>([&](auto lc) {
-      constexpr int l = decltype(lc)::value;
-      WFwd<PREC, W, NB> wf{wl + (size_t)(l - 1) * W * 256,
-                           (const u32x4*)((const __bf16*)nv.wfrag + (size_t)W * KP + (size_t)(l - 1) * W * W) + z,
-                           (const float*)nv.wcol + z + (size_t)KP * W + (size_t)(l - 1) * W * W, CF::FWD_GLOBAL, &K};
-#pragma unroll
-      for (int ob = 0; ob < NB; ob += 2) {
-        floatx16 a0 = bias_acc(sm_bias + l * W, K, ob), a1 = bias_acc(sm_bias + l * W, K, ob + 1);
-        layer_block2<PREC, NB>(wf, ob, Hs[l - 1], a0, a1);
-        store_relu<PREC>(a0, Hs[l][ob]);
-        store_relu<PREC>(a1, Hs[l][ob + 1]);
-      }
-    });
     // head (VALU): y_c = sum_f Wh[c][f] a_H[f] + bh[c]
     float y[C], gy[C];
 #pragma unroll
