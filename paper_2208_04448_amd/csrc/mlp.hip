@@ -99,9 +99,13 @@ __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef int intx8 __attribute__((ext_vector_type(8)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+// Two floats to packed bf16 (round to nearest even), a in the low half.  A vector
+// conversion becomes one two-source instruction; converting the values one at a
+// time costs two conversions and a permute.
 __device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
-  bf16x2 v = {(__bf16)a, (__bf16)b};
-  return __builtin_bit_cast(uint32_t, v);
+  const floatx2 f = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2));
 }
 __device__ __forceinline__ float shfl_xor32(float v) {
   // exchange with the lane 32 apart (other half of the wave)
@@ -161,14 +165,17 @@ __device__ __forceinline__ uint32_t relu_pk(uint32_t w) {
 }
 // Zero the halves of g whose matching half of a (a ReLU output, so >= +0) is zero:
 // t = min(a, 1) per 16-bit half is 1 where a > 0 and 0 where a == 0, and the
-// 16-bit product g * t keeps or clears each half.  Written as two packed 16-bit
-// integer instructions (the compiler otherwise splits the halves into compares
-// and selects).
+// 16-bit product g * t keeps or clears each half: two packed 16-bit integer
+// instructions, written as inline assembly because the optimiser turns the
+// product by {0, 1} into per-half compares and selects.  The compiler does not
+// count inline assembly as a vector-ALU write when it pads matrix-core operand
+// reads, so the trailing s_nop supplies the two wait states a matrix product
+// reading the result right away would need.
 __device__ __forceinline__ uint32_t mask_pk(uint32_t g, uint32_t a) {
-  const uint32_t ones = 0x00010001u;
-  uint32_t t, r;
-  asm("v_pk_min_u16 %0, %1, %2" : "=v"(t) : "v"(a), "s"(ones));
-  asm("v_pk_mul_lo_u16 %0, %1, %2" : "=v"(r) : "v"(g), "v"(t));
+  uint32_t r;
+  asm("v_pk_min_u16 %0, %1, %2\n\tv_pk_mul_lo_u16 %0, %3, %0\n\ts_nop 1"
+      : "=&v"(r)
+      : "v"(a), "s"(0x00010001u), "v"(g));
   return r;
 }
 template <int PREC>
