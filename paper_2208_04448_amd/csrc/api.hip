@@ -126,7 +126,7 @@ static Net& net_of(nvdb_model* m, int32_t net) {
 static const Net& net_of(const nvdb_model* m, int32_t net) { return net_of(const_cast<nvdb_model*>(m), net); }
 
 static void ensure_partials(Net& n, int G) {
-  n.partial.ensure((size_t)G * n.s.nparams());
+  n.partial.ensure((size_t)G * n.s.pstride());
   n.loss_partial.ensure(G);
 }
 
@@ -500,14 +500,23 @@ static void enqueue_step(nvdb_model* m, const Tree* tree, const std::vector<std:
       G = std::max(G, train_grid(n, m->train_g > 0 ? m->train_g : DEFAULT_G));
     }
     slot = 0;
+    SampleSpec gspec[NVDB_MAX_NETS];
+    floatx4* gout[NVDB_MAX_NETS];
+    int ng = 0;
     for (int k : grp) {
       Net& N = m->nets[k];
-      NVDB_REQUIRE(N.partial.n >= (size_t)G * N.s.nparams() && N.xt.n >= (size_t)L.nets[slot].spec.n,
+      NVDB_REQUIRE(N.partial.n >= (size_t)G * N.s.pstride() && N.xt.n >= (size_t)L.nets[slot].spec.n,
                    NVDB_E_STATE, "training workspace not reserved");
       TrainNet& tn = L.nets[slot++];
+      // the kernel draws i.i.d. samples over voxels or leaf slots itself; explicit
+      // index lists and the level-1 slots go through the gather kernel
+      tn.fused = !tn.spec.idx && (tn.spec.src == SRC_VOXELS || tn.spec.src == SRC_LEAF_SLOTS);
+      if (!tn.fused) {
+        gspec[ng] = tn.spec;
+        gout[ng++] = N.xt.p;
+      }
       tn.partial = N.partial.p;
       tn.loss_partial = N.loss_partial.p;
-      launch_gather(tn.spec, tv, N.xt.p, st);
       tn.xt = N.xt.p;
       const int64_t s = N.step + 1;
       AdamNet a = adam_view(N);
@@ -527,6 +536,7 @@ static void enqueue_step(nvdb_model* m, const Tree* tree, const std::vector<std:
       maxP = std::max(maxP, N.s.nparams());
     }
     L.G = G;
+    if (ng > 0) launch_gather_multi(gspec, gout, ng, tv, st);
     if (ev) NVDB_HIP(hipEventRecord(ev[evi++], st));
     launch_train(m->nets[grp[0]].ks, L, (int)grp.size(), st);
     if (ev) NVDB_HIP(hipEventRecord(ev[evi++], st));

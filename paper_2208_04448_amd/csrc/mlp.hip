@@ -277,6 +277,65 @@ __device__ __forceinline__ Smp fetch_sample(const SampleSpec& sp, const TreeView
   return s;
 }
 
+// The next tile's sample of a training lane, fetched while the current tile runs.
+// With the i.i.d. sampler over active voxels or leaf slots the kernel draws it
+// itself (the arithmetic of fetch_sample, split so that no load result is used in
+// the stage that issues it): stage 1 forms the population index and loads the
+// voxel key and value (voxels) or the leaf origin and mask word (leaf slots);
+// stage 2, later in the tile, loads a voxel's leaf origin.  Otherwise stage 1
+// reads the gathered record (x, y, z, target or class) into o.
+struct NextSample {
+  uint32_t key;  // voxel key, or population index of a leaf slot
+  uint2 aux;     // voxel value bits, or the leaf's mask word holding the slot
+  int4 o;        // leaf origin (or the gathered record's bits)
+};
+__device__ __forceinline__ void next_stage1(const TrainNet& TN, const TreeView& tv, int64_t j, NextSample& ns) {
+  const SampleSpec& sp = TN.spec;
+  if (j >= sp.n) return;
+  if (!TN.fused) {
+    ns.o = __builtin_bit_cast(int4, TN.xt[j]);
+    return;
+  }
+  const uint64_t hsh = sm_mix(sp.step_seed + SM_GOLDEN * (uint64_t)(j + 1));
+  const uint32_t g = (uint32_t)__umul64hi(hsh, (uint64_t)sp.npop);
+  if (sp.src == SRC_VOXELS) {
+    ns.key = tv.vox_key[g];
+    ns.aux.x = __float_as_uint(tv.values[g]);
+  } else {
+    ns.key = g;
+    const uint32_t leaf = g >> 9;
+    ns.o = tv.leaf_o[leaf];
+    ns.aux = *(const uint2*)&tv.leaf_mask[(size_t)leaf * 8 + ((g & 511u) >> 6)];
+  }
+}
+__device__ __forceinline__ void next_stage2(const TrainNet& TN, const TreeView& tv, int64_t j, NextSample& ns) {
+  if (j < TN.spec.n && TN.fused && TN.spec.src == SRC_VOXELS) ns.o = tv.leaf_o[ns.key >> 9];
+}
+__device__ __forceinline__ void next_sample(const TrainNet& TN, const NextSample& ns, Smp& s) {
+  const SampleSpec& sp = TN.spec;
+  if (!TN.fused) {
+    const floatx4 r = __builtin_bit_cast(floatx4, ns.o);
+    s.x[0] = r[0];
+    s.x[1] = r[1];
+    s.x[2] = r[2];
+    s.t = r[3];
+    s.cls = (int)r[3];
+    return;
+  }
+  const uint32_t n0 = ns.key & 511u;
+  const int px = ns.o.x + (int)(n0 >> 6), py = ns.o.y + (int)((n0 >> 3) & 7u), pz = ns.o.z + (int)(n0 & 7u);
+  s.x[0] = ((float)(px - sp.lo[0]) + 0.5f) * sp.inv_d;
+  s.x[1] = ((float)(py - sp.lo[1]) + 0.5f) * sp.inv_d;
+  s.x[2] = ((float)(pz - sp.lo[2]) + 0.5f) * sp.inv_d;
+  if (sp.src == SRC_VOXELS) {
+    s.t = __uint_as_float(ns.aux.x) * sp.tscale;
+  } else {
+    const uint64_t w = ((uint64_t)ns.aux.y << 32) | ns.aux.x;
+    s.t = (float)((w >> (n0 & 63u)) & 1ull);
+  }
+  s.cls = 0;
+}
+
 // gamma(x) into S layout.  Feature f < m is cos(2 pi b_f.x) = sin(2 pi (b_f.x + 1/4)),
 // m <= f < 2m is sin(2 pi b_{f-m}.x), f >= 2m is zero padding.  The hardware sine
 // takes revolutions; the phase is reduced with fract first.  The FP32 form forms the
@@ -763,7 +822,6 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
   const NetView& nv = TN.net;
   const SampleSpec& sp = TN.spec;
   const int wave = wave_id();
-  const int64_t P_ = nv.s.nparams();
 
   // ---- LDS carve-up
   char* wl0 = smem;                                                // bf16 layers 1..H-1
@@ -807,22 +865,21 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
 
   const int wo = wave >> 1, wi = wave & 1;
   const int64_t n_iter = (sp.n + 127) / 128;
-  float* partial = TN.partial + (size_t)blockIdx.x * P_;
+  float* partial = TN.partial + (size_t)blockIdx.x * nv.s.pstride();
 
   PhaseA<NIB0> pa;
   const bool fastenc = BF && 2 * nv.nfreq == 32 * NIB0;
   if (fastenc) pa.load(sm_benc0);
-  floatx4 xt_next = floatx4{0.f, 0.f, 0.f, 0.f};
+  NextSample nx{};
   {
     const int64_t j0 = (int64_t)blockIdx.x * 128 + wave * 32 + (lane_id() & 31);
-    if (j0 < sp.n) xt_next = TN.xt[j0];
+    next_stage1(TN, L.tree, j0, nx);
+    next_stage2(TN, L.tree, j0, nx);
   }
   for (int64_t it = blockIdx.x; it < n_iter; it += L.G) {
-    const floatx4 xt_cur = xt_next;
-    {
-      const int64_t jn = (it + L.G) * 128 + wave * 32 + (lane_id() & 31);
-      if (jn < sp.n) xt_next = TN.xt[jn];
-    }
+    const NextSample cur = nx;
+    const int64_t jn = (it + L.G) * 128 + wave * 32 + (lane_id() & 31);
+    next_stage1(TN, L.tree, jn, nx);
     const LaneK K = lane_consts();
     const int h = K.h, fl = K.fl;
     const int z = opaque_zero();
@@ -836,11 +893,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
     const int64_t j = it * 128 + wave * 32 + fl;
     Smp smp;
     smp.valid = j < sp.n;
-    smp.x[0] = xt_cur[0];
-    smp.x[1] = xt_cur[1];
-    smp.x[2] = xt_cur[2];
-    smp.t = xt_cur[3];
-    smp.cls = (int)xt_cur[3];
+    next_sample(TN, cur, smp);
 
     // ================= forward
     uint32_t Hs[H][NB][SR];  // Hs[l] = a_{l+1} (S layout), l = 0..H-1
@@ -883,6 +936,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
         });
       }
     }
+    next_stage2(TN, L.tree, jn, nx);  // the next tile's leaf origin (voxels)
     // head (VALU): y_c = sum_f Wh[c][f] a_H[f] + bh[c]
     float y[C], gy[C];
 #pragma unroll
@@ -1703,7 +1757,7 @@ __device__ __forceinline__ void write_shadow(const AdamNet& A, int64_t p, float 
 constexpr int RED_P = 64;
 __global__ void __launch_bounds__(256) k_reduce_adam(AdamLaunch AL) {
   const AdamNet& A = AL.nets[blockIdx.y];
-  const int64_t P = A.s.nparams();
+  const int64_t P = A.s.nparams(), R = A.s.pstride();
   const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
   const int64_t p = (int64_t)blockIdx.x * RED_P + lane;
   if (A.prev_loss && *A.prev_loss < *A.stop_below) {  // skipped step: carry the loss forward
@@ -1715,10 +1769,14 @@ __global__ void __launch_bounds__(256) k_reduce_adam(AdamLaunch AL) {
   }
   if ((int64_t)blockIdx.x * RED_P >= P) return;  // uniform per work-group
   if (blockIdx.x == 0 && threadIdx.x == 0 && A.ran) *A.ran = 1;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && A.loss_out) {
+  if (blockIdx.x == 0 && threadIdx.x < 64 && A.loss_out) {
+    // step loss: lane-strided sums of the work-group losses, then a butterfly over
+    // the wave; lane 0's result follows the same order on every run
     float L = 0.f;
-    for (int g = 0; g < A.G; ++g) L += A.loss_partial[g];
-    *A.loss_out = L * A.loss_scale;
+    for (int g = threadIdx.x; g < A.G; g += 64) L += A.loss_partial[g];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) L += __shfl_xor(L, off);
+    if (threadIdx.x == 0) *A.loss_out = L * A.loss_scale;
   }
   __shared__ float red[4][RED_P];
   const int per = (A.G + 3) / 4;
@@ -1730,13 +1788,13 @@ __global__ void __launch_bounds__(256) k_reduce_adam(AdamLaunch AL) {
     for (; g + 8 <= g1; g += 8) {
       float v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = col[(size_t)(g + u) * P];
+      for (int u = 0; u < 8; ++u) v[u] = col[(size_t)(g + u) * R];
       s0 += v[0] + v[4];
       s1 += v[1] + v[5];
       s2 += v[2] + v[6];
       s3 += v[3] + v[7];
     }
-    for (; g < g1; ++g) s0 += col[(size_t)g * P];
+    for (; g < g1; ++g) s0 += col[(size_t)g * R];
   }
   red[q][lane] = (s0 + s1) + (s2 + s3);
   __syncthreads();
@@ -1769,6 +1827,20 @@ __global__ void __launch_bounds__(256) k_gather(SampleSpec sp, TreeView tv, floa
   if (j >= sp.n) return;
   const Smp s = fetch_sample(sp, tv, j);
   out[j] = floatx4{s.x[0], s.x[1], s.x[2], sp.src == SRC_L1_SLOTS ? (float)s.cls : s.t};
+}
+
+// The samples of every network of one training launch in a single launch
+// (blockIdx.y = network).
+struct GatherLaunch {
+  SampleSpec sp[NVDB_MAX_NETS];
+  floatx4* out[NVDB_MAX_NETS];
+};
+__global__ void __launch_bounds__(256) k_gather_multi(GatherLaunch GL, TreeView tv) {
+  const SampleSpec& sp = GL.sp[blockIdx.y];
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= sp.n) return;
+  const Smp s = fetch_sample(sp, tv, j);
+  GL.out[blockIdx.y][j] = floatx4{s.x[0], s.x[1], s.x[2], sp.src == SRC_L1_SLOTS ? (float)s.cls : s.t};
 }
 
 __global__ void k_fill(float* p, int64_t n, float v) {
@@ -1828,6 +1900,18 @@ void launch_write_shadow(const AdamNet& A, hipStream_t st) {
 void launch_gather(const SampleSpec& sp, const TreeView& tv, floatx4* out, hipStream_t st) {
   if (sp.n <= 0) return;
   hipLaunchKernelGGL(k_gather, dim3((unsigned)((sp.n + 255) / 256)), dim3(256), 0, st, sp, tv, out);
+  NVDB_HIP(hipGetLastError());
+}
+void launch_gather_multi(const SampleSpec* sp, floatx4* const* out, int n, const TreeView& tv, hipStream_t st) {
+  GatherLaunch GL{};
+  int64_t nmax = 0;
+  for (int k = 0; k < n; ++k) {
+    GL.sp[k] = sp[k];
+    GL.out[k] = out[k];
+    nmax = std::max<int64_t>(nmax, sp[k].n);
+  }
+  if (nmax <= 0) return;
+  hipLaunchKernelGGL(k_gather_multi, dim3((unsigned)((nmax + 255) / 256), n), dim3(256), 0, st, GL, tv);
   NVDB_HIP(hipGetLastError());
 }
 void launch_quant_fp8(const NetShape& s, const float* theta, char* w8, float* w8inv, hipStream_t st) {

@@ -145,6 +145,8 @@ struct NetShape {
   }
   __host__ __device__ int64_t nparams() const { return woff(H) + (int64_t)C * W + C; }
   __host__ __device__ int win(int l) const { return l == 0 ? K : W; }
+  // floats between consecutive work-group partial gradient rows (rows start on 256-byte boundaries)
+  __host__ __device__ int64_t pstride() const { return (nparams() + 63) / 64 * 64; }
 };
 
 // Device-side view of one network: FP32 master parameters are canonical; the
@@ -179,6 +181,9 @@ struct TrainNet {
   NetView net;
   SampleSpec spec;
   const floatx4* xt;    // gathered samples of this step: (x, y, z, target or class)
+  // nonzero: the kernel draws the i.i.d. samples itself (voxels or leaf slots) from
+  // the launch's tree instead of reading xt
+  int32_t fused;
   float* partial;       // [G][P]
   float* loss_partial;  // [G]
   // Device-side stop test (warm-started sequences): the step is skipped when
@@ -255,6 +260,7 @@ void launch_reduce_adam(const AdamLaunch& A, int64_t max_p, int n_nets, hipStrea
 void launch_write_shadow(const AdamNet& A, hipStream_t st);
 void launch_sample(uint64_t sseed, uint32_t npop, int64_t n, uint32_t* out, hipStream_t st);
 void launch_gather(const SampleSpec& sp, const TreeView& tv, floatx4* out, hipStream_t st);
+void launch_gather_multi(const SampleSpec* sp, floatx4* const* out, int n, const TreeView& tv, hipStream_t st);
 void launch_fill(float* p, int64_t n, float v, hipStream_t st);
 // tree.hip
 Tree* build_tree_dense(const float* grid, const int32_t dims[3], const int32_t origin[3], const nvdb_active_rule& rule,
