@@ -508,9 +508,10 @@ static void enqueue_step(nvdb_model* m, const Tree* tree, const std::vector<std:
       NVDB_REQUIRE(N.partial.n >= (size_t)G * N.s.pstride() && N.xt.n >= (size_t)L.nets[slot].spec.n,
                    NVDB_E_STATE, "training workspace not reserved");
       TrainNet& tn = L.nets[slot++];
-      // the kernel draws i.i.d. samples over voxels or leaf slots itself; explicit
-      // index lists and the level-1 slots go through the gather kernel
-      tn.fused = !tn.spec.idx && (tn.spec.src == SRC_VOXELS || tn.spec.src == SRC_LEAF_SLOTS);
+      // the BF16 kernels draw i.i.d. samples over voxels or leaf slots themselves;
+      // explicit index lists, the level-1 slots and the FP32 form use the gather kernel
+      tn.fused = m->d.precision == NVDB_BF16 && !tn.spec.idx &&
+                 (tn.spec.src == SRC_VOXELS || tn.spec.src == SRC_LEAF_SLOTS);
       if (!tn.fused) {
         gspec[ng] = tn.spec;
         gout[ng++] = N.xt.p;

@@ -43,6 +43,9 @@
 #ifndef NVDB_TRAIN_FWD_CHAIN
 #define NVDB_TRAIN_FWD_CHAIN 1
 #endif
+#ifndef NVDB_TRAIN_DW0_LDS
+#define NVDB_TRAIN_DW0_LDS 1
+#endif
 #ifndef NVDB_TRAIN_DX_GLOBAL
 #define NVDB_TRAIN_DX_GLOBAL 0
 #endif
@@ -283,16 +286,18 @@ __device__ __forceinline__ Smp fetch_sample(const SampleSpec& sp, const TreeView
 // the stage that issues it): stage 1 forms the population index and loads the
 // voxel key and value (voxels) or the leaf origin and mask word (leaf slots);
 // stage 2, later in the tile, loads a voxel's leaf origin.  Otherwise stage 1
-// reads the gathered record (x, y, z, target or class) into o.
+// reads the gathered record (x, y, z, target or class) into o.  Only the BF16
+// kernels draw their own samples (FUSE); in the FP32 form the registers are scarcer.
 struct NextSample {
   uint32_t key;  // voxel key, or population index of a leaf slot
   uint2 aux;     // voxel value bits, or the leaf's mask word holding the slot
   int4 o;        // leaf origin (or the gathered record's bits)
 };
+template <bool FUSE>
 __device__ __forceinline__ void next_stage1(const TrainNet& TN, const TreeView& tv, int64_t j, NextSample& ns) {
   const SampleSpec& sp = TN.spec;
   if (j >= sp.n) return;
-  if (!TN.fused) {
+  if (!FUSE || !TN.fused) {
     ns.o = __builtin_bit_cast(int4, TN.xt[j]);
     return;
   }
@@ -308,12 +313,14 @@ __device__ __forceinline__ void next_stage1(const TrainNet& TN, const TreeView& 
     ns.aux = *(const uint2*)&tv.leaf_mask[(size_t)leaf * 8 + ((g & 511u) >> 6)];
   }
 }
+template <bool FUSE>
 __device__ __forceinline__ void next_stage2(const TrainNet& TN, const TreeView& tv, int64_t j, NextSample& ns) {
-  if (j < TN.spec.n && TN.fused && TN.spec.src == SRC_VOXELS) ns.o = tv.leaf_o[ns.key >> 9];
+  if (FUSE && j < TN.spec.n && TN.fused && TN.spec.src == SRC_VOXELS) ns.o = tv.leaf_o[ns.key >> 9];
 }
+template <bool FUSE>
 __device__ __forceinline__ void next_sample(const TrainNet& TN, const NextSample& ns, Smp& s) {
   const SampleSpec& sp = TN.spec;
-  if (!TN.fused) {
+  if (!FUSE || !TN.fused) {
     const floatx4 r = __builtin_bit_cast(floatx4, ns.o);
     s.x[0] = r[0];
     s.x[1] = r[1];
@@ -557,6 +564,24 @@ struct WBwd {
   }
 };
 
+// Raw buffer resource of a device array of `bytes` bytes (out-of-range lanes read 0).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* p, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+// BF16 transposed fragments of one layer (backward product) read from HBM/L2
+// with buffer loads: uniform resource and layer offset, a fixed 16-byte slot per
+// lane, so no per-load address arithmetic.
+template <int W>
+struct WBwdBuf {
+  __amdgpu_buffer_rsrc_t rsrc;
+  int soff;  // byte offset of the layer's fragments (uniform)
+  int voff;  // lane * 16
+  __device__ __forceinline__ bf16x8 operator()(int ib, int t, int kk) const {
+    return __builtin_bit_cast(
+        bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff, soff + ((ib * (W / 32) + t) * 2 + kk) * 1024, 0));
+  }
+};
+
 // Accumulator initialised with the bias of the lane's 16 output features.
 __device__ __forceinline__ floatx16 bias_acc(const float* bias, const LaneK& K, int ob) {
   const floatx4* b = (const floatx4*)(bias + 32 * ob + 4 * K.h);
@@ -788,7 +813,14 @@ struct TrainCfg {
   // as well spills far more)
   static constexpr int DWREG_FROM = (W >= 128) ? NVDB_DWREG_FROM : 0;
   static constexpr bool reg_layer(int l) { return DWREG && l >= DWREG_FROM; }
-  static constexpr bool any_rmw = !DWREG || DWREG_FROM > 0;
+  // BF16 4x128 with layers 1.. resident: layer 0's dW accumulates in LDS (a
+  // wave-private fp32 region) instead of the partial row; the dX products then
+  // read their weight fragments from HBM/L2, which frees the LDS weight copy.
+  static constexpr bool DW0_LDS = DWREG && NVDB_TRAIN_DW0_LDS != 0 && W >= 128 && DWREG_FROM == 1;
+  static constexpr bool DX_HBM = DX_GLOBAL || DW0_LDS;
+  static constexpr bool lds_layer(int l) { return DW0_LDS && l == 0; }
+  static constexpr bool fold_layer(int l) { return !reg_layer(l) && !lds_layer(l); }
+  static constexpr bool any_rmw = !DWREG || DWREG_FROM > (DW0_LDS ? 1 : 0);
   static constexpr int RB = (PREC == NVDB_BF16) ? 0 : (KP > W ? KP : W) + 4;  // fp32 row pitch (floats)
   static constexpr int ROWS_BYTES = (PREC == NVDB_BF16) ? 32 * 256 : 32 * RB * 4;
   // slot: G rows, input-activation rows, last-hidden-layer rows (head), gy [C][32].
@@ -797,9 +829,10 @@ struct TrainCfg {
   static constexpr bool HH_PRIVATE = (PREC != NVDB_BF16);
   static constexpr int SLOT_BYTES = (HH_PRIVATE ? 2 : 3) * ROWS_BYTES + 32 * C * 4;
   static constexpr int HH_BYTES = HH_PRIVATE ? 4 * ROWS_BYTES : 0;
-  static constexpr int WL_BYTES = (PREC == NVDB_BF16) ? (H - 1) * W * 256 : 0;
+  static constexpr int WL_BYTES = (PREC == NVDB_BF16 && !DX_HBM) ? (H - 1) * W * 256 : 0;
+  static constexpr int DW0_BYTES = DW0_LDS ? W * KP * 4 : 0;  // [wave][a][b][quad][lane][4] floats
   static constexpr int SMALL_FLOATS = H * W + C * W + 4 + 4 * (KP / 2) + 8;
-  static constexpr int LDS_BYTES = WL_BYTES + NSLOT * SLOT_BYTES + HH_BYTES + SMALL_FLOATS * 4;
+  static constexpr int LDS_BYTES = WL_BYTES + NSLOT * SLOT_BYTES + HH_BYTES + SMALL_FLOATS * 4 + DW0_BYTES;
   // dW blocks owned by a wave: waves form a 2 x 2 grid over (output, input) blocks.
   static constexpr int OBW = NB / 2;
   static constexpr int IBW0 = NIB0 / 2, IBW = NB / 2;
@@ -832,6 +865,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
   float* sm_bhead0 = sm_whead0 + C * W;                             // [C] (padded to 4)
   float* sm_benc0 = sm_bhead0 + 4;                                  // [KP/2][4]
   float* sm_red = sm_benc0 + 4 * (KP / 2);                          // [8] reductions
+  float* dw0 = sm_red + 8;                                          // layer 0's dW (DW0_LDS)
 
   // ---- stage parameters
   if constexpr (BF) {
@@ -843,6 +877,8 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
   for (int i = threadIdx.x; i < C * W; i += blockDim.x) sm_whead0[i] = nv.whead[i];
   if (threadIdx.x < C) sm_bhead0[threadIdx.x] = nv.bhead[threadIdx.x];
   for (int i = threadIdx.x; i < 4 * (KP / 2); i += blockDim.x) sm_benc0[i] = nv.benc[i];
+  if constexpr (CF::DW0_LDS)
+    for (int i = threadIdx.x; i < CF::DW0_BYTES / 16; i += blockDim.x) ((floatx4*)dw0)[i] = floatx4{0.f, 0.f, 0.f, 0.f};
   __syncthreads();
 
   // ---- per-wave accumulators kept across iterations
@@ -873,13 +909,13 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
   NextSample nx{};
   {
     const int64_t j0 = (int64_t)blockIdx.x * 128 + wave * 32 + (lane_id() & 31);
-    next_stage1(TN, L.tree, j0, nx);
-    next_stage2(TN, L.tree, j0, nx);
+    next_stage1<BF>(TN, L.tree, j0, nx);
+    next_stage2<BF>(TN, L.tree, j0, nx);
   }
   for (int64_t it = blockIdx.x; it < n_iter; it += L.G) {
     const NextSample cur = nx;
     const int64_t jn = (it + L.G) * 128 + wave * 32 + (lane_id() & 31);
-    next_stage1(TN, L.tree, jn, nx);
+    next_stage1<BF>(TN, L.tree, jn, nx);
     const LaneK K = lane_consts();
     const int h = K.h, fl = K.fl;
     const int z = opaque_zero();
@@ -893,7 +929,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
     const int64_t j = it * 128 + wave * 32 + fl;
     Smp smp;
     smp.valid = j < sp.n;
-    next_sample(TN, cur, smp);
+    next_sample<BF>(TN, cur, smp);
 
     // ================= forward
     uint32_t Hs[H][NB][SR];  // Hs[l] = a_{l+1} (S layout), l = 0..H-1
@@ -936,7 +972,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
         });
       }
     }
-    next_stage2(TN, L.tree, jn, nx);  // the next tile's leaf origin (voxels)
+    next_stage2<BF>(TN, L.tree, jn, nx);  // the next tile's leaf origin (voxels)
     // head (VALU): y_c = sum_f Wh[c][f] a_H[f] + bh[c]
     float y[C], gy[C];
 #pragma unroll
@@ -996,7 +1032,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
       }
       // layers folded into the partial row: fetch the running sums now so that the
       // loads complete under the exchange below
-      constexpr bool PREFETCH = !CF::reg_layer(l) && (BF ? l <= 1 : l == 0);  // where registers allow
+      constexpr bool PREFETCH = CF::fold_layer(l) && (BF ? l <= 1 : l == 0);  // where registers allow
       float prev[PREFETCH ? OBW : 1][PREFETCH ? CF::IBWMAX : 1][16];
       if constexpr (PREFETCH) {
         if (!first) {
@@ -1107,7 +1143,28 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
         __syncthreads();
       }
 
-      if constexpr (!CF::reg_layer(l)) {
+      if constexpr (CF::lds_layer(l)) {
+        // add this iteration's blocks to the wave's region of layer 0's dW in LDS
+#pragma unroll
+        for (int a = 0; a < OBW; ++a)
+#pragma unroll
+          for (int b = 0; b < CF::IBWMAX; ++b) {
+            if (b < IBWl) {
+              floatx4* q = (floatx4*)(dw0 + z) + ((wave * OBW + a) * IBWl + b) * 256 + lane_id();
+#pragma unroll
+              for (int qd = 0; qd < 4; ++qd) {
+                floatx4 v = q[64 * qd];
+                v[0] += dacc[l][a][b][4 * qd];
+                v[1] += dacc[l][a][b][4 * qd + 1];
+                v[2] += dacc[l][a][b][4 * qd + 2];
+                v[3] += dacc[l][a][b][4 * qd + 3];
+                q[64 * qd] = v;
+              }
+              dacc[l][a][b] = floatx16{};
+            }
+          }
+      }
+      if constexpr (CF::fold_layer(l)) {
         // fold this iteration's blocks into the work-group's partial row.  Every
         // running sum is loaded before the first store: a store may alias a later
         // load as far as the compiler knows, so interleaving them would cost one
@@ -1151,14 +1208,17 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
 
       if constexpr (l > 0) {
         // g_l = (W_l^T g_{l+1}) * 1[a_l > 0]
-        WBwd<PREC, W> wb{wl + (size_t)(l - 1) * W * 256,
-                         (const float*)nv.wrow + z + (size_t)W * KP + (size_t)(l - 1) * W * W,
-                         (const u32x4*)((const __bf16*)nv.wtfrag + (size_t)(l - 1) * W * W) + z, CF::DX_GLOBAL, &K};
+        WBwd<PREC, W> wb_p{wl + (size_t)(l - 1) * W * 256,
+                           (const float*)nv.wrow + z + (size_t)W * KP + (size_t)(l - 1) * W * W,
+                           (const u32x4*)((const __bf16*)nv.wtfrag + (size_t)(l - 1) * W * W) + z, CF::DX_GLOBAL, &K};
+        const WBwdBuf<W> wb_b{raw_rsrc(nv.wtfrag, BF ? wtfrag_elems(nv.s) * 2 : 0), z + (l - 1) * W * W * 2,
+                              lane_id() * 16};
         uint32_t Gn[NB][SR];
 #pragma unroll
         for (int ib = 0; ib < NB; ib += 2) {
           floatx16 a0 = floatx16{}, a1 = floatx16{};
-          layer_block2<PREC, NB>(wb, ib, Gc, a0, a1);
+          if constexpr (BF && CF::DX_HBM) layer_block2<PREC, NB>(wb_b, ib, Gc, a0, a1);
+          else layer_block2<PREC, NB>(wb_p, ib, Gc, a0, a1);
           store_masked<PREC>(a0, Gn[ib], Hs[l - 1][ib]);
           store_masked<PREC>(a1, Gn[ib + 1], Hs[l - 1][ib + 1]);
         }
@@ -1177,7 +1237,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
     if ((int64_t)blockIdx.x >= n_iter) {
       static_for<0, H>([&](auto lc) {
         constexpr int l = decltype(lc)::value;
-        if constexpr (!CF::reg_layer(l)) {
+        if constexpr (CF::fold_layer(l)) {
           const int64_t n_el = (int64_t)W * nv.s.win(l);
           for (int64_t q = threadIdx.x; q < n_el; q += blockDim.x) partial[nv.s.woff(l) + q] = 0.f;
         }
@@ -1208,6 +1268,25 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
           }
         }
     });
+  }
+  if constexpr (CF::DW0_LDS) {
+    // layer 0's dW from the wave's LDS region (every work-group writes its row)
+    const int win = nv.s.win(0);
+#pragma unroll
+    for (int a = 0; a < OBW; ++a)
+#pragma unroll
+      for (int b = 0; b < NIB0 / 2; ++b) {
+        const int ob = wo * OBW + a, ib = wi * (NIB0 / 2) + b, i = 32 * ib + fl;
+        const floatx4* q = (const floatx4*)dw0 + ((wave * OBW + a) * (NIB0 / 2) + b) * 256 + lane_id();
+        if (i < win) {
+#pragma unroll
+          for (int qd = 0; qd < 4; ++qd) {
+            const floatx4 v = q[64 * qd];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) partial[(size_t)sfeat(ob, 4 * qd + e, h) * win + i] = v[e];
+          }
+        }
+      }
   }
   // biases (waves of the first input column own them) and head: combine the lane halves
 #pragma unroll

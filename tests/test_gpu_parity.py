@@ -345,6 +345,24 @@ def test_fit_iid_matches_oracle_and_resumes(gpu_lib, sphere):
     assert np.max(np.abs(la - lo) / lo) <= 1e-5
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_fit_iid_leaf_slots_matches_oracle(gpu_lib, sphere, prec):
+    """The training kernel draws i.i.d. leaf-slot samples itself (level-0 classifier):
+    losses of 5 steps against the oracle drawing the same SplitMix64 indices."""
+    tr, ot = sphere
+    shapes = mlp.layer_shapes(36, 64, 3, 1)
+    B = workloads.pe_matrix(6)
+    th0 = workloads.init_params(36, 64, 3, 1, seed=4)
+    p = gpu_lib.FP32 if prec == "fp32" else gpu_lib.BF16
+    m = gpu_lib.Model({1: (64, 3, 18, 1)}, precision=p, domain_size=64, value_scale=3.0)
+    m.set_params(1, th0)
+    m.set_encoding(1, B)
+    lg = m.fit(tr, steps=5, batch=3000, nets_mask=2, seed=29)[1]
+    _, _, _, lo = F.train(th0.astype(np.float64), shapes, B.astype(np.float64), ot, "l0", (0, 0, 0), 64, T.SDF, 3.0,
+                          steps=5, batch=3000, seed=29)
+    assert np.max(np.abs(lg - lo) / lo) <= (1e-5 if p == gpu_lib.FP32 else 2e-2)
+
+
 def test_fit_state_and_input_errors(gpu_lib, sphere):
     tr, _ = sphere
     m = gpu_lib.Model({0: (64, 3, 18, 1)}, precision=gpu_lib.BF16, domain_size=64, value_scale=3.0)
