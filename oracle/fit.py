@@ -265,3 +265,33 @@ def errors(tr, vhat, kind, pred_mask=None):
         fn = sum(bin(int(w)).count("1") for w in np.bitwise_and(~pred_mask, truth).reshape(-1))
         rep["fp"], rep["fn"] = int(fp), int(fn)
     return rep
+
+
+def query_hits(tr, q):
+    """Online random access, step 1 (Sec. 3.5): the explicit tree decides for each
+    query position q (float, index space; voxel p covers [p, p+1) per axis) whether
+    it falls on an active voxel.  The voxel is floor(q); it is a hit iff its leaf
+    exists and the leaf's active mask holds it (the voxel is in the tree's active
+    set).  Non-finite queries and queries outside int32 are misses."""
+    q = np.asarray(q, np.float64).reshape(-1, 3)
+    ok = np.all(np.isfinite(q), axis=1) & np.all(np.abs(q) < 2.0 ** 31 - 2, axis=1)
+    p = np.zeros((len(q), 3), np.int64)
+    p[ok] = np.floor(q[ok]).astype(np.int64)
+    active = {tuple(v) for v in np.asarray(tr["ijk"], np.int64).tolist()}
+    return np.array([bool(ok[i]) and tuple(p[i]) in active for i in range(len(q))], dtype=bool)
+
+
+def query_values(theta, shapes, B, tr, lo, D, kind, band, q, background):
+    """Online random access of the [Hash,5,4,NN(3)] configuration (Sec. 3.5): a hit
+    gets the regressor's value at its own position, normalised like the voxel
+    centres, x = (q - lo) / D (so q = p + 1/2 reproduces the decode of voxel p),
+    scaled back to value units; every other query gets `background` (the volumes
+    here hold no active tiles).  Returns (values, hits)."""
+    q = np.asarray(q, np.float64).reshape(-1, 3)
+    hits = query_hits(tr, q)
+    vals = np.full(len(q), float(background))
+    if hits.any():
+        x = (q[hits] - np.asarray(lo, np.float64)) / float(D)
+        y = _batched_predict(theta, shapes, B, x)[:, 0]
+        vals[hits] = y * band if kind == T.SDF else y
+    return vals, hits

@@ -204,3 +204,42 @@ def test_topology_from_true_decisions_is_the_tree(sphere):
     N = len(tr["values"])
     assert (rep["n_pred"], rep["fp"], rep["fn"], rep["n_common"]) == (N - 2, 3, 5, N - 5)
     assert rep["max_abs"] == 0.5 and np.isclose(rep["rms"], np.sqrt(0.25 / (N - 5)))
+
+
+def test_query_random_access_pins():
+    """Random access (Sec. 3.5): queries at active voxel centres reproduce the
+    decode of those voxels; the hit set equals a brute-force walk over leaf
+    origins and masks; misses (outside every leaf, inactive voxels inside a
+    leaf, non-finite positions) get the background value."""
+    import workloads
+    v = workloads.sphere_sdf(n=24, center=(12.0, 12.0, 12.0), radius=7.0).numpy()
+    ijk, vals = T.active_set_dense(v, (-5, 3, 0), T.SDF, 2.0)
+    tr = T.build(ijk, vals)
+    shapes = mlp.layer_shapes(36, 16, 2, 1)
+    th = np.random.default_rng(0).uniform(-0.5, 0.5, mlp.param_count(36, 16, 2, 1))
+    B = mlp.pe_matrix(6)
+    lo, D = (-5, 3, 0), 24
+    idx = np.arange(0, len(vals), 7)
+    qc = tr["ijk"][idx].astype(np.float64) + 0.5
+    vq, hq = F.query_values(th, shapes, B, tr, lo, D, T.SDF, 2.0, qc, background=9.0)
+    assert hq.all()
+    assert np.array_equal(vq, F.decode_values(th, shapes, B, tr, lo, D, T.SDF, 2.0, idx=idx))
+    rng = np.random.default_rng(1)
+    q = rng.uniform(-8.0, 30.0, (3000, 3))
+    q[:5] = [[np.nan, 0, 0], [np.inf, 1, 1], [0.0, 0.0, -np.inf], [1e12, 0, 0], [-3e9, 5, 5]]
+    hits = F.query_hits(tr, q)
+    # brute force: leaf lookup by origin, then the mask bit
+    leaves = {tuple(o): i for i, o in enumerate(np.asarray(tr["leaf_origin"], np.int64).tolist())}
+    want = np.zeros(len(q), bool)
+    for i, p in enumerate(q):
+        if not np.all(np.isfinite(p)) or np.any(np.abs(p) >= 2.0 ** 31 - 2):
+            continue
+        c = np.floor(p).astype(np.int64)
+        li = leaves.get(tuple(c & ~7))
+        if li is None:
+            continue
+        n0 = int(((c[0] & 7) << 6) | ((c[1] & 7) << 3) | (c[2] & 7))
+        want[i] = bool((int(tr["leaf_mask"][li, n0 >> 6]) >> (n0 & 63)) & 1)
+    assert np.array_equal(hits, want) and 0 < hits.sum() < len(q)
+    vq, hq = F.query_values(th, shapes, B, tr, lo, D, T.SDF, 2.0, q, background=9.0)
+    assert np.array_equal(hq, hits) and np.all(vq[~hits] == 9.0) and np.all(np.abs(vq[hits]) < 9.0)
