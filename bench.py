@@ -61,6 +61,7 @@ def main():
     ap.add_argument("--skip-sequence", action="store_true")
     ap.add_argument("--skip-cloud", action="store_true")
     ap.add_argument("--skip-small", action="store_true")
+    ap.add_argument("--skip-query", action="store_true")
     ap.add_argument("--seq-frames", type=int, default=16)
     ap.add_argument("--seq-cap", type=int, default=2000)
     ap.add_argument("--seq-full-width", action="store_true",
@@ -255,6 +256,9 @@ def main():
                 "note": "BF16 job of fit_steps steps plus the continued steps, against the FP32 job"}
         print("fp32 job: %.3f s" % s32, file=sys.stderr, flush=True)
 
+    if not args.skip_query:
+        print("random-access leg ...", file=sys.stderr, flush=True)
+        out["random_access"] = random_access_leg(bf, tree)
     if not args.skip_cpu:
         print("cpu baseline (FP64 oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(grid)
@@ -439,6 +443,40 @@ def cloud_leg(fit_steps, tuned_g):
                     "frac_of_fp8_peak": N * flops_fwd(2 * M, W, H, C) / dec8_s / 1e12 / 5000.0,
                     "l1_slots_per_s": 4096 * L1 / l18_s, "rms_err": rep8["rms"], "max_abs_err": rep8["max_abs"],
                     "l1": {"fp": r18["fp"], "fn": r18["fn"], "mismatch": r18["mismatch"]}}}
+
+
+def random_access_leg(model, tree, n=1 << 20, batch=1 << 16, reps=5):
+    """Online random access (the tree decides, the regressor runs on active-voxel
+    hits only) of n uniform positions in the 512^3 box, in batches of 2^16 as the
+    paper measures it, against the pure network (the regressor on every
+    position); median of `reps` after one warm-up, the trained BF16 networks."""
+    import numpy as np
+    import torch
+
+    g = torch.Generator(device="cuda").manual_seed(5)
+    q = torch.rand((n, 3), generator=g, device="cuda") * float(N_GRID)
+    x = (q / float(N_GRID)).contiguous()
+
+    def timed(f):
+        f()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            f()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts))
+
+    _, hits = model.query(tree, q, background=BAND, batch=batch, return_hits=True)
+    t_q = timed(lambda: model.query(tree, q, background=BAND, batch=batch))
+    t_q1 = timed(lambda: model.query(tree, q, background=BAND, batch=0))
+    t_nn = timed(lambda: model.forward(0, x))
+    return {"queries": n, "batch": batch, "hit_fraction": float(hits.float().mean().item()),
+            "query_ms": t_q * 1e3, "queries_per_s": n / t_q, "query_ms_one_pass": t_q1 * 1e3,
+            "pure_network_ms": t_nn * 1e3,
+            "note": "uniform positions in the grid box; batches of 2^16 cost 4 launches each; one pass = all "
+                    "queries in one batch; pure network = regressor on every position (one launch)"}
 
 
 def small_leg(reps=5):

@@ -332,6 +332,22 @@ typedef struct {
 } nvdb_l1_report;
 nvdb_status nvdb_errors_l1(const nvdb_tree* tree, const uint8_t* classes_dev, nvdb_l1_report* out, void* stream);
 
+/* Online random access of the [Hash,5,4,NN(3)] configuration (Sec. 3.5):
+ * values at n query positions q_dev float32[n][3] in index space (voxel p
+ * covers [p, p+1) per axis).  The explicit tree decides each query: its voxel
+ * floor(q) is a hit when the voxel's leaf exists and its active mask holds it;
+ * hits get the regressor's value at q, normalised like the voxel centres
+ * ((q - domain_lo) / domain_size) and scaled back by value_scale, so a query at
+ * a voxel centre returns that voxel's decoded value; every other query
+ * (including non-finite positions) gets `background` (the trees built here
+ * hold no active tiles).  The regressor runs only on the hits.  Queries are
+ * processed in batches of `batch` (0: all at once).  hits_dev (uint8[n], may
+ * be NULL) receives 1 for regressor queries.  Device buffers; synchronises
+ * `stream`.  Errors: E_INVALID (bad buffers or sizes, n >= 2^31, non-finite
+ * background), E_STATE (regressor missing or unset). */
+nvdb_status nvdb_query(const nvdb_model* model, const nvdb_tree* tree, const float* q_dev, int64_t n, float background,
+                       int64_t batch, float* values_dev, uint8_t* hits_dev, void* stream);
+
 /* ------------------------------------------------- device-pointer calls */
 /* Used by the autograd binding; no allocation beyond the model's workspace,
  * no synchronisation.

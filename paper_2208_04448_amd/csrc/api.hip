@@ -1034,6 +1034,49 @@ nvdb_status nvdb_errors_l1(const nvdb_tree* tree, const uint8_t* classes_dev, nv
 }
 
 // ------------------------------------------------------------------ device-pointer calls
+nvdb_status nvdb_query(const nvdb_model* m, const nvdb_tree* tree, const float* q_dev, int64_t n, float background,
+                       int64_t batch, float* values_dev, uint8_t* hits_dev, void* stream) {
+  return guarded([&] {
+    NVDB_REQUIRE(m && tree, NVDB_E_INVALID, "null argument");
+    NVDB_REQUIRE(n >= 0 && (n == 0 || (q_dev && values_dev)), NVDB_E_INVALID, "bad buffers");
+    NVDB_REQUIRE(batch >= 0 && n < (1ll << 31), NVDB_E_INVALID, "bad query count or batch");
+    NVDB_REQUIRE(std::isfinite(background), NVDB_E_INVALID, "background must be finite");
+    const Net& N = net_of(m, NVDB_NET_REGRESSOR);
+    NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "regressor parameters or encoding not set");
+    if (n == 0) return;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t bs = batch > 0 ? std::min<int64_t>(batch, n) : n;
+    DevBuf<float> hit_x, y;
+    DevBuf<uint32_t> hit_idx, cnt;
+    hit_x.alloc(3 * (size_t)bs);
+    y.alloc((size_t)bs);
+    hit_idx.alloc((size_t)bs);
+    cnt.alloc(1);
+    const float inv_d = 1.f / (float)m->d.domain_size;
+    for (int64_t b0 = 0; b0 < n; b0 += bs) {
+      const int64_t nb = std::min(bs, n - b0);
+      query_zero_count(cnt.p, st);
+      query_classify(q_dev + 3 * b0, nb, *tree, background, m->d.domain_lo, inv_d, values_dev + b0,
+                     hits_dev ? hits_dev + b0 : nullptr, hit_x.p, hit_idx.p, cnt.p, st);
+      // the regressor over the batch's hits: launched for nb samples, it reads the
+      // hit count on the device (waves past it exit at once)
+      InferLaunch I{};
+      I.net = net_view(N);
+      base_spec(m, &I.spec);
+      I.spec.src = SRC_COORDS;
+      I.spec.direct = 1;
+      I.spec.coords = hit_x.p;
+      I.spec.n = nb;
+      I.spec.n_dev = cnt.p;
+      I.out_kind = OUT_Y;
+      I.y = y.p;
+      launch_infer(N.ks, I, infer_grid(nb), st);
+      query_scatter(y.p, hit_idx.p, nb, cnt.p, m->d.value_scale, values_dev + b0, st);
+    }
+    NVDB_HIP(hipStreamSynchronize(st));
+  });
+}
+
 nvdb_status nvdb_forward_dev(const nvdb_model* m, int32_t net, const float* x_dev, int64_t n, float* y_dev,
                              void* stream) {
   return guarded([&] {

@@ -1339,7 +1339,8 @@ __global__ void __launch_bounds__(64 * NVDB_INFER_WAVES, 1)
   constexpr bool BF = (PREC == NVDB_BF16);
   __shared__ __attribute__((aligned(16))) char smem[CF::LDS_BYTES];
   const NetView& nv = I.net;
-  const SampleSpec& sp = I.spec;
+  SampleSpec sp = I.spec;
+  if (sp.n_dev) sp.n = min(sp.n, (int64_t)*sp.n_dev);  // count known only on the device
   const int wave = wave_id();
 
   char* wl0 = smem;
@@ -1636,7 +1637,8 @@ __global__ void __launch_bounds__(64 * NVDB_INFER8_WAVES, NVDB_INFER8_WGS)
   constexpr int NA = NB > NIB0 ? NB : NIB0;
   __shared__ __attribute__((aligned(16))) char smem[CF::LDS_BYTES];
   const NetView& nv = I.net;
-  const SampleSpec& sp = I.spec;
+  SampleSpec sp = I.spec;
+  if (sp.n_dev) sp.n = min(sp.n, (int64_t)*sp.n_dev);  // count known only on the device
   const int wave = wave_id();
 
   char* wl0 = smem;

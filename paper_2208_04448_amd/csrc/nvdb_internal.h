@@ -128,6 +128,7 @@ struct SampleSpec {
   float inv_d;            // 1 / box size
   const float* coords;    // SRC_COORDS: [n][3]
   const float* gy;        // LOSS_EXTERNAL: [n][n_out]
+  const uint32_t* n_dev;  // decode: optional device-side count, the samples are the first min(n, *n_dev)
 };
 
 // ----------------------------------------------------------- net layout
@@ -265,6 +266,12 @@ void launch_fill(float* p, int64_t n, float v, hipStream_t st);
 // tree.hip
 Tree* build_tree_dense(const float* grid, const int32_t dims[3], const int32_t origin[3], const nvdb_active_rule& rule,
                        hipStream_t st);
+// query.hip
+void query_classify(const float* q, int64_t n, const Tree& tree, float background, const int32_t lo[3], float inv_d,
+                    float* values, uint8_t* hits, float* hit_x, uint32_t* hit_idx, uint32_t* n_hits, hipStream_t st);
+void query_scatter(const float* y, const uint32_t* idx, int64_t n, const uint32_t* n_hits, float scale, float* values,
+                   hipStream_t st);
+void query_zero_count(uint32_t* c, hipStream_t st);
 // sparse.hip
 Tree* build_tree_sparse(const int32_t* ijk, const float* v, int64_t n, const nvdb_active_rule& rule, hipStream_t st);
 void error_report(const Tree& t, const float* values, const uint64_t* pred_mask, nvdb_error_report* rep,

@@ -1,0 +1,112 @@
+// Online random access of the [Hash,5,4,NN(3)] configuration (NeuralVDB Sec. 3.5).
+//
+// The explicit tree decides each query: its voxel floor(q) is a hit when its
+// leaf exists (binary search over the leaf origins, which are stored in the
+// canonical order: level-2 origin, then n2, then n1) and the leaf's active mask
+// holds it.  Hits are compacted and only they run through the regressor (whose
+// launch reads the hit count on the device, so batches need no host round trip);
+// every other query gets the background value.
+#include <algorithm>
+#include <cmath>
+
+#include "nvdb_internal.h"
+
+namespace nvdb {
+
+namespace {
+
+// Canonical order of two leaf origins (both multiples of 8): level-2 origin
+// (arithmetic shifts floor negative coordinates), then the level-1 slot n2,
+// then the leaf slot n1.
+__device__ __forceinline__ bool leaf_before(const int4& a, const int4& b) {
+  if ((a.x >> 12) != (b.x >> 12)) return (a.x >> 12) < (b.x >> 12);
+  if ((a.y >> 12) != (b.y >> 12)) return (a.y >> 12) < (b.y >> 12);
+  if ((a.z >> 12) != (b.z >> 12)) return (a.z >> 12) < (b.z >> 12);
+  const int an2 = (((a.x >> 7) & 31) << 10) | (((a.y >> 7) & 31) << 5) | ((a.z >> 7) & 31);
+  const int bn2 = (((b.x >> 7) & 31) << 10) | (((b.y >> 7) & 31) << 5) | ((b.z >> 7) & 31);
+  if (an2 != bn2) return an2 < bn2;
+  const int an1 = (((a.x >> 3) & 15) << 8) | (((a.y >> 3) & 15) << 4) | ((a.z >> 3) & 15);
+  const int bn1 = (((b.x >> 3) & 15) << 8) | (((b.y >> 3) & 15) << 4) | ((b.z >> 3) & 15);
+  return an1 < bn1;
+}
+
+struct QueryTree {
+  const int4* leaf_o;
+  const uint64_t* leaf_mask;
+  int64_t n_leaf;
+};
+
+// Per query: hit test; misses get the background, hits are appended (in any
+// order: each value depends only on its own query) with their normalised
+// position and query index.
+__global__ void __launch_bounds__(256) k_query_classify(const float* __restrict__ q, int64_t n, QueryTree t, float bg,
+                                                        int lo0, int lo1, int lo2, float inv_d, float* __restrict__ values,
+                                                        uint8_t* __restrict__ hits, float* __restrict__ hit_x,
+                                                        uint32_t* __restrict__ hit_idx, uint32_t* n_hits) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float qx = q[3 * i], qy = q[3 * i + 1], qz = q[3 * i + 2];
+  const float lim = 2147483648.f;  // 2^31: every float below it floors into int32
+  bool hit = isfinite(qx) && isfinite(qy) && isfinite(qz) && fabsf(qx) < lim && fabsf(qy) < lim && fabsf(qz) < lim;
+  if (hit) {
+    const int px = (int)floorf(qx), py = (int)floorf(qy), pz = (int)floorf(qz);
+    const int4 o = make_int4(px & ~7, py & ~7, pz & ~7, 0);
+    int64_t a = 0, b = t.n_leaf;  // first leaf not before o
+    while (a < b) {
+      const int64_t m = (a + b) >> 1;
+      if (leaf_before(t.leaf_o[m], o)) a = m + 1;
+      else b = m;
+    }
+    hit = false;
+    if (a < t.n_leaf) {
+      const int4 f = t.leaf_o[a];
+      if (f.x == o.x && f.y == o.y && f.z == o.z) {
+        const uint32_t n0 = (uint32_t)(((px & 7) << 6) | ((py & 7) << 3) | (pz & 7));
+        hit = (t.leaf_mask[a * 8 + (n0 >> 6)] >> (n0 & 63u)) & 1ull;
+      }
+    }
+  }
+  if (hits) hits[i] = hit ? 1 : 0;
+  if (!hit) {
+    values[i] = bg;
+    return;
+  }
+  const uint32_t s = atomicAdd(n_hits, 1u);
+  hit_x[3 * (size_t)s] = (qx - (float)lo0) * inv_d;
+  hit_x[3 * (size_t)s + 1] = (qy - (float)lo1) * inv_d;
+  hit_x[3 * (size_t)s + 2] = (qz - (float)lo2) * inv_d;
+  hit_idx[s] = (uint32_t)i;
+}
+
+__global__ void __launch_bounds__(256) k_query_scatter(const float* __restrict__ y, const uint32_t* __restrict__ idx,
+                                                       int64_t n, const uint32_t* n_hits, float scale,
+                                                       float* __restrict__ values) {
+  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h < n && h < (int64_t)*n_hits) values[idx[h]] = y[h] * scale;
+}
+__global__ void k_query_zero(uint32_t* c) { *c = 0u; }
+
+}  // namespace
+
+void query_classify(const float* q, int64_t n, const Tree& tree, float background, const int32_t lo[3], float inv_d,
+                    float* values, uint8_t* hits, float* hit_x, uint32_t* hit_idx, uint32_t* n_hits, hipStream_t st) {
+  if (n <= 0) return;
+  QueryTree t{tree.leaf_o.p, tree.leaf_mask.p, tree.n_leaf};
+  hipLaunchKernelGGL(k_query_classify, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, q, n, t, background, lo[0],
+                     lo[1], lo[2], inv_d, values, hits, hit_x, hit_idx, n_hits);
+  NVDB_HIP(hipGetLastError());
+}
+
+void query_scatter(const float* y, const uint32_t* idx, int64_t n, const uint32_t* n_hits, float scale, float* values,
+                   hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_query_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, y, idx, n, n_hits, scale,
+                     values);
+  NVDB_HIP(hipGetLastError());
+}
+void query_zero_count(uint32_t* c, hipStream_t st) {
+  hipLaunchKernelGGL(k_query_zero, dim3(1), dim3(1), 0, st, c);
+  NVDB_HIP(hipGetLastError());
+}
+
+}  // namespace nvdb

@@ -84,6 +84,7 @@ _SIGS = {
                                           C.POINTER(_P)]),
     "nvdb_tree_build_sparse": (C.c_int32, [_P, _P, C.c_int64, C.POINTER(ActiveRule), _P, C.POINTER(_P)]),
     "nvdb_tree_get_info": (C.c_int32, [_P, C.POINTER(TreeInfo)]),
+    "nvdb_query": (C.c_int32, [_P, _P, _P, C.c_int64, C.c_float, C.c_int64, _P, _P, _P]),
     "nvdb_tree_export_l2": (C.c_int32, [_P, _P, _P]),
     "nvdb_tree_export": (C.c_int32, [_P, _P, _P, _P, _P, _P, _P]),
     "nvdb_tree_free": (None, [_P]),
@@ -335,6 +336,18 @@ class Model:
         t.h = h
         t.kind = upper.kind
         return t
+
+    def query(self, tree, q, background, batch=0, return_hits=False):
+        """Online random access: values at float32 index-space positions q [n, 3]
+        (device tensor); returns values (and uint8 hit flags)."""
+        import torch
+        q = q.contiguous().reshape(-1, 3)
+        assert q.is_cuda and q.dtype == torch.float32
+        n = q.shape[0]
+        v = torch.empty(n, dtype=torch.float32, device=q.device)
+        h = torch.empty(n, dtype=torch.uint8, device=q.device) if return_hits else None
+        _check(_lib.nvdb_query(self.h, tree.h, _ptr(q), n, float(background), int(batch), _ptr(v), _ptr(h), _stream()))
+        return (v, h) if return_hits else v
 
     def forward(self, net, x):
         import torch

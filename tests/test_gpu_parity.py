@@ -363,6 +363,55 @@ def test_fit_iid_leaf_slots_matches_oracle(gpu_lib, sphere, prec):
     assert np.max(np.abs(lg - lo) / lo) <= (1e-5 if p == gpu_lib.FP32 else 2e-2)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_query_random_access(gpu_lib, sphere, prec):
+    """Online random access (Sec. 3.5): hit decisions bit-exact against the oracle's
+    tree walk, values within the forward tolerance (in value units, band 3), queries
+    at voxel centres bit-equal to the full decode, batches of any size equal."""
+    tr, ot = sphere
+    shapes = mlp.layer_shapes(36, 64, 3, 1)
+    B = workloads.pe_matrix(6)
+    th = workloads.init_params(36, 64, 3, 1, seed=12)
+    p = gpu_lib.FP32 if prec == "fp32" else gpu_lib.BF16
+    m = gpu_lib.Model({0: (64, 3, 18, 1)}, precision=p, domain_size=64, value_scale=3.0)
+    m.set_params(0, th)
+    m.set_encoding(0, B)
+    rng = np.random.default_rng(8)
+    sel = rng.choice(len(ot["values"]), 1500, replace=False)
+    q = np.concatenate([rng.uniform(-6.0, 70.0, (20000, 3)), ot["ijk"][sel] + 0.5,
+                        [[np.nan, 1.0, 1.0], [1.0, np.inf, 1.0], [3e9, 0.0, 0.0], [-1e10, 5.0, 5.0], [63.999, 32.0, 32.0]]])
+    q = q.astype(np.float32)
+    qd = torch.from_numpy(q).to(DEV)
+    v, h = m.query(tr, qd, background=3.0, batch=0, return_hits=True)
+    v2 = m.query(tr, qd, background=3.0, batch=777)
+    assert torch.equal(v, v2)
+    v, h = v.cpu().numpy(), h.cpu().numpy().astype(bool)
+    ov, oh = F.query_values(th.astype(np.float64), shapes, B.astype(np.float64), ot, (0, 0, 0), 64, T.SDF, 3.0,
+                            q.astype(np.float64), 3.0)
+    assert np.array_equal(h, oh) and 0 < h.sum() < len(q)
+    assert np.all(v[~h] == 3.0)
+    tol = 3e-5 if p == gpu_lib.FP32 else 6e-2
+    assert np.max(np.abs(v[h] - ov[h]) / (1.0 + np.abs(ov[h]))) <= tol
+    dv, _ = m.decode(tr, masks=False)
+    n0 = 20000
+    assert np.array_equal(v[n0:n0 + len(sel)], dv.cpu().numpy()[sel])
+
+
+def test_query_rejects_bad_arguments(gpu_lib, sphere):
+    tr, _ = sphere
+    m = gpu_lib.Model({0: (64, 3, 18, 1)}, precision=gpu_lib.FP32, domain_size=64, value_scale=3.0)
+    q = torch.zeros((4, 3), device=DEV)
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        m.query(tr, q, background=0.0)
+    assert e.value.code == gpu_lib.E_STATE
+    m.set_params(0, workloads.init_params(36, 64, 3, 1, seed=1))
+    m.set_encoding(0, workloads.pe_matrix(6))
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        m.query(tr, q, background=float("nan"))
+    assert e.value.code == gpu_lib.E_INVALID
+    assert m.query(tr, torch.zeros((0, 3), device=DEV), background=1.0).numel() == 0
+
+
 def test_fit_state_and_input_errors(gpu_lib, sphere):
     tr, _ = sphere
     m = gpu_lib.Model({0: (64, 3, 18, 1)}, precision=gpu_lib.BF16, domain_size=64, value_scale=3.0)
