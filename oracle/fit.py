@@ -295,3 +295,21 @@ def query_values(theta, shapes, B, tr, lo, D, kind, band, q, background):
         y = _batched_predict(theta, shapes, B, x)[:, 0]
         vals[hits] = y * band if kind == T.SDF else y
     return vals, hits
+
+
+def topology_patches(true_ijk, pred_ijk):
+    """Patches (Sec. 3.3.1; Tab. memory_cost counts them at 12 bytes a coordinate):
+    the predicted voxels that are not active (false positives) and the active
+    voxels that were not predicted (false negatives), each list in the tree's
+    canonical voxel order.  Removing the first list from the prediction and adding
+    the second restores the true active set exactly."""
+    kt, kp = _voxel_keys(true_ijk), _voxel_keys(pred_ijk)
+    fp = np.asarray(pred_ijk, np.int64)[~np.isin(kp, kt)]
+    fn = np.asarray(true_ijk, np.int64)[~np.isin(kt, kp)]
+
+    def canonical(ijk):
+        if len(ijk) == 0:
+            return np.zeros((0, 3), np.int32)
+        return T.build(ijk.astype(np.int32), np.zeros(len(ijk)))["ijk"]
+
+    return canonical(fp), canonical(fn)

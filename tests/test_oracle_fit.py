@@ -243,3 +243,22 @@ def test_query_random_access_pins():
     assert np.array_equal(hits, want) and 0 < hits.sum() < len(q)
     vq, hq = F.query_values(th, shapes, B, tr, lo, D, T.SDF, 2.0, q, background=9.0)
     assert np.array_equal(hq, hits) and np.all(vq[~hits] == 9.0) and np.all(np.abs(vq[hits]) < 9.0)
+
+
+def test_topology_patches_restore_the_active_set():
+    """Patches: brute-force set differences, canonical order (that of the tree
+    build), and pred - fp + fn equals the true active set."""
+    rng = np.random.default_rng(3)
+    truth = np.unique(rng.integers(-20, 20, (400, 3)), axis=0)
+    keep = rng.random(len(truth)) < 0.8
+    extra = np.unique(rng.integers(-20, 20, (120, 3)), axis=0)
+    pred = np.unique(np.concatenate([truth[keep], extra]), axis=0)
+    fp, fn = F.topology_patches(truth, pred)
+    ts, ps = set(map(tuple, truth.tolist())), set(map(tuple, pred.tolist()))
+    assert set(map(tuple, fp.tolist())) == ps - ts and len(fp) == len(ps - ts)
+    assert set(map(tuple, fn.tolist())) == ts - ps and len(fn) == len(ts - ps)
+    assert len(fp) > 0 and len(fn) > 0
+    assert np.array_equal(fp, T.build(fp, np.zeros(len(fp)))["ijk"])
+    assert (ps - set(map(tuple, fp.tolist()))) | set(map(tuple, fn.tolist())) == ts
+    e, f = F.topology_patches(truth, truth)
+    assert len(e) == 0 and len(f) == 0
