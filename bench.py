@@ -423,11 +423,23 @@ def cloud_leg(fit_steps, tuned_g):
         dt = time.perf_counter() - t0
         rt = nvdb.errors_topology(tree, pred)
         pi = pred.info()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fpl, fnl = nvdb.topology_patches(tree, pred)
+        torch.cuda.synchronize()
+        patch_s = time.perf_counter() - t0
+        # storage (Sec. 4, Tab. memory_cost accounting): the explicit tree against the
+        # [Hash,5,NN(4),NN(3)] form with 16-bit networks and 12-byte patch coordinates
+        explicit = int(info.bytes_l2 + info.bytes_l1 + info.bytes_leaf_masks + info.bytes_voxels)
+        nets_b = 2 * (mdl.param_count(0) + mdl.param_count(2))
+        neural = int(info.bytes_l2) + nets_b + 12 * (len(fpl) + len(fnl))
         topo[name] = {"s": dt, "predicted_leaves": int(pi.n_leaves), "predicted_voxels": int(pi.n_voxels),
                       "slots_evaluated_per_s": (4096 * L1 + 512 * int(pi.n_leaves)) / dt,
                       "fp": rt["fp"], "fn": rt["fn"], "n_common": rt["n_common"], "rms_err_common": rt["rms"],
-                      "max_abs_err_common": rt["max_abs"]}
-        del pred
+                      "max_abs_err_common": rt["max_abs"], "patches_s": patch_s,
+                      "bytes_explicit": explicit, "bytes_neural_lossless_topology": neural,
+                      "compression_ratio": explicit / neural}
+        del pred, fpl, fnl
     return {"workload": "fBm cloud 1024^3 (6 octaves, lacunarity 2, gain 0.5), active where density > 0.55; "
                         "voxel regressor 4x128 + level-1 classifier 4x64 (3 classes), FFM m=64 sigma=10, BF16; "
                         "%d steps x 2^18 samples per network" % fit_steps,

@@ -320,6 +320,18 @@ typedef struct {
 nvdb_status nvdb_errors_topology(const nvdb_tree* truth, const nvdb_tree* pred, nvdb_topology_report* out,
                                  void* stream);
 
+/* Patches (Sec. 3.3.1; 12 bytes a coordinate in Tab. memory_cost): the voxels
+ * where a decoded topology `pred` (e.g. from nvdb_decode_topology) differs from
+ * the truth: fp_dev int32[fp_cap][3] receives the predicted voxels that are not
+ * active in `truth`, fn_dev int32[fn_cap][3] the active voxels `pred` misses,
+ * each in canonical voxel order (lists beyond the caps are cut; the counts
+ * n_fp / n_fn are always complete).  Removing the first list from `pred` and
+ * adding the second restores the true active set exactly (lossless topology).
+ * Synchronises `stream`.  Errors: E_INVALID (null counts, cap > 0 with a null
+ * list). */
+nvdb_status nvdb_topology_patches(const nvdb_tree* truth, const nvdb_tree* pred, int32_t* fp_dev, int64_t fp_cap,
+                                  int32_t* fn_dev, int64_t fn_cap, int64_t* n_fp, int64_t* n_fn, void* stream);
+
 /* Level-1 classifier report (Sec. 3.3.1, Sec. 4) over the 4096 leaf slots of
  * every level-1 node: classes_dev is uint8[n_l1][4096] as written by
  * nvdb_decode_l1; the true class of a slot is 0 when it has a child leaf, else

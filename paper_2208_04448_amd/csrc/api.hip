@@ -1077,6 +1077,18 @@ nvdb_status nvdb_query(const nvdb_model* m, const nvdb_tree* tree, const float* 
   });
 }
 
+nvdb_status nvdb_topology_patches(const nvdb_tree* truth, const nvdb_tree* pred, int32_t* fp_dev, int64_t fp_cap,
+                                  int32_t* fn_dev, int64_t fn_cap, int64_t* n_fp, int64_t* n_fn, void* stream) {
+  return guarded([&] {
+    NVDB_REQUIRE(truth && pred && n_fp && n_fn, NVDB_E_INVALID, "null argument");
+    NVDB_REQUIRE(fp_cap >= 0 && fn_cap >= 0 && (fp_cap == 0 || fp_dev) && (fn_cap == 0 || fn_dev), NVDB_E_INVALID,
+                 "bad patch buffers");
+    hipStream_t st = (hipStream_t)stream;
+    *n_fp = topology_patches(*pred, *truth, fp_dev, fp_cap, st);
+    *n_fn = topology_patches(*truth, *pred, fn_dev, fn_cap, st);
+  });
+}
+
 nvdb_status nvdb_forward_dev(const nvdb_model* m, int32_t net, const float* x_dev, int64_t n, float* y_dev,
                              void* stream) {
   return guarded([&] {

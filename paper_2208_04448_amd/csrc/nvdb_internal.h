@@ -272,6 +272,8 @@ void query_classify(const float* q, int64_t n, const Tree& tree, float backgroun
 void query_scatter(const float* y, const uint32_t* idx, int64_t n, const uint32_t* n_hits, float scale, float* values,
                    hipStream_t st);
 void query_zero_count(uint32_t* c, hipStream_t st);
+// voxels of a that b lacks, canonical order, at most cap written to out [cap][3]; returns the count
+int64_t topology_patches(const Tree& a, const Tree& b, int32_t* out, int64_t cap, hipStream_t st);
 // sparse.hip
 Tree* build_tree_sparse(const int32_t* ijk, const float* v, int64_t n, const nvdb_active_rule& rule, hipStream_t st);
 void error_report(const Tree& t, const float* values, const uint64_t* pred_mask, nvdb_error_report* rep,

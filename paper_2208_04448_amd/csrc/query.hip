@@ -5,7 +5,8 @@
 // canonical order: level-2 origin, then n2, then n1) and the leaf's active mask
 // holds it.  Hits are compacted and only they run through the regressor (whose
 // launch reads the hit count on the device, so batches need no host round trip);
-// every other query gets the background value.
+// every other query gets the background value.  The same leaf lookup lists the
+// patches of a decoded topology (voxels it adds or misses).
 #include <algorithm>
 #include <cmath>
 
@@ -36,6 +37,21 @@ struct QueryTree {
   int64_t n_leaf;
 };
 
+// Index of the leaf of t with origin o, or -1.
+__device__ __forceinline__ int64_t find_leaf(const QueryTree& t, const int4& o) {
+  int64_t a = 0, b = t.n_leaf;
+  while (a < b) {
+    const int64_t m = (a + b) >> 1;
+    if (leaf_before(t.leaf_o[m], o)) a = m + 1;
+    else b = m;
+  }
+  if (a < t.n_leaf) {
+    const int4 f = t.leaf_o[a];
+    if (f.x == o.x && f.y == o.y && f.z == o.z) return a;
+  }
+  return -1;
+}
+
 // Per query: hit test; misses get the background, hits are appended (in any
 // order: each value depends only on its own query) with their normalised
 // position and query index.
@@ -50,20 +66,11 @@ __global__ void __launch_bounds__(256) k_query_classify(const float* __restrict_
   bool hit = isfinite(qx) && isfinite(qy) && isfinite(qz) && fabsf(qx) < lim && fabsf(qy) < lim && fabsf(qz) < lim;
   if (hit) {
     const int px = (int)floorf(qx), py = (int)floorf(qy), pz = (int)floorf(qz);
-    const int4 o = make_int4(px & ~7, py & ~7, pz & ~7, 0);
-    int64_t a = 0, b = t.n_leaf;  // first leaf not before o
-    while (a < b) {
-      const int64_t m = (a + b) >> 1;
-      if (leaf_before(t.leaf_o[m], o)) a = m + 1;
-      else b = m;
-    }
+    const int64_t a = find_leaf(t, make_int4(px & ~7, py & ~7, pz & ~7, 0));
     hit = false;
-    if (a < t.n_leaf) {
-      const int4 f = t.leaf_o[a];
-      if (f.x == o.x && f.y == o.y && f.z == o.z) {
-        const uint32_t n0 = (uint32_t)(((px & 7) << 6) | ((py & 7) << 3) | (pz & 7));
-        hit = (t.leaf_mask[a * 8 + (n0 >> 6)] >> (n0 & 63u)) & 1ull;
-      }
+    if (a >= 0) {
+      const uint32_t n0 = (uint32_t)(((px & 7) << 6) | ((py & 7) << 3) | (pz & 7));
+      hit = (t.leaf_mask[a * 8 + (n0 >> 6)] >> (n0 & 63u)) & 1ull;
     }
   }
   if (hits) hits[i] = hit ? 1 : 0;
@@ -86,7 +93,57 @@ __global__ void __launch_bounds__(256) k_query_scatter(const float* __restrict__
 }
 __global__ void k_query_zero(uint32_t* c) { *c = 0u; }
 
+// Patches: per leaf of A, the voxels of A that B lacks (A = prediction, B = truth
+// gives the false positives; the other way round the false negatives).
+__global__ void __launch_bounds__(256) k_patch_count(QueryTree A, QueryTree B, uint64_t* __restrict__ cnt) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= A.n_leaf) return;
+  const int64_t k = find_leaf(B, A.leaf_o[l]);
+  uint64_t c = 0;
+  for (int w = 0; w < 8; ++w) c += __popcll(A.leaf_mask[l * 8 + w] & ~(k >= 0 ? B.leaf_mask[k * 8 + w] : 0ull));
+  cnt[l] = c;
+}
+__global__ void __launch_bounds__(256) k_patch_write(QueryTree A, QueryTree B, const uint64_t* __restrict__ off,
+                                                     int64_t cap, int32_t* __restrict__ out) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= A.n_leaf) return;
+  const int4 o = A.leaf_o[l];
+  const int64_t k = find_leaf(B, o);
+  int64_t s = (int64_t)off[l];
+  for (int w = 0; w < 8; ++w) {
+    uint64_t d = A.leaf_mask[l * 8 + w] & ~(k >= 0 ? B.leaf_mask[k * 8 + w] : 0ull);
+    while (d) {
+      const int n0 = 64 * w + __ffsll((long long)d) - 1;
+      d &= d - 1;
+      if (s < cap) {
+        out[3 * s] = o.x + (n0 >> 6);
+        out[3 * s + 1] = o.y + ((n0 >> 3) & 7);
+        out[3 * s + 2] = o.z + (n0 & 7);
+      }
+      ++s;
+    }
+  }
+}
+
 }  // namespace
+
+int64_t topology_patches(const Tree& a, const Tree& b, int32_t* out, int64_t cap, hipStream_t st) {
+  if (a.n_leaf == 0) return 0;
+  const QueryTree A{a.leaf_o.p, a.leaf_mask.p, a.n_leaf}, B{b.leaf_o.p, b.leaf_mask.p, b.n_leaf};
+  DevBuf<uint64_t> cnt, off;
+  cnt.alloc(a.n_leaf);
+  off.alloc(a.n_leaf);
+  const unsigned grid = (unsigned)((a.n_leaf + 255) / 256);
+  hipLaunchKernelGGL(k_patch_count, dim3(grid), dim3(256), 0, st, A, B, cnt.p);
+  NVDB_HIP(hipGetLastError());
+  const int64_t total = (int64_t)scan_u64(cnt.p, a.n_leaf, off.p, st);
+  if (out && cap > 0 && total > 0) {
+    hipLaunchKernelGGL(k_patch_write, dim3(grid), dim3(256), 0, st, A, B, off.p, cap, out);
+    NVDB_HIP(hipGetLastError());
+  }
+  NVDB_HIP(hipStreamSynchronize(st));
+  return total;
+}
 
 void query_classify(const float* q, int64_t n, const Tree& tree, float background, const int32_t lo[3], float inv_d,
                     float* values, uint8_t* hits, float* hit_x, uint32_t* hit_idx, uint32_t* n_hits, hipStream_t st) {

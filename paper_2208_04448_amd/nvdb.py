@@ -85,6 +85,8 @@ _SIGS = {
     "nvdb_tree_build_sparse": (C.c_int32, [_P, _P, C.c_int64, C.POINTER(ActiveRule), _P, C.POINTER(_P)]),
     "nvdb_tree_get_info": (C.c_int32, [_P, C.POINTER(TreeInfo)]),
     "nvdb_query": (C.c_int32, [_P, _P, _P, C.c_int64, C.c_float, C.c_int64, _P, _P, _P]),
+    "nvdb_topology_patches": (C.c_int32, [_P, _P, _P, C.c_int64, _P, C.c_int64, C.POINTER(C.c_int64),
+                                          C.POINTER(C.c_int64), _P]),
     "nvdb_tree_export_l2": (C.c_int32, [_P, _P, _P]),
     "nvdb_tree_export": (C.c_int32, [_P, _P, _P, _P, _P, _P, _P]),
     "nvdb_tree_free": (None, [_P]),
@@ -379,6 +381,18 @@ def errors_l1(tree, classes):
     r = L1Report()
     _check(_lib.nvdb_errors_l1(tree.h, _ptr(classes), C.byref(r), _stream()))
     return dict(n_slots=r.n_slots, fp=r.fp, fn=r.fn, mismatch=r.mismatch)
+
+
+def topology_patches(truth, pred):
+    """False-positive and false-negative voxel lists (device int32 [n, 3], canonical order)."""
+    import torch
+    nfp, nfn = C.c_int64(), C.c_int64()
+    _check(_lib.nvdb_topology_patches(truth.h, pred.h, None, 0, None, 0, C.byref(nfp), C.byref(nfn), _stream()))
+    fp = torch.empty((nfp.value, 3), dtype=torch.int32, device="cuda")
+    fn = torch.empty((nfn.value, 3), dtype=torch.int32, device="cuda")
+    _check(_lib.nvdb_topology_patches(truth.h, pred.h, _ptr(fp), nfp.value, _ptr(fn), nfn.value, C.byref(nfp),
+                                      C.byref(nfn), _stream()))
+    return fp, fn
 
 
 def errors_topology(truth, pred):

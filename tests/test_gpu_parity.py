@@ -830,6 +830,17 @@ def test_decode_topology_matches_oracle(gpu_lib, with_l0):
     for key in ("n_true", "n_pred", "fp", "fn", "n_common"):
         assert rep[key] == orep[key], key
     assert abs(rep["max_abs"] - orep["max_abs"]) <= 1e-6 and abs(rep["rms"] - orep["rms"]) <= 1e-9 * max(1, orep["rms"])
+    # patches: the library's lists equal the oracle's on the same decoded tree, and
+    # applying them restores the true topology exactly
+    fp, fn = gpu_lib.topology_patches(tr, pred)
+    ofp, ofn = F.topology_patches(ot["ijk"], g_ijk)
+    assert np.array_equal(fp.cpu().numpy(), ofp) and np.array_equal(fn.cpu().numpy(), ofn)
+    assert len(ofp) == rep["fp"] and len(ofn) == rep["fn"] and len(ofp) + len(ofn) > 0
+    keep = ~np.isin(F._voxel_keys(g_ijk), F._voxel_keys(ofp))
+    fixed = np.concatenate([g_ijk[keep], ofn]).astype(np.int32)
+    ft = gpu_lib.Tree.from_sparse(torch.from_numpy(fixed).to(DEV), torch.zeros(len(fixed), device=DEV), T.SDF, 3.0)
+    fe, te = ft.export(), tr.export()
+    assert np.array_equal(fe["leaf_origin"], te["leaf_origin"]) and np.array_equal(fe["leaf_mask"], te["leaf_mask"])
     # the FP8 form decodes the same topology up to its own rounding
     p8 = m.decode_topology(tr, fp8=True)
     n8 = p8.info().n_voxels
