@@ -70,7 +70,7 @@ def main():
                     help="work-groups per network; 0 runs the autotuner (profiling runs pin it)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (N=%d requested)" % args.gpus,
+        print("bench.py measures one GPU: the library has no multi-GPU path (N=%d requested)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 

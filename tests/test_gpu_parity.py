@@ -1,7 +1,7 @@
 """GPU parity: the HIP path (through the C-ABI) against the FP64 oracle on the
 same seeded inputs.
 
-Tolerances (derived in DESIGN.md, section "Tolerances"):
+Tolerances (derived from the arithmetic of each form):
   * integer work (tree arrays, sample indices, mask bits away from the decision
     boundary): bit-exact;
   * FP32 form: forward |dy| <= 1e-5 (1 + |y|); gradients <= 1e-5 relative (L2)
