@@ -256,6 +256,17 @@ def main():
                 "note": "BF16 job of fit_steps steps plus the continued steps, against the FP32 job"}
         print("fp32 job: %.3f s" % s32, file=sys.stderr, flush=True)
 
+    # the networks stored at 16 bits (Sec. 4): decode error with binary16 weights
+    saved = {k: bf.get_params(k) for k in (0, 1)}
+    for k in (0, 1):
+        bf.set_params16(k, nvdb.STORE_F16, bf.get_params16(k, nvdb.STORE_F16))
+    v16, m16 = bf.decode(tree)
+    r16 = nvdb.errors(tree, v16, m16)
+    for k in (0, 1):
+        bf.set_params(k, saved[k])
+    out["fp16_storage"] = {"max_abs_err_voxels": r16["max_abs"], "rms_err_voxels": r16["rms"], "iou": r16["iou"],
+                           "bytes_per_network": 2 * P,
+                           "note": "both networks rounded to binary16 and decoded (BF16 form)"}
     if not args.skip_query:
         print("random-access leg ...", file=sys.stderr, flush=True)
         out["random_access"] = random_access_leg(bf, tree)

@@ -153,6 +153,14 @@ nvdb_status nvdb_model_param_count(const nvdb_model* model, int32_t net, int64_t
 /* Parameters in the canonical flat layout, float32, host memory. */
 nvdb_status nvdb_model_set_params(nvdb_model* model, int32_t net, const float* params, int64_t n);
 nvdb_status nvdb_model_get_params(const nvdb_model* model, int32_t net, float* params, int64_t n);
+/* 16-bit storage of a network (Sec. 4 stores the networks at 16 bits): the
+ * canonical parameters rounded to nearest even into IEEE binary16
+ * (NVDB_STORE_F16; overflow to infinity, subnormals kept) or bfloat16
+ * (NVDB_STORE_BF16), host uint16[n]; set_params16 widens them exactly and
+ * loads them as nvdb_model_set_params does (non-finite values are rejected). */
+enum { NVDB_STORE_F16 = 0, NVDB_STORE_BF16 = 1 };
+nvdb_status nvdb_model_get_params16(const nvdb_model* model, int32_t net, int32_t kind, uint16_t* dst, int64_t n);
+nvdb_status nvdb_model_set_params16(nvdb_model* model, int32_t net, int32_t kind, const uint16_t* src, int64_t n);
 /* Feature-mapping matrix B, float32 [n_freq][3] row-major, host memory. */
 nvdb_status nvdb_model_set_encoding(nvdb_model* model, int32_t net, const float* B, int32_t n_freq);
 /* Adam state (checkpoint): first and second moments (canonical layout) and

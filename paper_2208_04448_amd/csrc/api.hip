@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <new>
 
 #include "nvdb_internal.h"
@@ -331,6 +332,88 @@ nvdb_status nvdb_model_get_params(const nvdb_model* m, int32_t net, float* param
     NVDB_HIP(hipDeviceSynchronize());
     NVDB_HIP(hipMemcpy(params, N.theta.p, n * 4, hipMemcpyDeviceToHost));
   });
+}
+
+// ---------------------------------------------------------------- 16-bit storage
+// float32 -> IEEE binary16, round to nearest even (overflow to infinity, NaN kept).
+static uint16_t f32_to_f16(float f) {
+  uint32_t x;
+  std::memcpy(&x, &f, 4);
+  const uint32_t sign = (x >> 16) & 0x8000u;
+  const uint32_t ax = x & 0x7fffffffu;
+  if (ax >= 0x7f800000u) return (uint16_t)(sign | 0x7c00u | (ax > 0x7f800000u ? 0x200u : 0u));  // inf / NaN
+  const int e = (int)(ax >> 23) - 127;  // unbiased exponent
+  if (e > 15) return (uint16_t)(sign | 0x7c00u);
+  uint32_t mant = (ax & 0x7fffffu) | 0x800000u;  // 24-bit significand (normal inputs)
+  int shift;                                     // bits dropped from the 24-bit significand
+  uint32_t ebits;
+  if (e >= -14) {  // normal half: keep 11 bits
+    shift = 13;
+    ebits = (uint32_t)(e + 15) << 10;
+  } else {  // subnormal half (or underflow to zero): value = m * 2^-24
+    if (ax < 0x33000000u) return (uint16_t)sign;  // below half the smallest subnormal
+    shift = 13 + (-14 - e);
+    ebits = 0;
+  }
+  uint32_t q = mant >> shift;
+  const uint32_t rem = mant & ((1u << shift) - 1u), half = 1u << (shift - 1);
+  if (rem > half || (rem == half && (q & 1u))) ++q;  // round to nearest even
+  if (ebits) {
+    // q carries the implicit bit at bit 10 (bit 11 after a rounding carry); adding
+    // it to the biased exponent field moves the carry into the exponent
+    const uint32_t h = ebits + q - 0x400u;
+    return (uint16_t)(sign | (h >= 0x7c00u ? 0x7c00u : h));
+  }
+  return (uint16_t)(sign | q);  // subnormal; a carry into bit 10 yields the smallest normal
+}
+// float32 -> bfloat16, round to nearest even (NaN kept quiet).
+static uint16_t f32_to_bf16(float f) {
+  uint32_t x;
+  std::memcpy(&x, &f, 4);
+  if ((x & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((x >> 16) | 0x40u);
+  return (uint16_t)((x + 0x7fffu + ((x >> 16) & 1u)) >> 16);
+}
+static float f16_to_f32(uint16_t h) {
+  const uint32_t sign = (uint32_t)(h & 0x8000u) << 16, e = (h >> 10) & 31u, m = h & 0x3ffu;
+  float v;
+  if (e == 0) v = std::ldexp((float)m, -24);
+  else if (e == 31) v = m ? std::numeric_limits<float>::quiet_NaN() : std::numeric_limits<float>::infinity();
+  else v = std::ldexp((float)(m | 0x400u), (int)e - 25);
+  uint32_t x;
+  std::memcpy(&x, &v, 4);
+  x |= sign;
+  std::memcpy(&v, &x, 4);
+  return v;
+}
+static float bf16_to_f32(uint16_t b) {
+  const uint32_t x = (uint32_t)b << 16;
+  float v;
+  std::memcpy(&v, &x, 4);
+  return v;
+}
+
+nvdb_status nvdb_model_get_params16(const nvdb_model* m, int32_t net, int32_t kind, uint16_t* dst, int64_t n) {
+  return guarded([&] {
+    NVDB_REQUIRE(kind == NVDB_STORE_F16 || kind == NVDB_STORE_BF16, NVDB_E_INVALID, "unknown 16-bit format");
+    const Net& N = net_of(m, net);
+    NVDB_REQUIRE(dst && n == N.s.nparams(), NVDB_E_INVALID, "parameter count mismatch");
+    std::vector<float> f((size_t)n);
+    NVDB_HIP(hipDeviceSynchronize());
+    NVDB_HIP(hipMemcpy(f.data(), N.theta.p, n * 4, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < n; ++i) dst[i] = kind == NVDB_STORE_F16 ? f32_to_f16(f[i]) : f32_to_bf16(f[i]);
+  });
+}
+
+nvdb_status nvdb_model_set_params16(nvdb_model* m, int32_t net, int32_t kind, const uint16_t* src, int64_t n) {
+  std::vector<float> f;
+  const nvdb_status st = guarded([&] {
+    NVDB_REQUIRE(kind == NVDB_STORE_F16 || kind == NVDB_STORE_BF16, NVDB_E_INVALID, "unknown 16-bit format");
+    NVDB_REQUIRE(src && n >= 0 && n < (1ll << 31), NVDB_E_INVALID, "bad parameters");
+    f.resize((size_t)n);
+    for (int64_t i = 0; i < n; ++i) f[i] = kind == NVDB_STORE_F16 ? f16_to_f32(src[i]) : bf16_to_f32(src[i]);
+  });
+  if (st != NVDB_OK) return st;
+  return nvdb_model_set_params(m, net, f.data(), n);
 }
 
 nvdb_status nvdb_model_set_encoding(nvdb_model* m, int32_t net, const float* B, int32_t n_freq) {

@@ -19,6 +19,7 @@ OK, E_INVALID, E_NOMEM, E_DEVICE, E_NUMERIC, E_STATE, E_UNSUPPORTED = 0, -1, -2,
 SDF, FOG = 0, 1
 NET_REGRESSOR, NET_L0, NET_L1, MAX_NETS = 0, 1, 2, 3
 FP32, BF16 = 0, 1
+STORE_F16, STORE_BF16 = 0, 1
 
 
 class NvdbError(RuntimeError):
@@ -94,6 +95,8 @@ _SIGS = {
     "nvdb_model_param_count": (C.c_int32, [_P, C.c_int32, C.POINTER(C.c_int64)]),
     "nvdb_model_set_params": (C.c_int32, [_P, C.c_int32, _P, C.c_int64]),
     "nvdb_model_get_params": (C.c_int32, [_P, C.c_int32, _P, C.c_int64]),
+    "nvdb_model_get_params16": (C.c_int32, [_P, C.c_int32, C.c_int32, _P, C.c_int64]),
+    "nvdb_model_set_params16": (C.c_int32, [_P, C.c_int32, C.c_int32, _P, C.c_int64]),
     "nvdb_model_set_encoding": (C.c_int32, [_P, C.c_int32, _P, C.c_int32]),
     "nvdb_model_get_opt_state": (C.c_int32, [_P, C.c_int32, _P, _P, C.c_int64, C.POINTER(C.c_int64)]),
     "nvdb_model_set_opt_state": (C.c_int32, [_P, C.c_int32, _P, _P, C.c_int64, C.c_int64]),
@@ -239,6 +242,16 @@ class Model:
     def set_encoding(self, net, B):
         a = np.ascontiguousarray(B, dtype=np.float32)
         _check(_lib.nvdb_model_set_encoding(self.h, net, a.ctypes.data_as(C.c_void_p), a.shape[0]))
+
+    def get_params16(self, net, kind):
+        """Parameters rounded to 16 bits (STORE_F16 or STORE_BF16), uint16 numpy array."""
+        out = np.zeros(self.param_count(net), np.uint16)
+        _check(_lib.nvdb_model_get_params16(self.h, net, kind, out.ctypes.data_as(C.c_void_p), out.size))
+        return out
+
+    def set_params16(self, net, kind, p16):
+        p16 = np.ascontiguousarray(p16, dtype=np.uint16)
+        _check(_lib.nvdb_model_set_params16(self.h, net, kind, p16.ctypes.data_as(C.c_void_p), p16.size))
 
     def get_opt_state(self, net):
         n = self.param_count(net)

@@ -918,3 +918,34 @@ def test_new_entry_points_reject_bad_arguments(gpu_lib, sphere):
     with pytest.raises(gpu_lib.NvdbError) as e:
         m.set_train_groups(513)
     assert e.value.code == gpu_lib.E_INVALID
+
+
+def test_params16_storage(gpu_lib, sphere):
+    """16-bit storage of the networks: binary16 codes bit-equal to numpy's
+    round-to-nearest-even conversion (normals, ties, subnormals, underflow,
+    overflow to infinity), bfloat16 codes bit-equal to torch's; loading the
+    codes back widens them exactly, and infinities are rejected."""
+    tr, _ = sphere
+    m = gpu_lib.Model({0: (64, 3, 18, 1)}, precision=gpu_lib.FP32, domain_size=64, value_scale=3.0)
+    n = m.param_count(0)
+    rng = np.random.default_rng(2)
+    th = (rng.standard_normal(n) * np.exp2(rng.integers(-30, 17, n))).astype(np.float32)
+    special = np.array([0.0, -0.0, 65504.0, 65519.99, 65520.0, -70000.0, 2.0 ** -24, 2.0 ** -25, 3 * 2.0 ** -26,
+                        2.0 ** -14, 1 + 2.0 ** -11, 1 + 3 * 2.0 ** -11, -(1 + 2.0 ** -11), 1e-8, 6.1e-5, 3.0e38,
+                        1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8], np.float32)
+    th[:len(special)] = special
+    m.set_params(0, th)
+    m.set_encoding(0, workloads.pe_matrix(6))
+    h = m.get_params16(0, gpu_lib.STORE_F16)
+    assert np.array_equal(h, th.astype(np.float16).view(np.uint16))
+    b = m.get_params16(0, gpu_lib.STORE_BF16)
+    assert np.array_equal(b, torch.from_numpy(th).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16))
+    with pytest.raises(gpu_lib.NvdbError) as e:  # 65520 and beyond overflow binary16
+        m.set_params16(0, gpu_lib.STORE_F16, h)
+    assert e.value.code == gpu_lib.E_INVALID
+    ok = np.isfinite(th.astype(np.float16))
+    h2 = np.where(ok, h, np.float16(1.0).view(np.uint16)).astype(np.uint16)
+    m.set_params16(0, gpu_lib.STORE_F16, h2)
+    assert np.array_equal(m.get_params(0), h2.view(np.float16).astype(np.float32))
+    m.set_params16(0, gpu_lib.STORE_BF16, b)
+    assert np.array_equal(m.get_params(0).view(np.uint32), b.astype(np.uint32) << 16)
