@@ -16,5 +16,7 @@ Modules
               hand-derived backward, Adam and the learning-rate staircase
   sampler  -- counter-based SplitMix64 batch indices
   fit      -- training loop, full decode and error report
+  moe      -- sparse domain decomposition: subdomains, tent gates, blended
+              decode (eq. moe)
 """
-from . import tree, mlp, sampler, fit  # noqa: F401
+from . import tree, mlp, sampler, fit, moe  # noqa: F401

@@ -74,6 +74,19 @@ def sphere_sdf(n=64, center=(32.0, 32.0, 32.0), radius=24.0, device="cpu"):
     return (d - radius).to(torch.float32)
 
 
+def two_spheres_sdf(n=128, centers=((50.0, 50.0, 50.0), (104.0, 24.0, 26.0)), radii=(24.0, 12.0),
+                    device="cpu"):
+    """Union of two disjoint spheres (signed distance, voxel units, n^3 lattice):
+    a scene of separate clusters.  The surface of the first sphere passes
+    through the corner shared by eight 64^3 blocks of the lattice."""
+    x, y, z = _grid((n, n, n), device)
+    out = None
+    for c, r in zip(centers, radii):
+        d = torch.sqrt((x.double() - c[0]) ** 2 + (y.double() - c[1]) ** 2 + (z.double() - c[2]) ** 2) - r
+        out = d if out is None else torch.minimum(out, d)
+    return out.to(torch.float32)
+
+
 def noise_sphere_sdf(n=512, center=(256.0, 256.0, 256.0), radius=200.0, amplitude=20.0,
                      octaves=4, scale=64.0, seed=0, device="cpu", chunk=32):
     """Sphere displaced by fBm gradient noise: phi = |p - c| - R - amplitude * fbm(p / scale).
