@@ -340,6 +340,52 @@ nvdb_status nvdb_errors_topology(const nvdb_tree* truth, const nvdb_tree* pred, 
 nvdb_status nvdb_topology_patches(const nvdb_tree* truth, const nvdb_tree* pred, int32_t* fp_dev, int64_t fp_cap,
                                   int32_t* fn_dev, int64_t fn_cap, int64_t* n_fp, int64_t* n_fn, void* stream);
 
+/* ------------------------------------------- sparse domain decomposition */
+/* Regular grid of cubic subdomains (Sec. 3.3, sparse domain decomposition):
+ * cell c = (cx, cy, cz) has the core [origin + c size, origin + (c+1) size)
+ * per axis and the widened box [origin + c size - halo, origin + (c+1) size +
+ * halo) (the paper takes halo 8 and size 512 to 2048).  Every call checks
+ * 1 <= halo, 2 halo <= size <= 2^24 and |origin| <= 2^24 (E_INVALID). */
+typedef struct {
+  int32_t origin[3];
+  int32_t size;
+  int32_t halo;
+} nvdb_subdomains;
+
+/* The cells whose core holds an active voxel of `tree` (the others are
+ * dropped, as the paper drops empty subdomains), ascending in (cx, cy, cz):
+ * the first min(n, cap) go to cells int32[cap][3] (host), the count n to
+ * *n_cells.  Synchronises `stream`.  Errors: E_INVALID (null arguments, bad
+ * grid, a tree spanning more than 2^24 candidate cells). */
+nvdb_status nvdb_subdomain_cells(const nvdb_tree* tree, const nvdb_subdomains* grid, int32_t* cells, int64_t cap,
+                                 int64_t* n_cells, void* stream);
+
+/* Training set of the expert of `cell`: the active voxels of `tree` inside the
+ * cell's widened box, with their values, as a new tree (its arrays are those
+ * of a tree built from that voxel list; it records the source's active rule).
+ * An expert's model takes domain_lo = the widened box's lower corner and
+ * domain_size = size + 2 halo (coordinates normalised to the subdomain's box).
+ * The caller frees the result with nvdb_tree_free.  Synchronises `stream`.
+ * Errors: E_INVALID (null arguments, bad grid, a box outside [-2^30, 2^30]). */
+nvdb_status nvdb_tree_subdomain(const nvdb_tree* tree, const nvdb_subdomains* grid, const int32_t cell[3],
+                                void* stream, nvdb_tree** out);
+
+/* Blended decode (eq. moe) at the active voxels of `tree`: expert k is the
+ * regressor of experts[k] and serves cell cells[k] (host int32[n_experts][3]).
+ * Voxel p gets sum_k G_k E_k / sum_k G_k over the experts whose widened box
+ * holds p (at most 8), with E_k the regressor at x = (p - domain_lo + 1/2) /
+ * domain_size of that expert's own model, times its value_scale, and G_k the
+ * clamped tent: the product over the axes of min(t, size + 2 halo - t,
+ * 2 halo) / (2 halo), t the distance of the voxel centre from the lower face of
+ * the widened box.  Each expert computes in its own precision.  values_dev is
+ * float32[N] in the tree's voxel order (as nvdb_decode).  Synchronises
+ * `stream`.  Errors: E_INVALID (null arguments, n_experts outside [1, 4096],
+ * two experts for one cell, experts spanning more than 2^24 cells, a tree of
+ * 2^29 voxels or more, or a voxel that no expert's widened box holds: then
+ * values_dev is unspecified), E_STATE (an expert's regressor unset). */
+nvdb_status nvdb_decode_moe(const nvdb_model* const* experts, const int32_t* cells, int32_t n_experts,
+                            const nvdb_subdomains* grid, const nvdb_tree* tree, float* values_dev, void* stream);
+
 /* Level-1 classifier report (Sec. 3.3.1, Sec. 4) over the 4096 leaf slots of
  * every level-1 node: classes_dev is uint8[n_l1][4096] as written by
  * nvdb_decode_l1; the true class of a slot is 0 when it has a child leaf, else

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <cfloat>
 #include <limits>
 #include <new>
 
@@ -1169,6 +1170,188 @@ nvdb_status nvdb_topology_patches(const nvdb_tree* truth, const nvdb_tree* pred,
     hipStream_t st = (hipStream_t)stream;
     *n_fp = topology_patches(*pred, *truth, fp_dev, fp_cap, st);
     *n_fn = topology_patches(*truth, *pred, fn_dev, fn_cap, st);
+  });
+}
+
+// -------------------------------------------- sparse domain decomposition
+}  // extern "C"
+
+static MoeGrid check_grid(const nvdb_subdomains* g) {
+  NVDB_REQUIRE(g != nullptr, NVDB_E_INVALID, "null subdomain grid");
+  NVDB_REQUIRE(g->halo >= 1 && g->size >= 2 * g->halo && g->size <= (1 << 24), NVDB_E_INVALID,
+               "subdomains need 1 <= halo and 2 halo <= size <= 2^24");
+  MoeGrid m{};
+  for (int d = 0; d < 3; ++d) {
+    NVDB_REQUIRE(g->origin[d] >= -(1 << 24) && g->origin[d] <= (1 << 24), NVDB_E_INVALID,
+                 "subdomain origin outside [-2^24, 2^24]");
+    m.o[d] = g->origin[d];
+  }
+  m.S = g->size;
+  m.h = g->halo;
+  return m;
+}
+static int64_t floor_div64(int64_t a, int64_t s) { return a >= 0 ? a / s : -((-a + s - 1) / s); }
+static int64_t cell_range_size(const MoeGrid& g) { return (int64_t)g.cdim[0] * g.cdim[1] * g.cdim[2]; }
+static constexpr int64_t MOE_MAX_RANGE = 1ll << 24;
+
+extern "C" {
+
+nvdb_status nvdb_subdomain_cells(const nvdb_tree* tree, const nvdb_subdomains* grid, int32_t* cells, int64_t cap,
+                                 int64_t* n_cells, void* stream) {
+  return guarded([&] {
+    NVDB_REQUIRE(tree && n_cells, NVDB_E_INVALID, "null argument");
+    NVDB_REQUIRE(cap >= 0 && (cap == 0 || cells), NVDB_E_INVALID, "bad cell buffer");
+    MoeGrid g = check_grid(grid);
+    *n_cells = 0;
+    if (tree->n_vox == 0) return;
+    hipStream_t st = (hipStream_t)stream;
+    int32_t lo[3], hi[3];
+    leaf_bbox(*tree, lo, hi, st);
+    for (int d = 0; d < 3; ++d) {
+      const int64_t a = floor_div64((int64_t)lo[d] - g.o[d], g.S), b = floor_div64((int64_t)hi[d] - 1 - g.o[d], g.S);
+      NVDB_REQUIRE(b - a + 1 <= MOE_MAX_RANGE, NVDB_E_INVALID, "the tree spans more than 2^24 cells");
+      g.clo[d] = (int32_t)a;
+      g.cdim[d] = (int32_t)(b - a + 1);
+    }
+    const int64_t total = cell_range_size(g);
+    NVDB_REQUIRE(total <= MOE_MAX_RANGE, NVDB_E_INVALID, "the tree spans more than 2^24 cells");
+    DevBuf<uint8_t> flag;
+    flag.alloc((size_t)total);
+    NVDB_HIP(hipMemsetAsync(flag.p, 0, (size_t)total, st));
+    moe_mark_cells(*tree, g, flag.p, st);
+    std::vector<uint8_t> h((size_t)total);
+    NVDB_HIP(hipMemcpyAsync(h.data(), flag.p, (size_t)total, hipMemcpyDeviceToHost, st));
+    NVDB_HIP(hipStreamSynchronize(st));
+    int64_t c = 0;
+    for (int64_t i = 0; i < total; ++i) {
+      if (!h[i]) continue;
+      if (c < cap) {
+        cells[3 * c] = g.clo[0] + (int32_t)(i / ((int64_t)g.cdim[1] * g.cdim[2]));
+        cells[3 * c + 1] = g.clo[1] + (int32_t)((i / g.cdim[2]) % g.cdim[1]);
+        cells[3 * c + 2] = g.clo[2] + (int32_t)(i % g.cdim[2]);
+      }
+      ++c;
+    }
+    *n_cells = c;
+  });
+}
+
+nvdb_status nvdb_tree_subdomain(const nvdb_tree* tree, const nvdb_subdomains* grid, const int32_t cell[3],
+                                void* stream, nvdb_tree** out) {
+  return guarded([&] {
+    NVDB_REQUIRE(tree && cell && out, NVDB_E_INVALID, "null argument");
+    *out = nullptr;
+    const MoeGrid g = check_grid(grid);
+    int32_t lo[3];
+    for (int d = 0; d < 3; ++d) {
+      const int64_t l = (int64_t)g.o[d] + (int64_t)cell[d] * g.S - g.h;
+      NVDB_REQUIRE(l >= -(1ll << 30) && l <= (1ll << 30), NVDB_E_INVALID, "cell outside the index range");
+      lo[d] = (int32_t)l;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    DevBuf<int32_t> ijk;
+    DevBuf<float> v;
+    DevBuf<uint32_t> count;
+    ijk.alloc(3 * (size_t)tree->n_vox);
+    v.alloc((size_t)tree->n_vox);
+    count.alloc(1);
+    const int64_t n = moe_extract(*tree, lo, g.S + 2 * g.h, ijk.p, v.p, count.p, st);
+    // every voxel of the source is kept: a band no finite value exceeds
+    const nvdb_active_rule keep{NVDB_SDF, FLT_MAX};
+    Tree* t = build_tree_sparse(ijk.p, v.p, n, keep, st);
+    t->kind = tree->kind;
+    t->thr = tree->thr;
+    *out = static_cast<nvdb_tree*>(t);
+  });
+}
+
+nvdb_status nvdb_decode_moe(const nvdb_model* const* experts, const int32_t* cells, int32_t n_experts,
+                            const nvdb_subdomains* grid, const nvdb_tree* tree, float* values_dev, void* stream) {
+  return guarded([&] {
+    NVDB_REQUIRE(experts && cells && tree, NVDB_E_INVALID, "null argument");
+    NVDB_REQUIRE(n_experts >= 1 && n_experts <= MOE_MAX_EXPERTS, NVDB_E_INVALID, "expert count outside [1, 4096]");
+    NVDB_REQUIRE(tree->n_vox < (1ll << 29), NVDB_E_INVALID, "the blended decode takes fewer than 2^29 voxels");
+    NVDB_REQUIRE(tree->n_vox == 0 || values_dev, NVDB_E_INVALID, "null output");
+    MoeGrid g = check_grid(grid);
+    std::vector<MoeBox> box((size_t)n_experts);
+    for (int k = 0; k < n_experts; ++k) {
+      NVDB_REQUIRE(experts[k] != nullptr, NVDB_E_INVALID, "null expert");
+      const Net& N = net_of(experts[k], NVDB_NET_REGRESSOR);
+      NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "expert regressor parameters or encoding not set");
+      for (int d = 0; d < 3; ++d) box[k].lo[d] = experts[k]->d.domain_lo[d];
+      box[k].inv_d = 1.f / (float)experts[k]->d.domain_size;
+    }
+    int64_t clo[3], chi[3];
+    for (int d = 0; d < 3; ++d) {
+      clo[d] = chi[d] = cells[d];
+      for (int k = 1; k < n_experts; ++k) {
+        clo[d] = std::min<int64_t>(clo[d], cells[3 * k + d]);
+        chi[d] = std::max<int64_t>(chi[d], cells[3 * k + d]);
+      }
+      NVDB_REQUIRE(chi[d] - clo[d] + 1 <= MOE_MAX_RANGE, NVDB_E_INVALID, "experts span more than 2^24 cells");
+      g.clo[d] = (int32_t)clo[d];
+      g.cdim[d] = (int32_t)(chi[d] - clo[d] + 1);
+    }
+    const int64_t total = cell_range_size(g);
+    NVDB_REQUIRE(total <= MOE_MAX_RANGE, NVDB_E_INVALID, "experts span more than 2^24 cells");
+    std::vector<int32_t> table((size_t)total, -1);
+    for (int k = 0; k < n_experts; ++k) {
+      const int64_t i =
+          ((cells[3 * k] - clo[0]) * (int64_t)g.cdim[1] + (cells[3 * k + 1] - clo[1])) * g.cdim[2] + (cells[3 * k + 2] - clo[2]);
+      NVDB_REQUIRE(table[(size_t)i] < 0, NVDB_E_INVALID, "two experts for one cell");
+      table[(size_t)i] = k;
+    }
+    const int64_t n = tree->n_vox;
+    if (n == 0) return;
+    hipStream_t st = (hipStream_t)stream;
+    DevBuf<int32_t> tab;
+    DevBuf<MoeBox> dbox;
+    DevBuf<uint32_t> cnt, start, cursor;
+    tab.alloc((size_t)total);
+    dbox.alloc((size_t)n_experts);
+    cnt.alloc((size_t)n_experts + 1);  // counts, then the uncovered voxels
+    start.alloc((size_t)n_experts);
+    cursor.alloc((size_t)n_experts);
+    NVDB_HIP(hipMemcpyAsync(tab.p, table.data(), (size_t)total * 4, hipMemcpyHostToDevice, st));
+    NVDB_HIP(hipMemcpyAsync(dbox.p, box.data(), box.size() * sizeof(MoeBox), hipMemcpyHostToDevice, st));
+    NVDB_HIP(hipMemsetAsync(cnt.p, 0, ((size_t)n_experts + 1) * 4, st));
+    NVDB_HIP(hipMemsetAsync(cursor.p, 0, (size_t)n_experts * 4, st));
+    moe_count(*tree, g, tab.p, n_experts, cnt.p, cnt.p + n_experts, st);
+    std::vector<uint32_t> hc((size_t)n_experts + 1);
+    NVDB_HIP(hipMemcpyAsync(hc.data(), cnt.p, hc.size() * 4, hipMemcpyDeviceToHost, st));
+    NVDB_HIP(hipStreamSynchronize(st));
+    NVDB_REQUIRE(hc[(size_t)n_experts] == 0, NVDB_E_INVALID, "voxels that no expert's widened box holds");
+    std::vector<uint32_t> hs((size_t)n_experts);
+    uint64_t pairs = 0;
+    for (int k = 0; k < n_experts; ++k) {
+      hs[k] = (uint32_t)pairs;
+      pairs += hc[k];
+    }
+    DevBuf<float> bx, y, yslot;
+    DevBuf<uint32_t> bslot;
+    bx.alloc(3 * (size_t)pairs);
+    y.alloc((size_t)pairs);
+    bslot.alloc((size_t)pairs);
+    yslot.alloc(8 * (size_t)n);
+    NVDB_HIP(hipMemcpyAsync(start.p, hs.data(), hs.size() * 4, hipMemcpyHostToDevice, st));
+    moe_route(*tree, g, tab.p, dbox.p, n_experts, start.p, cursor.p, bx.p, bslot.p, st);
+    for (int k = 0; k < n_experts; ++k) {
+      if (hc[k] == 0) continue;
+      const Net& N = net_of(experts[k], NVDB_NET_REGRESSOR);
+      InferLaunch I{};
+      I.net = net_view(N);
+      base_spec(experts[k], &I.spec);
+      I.spec.src = SRC_COORDS;
+      I.spec.direct = 1;
+      I.spec.coords = bx.p + 3 * (size_t)hs[k];
+      I.spec.n = hc[k];
+      I.out_kind = OUT_Y;
+      I.y = y.p + hs[k];
+      launch_infer(N.ks, I, infer_grid(hc[k]), st);
+      query_scatter(y.p + hs[k], bslot.p + hs[k], hc[k], cnt.p + k, experts[k]->d.value_scale, yslot.p, st);
+    }
+    moe_blend(*tree, g, tab.p, yslot.p, values_dev, st);
+    NVDB_HIP(hipStreamSynchronize(st));
   });
 }
 

@@ -1,0 +1,288 @@
+// Sparse domain decomposition (NeuralVDB Sec. 3.3, eq. moe).
+//
+// Index space is cut into a regular grid of cubic cells of edge S; the widened
+// box of cell c is its core [o + cS, o + (c+1)S) grown by a halo of h voxels on
+// every side.  Each kept cell has an expert network normalised to its widened
+// box, and a voxel's value is the average of the experts whose box holds it,
+// weighted by clamped-tent gates (product over the axes of
+// min(t, S + 2h - t, 2h) / 2h, t the distance of the voxel centre from the
+// box's lower face).  With S >= 2h a voxel meets at most two cells per axis,
+// so at most eight experts.
+//
+// The blended decode routes every (voxel, expert) pair into a per-expert bucket
+// of normalised coordinates, runs each expert's forward pass over its bucket,
+// scatters the outputs into eight slots per voxel, and blends the slots in a
+// fixed order (deterministic: bucket order never reaches the sums).
+#include <algorithm>
+#include <cfloat>
+#include <climits>
+#include <vector>
+
+#include "nvdb_internal.h"
+
+namespace nvdb {
+
+namespace {
+
+// Floor division in 64 bits: p - o can leave the int32 range for far grid origins.
+__device__ __forceinline__ int64_t floor_div(int64_t a, int64_t s) { return a >= 0 ? a / s : -((-a + s - 1) / s); }
+
+__device__ __forceinline__ int3 voxel_of(const int4* __restrict__ leaf_o, uint32_t key) {
+  const int4 o = leaf_o[key >> 9];
+  const uint32_t n0 = key & 511u;
+  return make_int3(o.x + (int)(n0 >> 6), o.y + (int)((n0 >> 3) & 7u), o.z + (int)(n0 & 7u));
+}
+
+// Cells met by voxel coordinate p along one axis: base, base + 1, ... (n of them).
+struct AxisCells {
+  int base, n;
+};
+__device__ __forceinline__ AxisCells axis_cells(int p, int o, int S, int h) {
+  const int64_t c0 = floor_div((int64_t)p - o, S);
+  const int64_t r = (int64_t)p - o - c0 * S;  // 0 <= r < S
+  AxisCells a;
+  a.base = (int)(c0 - (r < h ? 1 : 0));
+  a.n = 1 + (r < h ? 1 : 0) + (r >= S - h ? 1 : 0);
+  return a;
+}
+
+// Tent of cell c along one axis at the centre of voxel p (p in the widened box):
+// twice the distance to the lower face is a = 2 (p - (o + cS - h)) + 1.
+__device__ __forceinline__ float tent(int p, int c, int o, int S, int h) {
+  const int64_t a = 2 * ((int64_t)p - ((int64_t)o + (int64_t)c * S - h)) + 1;
+  const int m = (int)min(min(a, (int64_t)2 * (S + 2 * h) - a), (int64_t)4 * h);
+  return (float)m / (float)(4 * h);
+}
+
+__device__ __forceinline__ int expert_at(const MoeGrid& g, const int32_t* __restrict__ table, int cx, int cy, int cz) {
+  const int ix = cx - g.clo[0], iy = cy - g.clo[1], iz = cz - g.clo[2];
+  if ((unsigned)ix >= (unsigned)g.cdim[0] || (unsigned)iy >= (unsigned)g.cdim[1] || (unsigned)iz >= (unsigned)g.cdim[2])
+    return -1;
+  return table[((int64_t)ix * g.cdim[1] + iy) * g.cdim[2] + iz];
+}
+
+// Calls f(slot j, expert k, gate) for every expert whose widened box holds p,
+// in the fixed order j = (ix << 2) | (iy << 1) | iz.
+template <class F>
+__device__ __forceinline__ void for_each_expert(const MoeGrid& g, const int32_t* __restrict__ table, int3 p, F&& f) {
+  const AxisCells ax = axis_cells(p.x, g.o[0], g.S, g.h);
+  const AxisCells ay = axis_cells(p.y, g.o[1], g.S, g.h);
+  const AxisCells az = axis_cells(p.z, g.o[2], g.S, g.h);
+  for (int ix = 0; ix < ax.n; ++ix)
+    for (int iy = 0; iy < ay.n; ++iy)
+      for (int iz = 0; iz < az.n; ++iz) {
+        const int cx = ax.base + ix, cy = ay.base + iy, cz = az.base + iz;
+        const int k = expert_at(g, table, cx, cy, cz);
+        if (k < 0) continue;
+        const float w = tent(p.x, cx, g.o[0], g.S, g.h) * tent(p.y, cy, g.o[1], g.S, g.h) *
+                        tent(p.z, cz, g.o[2], g.S, g.h);
+        f((ix << 2) | (iy << 1) | iz, k, w);
+      }
+}
+
+// Bounding box of the leaf origins (init: INT_MAX x3, INT_MIN x3).
+__global__ void __launch_bounds__(256) k_leaf_bbox(const int4* __restrict__ leaf_o, int64_t n, int* __restrict__ box) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN};
+  if (l < n) {
+    const int4 o = leaf_o[l];
+    mn[0] = mx[0] = o.x;
+    mn[1] = mx[1] = o.y;
+    mn[2] = mx[2] = o.z;
+  }
+  for (int d = 0; d < 3; ++d)
+    for (int s = 32; s >= 1; s >>= 1) {
+      mn[d] = min(mn[d], __shfl_xor(mn[d], s));
+      mx[d] = max(mx[d], __shfl_xor(mx[d], s));
+    }
+  if ((threadIdx.x & 63) == 0) {
+    for (int d = 0; d < 3; ++d) {
+      atomicMin(&box[d], mn[d]);
+      atomicMax(&box[3 + d], mx[d]);
+    }
+  }
+}
+
+// Flags the core cell of every voxel (cells outside the range are ignored; the
+// host sizes the range to hold them all).
+__global__ void __launch_bounds__(256) k_moe_mark(const int4* __restrict__ leaf_o, const uint32_t* __restrict__ key,
+                                                  int64_t n, MoeGrid g, uint8_t* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int3 p = voxel_of(leaf_o, key[i]);
+  const int64_t ix = floor_div((int64_t)p.x - g.o[0], g.S) - g.clo[0];
+  const int64_t iy = floor_div((int64_t)p.y - g.o[1], g.S) - g.clo[1];
+  const int64_t iz = floor_div((int64_t)p.z - g.o[2], g.S) - g.clo[2];
+  if (ix >= 0 && ix < g.cdim[0] && iy >= 0 && iy < g.cdim[1] && iz >= 0 && iz < g.cdim[2])
+    flag[(ix * g.cdim[1] + iy) * g.cdim[2] + iz] = 1;
+}
+
+// Voxels inside a widened box [lo, lo + D)^3, appended (one atomic per wave).
+__global__ void __launch_bounds__(256) k_moe_extract(const int4* __restrict__ leaf_o, const uint32_t* __restrict__ key,
+                                                     const float* __restrict__ val, int64_t n, int lx, int ly, int lz,
+                                                     int D, int32_t* __restrict__ ijk, float* __restrict__ v,
+                                                     uint32_t* __restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool in = false;
+  int3 p = make_int3(0, 0, 0);
+  if (i < n) {
+    p = voxel_of(leaf_o, key[i]);
+    in = (int64_t)p.x - lx >= 0 && (int64_t)p.x - lx < D && (int64_t)p.y - ly >= 0 && (int64_t)p.y - ly < D &&
+         (int64_t)p.z - lz >= 0 && (int64_t)p.z - lz < D;
+  }
+  const uint64_t b = __ballot(in);
+  if (b == 0ull) return;
+  const int lane = (int)(threadIdx.x & 63u);
+  const int leader = __ffsll((long long)b) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(b));
+  base = __shfl(base, leader);
+  if (in) {
+    const uint32_t s = base + (uint32_t)__popcll(b & ((1ull << lane) - 1ull));
+    ijk[3 * (size_t)s] = p.x;
+    ijk[3 * (size_t)s + 1] = p.y;
+    ijk[3 * (size_t)s + 2] = p.z;
+    v[s] = val[i];
+  }
+}
+
+// Pass 1 of the routing: (voxel, expert) pairs per expert, and voxels no expert
+// covers.  Per-block histogram in LDS, one global atomic per (block, expert).
+__global__ void __launch_bounds__(256) k_moe_count(const int4* __restrict__ leaf_o, const uint32_t* __restrict__ key,
+                                                   int64_t n, MoeGrid g, const int32_t* __restrict__ table,
+                                                   int n_exp, uint32_t* __restrict__ cnt,
+                                                   uint32_t* __restrict__ uncovered) {
+  __shared__ uint32_t hist[MOE_MAX_EXPERTS];
+  __shared__ uint32_t unc;
+  for (int k = threadIdx.x; k < n_exp; k += blockDim.x) hist[k] = 0u;
+  if (threadIdx.x == 0) unc = 0u;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const int3 p = voxel_of(leaf_o, key[i]);
+    int m = 0;
+    for_each_expert(g, table, p, [&](int, int k, float) {
+      atomicAdd(&hist[k], 1u);
+      ++m;
+    });
+    if (m == 0) atomicAdd(&unc, 1u);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < n_exp; k += blockDim.x)
+    if (hist[k]) atomicAdd(&cnt[k], hist[k]);
+  if (threadIdx.x == 0 && unc) atomicAdd(uncovered, unc);
+}
+
+// Pass 2: writes each pair into its expert's bucket (offset `start[k]` plus a
+// block range reserved with one atomic): the expert's normalised coordinates
+// and the voxel's slot 8 i + j.
+__global__ void __launch_bounds__(256) k_moe_route(const int4* __restrict__ leaf_o, const uint32_t* __restrict__ key,
+                                                   int64_t n, MoeGrid g, const int32_t* __restrict__ table,
+                                                   const MoeBox* __restrict__ box, int n_exp,
+                                                   const uint32_t* __restrict__ start, uint32_t* __restrict__ cursor,
+                                                   float* __restrict__ bx, uint32_t* __restrict__ bslot) {
+  __shared__ uint32_t hist[MOE_MAX_EXPERTS];
+  __shared__ uint32_t base[MOE_MAX_EXPERTS];
+  for (int k = threadIdx.x; k < n_exp; k += blockDim.x) hist[k] = 0u;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int3 p = make_int3(0, 0, 0);
+  if (i < n) {
+    p = voxel_of(leaf_o, key[i]);
+    for_each_expert(g, table, p, [&](int, int k, float) { atomicAdd(&hist[k], 1u); });
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < n_exp; k += blockDim.x) {
+    base[k] = hist[k] ? start[k] + atomicAdd(&cursor[k], hist[k]) : 0u;
+    hist[k] = 0u;
+  }
+  __syncthreads();
+  if (i < n) {
+    for_each_expert(g, table, p, [&](int j, int k, float) {
+      const uint32_t s = base[k] + atomicAdd(&hist[k], 1u);
+      const MoeBox b = box[k];
+      bx[3 * (size_t)s] = ((float)(p.x - b.lo[0]) + 0.5f) * b.inv_d;
+      bx[3 * (size_t)s + 1] = ((float)(p.y - b.lo[1]) + 0.5f) * b.inv_d;
+      bx[3 * (size_t)s + 2] = ((float)(p.z - b.lo[2]) + 0.5f) * b.inv_d;
+      bslot[s] = (uint32_t)(8 * i + j);
+    });
+  }
+}
+
+// Gate-weighted average of the expert outputs held in the voxel's slots.
+__global__ void __launch_bounds__(256) k_moe_blend(const int4* __restrict__ leaf_o, const uint32_t* __restrict__ key,
+                                                   int64_t n, MoeGrid g, const int32_t* __restrict__ table,
+                                                   const float* __restrict__ yslot, float* __restrict__ values) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int3 p = voxel_of(leaf_o, key[i]);
+  float num = 0.f, den = 0.f;
+  for_each_expert(g, table, p, [&](int j, int, float w) {
+    num += w * yslot[8 * i + j];
+    den += w;
+  });
+  values[i] = den > 0.f ? num / den : __builtin_nanf("");
+}
+
+unsigned grid_of(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+void leaf_bbox(const Tree& t, int32_t lo[3], int32_t hi[3], hipStream_t st) {
+  const int init[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
+  DevBuf<int> box;
+  box.alloc(6);
+  NVDB_HIP(hipMemcpyAsync(box.p, init, sizeof(init), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_leaf_bbox, dim3(grid_of(t.n_leaf)), dim3(256), 0, st, t.leaf_o.p, t.n_leaf, box.p);
+  NVDB_HIP(hipGetLastError());
+  int h[6];
+  NVDB_HIP(hipMemcpyAsync(h, box.p, sizeof(h), hipMemcpyDeviceToHost, st));
+  NVDB_HIP(hipStreamSynchronize(st));
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = h[d];
+    hi[d] = h[3 + d] + 8;  // leaves span 8 voxels
+  }
+}
+
+void moe_mark_cells(const Tree& t, const MoeGrid& g, uint8_t* flag, hipStream_t st) {
+  if (t.n_vox == 0) return;
+  hipLaunchKernelGGL(k_moe_mark, dim3(grid_of(t.n_vox)), dim3(256), 0, st, t.leaf_o.p, t.vox_key.p, t.n_vox, g, flag);
+  NVDB_HIP(hipGetLastError());
+}
+
+int64_t moe_extract(const Tree& t, const int32_t lo[3], int32_t D, int32_t* ijk, float* v, uint32_t* count,
+                    hipStream_t st) {
+  NVDB_HIP(hipMemsetAsync(count, 0, sizeof(uint32_t), st));
+  if (t.n_vox > 0) {
+    hipLaunchKernelGGL(k_moe_extract, dim3(grid_of(t.n_vox)), dim3(256), 0, st, t.leaf_o.p, t.vox_key.p, t.values.p,
+                       t.n_vox, lo[0], lo[1], lo[2], D, ijk, v, count);
+    NVDB_HIP(hipGetLastError());
+  }
+  uint32_t c = 0;
+  NVDB_HIP(hipMemcpyAsync(&c, count, sizeof(c), hipMemcpyDeviceToHost, st));
+  NVDB_HIP(hipStreamSynchronize(st));
+  return (int64_t)c;
+}
+
+void moe_count(const Tree& t, const MoeGrid& g, const int32_t* table, int n_exp, uint32_t* cnt, uint32_t* uncovered,
+               hipStream_t st) {
+  hipLaunchKernelGGL(k_moe_count, dim3(grid_of(t.n_vox)), dim3(256), 0, st, t.leaf_o.p, t.vox_key.p, t.n_vox, g,
+                     table, n_exp, cnt, uncovered);
+  NVDB_HIP(hipGetLastError());
+}
+
+void moe_route(const Tree& t, const MoeGrid& g, const int32_t* table, const MoeBox* box, int n_exp,
+               const uint32_t* start, uint32_t* cursor, float* bx, uint32_t* bslot, hipStream_t st) {
+  hipLaunchKernelGGL(k_moe_route, dim3(grid_of(t.n_vox)), dim3(256), 0, st, t.leaf_o.p, t.vox_key.p, t.n_vox, g,
+                     table, box, n_exp, start, cursor, bx, bslot);
+  NVDB_HIP(hipGetLastError());
+}
+
+void moe_blend(const Tree& t, const MoeGrid& g, const int32_t* table, const float* yslot, float* values,
+               hipStream_t st) {
+  hipLaunchKernelGGL(k_moe_blend, dim3(grid_of(t.n_vox)), dim3(256), 0, st, t.leaf_o.p, t.vox_key.p, t.n_vox, g,
+                     table, yslot, values);
+  NVDB_HIP(hipGetLastError());
+}
+
+}  // namespace nvdb

@@ -276,6 +276,30 @@ void query_zero_count(uint32_t* c, hipStream_t st);
 int64_t topology_patches(const Tree& a, const Tree& b, int32_t* out, int64_t cap, hipStream_t st);
 // sparse.hip
 Tree* build_tree_sparse(const int32_t* ijk, const float* v, int64_t n, const nvdb_active_rule& rule, hipStream_t st);
+// moe.hip: sparse domain decomposition.  Grid origin o, cell edge S, halo h, and
+// the range [clo, clo + cdim) of cells a lookup table covers.
+struct MoeGrid {
+  int32_t o[3];
+  int32_t S, h;
+  int32_t clo[3];
+  int32_t cdim[3];
+};
+struct MoeBox {  // an expert's normalisation box: x = (p - lo + 1/2) * inv_d
+  int32_t lo[3];
+  float inv_d;
+};
+constexpr int MOE_MAX_EXPERTS = 4096;
+void leaf_bbox(const Tree& t, int32_t lo[3], int32_t hi[3], hipStream_t st);  // synchronises; hi exclusive
+void moe_mark_cells(const Tree& t, const MoeGrid& g, uint8_t* flag, hipStream_t st);
+// voxels of t inside [lo, lo + D)^3 into ijk [n][3], v [n] (any order); synchronises, returns the count
+int64_t moe_extract(const Tree& t, const int32_t lo[3], int32_t D, int32_t* ijk, float* v, uint32_t* count,
+                    hipStream_t st);
+void moe_count(const Tree& t, const MoeGrid& g, const int32_t* table, int n_exp, uint32_t* cnt, uint32_t* uncovered,
+               hipStream_t st);
+void moe_route(const Tree& t, const MoeGrid& g, const int32_t* table, const MoeBox* box, int n_exp,
+               const uint32_t* start, uint32_t* cursor, float* bx, uint32_t* bslot, hipStream_t st);
+void moe_blend(const Tree& t, const MoeGrid& g, const int32_t* table, const float* yslot, float* values,
+               hipStream_t st);
 void error_report(const Tree& t, const float* values, const uint64_t* pred_mask, nvdb_error_report* rep,
                   hipStream_t st);
 void error_report_l1(const Tree& t, const uint8_t* classes, nvdb_l1_report* rep, hipStream_t st);

@@ -78,6 +78,10 @@ class ErrorReport(C.Structure):
 
 
 _P = C.c_void_p
+class Subdomains(C.Structure):
+    _fields_ = [("origin", C.c_int32 * 3), ("size", C.c_int32), ("halo", C.c_int32)]
+
+
 _SIGS = {
     "nvdb_last_error": (C.c_char_p, []),
     "nvdb_abi_version": (C.c_int32, []),
@@ -89,6 +93,9 @@ _SIGS = {
     "nvdb_topology_patches": (C.c_int32, [_P, _P, _P, C.c_int64, _P, C.c_int64, C.POINTER(C.c_int64),
                                           C.POINTER(C.c_int64), _P]),
     "nvdb_tree_export_l2": (C.c_int32, [_P, _P, _P]),
+    "nvdb_subdomain_cells": (C.c_int32, [_P, C.POINTER(Subdomains), _P, C.c_int64, C.POINTER(C.c_int64), _P]),
+    "nvdb_tree_subdomain": (C.c_int32, [_P, C.POINTER(Subdomains), C.POINTER(C.c_int32), _P, C.POINTER(_P)]),
+    "nvdb_decode_moe": (C.c_int32, [C.POINTER(_P), _P, C.c_int32, C.POINTER(Subdomains), _P, _P, _P]),
     "nvdb_tree_export": (C.c_int32, [_P, _P, _P, _P, _P, _P, _P]),
     "nvdb_tree_free": (None, [_P]),
     "nvdb_model_create": (C.c_int32, [C.POINTER(ModelDesc), C.POINTER(_P)]),
@@ -182,6 +189,16 @@ class Tree:
         o, c = np.zeros((n, 3), np.int32), np.zeros((n, 512), np.uint64)
         _check(_lib.nvdb_tree_export_l2(self.h, o.ctypes.data_as(C.c_void_p), c.ctypes.data_as(C.c_void_p)))
         return o, c
+
+    def subdomain(self, origin, size, halo, cell):
+        """Tree of this tree's voxels inside the widened box of `cell` (the expert's training set)."""
+        g = Subdomains(_i3(origin), int(size), int(halo))
+        h = C.c_void_p()
+        _check(_lib.nvdb_tree_subdomain(self.h, C.byref(g), _i3(cell), _stream(), C.byref(h)))
+        t = Tree.__new__(Tree)
+        t.h = h
+        t.kind = self.kind
+        return t
 
     def info(self):
         i = TreeInfo()
@@ -406,6 +423,36 @@ def topology_patches(truth, pred):
     _check(_lib.nvdb_topology_patches(truth.h, pred.h, _ptr(fp), nfp.value, _ptr(fn), nfn.value, C.byref(nfp),
                                       C.byref(nfn), _stream()))
     return fp, fn
+
+
+def subdomain_cells(tree, origin, size, halo):
+    """Cells (int32 [n, 3], ascending) whose core holds an active voxel of the tree."""
+    g = Subdomains(_i3(origin), int(size), int(halo))
+    n = C.c_int64()
+    _check(_lib.nvdb_subdomain_cells(tree.h, C.byref(g), None, 0, C.byref(n), _stream()))
+    out = np.zeros((n.value, 3), np.int32)
+    _check(_lib.nvdb_subdomain_cells(tree.h, C.byref(g), out.ctypes.data_as(C.c_void_p), n.value, C.byref(n),
+                                     _stream()))
+    return out
+
+
+def subdomain_box(origin, size, halo, cell):
+    """Normalisation box of a cell's expert: (lower corner of the widened box, its edge)."""
+    lo = [int(o) + int(c) * int(size) - int(halo) for o, c in zip(origin, cell)]
+    return lo, int(size) + 2 * int(halo)
+
+
+def decode_moe(experts, cells, origin, size, halo, tree):
+    """Gate-weighted blend of the experts' regressors at the tree's active voxels (float32 [N], device)."""
+    import torch
+    cells = np.ascontiguousarray(np.asarray(cells, np.int32).reshape(-1, 3))
+    assert len(cells) == len(experts)
+    hs = (_P * len(experts))(*[e.h for e in experts])
+    g = Subdomains(_i3(origin), int(size), int(halo))
+    v = torch.empty(tree.info().n_voxels, dtype=torch.float32, device="cuda")
+    _check(_lib.nvdb_decode_moe(hs, cells.ctypes.data_as(C.c_void_p), len(experts), C.byref(g), tree.h, _ptr(v),
+                                _stream()))
+    return v
 
 
 def errors_topology(truth, pred):

@@ -1,0 +1,154 @@
+"""GPU parity of the sparse domain decomposition (Sec. 3.3, eq. moe) through the
+C-ABI against the oracle on the same seeded inputs.
+
+  * kept cells and the experts' subdomain trees: bit-exact;
+  * blended decode: the decode tolerances of each form in value units (value
+    scale 3): FP32 3e-5 (1 + |v|), BF16 6e-2.  A gate-weighted average is a
+    convex combination of the experts' outputs, so it keeps the largest expert
+    error; the gates themselves are products of multiples of 1/(4 halo) and
+    add at most a few FP32 ulps.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import mlp, moe, tree as T
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def scene(gpu_lib):
+    grid = workloads.two_spheres_sdf()
+    tr = gpu_lib.Tree(grid.to(DEV), (0, 0, 0), gpu_lib.SDF, 3.0)
+    ijk, vals = T.active_set_dense(grid.numpy(), (0, 0, 0), T.SDF, 3.0)
+    return tr, T.build(ijk, vals)
+
+
+GRIDS = [((0, 0, 0), 64, 8), ((-5, 3, 17), 40, 8), ((0, 0, 0), 16, 8), ((1000, -2000, 7), 256, 8),
+         ((-3, -3, -3), 24, 1)]
+
+
+@pytest.mark.parametrize("origin,size,halo", GRIDS)
+def test_subdomain_cells_match_oracle(gpu_lib, scene, origin, size, halo):
+    tr, ot = scene
+    got = gpu_lib.subdomain_cells(tr, origin, size, halo)
+    want = moe.kept_cells(ot["ijk"], origin, size)
+    assert np.array_equal(got, want.astype(np.int32))
+
+
+@pytest.mark.parametrize("origin,size,halo", GRIDS[:2])
+def test_tree_subdomain_matches_oracle(gpu_lib, scene, origin, size, halo):
+    tr, ot = scene
+    cells = moe.kept_cells(ot["ijk"], origin, size).tolist() + [[50, 50, 50]]  # the last one is empty
+    for c in cells:
+        sub = tr.subdomain(origin, size, halo, c)
+        ex = sub.export()
+        q, v = moe.subdomain_voxels(ot["ijk"], ot["values"], c, origin, size, halo)
+        assert sub.info().n_voxels == len(q)
+        if len(q) == 0:
+            continue
+        so = T.build(q, v)
+        assert np.array_equal(ex["leaf_origin"], so["leaf_origin"])
+        assert np.array_equal(ex["leaf_mask"], so["leaf_mask"])
+        assert np.array_equal(ex["leaf_off"].astype(np.int64), so["leaf_off"])
+        assert np.array_equal(ex["values"], so["values"].astype(np.float32))
+
+
+def _experts(gpu_lib, cells, origin, size, halo, shape, prec):
+    W, H, m = shape
+    K = 2 * m
+    shapes = mlp.layer_shapes(K, W, H, 1)
+    models, oracle_experts = [], []
+    for k, c in enumerate(cells):
+        lo, D = gpu_lib.subdomain_box(origin, size, halo, c)
+        theta = workloads.init_params(K, W, H, 1, seed=100 + k)
+        B = workloads.pe_matrix(6) if m == 18 else workloads.ffm_matrix(m, 10.0, seed=200 + k)
+        mdl = gpu_lib.Model({0: (W, H, m, 1)}, precision=prec, domain_lo=lo, domain_size=D, value_scale=3.0)
+        mdl.set_params(0, theta)
+        mdl.set_encoding(0, B)
+        models.append(mdl)
+        oracle_experts.append(dict(cell=c, theta=theta.astype(np.float64), shapes=shapes, B=B.astype(np.float64),
+                                   lo=lo, D=D, scale=3.0))
+    return models, oracle_experts
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("shape", [(64, 3, 18), (128, 4, 64)], ids=["64x3_pe6", "128x4_ffm64"])
+def test_decode_moe_matches_oracle(gpu_lib, scene, prec, shape):
+    tr, ot = scene
+    origin, size, halo = (0, 0, 0), 64, 8
+    p = gpu_lib.FP32 if prec == "fp32" else gpu_lib.BF16
+    cells = gpu_lib.subdomain_cells(tr, origin, size, halo)
+    assert len(cells) == 8
+    models, ex = _experts(gpu_lib, cells, origin, size, halo, shape, p)
+    got = gpu_lib.decode_moe(models, cells, origin, size, halo, tr).cpu().numpy().astype(np.float64)
+    want = moe.decode_moe(ot["ijk"], ex, origin, size, halo)
+    n_exp = sum(moe.gate(ot["ijk"], c, origin, size, halo) > 0 for c in cells)
+    assert (n_exp == 8).sum() > 1000  # the blend of eight experts is exercised
+    err = np.abs(got - want)
+    if p == gpu_lib.FP32:
+        assert np.all(err <= 3e-5 * (1 + np.abs(want)))
+    else:
+        assert np.max(err) <= 6e-2
+
+
+def test_decode_moe_offset_grid_and_ragged_counts(gpu_lib, scene):
+    """A grid offset from the lattice, cell edge 40 (not a multiple of 8), so
+    that cells hold ragged voxel counts and buckets start mid-tile."""
+    tr, ot = scene
+    origin, size, halo = (-5, 3, 17), 40, 8
+    cells = gpu_lib.subdomain_cells(tr, origin, size, halo)
+    models, ex = _experts(gpu_lib, cells, origin, size, halo, (64, 3, 18), gpu_lib.FP32)
+    got = gpu_lib.decode_moe(models, cells, origin, size, halo, tr).cpu().numpy().astype(np.float64)
+    want = moe.decode_moe(ot["ijk"], ex, origin, size, halo)
+    assert np.all(np.abs(got - want) <= 3e-5 * (1 + np.abs(want)))
+
+
+def test_decode_moe_single_expert_equals_decode(gpu_lib):
+    """One cell whose gate is 1 on every voxel: the blend returns the expert's
+    own decode exactly."""
+    grid = workloads.sphere_sdf()
+    tr = gpu_lib.Tree(grid.to(DEV), (0, 0, 0), gpu_lib.SDF, 3.0)
+    origin, size, halo = (0, 0, 0), 64, 4
+    cells = gpu_lib.subdomain_cells(tr, origin, size, halo)
+    assert cells.tolist() == [[0, 0, 0]]
+    for prec in (gpu_lib.FP32, gpu_lib.BF16):
+        models, _ = _experts(gpu_lib, cells, origin, size, halo, (128, 4, 64), prec)
+        got = gpu_lib.decode_moe(models, cells, origin, size, halo, tr).cpu().numpy()
+        ref, _ = models[0].decode(tr, masks=False)
+        assert np.array_equal(got.view(np.uint32), ref.cpu().numpy().view(np.uint32))
+
+
+def test_moe_rejects_bad_arguments(gpu_lib, scene):
+    tr, ot = scene
+    origin = (0, 0, 0)
+    cells = gpu_lib.subdomain_cells(tr, origin, 64, 8)
+    models, _ = _experts(gpu_lib, cells, origin, 64, 8, (64, 3, 18), gpu_lib.FP32)
+    for size, halo in [(64, 0), (15, 8)]:
+        with pytest.raises(gpu_lib.NvdbError) as e:
+            gpu_lib.subdomain_cells(tr, origin, size, halo)
+        assert e.value.code == gpu_lib.E_INVALID
+        with pytest.raises(gpu_lib.NvdbError) as e:
+            gpu_lib.decode_moe(models, cells, origin, size, halo, tr)
+        assert e.value.code == gpu_lib.E_INVALID
+    # two experts for one cell
+    dup = cells.copy()
+    dup[1] = dup[0]
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        gpu_lib.decode_moe(models, dup, origin, 64, 8, tr)
+    assert e.value.code == gpu_lib.E_INVALID
+    # voxels no expert covers (the second sphere's cell left out)
+    keep = [k for k, c in enumerate(cells.tolist()) if c != [1, 0, 0]]
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        gpu_lib.decode_moe([models[k] for k in keep], cells[keep], origin, 64, 8, tr)
+    assert e.value.code == gpu_lib.E_INVALID
+    # an expert without parameters
+    bare = gpu_lib.Model({0: (64, 3, 18, 1)}, precision=gpu_lib.FP32, domain_size=80, value_scale=3.0)
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        gpu_lib.decode_moe([bare] + models[1:], cells, origin, 64, 8, tr)
+    assert e.value.code == gpu_lib.E_STATE
+    # the library still works after the errors
+    assert gpu_lib.decode_moe(models, cells, origin, 64, 8, tr).shape[0] == tr.info().n_voxels
