@@ -62,6 +62,7 @@ def main():
     ap.add_argument("--skip-cloud", action="store_true")
     ap.add_argument("--skip-small", action="store_true")
     ap.add_argument("--skip-query", action="store_true")
+    ap.add_argument("--skip-moe", action="store_true")
     ap.add_argument("--seq-frames", type=int, default=16)
     ap.add_argument("--seq-cap", type=int, default=2000)
     ap.add_argument("--seq-full-width", action="store_true",
@@ -270,6 +271,9 @@ def main():
     if not args.skip_query:
         print("random-access leg ...", file=sys.stderr, flush=True)
         out["random_access"] = random_access_leg(bf, tree)
+    if not args.skip_moe:
+        print("sparse-domain-decomposition leg ...", file=sys.stderr, flush=True)
+        out["moe"] = moe_leg(tree, bf, rep, args.fit_steps, tuned_g)
     if not args.skip_cpu:
         print("cpu baseline (FP64 oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(grid)
@@ -466,6 +470,72 @@ def cloud_leg(fit_steps, tuned_g):
                     "frac_of_fp8_peak": N * flops_fwd(2 * M, W, H, C) / dec8_s / 1e12 / 5000.0,
                     "l1_slots_per_s": 4096 * L1 / l18_s, "rms_err": rep8["rms"], "max_abs_err": rep8["max_abs"],
                     "l1": {"fp": r18["fp"], "fn": r18["fn"], "mismatch": r18["mismatch"]}}}
+
+
+def moe_leg(tree, single, rep_single, fit_steps, tuned_g, size=256, halo=8, reps=3):
+    """Sparse domain decomposition (Sec. 3.3, eq. moe) of the 512^3 volume into
+    256^3 subdomains with an 8-voxel halo: one BF16 regressor per kept cell,
+    each fitted for fit_steps steps on the voxels of its widened box, then the
+    gate-weighted blended decode of every active voxel, timed against the single
+    network's regressor decode of the same tree (median of `reps` after one
+    warm-up)."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2208_04448_amd import nvdb
+
+    origin = (0, 0, 0)
+    cells = nvdb.subdomain_cells(tree, origin, size, halo)
+    K = 2 * M
+    B0 = workloads.ffm_matrix(M, 10.0, seed=11)
+    th0 = workloads.init_params(K, W, H, C, seed=21)
+    experts, n_sub = [], []
+    t0 = time.perf_counter()
+    train_ms = 0.0
+    for c in cells:
+        sub = tree.subdomain(origin, size, halo, c)
+        n_sub.append(sub.info().n_voxels)
+        lo, D = nvdb.subdomain_box(origin, size, halo, c)
+        mdl = nvdb.Model({0: (W, H, M, C)}, precision=nvdb.BF16, domain_lo=lo, domain_size=D, value_scale=BAND)
+        mdl.set_encoding(0, B0)
+        mdl.set_params(0, th0)
+        if tuned_g:
+            mdl.set_train_groups(tuned_g)
+        kt = {}
+        mdl.fit(sub, steps=fit_steps, batch=BATCH, nets_mask=1, seed=0, lr=1e-3, lr_decay=0.975, lr_interval=100,
+                kernel_times=kt)
+        train_ms += kt["train_kernel_ms"]
+        experts.append(mdl)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t0
+
+    def timed(f):
+        f()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            f()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts))
+
+    values = nvdb.decode_moe(experts, cells, origin, size, halo, tree)
+    r = nvdb.errors(tree, values)
+    n = tree.info().n_voxels
+    t_moe = timed(lambda: nvdb.decode_moe(experts, cells, origin, size, halo, tree))
+    t_one = timed(lambda: single.decode(tree, masks=False))
+    return {"subdomain_size": size, "halo": halo, "experts": len(cells), "voxels": n,
+            "routed_pairs_per_voxel": float(sum(n_sub)) / n,
+            "fit_s": t_fit, "train_kernel_ms": train_ms, "steps_per_expert": fit_steps,
+            "blend_decode_ms": t_moe * 1e3, "blend_voxels_per_s": n / t_moe,
+            "single_decode_ms": t_one * 1e3, "single_voxels_per_s": n / t_one,
+            "max_abs_err_voxels": r["max_abs"], "rms_err_voxels": r["rms"], "iou": r["iou"],
+            "single_network": {"max_abs_err_voxels": rep_single["max_abs"], "rms_err_voxels": rep_single["rms"],
+                               "iou": rep_single["iou"]},
+            "note": "one regressor per kept 256^3 cell, each fitted for the single network's step count on its "
+                    "widened box; blended decode = routing + one forward launch per expert + blend, wall clock"}
 
 
 def random_access_leg(model, tree, n=1 << 20, batch=1 << 16, reps=5):
