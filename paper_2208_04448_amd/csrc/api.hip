@@ -1304,38 +1304,48 @@ nvdb_status nvdb_decode_moe(const nvdb_model* const* experts, const int32_t* cel
     const int64_t n = tree->n_vox;
     if (n == 0) return;
     hipStream_t st = (hipStream_t)stream;
-    DevBuf<int32_t> tab;
-    DevBuf<MoeBox> dbox;
-    DevBuf<uint32_t> cnt, start, cursor;
-    tab.alloc((size_t)total);
-    dbox.alloc((size_t)n_experts);
-    cnt.alloc((size_t)n_experts + 1);  // counts, then the uncovered voxels
-    start.alloc((size_t)n_experts);
-    cursor.alloc((size_t)n_experts);
-    NVDB_HIP(hipMemcpyAsync(tab.p, table.data(), (size_t)total * 4, hipMemcpyHostToDevice, st));
-    NVDB_HIP(hipMemcpyAsync(dbox.p, box.data(), box.size() * sizeof(MoeBox), hipMemcpyHostToDevice, st));
-    NVDB_HIP(hipMemsetAsync(cnt.p, 0, ((size_t)n_experts + 1) * 4, st));
-    NVDB_HIP(hipMemsetAsync(cursor.p, 0, (size_t)n_experts * 4, st));
-    moe_count(*tree, g, tab.p, n_experts, cnt.p, cnt.p + n_experts, st);
-    std::vector<uint32_t> hc((size_t)n_experts + 1);
-    NVDB_HIP(hipMemcpyAsync(hc.data(), cnt.p, hc.size() * 4, hipMemcpyDeviceToHost, st));
+    // small arrays in one allocation: lookup table, boxes, counts (+ the
+    // uncovered voxels), bucket starts, cursors
+    const size_t E = (size_t)n_experts;
+    const size_t o_box = ((size_t)total * 4 + 255) & ~(size_t)255;
+    const size_t o_cnt = o_box + ((E * sizeof(MoeBox) + 255) & ~(size_t)255);
+    const size_t o_start = o_cnt + (((E + 1) * 4 + 255) & ~(size_t)255);
+    const size_t o_cur = o_start + ((E * 4 + 255) & ~(size_t)255);
+    DevBuf<uint8_t> small;
+    small.alloc(o_cur + E * 4);
+    int32_t* tab = (int32_t*)small.p;
+    MoeBox* dbox = (MoeBox*)(small.p + o_box);
+    uint32_t* cnt = (uint32_t*)(small.p + o_cnt);
+    uint32_t* start = (uint32_t*)(small.p + o_start);
+    uint32_t* cursor = (uint32_t*)(small.p + o_cur);
+    NVDB_HIP(hipMemcpyAsync(tab, table.data(), (size_t)total * 4, hipMemcpyHostToDevice, st));
+    NVDB_HIP(hipMemcpyAsync(dbox, box.data(), E * sizeof(MoeBox), hipMemcpyHostToDevice, st));
+    NVDB_HIP(hipMemsetAsync(cnt, 0, (E + 1) * 4, st));
+    NVDB_HIP(hipMemsetAsync(cursor, 0, E * 4, st));
+    moe_count(*tree, g, tab, n_experts, cnt, cnt + n_experts, st);
+    std::vector<uint32_t> hc(E + 1);
+    NVDB_HIP(hipMemcpyAsync(hc.data(), cnt, hc.size() * 4, hipMemcpyDeviceToHost, st));
     NVDB_HIP(hipStreamSynchronize(st));
-    NVDB_REQUIRE(hc[(size_t)n_experts] == 0, NVDB_E_INVALID, "voxels that no expert's widened box holds");
-    std::vector<uint32_t> hs((size_t)n_experts);
+    NVDB_REQUIRE(hc[E] == 0, NVDB_E_INVALID, "voxels that no expert's widened box holds");
+    std::vector<uint32_t> hs(E);
     uint64_t pairs = 0;
-    for (int k = 0; k < n_experts; ++k) {
+    for (size_t k = 0; k < E; ++k) {
       hs[k] = (uint32_t)pairs;
       pairs += hc[k];
     }
-    DevBuf<float> bx, y, yslot;
-    DevBuf<uint32_t> bslot;
-    bx.alloc(3 * (size_t)pairs);
-    y.alloc((size_t)pairs);
-    bslot.alloc((size_t)pairs);
-    yslot.alloc(8 * (size_t)n);
-    NVDB_HIP(hipMemcpyAsync(start.p, hs.data(), hs.size() * 4, hipMemcpyHostToDevice, st));
-    moe_route(*tree, g, tab.p, dbox.p, n_experts, start.p, cursor.p, bx.p, bslot.p, st);
-    for (int k = 0; k < n_experts; ++k) {
+    // per-pair coordinates, outputs and slots, and eight slots per voxel, in one allocation
+    const size_t o_y = (12 * pairs + 255) & ~(size_t)255;
+    const size_t o_bs = o_y + ((4 * pairs + 255) & ~(size_t)255);
+    const size_t o_ys = o_bs + ((4 * pairs + 255) & ~(size_t)255);
+    DevBuf<uint8_t> big;
+    big.alloc(o_ys + 32 * (size_t)n);
+    float* bx = (float*)big.p;
+    float* y = (float*)(big.p + o_y);
+    uint32_t* bslot = (uint32_t*)(big.p + o_bs);
+    float* yslot = (float*)(big.p + o_ys);
+    NVDB_HIP(hipMemcpyAsync(start, hs.data(), E * 4, hipMemcpyHostToDevice, st));
+    moe_route(*tree, g, tab, dbox, n_experts, start, cursor, bx, bslot, st);
+    for (size_t k = 0; k < E; ++k) {
       if (hc[k] == 0) continue;
       const Net& N = net_of(experts[k], NVDB_NET_REGRESSOR);
       InferLaunch I{};
@@ -1343,14 +1353,14 @@ nvdb_status nvdb_decode_moe(const nvdb_model* const* experts, const int32_t* cel
       base_spec(experts[k], &I.spec);
       I.spec.src = SRC_COORDS;
       I.spec.direct = 1;
-      I.spec.coords = bx.p + 3 * (size_t)hs[k];
+      I.spec.coords = bx + 3 * (size_t)hs[k];
       I.spec.n = hc[k];
       I.out_kind = OUT_Y;
-      I.y = y.p + hs[k];
+      I.y = y + hs[k];
       launch_infer(N.ks, I, infer_grid(hc[k]), st);
-      query_scatter(y.p + hs[k], bslot.p + hs[k], hc[k], cnt.p + k, experts[k]->d.value_scale, yslot.p, st);
+      query_scatter(y + hs[k], bslot + hs[k], hc[k], cnt + k, experts[k]->d.value_scale, yslot, st);
     }
-    moe_blend(*tree, g, tab.p, yslot.p, values_dev, st);
+    moe_blend(*tree, g, tab, yslot, values_dev, st);
     NVDB_HIP(hipStreamSynchronize(st));
   });
 }

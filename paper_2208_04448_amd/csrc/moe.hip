@@ -80,6 +80,39 @@ __device__ __forceinline__ void for_each_expert(const MoeGrid& g, const int32_t*
       }
 }
 
+// Expert of slot j (j = (ix << 2) | (iy << 1) | iz) for a voxel whose candidate
+// cells are ax, ay, az, or -1.
+__device__ __forceinline__ int slot_expert(const MoeGrid& g, const int32_t* __restrict__ table, const AxisCells& ax,
+                                           const AxisCells& ay, const AxisCells& az, int j) {
+  const int ix = j >> 2, iy = (j >> 1) & 1, iz = j & 1;
+  if (ix >= ax.n || iy >= ay.n || iz >= az.n) return -1;
+  return expert_at(g, table, ax.base + ix, ay.base + iy, az.base + iz);
+}
+
+__device__ __forceinline__ uint64_t lanes_below() {
+  const int lane = (int)(threadIdx.x & 63u);
+  return (1ull << lane) - 1ull;
+}
+
+// Adds one per lane with k >= 0 to hist[k], one LDS atomic per distinct k in
+// the wave; returns each lane's position among the adds to its bin.  Every lane
+// of the wave must call it (the loop runs on wave-uniform ballots).
+__device__ __forceinline__ uint32_t wave_hist_add(uint32_t* hist, int k) {
+  uint32_t pos = 0;
+  uint64_t pending = __ballot(k >= 0);
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const int kl = __shfl(k, leader);
+    const uint64_t m = __ballot(k == kl);
+    uint32_t base = 0;
+    if ((int)(threadIdx.x & 63u) == leader) base = atomicAdd(&hist[kl], (uint32_t)__popcll(m));
+    base = __shfl(base, leader);
+    if (k == kl) pos = base + (uint32_t)__popcll(m & lanes_below());
+    pending &= ~m;
+  }
+  return pos;
+}
+
 // Bounding box of the leaf origins (init: INT_MAX x3, INT_MIN x3).
 __global__ void __launch_bounds__(256) k_leaf_bbox(const int4* __restrict__ leaf_o, int64_t n, int* __restrict__ box) {
   const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -117,12 +150,15 @@ __global__ void __launch_bounds__(256) k_moe_mark(const int4* __restrict__ leaf_
     flag[(ix * g.cdim[1] + iy) * g.cdim[2] + iz] = 1;
 }
 
-// Voxels inside a widened box [lo, lo + D)^3, appended (one atomic per wave).
+// Voxels inside a widened box [lo, lo + D)^3, appended (one global atomic per
+// block).
 __global__ void __launch_bounds__(256) k_moe_extract(const int4* __restrict__ leaf_o, const uint32_t* __restrict__ key,
                                                      const float* __restrict__ val, int64_t n, int lx, int ly, int lz,
                                                      int D, int32_t* __restrict__ ijk, float* __restrict__ v,
                                                      uint32_t* __restrict__ count) {
+  __shared__ uint32_t wcount[4], wbase[4];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int w = (int)(threadIdx.x >> 6);
   bool in = false;
   int3 p = make_int3(0, 0, 0);
   if (i < n) {
@@ -131,14 +167,19 @@ __global__ void __launch_bounds__(256) k_moe_extract(const int4* __restrict__ le
          (int64_t)p.z - lz >= 0 && (int64_t)p.z - lz < D;
   }
   const uint64_t b = __ballot(in);
-  if (b == 0ull) return;
-  const int lane = (int)(threadIdx.x & 63u);
-  const int leader = __ffsll((long long)b) - 1;
-  uint32_t base = 0;
-  if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(b));
-  base = __shfl(base, leader);
+  if ((threadIdx.x & 63u) == 0) wcount[w] = (uint32_t)__popcll(b);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t t = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+    uint32_t s = t ? atomicAdd(count, t) : 0u;
+    for (int k = 0; k < 4; ++k) {
+      wbase[k] = s;
+      s += wcount[k];
+    }
+  }
+  __syncthreads();
   if (in) {
-    const uint32_t s = base + (uint32_t)__popcll(b & ((1ull << lane) - 1ull));
+    const uint32_t s = wbase[w] + (uint32_t)__popcll(b & lanes_below());
     ijk[3 * (size_t)s] = p.x;
     ijk[3 * (size_t)s + 1] = p.y;
     ijk[3 * (size_t)s + 2] = p.z;
@@ -146,8 +187,24 @@ __global__ void __launch_bounds__(256) k_moe_extract(const int4* __restrict__ le
   }
 }
 
+// Candidate cells of voxel i (none past n).
+__device__ __forceinline__ void voxel_cells(const int4* __restrict__ leaf_o, const uint32_t* __restrict__ key,
+                                            int64_t i, int64_t n, const MoeGrid& g, int3& p, AxisCells& ax,
+                                            AxisCells& ay, AxisCells& az) {
+  p = make_int3(0, 0, 0);
+  ax = ay = az = AxisCells{0, 0};
+  if (i < n) {
+    p = voxel_of(leaf_o, key[i]);
+    ax = axis_cells(p.x, g.o[0], g.S, g.h);
+    ay = axis_cells(p.y, g.o[1], g.S, g.h);
+    az = axis_cells(p.z, g.o[2], g.S, g.h);
+  }
+}
+
 // Pass 1 of the routing: (voxel, expert) pairs per expert, and voxels no expert
-// covers.  Per-block histogram in LDS, one global atomic per (block, expert).
+// covers.  Each block walks several 256-voxel tiles (block-uniform trip count)
+// into an LDS histogram (wave-aggregated adds), then adds it to the global
+// counts with one atomic per (block, expert).
 __global__ void __launch_bounds__(256) k_moe_count(const int4* __restrict__ leaf_o, const uint32_t* __restrict__ key,
                                                    int64_t n, MoeGrid g, const int32_t* __restrict__ table,
                                                    int n_exp, uint32_t* __restrict__ cnt,
@@ -157,15 +214,20 @@ __global__ void __launch_bounds__(256) k_moe_count(const int4* __restrict__ leaf
   for (int k = threadIdx.x; k < n_exp; k += blockDim.x) hist[k] = 0u;
   if (threadIdx.x == 0) unc = 0u;
   __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    const int3 p = voxel_of(leaf_o, key[i]);
-    int m = 0;
-    for_each_expert(g, table, p, [&](int, int k, float) {
-      atomicAdd(&hist[k], 1u);
-      ++m;
-    });
-    if (m == 0) atomicAdd(&unc, 1u);
+  for (int64_t t0 = (int64_t)blockIdx.x * 256; t0 < n; t0 += (int64_t)gridDim.x * 256) {
+    const int64_t i = t0 + threadIdx.x;
+    int3 p;
+    AxisCells ax, ay, az;
+    voxel_cells(leaf_o, key, i, n, g, p, ax, ay, az);
+    bool covered = false;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = slot_expert(g, table, ax, ay, az, j);
+      covered |= k >= 0;
+      (void)wave_hist_add(hist, k);
+    }
+    const uint64_t bad = __ballot(i < n && !covered);
+    if ((threadIdx.x & 63u) == 0 && bad) atomicAdd(&unc, (uint32_t)__popcll(bad));
   }
   __syncthreads();
   for (int k = threadIdx.x; k < n_exp; k += blockDim.x)
@@ -173,9 +235,11 @@ __global__ void __launch_bounds__(256) k_moe_count(const int4* __restrict__ leaf
   if (threadIdx.x == 0 && unc) atomicAdd(uncovered, unc);
 }
 
-// Pass 2: writes each pair into its expert's bucket (offset `start[k]` plus a
-// block range reserved with one atomic): the expert's normalised coordinates
-// and the voxel's slot 8 i + j.
+// Pass 2: writes each pair into its expert's bucket: the expert's normalised
+// coordinates and the voxel's slot 8 i + j.  A block counts its pairs per
+// expert, reserves one range per expert after `start[k]` with one atomic, then
+// walks its tiles again and fills the ranges (positions from fresh LDS
+// counters: any order within a range will do).
 __global__ void __launch_bounds__(256) k_moe_route(const int4* __restrict__ leaf_o, const uint32_t* __restrict__ key,
                                                    int64_t n, MoeGrid g, const int32_t* __restrict__ table,
                                                    const MoeBox* __restrict__ box, int n_exp,
@@ -183,29 +247,37 @@ __global__ void __launch_bounds__(256) k_moe_route(const int4* __restrict__ leaf
                                                    float* __restrict__ bx, uint32_t* __restrict__ bslot) {
   __shared__ uint32_t hist[MOE_MAX_EXPERTS];
   __shared__ uint32_t base[MOE_MAX_EXPERTS];
-  for (int k = threadIdx.x; k < n_exp; k += blockDim.x) hist[k] = 0u;
+  __shared__ uint32_t fill[MOE_MAX_EXPERTS];
+  for (int k = threadIdx.x; k < n_exp; k += blockDim.x) hist[k] = fill[k] = 0u;
   __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int3 p = make_int3(0, 0, 0);
-  if (i < n) {
-    p = voxel_of(leaf_o, key[i]);
-    for_each_expert(g, table, p, [&](int, int k, float) { atomicAdd(&hist[k], 1u); });
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t t0 = (int64_t)blockIdx.x * 256; t0 < n; t0 += stride) {
+    int3 p;
+    AxisCells ax, ay, az;
+    voxel_cells(leaf_o, key, t0 + threadIdx.x, n, g, p, ax, ay, az);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) (void)wave_hist_add(hist, slot_expert(g, table, ax, ay, az, j));
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < n_exp; k += blockDim.x) {
-    base[k] = hist[k] ? start[k] + atomicAdd(&cursor[k], hist[k]) : 0u;
-    hist[k] = 0u;
-  }
+  for (int k = threadIdx.x; k < n_exp; k += blockDim.x) base[k] = hist[k] ? start[k] + atomicAdd(&cursor[k], hist[k]) : 0u;
   __syncthreads();
-  if (i < n) {
-    for_each_expert(g, table, p, [&](int j, int k, float) {
-      const uint32_t s = base[k] + atomicAdd(&hist[k], 1u);
+  for (int64_t t0 = (int64_t)blockIdx.x * 256; t0 < n; t0 += stride) {
+    const int64_t i = t0 + threadIdx.x;
+    int3 p;
+    AxisCells ax, ay, az;
+    voxel_cells(leaf_o, key, i, n, g, p, ax, ay, az);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = slot_expert(g, table, ax, ay, az, j);
+      const uint32_t pos = wave_hist_add(fill, k);
+      if (k < 0) continue;
+      const uint32_t s = base[k] + pos;
       const MoeBox b = box[k];
       bx[3 * (size_t)s] = ((float)(p.x - b.lo[0]) + 0.5f) * b.inv_d;
       bx[3 * (size_t)s + 1] = ((float)(p.y - b.lo[1]) + 0.5f) * b.inv_d;
       bx[3 * (size_t)s + 2] = ((float)(p.z - b.lo[2]) + 0.5f) * b.inv_d;
       bslot[s] = (uint32_t)(8 * i + j);
-    });
+    }
   }
 }
 
@@ -225,6 +297,8 @@ __global__ void __launch_bounds__(256) k_moe_blend(const int4* __restrict__ leaf
 }
 
 unsigned grid_of(int64_t n) { return (unsigned)((n + 255) / 256); }
+// the routing passes: at most four blocks per compute unit, each walking several tiles
+unsigned route_grid(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 1024); }
 
 }  // namespace
 
@@ -266,14 +340,14 @@ int64_t moe_extract(const Tree& t, const int32_t lo[3], int32_t D, int32_t* ijk,
 
 void moe_count(const Tree& t, const MoeGrid& g, const int32_t* table, int n_exp, uint32_t* cnt, uint32_t* uncovered,
                hipStream_t st) {
-  hipLaunchKernelGGL(k_moe_count, dim3(grid_of(t.n_vox)), dim3(256), 0, st, t.leaf_o.p, t.vox_key.p, t.n_vox, g,
+  hipLaunchKernelGGL(k_moe_count, dim3(route_grid(t.n_vox)), dim3(256), 0, st, t.leaf_o.p, t.vox_key.p, t.n_vox, g,
                      table, n_exp, cnt, uncovered);
   NVDB_HIP(hipGetLastError());
 }
 
 void moe_route(const Tree& t, const MoeGrid& g, const int32_t* table, const MoeBox* box, int n_exp,
                const uint32_t* start, uint32_t* cursor, float* bx, uint32_t* bslot, hipStream_t st) {
-  hipLaunchKernelGGL(k_moe_route, dim3(grid_of(t.n_vox)), dim3(256), 0, st, t.leaf_o.p, t.vox_key.p, t.n_vox, g,
+  hipLaunchKernelGGL(k_moe_route, dim3(route_grid(t.n_vox)), dim3(256), 0, st, t.leaf_o.p, t.vox_key.p, t.n_vox, g,
                      table, box, n_exp, start, cursor, bx, bslot);
   NVDB_HIP(hipGetLastError());
 }
