@@ -473,7 +473,7 @@ def cloud_leg(fit_steps, tuned_g):
 
 
 def moe_leg(tree, single, rep_single, fit_steps, tuned_g, size=256, halo=8, reps=3):
-    """Sparse domain decomposition (Sec. 3.3, eq. moe) of the 512^3 volume into
+    """Sparse domain decomposition (Sec. 3.4, eq. moe) of the 512^3 volume into
     256^3 subdomains with an 8-voxel halo: one BF16 regressor per kept cell,
     each fitted for fit_steps steps on the voxels of its widened box, then the
     gate-weighted blended decode of every active voxel, timed against the single

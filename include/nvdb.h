@@ -341,7 +341,7 @@ nvdb_status nvdb_topology_patches(const nvdb_tree* truth, const nvdb_tree* pred,
                                   int32_t* fn_dev, int64_t fn_cap, int64_t* n_fp, int64_t* n_fn, void* stream);
 
 /* ------------------------------------------- sparse domain decomposition */
-/* Regular grid of cubic subdomains (Sec. 3.3, sparse domain decomposition):
+/* Regular grid of cubic subdomains (Sec. 3.4, sparse domain decomposition):
  * cell c = (cx, cy, cz) has the core [origin + c size, origin + (c+1) size)
  * per axis and the widened box [origin + c size - halo, origin + (c+1) size +
  * halo) (the paper takes halo 8 and size 512 to 2048).  Every call checks

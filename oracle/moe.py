@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see the package header).
 
-Sec. 3.3 ("Sparse Domain Decomposition", eq. moe): index space is cut into a
+Sec. 3.4 ("Sparse Domain Decomposition", eq. moe): index space is cut into a
 regular grid of cubic subdomains of edge S; subdomain D_k is widened on every
 side by a halo of h voxels (the paper takes h = 8), so that neighbours overlap.
 Subdomains holding no voxel are dropped.  Each remaining subdomain owns its own

@@ -1,4 +1,4 @@
-// Sparse domain decomposition (NeuralVDB Sec. 3.3, eq. moe).
+// Sparse domain decomposition (NeuralVDB Sec. 3.4, eq. moe).
 //
 // Index space is cut into a regular grid of cubic cells of edge S; the widened
 // box of cell c is its core [o + cS, o + (c+1)S) grown by a halo of h voxels on

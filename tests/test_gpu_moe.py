@@ -1,4 +1,4 @@
-"""GPU parity of the sparse domain decomposition (Sec. 3.3, eq. moe) through the
+"""GPU parity of the sparse domain decomposition (Sec. 3.4, eq. moe) through the
 C-ABI against the oracle on the same seeded inputs.
 
   * kept cells and the experts' subdomain trees: bit-exact;

@@ -1,4 +1,4 @@
-"""Pins of the sparse-domain-decomposition oracle (Sec. 3.3, eq. moe): tent
+"""Pins of the sparse-domain-decomposition oracle (Sec. 3.4, eq. moe): tent
 values in closed form, partition of unity, the eight-expert bound, kept cells
 by brute force, subdomain sizes of a dense block, the blend of constant
 experts (linear interpolation across the overlap), and the single-expert case
