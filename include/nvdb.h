@@ -378,8 +378,10 @@ nvdb_status nvdb_tree_subdomain(const nvdb_tree* tree, const nvdb_subdomains* gr
  * clamped tent: the product over the axes of min(t, size + 2 halo - t,
  * 2 halo) / (2 halo), t the distance of the voxel centre from the lower face of
  * the widened box.  Each expert computes in its own precision.  values_dev is
- * float32[N] in the tree's voxel order (as nvdb_decode).  Synchronises
- * `stream`.  Errors: E_INVALID (null arguments, n_experts outside [1, 4096],
+ * float32[N] in the tree's voxel order (as nvdb_decode).  Scratch (16 B per
+ * routed pair plus 32 B per voxel, grown to the largest call) stays allocated on
+ * each device until the process ends; calls on one device take turns on it.
+ * Synchronises `stream`.  Errors: E_INVALID (null arguments, n_experts outside [1, 4096],
  * two experts for one cell, experts spanning more than 2^24 cells, a tree of
  * 2^29 voxels or more, or a voxel that no expert's widened box holds: then
  * values_dev is unspecified), E_STATE (an expert's regressor unset). */

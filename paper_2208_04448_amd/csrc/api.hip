@@ -5,6 +5,8 @@
 #include <cstring>
 #include <cfloat>
 #include <limits>
+#include <map>
+#include <mutex>
 #include <new>
 
 #include "nvdb_internal.h"
@@ -1190,6 +1192,30 @@ static MoeGrid check_grid(const nvdb_subdomains* g) {
   m.h = g->halo;
   return m;
 }
+// Scratch of the blended decode, one per device, grown on demand and kept until
+// the process ends (never freed: the runtime may be gone at exit).  A call holds
+// its device's lock from the first use to its final synchronisation.
+struct MoeScratch {
+  std::mutex mu;
+  DevBuf<uint8_t> small, big;
+};
+static MoeScratch& moe_scratch() {
+  static std::mutex m;
+  static std::map<int, MoeScratch*> per_device;
+  int dev = 0;
+  NVDB_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(m);
+  MoeScratch*& s = per_device[dev];
+  if (!s) s = new MoeScratch();
+  return *s;
+}
+// Waits for the stream when a call leaves early, so that its kernels are done
+// with the shared scratch before the lock is released.
+struct StreamDrain {
+  hipStream_t st;
+  ~StreamDrain() { (void)hipStreamSynchronize(st); }
+};
+
 static int64_t floor_div64(int64_t a, int64_t s) { return a >= 0 ? a / s : -((-a + s - 1) / s); }
 static int64_t cell_range_size(const MoeGrid& g) { return (int64_t)g.cdim[0] * g.cdim[1] * g.cdim[2]; }
 static constexpr int64_t MOE_MAX_RANGE = 1ll << 24;
@@ -1311,13 +1337,16 @@ nvdb_status nvdb_decode_moe(const nvdb_model* const* experts, const int32_t* cel
     const size_t o_cnt = o_box + ((E * sizeof(MoeBox) + 255) & ~(size_t)255);
     const size_t o_start = o_cnt + (((E + 1) * 4 + 255) & ~(size_t)255);
     const size_t o_cur = o_start + ((E * 4 + 255) & ~(size_t)255);
-    DevBuf<uint8_t> small;
-    small.alloc(o_cur + E * 4);
-    int32_t* tab = (int32_t*)small.p;
-    MoeBox* dbox = (MoeBox*)(small.p + o_box);
-    uint32_t* cnt = (uint32_t*)(small.p + o_cnt);
-    uint32_t* start = (uint32_t*)(small.p + o_start);
-    uint32_t* cursor = (uint32_t*)(small.p + o_cur);
+    MoeScratch& ws = moe_scratch();
+    std::lock_guard<std::mutex> lock(ws.mu);
+    StreamDrain drain{st};  // declared after the lock: runs before it is released
+    ws.small.ensure(o_cur + E * 4);
+    uint8_t* small = ws.small.p;
+    int32_t* tab = (int32_t*)small;
+    MoeBox* dbox = (MoeBox*)(small + o_box);
+    uint32_t* cnt = (uint32_t*)(small + o_cnt);
+    uint32_t* start = (uint32_t*)(small + o_start);
+    uint32_t* cursor = (uint32_t*)(small + o_cur);
     NVDB_HIP(hipMemcpyAsync(tab, table.data(), (size_t)total * 4, hipMemcpyHostToDevice, st));
     NVDB_HIP(hipMemcpyAsync(dbox, box.data(), E * sizeof(MoeBox), hipMemcpyHostToDevice, st));
     NVDB_HIP(hipMemsetAsync(cnt, 0, (E + 1) * 4, st));
@@ -1337,12 +1366,12 @@ nvdb_status nvdb_decode_moe(const nvdb_model* const* experts, const int32_t* cel
     const size_t o_y = (12 * pairs + 255) & ~(size_t)255;
     const size_t o_bs = o_y + ((4 * pairs + 255) & ~(size_t)255);
     const size_t o_ys = o_bs + ((4 * pairs + 255) & ~(size_t)255);
-    DevBuf<uint8_t> big;
-    big.alloc(o_ys + 32 * (size_t)n);
-    float* bx = (float*)big.p;
-    float* y = (float*)(big.p + o_y);
-    uint32_t* bslot = (uint32_t*)(big.p + o_bs);
-    float* yslot = (float*)(big.p + o_ys);
+    ws.big.ensure(o_ys + 32 * (size_t)n);
+    uint8_t* big = ws.big.p;
+    float* bx = (float*)big;
+    float* y = (float*)(big + o_y);
+    uint32_t* bslot = (uint32_t*)(big + o_bs);
+    float* yslot = (float*)(big + o_ys);
     NVDB_HIP(hipMemcpyAsync(start, hs.data(), E * 4, hipMemcpyHostToDevice, st));
     moe_route(*tree, g, tab, dbox, n_experts, start, cursor, bx, bslot, st);
     for (size_t k = 0; k < E; ++k) {

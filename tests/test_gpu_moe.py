@@ -152,3 +152,28 @@ def test_moe_rejects_bad_arguments(gpu_lib, scene):
     assert e.value.code == gpu_lib.E_STATE
     # the library still works after the errors
     assert gpu_lib.decode_moe(models, cells, origin, 64, 8, tr).shape[0] == tr.info().n_voxels
+
+
+def test_decode_moe_full_size_sampled(gpu_lib):
+    """The benchmark's configuration: the 512^3 level set (2,994,515 voxels) in
+    256^3 cells with an 8-voxel halo, eight BF16 4x128 experts (K 128), one
+    blended decode of every voxel; 4096 sampled voxels checked against the
+    oracle, half of them where two or more experts blend."""
+    grid = workloads.noise_sphere_sdf(512, center=(256.0, 256.0, 256.0), radius=200.0, amplitude=20.0, octaves=4,
+                                      scale=64.0, seed=0, device=DEV)
+    ijk, vals = T.active_set_dense(grid.cpu().numpy(), (0, 0, 0), T.SDF, 3.0)
+    ot = T.build(ijk, vals)
+    tr = gpu_lib.Tree(grid, (0, 0, 0), T.SDF, 3.0)
+    origin, size, halo = (0, 0, 0), 256, 8
+    cells = gpu_lib.subdomain_cells(tr, origin, size, halo)
+    assert np.array_equal(cells, moe.kept_cells(ot["ijk"], origin, size).astype(np.int32))
+    models, ex = _experts(gpu_lib, cells, origin, size, halo, (128, 4, 64), gpu_lib.BF16)
+    got = gpu_lib.decode_moe(models, cells, origin, size, halo, tr).cpu().numpy().astype(np.float64)
+    n_exp = sum(moe.gate(ot["ijk"], c, origin, size, halo) > 0 for c in cells)
+    rng = np.random.default_rng(7)
+    multi = np.flatnonzero(n_exp >= 2)
+    sel = np.concatenate([rng.choice(multi, 2048, replace=False),
+                          rng.choice(len(ot["ijk"]), 2048, replace=False)])
+    want = moe.decode_moe(ot["ijk"][sel], ex, origin, size, halo)
+    assert np.max(np.abs(got[sel] - want)) <= 6e-2
+    assert np.all(np.isfinite(got))
