@@ -490,11 +490,12 @@ def moe_leg(tree, single, rep_single, fit_steps, tuned_g, size=256, halo=8, reps
     K = 2 * M
     B0 = workloads.ffm_matrix(M, 10.0, seed=11)
     th0 = workloads.init_params(K, W, H, C, seed=21)
-    experts, n_sub = [], []
+    experts, subs, n_sub = [], [], []
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    train_ms = 0.0
     for c in cells:
         sub = tree.subdomain(origin, size, halo, c)
+        subs.append(sub)
         n_sub.append(sub.info().n_voxels)
         lo, D = nvdb.subdomain_box(origin, size, halo, c)
         mdl = nvdb.Model({0: (W, H, M, C)}, precision=nvdb.BF16, domain_lo=lo, domain_size=D, value_scale=BAND)
@@ -502,11 +503,12 @@ def moe_leg(tree, single, rep_single, fit_steps, tuned_g, size=256, halo=8, reps
         mdl.set_params(0, th0)
         if tuned_g:
             mdl.set_train_groups(tuned_g)
-        kt = {}
-        mdl.fit(sub, steps=fit_steps, batch=BATCH, nets_mask=1, seed=0, lr=1e-3, lr_decay=0.975, lr_interval=100,
-                kernel_times=kt)
-        train_ms += kt["train_kernel_ms"]
         experts.append(mdl)
+    torch.cuda.synchronize()
+    t_split = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    nvdb.fit_experts(experts, subs, steps=fit_steps, batch=BATCH, nets_mask=1, seed=0, lr=1e-3, lr_decay=0.975,
+                     lr_interval=100)
     torch.cuda.synchronize()
     t_fit = time.perf_counter() - t0
 
@@ -528,14 +530,16 @@ def moe_leg(tree, single, rep_single, fit_steps, tuned_g, size=256, halo=8, reps
     t_one = timed(lambda: single.decode(tree, masks=False))
     return {"subdomain_size": size, "halo": halo, "experts": len(cells), "voxels": n,
             "routed_pairs_per_voxel": float(sum(n_sub)) / n,
-            "fit_s": t_fit, "train_kernel_ms": train_ms, "steps_per_expert": fit_steps,
+            "split_s": t_split, "fit_s": t_fit, "steps_per_expert": fit_steps,
+            "train_samples_per_s": len(cells) * fit_steps * BATCH / t_fit,
             "blend_decode_ms": t_moe * 1e3, "blend_voxels_per_s": n / t_moe,
             "single_decode_ms": t_one * 1e3, "single_voxels_per_s": n / t_one,
             "max_abs_err_voxels": r["max_abs"], "rms_err_voxels": r["rms"], "iou": r["iou"],
             "single_network": {"max_abs_err_voxels": rep_single["max_abs"], "rms_err_voxels": rep_single["rms"],
                                "iou": rep_single["iou"]},
             "note": "one regressor per kept 256^3 cell, each fitted for the single network's step count on its "
-                    "widened box; blended decode = routing + one forward launch per expert + blend, wall clock"}
+                    "widened box, the experts two at a time (nvdb_fit_experts); split = subdomain trees + models; "
+                    "blended decode = routing + one forward launch per expert + blend, wall clock"}
 
 
 def random_access_leg(model, tree, n=1 << 20, batch=1 << 16, reps=5):

@@ -8,6 +8,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <string>
 
 #include "nvdb_internal.h"
 
@@ -685,6 +686,74 @@ nvdb_status nvdb_fit(nvdb_model* m, const nvdb_tree* tree, const nvdb_fit_desc* 
         }
       }
       NVDB_REQUIRE(finite, NVDB_E_NUMERIC, "non-finite loss during fit");
+    }
+  });
+}
+
+nvdb_status nvdb_fit_experts(nvdb_model* const* models, const nvdb_tree* const* trees, int32_t n,
+                             const nvdb_fit_desc* fit, float* loss_host, void* stream) {
+  return guarded([&] {
+    NVDB_REQUIRE(models && trees && fit, NVDB_E_INVALID, "null argument");
+    NVDB_REQUIRE(n >= 1 && n <= MOE_MAX_EXPERTS, NVDB_E_INVALID, "expert count outside [1, 4096]");
+    for (int e = 0; e < n; ++e) {
+      NVDB_REQUIRE(models[e] && trees[e], NVDB_E_INVALID, "null expert or tree");
+      for (int f = 0; f < e; ++f) NVDB_REQUIRE(models[f] != models[e], NVDB_E_INVALID, "a model listed twice");
+    }
+    check_schedule(fit);
+    // every workspace first: a buffer grown while other experts' steps are queued
+    // would free memory, and a free waits for the whole device
+    for (int e = 0; e < n; ++e)
+      for (int k : fit_nets(models[e], trees[e], fit->nets_mask))
+        reserve_step(models[e]->nets[k], fit->batch, fit->steps,
+                     models[e]->train_g > 0 ? models[e]->train_g : DEFAULT_G);
+    hipStream_t st = (hipStream_t)stream;
+    // A one-network training launch at the default 128 work-groups holds half of
+    // the 256 compute units: two streams let two experts' steps run side by side.
+    constexpr int NS = 2;
+    hipStream_t s[NS] = {};
+    hipEvent_t after = nullptr;
+    nvdb_status bad = NVDB_OK;
+    std::string msg;
+    NVDB_HIP(hipEventCreateWithFlags(&after, hipEventDisableTiming));
+    NVDB_HIP(hipEventRecord(after, st));
+    for (int i = 0; i < NS && bad == NVDB_OK; ++i) {
+      if (hipStreamCreateWithFlags(&s[i], hipStreamNonBlocking) != hipSuccess ||
+          hipStreamWaitEvent(s[i], after, 0) != hipSuccess) {
+        bad = NVDB_E_DEVICE;
+        msg = "stream setup failed";
+      }
+    }
+    nvdb_fit_desc f = *fit;
+    f.train_kernel_ms = nullptr;  // no per-launch timing: the fits overlap
+    for (int e = 0; e < n && bad == NVDB_OK; ++e) {
+      const nvdb_status r = nvdb_fit(models[e], trees[e], &f, nullptr, s[e % NS]);
+      if (r != NVDB_OK) {
+        bad = r;
+        msg = nvdb_last_error();
+      }
+    }
+    for (int i = 0; i < NS; ++i)
+      if (s[i]) {
+        if (hipStreamSynchronize(s[i]) != hipSuccess && bad == NVDB_OK) {
+          bad = NVDB_E_DEVICE;
+          msg = "expert fit failed on the device";
+        }
+        (void)hipStreamDestroy(s[i]);
+      }
+    (void)hipEventDestroy(after);
+    if (bad != NVDB_OK) throw Error(bad, msg);
+    if (loss_host && fit->steps > 0) {
+      std::vector<float> h((size_t)fit->steps);
+      bool finite = true;
+      for (int e = 0; e < n; ++e)
+        for (int k : fit_nets(models[e], trees[e], fit->nets_mask)) {
+          NVDB_HIP(hipMemcpy(h.data(), models[e]->nets[k].losses.p, (size_t)fit->steps * 4, hipMemcpyDeviceToHost));
+          for (int i = 0; i < fit->steps; ++i) {
+            loss_host[((int64_t)e * NVDB_MAX_NETS + k) * fit->steps + i] = h[i];
+            finite = finite && std::isfinite(h[i]);
+          }
+        }
+      NVDB_REQUIRE(finite, NVDB_E_NUMERIC, "non-finite loss during an expert fit");
     }
   });
 }

@@ -109,6 +109,7 @@ _SIGS = {
     "nvdb_model_set_opt_state": (C.c_int32, [_P, C.c_int32, _P, _P, C.c_int64, C.c_int64]),
     "nvdb_model_free": (None, [_P]),
     "nvdb_fit": (C.c_int32, [_P, _P, C.POINTER(FitDesc), _P, _P]),
+    "nvdb_fit_experts": (C.c_int32, [C.POINTER(_P), C.POINTER(_P), C.c_int32, C.POINTER(FitDesc), _P, _P]),
     "nvdb_fit_sequence": (C.c_int32, [_P, _P, C.c_int32, C.POINTER(FitDesc), C.POINTER(FitDesc), C.c_int32, _P, _P,
                                       _P, _P]),
     "nvdb_autotune": (C.c_int32, [_P, _P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(TuneReport), _P]),
@@ -453,6 +454,21 @@ def decode_moe(experts, cells, origin, size, halo, tree):
     _check(_lib.nvdb_decode_moe(hs, cells.ctypes.data_as(C.c_void_p), len(experts), C.byref(g), tree.h, _ptr(v),
                                 _stream()))
     return v
+
+
+def fit_experts(models, trees, steps, batch, nets_mask, seed=0, lr=1e-3, lr_decay=0.975, lr_interval=100,
+                return_losses=False):
+    """The fits of independent models (one per subdomain) on their trees, two at a time on the GPU."""
+    assert len(models) == len(trees)
+    f = FitDesc()
+    f.steps, f.batch, f.seed = steps, batch, seed
+    f.lr, f.lr_decay, f.lr_interval, f.nets_mask = lr, lr_decay, lr_interval, nets_mask
+    hm = (_P * len(models))(*[m.h for m in models])
+    ht = (_P * len(trees))(*[t.h for t in trees])
+    losses = np.zeros((len(models), MAX_NETS, max(steps, 1)), np.float32) if return_losses else None
+    _check(_lib.nvdb_fit_experts(hm, ht, len(models), C.byref(f),
+                                 losses.ctypes.data_as(C.c_void_p) if return_losses else None, _stream()))
+    return losses[:, :, :steps] if return_losses else None
 
 
 def errors_topology(truth, pred):

@@ -177,3 +177,32 @@ def test_decode_moe_full_size_sampled(gpu_lib):
     want = moe.decode_moe(ot["ijk"][sel], ex, origin, size, halo)
     assert np.max(np.abs(got[sel] - want)) <= 6e-2
     assert np.all(np.isfinite(got))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_fit_experts_equals_sequential_fits(gpu_lib, scene, prec):
+    """Experts fitted together (two streams) end bit-identical to the same fits
+    run one after the other, with the same losses (the kernels are
+    deterministic and the fits share nothing)."""
+    tr, _ = scene
+    p = gpu_lib.FP32 if prec == "fp32" else gpu_lib.BF16
+    origin, size, halo = (0, 0, 0), 64, 8
+    cells = gpu_lib.subdomain_cells(tr, origin, size, halo)[:5]
+    trees = [tr.subdomain(origin, size, halo, c) for c in cells]
+    a, _ = _experts(gpu_lib, cells, origin, size, halo, (64, 3, 18), p)
+    b, _ = _experts(gpu_lib, cells, origin, size, halo, (64, 3, 18), p)
+    la = np.stack([m.fit(t, steps=30, batch=4096, nets_mask=1, seed=3) for m, t in zip(a, trees)])
+    lb = gpu_lib.fit_experts(b, trees, steps=30, batch=4096, nets_mask=1, seed=3, return_losses=True)
+    for ma, mb in zip(a, b):
+        assert np.array_equal(ma.get_params(0).view(np.uint32), mb.get_params(0).view(np.uint32))
+    assert np.array_equal(la[:, 0], lb[:, 0])
+    assert np.all(np.isfinite(lb[:, 0])) and np.all(lb[:, 0, -5:].mean(1) < lb[:, 0, :3].mean(1))
+    # a second round continues from the step counters, as nvdb_fit does
+    for m, t in zip(a, trees):
+        m.fit(t, steps=5, batch=4096, nets_mask=1, seed=3, return_losses=False)
+    gpu_lib.fit_experts(b, trees, steps=5, batch=4096, nets_mask=1, seed=3)
+    for ma, mb in zip(a, b):
+        assert np.array_equal(ma.get_params(0).view(np.uint32), mb.get_params(0).view(np.uint32))
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        gpu_lib.fit_experts([b[0], b[0]], trees[:2], steps=1, batch=4096, nets_mask=1)
+    assert e.value.code == gpu_lib.E_INVALID
