@@ -271,12 +271,13 @@ def main():
     if not args.skip_query:
         print("random-access leg ...", file=sys.stderr, flush=True)
         out["random_access"] = random_access_leg(bf, tree)
+    moe_ctx = None
     if not args.skip_moe:
         print("sparse-domain-decomposition leg ...", file=sys.stderr, flush=True)
-        out["moe"] = moe_leg(tree, bf, rep, args.fit_steps, tuned_g)
+        out["moe"], moe_ctx = moe_leg(tree, bf, rep, args.fit_steps, tuned_g)
     if not args.skip_cpu:
         print("cpu baseline (FP64 oracle) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(grid)
+        out["cpu_baseline"] = cpu_baseline(grid, moe_ctx)
     del grid, bf
     torch.cuda.empty_cache()
     if not args.skip_sequence:
@@ -528,18 +529,22 @@ def moe_leg(tree, single, rep_single, fit_steps, tuned_g, size=256, halo=8, reps
     n = tree.info().n_voxels
     t_moe = timed(lambda: nvdb.decode_moe(experts, cells, origin, size, halo, tree))
     t_one = timed(lambda: single.decode(tree, masks=False))
+    pairs = sum(n_sub)
+    ctx = {"cells": cells, "origin": origin, "size": size, "halo": halo,
+           "experts": [(e.get_params(0), nvdb.subdomain_box(origin, size, halo, c)) for e, c in zip(experts, cells)]}
     return {"subdomain_size": size, "halo": halo, "experts": len(cells), "voxels": n,
             "routed_pairs_per_voxel": float(sum(n_sub)) / n,
             "split_s": t_split, "fit_s": t_fit, "steps_per_expert": fit_steps,
             "train_samples_per_s": len(cells) * fit_steps * BATCH / t_fit,
             "blend_decode_ms": t_moe * 1e3, "blend_voxels_per_s": n / t_moe,
+            "blend_tflops_whole_call": pairs * flops_fwd(2 * M, W, H, C) / t_moe / 1e12,
             "single_decode_ms": t_one * 1e3, "single_voxels_per_s": n / t_one,
             "max_abs_err_voxels": r["max_abs"], "rms_err_voxels": r["rms"], "iou": r["iou"],
             "single_network": {"max_abs_err_voxels": rep_single["max_abs"], "rms_err_voxels": rep_single["rms"],
                                "iou": rep_single["iou"]},
             "note": "one regressor per kept 256^3 cell, each fitted for the single network's step count on its "
                     "widened box, the experts two at a time (nvdb_fit_experts); split = subdomain trees + models; "
-                    "blended decode = routing + one forward launch per expert + blend, wall clock"}
+                    "blended decode = routing + one forward launch per expert + blend, wall clock"}, ctx
 
 
 def random_access_leg(model, tree, n=1 << 20, batch=1 << 16, reps=5):
@@ -656,9 +661,11 @@ def small_leg(reps=5):
     return res
 
 
-def cpu_baseline(grid):
+def cpu_baseline(grid, moe_ctx=None):
     """The FP64 oracle on the host: 3 Adam steps of the regressor at 2^14 samples
-    on the same volume, after building the oracle's own tree from the grid."""
+    on the same volume, after building the oracle's own tree from the grid; with
+    the experts of the decomposition leg, the oracle's blended decode of 2^14
+    sampled voxels."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
@@ -684,10 +691,22 @@ def cpu_baseline(grid):
     F.decode_values(th, shapes, B, tr, (0, 0, 0), N_GRID, T.SDF, BAND, idx=sel)
     dec_s = time.perf_counter() - t
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    return {"value": steps * batch / fit_s, "unit": "train samples/s", "cores": int(threads), "kind": "oracle",
+    extra = {}
+    if moe_ctx is not None:
+        from oracle import moe
+        shapes_e = mlp.layer_shapes(K, W, H, C)
+        ex = [dict(cell=c, theta=th_e.astype(np.float64), shapes=shapes_e, B=B, lo=lo_d[0], D=lo_d[1], scale=BAND)
+              for c, (th_e, lo_d) in zip(moe_ctx["cells"], moe_ctx["experts"])]
+        nm = 1 << 14
+        sel_m = np.random.default_rng(1).choice(len(vals), nm, replace=False)
+        t = time.perf_counter()
+        moe.decode_moe(tr["ijk"][sel_m], ex, moe_ctx["origin"], moe_ctx["size"], moe_ctx["halo"])
+        extra["moe_blend_voxels_per_s"] = nm / (time.perf_counter() - t)
+    return {**extra, "value": steps * batch / fit_s, "unit": "train samples/s", "cores": int(threads), "kind": "oracle",
             "sample": "3 Adam steps x 2^14 samples of the 4x128 regressor on the same 512^3 volume, FP64 numpy "
                       "(oracle tree build of %d voxels took %.1f s, not counted); decode of 2^17 sampled voxels "
-                      "for decode_voxels_per_s" % (len(vals), build_s),
+                      "for decode_voxels_per_s; blended decode (8 experts) of 2^14 sampled voxels for "
+                      "moe_blend_voxels_per_s" % (len(vals), build_s),
             "decode_voxels_per_s": nd / dec_s}
 
 
