@@ -209,13 +209,15 @@ nvdb_status nvdb_fit(nvdb_model* model, const nvdb_tree* tree, const nvdb_fit_de
 /* Fits of several independent models (the experts of a sparse domain
  * decomposition, Sec. 3.4: each subdomain's networks train on their own voxels
  * with no exchange), models[e] on trees[e], each exactly as nvdb_fit would run
- * it, with the same schedule.  The fits go round-robin onto two internal
- * streams (default priority) that start after the work already on `stream`, so
- * two experts' training launches share the GPU.  The call returns when every fit
- * is done.  loss_host, if not NULL, receives float[n][NVDB_MAX_NETS][steps].
- * fit->train_kernel_ms is ignored.  Errors: E_INVALID (null arguments, n outside
- * [1, 4096], a model listed twice, bad schedule), otherwise those of nvdb_fit
- * (the first failing expert's status and message; the others may have run). */
+ * it, with the same schedule (i.i.d. draws only).  The experts go round-robin
+ * onto two internal streams (default priority) that start after the work
+ * already on `stream`, and their steps are enqueued step by step across the
+ * experts, so two experts' training launches share the GPU.  The call returns
+ * when every fit is done.  loss_host, if not NULL, receives
+ * float[n][NVDB_MAX_NETS][steps].  fit->train_kernel_ms is ignored.  Errors:
+ * E_INVALID (null arguments, n outside [1, 4096], a model listed twice, explicit
+ * sample orders, bad schedule), otherwise those of nvdb_fit (on an error the
+ * experts may have run part of the schedule). */
 nvdb_status nvdb_fit_experts(nvdb_model* const* models, const nvdb_tree* const* trees, int32_t n,
                              const nvdb_fit_desc* fit, float* loss_host, void* stream);
 /* Launch-shape autotuner.  The training step splits each network's batch over

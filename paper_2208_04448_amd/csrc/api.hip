@@ -695,6 +695,8 @@ nvdb_status nvdb_fit_experts(nvdb_model* const* models, const nvdb_tree* const* 
   return guarded([&] {
     NVDB_REQUIRE(models && trees && fit, NVDB_E_INVALID, "null argument");
     NVDB_REQUIRE(n >= 1 && n <= MOE_MAX_EXPERTS, NVDB_E_INVALID, "expert count outside [1, 4096]");
+    for (int k = 0; k < NVDB_MAX_NETS; ++k)
+      NVDB_REQUIRE(fit->idx_dev[k] == nullptr, NVDB_E_INVALID, "explicit sample orders are per model (nvdb_fit)");
     for (int e = 0; e < n; ++e) {
       NVDB_REQUIRE(models[e] && trees[e], NVDB_E_INVALID, "null expert or tree");
       for (int f = 0; f < e; ++f) NVDB_REQUIRE(models[f] != models[e], NVDB_E_INVALID, "a model listed twice");
@@ -702,13 +704,21 @@ nvdb_status nvdb_fit_experts(nvdb_model* const* models, const nvdb_tree* const* 
     check_schedule(fit);
     // every workspace first: a buffer grown while other experts' steps are queued
     // would free memory, and a free waits for the whole device
-    for (int e = 0; e < n; ++e)
-      for (int k : fit_nets(models[e], trees[e], fit->nets_mask))
+    std::vector<std::vector<int>> nets((size_t)n);
+    std::vector<std::vector<std::vector<int>>> groups((size_t)n);
+    for (int e = 0; e < n; ++e) {
+      nets[e] = fit_nets(models[e], trees[e], fit->nets_mask);
+      groups[e] = kernel_groups(models[e], nets[e]);
+      for (int k : nets[e])
         reserve_step(models[e]->nets[k], fit->batch, fit->steps,
                      models[e]->train_g > 0 ? models[e]->train_g : DEFAULT_G);
+    }
+    const Phase ph{fit->batch, fit->seed, fit->lr, fit->lr_decay, fit->lr_interval, nullptr};
     hipStream_t st = (hipStream_t)stream;
     // A one-network training launch at the default 128 work-groups holds half of
     // the 256 compute units: two streams let two experts' steps run side by side.
+    // Steps are enqueued step-major across the experts, so that a full hardware
+    // queue on one stream never leaves the other without work.
     constexpr int NS = 2;
     hipStream_t s[NS] = {};
     hipEvent_t after = nullptr;
@@ -723,14 +733,16 @@ nvdb_status nvdb_fit_experts(nvdb_model* const* models, const nvdb_tree* const* 
         msg = "stream setup failed";
       }
     }
-    nvdb_fit_desc f = *fit;
-    f.train_kernel_ms = nullptr;  // no per-launch timing: the fits overlap
-    for (int e = 0; e < n && bad == NVDB_OK; ++e) {
-      const nvdb_status r = nvdb_fit(models[e], trees[e], &f, nullptr, s[e % NS]);
-      if (r != NVDB_OK) {
-        bad = r;
-        msg = nvdb_last_error();
-      }
+    try {
+      for (int step = 0; step < fit->steps && bad == NVDB_OK; ++step)
+        for (int e = 0; e < n; ++e) {
+          StepHooks hk;
+          for (int k : nets[e]) hk.loss_out[k] = models[e]->nets[k].losses.p + step;
+          enqueue_step(models[e], trees[e], groups[e], ph, step, hk, nullptr, s[e % NS]);
+        }
+    } catch (const Error& x) {
+      bad = x.code;
+      msg = x.what();
     }
     for (int i = 0; i < NS; ++i)
       if (s[i]) {
@@ -746,7 +758,7 @@ nvdb_status nvdb_fit_experts(nvdb_model* const* models, const nvdb_tree* const* 
       std::vector<float> h((size_t)fit->steps);
       bool finite = true;
       for (int e = 0; e < n; ++e)
-        for (int k : fit_nets(models[e], trees[e], fit->nets_mask)) {
+        for (int k : nets[e]) {
           NVDB_HIP(hipMemcpy(h.data(), models[e]->nets[k].losses.p, (size_t)fit->steps * 4, hipMemcpyDeviceToHost));
           for (int i = 0; i < fit->steps; ++i) {
             loss_host[((int64_t)e * NVDB_MAX_NETS + k) * fit->steps + i] = h[i];
