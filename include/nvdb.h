@@ -402,6 +402,18 @@ nvdb_status nvdb_tree_subdomain(const nvdb_tree* tree, const nvdb_subdomains* gr
 nvdb_status nvdb_decode_moe(const nvdb_model* const* experts, const int32_t* cells, int32_t n_experts,
                             const nvdb_subdomains* grid, const nvdb_tree* tree, float* values_dev, void* stream);
 
+/* The same blend for the level-0 masks (Sec. 3.4 applies the decomposition to
+ * masks as well as values): expert k's level-0 classifier runs at every voxel slot
+ * of the tree's leaves that its widened box holds, and slot bit = (sum_k G_k
+ * logit_k / sum_k G_k > 0).  mask_dev is uint64[n_leaves][8] (as in
+ * nvdb_decode).  The cell size and the grid origin must be multiples of 8 (then a
+ * leaf never straddles two cores and every slot has its leaf's expert).  Scratch,
+ * synchronisation and errors as nvdb_decode_moe, with 2^29 voxel slots as the
+ * limit and E_STATE for an unset level-0 classifier. */
+nvdb_status nvdb_decode_moe_mask(const nvdb_model* const* experts, const int32_t* cells, int32_t n_experts,
+                                 const nvdb_subdomains* grid, const nvdb_tree* tree, uint64_t* mask_dev,
+                                 void* stream);
+
 /* Level-1 classifier report (Sec. 3.3.1, Sec. 4) over the 4096 leaf slots of
  * every level-1 node: classes_dev is uint8[n_l1][4096] as written by
  * nvdb_decode_l1; the true class of a slot is 0 when it has a child leaf, else

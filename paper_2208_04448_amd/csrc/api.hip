@@ -1372,106 +1372,130 @@ nvdb_status nvdb_tree_subdomain(const nvdb_tree* tree, const nvdb_subdomains* gr
   });
 }
 
+}  // extern "C"
+
+// Blended decode over the active voxels (regressors, values) or over every voxel
+// slot of the leaves (level-0 classifiers, mask bits).
+static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cells, int32_t n_experts,
+                            const nvdb_subdomains* grid, const nvdb_tree* tree, int net, float* values_dev,
+                            uint64_t* mask_dev, hipStream_t st) {
+  NVDB_REQUIRE(experts && cells && tree, NVDB_E_INVALID, "null argument");
+  NVDB_REQUIRE(n_experts >= 1 && n_experts <= MOE_MAX_EXPERTS, NVDB_E_INVALID, "expert count outside [1, 4096]");
+  const bool slots = net == NVDB_NET_L0;
+  const int64_t n = slots ? 512 * tree->n_leaf : tree->n_vox;
+  NVDB_REQUIRE(n < (1ll << 29), NVDB_E_INVALID, "the blended decode takes fewer than 2^29 voxels or slots");
+  NVDB_REQUIRE(n == 0 || (slots ? mask_dev != nullptr : values_dev != nullptr), NVDB_E_INVALID, "null output");
+  MoeGrid g = check_grid(grid);
+  if (slots)
+    NVDB_REQUIRE(g.S % 8 == 0 && g.o[0] % 8 == 0 && g.o[1] % 8 == 0 && g.o[2] % 8 == 0, NVDB_E_INVALID,
+                 "the mask decode needs a cell size and grid origin that are multiples of 8");
+  std::vector<MoeBox> box((size_t)n_experts);
+  for (int k = 0; k < n_experts; ++k) {
+    NVDB_REQUIRE(experts[k] != nullptr, NVDB_E_INVALID, "null expert");
+    const Net& N = net_of(experts[k], net);
+    NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "expert network parameters or encoding not set");
+    for (int d = 0; d < 3; ++d) box[k].lo[d] = experts[k]->d.domain_lo[d];
+    box[k].inv_d = 1.f / (float)experts[k]->d.domain_size;
+  }
+  int64_t clo[3], chi[3];
+  for (int d = 0; d < 3; ++d) {
+    clo[d] = chi[d] = cells[d];
+    for (int k = 1; k < n_experts; ++k) {
+      clo[d] = std::min<int64_t>(clo[d], cells[3 * k + d]);
+      chi[d] = std::max<int64_t>(chi[d], cells[3 * k + d]);
+    }
+    NVDB_REQUIRE(chi[d] - clo[d] + 1 <= MOE_MAX_RANGE, NVDB_E_INVALID, "experts span more than 2^24 cells");
+    g.clo[d] = (int32_t)clo[d];
+    g.cdim[d] = (int32_t)(chi[d] - clo[d] + 1);
+  }
+  const int64_t total = cell_range_size(g);
+  NVDB_REQUIRE(total <= MOE_MAX_RANGE, NVDB_E_INVALID, "experts span more than 2^24 cells");
+  std::vector<int32_t> table((size_t)total, -1);
+  for (int k = 0; k < n_experts; ++k) {
+    const int64_t i =
+        ((cells[3 * k] - clo[0]) * (int64_t)g.cdim[1] + (cells[3 * k + 1] - clo[1])) * g.cdim[2] + (cells[3 * k + 2] - clo[2]);
+    NVDB_REQUIRE(table[(size_t)i] < 0, NVDB_E_INVALID, "two experts for one cell");
+    table[(size_t)i] = k;
+  }
+  if (n == 0) return;
+  // small arrays in one allocation: lookup table, boxes, counts (+ the
+  // uncovered voxels), bucket starts, cursors
+  const size_t E = (size_t)n_experts;
+  const size_t o_box = ((size_t)total * 4 + 255) & ~(size_t)255;
+  const size_t o_cnt = o_box + ((E * sizeof(MoeBox) + 255) & ~(size_t)255);
+  const size_t o_start = o_cnt + (((E + 1) * 4 + 255) & ~(size_t)255);
+  const size_t o_cur = o_start + ((E * 4 + 255) & ~(size_t)255);
+  MoeScratch& ws = moe_scratch();
+  std::lock_guard<std::mutex> lock(ws.mu);
+  StreamDrain drain{st};  // declared after the lock: runs before it is released
+  ws.small.ensure(o_cur + E * 4);
+  uint8_t* small = ws.small.p;
+  int32_t* tab = (int32_t*)small;
+  MoeBox* dbox = (MoeBox*)(small + o_box);
+  uint32_t* cnt = (uint32_t*)(small + o_cnt);
+  uint32_t* start = (uint32_t*)(small + o_start);
+  uint32_t* cursor = (uint32_t*)(small + o_cur);
+  NVDB_HIP(hipMemcpyAsync(tab, table.data(), (size_t)total * 4, hipMemcpyHostToDevice, st));
+  NVDB_HIP(hipMemcpyAsync(dbox, box.data(), E * sizeof(MoeBox), hipMemcpyHostToDevice, st));
+  NVDB_HIP(hipMemsetAsync(cnt, 0, (E + 1) * 4, st));
+  NVDB_HIP(hipMemsetAsync(cursor, 0, E * 4, st));
+  moe_count(*tree, slots, g, tab, n_experts, cnt, cnt + n_experts, st);
+  std::vector<uint32_t> hc(E + 1);
+  NVDB_HIP(hipMemcpyAsync(hc.data(), cnt, hc.size() * 4, hipMemcpyDeviceToHost, st));
+  NVDB_HIP(hipStreamSynchronize(st));
+  NVDB_REQUIRE(hc[E] == 0, NVDB_E_INVALID, "voxels that no expert's widened box holds");
+  std::vector<uint32_t> hs(E);
+  uint64_t pairs = 0;
+  for (size_t k = 0; k < E; ++k) {
+    hs[k] = (uint32_t)pairs;
+    pairs += hc[k];
+  }
+  // per-pair coordinates, outputs and slots, and eight slots per voxel, in one allocation
+  const size_t o_y = (12 * pairs + 255) & ~(size_t)255;
+  const size_t o_bs = o_y + ((4 * pairs + 255) & ~(size_t)255);
+  const size_t o_ys = o_bs + ((4 * pairs + 255) & ~(size_t)255);
+  ws.big.ensure(o_ys + 32 * (size_t)n);
+  uint8_t* big = ws.big.p;
+  float* bx = (float*)big;
+  float* y = (float*)(big + o_y);
+  uint32_t* bslot = (uint32_t*)(big + o_bs);
+  float* yslot = (float*)(big + o_ys);
+  NVDB_HIP(hipMemcpyAsync(start, hs.data(), E * 4, hipMemcpyHostToDevice, st));
+  moe_route(*tree, slots, g, tab, dbox, n_experts, start, cursor, bx, bslot, st);
+  for (size_t k = 0; k < E; ++k) {
+    if (hc[k] == 0) continue;
+    const Net& N = net_of(experts[k], net);
+    InferLaunch I{};
+    I.net = net_view(N);
+    base_spec(experts[k], &I.spec);
+    I.spec.src = SRC_COORDS;
+    I.spec.direct = 1;
+    I.spec.coords = bx + 3 * (size_t)hs[k];
+    I.spec.n = hc[k];
+    I.out_kind = OUT_Y;
+    I.y = y + hs[k];
+    launch_infer(N.ks, I, infer_grid(hc[k]), st);
+    query_scatter(y + hs[k], bslot + hs[k], hc[k], cnt + k, slots ? 1.f : experts[k]->d.value_scale, yslot, st);
+  }
+  moe_blend(*tree, slots, g, tab, yslot, slots ? nullptr : values_dev, slots ? mask_dev : nullptr, st);
+  NVDB_HIP(hipStreamSynchronize(st));
+}
+
+extern "C" {
+
 nvdb_status nvdb_decode_moe(const nvdb_model* const* experts, const int32_t* cells, int32_t n_experts,
                             const nvdb_subdomains* grid, const nvdb_tree* tree, float* values_dev, void* stream) {
   return guarded([&] {
-    NVDB_REQUIRE(experts && cells && tree, NVDB_E_INVALID, "null argument");
-    NVDB_REQUIRE(n_experts >= 1 && n_experts <= MOE_MAX_EXPERTS, NVDB_E_INVALID, "expert count outside [1, 4096]");
-    NVDB_REQUIRE(tree->n_vox < (1ll << 29), NVDB_E_INVALID, "the blended decode takes fewer than 2^29 voxels");
-    NVDB_REQUIRE(tree->n_vox == 0 || values_dev, NVDB_E_INVALID, "null output");
-    MoeGrid g = check_grid(grid);
-    std::vector<MoeBox> box((size_t)n_experts);
-    for (int k = 0; k < n_experts; ++k) {
-      NVDB_REQUIRE(experts[k] != nullptr, NVDB_E_INVALID, "null expert");
-      const Net& N = net_of(experts[k], NVDB_NET_REGRESSOR);
-      NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "expert regressor parameters or encoding not set");
-      for (int d = 0; d < 3; ++d) box[k].lo[d] = experts[k]->d.domain_lo[d];
-      box[k].inv_d = 1.f / (float)experts[k]->d.domain_size;
-    }
-    int64_t clo[3], chi[3];
-    for (int d = 0; d < 3; ++d) {
-      clo[d] = chi[d] = cells[d];
-      for (int k = 1; k < n_experts; ++k) {
-        clo[d] = std::min<int64_t>(clo[d], cells[3 * k + d]);
-        chi[d] = std::max<int64_t>(chi[d], cells[3 * k + d]);
-      }
-      NVDB_REQUIRE(chi[d] - clo[d] + 1 <= MOE_MAX_RANGE, NVDB_E_INVALID, "experts span more than 2^24 cells");
-      g.clo[d] = (int32_t)clo[d];
-      g.cdim[d] = (int32_t)(chi[d] - clo[d] + 1);
-    }
-    const int64_t total = cell_range_size(g);
-    NVDB_REQUIRE(total <= MOE_MAX_RANGE, NVDB_E_INVALID, "experts span more than 2^24 cells");
-    std::vector<int32_t> table((size_t)total, -1);
-    for (int k = 0; k < n_experts; ++k) {
-      const int64_t i =
-          ((cells[3 * k] - clo[0]) * (int64_t)g.cdim[1] + (cells[3 * k + 1] - clo[1])) * g.cdim[2] + (cells[3 * k + 2] - clo[2]);
-      NVDB_REQUIRE(table[(size_t)i] < 0, NVDB_E_INVALID, "two experts for one cell");
-      table[(size_t)i] = k;
-    }
-    const int64_t n = tree->n_vox;
-    if (n == 0) return;
-    hipStream_t st = (hipStream_t)stream;
-    // small arrays in one allocation: lookup table, boxes, counts (+ the
-    // uncovered voxels), bucket starts, cursors
-    const size_t E = (size_t)n_experts;
-    const size_t o_box = ((size_t)total * 4 + 255) & ~(size_t)255;
-    const size_t o_cnt = o_box + ((E * sizeof(MoeBox) + 255) & ~(size_t)255);
-    const size_t o_start = o_cnt + (((E + 1) * 4 + 255) & ~(size_t)255);
-    const size_t o_cur = o_start + ((E * 4 + 255) & ~(size_t)255);
-    MoeScratch& ws = moe_scratch();
-    std::lock_guard<std::mutex> lock(ws.mu);
-    StreamDrain drain{st};  // declared after the lock: runs before it is released
-    ws.small.ensure(o_cur + E * 4);
-    uint8_t* small = ws.small.p;
-    int32_t* tab = (int32_t*)small;
-    MoeBox* dbox = (MoeBox*)(small + o_box);
-    uint32_t* cnt = (uint32_t*)(small + o_cnt);
-    uint32_t* start = (uint32_t*)(small + o_start);
-    uint32_t* cursor = (uint32_t*)(small + o_cur);
-    NVDB_HIP(hipMemcpyAsync(tab, table.data(), (size_t)total * 4, hipMemcpyHostToDevice, st));
-    NVDB_HIP(hipMemcpyAsync(dbox, box.data(), E * sizeof(MoeBox), hipMemcpyHostToDevice, st));
-    NVDB_HIP(hipMemsetAsync(cnt, 0, (E + 1) * 4, st));
-    NVDB_HIP(hipMemsetAsync(cursor, 0, E * 4, st));
-    moe_count(*tree, g, tab, n_experts, cnt, cnt + n_experts, st);
-    std::vector<uint32_t> hc(E + 1);
-    NVDB_HIP(hipMemcpyAsync(hc.data(), cnt, hc.size() * 4, hipMemcpyDeviceToHost, st));
-    NVDB_HIP(hipStreamSynchronize(st));
-    NVDB_REQUIRE(hc[E] == 0, NVDB_E_INVALID, "voxels that no expert's widened box holds");
-    std::vector<uint32_t> hs(E);
-    uint64_t pairs = 0;
-    for (size_t k = 0; k < E; ++k) {
-      hs[k] = (uint32_t)pairs;
-      pairs += hc[k];
-    }
-    // per-pair coordinates, outputs and slots, and eight slots per voxel, in one allocation
-    const size_t o_y = (12 * pairs + 255) & ~(size_t)255;
-    const size_t o_bs = o_y + ((4 * pairs + 255) & ~(size_t)255);
-    const size_t o_ys = o_bs + ((4 * pairs + 255) & ~(size_t)255);
-    ws.big.ensure(o_ys + 32 * (size_t)n);
-    uint8_t* big = ws.big.p;
-    float* bx = (float*)big;
-    float* y = (float*)(big + o_y);
-    uint32_t* bslot = (uint32_t*)(big + o_bs);
-    float* yslot = (float*)(big + o_ys);
-    NVDB_HIP(hipMemcpyAsync(start, hs.data(), E * 4, hipMemcpyHostToDevice, st));
-    moe_route(*tree, g, tab, dbox, n_experts, start, cursor, bx, bslot, st);
-    for (size_t k = 0; k < E; ++k) {
-      if (hc[k] == 0) continue;
-      const Net& N = net_of(experts[k], NVDB_NET_REGRESSOR);
-      InferLaunch I{};
-      I.net = net_view(N);
-      base_spec(experts[k], &I.spec);
-      I.spec.src = SRC_COORDS;
-      I.spec.direct = 1;
-      I.spec.coords = bx + 3 * (size_t)hs[k];
-      I.spec.n = hc[k];
-      I.out_kind = OUT_Y;
-      I.y = y + hs[k];
-      launch_infer(N.ks, I, infer_grid(hc[k]), st);
-      query_scatter(y + hs[k], bslot + hs[k], hc[k], cnt + k, experts[k]->d.value_scale, yslot, st);
-    }
-    moe_blend(*tree, g, tab, yslot, values_dev, st);
-    NVDB_HIP(hipStreamSynchronize(st));
+    decode_moe_impl(experts, cells, n_experts, grid, tree, NVDB_NET_REGRESSOR, values_dev, nullptr,
+                    (hipStream_t)stream);
+  });
+}
+
+nvdb_status nvdb_decode_moe_mask(const nvdb_model* const* experts, const int32_t* cells, int32_t n_experts,
+                                 const nvdb_subdomains* grid, const nvdb_tree* tree, uint64_t* mask_dev,
+                                 void* stream) {
+  return guarded([&] {
+    decode_moe_impl(experts, cells, n_experts, grid, tree, NVDB_NET_L0, nullptr, mask_dev, (hipStream_t)stream);
   });
 }
 

@@ -187,14 +187,20 @@ __global__ void __launch_bounds__(256) k_moe_extract(const int4* __restrict__ le
   }
 }
 
-// Candidate cells of voxel i (none past n).
+// Item i is voxel i (key[i] = leaf << 9 | n0) or, with key null, voxel slot i
+// of the leaves (i = leaf << 9 | n0 itself).
+__device__ __forceinline__ int3 item_of(const int4* __restrict__ leaf_o, const uint32_t* __restrict__ key, int64_t i) {
+  return voxel_of(leaf_o, key ? key[i] : (uint32_t)i);
+}
+
+// Candidate cells of item i (none past n).
 __device__ __forceinline__ void voxel_cells(const int4* __restrict__ leaf_o, const uint32_t* __restrict__ key,
                                             int64_t i, int64_t n, const MoeGrid& g, int3& p, AxisCells& ax,
                                             AxisCells& ay, AxisCells& az) {
   p = make_int3(0, 0, 0);
   ax = ay = az = AxisCells{0, 0};
   if (i < n) {
-    p = voxel_of(leaf_o, key[i]);
+    p = item_of(leaf_o, key, i);
     ax = axis_cells(p.x, g.o[0], g.S, g.h);
     ay = axis_cells(p.y, g.o[1], g.S, g.h);
     az = axis_cells(p.z, g.o[2], g.S, g.h);
@@ -281,19 +287,29 @@ __global__ void __launch_bounds__(256) k_moe_route(const int4* __restrict__ leaf
   }
 }
 
-// Gate-weighted average of the expert outputs held in the voxel's slots.
+// Gate-weighted average of the expert outputs held in the item's 8 slots: a
+// value per voxel, or (mask non-null) the bit "blended logit > 0" per voxel slot,
+// packed 64 to a word by the wave that computed them.
 __global__ void __launch_bounds__(256) k_moe_blend(const int4* __restrict__ leaf_o, const uint32_t* __restrict__ key,
                                                    int64_t n, MoeGrid g, const int32_t* __restrict__ table,
-                                                   const float* __restrict__ yslot, float* __restrict__ values) {
+                                                   const float* __restrict__ yslot, float* __restrict__ values,
+                                                   uint64_t* __restrict__ mask) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int3 p = voxel_of(leaf_o, key[i]);
-  float num = 0.f, den = 0.f;
-  for_each_expert(g, table, p, [&](int j, int, float w) {
-    num += w * yslot[8 * i + j];
-    den += w;
-  });
-  values[i] = den > 0.f ? num / den : __builtin_nanf("");
+  float v = 0.f;
+  if (i < n) {
+    const int3 p = item_of(leaf_o, key, i);
+    float num = 0.f, den = 0.f;
+    for_each_expert(g, table, p, [&](int j, int, float w) {
+      num += w * yslot[8 * i + j];
+      den += w;
+    });
+    v = den > 0.f ? num / den : __builtin_nanf("");
+    if (values) values[i] = v;
+  }
+  if (mask) {
+    const uint64_t bits = __ballot(i < n && v > 0.f);
+    if ((threadIdx.x & 63u) == 0 && i < n) mask[i >> 6] = bits;
+  }
 }
 
 unsigned grid_of(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -338,24 +354,27 @@ int64_t moe_extract(const Tree& t, const int32_t lo[3], int32_t D, int32_t* ijk,
   return (int64_t)c;
 }
 
-void moe_count(const Tree& t, const MoeGrid& g, const int32_t* table, int n_exp, uint32_t* cnt, uint32_t* uncovered,
-               hipStream_t st) {
-  hipLaunchKernelGGL(k_moe_count, dim3(route_grid(t.n_vox)), dim3(256), 0, st, t.leaf_o.p, t.vox_key.p, t.n_vox, g,
-                     table, n_exp, cnt, uncovered);
+static int64_t items(const Tree& t, bool slots) { return slots ? 512 * t.n_leaf : t.n_vox; }
+static const uint32_t* item_key(const Tree& t, bool slots) { return slots ? nullptr : t.vox_key.p; }
+
+void moe_count(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table, int n_exp, uint32_t* cnt,
+               uint32_t* uncovered, hipStream_t st) {
+  hipLaunchKernelGGL(k_moe_count, dim3(route_grid(items(t, slots))), dim3(256), 0, st, t.leaf_o.p, item_key(t, slots),
+                     items(t, slots), g, table, n_exp, cnt, uncovered);
   NVDB_HIP(hipGetLastError());
 }
 
-void moe_route(const Tree& t, const MoeGrid& g, const int32_t* table, const MoeBox* box, int n_exp,
+void moe_route(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table, const MoeBox* box, int n_exp,
                const uint32_t* start, uint32_t* cursor, float* bx, uint32_t* bslot, hipStream_t st) {
-  hipLaunchKernelGGL(k_moe_route, dim3(route_grid(t.n_vox)), dim3(256), 0, st, t.leaf_o.p, t.vox_key.p, t.n_vox, g,
-                     table, box, n_exp, start, cursor, bx, bslot);
+  hipLaunchKernelGGL(k_moe_route, dim3(route_grid(items(t, slots))), dim3(256), 0, st, t.leaf_o.p, item_key(t, slots),
+                     items(t, slots), g, table, box, n_exp, start, cursor, bx, bslot);
   NVDB_HIP(hipGetLastError());
 }
 
-void moe_blend(const Tree& t, const MoeGrid& g, const int32_t* table, const float* yslot, float* values,
-               hipStream_t st) {
-  hipLaunchKernelGGL(k_moe_blend, dim3(grid_of(t.n_vox)), dim3(256), 0, st, t.leaf_o.p, t.vox_key.p, t.n_vox, g,
-                     table, yslot, values);
+void moe_blend(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table, const float* yslot, float* values,
+               uint64_t* mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_moe_blend, dim3(grid_of(items(t, slots))), dim3(256), 0, st, t.leaf_o.p, item_key(t, slots),
+                     items(t, slots), g, table, yslot, values, mask);
   NVDB_HIP(hipGetLastError());
 }
 

@@ -294,12 +294,13 @@ void moe_mark_cells(const Tree& t, const MoeGrid& g, uint8_t* flag, hipStream_t 
 // voxels of t inside [lo, lo + D)^3 into ijk [n][3], v [n] (any order); synchronises, returns the count
 int64_t moe_extract(const Tree& t, const int32_t lo[3], int32_t D, int32_t* ijk, float* v, uint32_t* count,
                     hipStream_t st);
-void moe_count(const Tree& t, const MoeGrid& g, const int32_t* table, int n_exp, uint32_t* cnt, uint32_t* uncovered,
-               hipStream_t st);
-void moe_route(const Tree& t, const MoeGrid& g, const int32_t* table, const MoeBox* box, int n_exp,
+// routing and blend over the active voxels, or (slots) over every voxel slot of the leaves
+void moe_count(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table, int n_exp, uint32_t* cnt,
+               uint32_t* uncovered, hipStream_t st);
+void moe_route(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table, const MoeBox* box, int n_exp,
                const uint32_t* start, uint32_t* cursor, float* bx, uint32_t* bslot, hipStream_t st);
-void moe_blend(const Tree& t, const MoeGrid& g, const int32_t* table, const float* yslot, float* values,
-               hipStream_t st);
+void moe_blend(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table, const float* yslot, float* values,
+               uint64_t* mask, hipStream_t st);
 void error_report(const Tree& t, const float* values, const uint64_t* pred_mask, nvdb_error_report* rep,
                   hipStream_t st);
 void error_report_l1(const Tree& t, const uint8_t* classes, nvdb_l1_report* rep, hipStream_t st);

@@ -96,6 +96,7 @@ _SIGS = {
     "nvdb_subdomain_cells": (C.c_int32, [_P, C.POINTER(Subdomains), _P, C.c_int64, C.POINTER(C.c_int64), _P]),
     "nvdb_tree_subdomain": (C.c_int32, [_P, C.POINTER(Subdomains), C.POINTER(C.c_int32), _P, C.POINTER(_P)]),
     "nvdb_decode_moe": (C.c_int32, [C.POINTER(_P), _P, C.c_int32, C.POINTER(Subdomains), _P, _P, _P]),
+    "nvdb_decode_moe_mask": (C.c_int32, [C.POINTER(_P), _P, C.c_int32, C.POINTER(Subdomains), _P, _P, _P]),
     "nvdb_tree_export": (C.c_int32, [_P, _P, _P, _P, _P, _P, _P]),
     "nvdb_tree_free": (None, [_P]),
     "nvdb_model_create": (C.c_int32, [C.POINTER(ModelDesc), C.POINTER(_P)]),
@@ -469,6 +470,19 @@ def fit_experts(models, trees, steps, batch, nets_mask, seed=0, lr=1e-3, lr_deca
     _check(_lib.nvdb_fit_experts(hm, ht, len(models), C.byref(f),
                                  losses.ctypes.data_as(C.c_void_p) if return_losses else None, _stream()))
     return losses[:, :, :steps] if return_losses else None
+
+
+def decode_moe_mask(experts, cells, origin, size, halo, tree):
+    """Blended level-0 masks (int64 [n_leaves, 8] bit words, device) of the experts' classifiers."""
+    import torch
+    cells = np.ascontiguousarray(np.asarray(cells, np.int32).reshape(-1, 3))
+    assert len(cells) == len(experts)
+    hs = (_P * len(experts))(*[e.h for e in experts])
+    g = Subdomains(_i3(origin), int(size), int(halo))
+    mk = torch.empty((tree.info().n_leaves, 8), dtype=torch.int64, device="cuda")
+    _check(_lib.nvdb_decode_moe_mask(hs, cells.ctypes.data_as(C.c_void_p), len(experts), C.byref(g), tree.h,
+                                     _ptr(mk), _stream()))
+    return mk
 
 
 def errors_topology(truth, pred):

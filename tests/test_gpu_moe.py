@@ -57,7 +57,9 @@ def test_tree_subdomain_matches_oracle(gpu_lib, scene, origin, size, halo):
         assert np.array_equal(ex["values"], so["values"].astype(np.float32))
 
 
-def _experts(gpu_lib, cells, origin, size, halo, shape, prec):
+def _experts(gpu_lib, cells, origin, size, halo, shape, prec, net=0):
+    """One random-parameter expert per cell (network `net`: 0 regressor, value
+    scale 3; 1 level-0 classifier, logits) and the oracle's description of it."""
     W, H, m = shape
     K = 2 * m
     shapes = mlp.layer_shapes(K, W, H, 1)
@@ -65,13 +67,15 @@ def _experts(gpu_lib, cells, origin, size, halo, shape, prec):
     for k, c in enumerate(cells):
         lo, D = gpu_lib.subdomain_box(origin, size, halo, c)
         theta = workloads.init_params(K, W, H, 1, seed=100 + k)
+        if net == 1:  # logits of order 1, not 1e-2, so that most mask bits are decisive
+            theta[-(W + 1):] *= 20.0
         B = workloads.pe_matrix(6) if m == 18 else workloads.ffm_matrix(m, 10.0, seed=200 + k)
-        mdl = gpu_lib.Model({0: (W, H, m, 1)}, precision=prec, domain_lo=lo, domain_size=D, value_scale=3.0)
-        mdl.set_params(0, theta)
-        mdl.set_encoding(0, B)
+        mdl = gpu_lib.Model({net: (W, H, m, 1)}, precision=prec, domain_lo=lo, domain_size=D, value_scale=3.0)
+        mdl.set_params(net, theta)
+        mdl.set_encoding(net, B)
         models.append(mdl)
         oracle_experts.append(dict(cell=c, theta=theta.astype(np.float64), shapes=shapes, B=B.astype(np.float64),
-                                   lo=lo, D=D, scale=3.0))
+                                   lo=lo, D=D, scale=3.0 if net == 0 else 1.0))
     return models, oracle_experts
 
 
@@ -205,4 +209,33 @@ def test_fit_experts_equals_sequential_fits(gpu_lib, scene, prec):
         assert np.array_equal(ma.get_params(0).view(np.uint32), mb.get_params(0).view(np.uint32))
     with pytest.raises(gpu_lib.NvdbError) as e:
         gpu_lib.fit_experts([b[0], b[0]], trees[:2], steps=1, batch=4096, nets_mask=1)
+    assert e.value.code == gpu_lib.E_INVALID
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_decode_moe_mask_matches_oracle(gpu_lib, scene, prec):
+    """Blended level-0 masks: every voxel slot of every leaf, bit = blended logit
+    > 0, against the oracle's blend at the slot centres (slots whose logit lies
+    within the forward tolerance of 0 may go either way)."""
+    tr, ot = scene
+    origin, size, halo = (0, 0, 0), 64, 8
+    p = gpu_lib.FP32 if prec == "fp32" else gpu_lib.BF16
+    cells = gpu_lib.subdomain_cells(tr, origin, size, halo)
+    models, ex = _experts(gpu_lib, cells, origin, size, halo, (64, 3, 18), p, net=1)
+    mk = gpu_lib.decode_moe_mask(models, cells, origin, size, halo, tr).cpu().numpy().view(np.uint64)
+    L = len(ot["leaf_origin"])
+    slots = (ot["leaf_origin"][:, None, :].astype(np.int64) + T.n0_to_offset(np.arange(512))[None]).reshape(-1, 3)
+    lg = moe.decode_moe(slots, ex, origin, size, halo).reshape(L, 512)
+    bits = np.unpackbits(mk.view(np.uint8), bitorder="little").reshape(L, 512).astype(bool)
+    near = np.abs(lg) <= (1e-4 if p == gpu_lib.FP32 else 2e-2)
+    assert near.mean() < 0.1
+    assert not np.any((bits != (lg > 0)) & ~near)
+    # a grid whose cells can cut a leaf is refused
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        gpu_lib.decode_moe_mask(models, cells, (4, 0, 0), size, halo, tr)
+    assert e.value.code == gpu_lib.E_INVALID
+    # experts without a level-0 classifier
+    reg, _ = _experts(gpu_lib, cells, origin, size, halo, (64, 3, 18), p, net=0)
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        gpu_lib.decode_moe_mask(reg, cells, origin, size, halo, tr)
     assert e.value.code == gpu_lib.E_INVALID
