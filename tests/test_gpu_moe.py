@@ -239,3 +239,29 @@ def test_decode_moe_mask_matches_oracle(gpu_lib, scene, prec):
     with pytest.raises(gpu_lib.NvdbError) as e:
         gpu_lib.decode_moe_mask(reg, cells, origin, size, halo, tr)
     assert e.value.code == gpu_lib.E_INVALID
+
+
+def test_moe_empty_and_single_voxel(gpu_lib):
+    """Edge cases: a tree with no active voxel (no cells, empty subdomain, empty
+    decode) and a single voxel at negative coordinates near a cell corner of an
+    offset grid (its one expert, blended with itself)."""
+    empty = gpu_lib.Tree(torch.full((9, 10, 11), 50.0, device=DEV), (0, 0, 0), gpu_lib.SDF, 3.0)
+    origin, size, halo = (0, 0, 0), 16, 8
+    assert gpu_lib.subdomain_cells(empty, origin, size, halo).shape == (0, 3)
+    assert empty.subdomain(origin, size, halo, (0, 0, 0)).info().n_voxels == 0
+    models, _ = _experts(gpu_lib, np.zeros((1, 3), np.int32), origin, size, halo, (64, 3, 18), gpu_lib.FP32)
+    assert gpu_lib.decode_moe(models, [[0, 0, 0]], origin, size, halo, empty).numel() == 0
+
+    grid = torch.where(torch.arange(5 * 6 * 7).reshape(5, 6, 7) == 101, 0.0, 9.0)
+    one = gpu_lib.Tree(grid.to(DEV), (-1, -1, -1), gpu_lib.SDF, 1.0)
+    ijk, vals = T.active_set_dense(grid.numpy(), (-1, -1, -1), T.SDF, 1.0)
+    assert len(ijk) == 1
+    origin, size, halo = (-9, 0, 3), 16, 8
+    cells = gpu_lib.subdomain_cells(one, origin, size, halo)
+    assert np.array_equal(cells, moe.kept_cells(ijk, origin, size).astype(np.int32))
+    sub = one.subdomain(origin, size, halo, cells[0])
+    assert sub.info().n_voxels == 1
+    models, ex = _experts(gpu_lib, cells, origin, size, halo, (64, 3, 18), gpu_lib.FP32)
+    got = gpu_lib.decode_moe(models, cells, origin, size, halo, one).cpu().numpy().astype(np.float64)
+    want = moe.decode_moe(ijk, ex, origin, size, halo)
+    assert np.all(np.abs(got - want) <= 3e-5 * (1 + np.abs(want)))
