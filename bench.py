@@ -475,11 +475,11 @@ def cloud_leg(fit_steps, tuned_g):
 
 def moe_leg(tree, single, rep_single, fit_steps, tuned_g, size=256, halo=8, reps=3):
     """Sparse domain decomposition (Sec. 3.4, eq. moe) of the 512^3 volume into
-    256^3 subdomains with an 8-voxel halo: one BF16 regressor per kept cell,
-    each fitted for fit_steps steps on the voxels of its widened box, then the
-    gate-weighted blended decode of every active voxel, timed against the single
-    network's regressor decode of the same tree (median of `reps` after one
-    warm-up)."""
+    256^3 subdomains with an 8-voxel halo: one BF16 regressor and one level-0
+    classifier per kept cell, each fitted for fit_steps steps on its widened box,
+    then the gate-weighted blended decode of every active voxel (timed against
+    the single network's regressor decode of the same tree, median of `reps`
+    after one warm-up) and the blended level-0 masks."""
     import numpy as np
     import torch
 
@@ -490,7 +490,9 @@ def moe_leg(tree, single, rep_single, fit_steps, tuned_g, size=256, halo=8, reps
     cells = nvdb.subdomain_cells(tree, origin, size, halo)
     K = 2 * M
     B0 = workloads.ffm_matrix(M, 10.0, seed=11)
+    B1 = workloads.ffm_matrix(M, 10.0, seed=12)
     th0 = workloads.init_params(K, W, H, C, seed=21)
+    th1 = workloads.init_params(K, W, H, C, seed=22)
     experts, subs, n_sub = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -499,16 +501,19 @@ def moe_leg(tree, single, rep_single, fit_steps, tuned_g, size=256, halo=8, reps
         subs.append(sub)
         n_sub.append(sub.info().n_voxels)
         lo, D = nvdb.subdomain_box(origin, size, halo, c)
-        mdl = nvdb.Model({0: (W, H, M, C)}, precision=nvdb.BF16, domain_lo=lo, domain_size=D, value_scale=BAND)
+        mdl = nvdb.Model({0: (W, H, M, C), 1: (W, H, M, C)}, precision=nvdb.BF16, domain_lo=lo, domain_size=D,
+                         value_scale=BAND)
         mdl.set_encoding(0, B0)
         mdl.set_params(0, th0)
+        mdl.set_encoding(1, B1)
+        mdl.set_params(1, th1)
         if tuned_g:
             mdl.set_train_groups(tuned_g)
         experts.append(mdl)
     torch.cuda.synchronize()
     t_split = time.perf_counter() - t0
     t0 = time.perf_counter()
-    nvdb.fit_experts(experts, subs, steps=fit_steps, batch=BATCH, nets_mask=1, seed=0, lr=1e-3, lr_decay=0.975,
+    nvdb.fit_experts(experts, subs, steps=fit_steps, batch=BATCH, nets_mask=3, seed=0, lr=1e-3, lr_decay=0.975,
                      lr_interval=100)
     torch.cuda.synchronize()
     t_fit = time.perf_counter() - t0
@@ -525,7 +530,8 @@ def moe_leg(tree, single, rep_single, fit_steps, tuned_g, size=256, halo=8, reps
         return float(np.median(ts))
 
     values = nvdb.decode_moe(experts, cells, origin, size, halo, tree)
-    r = nvdb.errors(tree, values)
+    masks = nvdb.decode_moe_mask(experts, cells, origin, size, halo, tree)
+    r = nvdb.errors(tree, values, masks)
     n = tree.info().n_voxels
     t_moe = timed(lambda: nvdb.decode_moe(experts, cells, origin, size, halo, tree))
     t_one = timed(lambda: single.decode(tree, masks=False))
@@ -535,16 +541,18 @@ def moe_leg(tree, single, rep_single, fit_steps, tuned_g, size=256, halo=8, reps
     return {"subdomain_size": size, "halo": halo, "experts": len(cells), "voxels": n,
             "routed_pairs_per_voxel": float(sum(n_sub)) / n,
             "split_s": t_split, "fit_s": t_fit, "steps_per_expert": fit_steps,
-            "train_samples_per_s": len(cells) * fit_steps * BATCH / t_fit,
+            "train_samples_per_s": 2 * len(cells) * fit_steps * BATCH / t_fit,
             "blend_decode_ms": t_moe * 1e3, "blend_voxels_per_s": n / t_moe,
             "blend_tflops_whole_call": pairs * flops_fwd(2 * M, W, H, C) / t_moe / 1e12,
             "single_decode_ms": t_one * 1e3, "single_voxels_per_s": n / t_one,
             "max_abs_err_voxels": r["max_abs"], "rms_err_voxels": r["rms"], "iou": r["iou"],
+            "l0_fp": r["fp"], "l0_fn": r["fn"],
             "single_network": {"max_abs_err_voxels": rep_single["max_abs"], "rms_err_voxels": rep_single["rms"],
-                               "iou": rep_single["iou"]},
-            "note": "one regressor per kept 256^3 cell, each fitted for the single network's step count on its "
-                    "widened box, the experts two at a time (nvdb_fit_experts); split = subdomain trees + models; "
-                    "blended decode = routing + one forward launch per expert + blend, wall clock"}, ctx
+                               "iou": rep_single["iou"], "l0_fp": rep_single["fp"], "l0_fn": rep_single["fn"]},
+            "note": "one regressor and one level-0 classifier per kept 256^3 cell, each fitted for the single "
+                    "network's step count on its widened box (nvdb_fit_experts); split = subdomain trees + models; "
+                    "blended decode = routing + one forward launch per expert + blend (values), wall clock; "
+                    "l0_fp / l0_fn from the blended level-0 masks"}, ctx
 
 
 def random_access_leg(model, tree, n=1 << 20, batch=1 << 16, reps=5):
