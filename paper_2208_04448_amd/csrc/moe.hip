@@ -215,7 +215,8 @@ __global__ void __launch_bounds__(256) k_moe_count(const int4* __restrict__ leaf
                                                    int64_t n, MoeGrid g, const int32_t* __restrict__ table,
                                                    int n_exp, uint32_t* __restrict__ cnt,
                                                    uint32_t* __restrict__ uncovered) {
-  __shared__ uint32_t hist[MOE_MAX_EXPERTS];
+  extern __shared__ uint32_t lds[];  // n_exp counters, sized at launch
+  uint32_t* hist = lds;
   __shared__ uint32_t unc;
   for (int k = threadIdx.x; k < n_exp; k += blockDim.x) hist[k] = 0u;
   if (threadIdx.x == 0) unc = 0u;
@@ -251,9 +252,10 @@ __global__ void __launch_bounds__(256) k_moe_route(const int4* __restrict__ leaf
                                                    const MoeBox* __restrict__ box, int n_exp,
                                                    const uint32_t* __restrict__ start, uint32_t* __restrict__ cursor,
                                                    float* __restrict__ bx, uint32_t* __restrict__ bslot) {
-  __shared__ uint32_t hist[MOE_MAX_EXPERTS];
-  __shared__ uint32_t base[MOE_MAX_EXPERTS];
-  __shared__ uint32_t fill[MOE_MAX_EXPERTS];
+  extern __shared__ uint32_t lds[];  // 3 n_exp words, sized at launch
+  uint32_t* hist = lds;
+  uint32_t* base = lds + n_exp;
+  uint32_t* fill = lds + 2 * n_exp;
   for (int k = threadIdx.x; k < n_exp; k += blockDim.x) hist[k] = fill[k] = 0u;
   __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * 256;
@@ -359,14 +361,16 @@ static const uint32_t* item_key(const Tree& t, bool slots) { return slots ? null
 
 void moe_count(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table, int n_exp, uint32_t* cnt,
                uint32_t* uncovered, hipStream_t st) {
-  hipLaunchKernelGGL(k_moe_count, dim3(route_grid(items(t, slots))), dim3(256), 0, st, t.leaf_o.p, item_key(t, slots),
+  hipLaunchKernelGGL(k_moe_count, dim3(route_grid(items(t, slots))), dim3(256), (size_t)n_exp * 4, st, t.leaf_o.p,
+                     item_key(t, slots),
                      items(t, slots), g, table, n_exp, cnt, uncovered);
   NVDB_HIP(hipGetLastError());
 }
 
 void moe_route(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table, const MoeBox* box, int n_exp,
                const uint32_t* start, uint32_t* cursor, float* bx, uint32_t* bslot, hipStream_t st) {
-  hipLaunchKernelGGL(k_moe_route, dim3(route_grid(items(t, slots))), dim3(256), 0, st, t.leaf_o.p, item_key(t, slots),
+  hipLaunchKernelGGL(k_moe_route, dim3(route_grid(items(t, slots))), dim3(256), (size_t)n_exp * 12, st, t.leaf_o.p,
+                     item_key(t, slots),
                      items(t, slots), g, table, box, n_exp, start, cursor, bx, bslot);
   NVDB_HIP(hipGetLastError());
 }
