@@ -298,7 +298,7 @@ nvdb_status nvdb_decode_l1(const nvdb_model* model, const nvdb_tree* tree, uint8
  * FP32.  Conversions round to nearest even after clamping to +-448.  The e4m3
  * weights are rebuilt from the FP32 master parameters on every call (the
  * paper stores 16-bit networks, Sec. 4, and leaves lower-precision inference to
- * future work, Sec. 7; this form is that direction).  Asynchronous;
+ * future work, Sec. 5; this form is that direction).  Asynchronous;
  * E_UNSUPPORTED when the network shape has no FP8 kernel. */
 nvdb_status nvdb_decode_fp8(const nvdb_model* model, const nvdb_tree* tree, float* values_dev, uint64_t* pred_mask_dev,
                             void* stream);

@@ -202,33 +202,47 @@ def topology_from_decisions(tr, classes, active_fn, value_fn):
     return dict(leaf_origin=leaf_o, ijk=ijk, values=values)
 
 
+def topology_from_values(tr, classes, kind, thr, value_fn, active_fn=None):
+    """Decided topology of the lower levels (Sec. 3.3, 3.5) from per-voxel functions.
+
+    classes: level-1 class of every leaf slot of tr's level-1 nodes (0 = leaf).
+    Inside every predicted leaf a voxel slot p is active where active_fn(p) holds
+    (the level-0 classifier's decision); without one, where the value the
+    regressor gives it passes the volume's own active rule: |v| <= band for a
+    level set (closed interval, Sec. 3.2.1), v > threshold for fog.  value_fn(p)
+    gives the values in value units.  Returns leaf origins, voxel coordinates and
+    values in canonical order."""
+    if active_fn is not None:
+        def values(p, act):
+            return value_fn(p[act])
+        return topology_from_decisions(tr, classes, active_fn, values)
+    cache = {}
+
+    def active(p):
+        v = np.asarray(value_fn(p), np.float64)
+        cache["v"] = v
+        return np.abs(v) <= thr if kind == T.SDF else v > thr
+
+    def values(p, act):
+        return cache["v"][act]
+    return topology_from_decisions(tr, classes, active, values)
+
+
 def decode_topology(tr, lo, D, kind, thr, value_scale, l1, reg, l0=None, fp8=False):
     """Full decode with the networks: level-1 classes at every leaf slot, then the
     level-0 classifier (logit > 0) or, without one, the regressor's value tested
-    with the volume's active rule (SDF |v| <= band, fog v > threshold), then the
-    regressor's values.  l1, reg, l0: (theta, shapes, B)."""
+    with the volume's active rule (topology_from_values), then the regressor's
+    values.  l1, reg, l0: (theta, shapes, B)."""
     cls = l1_classes(decode_l1(*l1, tr, lo, D, fp8=fp8))
 
     def reg_values(p):
         return _batched_predict(*reg, mlp.normalize_voxel(p, lo, D), fp8=fp8)[:, 0] * value_scale
 
+    active = None
     if l0 is not None:
         def active(p):
             return _batched_predict(*l0, mlp.normalize_voxel(p, lo, D), fp8=fp8)[:, 0] > 0
-
-        def values(p, act):
-            return reg_values(p[act])
-    else:
-        cache = {}
-
-        def active(p):
-            v = reg_values(p)
-            cache["v"] = v
-            return np.abs(v) <= thr if kind == T.SDF else v > thr
-
-        def values(p, act):
-            return cache["v"][act]
-    return topology_from_decisions(tr, cls, active, values)
+    return topology_from_values(tr, cls, kind, thr, reg_values, active)
 
 
 def _voxel_keys(ijk):

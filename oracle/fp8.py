@@ -4,7 +4,7 @@ Test infrastructure: only the tests, the smoke check and the CPU baseline of
 the benchmark use this package.
 
 The paper stores networks in 16 bits and names mixed-precision inference as
-future work (Sec. 7); the FP8 form is this implementation's reading of that
+future work (Sec. 5, Discussion); the FP8 form is this implementation's reading of that
 direction for decoding.  Its definition:
   * a value is rounded to e4m3 (1 sign, 4 exponent bits with bias 7, 3 mantissa
     bits, subnormals, largest finite 448, no infinities) to nearest, ties to an

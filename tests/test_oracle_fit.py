@@ -262,3 +262,83 @@ def test_topology_patches_restore_the_active_set():
     assert (ps - set(map(tuple, fp.tolist()))) | set(map(tuple, fn.tolist())) == ts
     e, f = F.topology_patches(truth, truth)
     assert len(e) == 0 and len(f) == 0
+
+
+# ---------------------------------------------------------------- IoU and the decided topology (Sec. 4, 3.3, 3.5)
+def test_iou_planted_case():
+    """IoU of the interiors {v <= 0} (Sec. 4) on six hand-counted voxels, zeros
+    included: truth interior {0, 1, 4, 5}, decoded interior {0, 2, 3, 4, 5};
+    intersection {0, 4, 5} = 3, union = all six, IoU = 1/2.  The readings v < 0
+    (2/3) or intersection over the true interior (3/4) give other values."""
+    ijk = np.array([[0, 0, 0], [0, 0, 1], [0, 1, 0], [1, 0, 0], [9, 0, 0], [0, 9, 9]], np.int32)
+    truth = np.array([-1.0, 0.0, 0.5, 2.0, -0.2, 0.0])
+    tr = T.build(ijk, truth)
+    order = {tuple(p): i for i, p in enumerate(ijk.tolist())}
+    perm = np.array([order[tuple(p)] for p in tr["ijk"].tolist()])  # canonical voxel order -> planted index
+    decoded = np.array([-0.5, 0.1, -0.1, 0.0, -1.0, 0.0])[perm]
+    rep = F.errors(tr, decoded, T.SDF)
+    assert rep["iou"] == 0.5
+    # a decode that keeps every interior voxel and adds none is exact
+    assert F.errors(tr, truth[perm], T.SDF)["iou"] == 1.0
+    # fog volumes carry no IoU (RMSE is their measure)
+    assert "iou" not in F.errors(tr, decoded, T.FOG)
+
+
+def _true_classes(tr):
+    n = 4096 * len(tr["l1_origin"])
+    slots = np.arange(n)
+    child = T.mask_bits(tr["l1_child"], slots >> 12, slots & 4095)
+    return np.where(child == 1, 0, 2)
+
+
+def test_topology_active_rule_rebuilds_truth_sdf():
+    """With the true level-1 classes and a regressor that returns the exact level
+    set, the active rule |v| <= band rebuilds the true active set and values.
+    The sphere has lattice voxels at |v| = 3 exactly (distance 27 or 21 from the
+    centre), so a strict band would drop them."""
+    grid = workloads.sphere_sdf().numpy().astype(np.float64)
+    ijk, vals = T.active_set_dense(grid, (0, 0, 0), T.SDF, 3.0)
+    tr = T.build(ijk, vals)
+    assert np.sum(np.abs(tr["values"]) == 3.0) > 0
+
+    def sdf(p):
+        return np.linalg.norm(np.asarray(p, np.float64) - 32.0, axis=1) - 24.0
+
+    out = F.topology_from_values(tr, _true_classes(tr), T.SDF, 3.0, sdf)
+    assert np.array_equal(out["ijk"], tr["ijk"])
+    assert np.allclose(out["values"], tr["values"], rtol=0, atol=4e-6)  # the grid holds float32 values
+    assert np.array_equal(out["leaf_origin"], tr["leaf_origin"])
+    # a level-0 decision that returns the true mask gives the same tree
+    act = {tuple(p) for p in tr["ijk"].tolist()}
+    out0 = F.topology_from_values(tr, _true_classes(tr), T.SDF, 3.0, sdf,
+                                  active_fn=lambda p: np.array([tuple(q) in act for q in p.tolist()]))
+    assert np.array_equal(out0["ijk"], tr["ijk"]) and np.allclose(out0["values"], tr["values"], rtol=0, atol=4e-6)
+
+
+def test_topology_active_rule_rebuilds_truth_fog():
+    """Fog keeps v > threshold (strict): planted voxels at exactly the threshold
+    stay inactive, and a regressor returning the grid rebuilds the true set."""
+    rng = np.random.default_rng(3)
+    grid = rng.random((24, 20, 16))
+    grid[grid < 0.6] = 0.0
+    grid[3, 4, 5] = grid[10, 11, 12] = grid[20, 1, 2] = 0.5      # exactly the threshold
+    origin = (-8, 0, 16)
+    ijk, vals = T.active_set_dense(grid, origin, T.FOG, 0.5)
+    tr = T.build(ijk, vals)
+
+    def lookup(p):
+        q = np.asarray(p, np.int64) - np.asarray(origin)
+        inside = np.all((q >= 0) & (q < np.array(grid.shape)), axis=1)
+        v = np.zeros(len(q))
+        v[inside] = grid[q[inside, 0], q[inside, 1], q[inside, 2]]
+        return v
+
+    out = F.topology_from_values(tr, _true_classes(tr), T.FOG, 0.5, lookup)
+    assert np.array_equal(out["ijk"], tr["ijk"]) and np.array_equal(out["values"], tr["values"])
+    assert not any(tuple(p) in {(-5, 4, 21), (2, 11, 28), (12, 1, 18)} for p in out["ijk"].tolist())
+    # a level-1 class that drops a leaf drops exactly that leaf's voxels
+    cls = _true_classes(tr)
+    first_leaf = np.nonzero(cls == 0)[0][0]
+    cls[first_leaf] = 2
+    out2 = F.topology_from_values(tr, cls, T.FOG, 0.5, lookup)
+    assert len(out2["ijk"]) == len(tr["ijk"]) - int(np.sum(tr["vox_leaf"] == 0))
