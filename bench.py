@@ -275,9 +275,13 @@ def main():
     if not args.skip_moe:
         print("sparse-domain-decomposition leg ...", file=sys.stderr, flush=True)
         out["moe"], moe_ctx = moe_leg(tree, bf, rep, args.fit_steps, tuned_g)
+    c4_grads = None
+    if not args.skip_small:
+        print("small-network leg ...", file=sys.stderr, flush=True)
+        out["small"], c4_grads = small_leg()
     if not args.skip_cpu:
         print("cpu baseline (FP64 oracle) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(grid, moe_ctx)
+        out["cpu_baseline"] = cpu_baseline(grid, moe_ctx, c4_grads)
     del grid, bf
     torch.cuda.empty_cache()
     if not args.skip_sequence:
@@ -288,9 +292,6 @@ def main():
         print("cloud leg ...", file=sys.stderr, flush=True)
         out["cloud"] = cloud_leg(args.fit_steps, tuned_g)
         torch.cuda.empty_cache()
-    if not args.skip_small:
-        print("small-network leg ...", file=sys.stderr, flush=True)
-        out["small"] = small_leg()
 
     print(json.dumps(out), flush=True)
 
@@ -581,7 +582,7 @@ def random_access_leg(model, tree, n=1 << 20, batch=1 << 16, reps=5):
     _, hits = model.query(tree, q, background=BAND, batch=batch, return_hits=True)
     t_q = timed(lambda: model.query(tree, q, background=BAND, batch=batch))
     t_q1 = timed(lambda: model.query(tree, q, background=BAND, batch=0))
-    t_nn = timed(lambda: model.forward(0, x))
+    t_nn = timed(lambda: model.forward_coords(0, x))
     return {"queries": n, "batch": batch, "hit_fraction": float(hits.float().mean().item()),
             "query_ms": t_q * 1e3, "queries_per_s": n / t_q, "query_ms_one_pass": t_q1 * 1e3,
             "pure_network_ms": t_nn * 1e3,
@@ -610,6 +611,7 @@ def small_leg(reps=5):
     zeros = np.zeros(len(th0[0]), np.float32)
     res = {"workload": "64^3 sphere SDF (r 24, band +-3, 43,878 voxels, 257 leaves); regressor + level-0 "
                        "classifier 3x64, PE-6 (K 36)"}
+    c4_grads = {}
     for name, prec in (("fp32", nvdb.FP32), ("bf16", nvdb.BF16)):
         model = nvdb.Model({0: (64, 3, 18, 1), 1: (64, 3, 18, 1)}, precision=prec, domain_size=64, value_scale=BAND)
         for k in (0, 1):
@@ -632,24 +634,20 @@ def small_leg(reps=5):
             rep = one_epoch()
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t)
-        # C4: batch 2^22 i.i.d. voxel samples, MSE against the targets
+        # C4: batch 2^22 i.i.d. voxel samples, MSE against the targets; the kernels gather
+        # and normalise the samples from their population indices
         n = 1 << 22
         tree = nvdb.Tree(grid, (0, 0, 0), nvdb.SDF, BAND)
-        ii = nvdb.sample_indices(0, 0, 0, 43878, n).long()
-        ex = tree.export()
-        offs = np.repeat(np.arange(len(ex["leaf_origin"])), np.diff(ex["leaf_off"].astype(np.int64)))
-        mask_bits = np.unpackbits(ex["leaf_mask"].view(np.uint8), bitorder="little").reshape(-1, 512)
-        n0 = np.concatenate([np.nonzero(r)[0] for r in mask_bits])
-        p = ex["leaf_origin"][offs] + np.stack([(n0 >> 6) & 7, (n0 >> 3) & 7, n0 & 7], 1)
-        xs = torch.from_numpy(((p + 0.5) / 64.0).astype(np.float32)).cuda()[ii].contiguous()
-        ts_ = torch.from_numpy(ex["values"] / BAND).cuda()[ii].contiguous()
-        model.set_params(0, th0[0])
+        ii = nvdb.sample_indices(0, 0, 0, 43878, n)
+        vals = torch.from_numpy(tree.export()["values"] / BAND).cuda()
+        ts_ = vals[ii.long()].contiguous()
+        model.reserve_dev(0, n)
         Fn = nvdb.mlp_function()
-        theta = torch.zeros(len(th0[0]), device="cuda", requires_grad=True)
+        theta = torch.from_numpy(th0[0]).cuda().requires_grad_(True)
 
         def fwd_bwd():
             theta.grad = None
-            y = Fn.apply(model, 0, xs, theta)
+            y = Fn.apply(model, 0, tree, ii, theta)
             ((y[:, 0] - ts_) ** 2).mean().backward()
 
         fwd_bwd()
@@ -660,22 +658,106 @@ def small_leg(reps=5):
             fwd_bwd()
             torch.cuda.synchronize()
             tb.append(time.perf_counter() - t)
+        # gradient of the same loss over the batch's first 2^16 samples, for the check
+        # against the oracle in the cpu_baseline leg
+        nc = 1 << 16
+        theta.grad = None
+        y = Fn.apply(model, 0, tree, ii[:nc].contiguous(), theta)
+        ((y[:, 0] - ts_[:nc]) ** 2).mean().backward()
+        c4_grads[name] = theta.grad.detach().cpu().numpy().astype(np.float64)
         med = float(np.median(tb))
         res[name] = {"one_epoch_job_ms": float(np.median(ts)) * 1e3, "max_abs_err_voxels": rep["max_abs"],
                      "rms_err_voxels": rep["rms"], "iou": rep["iou"],
                      "batch_2_22_fwd_bwd_ms": med * 1e3, "batch_2_22_samples_per_s": n / med,
                      "batch_2_22_tflops": n * flops_fwd_bwd(36, 64, 3, 1) / med / 1e12}
         del model
-    return res
+    return res, c4_grads
 
 
-def cpu_baseline(grid, moe_ctx=None):
-    """The FP64 oracle on the host: 3 Adam steps of the regressor at 2^14 samples
-    on the same volume, after building the oracle's own tree from the grid; with
-    the experts of the decomposition leg, the oracle's blended decode of 2^14
-    sampled voxels."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def c4_gradient_check(c4_grads):
+    """The C4 gradient check against the FP64 oracle: the GPU gradients of the MSE
+    over the first 2^16 samples of the C4 batch (i.i.d. voxel samples of the 64^3
+    sphere, 3x64 PE-6 regressor) against the oracle's analytic gradient, per tensor
+    and on 256 weights drawn with seed 0; and the oracle's analytic gradient against
+    central finite differences (h = 1e-3, FP64) of the loss over the first 2^10
+    samples on the same 256 weights.  A weight whose +-h perturbation moves any
+    hidden pre-activation across zero (a ReLU kink, where the difference quotient
+    is not the derivative) is reported apart.  The full 2^22 batch is compared in
+    the parity tests."""
     import numpy as np
-    from threadpoolctl import threadpool_info
+
+    import workloads
+    from oracle import fit as F, mlp, sampler as S, tree as T
+
+    t0 = time.perf_counter()
+    v = workloads.sphere_sdf().numpy()
+    ot = T.build(*T.active_set_dense(v, (0, 0, 0), T.SDF, BAND))
+    shapes = mlp.layer_shapes(36, 64, 3, 1)
+    B = workloads.pe_matrix(6).astype(np.float64)
+    th = workloads.init_params(36, 64, 3, 1, seed=0).astype(np.float64)
+    params = mlp.unflatten(th, shapes)
+    n = 1 << 16
+    idx = S.iid_indices(0, 0, 0, 1 << 22, len(ot["values"]))[:n]
+    x, t = F.net_inputs(ot, "regressor", idx, (0, 0, 0), 64, T.SDF, BAND)
+    yo, cache = mlp.forward(params, mlp.encode(x, B))
+    go = mlp.flatten(mlp.backward(params, cache, 2.0 * (yo[:, 0] - t)[:, None] / n))
+    pick = np.random.default_rng(0).choice(len(th), 256, replace=False)
+    out = {"samples": n, "weights_sampled": 256}
+    for name, g in c4_grads.items():
+        rel = np.abs(g[pick] - go[pick]) / np.maximum(np.abs(go[pick]), 1e-12)
+        a, te = 0, []
+        for o, i_ in shapes:
+            for m_ in (o * i_, o):
+                te.append(float(np.max(np.abs(g[a:a + m_] - go[a:a + m_])) / max(np.max(np.abs(go[a:a + m_])), 1e-30)))
+                a += m_
+        out["gpu_%s_vs_oracle" % name] = {"sampled_max_rel": float(np.max(rel)),
+                                           "sampled_median_rel": float(np.median(rel)),
+                                           "max_tensor_elementwise": max(te)}
+    nf, h = 1 << 10, 1e-3
+    z0 = mlp.encode(x[:nf], B)
+    ts = t[:nf]
+
+    def run(theta):
+        y, c = mlp.forward(mlp.unflatten(theta, shapes), z0)
+        return float(np.mean((y[:, 0] - ts) ** 2)), [c[i] > 0 for i in range(1, len(c), 2)]
+    l0, pat0 = run(th)
+    yo, cache = mlp.forward(params, z0)
+    ga = mlp.flatten(mlp.backward(params, cache, 2.0 * (yo[:, 0] - ts)[:, None] / nf))
+    rel, kink = np.empty(len(pick)), np.zeros(len(pick), bool)
+    for q, k in enumerate(pick):
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h
+        tm[k] -= h
+        (lp, pp), (lm, pm) = run(tp), run(tm)
+        kink[q] = any(np.any(a != b) or np.any(a != c) for a, b, c in zip(pat0, pp, pm))
+        rel[q] = abs((lp - lm) / (2 * h) - ga[k]) / max(abs(ga[k]), 1e-12)
+    out["oracle_vs_fd"] = {"samples": nf, "h": h, "smooth_weights": int(np.sum(~kink)),
+                           "smooth_max_rel": float(np.max(rel[~kink])) if np.any(~kink) else None,
+                           "smooth_median_rel": float(np.median(rel[~kink])) if np.any(~kink) else None,
+                           "kink_weights": int(np.sum(kink)),
+                           "kink_max_rel": float(np.max(rel[kink])) if np.any(kink) else None}
+    out["seconds"] = time.perf_counter() - t0
+    return out
+
+
+def cpu_baseline(grid, moe_ctx=None, c4_grads=None):
+    """The FP64 oracle on the host: Adam steps of the 4x128 regressor at 2^14
+    samples and the decode of sampled voxels on the same volume, on all host
+    cores (numpy's BLAS threads) and on one thread; with the experts of the
+    decomposition leg, the oracle's blended decode of 2^14 sampled voxels; with
+    the small leg's gradients, the C4 gradient check."""
+    import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     import workloads
     from oracle import fit as F, mlp, tree as T
@@ -689,16 +771,21 @@ def cpu_baseline(grid, moe_ctx=None):
     shapes = mlp.layer_shapes(K, W, H, C)
     th = workloads.init_params(K, W, H, C, seed=21).astype(np.float64)
     B = workloads.ffm_matrix(M, 10.0, seed=11).astype(np.float64)
-    steps, batch = 3, 1 << 14
-    t = time.perf_counter()
-    F.train(th, shapes, B, tr, "regressor", (0, 0, 0), N_GRID, T.SDF, BAND, steps=steps, batch=batch, seed=0)
-    fit_s = time.perf_counter() - t
-    nd = 1 << 17
-    sel = np.random.default_rng(0).choice(len(vals), nd, replace=False)
-    t = time.perf_counter()
-    F.decode_values(th, shapes, B, tr, (0, 0, 0), N_GRID, T.SDF, BAND, idx=sel)
-    dec_s = time.perf_counter() - t
+    batch = 1 << 14
+
+    def rates(steps, nd):
+        t = time.perf_counter()
+        F.train(th, shapes, B, tr, "regressor", (0, 0, 0), N_GRID, T.SDF, BAND, steps=steps, batch=batch, seed=0)
+        fit_s = time.perf_counter() - t
+        sel = np.random.default_rng(0).choice(len(vals), nd, replace=False)
+        t = time.perf_counter()
+        F.decode_values(th, shapes, B, tr, (0, 0, 0), N_GRID, T.SDF, BAND, idx=sel)
+        return steps * batch / fit_s, nd / (time.perf_counter() - t)
+
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    fit_all, dec_all = rates(10, 1 << 20)
+    with threadpool_limits(limits=1):
+        fit_one, dec_one = rates(2, 1 << 15)
     extra = {}
     if moe_ctx is not None:
         from oracle import moe
@@ -710,12 +797,21 @@ def cpu_baseline(grid, moe_ctx=None):
         t = time.perf_counter()
         moe.decode_moe(tr["ijk"][sel_m], ex, moe_ctx["origin"], moe_ctx["size"], moe_ctx["halo"])
         extra["moe_blend_voxels_per_s"] = nm / (time.perf_counter() - t)
-    return {**extra, "value": steps * batch / fit_s, "unit": "train samples/s", "cores": int(threads), "kind": "oracle",
-            "sample": "3 Adam steps x 2^14 samples of the 4x128 regressor on the same 512^3 volume, FP64 numpy "
-                      "(oracle tree build of %d voxels took %.1f s, not counted); decode of 2^17 sampled voxels "
-                      "for decode_voxels_per_s; blended decode (8 experts) of 2^14 sampled voxels for "
-                      "moe_blend_voxels_per_s" % (len(vals), build_s),
-            "decode_voxels_per_s": nd / dec_s}
+    if c4_grads:
+        extra["c4_gradient_check"] = c4_gradient_check(c4_grads)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    return {**extra, "value": fit_all, "unit": "train samples/s", "cores": int(threads), "kind": "oracle",
+            "sample": "10 Adam steps x 2^14 samples of the 4x128 regressor on the same 512^3 volume, FP64 numpy on "
+                      "all cores (oracle tree build of %d voxels took %.1f s, not counted); decode of 2^20 sampled "
+                      "voxels for decode_voxels_per_s; single-thread rates from 2 steps x 2^14 and 2^15 decoded "
+                      "voxels; blended decode (8 experts) of 2^14 sampled voxels for moe_blend_voxels_per_s"
+                      % (len(vals), build_s),
+            "decode_voxels_per_s": dec_all, "single_thread": {"train_samples_per_s": fit_one,
+                                                              "decode_voxels_per_s": dec_one},
+            "nproc": os.cpu_count(), "affinity_cpus": affinity, "cpu_model": _cpu_model()}
 
 
 if __name__ == "__main__":

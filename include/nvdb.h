@@ -150,7 +150,9 @@ typedef struct {
 
 nvdb_status nvdb_model_create(const nvdb_model_desc* desc, nvdb_model** out);
 nvdb_status nvdb_model_param_count(const nvdb_model* model, int32_t net, int64_t* n);
-/* Parameters in the canonical flat layout, float32, host memory. */
+/* Parameters in the canonical flat layout, float32, host memory.  Both wait
+ * for the work this model has enqueued (its last recorded event), not for the
+ * whole device, and return once the copy is complete. */
 nvdb_status nvdb_model_set_params(nvdb_model* model, int32_t net, const float* params, int64_t n);
 nvdb_status nvdb_model_get_params(const nvdb_model* model, int32_t net, float* params, int64_t n);
 /* 16-bit storage of a network (Sec. 4 stores the networks at 16 bits): the
@@ -180,8 +182,10 @@ void nvdb_model_free(nvdb_model* model);
  * leaves (level-0 classifier), all leaf slots of the level-1 nodes (level-1
  * classifier) -- or, when idx_dev[net] is given, taken in order from that
  * device array of idx_count[net] population indices, `batch` per step with a
- * shorter final step (one pass = one epoch).  The loss of a step is the mean
- * over its samples. */
+ * shorter final step (one pass = one epoch); with index lists the call
+ * synchronises `stream` and fails with E_INVALID if an index was at or beyond
+ * its population size (such an index is read as 0).  The loss of a step is the
+ * mean over its samples. */
 typedef struct {
   int32_t steps;                 /* steps to run (per trained network)                   */
   int32_t batch;                 /* samples per step, 1 .. 2^24                          */
@@ -374,6 +378,13 @@ typedef struct {
 nvdb_status nvdb_subdomain_cells(const nvdb_tree* tree, const nvdb_subdomains* grid, int32_t* cells, int64_t cap,
                                  int64_t* n_cells, void* stream);
 
+/* Normalisation box of the expert of `cell` (Sec. 3.4: each subdomain's
+ * network sees coordinates normalised to its own bounding box): lo[3] = the
+ * widened box's lower corner origin + cell size - halo, *size = size + 2 halo;
+ * an expert's model takes domain_lo = lo and domain_size = *size.  Host only.
+ * Errors: E_INVALID (null arguments, bad grid, a corner outside [-2^30, 2^30]). */
+nvdb_status nvdb_subdomain_box(const nvdb_subdomains* grid, const int32_t cell[3], int32_t lo[3], int32_t* size);
+
 /* Training set of the expert of `cell`: the active voxels of `tree` inside the
  * cell's widened box, with their values, as a new tree (its arrays are those
  * of a tree built from that voxel list; it records the source's active rule).
@@ -443,20 +454,63 @@ nvdb_status nvdb_query(const nvdb_model* model, const nvdb_tree* tree, const flo
                        int64_t batch, float* values_dev, uint8_t* hits_dev, void* stream);
 
 /* ------------------------------------------------- device-pointer calls */
-/* Used by the autograd binding; no allocation beyond the model's workspace,
- * no synchronisation.
- * nvdb_forward_dev: y_dev[n][n_out] = f(x) for normalised coordinates
- *   x_dev float32[n][3].
- * nvdb_backward_dev: grad_dev[P] (canonical layout) = sum_i gy_dev[i] . df(x_i)/dtheta,
- *   recomputing the forward activations inside the fused kernel.
+/* Calls for the autograd binding and for callers that keep their own batches
+ * on the device.  None of them allocates or synchronises: their workspace is
+ * reserved beforehand by nvdb_model_reserve_dev, so a sequence of them can be
+ * recorded into a HIP graph.  They are asynchronous on `stream`.
+ *
+ * nvdb_model_reserve_dev: workspace for _dev calls of network `net` on batches
+ *   of up to max_n samples (partial gradient rows and gathered samples).  It
+ *   allocates and synchronises; the buffers keep their addresses until the next
+ *   reserve call or nvdb_model_free, so recorded graphs stay valid in between.
+ *   The work-groups per training launch are fixed here (the autotuned value,
+ *   else the default).  Errors: E_INVALID (max_n outside [1, 2^24]).
+ *
+ * The population of a network (Sec. 3.3.1) on `tree`: the regressor's is the
+ *   tree's N active voxels in its voxel order, the level-0 classifier's the
+ *   512 L voxel slots of its leaves (index leaf * 512 + n0), the level-1
+ *   classifier's the 4096 L1 leaf slots of its level-1 nodes (node * 4096 + n1,
+ *   at leaf centres).  An index is gathered and normalised inside the kernel
+ *   with the model's box (Sec. 3.4): x = (p - domain_lo + 1/2) / domain_size.
+ *   Indices must be below the population size: an index beyond it is read as 0
+ *   and counted in the model's index-error word (nvdb_model_take_errors).
+ *
+ * nvdb_forward_dev: y_dev float32[n][n_out] = network outputs (normalised units,
+ *   logits for classifiers) at the samples idx_dev uint32[n].
+ * nvdb_backward_dev: grad_dev float32[P] (canonical layout) =
+ *   sum_i sum_c gy_dev[i][c] dy_c(x_i)/dtheta over the samples idx_dev[i], the
+ *   forward activations recomputed inside the fused kernel (no activation is
+ *   stored).  n <= the reserved max_n (E_STATE otherwise).
+ * nvdb_forward_coords_dev / nvdb_backward_coords_dev: the same at caller-given
+ *   normalised coordinates x_dev float32[n][3] instead of population indices.
+ * nvdb_model_set_params_dev / nvdb_model_get_params_dev: the canonical FP32
+ *   parameters from / to device memory (float32[P]), ordered on `stream`; set
+ *   also rewrites the kernels' weight copies.  Values are not checked for
+ *   finiteness (that would need a synchronisation).
  * nvdb_sample_indices_dev: the sampler's indices idx_dev[j] = floor(h * n_pop / 2^64),
- *   h = SplitMix64 hash of (seed, stream_id, step, j), j < batch. */
-nvdb_status nvdb_forward_dev(const nvdb_model* model, int32_t net, const float* x_dev, int64_t n, float* y_dev,
-                             void* stream);
-nvdb_status nvdb_backward_dev(nvdb_model* model, int32_t net, const float* x_dev, const float* gy_dev, int64_t n,
-                              float* grad_dev, void* stream);
+ *   h = SplitMix64 hash of (seed, stream_id, step, j), j < batch.
+ * Errors of all: E_INVALID (null or oversized buffers, empty population),
+ *   E_STATE (parameters or encoding unset, workspace not reserved). */
+nvdb_status nvdb_model_reserve_dev(nvdb_model* model, int32_t net, int64_t max_n);
+nvdb_status nvdb_forward_dev(const nvdb_model* model, int32_t net, const nvdb_tree* tree, const uint32_t* idx_dev,
+                             int64_t n, float* y_dev, void* stream);
+nvdb_status nvdb_backward_dev(nvdb_model* model, int32_t net, const nvdb_tree* tree, const uint32_t* idx_dev,
+                              const float* gy_dev, int64_t n, float* grad_dev, void* stream);
+nvdb_status nvdb_forward_coords_dev(const nvdb_model* model, int32_t net, const float* x_dev, int64_t n, float* y_dev,
+                                    void* stream);
+nvdb_status nvdb_backward_coords_dev(nvdb_model* model, int32_t net, const float* x_dev, const float* gy_dev,
+                                     int64_t n, float* grad_dev, void* stream);
+nvdb_status nvdb_model_set_params_dev(nvdb_model* model, int32_t net, const float* params_dev, int64_t n,
+                                      void* stream);
+nvdb_status nvdb_model_get_params_dev(const nvdb_model* model, int32_t net, float* params_dev, int64_t n,
+                                      void* stream);
 nvdb_status nvdb_sample_indices_dev(uint64_t seed, int32_t stream_id, int64_t step, int64_t n_pop, int64_t batch,
                                     uint32_t* idx_dev, void* stream);
+/* Waits for the model's enqueued work, then returns and clears its error word:
+ * *n_bad_index = number of sample indices at or beyond their population size
+ * read since the last call (explicit index lists of nvdb_fit and the _dev
+ * calls).  nvdb_fit with index lists checks it itself (E_INVALID). */
+nvdb_status nvdb_model_take_errors(nvdb_model* model, int64_t* n_bad_index);
 
 #ifdef __cplusplus
 }

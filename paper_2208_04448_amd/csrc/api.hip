@@ -33,6 +33,12 @@ struct Net {
   mutable DevBuf<char> w8;
   mutable DevBuf<float> w8inv;
   DevBuf<float> bias, whead, bhead, benc;
+  // workspace of the _dev calls (nvdb_model_reserve_dev): fixed addresses, so
+  // graphs that record those calls stay valid until the next reservation
+  DevBuf<float> dpart, dlossp;
+  DevBuf<floatx4> dxt;
+  int64_t dev_n = 0;
+  int dev_G = 0;
   int64_t step = 0;
   bool params_set = false, enc_set = false;
 };
@@ -44,6 +50,14 @@ struct nvdb_model {
   nvdb_model_desc d{};
   nvdb::Net nets[NVDB_MAX_NETS];
   int train_g = 0;  // work-groups per network chosen by nvdb_autotune (0: default)
+  // recorded on the caller's stream after the model's enqueued work; host-side
+  // parameter copies wait for it instead of the whole device
+  hipEvent_t done = nullptr;
+  // [0]: explicit sample indices found at or beyond their population size
+  nvdb::DevBuf<unsigned long long> errw;
+  ~nvdb_model() {
+    if (done) (void)hipEventDestroy(done);
+  }
 };
 
 using namespace nvdb;
@@ -129,6 +143,25 @@ static Net& net_of(nvdb_model* m, int32_t net) {
   return m->nets[net];
 }
 static const Net& net_of(const nvdb_model* m, int32_t net) { return net_of(const_cast<nvdb_model*>(m), net); }
+
+// The model's work enqueued on `st` so far: host copies of its state wait for this.
+// Not recorded while `st` is being captured into a graph: the graph's launch is the
+// caller's to order.
+static void mark(const nvdb_model* m, hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  NVDB_HIP(hipStreamIsCapturing(st, &cs));
+  if (cs == hipStreamCaptureStatusNone) NVDB_HIP(hipEventRecord(m->done, st));
+}
+static void wait_model(const nvdb_model* m) { NVDB_HIP(hipEventSynchronize(m->done)); }
+
+// Reads and clears the model's count of out-of-range sample indices (waits for its work).
+static int64_t take_bad_indices(const nvdb_model* m) {
+  wait_model(m);
+  unsigned long long v = 0;
+  NVDB_HIP(hipMemcpy(&v, m->errw.p, sizeof(v), hipMemcpyDeviceToHost));
+  if (v) NVDB_HIP(hipMemset(m->errw.p, 0, sizeof(v)));
+  return (int64_t)v;
+}
 
 static void ensure_partials(Net& n, int G) {
   n.partial.ensure((size_t)G * n.s.pstride());
@@ -302,6 +335,9 @@ nvdb_status nvdb_model_create(const nvdb_model_desc* desc, nvdb_model** out) {
         NVDB_HIP(hipMemset(n.benc.p, 0, n.benc.n * 4));
       }
       NVDB_REQUIRE(any, NVDB_E_INVALID, "model has no networks");
+      NVDB_HIP(hipEventCreateWithFlags(&m->done, hipEventDisableTiming));
+      m->errw.alloc(1);
+      NVDB_HIP(hipMemset(m->errw.p, 0, sizeof(unsigned long long)));
     } catch (...) {
       delete m;
       throw;
@@ -322,9 +358,10 @@ nvdb_status nvdb_model_set_params(nvdb_model* m, int32_t net, const float* param
     Net& N = net_of(m, net);
     NVDB_REQUIRE(params && n == N.s.nparams(), NVDB_E_INVALID, "parameter count mismatch");
     for (int64_t i = 0; i < n; ++i) NVDB_REQUIRE(std::isfinite(params[i]), NVDB_E_INVALID, "non-finite parameter");
+    wait_model(m);
     NVDB_HIP(hipMemcpy(N.theta.p, params, n * 4, hipMemcpyHostToDevice));
     launch_write_shadow(adam_view(N), nullptr);
-    NVDB_HIP(hipDeviceSynchronize());
+    NVDB_HIP(hipStreamSynchronize(nullptr));
     N.params_set = true;
   });
 }
@@ -333,7 +370,7 @@ nvdb_status nvdb_model_get_params(const nvdb_model* m, int32_t net, float* param
   return guarded([&] {
     const Net& N = net_of(m, net);
     NVDB_REQUIRE(params && n == N.s.nparams(), NVDB_E_INVALID, "parameter count mismatch");
-    NVDB_HIP(hipDeviceSynchronize());
+    wait_model(m);
     NVDB_HIP(hipMemcpy(params, N.theta.p, n * 4, hipMemcpyDeviceToHost));
   });
 }
@@ -402,7 +439,7 @@ nvdb_status nvdb_model_get_params16(const nvdb_model* m, int32_t net, int32_t ki
     const Net& N = net_of(m, net);
     NVDB_REQUIRE(dst && n == N.s.nparams(), NVDB_E_INVALID, "parameter count mismatch");
     std::vector<float> f((size_t)n);
-    NVDB_HIP(hipDeviceSynchronize());
+    wait_model(m);
     NVDB_HIP(hipMemcpy(f.data(), N.theta.p, n * 4, hipMemcpyDeviceToHost));
     for (int64_t i = 0; i < n; ++i) dst[i] = kind == NVDB_STORE_F16 ? f32_to_f16(f[i]) : f32_to_bf16(f[i]);
   });
@@ -440,7 +477,7 @@ nvdb_status nvdb_model_get_opt_state(const nvdb_model* m, int32_t net, float* mm
   return guarded([&] {
     const Net& N = net_of(m, net);
     NVDB_REQUIRE(n == N.s.nparams(), NVDB_E_INVALID, "parameter count mismatch");
-    NVDB_HIP(hipDeviceSynchronize());
+    wait_model(m);
     if (mm) NVDB_HIP(hipMemcpy(mm, N.m.p, n * 4, hipMemcpyDeviceToHost));
     if (vv) NVDB_HIP(hipMemcpy(vv, N.v.p, n * 4, hipMemcpyDeviceToHost));
     if (step) *step = N.step;
@@ -452,6 +489,7 @@ nvdb_status nvdb_model_set_opt_state(nvdb_model* m, int32_t net, const float* mm
   return guarded([&] {
     Net& N = net_of(m, net);
     NVDB_REQUIRE(mm && vv && n == N.s.nparams() && step >= 0, NVDB_E_INVALID, "bad optimiser state");
+    wait_model(m);
     NVDB_HIP(hipMemcpy(N.m.p, mm, n * 4, hipMemcpyHostToDevice));
     NVDB_HIP(hipMemcpy(N.v.p, vv, n * 4, hipMemcpyHostToDevice));
     N.step = step;
@@ -577,6 +615,7 @@ static void enqueue_step(nvdb_model* m, const Tree* tree, const std::vector<std:
         const int64_t off = (int64_t)step * ph.batch;
         n = std::min<int64_t>(ph.batch, ph.idx->idx_count[k] - off);
         tn.spec.idx = ph.idx->idx_dev[k] + off;
+        tn.spec.bad_idx = m->errw.p;
       } else {
         tn.spec.step_seed = step_seed(ph.seed, k, N.step);
       }
@@ -662,6 +701,10 @@ nvdb_status nvdb_fit(nvdb_model* m, const nvdb_tree* tree, const nvdb_fit_desc* 
       for (int k : nets) hk.loss_out[k] = m->nets[k].losses.p + step;
       enqueue_step(m, tree, groups, ph, step, hk, ev.empty() ? nullptr : ev.data() + 2 * groups.size() * step, st);
     }
+    mark(m, st);
+    bool lists = false;
+    for (int k : nets) lists = lists || fit->idx_dev[k] != nullptr;
+    if (lists) NVDB_REQUIRE(take_bad_indices(m) == 0, NVDB_E_INVALID, "sample index at or beyond its population size");
     if (!ev.empty()) {
       NVDB_HIP(hipEventSynchronize(ev.back()));
       double tot = 0.0;
@@ -1078,20 +1121,32 @@ extern "C" {
 
 nvdb_status nvdb_decode(const nvdb_model* m, const nvdb_tree* tree, float* values_dev, uint64_t* pred_mask_dev,
                         void* stream) {
-  return guarded([&] { decode_impl(m, tree, values_dev, pred_mask_dev, false, (hipStream_t)stream); });
+  return guarded([&] {
+    decode_impl(m, tree, values_dev, pred_mask_dev, false, (hipStream_t)stream);
+    mark(m, (hipStream_t)stream);
+  });
 }
 
 nvdb_status nvdb_decode_fp8(const nvdb_model* m, const nvdb_tree* tree, float* values_dev, uint64_t* pred_mask_dev,
                             void* stream) {
-  return guarded([&] { decode_impl(m, tree, values_dev, pred_mask_dev, true, (hipStream_t)stream); });
+  return guarded([&] {
+    decode_impl(m, tree, values_dev, pred_mask_dev, true, (hipStream_t)stream);
+    mark(m, (hipStream_t)stream);
+  });
 }
 
 nvdb_status nvdb_decode_l1(const nvdb_model* m, const nvdb_tree* tree, uint8_t* classes_dev, void* stream) {
-  return guarded([&] { decode_l1_impl(m, tree, classes_dev, false, (hipStream_t)stream); });
+  return guarded([&] {
+    decode_l1_impl(m, tree, classes_dev, false, (hipStream_t)stream);
+    mark(m, (hipStream_t)stream);
+  });
 }
 
 nvdb_status nvdb_decode_l1_fp8(const nvdb_model* m, const nvdb_tree* tree, uint8_t* classes_dev, void* stream) {
-  return guarded([&] { decode_l1_impl(m, tree, classes_dev, true, (hipStream_t)stream); });
+  return guarded([&] {
+    decode_l1_impl(m, tree, classes_dev, true, (hipStream_t)stream);
+    mark(m, (hipStream_t)stream);
+  });
 }
 
 nvdb_status nvdb_errors(const nvdb_tree* tree, const float* values_dev, const uint64_t* pred_mask_dev,
@@ -1343,6 +1398,28 @@ nvdb_status nvdb_subdomain_cells(const nvdb_tree* tree, const nvdb_subdomains* g
   });
 }
 
+}  // extern "C"
+
+// Lower corner of the widened box of `cell` (its expert's normalisation box).
+static void widened_lo(const MoeGrid& g, const int32_t cell[3], int32_t lo[3]) {
+  for (int d = 0; d < 3; ++d) {
+    const int64_t l = (int64_t)g.o[d] + (int64_t)cell[d] * g.S - g.h;
+    NVDB_REQUIRE(l >= -(1ll << 30) && l <= (1ll << 30), NVDB_E_INVALID, "cell outside the index range");
+    lo[d] = (int32_t)l;
+  }
+}
+
+extern "C" {
+
+nvdb_status nvdb_subdomain_box(const nvdb_subdomains* grid, const int32_t cell[3], int32_t lo[3], int32_t* size) {
+  return guarded([&] {
+    NVDB_REQUIRE(cell && lo && size, NVDB_E_INVALID, "null argument");
+    const MoeGrid g = check_grid(grid);
+    widened_lo(g, cell, lo);
+    *size = g.S + 2 * g.h;
+  });
+}
+
 nvdb_status nvdb_tree_subdomain(const nvdb_tree* tree, const nvdb_subdomains* grid, const int32_t cell[3],
                                 void* stream, nvdb_tree** out) {
   return guarded([&] {
@@ -1350,11 +1427,7 @@ nvdb_status nvdb_tree_subdomain(const nvdb_tree* tree, const nvdb_subdomains* gr
     *out = nullptr;
     const MoeGrid g = check_grid(grid);
     int32_t lo[3];
-    for (int d = 0; d < 3; ++d) {
-      const int64_t l = (int64_t)g.o[d] + (int64_t)cell[d] * g.S - g.h;
-      NVDB_REQUIRE(l >= -(1ll << 30) && l <= (1ll << 30), NVDB_E_INVALID, "cell outside the index range");
-      lo[d] = (int32_t)l;
-    }
+    widened_lo(g, cell, lo);
     hipStream_t st = (hipStream_t)stream;
     DevBuf<int32_t> ijk;
     DevBuf<float> v;
@@ -1499,59 +1572,168 @@ nvdb_status nvdb_decode_moe_mask(const nvdb_model* const* experts, const int32_t
   });
 }
 
-nvdb_status nvdb_forward_dev(const nvdb_model* m, int32_t net, const float* x_dev, int64_t n, float* y_dev,
-                             void* stream) {
+}  // extern "C"
+
+// Forward pass of one network over n samples given by spec (population indices
+// of `tree`, or coordinates); no allocation.
+static void forward_dev_impl(const nvdb_model* m, int32_t net, const Tree* tree, const SampleSpec& sp, float* y_dev,
+                             hipStream_t st) {
+  const Net& N = net_of(m, net);
+  InferLaunch I{};
+  I.net = net_view(N);
+  I.spec = sp;
+  I.tree = tree_view(tree);
+  I.out_kind = OUT_Y;
+  I.y = y_dev;
+  launch_infer(N.ks, I, infer_grid(sp.n), st);
+  mark(m, st);
+}
+
+// Summed parameter gradient of sum_i gy_i . y(x_i) through the fused training
+// kernel (activations recomputed), into grad_dev; workspace from the reservation.
+static void backward_dev_impl(nvdb_model* m, int32_t net, const Tree* tree, SampleSpec sp, const float* gy_dev,
+                              float* grad_dev, hipStream_t st) {
+  Net& N = net_of(m, net);
+  NVDB_REQUIRE(N.dev_n > 0 && sp.n <= N.dev_n, NVDB_E_STATE,
+               "_dev workspace not reserved for this batch (nvdb_model_reserve_dev)");
+  const int G = train_grid(sp.n, N.dev_G);
+  TrainLaunch L{};
+  L.G = G;
+  L.tree = tree_view(tree);
+  TrainNet& tn = L.nets[0];
+  tn.net = net_view(N);
+  sp.loss = LOSS_EXTERNAL;
+  sp.gy = gy_dev;
+  sp.inv_n = 1.f;
+  tn.spec = sp;
+  tn.partial = N.dpart.p;
+  tn.loss_partial = N.dlossp.p;
+  launch_gather(tn.spec, L.tree, N.dxt.p, st);
+  tn.xt = N.dxt.p;
+  launch_train(N.ks, L, 1, st);
+  AdamLaunch AL{};
+  AL.nets[0] = adam_view(N);
+  AL.nets[0].partial = N.dpart.p;
+  AL.nets[0].loss_partial = N.dlossp.p;
+  AL.nets[0].G = G;
+  AL.nets[0].grad_out = grad_dev;
+  launch_reduce_adam(AL, N.s.nparams(), 1, st);
+  mark(m, st);
+}
+
+// Sample spec of n population indices of network `net` on `tree`.
+static SampleSpec index_spec(const nvdb_model* m, int32_t net, const Tree* tree, const uint32_t* idx, int64_t n) {
+  NVDB_REQUIRE(tree != nullptr, NVDB_E_INVALID, "null tree");
+  SampleSpec sp;
+  base_spec(m, &sp);
+  int64_t pop;
+  sp.src = population_src(net, tree, &pop);
+  NVDB_REQUIRE(pop > 0 && pop < (1ll << 32), NVDB_E_INVALID, "empty or oversized population");
+  sp.npop = (uint32_t)pop;
+  sp.idx = idx;
+  sp.bad_idx = m->errw.p;
+  sp.n = n;
+  return sp;
+}
+
+static const Net& ready_net(const nvdb_model* m, int32_t net) {
+  const Net& N = net_of(m, net);
+  NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "parameters or encoding not set");
+  return N;
+}
+
+extern "C" {
+
+nvdb_status nvdb_model_reserve_dev(nvdb_model* m, int32_t net, int64_t max_n) {
   return guarded([&] {
-    const Net& N = net_of(m, net);
-    NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "parameters or encoding not set");
-    NVDB_REQUIRE(n >= 0 && (n == 0 || (x_dev && y_dev)), NVDB_E_INVALID, "bad buffers");
-    if (n == 0) return;
-    InferLaunch I{};
-    I.net = net_view(N);
-    base_spec(m, &I.spec);
-    I.spec.src = SRC_COORDS;
-    I.spec.direct = 1;
-    I.spec.coords = x_dev;
-    I.spec.n = n;
-    I.out_kind = OUT_Y;
-    I.y = y_dev;
-    launch_infer(N.ks, I, infer_grid(n), (hipStream_t)stream);
+    Net& N = net_of(m, net);
+    NVDB_REQUIRE(max_n >= 1 && max_n <= (1 << 24), NVDB_E_INVALID, "max_n must be in 1..2^24");
+    wait_model(m);
+    const int G = train_grid(max_n, m->train_g > 0 ? m->train_g : DEFAULT_G);
+    N.dev_n = 0;
+    N.dpart.alloc((size_t)G * N.s.pstride());
+    N.dlossp.alloc(G);
+    N.dxt.alloc((size_t)max_n);
+    N.dev_G = G;
+    N.dev_n = max_n;
   });
 }
 
-nvdb_status nvdb_backward_dev(nvdb_model* m, int32_t net, const float* x_dev, const float* gy_dev, int64_t n,
-                              float* grad_dev, void* stream) {
+nvdb_status nvdb_forward_dev(const nvdb_model* m, int32_t net, const nvdb_tree* tree, const uint32_t* idx_dev,
+                             int64_t n, float* y_dev, void* stream) {
+  return guarded([&] {
+    ready_net(m, net);
+    NVDB_REQUIRE(n >= 0 && n < (1ll << 31) && (n == 0 || (idx_dev && y_dev)), NVDB_E_INVALID, "bad buffers");
+    if (n == 0) return;
+    forward_dev_impl(m, net, tree, index_spec(m, net, tree, idx_dev, n), y_dev, (hipStream_t)stream);
+  });
+}
+
+nvdb_status nvdb_backward_dev(nvdb_model* m, int32_t net, const nvdb_tree* tree, const uint32_t* idx_dev,
+                              const float* gy_dev, int64_t n, float* grad_dev, void* stream) {
+  return guarded([&] {
+    ready_net(m, net);
+    NVDB_REQUIRE(n >= 1 && idx_dev && gy_dev && grad_dev, NVDB_E_INVALID, "bad buffers");
+    backward_dev_impl(m, net, tree, index_spec(m, net, tree, idx_dev, n), gy_dev, grad_dev, (hipStream_t)stream);
+  });
+}
+
+nvdb_status nvdb_forward_coords_dev(const nvdb_model* m, int32_t net, const float* x_dev, int64_t n, float* y_dev,
+                                    void* stream) {
+  return guarded([&] {
+    ready_net(m, net);
+    NVDB_REQUIRE(n >= 0 && n < (1ll << 31) && (n == 0 || (x_dev && y_dev)), NVDB_E_INVALID, "bad buffers");
+    if (n == 0) return;
+    SampleSpec sp;
+    base_spec(m, &sp);
+    sp.src = SRC_COORDS;
+    sp.direct = 1;
+    sp.coords = x_dev;
+    sp.n = n;
+    forward_dev_impl(m, net, nullptr, sp, y_dev, (hipStream_t)stream);
+  });
+}
+
+nvdb_status nvdb_backward_coords_dev(nvdb_model* m, int32_t net, const float* x_dev, const float* gy_dev, int64_t n,
+                                     float* grad_dev, void* stream) {
+  return guarded([&] {
+    ready_net(m, net);
+    NVDB_REQUIRE(n >= 1 && x_dev && gy_dev && grad_dev, NVDB_E_INVALID, "bad buffers");
+    SampleSpec sp;
+    base_spec(m, &sp);
+    sp.src = SRC_COORDS;
+    sp.coords = x_dev;
+    sp.n = n;
+    backward_dev_impl(m, net, nullptr, sp, gy_dev, grad_dev, (hipStream_t)stream);
+  });
+}
+
+nvdb_status nvdb_model_set_params_dev(nvdb_model* m, int32_t net, const float* params_dev, int64_t n, void* stream) {
   return guarded([&] {
     Net& N = net_of(m, net);
-    NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "parameters or encoding not set");
-    NVDB_REQUIRE(n >= 1 && x_dev && gy_dev && grad_dev, NVDB_E_INVALID, "bad buffers");
+    NVDB_REQUIRE(params_dev && n == N.s.nparams(), NVDB_E_INVALID, "parameter count mismatch");
     hipStream_t st = (hipStream_t)stream;
-    const int G = train_grid(n, m->train_g > 0 ? m->train_g : DEFAULT_G);
-    ensure_partials(N, G);
-    TrainLaunch L{};
-    L.G = G;
-    TrainNet& tn = L.nets[0];
-    tn.net = net_view(N);
-    base_spec(m, &tn.spec);
-    tn.spec.src = SRC_COORDS;
-    tn.spec.loss = LOSS_EXTERNAL;
-    tn.spec.coords = x_dev;
-    tn.spec.gy = gy_dev;
-    tn.spec.n = n;
-    tn.spec.inv_n = 1.f;
-    tn.partial = N.partial.p;
-    tn.loss_partial = N.loss_partial.p;
-    N.xt.ensure(n);
-    launch_gather(tn.spec, TreeView{}, N.xt.p, st);
-    tn.xt = N.xt.p;
-    launch_train(N.ks, L, 1, st);
-    AdamLaunch AL{};
-    AL.nets[0] = adam_view(N);
-    AL.nets[0].partial = N.partial.p;
-    AL.nets[0].loss_partial = N.loss_partial.p;
-    AL.nets[0].G = G;
-    AL.nets[0].grad_out = grad_dev;
-    launch_reduce_adam(AL, N.s.nparams(), 1, st);
+    NVDB_HIP(hipMemcpyAsync(N.theta.p, params_dev, n * 4, hipMemcpyDeviceToDevice, st));
+    launch_write_shadow(adam_view(N), st);
+    mark(m, st);
+    N.params_set = true;
+  });
+}
+
+nvdb_status nvdb_model_get_params_dev(const nvdb_model* m, int32_t net, float* params_dev, int64_t n, void* stream) {
+  return guarded([&] {
+    const Net& N = net_of(m, net);
+    NVDB_REQUIRE(params_dev && n == N.s.nparams(), NVDB_E_INVALID, "parameter count mismatch");
+    hipStream_t st = (hipStream_t)stream;
+    NVDB_HIP(hipMemcpyAsync(params_dev, N.theta.p, n * 4, hipMemcpyDeviceToDevice, st));
+    mark(m, st);
+  });
+}
+
+nvdb_status nvdb_model_take_errors(nvdb_model* m, int64_t* n_bad_index) {
+  return guarded([&] {
+    NVDB_REQUIRE(m && n_bad_index, NVDB_E_INVALID, "null argument");
+    *n_bad_index = take_bad_indices(m);
   });
 }
 

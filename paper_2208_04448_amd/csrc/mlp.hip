@@ -222,7 +222,9 @@ struct Smp {
   bool valid;
 };
 
-__device__ __forceinline__ Smp fetch_sample(const SampleSpec& sp, const TreeView& tv, int64_t j) {
+// `count` selects the one caller per sample that counts an out-of-range index (the two
+// lane halves of a decode wave fetch the same sample).
+__device__ __forceinline__ Smp fetch_sample(const SampleSpec& sp, const TreeView& tv, int64_t j, bool count = true) {
   Smp s;
   s.x[0] = s.x[1] = s.x[2] = 0.f;
   s.t = 0.f;
@@ -240,6 +242,10 @@ __device__ __forceinline__ Smp fetch_sample(const SampleSpec& sp, const TreeView
     g = (uint32_t)j;
   } else if (sp.idx) {
     g = sp.idx[j];
+    if (g >= sp.npop) {  // out of the population: read index 0 and count it
+      if (sp.bad_idx && count) atomicAdd(sp.bad_idx, 1ull);
+      g = 0;
+    }
   } else {
     uint64_t h = sm_mix(sp.step_seed + SM_GOLDEN * (uint64_t)(j + 1));
     g = (uint32_t)__umul64hi(h, (uint64_t)sp.npop);
@@ -1378,7 +1384,7 @@ __global__ void __launch_bounds__(64 * NVDB_INFER_WAVES, 1)
     uint32_t A[NT][NA][SR];
 #pragma unroll
     for (int u = 0; u < NT; ++u) {
-      const Smp smp = fetch_sample(sp, I.tree, base + 32 * u + fl);
+      const Smp smp = fetch_sample(sp, I.tree, base + 32 * u + fl, h == 0);
       uint32_t X0[NIB0][SR];
       if constexpr (BF) {
         if (fastenc) encode_bf16_mfma<NIB0>(pa, smp, X0);
@@ -1680,7 +1686,7 @@ __global__ void __launch_bounds__(64 * NVDB_INFER8_WAVES, NVDB_INFER8_WGS)
 #pragma unroll
     for (int u = 0; u < NT; ++u) {
       zmax[u] = 0.f;
-      const Smp smp = fetch_sample(sp, I.tree, base + 32 * u + fl);
+      const Smp smp = fetch_sample(sp, I.tree, base + 32 * u + fl, h == 0);
       float X0[NIB0][16];
       if (fastenc) {
         floatx16 ph[NIB0 / 2];

@@ -129,6 +129,7 @@ struct SampleSpec {
   const float* coords;    // SRC_COORDS: [n][3]
   const float* gy;        // LOSS_EXTERNAL: [n][n_out]
   const uint32_t* n_dev;  // decode: optional device-side count, the samples are the first min(n, *n_dev)
+  unsigned long long* bad_idx;  // explicit indices: count of indices >= npop (read as index 0), or null
 };
 
 // ----------------------------------------------------------- net layout

@@ -123,8 +123,16 @@ _SIGS = {
     "nvdb_errors_l1": (C.c_int32, [_P, _P, C.POINTER(L1Report), _P]),
     "nvdb_decode_topology": (C.c_int32, [_P, _P, C.c_int32, C.POINTER(_P), _P]),
     "nvdb_errors_topology": (C.c_int32, [_P, _P, C.POINTER(TopologyReport), _P]),
-    "nvdb_forward_dev": (C.c_int32, [_P, C.c_int32, _P, C.c_int64, _P, _P]),
-    "nvdb_backward_dev": (C.c_int32, [_P, C.c_int32, _P, _P, C.c_int64, _P, _P]),
+    "nvdb_model_reserve_dev": (C.c_int32, [_P, C.c_int32, C.c_int64]),
+    "nvdb_forward_dev": (C.c_int32, [_P, C.c_int32, _P, _P, C.c_int64, _P, _P]),
+    "nvdb_backward_dev": (C.c_int32, [_P, C.c_int32, _P, _P, _P, C.c_int64, _P, _P]),
+    "nvdb_forward_coords_dev": (C.c_int32, [_P, C.c_int32, _P, C.c_int64, _P, _P]),
+    "nvdb_backward_coords_dev": (C.c_int32, [_P, C.c_int32, _P, _P, C.c_int64, _P, _P]),
+    "nvdb_model_set_params_dev": (C.c_int32, [_P, C.c_int32, _P, C.c_int64, _P]),
+    "nvdb_model_get_params_dev": (C.c_int32, [_P, C.c_int32, _P, C.c_int64, _P]),
+    "nvdb_model_take_errors": (C.c_int32, [_P, C.POINTER(C.c_int64)]),
+    "nvdb_subdomain_box": (C.c_int32, [C.POINTER(Subdomains), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_int32)]),
     "nvdb_sample_indices_dev": (C.c_int32, [C.c_uint64, C.c_int32, C.c_int64, C.c_int64, C.c_int64, _P, _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -151,6 +159,17 @@ def _ptr(t):
 
 def _i3(v):
     return (C.c_int32 * 3)(*[int(a) for a in v])
+
+
+def _index_tensor(t, name="idx"):
+    """A population-index list as the library reads it: a contiguous 1-D int32 or
+    uint32 CUDA tensor (an int64 tensor would be read as pairs of 32-bit words)."""
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype in (torch.int32, torch.uint32) and t.dim() == 1):
+        raise NvdbError(E_INVALID, "%s must be a 1-D int32/uint32 CUDA tensor" % name)
+    if not t.is_contiguous():
+        raise NvdbError(E_INVALID, "%s must be contiguous" % name)
+    return t
 
 
 # ---------------------------------------------------------------------------- trees
@@ -297,6 +316,7 @@ class Model:
         f.lr, f.lr_decay, f.lr_interval, f.nets_mask = lr, lr_decay, lr_interval, nets_mask
         keep = []
         for k, t in (idx or {}).items():
+            _index_tensor(t, "idx[%d]" % k)
             keep.append(t)
             f.idx_dev[k] = t.data_ptr()
             f.idx_count[k] = t.numel()
@@ -383,19 +403,63 @@ class Model:
         _check(_lib.nvdb_query(self.h, tree.h, _ptr(q), n, float(background), int(batch), _ptr(v), _ptr(h), _stream()))
         return (v, h) if return_hits else v
 
-    def forward(self, net, x):
+    def reserve_dev(self, net, max_n):
+        """Workspace for forward/backward calls of up to max_n samples (allocates once)."""
+        _check(_lib.nvdb_model_reserve_dev(self.h, net, int(max_n)))
+
+    def forward(self, net, tree, idx, out=None):
+        """Network outputs [n, n_out] at population indices idx of `tree` (gathered and
+        normalised in the kernel)."""
+        import torch
+        _index_tensor(idx)
+        y = out if out is not None else torch.empty((idx.numel(), self.nets[net][3]), dtype=torch.float32,
+                                                     device=idx.device)
+        _check(_lib.nvdb_forward_dev(self.h, net, tree.h, _ptr(idx), idx.numel(), _ptr(y), _stream()))
+        return y
+
+    def backward(self, net, tree, idx, gy, out=None):
+        """Summed parameter gradient of sum_i gy_i . y(idx_i) (canonical layout); needs reserve_dev."""
+        import torch
+        _index_tensor(idx)
+        gy = gy.contiguous()
+        assert gy.dtype == torch.float32 and gy.numel() == idx.numel() * self.nets[net][3]
+        g = out if out is not None else torch.empty(self.param_count(net), dtype=torch.float32, device=idx.device)
+        _check(_lib.nvdb_backward_dev(self.h, net, tree.h, _ptr(idx), _ptr(gy), idx.numel(), _ptr(g), _stream()))
+        return g
+
+    def forward_coords(self, net, x):
+        """Network outputs at normalised coordinates x [n, 3] (device tensor)."""
         import torch
         x = x.contiguous()
         y = torch.empty((x.shape[0], self.nets[net][3]), dtype=torch.float32, device=x.device)
-        _check(_lib.nvdb_forward_dev(self.h, net, _ptr(x), x.shape[0], _ptr(y), _stream()))
+        _check(_lib.nvdb_forward_coords_dev(self.h, net, _ptr(x), x.shape[0], _ptr(y), _stream()))
         return y
 
-    def backward(self, net, x, gy):
+    def backward_coords(self, net, x, gy):
+        """Summed parameter gradient at normalised coordinates; needs reserve_dev."""
         import torch
         x, gy = x.contiguous(), gy.contiguous()
         g = torch.empty(self.param_count(net), dtype=torch.float32, device=x.device)
-        _check(_lib.nvdb_backward_dev(self.h, net, _ptr(x), _ptr(gy), x.shape[0], _ptr(g), _stream()))
+        _check(_lib.nvdb_backward_coords_dev(self.h, net, _ptr(x), _ptr(gy), x.shape[0], _ptr(g), _stream()))
         return g
+
+    def set_params_dev(self, net, theta):
+        """Load the canonical parameters from a float32 CUDA tensor (ordered on the current stream)."""
+        import torch
+        assert theta.is_cuda and theta.dtype == torch.float32 and theta.is_contiguous()
+        _check(_lib.nvdb_model_set_params_dev(self.h, net, _ptr(theta), theta.numel(), _stream()))
+
+    def get_params_dev(self, net):
+        import torch
+        t = torch.empty(self.param_count(net), dtype=torch.float32, device="cuda")
+        _check(_lib.nvdb_model_get_params_dev(self.h, net, _ptr(t), t.numel(), _stream()))
+        return t
+
+    def take_errors(self):
+        """Number of out-of-range sample indices read since the last call (synchronises)."""
+        n = C.c_int64()
+        _check(_lib.nvdb_model_take_errors(self.h, C.byref(n)))
+        return n.value
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -440,8 +504,10 @@ def subdomain_cells(tree, origin, size, halo):
 
 def subdomain_box(origin, size, halo, cell):
     """Normalisation box of a cell's expert: (lower corner of the widened box, its edge)."""
-    lo = [int(o) + int(c) * int(size) - int(halo) for o, c in zip(origin, cell)]
-    return lo, int(size) + 2 * int(halo)
+    g = Subdomains(_i3(origin), int(size), int(halo))
+    lo, d = (C.c_int32 * 3)(), C.c_int32()
+    _check(_lib.nvdb_subdomain_box(C.byref(g), _i3(cell), lo, C.byref(d)))
+    return list(lo), d.value
 
 
 def decode_moe(experts, cells, origin, size, halo, tree):
@@ -503,22 +569,27 @@ def sample_indices(seed, stream_id, step, n_pop, batch):
 def mlp_function():
     """torch.autograd.Function whose forward and backward are the fused HIP kernels.
 
-    apply(model, net, x, theta_placeholder) -> y; the gradient arrives in
-    theta_placeholder.grad (canonical layout).  The backward recomputes the
-    forward activations inside the fused kernel instead of storing them."""
+    apply(model, net, tree, idx, theta) -> y [n, n_out]: the network with the
+    canonical parameter tensor theta (float32 CUDA, P) at population indices idx
+    of `tree`.  theta is loaded into the model on the current stream by both
+    passes, so a torch optimiser can train it; its gradient is the fused
+    backward kernel's, which recomputes the forward activations instead of
+    storing them.  The model needs reserve_dev(net, n) for the backward."""
     import torch
 
     class NvdbMLP(torch.autograd.Function):
         @staticmethod
-        def forward(ctx, model, net, x, theta):
-            ctx.model, ctx.net = model, net
-            ctx.save_for_backward(x)
-            return model.forward(net, x)
+        def forward(ctx, model, net, tree, idx, theta):
+            ctx.model, ctx.net, ctx.tree = model, net, tree
+            ctx.save_for_backward(idx, theta)
+            model.set_params_dev(net, theta.detach())
+            return model.forward(net, tree, idx)
 
         @staticmethod
         def backward(ctx, gy):
-            (x,) = ctx.saved_tensors
-            g = ctx.model.backward(ctx.net, x, gy.float())
-            return None, None, None, g
+            idx, theta = ctx.saved_tensors
+            ctx.model.set_params_dev(ctx.net, theta.detach())
+            g = ctx.model.backward(ctx.net, ctx.tree, idx, gy.float())
+            return None, None, None, None, g
 
     return NvdbMLP

@@ -25,3 +25,17 @@ def gpu_lib():
         pytest.skip("no GPU in this environment")
     from paper_2208_04448_amd import nvdb
     return nvdb
+
+
+@pytest.fixture(scope="session")
+def record():
+    """record(name, **values): appends measured errors of a test as one JSON line to
+    $NVDB_RECORD (if set), so that tolerances can be set from observed values."""
+    import json
+    path = os.environ.get("NVDB_RECORD")
+
+    def _rec(name, **vals):
+        if path:
+            with open(path, "a") as f:
+                f.write(json.dumps(dict(test=name, **{k: float(v) for k, v in vals.items()})) + "\n")
+    return _rec

@@ -5,6 +5,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -73,3 +74,18 @@ def test_null_arguments(nvdb):
     dims = (C.c_int32 * 3)(0, 4, 4)
     rule = nvdb.ActiveRule(0, 1.0)
     assert nvdb._lib.nvdb_tree_build_dense(C.c_void_p(16), dims, org, C.byref(rule), None, C.byref(h)) == nvdb.E_INVALID
+
+
+def test_subdomain_box_host_call(nvdb):
+    """The expert's normalisation box comes from the library (host arithmetic, no GPU):
+    the widened box of the oracle's decomposition, edge size + 2 halo."""
+    from oracle import moe
+    for origin, size, halo, cell in (((0, 0, 0), 256, 8, (1, 0, 1)), ((-40, 7, 1000), 64, 8, (-3, 2, 0)),
+                                     ((5, -9, 3), 2048, 16, (0, -1, 4))):
+        lo, d = nvdb.subdomain_box(origin, size, halo, cell)
+        olo, od = moe.widened_box(np.asarray(cell), np.asarray(origin), size, halo)
+        assert list(lo) == [int(a) for a in olo] and d == od == size + 2 * halo
+    with pytest.raises(nvdb.NvdbError):
+        nvdb.subdomain_box((0, 0, 0), 8, 8, (0, 0, 0))  # size < 2 halo
+    with pytest.raises(nvdb.NvdbError):
+        nvdb.subdomain_box((0, 0, 0), 1 << 20, 8, (1 << 12, 0, 0))  # corner beyond 2^30

@@ -1,22 +1,23 @@
 """GPU parity: the HIP path (through the C-ABI) against the FP64 oracle on the
 same seeded inputs.
 
-Tolerances (derived from the arithmetic of each form):
+Tolerances (derived from the arithmetic of each form, set a few times above
+the errors measured on the device, which NVDB_RECORD=<file> records):
   * integer work (tree arrays, sample indices, mask bits away from the decision
     boundary): bit-exact;
-  * FP32 form: forward |dy| <= 1e-5 (1 + |y|); gradients <= 1e-5 relative (L2)
-    per layer; values after a short fit <= 1e-3 relative (Adam amplifies the
-    last-bit differences of near-zero gradients);
-  * BF16 form: forward |dy| <= 2e-2 (outputs are in normalised units, |y| <~ 1);
-    gradients <= 0.2 relative per layer with cosine >= 0.98 (an FP64 computation
-    that rounds the same operands to bf16 lands at 0.06-0.09 on these cases).
+  * FP32 form: forward |dy| <= 1e-6 (1 + |y|); gradients element-wise per
+    tensor (W_l and b_l apart) max |dg| <= 3e-6 max |g|; losses of short fits
+    1e-5 relative, parameters in aggregate (Adam amplifies the last-bit
+    differences of near-zero gradients);
+  * BF16 form: against the FP64 oracle and, tighter, against its BF16 form
+    (oracle/bf16.py), see the constants below.
 """
 import numpy as np
 import pytest
 import torch
 
 import workloads
-from oracle import fit as F, mlp, sampler as S, tree as T
+from oracle import bf16 as bf16_form, fit as F, mlp, sampler as S, tree as T
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -27,6 +28,27 @@ SHAPES = [  # (W, H, n_freq, n_out, net id)
     (128, 3, 64, 1, 1),
     (64, 4, 64, 3, 2),
 ]
+
+
+# BF16 form against the FP64 oracle (operands carry 8 significant bits, unit
+# roundoff 2^-9): forward |dy| / (1 + |y|); gradients of random cotangents
+# per tensor, max |dg| / max |g| (heavy cancellation: an FP64 computation that
+# rounds the same operands to bf16 lands near the same values).
+BF16_FWD_TOL = 2e-3  # measured <= 5.9e-4 against the FP64 oracle
+BF16_RAND_GRAD_TOL = 0.5  # measured <= 0.2 against the FP64 oracle (cancellation)
+C4_BF16_TOL = 3e-2  # measured 1.0e-2 against the FP64 oracle
+C4_BF16_FORM_TOL = 3e-3  # measured 8.8e-4 (2^22 samples of PE features)
+# Against the BF16 form of the oracle (oracle/bf16.py: the same operands rounded to
+# bfloat16, exact sums) the differences come from float32 sums, float32 phases and
+# the hardware sine deciding the bfloat16 code of an encoded feature differently
+# from float64 now and then (one code step, 2^-8 relative, of one input).  Phases of
+# positional encoding stay below 2^5 revolutions, so such flips are rare: measured
+# forward <= 2e-4, gradients of random cotangents <= 1.4e-4 of the tensor maximum
+# (4e-7 where no flip occurred).  Fourier features with sigma 10 have phases of tens
+# of revolutions whose float32 rounding flips about one code in a hundred: measured
+# forward <= 3e-4, gradients of random cotangents (strong cancellation) <= 5e-2.
+BF16_FORM_FWD_TOL = {"pe": 1e-3, "ffm": 1e-3}
+BF16_FORM_GRAD_TOL = {"pe": 1e-3, "ffm": 0.1}
 
 
 def enc_matrix(m, seed):
@@ -48,6 +70,18 @@ def layer_rel_errors(g, go, shapes):
     offs = np.cumsum([0] + [o * i + o for o, i in shapes])
     return [float(np.linalg.norm(g[a:b] - go[a:b]) / max(np.linalg.norm(go[a:b]), 1e-30))
             for a, b in zip(offs[:-1], offs[1:])]
+
+
+def tensor_errors(g, go, shapes):
+    """Element-wise error of every parameter tensor (W_l and b_l separately):
+    max_i |g_i - go_i| / max_i |go_i| over the tensor's elements."""
+    out, a = [], 0
+    for o, i in shapes:
+        for n in (o * i, o):
+            d, r = g[a:a + n], go[a:a + n]
+            out.append(float(np.max(np.abs(d - r)) / max(np.max(np.abs(r)), 1e-30)))
+            a += n
+    return out
 
 
 # --------------------------------------------------------------------------- sampler
@@ -200,16 +234,22 @@ def test_tree_rejects_nan(gpu_lib):
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("shape", SHAPES, ids=["%dx%d_m%d_c%d" % s[:4] for s in SHAPES])
 @pytest.mark.parametrize("n", [1, 33, 1000, 4097])
-def test_forward_parity(gpu_lib, prec, shape, n):
+def test_forward_parity(gpu_lib, record, prec, shape, n):
     p = gpu_lib.FP32 if prec == "fp32" else gpu_lib.BF16
     model, theta, B, shapes = model_for(gpu_lib, shape, p)
     x = np.random.default_rng(n).random((n, 3)).astype(np.float32)
-    y = model.forward(shape[4], torch.from_numpy(x).to(DEV)).cpu().numpy()
+    y = model.forward_coords(shape[4], torch.from_numpy(x).to(DEV)).cpu().numpy()
     yo = mlp.predict(mlp.unflatten(theta, shapes), x.astype(np.float64), B)
+    err = float(np.max(np.abs(y - yo) / (1 + np.abs(yo))))
     if p == gpu_lib.FP32:
-        assert np.all(np.abs(y - yo) <= 1e-5 * (1 + np.abs(yo)))
+        record("forward_%s_%dx%d_n%d" % (prec, shape[0], shape[1], n), err=err)
+        assert err <= 1e-6
     else:
-        assert np.max(np.abs(y - yo)) <= 2e-2
+        yb, _ = bf16_form.forward_bf16(mlp.unflatten(theta, shapes), mlp.encode(x.astype(np.float64), B))
+        err_b = float(np.max(np.abs(y - yb) / (1 + np.abs(yb))))
+        record("forward_%s_%dx%d_n%d" % (prec, shape[0], shape[1], n), err=err, err_bf16_form=err_b)
+        assert err <= BF16_FWD_TOL
+        assert err_b <= BF16_FORM_FWD_TOL["pe" if shape[2] == 18 else "ffm"]
 
 
 def away_from_kinks(theta, shapes, B, x, margin):
@@ -224,7 +264,7 @@ def away_from_kinks(theta, shapes, B, x, margin):
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("shape", SHAPES, ids=["%dx%d_m%d_c%d" % s[:4] for s in SHAPES])
 @pytest.mark.parametrize("n", [77, 3000])
-def test_backward_parity(gpu_lib, prec, shape, n):
+def test_backward_parity(gpu_lib, record, prec, shape, n):
     p = gpu_lib.FP32 if prec == "fp32" else gpu_lib.BF16
     model, theta, B, shapes = model_for(gpu_lib, shape, p)
     rng = np.random.default_rng(n + 5)
@@ -234,23 +274,32 @@ def test_backward_parity(gpu_lib, prec, shape, n):
     x = x[:n]
     assert len(x) == n
     gy = rng.standard_normal((n, shape[3])).astype(np.float32)
-    g = model.backward(shape[4], torch.from_numpy(x).to(DEV), torch.from_numpy(gy).to(DEV)).cpu().numpy()
+    model.reserve_dev(shape[4], n)
+    g = model.backward_coords(shape[4], torch.from_numpy(x).to(DEV), torch.from_numpy(gy).to(DEV)).cpu().numpy()
     go = F.param_grad(theta, shapes, B, x.astype(np.float64), gy.astype(np.float64))
-    errs = layer_rel_errors(g.astype(np.float64), go, shapes)
+    errs = tensor_errors(g.astype(np.float64), go, shapes)
+    lerrs = layer_rel_errors(g.astype(np.float64), go, shapes)
     if p == gpu_lib.FP32:
-        assert max(errs) <= 1e-5, errs
+        record("backward_%s_%dx%d_n%d" % (prec, shape[0], shape[1], n), elem=max(errs), layer_l2=max(lerrs))
+        assert max(errs) <= 3e-6, errs
     else:
-        assert max(errs) <= 0.2, errs
-        cos = float(g @ go / (np.linalg.norm(g) * np.linalg.norm(go)))
-        assert cos >= 0.98
+        params = mlp.unflatten(theta, shapes)
+        _, cb = bf16_form.forward_bf16(params, mlp.encode(x.astype(np.float64), B))
+        gb = mlp.flatten(bf16_form.backward_bf16(params, cb, gy.astype(np.float64)))
+        errs_b = tensor_errors(g.astype(np.float64), gb, shapes)
+        record("backward_%s_%dx%d_n%d" % (prec, shape[0], shape[1], n), elem=max(errs), layer_l2=max(lerrs),
+               elem_bf16_form=max(errs_b), l2_bf16_form=max(layer_rel_errors(g.astype(np.float64), gb, shapes)))
+        assert max(errs) <= BF16_RAND_GRAD_TOL, errs
+        assert max(errs_b) <= BF16_FORM_GRAD_TOL["pe" if shape[2] == 18 else "ffm"], errs_b
 
 
 def test_backward_deterministic(gpu_lib):
     model, theta, B, shapes = model_for(gpu_lib, SHAPES[1], gpu_lib.BF16)
     x = torch.rand(50000, 3, device=DEV, generator=torch.Generator(DEV).manual_seed(3))
     gy = torch.randn(50000, 1, device=DEV, generator=torch.Generator(DEV).manual_seed(4))
-    a = model.backward(0, x, gy)
-    b = model.backward(0, x, gy)
+    model.reserve_dev(0, 50000)
+    a = model.backward_coords(0, x, gy)
+    b = model.backward_coords(0, x, gy)
     assert torch.equal(a, b)
 
 
@@ -588,9 +637,11 @@ def test_c2_decode_sampled(gpu_lib, c2, prec):
 
 # --------------------------------------------------------------------------- C4 gradient check
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_c4_gradient_batch_2_22(gpu_lib, sphere, prec):
+def test_c4_gradient_batch_2_22(gpu_lib, sphere, record, prec):
     """Fused backward behind torch.autograd.Function at batch 2^22 (i.i.d. voxel samples
-    of the C1 volume, MSE loss) against the oracle's analytic gradient."""
+    of the C1 volume, MSE loss, the samples gathered and normalised in the kernel from
+    their population indices) against the oracle's analytic gradient, per tensor and
+    element-wise, and on 256 sampled weights (seed 0)."""
     tr, ot = sphere
     p = gpu_lib.FP32 if prec == "fp32" else gpu_lib.BF16
     shapes = mlp.layer_shapes(36, 64, 3, 1)
@@ -600,15 +651,17 @@ def test_c4_gradient_batch_2_22(gpu_lib, sphere, prec):
     model.set_params(0, th)
     model.set_encoding(0, B)
     n = 1 << 22
+    model.reserve_dev(0, n)
     idx = S.iid_indices(0, 0, 0, n, len(ot["values"]))
     x, t = F.net_inputs(ot, "regressor", idx, (0, 0, 0), 64, T.SDF, 3.0)
-    xd = torch.from_numpy(x.astype(np.float32)).to(DEV)
+    idx_d = torch.from_numpy(idx.astype(np.int32)).to(DEV)
     td = torch.from_numpy(t.astype(np.float32)).to(DEV)
     Fn = gpu_lib.mlp_function()
-    theta = torch.zeros(len(th), device=DEV, requires_grad=True)
-    y = Fn.apply(model, 0, xd, theta)
+    theta = torch.from_numpy(th).to(DEV).requires_grad_(True)
+    y = Fn.apply(model, 0, tr, idx_d, theta)
     loss = ((y[:, 0] - td) ** 2).mean()
     loss.backward()
+    assert model.take_errors() == 0
     g = theta.grad.cpu().numpy().astype(np.float64)
     # oracle: the same gradient in FP64, accumulated over chunks
     thd = th.astype(np.float64)
@@ -619,8 +672,23 @@ def test_c4_gradient_batch_2_22(gpu_lib, sphere, prec):
         yo, cache = mlp.forward(params, mlp.encode(xi, B.astype(np.float64)))
         gy = 2.0 * (yo[:, 0] - ti)[:, None] / n
         go += mlp.flatten(mlp.backward(params, cache, gy))
-    errs = layer_rel_errors(g, go, shapes)
-    assert max(errs) <= (1e-4 if p == gpu_lib.FP32 else 5e-2), errs
+    errs = tensor_errors(g, go, shapes)
+    pick = np.random.default_rng(0).choice(len(thd), 256, replace=False)
+    rel = np.abs(g[pick] - go[pick]) / np.maximum(np.abs(go[pick]), 1e-12)
+    extra = {}
+    if p == gpu_lib.BF16:
+        # the BF16 form of the oracle on the same batch
+        gb = np.zeros_like(thd)
+        for i in range(0, n, 1 << 18):
+            xi, ti = x[i:i + (1 << 18)], t[i:i + (1 << 18)]
+            yb, cb = bf16_form.forward_bf16(params, mlp.encode(xi, B.astype(np.float64)))
+            gb += mlp.flatten(bf16_form.backward_bf16(params, cb, 2.0 * (yb[:, 0] - ti)[:, None] / n))
+        extra["elem_bf16_form"] = max(tensor_errors(g, gb, shapes))
+    record("c4_%s" % prec, elem=max(errs), layer_l2=max(layer_rel_errors(g, go, shapes)),
+           sampled_max_rel=float(np.max(rel)), sampled_median_rel=float(np.median(rel)), **extra)
+    assert max(errs) <= (3e-6 if p == gpu_lib.FP32 else C4_BF16_TOL), errs
+    if p == gpu_lib.BF16:
+        assert extra["elem_bf16_form"] <= C4_BF16_FORM_TOL, extra
 
 
 # --------------------------------------------------------------------------- warm-start sequence (Sec. 3.6)
