@@ -1299,6 +1299,45 @@ nvdb_status nvdb_query(const nvdb_model* m, const nvdb_tree* tree, const float* 
   });
 }
 
+nvdb_status nvdb_query_noalloc(const nvdb_model* m, const nvdb_tree* tree, const float* q_dev, int64_t n,
+                               float background, int64_t batch, float* values_dev, uint8_t* hits_dev, void* stream) {
+  return guarded([&] {
+    NVDB_REQUIRE(m && tree, NVDB_E_INVALID, "null argument");
+    NVDB_REQUIRE(n >= 0 && (n == 0 || (q_dev && values_dev)), NVDB_E_INVALID, "bad buffers");
+    NVDB_REQUIRE(n < (1ll << 31), NVDB_E_INVALID, "bad query count");
+    NVDB_REQUIRE(batch >= 0 && batch <= QUERY_NOALLOC_MAX_BATCH, NVDB_E_INVALID,
+                 "batch must be in 0..65536 (the static scratch holds one batch)");
+    NVDB_REQUIRE(std::isfinite(background), NVDB_E_INVALID, "background must be finite");
+    const Net& N = net_of(m, NVDB_NET_REGRESSOR);
+    NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "regressor parameters or encoding not set");
+    if (n == 0) return;
+    hipStream_t st = (hipStream_t)stream;
+    const QueryScratch qs = query_noalloc_scratch();
+    const int64_t bs = std::min<int64_t>(batch > 0 ? batch : QUERY_NOALLOC_MAX_BATCH, n);
+    const float inv_d = 1.f / (float)m->d.domain_size;
+    // batches run one after the other on `stream` and reuse the same scratch
+    for (int64_t b0 = 0; b0 < n; b0 += bs) {
+      const int64_t nb = std::min(bs, n - b0);
+      query_zero_count(qs.cnt, st);
+      query_classify(q_dev + 3 * b0, nb, *tree, background, m->d.domain_lo, inv_d, values_dev + b0,
+                     hits_dev ? hits_dev + b0 : nullptr, qs.hit_x, qs.hit_idx, qs.cnt, st);
+      InferLaunch I{};
+      I.net = net_view(N);
+      base_spec(m, &I.spec);
+      I.spec.src = SRC_COORDS;
+      I.spec.direct = 1;
+      I.spec.coords = qs.hit_x;
+      I.spec.n = nb;
+      I.spec.n_dev = qs.cnt;
+      I.out_kind = OUT_Y;
+      I.y = qs.y;
+      launch_infer(N.ks, I, infer_grid(nb), st);
+      query_scatter(qs.y, qs.hit_idx, nb, qs.cnt, m->d.value_scale, values_dev + b0, st);
+    }
+    mark(m, st);
+  });
+}
+
 nvdb_status nvdb_topology_patches(const nvdb_tree* truth, const nvdb_tree* pred, int32_t* fp_dev, int64_t fp_cap,
                                   int32_t* fn_dev, int64_t fn_cap, int64_t* n_fp, int64_t* n_fn, void* stream) {
   return guarded([&] {

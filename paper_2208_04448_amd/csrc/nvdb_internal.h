@@ -273,6 +273,16 @@ void query_classify(const float* q, int64_t n, const Tree& tree, float backgroun
 void query_scatter(const float* y, const uint32_t* idx, int64_t n, const uint32_t* n_hits, float scale, float* values,
                    hipStream_t st);
 void query_zero_count(uint32_t* c, hipStream_t st);
+// Device addresses of the static scratch of the allocation-free random access on
+// the current device (looked up once per device).
+constexpr int64_t QUERY_NOALLOC_MAX_BATCH = 1 << 16;
+struct QueryScratch {
+  float* hit_x;       // [max batch][3]
+  float* y;           // [max batch]
+  uint32_t* hit_idx;  // [max batch]
+  uint32_t* cnt;      // [1]
+};
+QueryScratch query_noalloc_scratch();
 // voxels of a that b lacks, canonical order, at most cap written to out [cap][3]; returns the count
 int64_t topology_patches(const Tree& a, const Tree& b, int32_t* out, int64_t cap, hipStream_t st);
 // sparse.hip

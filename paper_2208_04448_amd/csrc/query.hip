@@ -9,10 +9,44 @@
 // patches of a decoded topology (voxels it adds or misses).
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 
 #include "nvdb_internal.h"
 
 namespace nvdb {
+
+// Scratch of the allocation-free random access (nvdb_query_noalloc), one copy
+// per GPU for the life of the process: per query of a batch of at most
+// QUERY_NOALLOC_MAX_BATCH its normalised position (3 floats), regressor output
+// and query index, then the hit counter.  In host code `scratch` names a host
+// stand-in, never the device memory: kernels get the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t QS_X = 0;
+constexpr size_t QS_Y = QS_X + 12 * (size_t)QUERY_NOALLOC_MAX_BATCH;
+constexpr size_t QS_IDX = QS_Y + 4 * (size_t)QUERY_NOALLOC_MAX_BATCH;
+constexpr size_t QS_CNT = QS_IDX + 4 * (size_t)QUERY_NOALLOC_MAX_BATCH;
+constexpr size_t QS_BYTES = QS_CNT + 256;
+static __device__ __align__(256) char scratch[QS_BYTES];
+
+QueryScratch query_noalloc_scratch() {
+  static std::mutex mu;
+  static std::map<int, char*> base;  // device -> address of its copy of `scratch`
+  int dev = 0;
+  NVDB_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(mu);
+  char*& p = base[dev];
+  if (!p) {
+    void* a = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !a) {
+      base.erase(dev);
+      throw Error(NVDB_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    p = (char*)a;
+  }
+  return QueryScratch{(float*)(p + QS_X), (float*)(p + QS_Y), (uint32_t*)(p + QS_IDX), (uint32_t*)(p + QS_CNT)};
+}
 
 namespace {
 

@@ -133,6 +133,7 @@ _SIGS = {
     "nvdb_model_take_errors": (C.c_int32, [_P, C.POINTER(C.c_int64)]),
     "nvdb_subdomain_box": (C.c_int32, [C.POINTER(Subdomains), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                        C.POINTER(C.c_int32)]),
+    "nvdb_query_noalloc": (C.c_int32, [_P, _P, _P, C.c_int64, C.c_float, C.c_int64, _P, _P, _P]),
     "nvdb_sample_indices_dev": (C.c_int32, [C.c_uint64, C.c_int32, C.c_int64, C.c_int64, C.c_int64, _P, _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -402,6 +403,19 @@ class Model:
         h = torch.empty(n, dtype=torch.uint8, device=q.device) if return_hits else None
         _check(_lib.nvdb_query(self.h, tree.h, _ptr(q), n, float(background), int(batch), _ptr(v), _ptr(h), _stream()))
         return (v, h) if return_hits else v
+
+    def query_noalloc(self, tree, q, background, batch=0, values=None, hits=None):
+        """nvdb_query_noalloc: the random access with no device allocation inside the
+        library (static per-GPU scratch, batches of at most 65536).  Output tensors
+        may be passed in; returns (values, hits)."""
+        import torch
+        q = q.contiguous().reshape(-1, 3)
+        assert q.is_cuda and q.dtype == torch.float32
+        n = q.shape[0]
+        v = values if values is not None else torch.empty(n, dtype=torch.float32, device=q.device)
+        _check(_lib.nvdb_query_noalloc(self.h, tree.h, _ptr(q), n, float(background), int(batch), _ptr(v), _ptr(hits),
+                                       _stream()))
+        return v, hits
 
     def reserve_dev(self, net, max_n):
         """Workspace for forward/backward calls of up to max_n samples (allocates once)."""
