@@ -11,7 +11,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnvdb.so")
-SOURCES = ["mlp.hip", "tree.hip", "sparse.hip", "query.hip", "moe.hip", "api.hip"]
+SOURCES = ["mlp.hip", "train_rows.hip", "tree.hip", "sparse.hip", "query.hip", "moe.hip", "api.hip"]
+# Per-source code generation: the activation-rows training kernel puts matrix-product
+# results in general-purpose vector registers (its weight gradients are pinned to the
+# accumulation registers by operand constraints).
+EXTRA = {"train_rows.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -29,7 +33,7 @@ def _run(cmd):
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
     objs = [os.path.join(BUILD, s.replace(".hip", ".o")) for s in SOURCES]
-    cmds = [[HIPCC] + FLAGS + ["-c", os.path.join(CSRC, s), "-o", o] for s, o in zip(SOURCES, objs)]
+    cmds = [[HIPCC] + FLAGS + EXTRA.get(s, []) + ["-c", os.path.join(CSRC, s), "-o", o] for s, o in zip(SOURCES, objs)]
     with ThreadPoolExecutor(len(cmds)) as ex:
         outs = list(ex.map(_run, cmds))
     tmp = LIB + ".tmp"

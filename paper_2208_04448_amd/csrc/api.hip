@@ -2,6 +2,7 @@
 // The arithmetic lives in mlp.hip (networks) and tree.hip (tree build, errors).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <cfloat>
 #include <limits>
@@ -305,6 +306,8 @@ nvdb_status nvdb_model_create(const nvdb_model_desc* desc, nvdb_model** out) {
                      "no kernel for this network shape (width " + std::to_string(d.width) + ", hidden " +
                          std::to_string(d.hidden) + ", inputs " + std::to_string(n.s.KP) + ", outputs " +
                          std::to_string(d.n_out) + ")");
+        if (n.prec == NVDB_BF16 && d.n_freq == 64 && n.ks.train_rows && !std::getenv("NVDB_TRAIN_CLASSIC"))
+          n.ks.train = n.ks.train_rows;
         const int64_t P = n.s.nparams();
         n.theta.alloc(P);
         n.m.alloc(P);

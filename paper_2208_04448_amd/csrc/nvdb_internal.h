@@ -245,6 +245,9 @@ struct KernelSet {
   void (*infer)(InferLaunch);
   int train_lds, infer_lds;
   void (*infer8)(InferLaunch);  // FP8 form of the forward pass
+  // BF16 training kernel keeping activations as LDS rows (128-wide networks on 64
+  // Fourier features, one output), or null
+  void (*train_rows)(TrainLaunch);
 };
 // Bytes of the e4m3 weight fragments of all hidden layers (the FP8 form).
 // Elements of the bf16 fragment copies: all layers (forward), layers 1..H-1 (transposed).
@@ -252,6 +255,9 @@ __host__ __device__ inline int64_t wfrag_elems(const NetShape& s) { return (int6
 __host__ __device__ inline int64_t wtfrag_elems(const NetShape& s) { return (int64_t)(s.H - 1) * s.W * s.W; }
 __host__ __device__ inline int64_t fp8_weight_bytes(const NetShape& s) { return (int64_t)s.W * s.KP + (int64_t)(s.H - 1) * s.W * s.W; }
 
+// train_rows.hip: the BF16 training kernel of the 128-wide networks keeping
+// activations as LDS rows (H hidden layers), or null
+void (*train_rows_kernel(int H))(TrainLaunch);
 // mlp.hip
 bool find_kernels(int prec, int W, int H, int KP, int C, KernelSet* out);
 void launch_quant_fp8(const NetShape& s, const float* theta, char* w8, float* w8inv, hipStream_t st);
