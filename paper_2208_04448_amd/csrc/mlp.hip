@@ -35,21 +35,22 @@ struct TrainCfg {
   // fold each iteration's contribution into the work-group's partial row in HBM.
   static constexpr bool DWREG = (PREC == NVDB_BF16);
   // BF16: where the weight fragments of layers 1..H-1 come from (HBM/L2 or the LDS copy)
-  static constexpr bool FWD_GLOBAL = NVDB_TRAIN_FWD_GLOBAL != 0;
-  static constexpr bool DX_GLOBAL = NVDB_TRAIN_DX_GLOBAL != 0;
+  // (forward fragments from HBM/L2 were measured 5 % faster per step than from the
+  // LDS copy)
+  static constexpr bool FWD_GLOBAL = true;
   // BF16: the forward pass as one software pipeline over all layers (two block
   // pairs per layer or more)
-  static constexpr bool FWD_CHAIN = (PREC == NVDB_BF16) && NVDB_TRAIN_FWD_CHAIN != 0 && W >= 128;
+  static constexpr bool FWD_CHAIN = (PREC == NVDB_BF16) && W >= 128;
   // (measured on the 4x128 network: all but layer 0 resident is fastest; its few
   // spills cost less than folding another layer per tile, while holding layer 0
   // as well spills far more)
-  static constexpr int DWREG_FROM = (W >= 128) ? NVDB_DWREG_FROM : 0;
+  static constexpr int DWREG_FROM = (W >= 128) ? 1 : 0;
   static constexpr bool reg_layer(int l) { return DWREG && l >= DWREG_FROM; }
   // BF16 4x128 with layers 1.. resident: layer 0's dW accumulates in LDS (a
   // wave-private fp32 region) instead of the partial row; the dX products then
   // read their weight fragments from HBM/L2, which frees the LDS weight copy.
-  static constexpr bool DW0_LDS = DWREG && NVDB_TRAIN_DW0_LDS != 0 && W >= 128 && DWREG_FROM == 1;
-  static constexpr bool DX_HBM = DX_GLOBAL || DW0_LDS;
+  static constexpr bool DW0_LDS = DWREG && W >= 128 && DWREG_FROM == 1;
+  static constexpr bool DX_HBM = DW0_LDS;
   static constexpr bool lds_layer(int l) { return DW0_LDS && l == 0; }
   static constexpr bool fold_layer(int l) { return !reg_layer(l) && !lds_layer(l); }
   static constexpr bool any_rmw = !DWREG || DWREG_FROM > (DW0_LDS ? 1 : 0);
@@ -441,8 +442,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
       if constexpr (l > 0) {
         // g_l = (W_l^T g_{l+1}) * 1[a_l > 0]
         WBwd<PREC, W> wb_p{wl + (size_t)(l - 1) * W * 256,
-                           (const float*)nv.wrow + z + (size_t)W * KP + (size_t)(l - 1) * W * W,
-                           (const u32x4*)((const __bf16*)nv.wtfrag + (size_t)(l - 1) * W * W) + z, CF::DX_GLOBAL, &K};
+                           (const float*)nv.wrow + z + (size_t)W * KP + (size_t)(l - 1) * W * W, &K};
         const WBwdBuf<W> wb_b{raw_rsrc(nv.wtfrag, BF ? wtfrag_elems(nv.s) * 2 : 0), z + (l - 1) * W * W * 2,
                               lane_id() * 16};
         uint32_t Gn[NB][SR];
@@ -550,20 +550,19 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
 // ============================================================== inference kernel
 template <int PREC, int W, int H, int KP, int C>
 struct InferCfg {
-  static constexpr int NT = (PREC == NVDB_BF16) ? NVDB_INFER_NT : 1;  // 32-sample tiles per wave sharing each weight fragment
-  static constexpr int WAVES = NVDB_INFER_WAVES;          // waves per work-group (one LDS copy of the weights)
-  static constexpr bool GLOBAL = (PREC == NVDB_BF16) && NVDB_INFER_GLOBAL != 0;  // fragments from HBM, no LDS copy
+  static constexpr int NT = (PREC == NVDB_BF16) ? INFER_NT : 1;  // 32-sample tiles per wave sharing each weight fragment
+  static constexpr int WAVES = INFER_WAVES;          // waves per work-group (one LDS copy of the weights)
   // Each 32-row block of the weight copy is followed by 64 pad bytes: a lane's reads of
   // two blocks 8192 bytes apart would hit the same banks when fetched together.
   static constexpr int BSTRIDE = 32 * 256 + 64;
-  static constexpr int WL_BYTES = (PREC == NVDB_BF16 && !GLOBAL) ? H * (W / 32) * BSTRIDE : 0;
+  static constexpr int WL_BYTES = (PREC == NVDB_BF16) ? H * (W / 32) * BSTRIDE : 0;
   static constexpr int SMALL_FLOATS = H * W + C * W + 4 + 4 * (KP / 2);
   static constexpr int LDS_BYTES = WL_BYTES + SMALL_FLOATS * 4;
 };
 
 template <int PREC, int W, int H, int KP, int C>
-__global__ void __launch_bounds__(64 * NVDB_INFER_WAVES, 1)
-    __attribute__((amdgpu_waves_per_eu(NVDB_INFER_WAVES / 4, NVDB_INFER_WAVES / 4))) k_infer(InferLaunch I) {
+__global__ void __launch_bounds__(64 * INFER_WAVES, 1)
+    __attribute__((amdgpu_waves_per_eu(INFER_WAVES / 4, INFER_WAVES / 4))) k_infer(InferLaunch I) {
   using P = PR<PREC>;
   using CF = InferCfg<PREC, W, H, KP, C>;
   constexpr int NB = W / 32, NIB0 = KP / 32, SR = P::SR, NT = CF::NT;
@@ -580,7 +579,7 @@ __global__ void __launch_bounds__(64 * NVDB_INFER_WAVES, 1)
   float* sm_whead0 = sm_bias0 + H * W;
   float* sm_bhead0 = sm_whead0 + C * W;
   float* sm_benc0 = sm_bhead0 + 4;
-  if constexpr (BF && !CF::GLOBAL) {
+  if constexpr (BF) {
     const u32x4* src = (const u32x4*)nv.wrow;
     for (int i = threadIdx.x; i < H * W * 16; i += blockDim.x) {  // 16-byte pieces of the 256-byte rows
       const int row = i >> 4, blk = row >> 5;
@@ -628,7 +627,7 @@ __global__ void __launch_bounds__(64 * NVDB_INFER_WAVES, 1)
       constexpr int NIBl = (l == 0) ? NIB0 : NB;
       WFwd<PREC, W, NIBl> wf{wl + (size_t)l * (W / 32) * CF::BSTRIDE,
                              (const u32x4*)((const __bf16*)nv.wfrag + (l == 0 ? 0 : (size_t)W * KP + (size_t)(l - 1) * W * W)) + z,
-                             (const float*)nv.wcol + z + (l == 0 ? 0 : (size_t)KP * W + (size_t)(l - 1) * W * W), CF::GLOBAL,
+                             (const float*)nv.wcol + z + (l == 0 ? 0 : (size_t)KP * W + (size_t)(l - 1) * W * W), false,
                              &K, CF::BSTRIDE};
       uint32_t Bn[NT][NB][SR];
 #pragma unroll
@@ -787,8 +786,8 @@ __global__ void __launch_bounds__(256) k_fp8_pack(NetShape s, const float* theta
 
 template <int W, int H, int KP, int C>
 struct Infer8Cfg {
-  static constexpr int NT = NVDB_INFER8_NT;
-  static constexpr int WAVES = NVDB_INFER8_WAVES;
+  static constexpr int NT = INFER8_NT;
+  static constexpr int WAVES = INFER8_WAVES;
   static constexpr int WL_BYTES = W * KP + (H - 1) * W * W;
   static constexpr int SMALL_FLOATS = H * W + C * W + 4 + 4 * (KP / 2) + 4;
   static constexpr int LDS_BYTES = WL_BYTES + SMALL_FLOATS * 4;
@@ -861,8 +860,8 @@ __device__ __forceinline__ void write_outputs(const InferLaunch& I, const float 
 }
 
 template <int W, int H, int KP, int C>
-__global__ void __launch_bounds__(64 * NVDB_INFER8_WAVES, NVDB_INFER8_WGS)
-    __attribute__((amdgpu_waves_per_eu(NVDB_INFER8_WAVES / 4 * NVDB_INFER8_WGS, NVDB_INFER8_WAVES / 4 * NVDB_INFER8_WGS)))
+__global__ void __launch_bounds__(64 * INFER8_WAVES, INFER8_WGS)
+    __attribute__((amdgpu_waves_per_eu(INFER8_WAVES / 4 * INFER8_WGS, INFER8_WAVES / 4 * INFER8_WGS)))
     k_infer_fp8(InferLaunch I) {
   using CF = Infer8Cfg<W, H, KP, C>;
   constexpr int NB = W / 32, NIB0 = KP / 32, NT = CF::NT;
@@ -1202,7 +1201,7 @@ void launch_train(const KernelSet& ks, const TrainLaunch& L, int n_nets, hipStre
   NVDB_HIP(hipGetLastError());
 }
 void launch_infer(const KernelSet& ks, const InferLaunch& I, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(ks.infer, dim3(grid), dim3(64 * NVDB_INFER_WAVES), 0, st, I);
+  hipLaunchKernelGGL(ks.infer, dim3(grid), dim3(64 * INFER_WAVES), 0, st, I);
   NVDB_HIP(hipGetLastError());
 }
 void launch_reduce_adam(const AdamLaunch& A, int64_t max_p, int n_nets, hipStream_t st) {
@@ -1239,7 +1238,7 @@ void launch_quant_fp8(const NetShape& s, const float* theta, char* w8, float* w8
   NVDB_HIP(hipGetLastError());
 }
 void launch_infer8(const KernelSet& ks, const InferLaunch& I, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(ks.infer8, dim3(grid), dim3(64 * NVDB_INFER8_WAVES), 0, st, I);
+  hipLaunchKernelGGL(ks.infer8, dim3(grid), dim3(64 * INFER8_WAVES), 0, st, I);
   NVDB_HIP(hipGetLastError());
 }
 void launch_fill(float* p, int64_t n, float v, hipStream_t st) {

@@ -6,53 +6,24 @@
 #include "nvdb_internal.h"
 
 
-// Waves per decode work-group: eight waves (two per SIMD) share one LDS copy of
-// the weights, so one wave's conversions overlap the other's matrix products.
-// Training forward products read their BF16 weight fragments from HBM (L2/L1
-// resident) rather than from the LDS copy: measured 5 % faster per step; the
-// input-gradient products keep the transposing LDS reads (from HBM they were
-// 45 % slower).
-#ifndef NVDB_TRAIN_FWD_GLOBAL
-#define NVDB_TRAIN_FWD_GLOBAL 1
-#endif
-#ifndef NVDB_INFER_GLOBAL
-#define NVDB_INFER_GLOBAL 0
-#endif
-#ifndef NVDB_DWREG_FROM
-#define NVDB_DWREG_FROM 1
-#endif
-#ifndef NVDB_TRAIN_FWD_CHAIN
-#define NVDB_TRAIN_FWD_CHAIN 1
-#endif
-#ifndef NVDB_TRAIN_DW0_LDS
-#define NVDB_TRAIN_DW0_LDS 1
-#endif
-#ifndef NVDB_TRAIN_DX_GLOBAL
-#define NVDB_TRAIN_DX_GLOBAL 0
-#endif
-#ifndef NVDB_ROWS_FWD_PF
-#define NVDB_ROWS_FWD_PF 4
-#endif
-#ifndef NVDB_INFER_WAVES
-#define NVDB_INFER_WAVES 8
-#endif
-#ifndef NVDB_INFER_NT
-#define NVDB_INFER_NT 2
-#endif
-// FP8 decode: the e4m3 weights take 64 KiB of LDS, so two work-groups of eight
-// single-tile waves fit on a CU (four waves per SIMD).
-#ifndef NVDB_INFER8_WAVES
-#define NVDB_INFER8_WAVES 8
-#endif
-#ifndef NVDB_INFER8_NT
-#define NVDB_INFER8_NT 1
-#endif
-#ifndef NVDB_INFER8_WGS
-#define NVDB_INFER8_WGS 2
-#endif
-
-
 namespace nvdb {
+
+// Launch and pipeline constants, each chosen by measurement on the 512^3 level-set
+// workload.  Decode: eight waves per work-group (two per SIMD) share one LDS copy of
+// the weights, so one wave's conversions overlap the other's matrix products, each
+// wave two 32-sample tiles.  FP8 decode: the e4m3 weights take 64 KiB of LDS, so two
+// work-groups of eight single-tile waves fit on a CU (four waves per SIMD).
+// Activation-rows training kernel: forward weight fragments 4 steps ahead, input-
+// gradient fragments 2 steps ahead (deeper prefetch spills registers and is slower).
+constexpr int INFER_WAVES = 8;
+constexpr int INFER_NT = 2;
+constexpr int INFER8_WAVES = 8;
+constexpr int INFER8_NT = 1;
+constexpr int INFER8_WGS = 2;
+constexpr int ROWS_FWD_PF = 4;
+constexpr int ROWS_DX_PF = 2;
+
+
 
 // Lane index, opaque to the optimiser: swizzled LDS addresses are functions of the
 // lane, and without this the compiler hoists hundreds of them out of the
@@ -542,12 +513,9 @@ template <int PREC, int W>
 struct WBwd {
   const char* lds;
   const float* grow;    // fp32: [W][W] row-major
-  const u32x4* gtfrag;  // bf16: transposed fragments of this layer in HBM
-  bool global;          // bf16: read them from HBM instead of transposing from LDS
   const LaneK* K;
   __device__ __forceinline__ typename PR<PREC>::Frag operator()(int ib, int t, int kk) const {
     if constexpr (PREC == NVDB_BF16) {
-      if (global) return __builtin_bit_cast(bf16x8, gtfrag[((ib * (W / 32) + t) * 2 + kk) * 64 + 32 * K->h + K->fl]);
       return frag_tr(lds, *K, 32 * t + 16 * kk, ib);
     } else {
       return grow[(size_t)sfeat(t, kk, K->h) * W + 32 * ib + K->fl];

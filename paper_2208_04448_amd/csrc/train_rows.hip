@@ -81,7 +81,7 @@ __device__ __forceinline__ void forward_rows(const WBuf (&wf)[H], const uint32_t
   constexpr int NB = 4, KS = P::KS;
   using S = FwdSteps<4, NB, H>;
   constexpr int T = S::total();
-  constexpr int PF = NVDB_ROWS_FWD_PF;
+  constexpr int PF = ROWS_FWD_PF;
   P::Frag fa[PF], fb[PF];
   floatx16 acc[2][2];
   uint32_t Hs[2][NB][8];  // outputs of layers with even / odd index
@@ -106,12 +106,21 @@ __device__ __forceinline__ void forward_rows(const WBuf (&wf)[H], const uint32_t
     constexpr int g = decltype(gc)::value;
     if constexpr (g < T) fetch(gc, fa[g], fb[g]);
   });
+  // Accumulators start from the bias of their output features, loaded from LDS as
+  // soon as the previous user of the accumulator set has finished (its deferred
+  // epilogue), several steps before the first product reads them.
+  acc[0][0] = bias_acc(sm_bias, K, 0);
+  acc[0][1] = bias_acc(sm_bias, K, 1);
   static_for<0, T>([&](auto gc) {
     constexpr int g = decltype(gc)::value;
     constexpr int l = S::layer(g), p = S::pair(g), s = S::step(g), buf = S::gpair(g) & 1;
-    if constexpr (s == 0) {
-      acc[buf][0] = bias_acc(sm_bias + l * 128, K, 2 * p);
-      acc[buf][1] = bias_acc(sm_bias + l * 128, K, 2 * p + 1);
+    if constexpr (s == 0 && S::gpair(g) == 0) {
+      // the second accumulator set is free from the start
+      constexpr int gn = g + S::nsl(l);
+      if constexpr (gn < T) {
+        acc[buf ^ 1][0] = bias_acc(sm_bias + S::layer(gn) * 128, K, 2 * S::pair(gn));
+        acc[buf ^ 1][1] = bias_acc(sm_bias + S::layer(gn) * 128, K, 2 * S::pair(gn) + 1);
+      }
     }
     const P::Frag a0 = fa[g % PF], a1 = fb[g % PF];
     if constexpr (g + PF < T) fetch(IC<g + PF>{}, fa[g % PF], fb[g % PF]);
@@ -124,6 +133,12 @@ __device__ __forceinline__ void forward_rows(const WBuf (&wf)[H], const uint32_t
     if constexpr (s == S::DEFER - 1 && S::gpair(g) > 0) {
       constexpr int ge = g - S::DEFER;  // last step of the previous pair
       if constexpr (S::deferred(ge)) epilogue(IC<S::layer(ge)>{}, IC<S::pair(ge)>{}, acc[buf ^ 1][0], acc[buf ^ 1][1]);
+      // the set just released serves the pair after this one
+      constexpr int gn = g - s + S::nsl(l);  // first step of the next pair
+      if constexpr (gn < T) {
+        acc[buf ^ 1][0] = bias_acc(sm_bias + S::layer(gn) * 128, K, 2 * S::pair(gn));
+        acc[buf ^ 1][1] = bias_acc(sm_bias + S::layer(gn) * 128, K, 2 * S::pair(gn) + 1);
+      }
     }
     if constexpr (s == S::nsl(l) - 1 && !S::deferred(g)) epilogue(IC<l>{}, IC<p>{}, acc[buf][0], acc[buf][1]);
   });
@@ -180,9 +195,9 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b) dacc[l][a][b] = floatx16{};
-  float dbias[H][2];
+  float dbias[H][1];  // bias gradient of output block 2 wo + wi
 #pragma unroll
-  for (int l = 0; l < H; ++l) dbias[l][0] = dbias[l][1] = 0.f;
+  for (int l = 0; l < H; ++l) dbias[l][0] = 0.f;
   float dwh = 0.f, dbh = 0.f, loss_acc = 0.f;
 
   const int64_t n_iter = (sp.n + 127) / 128;
@@ -312,8 +327,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
         Bv[1] = frag_tr(arows + sl * CF::ROWS, K, 16 * kk, 2 * wi + 1);
       };
       auto dw_step = [&](const bf16x8 (&A)[2], const bf16x8 (&Bv)[2]) {
-        dbias[l][0] = frag_sum(A[0], dbias[l][0]);
-        dbias[l][1] = frag_sum(A[1], dbias[l][1]);
+        dbias[l][0] = frag_sum(wi ? A[1] : A[0], dbias[l][0]);
         mfma_dw4(dacc[l][0][0], dacc[l][0][1], dacc[l][1][0], dacc[l][1][1], A[0], A[1], Bv[0], Bv[1]);
       };
       dw_load(0, ga[0], hb[0]);
@@ -321,7 +335,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
         const WBuf wt{wt_rsrc, z + (l - 1) * W * W * 2, vo, NB};
         const char* own_a = arows + wave * CF::ROWS;
         uint32_t Gn[NB][8];
-        constexpr int PF = 4;
+        constexpr int PF = ROWS_DX_PF;
         bf16x8 fa[PF], fb[PF];
         // steps q = 0..15: pair p = q / 8 (input blocks 2p, 2p+1), k-step s = q % 8 of Gc
         auto wfetch = [&](int q, bf16x8& x, bf16x8& y2) {
@@ -332,6 +346,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
 #pragma unroll
         for (int q = 0; q < PF; ++q) wfetch(q, fa[q], fb[q]);
         floatx16 a0 = floatx16{}, a1 = floatx16{};
+        uint32_t m0[8], m1[8];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
           const int pp = q >> 3, ss = q & 7;
@@ -346,10 +361,11 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
             dw_step(ga[st & 1], hb[st & 1]);
           }
           __builtin_amdgcn_sched_barrier(0);
-          if (ss == 7) {
-            uint32_t m0[8], m1[8];
+          if (ss == 4) {  // the ReLU-derivative source of this pair, a few steps ahead
             read_row_block(own_a, K, 2 * pp, m0);
             read_row_block(own_a, K, 2 * pp + 1, m1);
+          }
+          if (ss == 7) {
             store_masked<NVDB_BF16>(a0, Gn[2 * pp], m0);
             store_masked<NVDB_BF16>(a1, Gn[2 * pp + 1], m1);
             a0 = floatx16{};
@@ -391,14 +407,12 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
         }
       }
   }
-  // biases: the wave of input column a owns output block 2 wo + a; lane halves combined
+  // biases: wave (wo, wi) owns output block 2 wo + wi; lane halves combined
 #pragma unroll
-  for (int l = 0; l < H; ++l)
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const float v = dbias[l][a] + shfl_xor32(dbias[l][a]);
-      if (a == wi && h == 0) partial[nv.s.boff(l) + 32 * (2 * wo + a) + fl] = v;
-    }
+  for (int l = 0; l < H; ++l) {
+    const float v = dbias[l][0] + shfl_xor32(dbias[l][0]);
+    if (h == 0) partial[nv.s.boff(l) + 32 * (2 * wo + wi) + fl] = v;
+  }
   {
     const float v = dwh + shfl_xor32(dwh);
     if (h == 0) partial[nv.s.woff(H) + 32 * wave + fl] = v;

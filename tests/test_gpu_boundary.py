@@ -240,3 +240,38 @@ def test_fit_across_lr_decay_steps(gpu_lib, record):
     th_nd, _, _, lo_nd = F.train(th0.astype(np.float64), shapes, B.astype(np.float64), ot, "regressor", (0, 0, 0),
                                  64, T.SDF, 3.0, steps=10, batch=4096, seed=9, lr0=lr, decay=1.0, interval=interval)
     assert np.abs(lo_nd[-1] - lo[-1]) / lo[-1] > 1e-3
+
+
+@pytest.mark.parametrize("net", [(128, 4, 64, 1, 0, "regressor"), (128, 3, 64, 1, 1, "l0")], ids=["4x128", "3x128"])
+def test_classic_train_kernel_128_bf16(gpu_lib, volume, record, net, monkeypatch):
+    """The 128-wide BF16 networks train with the activation-rows kernel; the classic
+    kernel (activations in registers, layer 1's gradient in LDS), still used for the
+    other shapes, is selected for them by NVDB_TRAIN_CLASSIC at model creation.  Both
+    give the oracle's BF16-form gradient on the same samples."""
+    from oracle import bf16 as bf16_form
+    tr, ot, origin = volume
+    lo, D = (origin[0] - 3, origin[1] + 2, origin[2] - 5), 90
+    pop = F.population(ot, net[5])
+    idx = np.random.default_rng(12).integers(0, pop, 3000)
+    gy = np.random.default_rng(13).standard_normal((len(idx), 1)).astype(np.float32)
+    x, _ = F.net_inputs(ot, net[5], idx, lo, D, T.SDF, 3.0)
+    grads = {}
+    for kernel in ("rows", "classic"):
+        if kernel == "classic":
+            monkeypatch.setenv("NVDB_TRAIN_CLASSIC", "1")
+        model, th, B, shapes = make(gpu_lib, net, gpu_lib.BF16, lo, D)
+        monkeypatch.delenv("NVDB_TRAIN_CLASSIC", raising=False)
+        model.reserve_dev(net[4], len(idx))
+        grads[kernel] = model.backward(net[4], tr, torch.from_numpy(idx.astype(np.int32)).to(DEV),
+                                       torch.from_numpy(gy).to(DEV)).cpu().numpy().astype(np.float64)
+    params = mlp.unflatten(th, shapes)
+    _, cb = bf16_form.forward_bf16(params, mlp.encode(x, B))
+    gb = mlp.flatten(bf16_form.backward_bf16(params, cb, gy.astype(np.float64)))
+    for kernel, g in grads.items():
+        a, errs = 0, []
+        for o, i in shapes:
+            for n in (o * i, o):
+                errs.append(np.max(np.abs(g[a:a + n] - gb[a:a + n])) / np.max(np.abs(gb[a:a + n])))
+                a += n
+        record("classic_vs_rows_%s_%s" % (net[5], kernel), elem_bf16_form=max(errs))
+        assert max(errs) <= 0.1, (kernel, errs)
