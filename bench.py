@@ -457,6 +457,24 @@ def cloud_leg(fit_steps, tuned_g):
                       "bytes_explicit": explicit, "bytes_neural_lossless_topology": neural,
                       "compression_ratio": explicit / neural}
         del pred, fpl, fnl
+    # the stored object: the compact archive ([Hash,5,NN(4),NN(3)] without the level-0
+    # classifier: level-1 classifier + regressor, 16-bit weights, patches), written and
+    # decoded back to the true topology
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    blob = nvdb.archive_write(mdl, tree, 0b101, nvdb.STORE_F16, explicit_l1=False, patches=True)
+    wr_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    back, ainfo = nvdb.archive_decode(blob)
+    torch.cuda.synchronize()
+    rd_s = time.perf_counter() - t0
+    ra = nvdb.errors_topology(tree, back)
+    explicit = int(info.bytes_l2 + info.bytes_l1 + info.bytes_leaf_masks + info.bytes_voxels)
+    archive = {"bytes": len(blob), "bytes_explicit": explicit, "compression_ratio": explicit / len(blob),
+               "patches": int(ainfo.n_fp + ainfo.n_fn), "write_s": wr_s, "decode_s": rd_s,
+               "decoded_fp": ra["fp"], "decoded_fn": ra["fn"], "decoded_rms_err": ra["rms"],
+               "decoded_voxels_per_s": N / rd_s}
+    del back, blob
     return {"workload": "fBm cloud 1024^3 (6 octaves, lacunarity 2, gain 0.5), active where density > 0.55; "
                         "voxel regressor 4x128 + level-1 classifier 4x64 (3 classes), FFM m=64 sigma=10, BF16; "
                         "%d steps x 2^18 samples per network" % fit_steps,
@@ -466,7 +484,7 @@ def cloud_leg(fit_steps, tuned_g):
             "l1_slots_per_s": 4096 * L1 / l1_s, "l1_decode_ms": l1_s * 1e3,
             "rms_err": rep["rms"], "max_abs_err": rep["max_abs"],
             "l1": {"n_slots": r1["n_slots"], "fp": r1["fp"], "fn": r1["fn"], "mismatch": r1["mismatch"]},
-            "topology_decode": topo,
+            "topology_decode": topo, "archive": archive,
             "fp8": {"decoded_voxels_per_s": N / dec8_s, "decode_ms": dec8_s * 1e3,
                     "decode_tflops": N * flops_fwd(2 * M, W, H, C) / dec8_s / 1e12,
                     "frac_of_fp8_peak": N * flops_fwd(2 * M, W, H, C) / dec8_s / 1e12 / 5000.0,

@@ -323,7 +323,9 @@ nvdb_status nvdb_errors(const nvdb_tree* tree, const float* values_dev, const ui
                         nvdb_error_report* out, void* stream);
 /* Full decode of the lower tree levels (Sec. 3.3, 3.5): the level-1 classifier
  * predicts, for every leaf slot of the level-1 nodes of `upper` (whose upper
- * levels are stored explicitly), which slots hold a leaf; inside every
+ * levels are stored explicitly), which slots hold a leaf (a model without the
+ * level-1 classifier takes the slots' classes from the child and tile masks
+ * that `upper` stores, the [Hash,5,4,NN(3)] form); inside every
  * predicted leaf the level-0 classifier predicts the active voxels (logit > 0)
  * or, when the model has no level-0 classifier, the regressor's value at every
  * voxel slot is tested with the volume's active rule (SDF |v| <= band, fog
@@ -466,6 +468,50 @@ nvdb_status nvdb_query(const nvdb_model* model, const nvdb_tree* tree, const flo
  * device address cannot be obtained. */
 nvdb_status nvdb_query_noalloc(const nvdb_model* model, const nvdb_tree* tree, const float* q_dev, int64_t n,
                                float background, int64_t batch, float* values_dev, uint8_t* hits_dev, void* stream);
+
+/* ---------------------------------------------------------------- archive */
+/* Compact serialised NeuralVDB (Sec. 3.3.2: the upper tree levels are kept
+ * explicitly and the lower levels are replaced by networks; Sec. 4: networks
+ * stored at 16 bits; Tab. memory_cost: 12 bytes per patch coordinate).  The byte
+ * image (little-endian, sections 4-byte aligned): a 112-byte header (magic
+ * "NVDB", version 1, flags, 16-bit format, the arithmetic the patches were taken
+ * with, active rule, value scale, normalisation box, grid box, network mask, node
+ * and patch counts); per level-2 node its origin (12 B) and child mask (4096 B);
+ * per level-1 node its origin (12 B) and, when the level is stored explicitly
+ * ([Hash,5,4,NN(3)]), its child and tile masks (2 x 512 B); per network
+ * (regressor, level-0, level-1 classifier, those in nets_mask) its shape
+ * int32[4] (width, hidden, n_freq, n_out), encoding float32[n_freq][3] and
+ * parameters uint16[P] rounded to nearest even (padded to 4 bytes); then the
+ * false-positive and false-negative voxel coordinates int32[n][3].
+ * nvdb_archive_write: the archive of `model`'s networks for the volume `truth`.
+ * With patches, the writer decodes the topology the reader will decode (the
+ * 16-bit networks, in the model's arithmetic, from the stored upper levels)
+ * and lists where it differs from `truth`, so the reader restores the true
+ * active set exactly.  cap 0 with buf NULL returns the size only.
+ * Synchronises `stream`.  Errors: E_INVALID (bad description, buffer smaller
+ * than *size), E_STATE (a network missing or unset).
+ * nvdb_archive_decode: the tree decoded from an archive: the lower levels by
+ * inference from the stored upper levels (nvdb_decode_topology), the patches
+ * applied, values from the regressor at every voxel.  The caller frees the tree.
+ * Synchronises `stream`.  Errors: E_INVALID (not an archive, truncated, corrupt
+ * sizes or origins, patches that do not match the decoded tree). */
+typedef struct {
+  int32_t nets_mask;    /* networks stored; must hold the regressor                  */
+  int32_t storage;      /* NVDB_STORE_F16 or NVDB_STORE_BF16                        */
+  int32_t explicit_l1;  /* 1: level-1 child / tile masks stored (no level-1 net)    */
+  int32_t patches;      /* 1: store the patches that make the topology lossless      */
+} nvdb_archive_desc;
+typedef struct {
+  int32_t flags;      /* bit 0: level-1 masks stored; bit 1: patches stored */
+  int32_t nets_mask;  /* networks stored                                     */
+  int32_t rule_kind;  /* active rule of the encoded volume                   */
+  float rule_thr;
+  int64_t n_l2, n_l1, n_fp, n_fn;
+} nvdb_archive_info;
+nvdb_status nvdb_archive_write(const nvdb_model* model, const nvdb_tree* truth, const nvdb_archive_desc* desc,
+                               uint8_t* buf, int64_t cap, int64_t* size, void* stream);
+nvdb_status nvdb_archive_decode(const uint8_t* buf, int64_t size, nvdb_tree** out, nvdb_archive_info* info,
+                                void* stream);
 
 /* ------------------------------------------------- device-pointer calls */
 /* Calls for the autograd binding and for callers that keep their own batches

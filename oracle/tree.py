@@ -187,3 +187,20 @@ def explicit_bytes(n_leaves, n_l1, n_l2):
     return dict(l2=n_l2 * L2_NODE_BYTES, l1=n_l1 * L1_NODE_BYTES,
                 leaf_mask=n_leaves * LEAF_MASK_BYTES,
                 voxels=n_leaves * VOXELS_PER_LEAF * VOXEL_BYTES)
+
+
+# A neural level keeps no nodes: its network's parameters (4 bytes each in the
+# table's in-memory count, 2 in a 16-bit file) and 12 bytes per patched voxel or
+# slot; neural level-1 nodes keep their 12-byte origins (the level-2 masks only
+# say which level-1 nodes exist, the origins place them).
+PATCH_BYTES = 12
+ORIGIN_BYTES = 12
+
+
+def neural_bytes(n_l2, n_l1, params_l1, patches_l1, params_l0, patches_l0, params_voxels, bytes_per_param=4):
+    """Bytes of a [Hash,5,NN(4),NN(3)] NeuralVDB per level (Tab. memory_cost, right block):
+    explicit level-2 nodes, then per neural level its parameters and patches."""
+    return dict(l2=n_l2 * L2_NODE_BYTES,
+                l1=n_l1 * ORIGIN_BYTES + bytes_per_param * params_l1 + PATCH_BYTES * patches_l1,
+                leaf_mask=bytes_per_param * params_l0 + PATCH_BYTES * patches_l0,
+                voxels=bytes_per_param * params_voxels)

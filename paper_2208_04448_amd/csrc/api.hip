@@ -1160,13 +1160,12 @@ nvdb_status nvdb_errors(const nvdb_tree* tree, const float* values_dev, const ui
   });
 }
 
-nvdb_status nvdb_decode_topology(const nvdb_model* m, const nvdb_tree* upper, int32_t fp8, nvdb_tree** out,
-                                 void* stream) {
-  return guarded([&] {
-    NVDB_REQUIRE(m && upper && out, NVDB_E_INVALID, "null argument");
-    *out = nullptr;
-    hipStream_t st = (hipStream_t)stream;
-    const bool use_fp8 = fp8 != 0;
+}  // extern "C"
+
+// The lower tree levels decoded below the level-1 nodes of `upper` (see
+// nvdb_decode_topology); synchronises `st`.
+static nvdb_tree* decode_topology_impl(const nvdb_model* m, const nvdb_tree* upper, bool use_fp8, hipStream_t st) {
+  {
     const Net& R = net_of(m, NVDB_NET_REGRESSOR);
     NVDB_REQUIRE(R.params_set && R.enc_set, NVDB_E_STATE, "regressor parameters or encoding not set");
     const bool has_l0 = m->nets[NVDB_NET_L0].present;
@@ -1198,7 +1197,10 @@ nvdb_status nvdb_decode_topology(const nvdb_model* m, const nvdb_tree* upper, in
       flag.alloc(std::max<int64_t>(n_slots, 1));
       prefix.alloc(std::max<int64_t>(n_slots, 1));
       if (n_slots > 0) {
-        decode_l1_impl(m, upper, cls.p, use_fp8, st);
+        // level-1 classes from the level-1 classifier, or, for a model without one,
+        // from the child and tile masks `upper` stores explicitly
+        if (m->nets[NVDB_NET_L1].present) decode_l1_impl(m, upper, cls.p, use_fp8, st);
+        else classes_from_masks(*upper, cls.p, st);
         pred_flags(cls.p, n_slots, flag.p, st);
       }
       const uint64_t nleaf = scan_u64(flag.p, n_slots, prefix.p, st);
@@ -1238,7 +1240,18 @@ nvdb_status nvdb_decode_topology(const nvdb_model* m, const nvdb_tree* upper, in
       delete t;
       throw;
     }
-    *out = t;
+    return t;
+  }
+}
+
+extern "C" {
+
+nvdb_status nvdb_decode_topology(const nvdb_model* m, const nvdb_tree* upper, int32_t fp8, nvdb_tree** out,
+                                 void* stream) {
+  return guarded([&] {
+    NVDB_REQUIRE(m && upper && out, NVDB_E_INVALID, "null argument");
+    *out = nullptr;
+    *out = decode_topology_impl(m, upper, fp8 != 0, (hipStream_t)stream);
   });
 }
 
@@ -1786,6 +1799,395 @@ nvdb_status nvdb_sample_indices_dev(uint64_t seed, int32_t stream_id, int64_t st
                  "bad sampler arguments");
     NVDB_REQUIRE(batch == 0 || idx_dev, NVDB_E_INVALID, "null output");
     launch_sample(step_seed(seed, stream_id, step), (uint32_t)n_pop, batch, idx_dev, (hipStream_t)stream);
+  });
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ archive
+// Byte image of a NeuralVDB: header, level-2 nodes (origin, child mask),
+// level-1 nodes (origin; child and tile masks when stored explicitly), per
+// network its shape, encoding matrix and 16-bit parameters, then the patch
+// coordinates.  Little-endian, every section 4-byte aligned.
+namespace {
+struct ArchiveHeader {
+  char magic[4];
+  uint32_t version;
+  uint32_t flags;    // bit 0: level-1 child / tile masks stored; bit 1: patches stored
+  uint32_t storage;  // NVDB_STORE_F16 or NVDB_STORE_BF16
+  int32_t precision;  // arithmetic the patches were taken with (the reader's)
+  int32_t rule_kind;
+  float rule_thr;
+  float value_scale;
+  int32_t domain_lo[3];
+  int32_t domain_size;
+  int32_t grid_origin[3];
+  int32_t grid_dims[3];
+  uint32_t nets_mask;
+  uint32_t reserved;
+  int64_t n_l2, n_l1, n_fp, n_fn;
+};
+static_assert(sizeof(ArchiveHeader) == 112, "archive header layout");
+constexpr uint32_t ARCHIVE_VERSION = 1;
+constexpr uint32_t AR_L1_MASKS = 1u, AR_PATCHES = 2u;
+
+int64_t pad4(int64_t n) { return (n + 3) & ~int64_t(3); }
+int64_t net_bytes(const NetShape& s, int32_t n_freq) { return 16 + 12 * (int64_t)n_freq + pad4(2 * s.nparams()); }
+
+struct Writer {
+  uint8_t* buf;
+  int64_t cap, pos = 0;
+  void put(const void* p, int64_t n) {
+    if (buf && pos + n <= cap) std::memcpy(buf + pos, p, (size_t)n);
+    pos += n;
+  }
+  void pad() {
+    static const uint8_t z[4] = {0, 0, 0, 0};
+    put(z, pad4(pos) - pos);
+  }
+};
+struct Reader {
+  const uint8_t* buf;
+  int64_t size, pos = 0;
+  const uint8_t* take(int64_t n) {
+    NVDB_REQUIRE(n >= 0 && pos + n <= size, NVDB_E_INVALID, "archive truncated");
+    const uint8_t* p = buf + pos;
+    pos += n;
+    return p;
+  }
+  template <class T>
+  T get() {
+    T v;
+    std::memcpy(&v, take(sizeof(T)), sizeof(T));
+    return v;
+  }
+};
+
+// A model holding the networks of `m` selected by nets_mask with their
+// parameters rounded to 16 bits (the archive's content), in `precision`.
+nvdb_model* rounded_model(const nvdb_model* m, int32_t nets_mask, int32_t storage, int32_t precision) {
+  nvdb_model_desc d = m->d;
+  d.precision = precision;
+  for (int k = 0; k < NVDB_MAX_NETS; ++k) d.has_net[k] = (nets_mask >> k) & 1;
+  nvdb_model* r = nullptr;
+  nvdb_status st = nvdb_model_create(&d, &r);
+  if (st != NVDB_OK) throw Error(st, g_err);
+  try {
+    for (int k = 0; k < NVDB_MAX_NETS; ++k) {
+      if (!d.has_net[k]) continue;
+      const Net& N = m->nets[k];
+      const int64_t P = N.s.nparams();
+      std::vector<uint16_t> p16((size_t)P);
+      st = nvdb_model_get_params16(m, k, storage, p16.data(), P);
+      if (st == NVDB_OK) st = nvdb_model_set_params16(r, k, storage, p16.data(), P);
+      if (st != NVDB_OK) throw Error(st, g_err);
+      std::vector<float> b(4 * (size_t)(N.s.KP / 2));
+      NVDB_HIP(hipMemcpy(b.data(), N.benc.p, b.size() * 4, hipMemcpyDeviceToHost));
+      std::vector<float> B3(3 * (size_t)N.d.n_freq);
+      for (int i = 0; i < N.d.n_freq; ++i)
+        for (int c = 0; c < 3; ++c) B3[3 * i + c] = b[4 * i + c];
+      st = nvdb_model_set_encoding(r, k, B3.data(), N.d.n_freq);
+      if (st != NVDB_OK) throw Error(st, g_err);
+    }
+  } catch (...) {
+    delete r;
+    throw;
+  }
+  return r;
+}
+}  // namespace
+
+extern "C" {
+
+nvdb_status nvdb_archive_write(const nvdb_model* m, const nvdb_tree* truth, const nvdb_archive_desc* ad, uint8_t* buf,
+                               int64_t cap, int64_t* size, void* stream) {
+  return guarded([&] {
+    NVDB_REQUIRE(m && truth && ad && size && cap >= 0 && (cap == 0 || buf), NVDB_E_INVALID, "null argument");
+    NVDB_REQUIRE(ad->storage == NVDB_STORE_F16 || ad->storage == NVDB_STORE_BF16, NVDB_E_INVALID,
+                 "unknown 16-bit format");
+    const int32_t mask = ad->nets_mask;
+    NVDB_REQUIRE(mask > 0 && mask < (1 << NVDB_MAX_NETS) && (mask & (1 << NVDB_NET_REGRESSOR)), NVDB_E_INVALID,
+                 "an archive holds the regressor and optionally the classifiers");
+    NVDB_REQUIRE(ad->explicit_l1 ? !(mask & (1 << NVDB_NET_L1)) : (mask & (1 << NVDB_NET_L1)) != 0, NVDB_E_INVALID,
+                 "level-1 nodes are stored either as masks or as the level-1 classifier");
+    for (int k = 0; k < NVDB_MAX_NETS; ++k)
+      if (mask & (1 << k)) {
+        const Net& N = net_of(m, k);
+        NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "parameters or encoding not set");
+      }
+    hipStream_t st = (hipStream_t)stream;
+    wait_model(m);
+    // the patches are taken against the topology the reader will decode: the same
+    // 16-bit networks in the same arithmetic, from the stored upper levels
+    std::vector<int32_t> fp, fn;
+    if (ad->patches) {
+      nvdb_model* r = rounded_model(m, mask, ad->storage, m->d.precision);
+      nvdb_tree* upper = nullptr;
+      nvdb_tree* pred = nullptr;
+      try {
+        if (ad->explicit_l1) {
+          pred = decode_topology_impl(r, truth, false, st);
+        } else {
+          // the reader has no level-1 masks: decode from a copy of the upper levels without them
+          upper = new nvdb_tree();
+          upper->n_l1 = truth->n_l1;
+          upper->n_l2 = truth->n_l2;
+          upper->l2_origin = truth->l2_origin;
+          upper->kind = truth->kind;
+          upper->thr = truth->thr;
+          std::memcpy(upper->origin, truth->origin, sizeof(upper->origin));
+          std::memcpy(upper->dims, truth->dims, sizeof(upper->dims));
+          const int64_t nl1 = std::max<int64_t>(truth->n_l1, 1);
+          upper->l1_o.alloc(nl1);
+          upper->l1_child.alloc(nl1 * 64);
+          upper->l1_active.alloc(nl1 * 64);
+          if (truth->n_l1)
+            NVDB_HIP(hipMemcpyAsync(upper->l1_o.p, truth->l1_o.p, truth->n_l1 * sizeof(int4), hipMemcpyDeviceToDevice, st));
+          NVDB_HIP(hipMemsetAsync(upper->l1_child.p, 0, nl1 * 64 * 8, st));
+          NVDB_HIP(hipMemsetAsync(upper->l1_active.p, 0, nl1 * 64 * 8, st));
+          pred = decode_topology_impl(r, upper, false, st);
+        }
+        int64_t nfp = 0, nfn = 0;
+        NVDB_REQUIRE(truth->n_l1 == pred->n_l1, NVDB_E_STATE, "decoded tree lost level-1 nodes");
+        nfp = topology_patches(*pred, *truth, nullptr, 0, st);
+        nfn = topology_patches(*truth, *pred, nullptr, 0, st);
+        DevBuf<int32_t> dfp, dfn;
+        dfp.alloc(3 * std::max<int64_t>(nfp, 1));
+        dfn.alloc(3 * std::max<int64_t>(nfn, 1));
+        topology_patches(*pred, *truth, dfp.p, nfp, st);
+        topology_patches(*truth, *pred, dfn.p, nfn, st);
+        fp.resize(3 * (size_t)nfp);
+        fn.resize(3 * (size_t)nfn);
+        if (nfp) NVDB_HIP(hipMemcpy(fp.data(), dfp.p, 12 * (size_t)nfp, hipMemcpyDeviceToHost));
+        if (nfn) NVDB_HIP(hipMemcpy(fn.data(), dfn.p, 12 * (size_t)nfn, hipMemcpyDeviceToHost));
+      } catch (...) {
+        delete pred;
+        delete upper;
+        delete r;
+        throw;
+      }
+      delete pred;
+      delete upper;
+      delete r;
+    }
+    ArchiveHeader hd{};
+    std::memcpy(hd.magic, "NVDB", 4);
+    hd.version = ARCHIVE_VERSION;
+    hd.flags = (ad->explicit_l1 ? AR_L1_MASKS : 0u) | (ad->patches ? AR_PATCHES : 0u);
+    hd.storage = (uint32_t)ad->storage;
+    hd.precision = m->d.precision;
+    hd.rule_kind = truth->kind;
+    hd.rule_thr = truth->thr;
+    hd.value_scale = m->d.value_scale;
+    for (int d = 0; d < 3; ++d) {
+      hd.domain_lo[d] = m->d.domain_lo[d];
+      hd.grid_origin[d] = truth->origin[d];
+      hd.grid_dims[d] = truth->dims[d];
+    }
+    hd.domain_size = m->d.domain_size;
+    hd.nets_mask = (uint32_t)mask;
+    hd.n_l2 = truth->n_l2;
+    hd.n_l1 = truth->n_l1;
+    hd.n_fp = (int64_t)fp.size() / 3;
+    hd.n_fn = (int64_t)fn.size() / 3;
+    Writer w{buf, cap};
+    w.put(&hd, sizeof(hd));
+    // level 2
+    std::vector<int32_t> l2o(3 * (size_t)truth->n_l2);
+    std::vector<uint64_t> l2c(512 * (size_t)truth->n_l2);
+    nvdb_status s2 = nvdb_tree_export_l2(truth, l2o.data(), l2c.data());
+    if (s2 != NVDB_OK) throw Error(s2, g_err);
+    for (int64_t i = 0; i < truth->n_l2; ++i) {
+      w.put(&l2o[3 * i], 12);
+      w.put(&l2c[512 * i], 4096);
+    }
+    // level 1
+    if (truth->n_l1) {
+      std::vector<int4> o((size_t)truth->n_l1);
+      std::vector<uint64_t> c, a;
+      NVDB_HIP(hipMemcpy(o.data(), truth->l1_o.p, truth->n_l1 * sizeof(int4), hipMemcpyDeviceToHost));
+      if (ad->explicit_l1) {
+        c.resize(64 * (size_t)truth->n_l1);
+        a.resize(64 * (size_t)truth->n_l1);
+        NVDB_HIP(hipMemcpy(c.data(), truth->l1_child.p, c.size() * 8, hipMemcpyDeviceToHost));
+        NVDB_HIP(hipMemcpy(a.data(), truth->l1_active.p, a.size() * 8, hipMemcpyDeviceToHost));
+      }
+      for (int64_t i = 0; i < truth->n_l1; ++i) {
+        const int32_t xyz[3] = {o[i].x, o[i].y, o[i].z};
+        w.put(xyz, 12);
+        if (ad->explicit_l1) {
+          w.put(&c[64 * i], 512);
+          w.put(&a[64 * i], 512);
+        }
+      }
+    }
+    // networks
+    for (int k = 0; k < NVDB_MAX_NETS; ++k) {
+      if (!(mask & (1 << k))) continue;
+      const Net& N = m->nets[k];
+      const int32_t desc[4] = {N.d.width, N.d.hidden, N.d.n_freq, N.d.n_out};
+      w.put(desc, 16);
+      std::vector<float> b(4 * (size_t)(N.s.KP / 2));
+      NVDB_HIP(hipMemcpy(b.data(), N.benc.p, b.size() * 4, hipMemcpyDeviceToHost));
+      for (int i = 0; i < N.d.n_freq; ++i) w.put(&b[4 * i], 12);
+      const int64_t P = N.s.nparams();
+      std::vector<uint16_t> p16((size_t)P);
+      nvdb_status s3 = nvdb_model_get_params16(m, k, ad->storage, p16.data(), P);
+      if (s3 != NVDB_OK) throw Error(s3, g_err);
+      w.put(p16.data(), 2 * P);
+      w.pad();
+    }
+    if (!fp.empty()) w.put(fp.data(), 4 * (int64_t)fp.size());
+    if (!fn.empty()) w.put(fn.data(), 4 * (int64_t)fn.size());
+    *size = w.pos;
+    NVDB_REQUIRE(cap == 0 || w.pos <= cap, NVDB_E_INVALID, "archive buffer too small");
+  });
+}
+
+nvdb_status nvdb_archive_decode(const uint8_t* buf, int64_t size, nvdb_tree** out, nvdb_archive_info* info,
+                                void* stream) {
+  return guarded([&] {
+    NVDB_REQUIRE(buf && out && size >= 0, NVDB_E_INVALID, "null argument");
+    *out = nullptr;
+    hipStream_t st = (hipStream_t)stream;
+    Reader r{buf, size};
+    const ArchiveHeader hd = r.get<ArchiveHeader>();
+    NVDB_REQUIRE(std::memcmp(hd.magic, "NVDB", 4) == 0 && hd.version == ARCHIVE_VERSION, NVDB_E_INVALID,
+                 "not a NeuralVDB archive of this version");
+    NVDB_REQUIRE((hd.flags & ~(AR_L1_MASKS | AR_PATCHES)) == 0 && hd.nets_mask > 0 &&
+                     hd.nets_mask < (1u << NVDB_MAX_NETS) && (hd.nets_mask & (1u << NVDB_NET_REGRESSOR)) &&
+                     (hd.storage == NVDB_STORE_F16 || hd.storage == NVDB_STORE_BF16) &&
+                     (hd.precision == NVDB_FP32 || hd.precision == NVDB_BF16) && hd.n_l2 >= 0 && hd.n_l1 >= 0 &&
+                     hd.n_fp >= 0 && hd.n_fn >= 0 && hd.n_l1 < (1ll << 24) && hd.n_l2 < (1ll << 20),
+                 NVDB_E_INVALID, "corrupt archive header");
+    const bool explicit_l1 = hd.flags & AR_L1_MASKS;
+    NVDB_REQUIRE(explicit_l1 == !(hd.nets_mask & (1u << NVDB_NET_L1)), NVDB_E_INVALID,
+                 "archive must hold level-1 masks or a level-1 classifier, not both");
+    // upper levels
+    nvdb_tree* upper = new nvdb_tree();
+    nvdb_model* model = nullptr;
+    nvdb_tree* pred = nullptr;
+    try {
+      upper->kind = hd.rule_kind;
+      upper->thr = hd.rule_thr;
+      for (int d = 0; d < 3; ++d) {
+        upper->origin[d] = hd.grid_origin[d];
+        upper->dims[d] = hd.grid_dims[d];
+      }
+      upper->n_l2 = hd.n_l2;
+      upper->n_l1 = hd.n_l1;
+      upper->l2_origin.resize(3 * (size_t)hd.n_l2);
+      for (int64_t i = 0; i < hd.n_l2; ++i) {
+        std::memcpy(&upper->l2_origin[3 * i], r.take(12), 12);
+        r.take(4096);  // child masks: implied by the level-1 origins
+      }
+      const int64_t nl1 = std::max<int64_t>(hd.n_l1, 1);
+      std::vector<int4> o((size_t)nl1, int4{0, 0, 0, 0});
+      std::vector<uint64_t> c(64 * (size_t)nl1, 0ull), a(64 * (size_t)nl1, 0ull);
+      for (int64_t i = 0; i < hd.n_l1; ++i) {
+        int32_t xyz[3];
+        std::memcpy(xyz, r.take(12), 12);
+        NVDB_REQUIRE((xyz[0] & 127) == 0 && (xyz[1] & 127) == 0 && (xyz[2] & 127) == 0, NVDB_E_INVALID,
+                     "corrupt level-1 origin");
+        o[i] = int4{xyz[0], xyz[1], xyz[2], 0};
+        if (explicit_l1) {
+          std::memcpy(&c[64 * i], r.take(512), 512);
+          std::memcpy(&a[64 * i], r.take(512), 512);
+        }
+      }
+      upper->l1_o.alloc(nl1);
+      upper->l1_child.alloc(64 * nl1);
+      upper->l1_active.alloc(64 * nl1);
+      NVDB_HIP(hipMemcpy(upper->l1_o.p, o.data(), nl1 * sizeof(int4), hipMemcpyHostToDevice));
+      NVDB_HIP(hipMemcpy(upper->l1_child.p, c.data(), c.size() * 8, hipMemcpyHostToDevice));
+      NVDB_HIP(hipMemcpy(upper->l1_active.p, a.data(), a.size() * 8, hipMemcpyHostToDevice));
+      // networks
+      nvdb_model_desc d{};
+      d.precision = hd.precision;
+      for (int k = 0; k < 3; ++k) d.domain_lo[k] = hd.domain_lo[k];
+      d.domain_size = hd.domain_size;
+      d.value_scale = hd.value_scale;
+      struct Blob {
+        const uint8_t* B;
+        const uint8_t* p16;
+        int64_t P;
+      };
+      Blob blobs[NVDB_MAX_NETS] = {};
+      for (int k = 0; k < NVDB_MAX_NETS; ++k) {
+        if (!(hd.nets_mask & (1u << k))) continue;
+        int32_t desc[4];
+        std::memcpy(desc, r.take(16), 16);
+        NVDB_REQUIRE(desc[2] >= 1 && desc[2] <= 64 && desc[0] > 0 && desc[1] > 0 && desc[3] > 0, NVDB_E_INVALID,
+                     "corrupt network shape");
+        d.has_net[k] = 1;
+        d.net[k] = nvdb_net_desc{desc[0], desc[1], desc[2], desc[3]};
+        blobs[k].B = r.take(12 * (int64_t)desc[2]);
+        NetShape s{};
+        s.K = 2 * desc[2];
+        s.W = desc[0];
+        s.H = desc[1];
+        s.C = desc[3];
+        blobs[k].P = s.nparams();
+        blobs[k].p16 = r.take(pad4(2 * blobs[k].P));
+      }
+      nvdb_status s1 = nvdb_model_create(&d, &model);
+      if (s1 != NVDB_OK) throw Error(s1, g_err);
+      for (int k = 0; k < NVDB_MAX_NETS; ++k) {
+        if (!d.has_net[k]) continue;
+        std::vector<uint16_t> p16((size_t)blobs[k].P);
+        std::memcpy(p16.data(), blobs[k].p16, 2 * (size_t)blobs[k].P);
+        std::vector<float> B3(3 * (size_t)d.net[k].n_freq);
+        std::memcpy(B3.data(), blobs[k].B, 12 * (size_t)d.net[k].n_freq);
+        s1 = nvdb_model_set_params16(model, k, (int32_t)hd.storage, p16.data(), blobs[k].P);
+        if (s1 == NVDB_OK) s1 = nvdb_model_set_encoding(model, k, B3.data(), d.net[k].n_freq);
+        if (s1 != NVDB_OK) throw Error(s1, g_err);
+      }
+      const int32_t* fp = (const int32_t*)r.take(12 * hd.n_fp);
+      const int32_t* fn = (const int32_t*)r.take(12 * hd.n_fn);
+      NVDB_REQUIRE(r.pos == size, NVDB_E_INVALID, "trailing bytes after the archive");
+      // the lower levels by inference, then the patches
+      pred = decode_topology_impl(model, upper, false, st);
+      nvdb_tree* result = pred;
+      if (hd.flags & AR_PATCHES) {
+        DevBuf<int32_t> dfp, dfn;
+        dfp.alloc(3 * std::max<int64_t>(hd.n_fp, 1));
+        dfn.alloc(3 * std::max<int64_t>(hd.n_fn, 1));
+        if (hd.n_fp) NVDB_HIP(hipMemcpy(dfp.p, fp, 12 * (size_t)hd.n_fp, hipMemcpyHostToDevice));
+        if (hd.n_fn) NVDB_HIP(hipMemcpy(dfn.p, fn, 12 * (size_t)hd.n_fn, hipMemcpyHostToDevice));
+        Tree* fixed = apply_patches(*pred, dfp.p, hd.n_fp, dfn.p, hd.n_fn, st);
+        result = static_cast<nvdb_tree*>(fixed);
+        delete pred;
+        pred = nullptr;
+        try {
+          // values of the restored voxels from the regressor
+          if (result->n_vox > 0) decode_impl(model, result, result->values.p, nullptr, false, st);
+          NVDB_HIP(hipStreamSynchronize(st));
+        } catch (...) {
+          delete result;
+          throw;
+        }
+      }
+      if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->flags = (int32_t)hd.flags;
+        info->nets_mask = (int32_t)hd.nets_mask;
+        info->rule_kind = hd.rule_kind;
+        info->rule_thr = hd.rule_thr;
+        info->n_l2 = hd.n_l2;
+        info->n_l1 = hd.n_l1;
+        info->n_fp = hd.n_fp;
+        info->n_fn = hd.n_fn;
+      }
+      *out = result;
+      pred = nullptr;
+    } catch (...) {
+      delete pred;
+      delete model;
+      delete upper;
+      throw;
+    }
+    delete model;
+    delete upper;
   });
 }
 

@@ -291,6 +291,11 @@ struct QueryScratch {
 QueryScratch query_noalloc_scratch();
 // voxels of a that b lacks, canonical order, at most cap written to out [cap][3]; returns the count
 int64_t topology_patches(const Tree& a, const Tree& b, int32_t* out, int64_t cap, hipStream_t st);
+// archive.hip: classes of every leaf slot of the level-1 nodes from their explicit
+// child / tile masks; the tree of a decoded tree's voxels without the listed false
+// positives and with the listed false negatives (device lists int32 [n][3])
+void classes_from_masks(const Tree& t, uint8_t* cls, hipStream_t st);
+Tree* apply_patches(const Tree& pred, const int32_t* fp, int64_t n_fp, const int32_t* fn, int64_t n_fn, hipStream_t st);
 // sparse.hip
 Tree* build_tree_sparse(const int32_t* ijk, const float* v, int64_t n, const nvdb_active_rule& rule, hipStream_t st);
 // moe.hip: sparse domain decomposition.  Grid origin o, cell edge S, halo h, and

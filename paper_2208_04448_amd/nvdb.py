@@ -82,6 +82,15 @@ class Subdomains(C.Structure):
     _fields_ = [("origin", C.c_int32 * 3), ("size", C.c_int32), ("halo", C.c_int32)]
 
 
+class ArchiveDesc(C.Structure):
+    _fields_ = [("nets_mask", C.c_int32), ("storage", C.c_int32), ("explicit_l1", C.c_int32), ("patches", C.c_int32)]
+
+
+class ArchiveInfo(C.Structure):
+    _fields_ = [("flags", C.c_int32), ("nets_mask", C.c_int32), ("rule_kind", C.c_int32), ("rule_thr", C.c_float),
+                ("n_l2", C.c_int64), ("n_l1", C.c_int64), ("n_fp", C.c_int64), ("n_fn", C.c_int64)]
+
+
 _SIGS = {
     "nvdb_last_error": (C.c_char_p, []),
     "nvdb_abi_version": (C.c_int32, []),
@@ -134,6 +143,8 @@ _SIGS = {
     "nvdb_subdomain_box": (C.c_int32, [C.POINTER(Subdomains), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                        C.POINTER(C.c_int32)]),
     "nvdb_query_noalloc": (C.c_int32, [_P, _P, _P, C.c_int64, C.c_float, C.c_int64, _P, _P, _P]),
+    "nvdb_archive_write": (C.c_int32, [_P, _P, C.POINTER(ArchiveDesc), _P, C.c_int64, C.POINTER(C.c_int64), _P]),
+    "nvdb_archive_decode": (C.c_int32, [_P, C.c_int64, C.POINTER(_P), C.POINTER(ArchiveInfo), _P]),
     "nvdb_sample_indices_dev": (C.c_int32, [C.c_uint64, C.c_int32, C.c_int64, C.c_int64, C.c_int64, _P, _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -503,6 +514,28 @@ def topology_patches(truth, pred):
     _check(_lib.nvdb_topology_patches(truth.h, pred.h, _ptr(fp), nfp.value, _ptr(fn), nfn.value, C.byref(nfp),
                                       C.byref(nfn), _stream()))
     return fp, fn
+
+
+def archive_write(model, truth, nets_mask, storage=STORE_F16, explicit_l1=False, patches=True):
+    """Compact byte image (bytes) of the model's networks in nets_mask for the volume `truth`."""
+    d = ArchiveDesc(int(nets_mask), int(storage), int(bool(explicit_l1)), int(bool(patches)))
+    n = C.c_int64()
+    _check(_lib.nvdb_archive_write(model.h, truth.h, C.byref(d), None, 0, C.byref(n), _stream()))
+    buf = (C.c_uint8 * n.value)()
+    _check(_lib.nvdb_archive_write(model.h, truth.h, C.byref(d), buf, n.value, C.byref(n), _stream()))
+    return bytes(buf)
+
+
+def archive_decode(data):
+    """Tree decoded from an archive (bytes) and the archive's ArchiveInfo."""
+    data = bytes(data)
+    buf = (C.c_uint8 * max(len(data), 1)).from_buffer_copy(data or b"\0")
+    h, info = C.c_void_p(), ArchiveInfo()
+    _check(_lib.nvdb_archive_decode(buf, len(data), C.byref(h), C.byref(info), _stream()))
+    t = Tree.__new__(Tree)
+    t.h = h
+    t.kind = info.rule_kind
+    return t, info
 
 
 def subdomain_cells(tree, origin, size, halo):

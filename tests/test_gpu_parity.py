@@ -980,9 +980,10 @@ def test_new_entry_points_reject_bad_arguments(gpu_lib, sphere):
         with pytest.raises(gpu_lib.NvdbError) as e:
             m.autotune(tr, nets_mask=1, **bad)
         assert e.value.code == gpu_lib.E_INVALID
-    with pytest.raises(gpu_lib.NvdbError) as e:      # no level-1 classifier in the model
-        m.decode_topology(tr)
-    assert e.value.code == gpu_lib.E_INVALID
+    # without a level-1 classifier the classes of the leaf slots come from the
+    # tree's own level-1 masks: the decoded leaves are the tree's leaves
+    pred = m.decode_topology(tr)
+    assert np.array_equal(pred.export()["leaf_origin"], tr.export()["leaf_origin"])
     with pytest.raises(gpu_lib.NvdbError) as e:
         m.set_train_groups(513)
     assert e.value.code == gpu_lib.E_INVALID

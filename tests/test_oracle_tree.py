@@ -144,6 +144,12 @@ def test_byte_accounting_matches_paper():
     total = g["l2_bytes"] + g["nn4_l1_bytes"] + g["nn4_l0_bytes"] + g["nn4_voxel_bytes"]
     assert total == g["nn4_total_bytes"]
     assert round(100.0 * total / g["total_bytes"], 3) == g["nn4_percent"]
+    # the same column per level from the oracle's accounting, level-1 row included
+    nb = T.neural_bytes(g["l2_nodes"], g["l1_nodes"], g["nn4_l1_params"], g["nn4_l1_patches"], g["nn4_l0_params"],
+                        g["nn4_l0_patches"], g["nn4_voxel_params"])
+    assert (nb["l2"], nb["l1"], nb["leaf_mask"], nb["voxels"]) == (g["l2_bytes"], g["nn4_l1_bytes"],
+                                                                     g["nn4_l0_bytes"], g["nn4_voxel_bytes"])
+    assert sum(nb.values()) == g["nn4_total_bytes"]
 
 
 def test_active_set_sparse_rule_and_order():
