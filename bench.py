@@ -182,7 +182,7 @@ def main():
                  "l0_fp": rep["fp"], "l0_fn": rep["fn"], "final_loss": [float(losses[0, -1]), float(losses[1, -1])]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_BF16_TFLOPS, "traffic": measured_traffic(),
-                     "kernel": "k_train<bf16,128,4,128,1> (both networks per launch)",
+                     "kernel": "k_train_rows<4> (BF16 4x128, both networks per launch)",
                      "flops_per_launch": launch_flops, "avg_launch_ms": train_launch_s * 1e3},
         "autotune": {"work_groups_per_network": tuned_g, "ms_per_step": {str(g): t for g, t in tune_ms.items()}},
     }
@@ -298,13 +298,15 @@ def main():
 
 def measured_traffic():
     """HBM bytes per launch of the timed train kernel from the committed rocprofv3
-    counter summary, or None when the kernel source has changed since."""
-    path = os.path.join(ROOT, "profiles", "k_train_bf16_4x128_sphere512_traffic.json")
-    src = os.path.join(ROOT, "paper_2208_04448_amd", "csrc", "mlp.hip")
+    counter summary, or None when the kernel's sources have changed since."""
+    path = os.path.join(ROOT, "profiles", "k_train_rows_bf16_4x128_sphere512_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+    h = hashlib.sha256()
+    for f in rec.get("sources", []):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if not rec.get("sources") or rec.get("source_sha256") != h.hexdigest():
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -457,24 +459,28 @@ def cloud_leg(fit_steps, tuned_g):
                       "bytes_explicit": explicit, "bytes_neural_lossless_topology": neural,
                       "compression_ratio": explicit / neural}
         del pred, fpl, fnl
-    # the stored object: the compact archive ([Hash,5,NN(4),NN(3)] without the level-0
-    # classifier: level-1 classifier + regressor, 16-bit weights, patches), written and
-    # decoded back to the true topology
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    blob = nvdb.archive_write(mdl, tree, 0b101, nvdb.STORE_F16, explicit_l1=False, patches=True)
-    wr_s = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    back, ainfo = nvdb.archive_decode(blob)
-    torch.cuda.synchronize()
-    rd_s = time.perf_counter() - t0
-    ra = nvdb.errors_topology(tree, back)
+    # the stored objects: compact archives written and decoded back to the true topology,
+    # [Hash,5,4,NN(3)] (level-1 and leaf masks stored, the regressor for the values) and
+    # [Hash,5,NN(4),NN(3)] without a level-0 classifier (level-1 classifier + regressor
+    # with the active rule, patches); 16-bit weights
     explicit = int(info.bytes_l2 + info.bytes_l1 + info.bytes_leaf_masks + info.bytes_voxels)
-    archive = {"bytes": len(blob), "bytes_explicit": explicit, "compression_ratio": explicit / len(blob),
-               "patches": int(ainfo.n_fp + ainfo.n_fn), "write_s": wr_s, "decode_s": rd_s,
-               "decoded_fp": ra["fp"], "decoded_fn": ra["fn"], "decoded_rms_err": ra["rms"],
-               "decoded_voxels_per_s": N / rd_s}
-    del back, blob
+    archive = {"bytes_explicit": explicit}
+    for name, mask, kw in (("hash54nn3", 0b001, dict(explicit_l1=True, explicit_l0=True)),
+                           ("hash5nn4nn3", 0b101, dict(explicit_l1=False, patches=True))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        blob = nvdb.archive_write(mdl, tree, mask, nvdb.STORE_F16, **kw)
+        wr_s = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        back, ainfo = nvdb.archive_decode(blob)
+        torch.cuda.synchronize()
+        rd_s = time.perf_counter() - t0
+        ra = nvdb.errors_topology(tree, back)
+        archive[name] = {"bytes": len(blob), "compression_ratio": explicit / len(blob),
+                         "patches": int(ainfo.n_fp + ainfo.n_fn), "write_s": wr_s, "decode_s": rd_s,
+                         "decoded_fp": ra["fp"], "decoded_fn": ra["fn"], "decoded_rms_err": ra["rms"],
+                         "decoded_max_abs_err": ra["max_abs"], "decoded_voxels_per_s": N / rd_s}
+        del back, blob
     return {"workload": "fBm cloud 1024^3 (6 octaves, lacunarity 2, gain 0.5), active where density > 0.55; "
                         "voxel regressor 4x128 + level-1 classifier 4x64 (3 classes), FFM m=64 sigma=10, BF16; "
                         "%d steps x 2^18 samples per network" % fit_steps,

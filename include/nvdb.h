@@ -473,17 +473,21 @@ nvdb_status nvdb_query_noalloc(const nvdb_model* model, const nvdb_tree* tree, c
 /* Compact serialised NeuralVDB (Sec. 3.3.2: the upper tree levels are kept
  * explicitly and the lower levels are replaced by networks; Sec. 4: networks
  * stored at 16 bits; Tab. memory_cost: 12 bytes per patch coordinate).  The byte
- * image (little-endian, sections 4-byte aligned): a 112-byte header (magic
+ * image (little-endian, sections 4-byte aligned): a 120-byte header (magic
  * "NVDB", version 1, flags, 16-bit format, the arithmetic the patches were taken
- * with, active rule, value scale, normalisation box, grid box, network mask, node
- * and patch counts); per level-2 node its origin (12 B) and child mask (4096 B);
- * per level-1 node its origin (12 B) and, when the level is stored explicitly
- * ([Hash,5,4,NN(3)]), its child and tile masks (2 x 512 B); per network
+ * with, active rule, value scale, normalisation box, grid box, network mask, node,
+ * patch and stored-leaf counts); per level-2 node its origin (12 B) and child
+ * mask (4096 B); per level-1 node its origin (12 B) and, when the level is stored
+ * explicitly, its child and tile masks (2 x 512 B); when the leaf masks are
+ * stored ([Hash,5,4,NN(3)]: only the voxel values are neural), each leaf's
+ * 512-bit mask (64 B) in canonical leaf order; per network
  * (regressor, level-0, level-1 classifier, those in nets_mask) its shape
  * int32[4] (width, hidden, n_freq, n_out), encoding float32[n_freq][3] and
  * parameters uint16[P] rounded to nearest even (padded to 4 bytes); then the
  * false-positive and false-negative voxel coordinates int32[n][3].
- * nvdb_archive_write: the archive of `model`'s networks for the volume `truth`.
+ * nvdb_archive_write: the archive of `model`'s networks for the volume `truth`
+ * (stored leaf masks need stored level-1 masks, no level-0 classifier and no
+ * patches: their topology is exact).
  * With patches, the writer decodes the topology the reader will decode (the
  * 16-bit networks, in the model's arithmetic, from the stored upper levels)
  * and lists where it differs from `truth`, so the reader restores the true
@@ -500,13 +504,14 @@ typedef struct {
   int32_t storage;      /* NVDB_STORE_F16 or NVDB_STORE_BF16                        */
   int32_t explicit_l1;  /* 1: level-1 child / tile masks stored (no level-1 net)    */
   int32_t patches;      /* 1: store the patches that make the topology lossless      */
+  int32_t explicit_l0;  /* 1: leaf masks stored (no level-0 inference)              */
 } nvdb_archive_desc;
 typedef struct {
-  int32_t flags;      /* bit 0: level-1 masks stored; bit 1: patches stored */
+  int32_t flags;      /* bit 0: level-1 masks, bit 1: patches, bit 2: leaf masks */
   int32_t nets_mask;  /* networks stored                                     */
   int32_t rule_kind;  /* active rule of the encoded volume                   */
   float rule_thr;
-  int64_t n_l2, n_l1, n_fp, n_fn;
+  int64_t n_l2, n_l1, n_fp, n_fn, n_leaf;  /* n_leaf: leaf masks stored           */
 } nvdb_archive_info;
 nvdb_status nvdb_archive_write(const nvdb_model* model, const nvdb_tree* truth, const nvdb_archive_desc* desc,
                                uint8_t* buf, int64_t cap, int64_t* size, void* stream);

@@ -1164,11 +1164,15 @@ nvdb_status nvdb_errors(const nvdb_tree* tree, const float* values_dev, const ui
 
 // The lower tree levels decoded below the level-1 nodes of `upper` (see
 // nvdb_decode_topology); synchronises `st`.
-static nvdb_tree* decode_topology_impl(const nvdb_model* m, const nvdb_tree* upper, bool use_fp8, hipStream_t st) {
+// leaf_masks (device, n_leaf_given x 8 words, canonical leaf order) replaces the
+// level-0 inference when the leaf masks are stored explicitly.
+static nvdb_tree* decode_topology_impl(const nvdb_model* m, const nvdb_tree* upper, bool use_fp8, hipStream_t st,
+                                       const uint64_t* leaf_masks = nullptr, int64_t n_leaf_given = 0) {
   {
     const Net& R = net_of(m, NVDB_NET_REGRESSOR);
     NVDB_REQUIRE(R.params_set && R.enc_set, NVDB_E_STATE, "regressor parameters or encoding not set");
-    const bool has_l0 = m->nets[NVDB_NET_L0].present;
+    const bool masks_given = leaf_masks != nullptr;
+    const bool has_l0 = !masks_given && m->nets[NVDB_NET_L0].present;
     if (has_l0)
       NVDB_REQUIRE(m->nets[NVDB_NET_L0].params_set && m->nets[NVDB_NET_L0].enc_set, NVDB_E_STATE,
                    "level-0 classifier parameters or encoding not set");
@@ -1211,7 +1215,11 @@ static nvdb_tree* decode_topology_impl(const nvdb_model* m, const nvdb_tree* upp
       if (n_slots > 0) pred_leaves(cls.p, prefix.p, t->l1_o.p, n_slots, t->leaf_o.p, t->l1_child.p, t->l1_active.p, st);
       // level 0: voxel masks
       DevBuf<float> slot_y;
-      if (t->n_leaf > 0) {
+      if (masks_given) {
+        NVDB_REQUIRE(t->n_leaf == n_leaf_given, NVDB_E_INVALID, "stored leaf masks do not match the level-1 masks");
+        if (t->n_leaf > 0)
+          NVDB_HIP(hipMemcpyAsync(t->leaf_mask.p, leaf_masks, t->n_leaf * 64, hipMemcpyDeviceToDevice, st));
+      } else if (t->n_leaf > 0) {
         if (has_l0) {
           InferLaunch I{};
           I.out_kind = OUT_MASK;
@@ -1226,9 +1234,10 @@ static nvdb_tree* decode_topology_impl(const nvdb_model* m, const nvdb_tree* upp
           mask_from_values(slot_y.p, t->n_leaf, m->d.value_scale, t->kind, t->thr, t->leaf_mask.p, st);
         }
       }
-      pred_voxels(t->leaf_mask.p, t->n_leaf, t, has_l0 ? nullptr : slot_y.p, m->d.value_scale, st);
+      const bool values_from_slots = !has_l0 && !masks_given;
+      pred_voxels(t->leaf_mask.p, t->n_leaf, t, values_from_slots ? slot_y.p : nullptr, m->d.value_scale, st);
       // values at the predicted voxels
-      if (has_l0 && t->n_vox > 0) {
+      if (!values_from_slots && t->n_vox > 0) {
         InferLaunch I{};
         I.out_kind = OUT_VALUES;
         I.out_scale = m->d.value_scale;
@@ -1825,11 +1834,11 @@ struct ArchiveHeader {
   int32_t grid_dims[3];
   uint32_t nets_mask;
   uint32_t reserved;
-  int64_t n_l2, n_l1, n_fp, n_fn;
+  int64_t n_l2, n_l1, n_fp, n_fn, n_leaf;
 };
-static_assert(sizeof(ArchiveHeader) == 112, "archive header layout");
+static_assert(sizeof(ArchiveHeader) == 120, "archive header layout");
 constexpr uint32_t ARCHIVE_VERSION = 1;
-constexpr uint32_t AR_L1_MASKS = 1u, AR_PATCHES = 2u;
+constexpr uint32_t AR_L1_MASKS = 1u, AR_PATCHES = 2u, AR_L0_MASKS = 4u;
 
 int64_t pad4(int64_t n) { return (n + 3) & ~int64_t(3); }
 int64_t net_bytes(const NetShape& s, int32_t n_freq) { return 16 + 12 * (int64_t)n_freq + pad4(2 * s.nparams()); }
@@ -1910,6 +1919,8 @@ nvdb_status nvdb_archive_write(const nvdb_model* m, const nvdb_tree* truth, cons
                  "an archive holds the regressor and optionally the classifiers");
     NVDB_REQUIRE(ad->explicit_l1 ? !(mask & (1 << NVDB_NET_L1)) : (mask & (1 << NVDB_NET_L1)) != 0, NVDB_E_INVALID,
                  "level-1 nodes are stored either as masks or as the level-1 classifier");
+    NVDB_REQUIRE(!ad->explicit_l0 || (ad->explicit_l1 && !(mask & (1 << NVDB_NET_L0)) && !ad->patches),
+                 NVDB_E_INVALID, "stored leaf masks need stored level-1 masks, no level-0 classifier and no patches");
     for (int k = 0; k < NVDB_MAX_NETS; ++k)
       if (mask & (1 << k)) {
         const Net& N = net_of(m, k);
@@ -1973,7 +1984,9 @@ nvdb_status nvdb_archive_write(const nvdb_model* m, const nvdb_tree* truth, cons
     ArchiveHeader hd{};
     std::memcpy(hd.magic, "NVDB", 4);
     hd.version = ARCHIVE_VERSION;
-    hd.flags = (ad->explicit_l1 ? AR_L1_MASKS : 0u) | (ad->patches ? AR_PATCHES : 0u);
+    hd.flags = (ad->explicit_l1 ? AR_L1_MASKS : 0u) | (ad->patches ? AR_PATCHES : 0u) |
+               (ad->explicit_l0 ? AR_L0_MASKS : 0u);
+    hd.n_leaf = ad->explicit_l0 ? truth->n_leaf : 0;
     hd.storage = (uint32_t)ad->storage;
     hd.precision = m->d.precision;
     hd.rule_kind = truth->kind;
@@ -2021,6 +2034,12 @@ nvdb_status nvdb_archive_write(const nvdb_model* m, const nvdb_tree* truth, cons
         }
       }
     }
+    // level 0
+    if (ad->explicit_l0 && truth->n_leaf > 0) {
+      std::vector<uint64_t> lm(8 * (size_t)truth->n_leaf);
+      NVDB_HIP(hipMemcpy(lm.data(), truth->leaf_mask.p, lm.size() * 8, hipMemcpyDeviceToHost));
+      w.put(lm.data(), 8 * (int64_t)lm.size());
+    }
     // networks
     for (int k = 0; k < NVDB_MAX_NETS; ++k) {
       if (!(mask & (1 << k))) continue;
@@ -2054,11 +2073,17 @@ nvdb_status nvdb_archive_decode(const uint8_t* buf, int64_t size, nvdb_tree** ou
     const ArchiveHeader hd = r.get<ArchiveHeader>();
     NVDB_REQUIRE(std::memcmp(hd.magic, "NVDB", 4) == 0 && hd.version == ARCHIVE_VERSION, NVDB_E_INVALID,
                  "not a NeuralVDB archive of this version");
-    NVDB_REQUIRE((hd.flags & ~(AR_L1_MASKS | AR_PATCHES)) == 0 && hd.nets_mask > 0 &&
+    NVDB_REQUIRE((hd.flags & ~(AR_L1_MASKS | AR_PATCHES | AR_L0_MASKS)) == 0 && hd.nets_mask > 0 &&
                      hd.nets_mask < (1u << NVDB_MAX_NETS) && (hd.nets_mask & (1u << NVDB_NET_REGRESSOR)) &&
                      (hd.storage == NVDB_STORE_F16 || hd.storage == NVDB_STORE_BF16) &&
                      (hd.precision == NVDB_FP32 || hd.precision == NVDB_BF16) && hd.n_l2 >= 0 && hd.n_l1 >= 0 &&
-                     hd.n_fp >= 0 && hd.n_fn >= 0 && hd.n_l1 < (1ll << 24) && hd.n_l2 < (1ll << 20),
+                     hd.n_fp >= 0 && hd.n_fn >= 0 && hd.n_l1 < (1ll << 24) && hd.n_l2 < (1ll << 20) &&
+                     hd.n_leaf >= 0 && hd.n_leaf <= 4096 * hd.n_l1,
+                 NVDB_E_INVALID, "corrupt archive header");
+    const bool explicit_l0 = hd.flags & AR_L0_MASKS;
+    NVDB_REQUIRE(explicit_l0 ? ((hd.flags & AR_L1_MASKS) && !(hd.nets_mask & (1u << NVDB_NET_L0)) &&
+                                !(hd.flags & AR_PATCHES))
+                             : hd.n_leaf == 0,
                  NVDB_E_INVALID, "corrupt archive header");
     const bool explicit_l1 = hd.flags & AR_L1_MASKS;
     NVDB_REQUIRE(explicit_l1 == !(hd.nets_mask & (1u << NVDB_NET_L1)), NVDB_E_INVALID,
@@ -2095,6 +2120,7 @@ nvdb_status nvdb_archive_decode(const uint8_t* buf, int64_t size, nvdb_tree** ou
           std::memcpy(&a[64 * i], r.take(512), 512);
         }
       }
+      const uint8_t* leaf_masks = explicit_l0 ? r.take(64 * hd.n_leaf) : nullptr;
       upper->l1_o.alloc(nl1);
       upper->l1_child.alloc(64 * nl1);
       upper->l1_active.alloc(64 * nl1);
@@ -2145,8 +2171,13 @@ nvdb_status nvdb_archive_decode(const uint8_t* buf, int64_t size, nvdb_tree** ou
       const int32_t* fp = (const int32_t*)r.take(12 * hd.n_fp);
       const int32_t* fn = (const int32_t*)r.take(12 * hd.n_fn);
       NVDB_REQUIRE(r.pos == size, NVDB_E_INVALID, "trailing bytes after the archive");
-      // the lower levels by inference, then the patches
-      pred = decode_topology_impl(model, upper, false, st);
+      // the lower levels by inference (or from the stored leaf masks), then the patches
+      DevBuf<uint64_t> lm;
+      if (explicit_l0) {
+        lm.alloc(std::max<int64_t>(8 * hd.n_leaf, 1));
+        if (hd.n_leaf) NVDB_HIP(hipMemcpy(lm.p, leaf_masks, 64 * (size_t)hd.n_leaf, hipMemcpyHostToDevice));
+      }
+      pred = decode_topology_impl(model, upper, false, st, explicit_l0 ? lm.p : nullptr, hd.n_leaf);
       nvdb_tree* result = pred;
       if (hd.flags & AR_PATCHES) {
         DevBuf<int32_t> dfp, dfn;
@@ -2177,6 +2208,7 @@ nvdb_status nvdb_archive_decode(const uint8_t* buf, int64_t size, nvdb_tree** ou
         info->n_l1 = hd.n_l1;
         info->n_fp = hd.n_fp;
         info->n_fn = hd.n_fn;
+        info->n_leaf = hd.n_leaf;
       }
       *out = result;
       pred = nullptr;

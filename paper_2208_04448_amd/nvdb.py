@@ -83,12 +83,14 @@ class Subdomains(C.Structure):
 
 
 class ArchiveDesc(C.Structure):
-    _fields_ = [("nets_mask", C.c_int32), ("storage", C.c_int32), ("explicit_l1", C.c_int32), ("patches", C.c_int32)]
+    _fields_ = [("nets_mask", C.c_int32), ("storage", C.c_int32), ("explicit_l1", C.c_int32), ("patches", C.c_int32),
+                ("explicit_l0", C.c_int32)]
 
 
 class ArchiveInfo(C.Structure):
     _fields_ = [("flags", C.c_int32), ("nets_mask", C.c_int32), ("rule_kind", C.c_int32), ("rule_thr", C.c_float),
-                ("n_l2", C.c_int64), ("n_l1", C.c_int64), ("n_fp", C.c_int64), ("n_fn", C.c_int64)]
+                ("n_l2", C.c_int64), ("n_l1", C.c_int64), ("n_fp", C.c_int64), ("n_fn", C.c_int64),
+                ("n_leaf", C.c_int64)]
 
 
 _SIGS = {
@@ -516,9 +518,12 @@ def topology_patches(truth, pred):
     return fp, fn
 
 
-def archive_write(model, truth, nets_mask, storage=STORE_F16, explicit_l1=False, patches=True):
-    """Compact byte image (bytes) of the model's networks in nets_mask for the volume `truth`."""
-    d = ArchiveDesc(int(nets_mask), int(storage), int(bool(explicit_l1)), int(bool(patches)))
+def archive_write(model, truth, nets_mask, storage=STORE_F16, explicit_l1=False, patches=None, explicit_l0=False):
+    """Compact byte image (bytes) of the model's networks in nets_mask for the volume `truth`
+    (patches default: stored unless the leaf masks are)."""
+    if patches is None:
+        patches = not explicit_l0
+    d = ArchiveDesc(int(nets_mask), int(storage), int(bool(explicit_l1)), int(bool(patches)), int(bool(explicit_l0)))
     n = C.c_int64()
     _check(_lib.nvdb_archive_write(model.h, truth.h, C.byref(d), None, 0, C.byref(n), _stream()))
     buf = (C.c_uint8 * n.value)()

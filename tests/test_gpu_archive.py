@@ -18,8 +18,8 @@ from oracle import tree as T
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
 
-HEADER = struct.Struct("<4sIIIiiff3ii3i3iII4q")
-assert HEADER.size == 112
+HEADER = struct.Struct("<4sIIIiiff3ii3i3iII5q")
+assert HEADER.size == 120
 
 
 def parse(buf, param_count):
@@ -27,7 +27,7 @@ def parse(buf, param_count):
     f = HEADER.unpack_from(buf, 0)
     hd = dict(magic=f[0], version=f[1], flags=f[2], storage=f[3], precision=f[4], rule_kind=f[5], rule_thr=f[6],
               value_scale=f[7], domain_lo=f[8:11], domain_size=f[11], grid_origin=f[12:15], grid_dims=f[15:18],
-              nets_mask=f[18], n_l2=f[20], n_l1=f[21], n_fp=f[22], n_fn=f[23])
+              nets_mask=f[18], n_l2=f[20], n_l1=f[21], n_fp=f[22], n_fn=f[23], n_leaf=f[24])
     pos = HEADER.size
     l2o, l2c = [], []
     for _ in range(hd["n_l2"]):
@@ -43,6 +43,8 @@ def parse(buf, param_count):
             l1c.append(np.frombuffer(buf, np.uint64, 64, pos))
             l1a.append(np.frombuffer(buf, np.uint64, 64, pos + 512))
             pos += 1024
+    leaf_mask = np.frombuffer(buf, np.uint64, 8 * hd["n_leaf"], pos).reshape(-1, 8)
+    pos += 64 * hd["n_leaf"]
     nets = {}
     for k in range(3):
         if not (hd["nets_mask"] >> k) & 1:
@@ -61,7 +63,7 @@ def parse(buf, param_count):
     pos += 12 * hd["n_fn"]
     return dict(header=hd, l2_origin=np.array(l2o).reshape(-1, 3), l2_child=np.array(l2c).reshape(-1, 512),
                 l1_origin=np.array(l1o).reshape(-1, 3), l1_child=np.array(l1c).reshape(-1, 64),
-                l1_active=np.array(l1a).reshape(-1, 64), nets=nets, fp=fp, fn=fn, end=pos)
+                l1_active=np.array(l1a).reshape(-1, 64), leaf_mask=leaf_mask, nets=nets, fp=fp, fn=fn, end=pos)
 
 
 def n_params(W, H, nf, C):
@@ -69,10 +71,11 @@ def n_params(W, H, nf, C):
     return K * W + W + (H - 1) * (W * W + W) + W * C + C
 
 
-def archive_size(n_l2, n_l1, explicit_l1, shapes, n_fp, n_fn):
-    """Bytes of the image by the documented layout."""
+def archive_size(n_l2, n_l1, explicit_l1, n_leaf, shapes, n_fp, n_fn):
+    """Bytes of the image by the documented layout (n_leaf: leaf masks stored)."""
     nets = sum(16 + 12 * nf + ((2 * n_params(W, H, nf, C) + 3) & ~3) for W, H, nf, C in shapes)
-    return 112 + n_l2 * (12 + 4096) + n_l1 * (12 + (1024 if explicit_l1 else 0)) + nets + 12 * (n_fp + n_fn)
+    return (120 + n_l2 * (12 + 4096) + n_l1 * (12 + (1024 if explicit_l1 else 0)) + 64 * n_leaf + nets
+            + 12 * (n_fp + n_fn))
 
 
 def codes16(theta, storage, lib):
@@ -113,24 +116,27 @@ def rounded(gpu_lib, m, prec, mask, storage):
     return r
 
 
-CASES = [  # (precision, storage, networks, level-1 masks stored)
-    ("fp32", "f16", 0b111, False),
-    ("bf16", "bf16", 0b101, False),
-    ("bf16", "f16", 0b011, True),
-    ("fp32", "bf16", 0b001, True),
+CASES = [  # (precision, storage, networks, level-1 masks stored, leaf masks stored)
+    ("fp32", "f16", 0b111, False, False),
+    ("bf16", "bf16", 0b101, False, False),
+    ("bf16", "f16", 0b011, True, False),
+    ("fp32", "bf16", 0b001, True, False),
+    ("bf16", "f16", 0b001, True, True),
 ]
 
 
-@pytest.mark.parametrize("prec,store,mask,explicit", CASES)
-def test_archive_round_trip(gpu_lib, fitted, prec, store, mask, explicit):
+@pytest.mark.parametrize("prec,store,mask,explicit,explicit_l0", CASES)
+def test_archive_round_trip(gpu_lib, fitted, prec, store, mask, explicit, explicit_l0):
     tr = fitted["tree"]
     m = fitted[prec]
     P = gpu_lib.FP32 if prec == "fp32" else gpu_lib.BF16
     S = gpu_lib.STORE_F16 if store == "f16" else gpu_lib.STORE_BF16
-    buf = gpu_lib.archive_write(m, tr, mask, S, explicit_l1=explicit, patches=True)
+    patches = not explicit_l0
+    buf = gpu_lib.archive_write(m, tr, mask, S, explicit_l1=explicit, patches=patches, explicit_l0=explicit_l0)
     a = parse(buf, n_params)
     hd = a["header"]
-    assert hd["magic"] == b"NVDB" and hd["version"] == 1 and hd["flags"] == (1 if explicit else 0) | 2
+    flags = (1 if explicit else 0) | (2 if patches else 0) | (4 if explicit_l0 else 0)
+    assert hd["magic"] == b"NVDB" and hd["version"] == 1 and hd["flags"] == flags
     assert (hd["storage"], hd["precision"], hd["rule_kind"], hd["nets_mask"]) == (S, P, T.SDF, mask)
     assert hd["rule_thr"] == 3.0 and hd["value_scale"] == 3.0 and hd["domain_size"] == 256
     assert hd["domain_lo"] == (0, 0, 0)
@@ -138,13 +144,17 @@ def test_archive_round_trip(gpu_lib, fitted, prec, store, mask, explicit):
     assert hd["grid_origin"] == tuple(ti.grid_origin) and hd["grid_dims"] == tuple(ti.grid_dims)
     # sizes: the parser ends where the image ends, and the layout's accounting agrees
     shapes = [NETS[k] for k in range(3) if (mask >> k) & 1]
-    assert a["end"] == len(buf) == archive_size(ti.n_l2, ti.n_l1, explicit, shapes, hd["n_fp"], hd["n_fn"])
+    assert hd["n_leaf"] == (ti.n_leaves if explicit_l0 else 0)
+    assert a["end"] == len(buf) == archive_size(ti.n_l2, ti.n_l1, explicit, hd["n_leaf"], shapes, hd["n_fp"],
+                                                hd["n_fn"])
     # upper levels as the tree holds them
     l2o, l2c = tr.export_l2()
     assert np.array_equal(a["l2_origin"], l2o) and np.array_equal(a["l2_child"], l2c)
     assert np.array_equal(a["l1_origin"], ex["l1_origin"])
     if explicit:
         assert np.array_equal(a["l1_child"], ex["l1_child"]) and not a["l1_active"].any()
+    if explicit_l0:
+        assert np.array_equal(a["leaf_mask"], ex["leaf_mask"])
     # networks: shapes, encodings exactly, parameters as round-to-nearest-even 16-bit codes
     for k, net in a["nets"].items():
         assert net["shape"] == NETS[k]
@@ -153,8 +163,11 @@ def test_archive_round_trip(gpu_lib, fitted, prec, store, mask, explicit):
     # patches: the difference between the truth and what the stored networks decode
     r = rounded(gpu_lib, m, P, mask, S)
     pred = r.decode_topology(tr)
-    fp, fn = gpu_lib.topology_patches(tr, pred)
-    assert np.array_equal(a["fp"], fp.cpu().numpy()) and np.array_equal(a["fn"], fn.cpu().numpy())
+    if patches:
+        fp, fn = gpu_lib.topology_patches(tr, pred)
+        assert np.array_equal(a["fp"], fp.cpu().numpy()) and np.array_equal(a["fn"], fn.cpu().numpy())
+    else:
+        assert hd["n_fp"] == 0 and hd["n_fn"] == 0
     # decode: the true topology exactly, the values of the stored regressor
     dt, info = gpu_lib.archive_decode(buf)
     assert (info.n_l2, info.n_l1, info.n_fp, info.n_fn) == (ti.n_l2, ti.n_l1, hd["n_fp"], hd["n_fn"])
@@ -163,6 +176,8 @@ def test_archive_round_trip(gpu_lib, fitted, prec, store, mask, explicit):
         assert np.array_equal(de[key], ex[key]), key
     want, _ = r.decode(tr, values=True, masks=False)
     assert np.array_equal(de["values"], want.cpu().numpy())
+    if explicit_l0:
+        return
     # without patches the image decodes to what the networks predict, no more
     buf0 = gpu_lib.archive_write(m, tr, mask, S, explicit_l1=explicit, patches=False)
     assert len(buf0) == len(buf) - 12 * (hd["n_fp"] + hd["n_fn"])
@@ -199,6 +214,15 @@ def test_archive_rejects_corrupt_images(gpu_lib, fitted):
         with pytest.raises(gpu_lib.NvdbError) as e:
             gpu_lib.archive_decode(b)
         assert e.value.code == gpu_lib.E_INVALID, i
+    # stored leaf masks whose count disagrees with the header
+    b5 = gpu_lib.archive_write(fitted["bf16"], tr, 0b001, gpu_lib.STORE_F16, explicit_l1=True, explicit_l0=True)
+    n_leaf_at = HEADER.size - 8
+    n_leaf = struct.unpack_from("<q", b5, n_leaf_at)[0]
+    assert n_leaf == tr.info().n_leaves
+    for wrong in (n_leaf - 1, n_leaf + 1, -1):
+        with pytest.raises(gpu_lib.NvdbError) as e:
+            gpu_lib.archive_decode(b5[:n_leaf_at] + struct.pack("<q", wrong) + b5[HEADER.size:])
+        assert e.value.code == gpu_lib.E_INVALID, wrong
     t, _ = gpu_lib.archive_decode(buf)  # the library still works after the rejections
     assert t.info().n_voxels == tr.info().n_voxels
 
@@ -209,6 +233,12 @@ def test_archive_write_rejects_bad_descriptions(gpu_lib, fitted):
         with pytest.raises(gpu_lib.NvdbError) as e:
             gpu_lib.archive_write(m, tr, mask, gpu_lib.STORE_F16, explicit_l1=explicit)
         assert e.value.code == gpu_lib.E_INVALID, (mask, explicit)
+    # stored leaf masks: need the level-1 masks, exclude the level-0 classifier and patches
+    for mask, explicit, patches in ((0b101, False, False), (0b011, True, False), (0b001, True, True)):
+        with pytest.raises(gpu_lib.NvdbError) as e:
+            gpu_lib.archive_write(m, tr, mask, gpu_lib.STORE_F16, explicit_l1=explicit, patches=patches,
+                                  explicit_l0=True)
+        assert e.value.code == gpu_lib.E_INVALID, (mask, explicit, patches)
     with pytest.raises(gpu_lib.NvdbError) as e:
         gpu_lib.archive_write(m, tr, 0b001, 7, explicit_l1=True)
     assert e.value.code == gpu_lib.E_INVALID
