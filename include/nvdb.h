@@ -126,8 +126,10 @@ enum { NVDB_FP32 = 0, NVDB_BF16 = 1 };
  * layers of width W, an identity head with n_out outputs.  Parameter count
  * P = K W + W + (H-1)(W^2+W) + W n_out + n_out, canonical flat layout
  * W1, b1, W2, b2, ..., W_{H+1}, b_{H+1} with each W row-major [out][in].
- * Kernels exist for W in {64, 128}, H in {2, 3, 4}, 2 n_freq <= 128,
- * n_out in {1, 3}. */
+ * Kernels exist, with KP = max(64, K rounded up to a multiple of 32), for
+ * (W, H, KP, n_out) in {(64, 3, 64, 1), (64, 4, 128, 3), (128, 4, 128, 1),
+ * (128, 3, 128, 1)} in both precisions and (128, 3, 256, 1) in BF16 (as many
+ * Fourier features as the width); other shapes fail with E_UNSUPPORTED. */
 typedef struct {
   int32_t width;
   int32_t hidden;

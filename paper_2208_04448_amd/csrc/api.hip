@@ -290,7 +290,7 @@ nvdb_status nvdb_model_create(const nvdb_model_desc* desc, nvdb_model** out) {
         any = true;
         Net& n = m->nets[k];
         const nvdb_net_desc& d = desc->net[k];
-        NVDB_REQUIRE(d.n_freq > 0 && 2 * d.n_freq <= 128, NVDB_E_UNSUPPORTED, "n_freq must be in 1..64");
+        NVDB_REQUIRE(d.n_freq > 0 && 2 * d.n_freq <= 256, NVDB_E_UNSUPPORTED, "n_freq must be in 1..128");
         NVDB_REQUIRE(d.n_out == 1 || d.n_out == 3, NVDB_E_UNSUPPORTED, "n_out must be 1 or 3");
         NVDB_REQUIRE(k != NVDB_NET_L1 || d.n_out == 3, NVDB_E_INVALID, "the level-1 classifier has 3 outputs");
         NVDB_REQUIRE(k == NVDB_NET_L1 || d.n_out == 1, NVDB_E_INVALID, "regressor and level-0 classifier have 1 output");
@@ -2143,7 +2143,7 @@ nvdb_status nvdb_archive_decode(const uint8_t* buf, int64_t size, nvdb_tree** ou
         if (!(hd.nets_mask & (1u << k))) continue;
         int32_t desc[4];
         std::memcpy(desc, r.take(16), 16);
-        NVDB_REQUIRE(desc[2] >= 1 && desc[2] <= 64 && desc[0] > 0 && desc[1] > 0 && desc[3] > 0, NVDB_E_INVALID,
+        NVDB_REQUIRE(desc[2] >= 1 && desc[2] <= 128 && desc[0] > 0 && desc[1] > 0 && desc[3] > 0, NVDB_E_INVALID,
                      "corrupt network shape");
         d.has_net[k] = 1;
         d.net[k] = nvdb_net_desc{desc[0], desc[1], desc[2], desc[3]};

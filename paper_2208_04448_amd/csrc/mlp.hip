@@ -49,7 +49,7 @@ struct TrainCfg {
   // BF16 4x128 with layers 1.. resident: layer 0's dW accumulates in LDS (a
   // wave-private fp32 region) instead of the partial row; the dX products then
   // read their weight fragments from HBM/L2, which frees the LDS weight copy.
-  static constexpr bool DW0_LDS = DWREG && W >= 128 && DWREG_FROM == 1;
+  static constexpr bool DW0_LDS = DWREG && W >= 128 && DWREG_FROM == 1 && KP <= 128;
   static constexpr bool DX_HBM = DW0_LDS;
   static constexpr bool lds_layer(int l) { return DW0_LDS && l == 0; }
   static constexpr bool fold_layer(int l) { return !reg_layer(l) && !lds_layer(l); }
@@ -60,7 +60,13 @@ struct TrainCfg {
   // The FP32 form keeps the last hidden layer's rows in a private buffer per wave
   // instead (written right after the forward pass) to free its registers.
   static constexpr bool HH_PRIVATE = (PREC != NVDB_BF16);
-  static constexpr int SLOT_BYTES = (HH_PRIVATE ? 2 : 3) * ROWS_BYTES + 32 * C * 4;
+  // BF16: layer 0's input rows in panels of 128 features, each one 256-byte row per
+  // sample; panel 0 follows the G rows, further panels follow gy.
+  static constexpr int XPANELS = (PREC == NVDB_BF16 && KP > 128) ? KP / 128 : 1;
+  static_assert(XPANELS == 1 || KP % 128 == 0, "input panels of 128 features");
+  static constexpr int XP_OFF = (HH_PRIVATE ? 2 : 3) * ROWS_BYTES + 32 * C * 4;
+  static constexpr int SLOT_BYTES = XP_OFF + (XPANELS - 1) * ROWS_BYTES;
+  static __device__ __forceinline__ int xpanel(int p) { return p == 0 ? ROWS_BYTES : XP_OFF + (p - 1) * ROWS_BYTES; }
   static constexpr int HH_BYTES = HH_PRIVATE ? 4 * ROWS_BYTES : 0;
   static constexpr int WL_BYTES = (PREC == NVDB_BF16 && !DX_HBM) ? (H - 1) * W * 256 : 0;
   static constexpr int DW0_BYTES = DW0_LDS ? W * KP * 4 : 0;  // [wave][a][b][quad][lane][4] floats
@@ -290,8 +296,15 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
           char* sl = slots + my_slot * CF::SLOT_BYTES;
           if constexpr (BF) {
             write_rows_bf16<NB>(sl, K, Gc);
-            if constexpr (l == 0) write_rows_bf16<NIB0>(sl + CF::ROWS_BYTES, K, X0);
-            else write_rows_bf16<NB>(sl + CF::ROWS_BYTES, K, Hs[l - 1 < 0 ? 0 : l - 1]);
+            if constexpr (l == 0) {
+              constexpr int NP = NIB0 / CF::XPANELS;
+              static_for<0, CF::XPANELS>([&](auto pc) {
+                constexpr int pn = decltype(pc)::value;
+                write_rows_bf16<NP>(sl + CF::xpanel(pn), K, *reinterpret_cast<const uint32_t(*)[NP][8]>(&X0[NP * pn]));
+              });
+            } else {
+              write_rows_bf16<NB>(sl + CF::ROWS_BYTES, K, Hs[l - 1 < 0 ? 0 : l - 1]);
+            }
             if constexpr (HEAD) write_rows_bf16<NB>(sl + 2 * CF::ROWS_BYTES, K, Hs[H - 1]);
           } else {
             write_rows_f32<NB>((float*)sl, CF::RB, K, Gc);
@@ -327,7 +340,8 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
             for (int b = 0; b < CF::IBWMAX; ++b) {
               if (b < IBWl) {
                 const int ib = wi * IBWl + b;
-                if constexpr (BF) hb[b] = frag_tr(sl + CF::ROWS_BYTES, K, 16 * kk, ib);
+                constexpr int NP = (l == 0) ? NIB0 / CF::XPANELS : NB;
+                if constexpr (BF) hb[b] = frag_tr(sl + ((l == 0) ? CF::xpanel(ib / NP) : CF::ROWS_BYTES), K, 16 * kk, ib % NP);
                 else hb[b] = ((const float*)(sl + CF::ROWS_BYTES))[(2 * kk + h) * CF::RB + 32 * ib + fl];
               }
             }
@@ -627,8 +641,8 @@ __global__ void __launch_bounds__(64 * INFER_WAVES, 1)
       constexpr int NIBl = (l == 0) ? NIB0 : NB;
       WFwd<PREC, W, NIBl> wf{wl + (size_t)l * (W / 32) * CF::BSTRIDE,
                              (const u32x4*)((const __bf16*)nv.wfrag + (l == 0 ? 0 : (size_t)W * KP + (size_t)(l - 1) * W * W)) + z,
-                             (const float*)nv.wcol + z + (l == 0 ? 0 : (size_t)KP * W + (size_t)(l - 1) * W * W), false,
-                             &K, CF::BSTRIDE};
+                             (const float*)nv.wcol + z + (l == 0 ? 0 : (size_t)KP * W + (size_t)(l - 1) * W * W),
+                             BF && l == 0 && KP > ROW_ELEMS, &K, CF::BSTRIDE};
       uint32_t Bn[NT][NB][SR];
 #pragma unroll
       for (int ob = 0; ob < NB; ++ob) {
@@ -1033,8 +1047,9 @@ __device__ __forceinline__ void write_shadow(const AdamNet& A, int64_t p, float 
   const int win = s.win(l);
   const int o = (int)((p - s.woff(l)) / win), i = (int)((p - s.woff(l)) % win);
   if (A.prec == NVDB_BF16) {
+    // 256-byte rows (the LDS image): layer 0 only when its inputs fit one row
     __bf16* rows = (__bf16*)A.wrow + (size_t)l * s.W * ROW_ELEMS;
-    rows[(size_t)o * ROW_ELEMS + swz_elem(o, i)] = (__bf16)th;
+    if (l > 0 || s.KP <= ROW_ELEMS) rows[(size_t)o * ROW_ELEMS + swz_elem(o, i)] = (__bf16)th;
     {
       // forward A fragment (ob, t, kk): lane (r, g) element e holds
       // W[32 ob + r][32 t + 16 kk + 8 (e >> 2) + 4 g + (e & 3)]
@@ -1193,6 +1208,12 @@ bool find_kernels(int prec, int W, int H, int KP, int C, KernelSet* out) {
   }
   NVDB_FOR_SHAPES(NVDB_MATCH)
 #undef NVDB_MATCH
+  // Fourier features as many as the width (m = W = 128, K = 256), BF16 form only: the
+  // FP32 form's 256-float input rows do not fit the LDS next to its other buffers
+  if (prec == NVDB_BF16 && W == 128 && H == 3 && KP == 256 && C == 1) {
+    *out = make_set<NVDB_BF16, 128, 3, 256, 1>();
+    return true;
+  }
   return false;
 }
 

@@ -293,6 +293,58 @@ def test_backward_parity(gpu_lib, record, prec, shape, n):
         assert max(errs_b) <= BF16_FORM_GRAD_TOL["pe" if shape[2] == 18 else "ffm"], errs_b
 
 
+def test_ffm_features_as_many_as_width(gpu_lib, record, sphere):
+    """Fourier features as many as the network's width (m = W = 128, K = 256 inputs,
+    3x128, the hyper-parameter heuristic of the appendix), BF16 form: forward and
+    random-cotangent gradients against the FP64 oracle and its BF16 form, a short
+    fit's losses against the oracle drawing the same samples, and the shape refused
+    in the FP32 form."""
+    shape = (128, 3, 128, 1, 0)
+    model, theta, B, shapes = model_for(gpu_lib, shape, gpu_lib.BF16)
+    params = mlp.unflatten(theta, shapes)
+    for n in (33, 4097):
+        x = np.random.default_rng(n).random((n, 3)).astype(np.float32)
+        y = model.forward_coords(0, torch.from_numpy(x).to(DEV)).cpu().numpy()
+        yo = mlp.predict(params, x.astype(np.float64), B)
+        yb, _ = bf16_form.forward_bf16(params, mlp.encode(x.astype(np.float64), B))
+        err = float(np.max(np.abs(y - yo) / (1 + np.abs(yo))))
+        err_b = float(np.max(np.abs(y - yb) / (1 + np.abs(yb))))
+        record("forward_bf16_3x128_m128_n%d" % n, err=err, err_bf16_form=err_b)
+        assert err <= BF16_FWD_TOL and err_b <= BF16_FORM_FWD_TOL["ffm"], (err, err_b)
+    n = 3000
+    rng = np.random.default_rng(8)
+    x = rng.random((n, 3)).astype(np.float32)
+    gy = rng.standard_normal((n, 1)).astype(np.float32)
+    model.reserve_dev(0, n)
+    g = model.backward_coords(0, torch.from_numpy(x).to(DEV), torch.from_numpy(gy).to(DEV)).cpu().numpy()
+    _, cb = bf16_form.forward_bf16(params, mlp.encode(x.astype(np.float64), B))
+    gb = mlp.flatten(bf16_form.backward_bf16(params, cb, gy.astype(np.float64)))
+    go = F.param_grad(theta, shapes, B, x.astype(np.float64), gy.astype(np.float64))
+    errs, errs_b = tensor_errors(g.astype(np.float64), go, shapes), tensor_errors(g.astype(np.float64), gb, shapes)
+    record("backward_bf16_3x128_m128", elem=max(errs), elem_bf16_form=max(errs_b))
+    assert max(errs) <= BF16_RAND_GRAD_TOL and max(errs_b) <= BF16_FORM_GRAD_TOL["ffm"], (errs, errs_b)
+    # a short fit on the 64^3 sphere: per-step losses against the oracle
+    tr, ot = sphere
+    fm, th, Bf, sh = model_for(gpu_lib, shape, gpu_lib.BF16, domain=64, seed=3)
+    L = fm.fit(tr, steps=4, batch=4096, nets_mask=1, seed=2, lr=1e-3)
+    _, _, _, lo_ = F.train(th, sh, Bf, ot, "regressor", (0, 0, 0), 64, T.SDF, 3.0, steps=4, batch=4096, seed=2,
+                           lr0=1e-3)
+    rel = np.abs(np.asarray(L[0][:4], np.float64) - np.asarray(lo_)) / np.asarray(lo_)
+    record("fit_bf16_3x128_m128", rel_loss=float(rel.max()))
+    assert rel.max() <= 2e-2, rel
+    # decode of every voxel with the fitted weights, BF16 and FP8 forms
+    thf = fm.get_params(0).astype(np.float64)
+    vb, _ = fm.decode(tr, values=True, masks=False)
+    vo = F.decode_values(thf, sh, Bf, ot, (0, 0, 0), 64, T.SDF, 3.0) / 3.0
+    assert np.max(np.abs(vb.cpu().numpy() / 3.0 - vo) / (1 + np.abs(vo))) <= BF16_FWD_TOL
+    v8, _ = fm.decode(tr, values=True, masks=False, fp8=True)
+    vo8 = F.decode_values(thf, sh, Bf, ot, (0, 0, 0), 64, T.SDF, 3.0, fp8=True) / 3.0
+    assert np.max(np.abs(v8.cpu().numpy() / 3.0 - vo8)) <= 3e-2
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        gpu_lib.Model({0: (128, 3, 128, 1)}, precision=gpu_lib.FP32, domain_size=64, value_scale=3.0)
+    assert e.value.code == gpu_lib.E_UNSUPPORTED
+
+
 def test_backward_deterministic(gpu_lib):
     model, theta, B, shapes = model_for(gpu_lib, SHAPES[1], gpu_lib.BF16)
     x = torch.rand(50000, 3, device=DEV, generator=torch.Generator(DEV).manual_seed(3))
@@ -763,6 +815,64 @@ def test_fit_sequence_matches_oracle(gpu_lib):
             upd = np.linalg.norm(tho - start)
             rel = np.linalg.norm(fp[f, k * P:(k + 1) * P] - tho) / max(upd, 1e-30)
             assert rel <= 2e-2, (k, f, rel)
+
+
+def test_fit_sequence_bf16_replay(gpu_lib):
+    """The benchmark's kind of sequence in the BF16 form: three frames of an
+    advected water surface (64 x 32 x 64, band 3, wet region growing), regressor
+    and level-0 classifier 4x128 with Fourier features m = 64 (the activation-rows
+    training kernel), frame 0 cold then refit, frames 1-2 warm-started with the
+    device-side stop test.  Stop decisions follow the library's own losses exactly;
+    the cold pass's first steps and every warm frame, replayed by the FP64 oracle
+    from the library's weights at the start of that frame, agree to the BF16
+    bounds."""
+    frames = [workloads.water_frame(t, nx=64, ny=32, nz=64, speed=1.0, base=16.0, amp=4.0, scale=16.0, wet0=40.0,
+                                    wet1=64.0, n_frames=3) for t in range(3)]
+    trees = [gpu_lib.Tree(v.to(DEV), (0, 0, 0), T.SDF, 3.0) for v in frames]
+    otrees = [T.build(*T.active_set_dense(v.numpy(), (0, 0, 0), T.SDF, 3.0)) for v in frames]
+    Wd, Hd, md = 128, 4, 64
+    shapes = mlp.layer_shapes(2 * md, Wd, Hd, 1)
+    Bs = {k: workloads.ffm_matrix(md, 10.0, seed=60 + k) for k in (0, 1)}
+    th0 = {k: workloads.init_params(2 * md, Wd, Hd, 1, seed=62 + k) for k in (0, 1)}
+    cold = dict(steps=60, batch=4096, seed=3, lr=1e-3, lr_decay=0.975, lr_interval=100)
+    warm = dict(steps=15, batch=4096, seed=11, lr=1e-4, lr_decay=0.975, lr_interval=100)
+    S = warm["steps"]
+    LTOL = 2e-2  # BF16 losses against FP64 over a replayed frame
+    m = gpu_lib.Model({0: (Wd, Hd, md, 1), 1: (Wd, Hd, md, 1)}, precision=gpu_lib.BF16, domain_size=64,
+                      value_scale=3.0)
+    for k in (0, 1):
+        m.set_params(k, th0[k])
+        m.set_encoding(k, Bs[k])
+    reps, L, fp = m.fit_sequence(trees, cold, warm, nets_mask=3, use_graph=True)
+    fp = fp.cpu().numpy()
+    P = mlp.param_count(2 * md, Wd, Hd, 1)
+    c0 = cold["steps"] + warm["steps"]
+    for k, net in ((0, "regressor"), (1, "l0")):
+        target = L[k, c0 - 1]
+        assert reps[0][0][k] == c0
+        for f in range(1, 3):
+            seg = L[k, c0 + (f - 1) * S: c0 + f * S]
+            below = np.nonzero(seg < target)[0]
+            want = below[0] + 1 if len(below) else S
+            assert reps[f][0][k] == want, (k, f, seg, target)
+        B = Bs[k].astype(np.float64)
+        _, _, _, lc = F.train(th0[k].astype(np.float64), shapes, B, otrees[0], net, (0, 0, 0), 64, T.SDF, 3.0, 5,
+                              cold["batch"], seed=cold["seed"], lr0=cold["lr"])
+        assert np.max(np.abs(L[k, :5] - lc) / lc) <= LTOL
+        for f in range(1, 3):
+            start = fp[f - 1, k * P:(k + 1) * P].astype(np.float64)
+            tho, _, _, lo = F.train(start, shapes, B, otrees[f], net, (0, 0, 0), 64, T.SDF, 3.0, S, warm["batch"],
+                                    seed=warm["seed"] + f, lr0=warm["lr"], stop_below=float(target))
+            r = reps[f][0][k]
+            seg = L[k, c0 + (f - 1) * S: c0 + (f - 1) * S + r]
+            n = min(r, len(lo))
+            assert np.max(np.abs(seg[:n] - lo[:n]) / lo[:n]) <= LTOL, (k, f)
+            if r != len(lo):
+                assert abs(lo[n - 1] - target) <= 2 * LTOL * target, (k, f, r, len(lo))
+                continue
+            upd = np.linalg.norm(tho - start)
+            rel = np.linalg.norm(fp[f, k * P:(k + 1) * P] - tho) / max(upd, 1e-30)
+            assert rel <= 0.3, (k, f, rel)
 
 
 def test_fit_sequence_graph_chunks(gpu_lib, sphere):
