@@ -761,8 +761,9 @@ nvdb_status nvdb_fit_experts(nvdb_model* const* models, const nvdb_tree* const* 
     }
     const Phase ph{fit->batch, fit->seed, fit->lr, fit->lr_decay, fit->lr_interval, nullptr};
     hipStream_t st = (hipStream_t)stream;
-    // A one-network training launch at the default 128 work-groups holds half of
-    // the 256 compute units: two streams let two experts' steps run side by side.
+    // A one-network training launch at 128 work-groups (the count the autotuner
+    // picks for the 4x128 networks) holds half of the 256 compute units: two
+    // streams let two experts' steps run side by side.
     // Steps are enqueued step-major across the experts, so that a full hardware
     // queue on one stream never leaves the other without work.
     constexpr int NS = 2;
