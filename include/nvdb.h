@@ -135,6 +135,11 @@ typedef struct {
   int32_t hidden;
   int32_t n_freq;
   int32_t n_out;
+  /* Hidden activation (App. on activation functions): 0 for ReLU, w > 0 for
+   * sin(w z) on every hidden layer (the appendix uses w in 1.5 .. 3).  Kernels for
+   * sin exist for (W, H, KP, n_out) = (64, 3, 64, 1) in both precisions and
+   * (128, 3, 256, 1) in BF16; they have no FP8 form. */
+  float sin_freq;
 } nvdb_net_desc;
 
 typedef struct {
@@ -484,7 +489,8 @@ nvdb_status nvdb_query_noalloc(const nvdb_model* model, const nvdb_tree* tree, c
  * stored ([Hash,5,4,NN(3)]: only the voxel values are neural), each leaf's
  * 512-bit mask (64 B) in canonical leaf order; per network
  * (regressor, level-0, level-1 classifier, those in nets_mask) its shape
- * int32[4] (width, hidden, n_freq, n_out), encoding float32[n_freq][3] and
+ * int32[4] (width, hidden, n_freq, n_out) and sin frequency float32 (0: ReLU),
+ * encoding float32[n_freq][3] and
  * parameters uint16[P] rounded to nearest even (padded to 4 bytes); then the
  * false-positive and false-negative voxel coordinates int32[n][3].
  * nvdb_archive_write: the archive of `model`'s networks for the volume `truth`

@@ -13,17 +13,21 @@ decoding, and this module defines it:
     bf16(W_l) and the layer input (bf16 of the mapped features gamma(x) for
     the first layer, the stored activations for the others); the products are
     summed exactly and the float32 bias added;
-  * each hidden activation is stored as h_l = bf16(ReLU(z_l));
+  * each hidden activation is stored as h_l = bf16(act(z_l)) (ReLU, or
+    sin(omega z_l) with its derivative factor stored as d_l = bf16(omega cos(omega z_l)));
   * the identity head multiplies the stored h_H by its unrounded weights;
   * backward, with the output gradient gy unrounded: the head's input
     gradient g_H = bf16((W_head^T gy) * 1[z_H > 0]) is stored in bfloat16,
     dW_head = sum gy h_H^T, db_head = sum gy; for each hidden layer
     dW_l = sum g_l h_{l-1}^T and db_l = sum g_l of the stored bfloat16 values,
-    and g_{l-1} = bf16((bf16(W_l)^T g_l) * 1[z_{l-1} > 0]).
+    and g_{l-1} = bf16((bf16(W_l)^T g_l) * d_{l-1}) with d = 1[z > 0] for ReLU
+    (the head's input gradient likewise).
 Where all of these values are already bfloat16 numbers the form equals the
 plain float64 pass of oracle.mlp.
 """
 import numpy as np
+
+from . import mlp
 
 
 def round_bf16(v):
@@ -59,11 +63,12 @@ def round_bf16(v):
 def forward_bf16(params, z0):
     """Forward pass of the BF16 form on mapped features z0 (n, K).  Returns the
     output (n, c) and the cache [h_0, z_1, h_1, ..., z_H, h_H] of stored values."""
+    omega = getattr(params, "omega", 0.0)
     h = round_bf16(z0)
     cache = [h]
     for Wl, bl in params[:-1]:
         z = h @ round_bf16(Wl).T + bl
-        h = round_bf16(np.maximum(z, 0.0))
+        h = round_bf16(mlp.activation(z, omega))
         cache += [z, h]
     Wo, bo = params[-1]
     return h @ Wo.T + bo, cache
@@ -72,14 +77,19 @@ def forward_bf16(params, z0):
 def backward_bf16(params, cache, gy):
     """Parameter gradient [(dW_l, db_l)] of the BF16 form for output gradients gy (n, c)."""
     H = len(params) - 1
+    omega = getattr(params, "omega", 0.0)
+
+    def factor(z):  # the stored derivative factor d of a hidden layer
+        d = mlp.activation_grad(z, omega)
+        return d if omega == 0 else round_bf16(d)
     gy = np.asarray(gy, np.float64)
     Wo, _ = params[H]
     grads = [None] * (H + 1)
     grads[H] = (gy.T @ cache[2 * H], gy.sum(axis=0))
-    g = round_bf16((gy @ Wo) * (cache[2 * H - 1] > 0))
+    g = round_bf16((gy @ Wo) * factor(cache[2 * H - 1]))
     for l in range(H - 1, -1, -1):
         grads[l] = (g.T @ cache[2 * l], g.sum(axis=0))
         if l > 0:
             Wl, _ = params[l]
-            g = round_bf16((g @ round_bf16(Wl)) * (cache[2 * l - 1] > 0))
+            g = round_bf16((g @ round_bf16(Wl)) * factor(cache[2 * l - 1]))
     return grads

@@ -76,7 +76,10 @@ def quantize_activations(h):
 
 
 def forward_fp8(params, z0):
-    """FP8-form forward of an MLP given as [(W_1, b_1), ..., (W_H, b_H), (W_out, b_out)]."""
+    """FP8-form forward of an MLP given as [(W_1, b_1), ..., (W_H, b_H), (W_out, b_out)]
+    (ReLU networks only)."""
+    if getattr(params, "omega", 0.0) != 0:
+        raise ValueError("the FP8 form is defined for ReLU networks only")
     h = np.asarray(z0, np.float64)
     for Wl, bl in params[:-1]:
         Wq, sw = quantize_weights(Wl)

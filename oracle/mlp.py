@@ -16,6 +16,10 @@ Readings taken where the paper is silent:
   * feature mapping: gamma(x) = [cos(2 pi B x) ; sin(2 pi B x)] with B of shape
     (m, 3).  Positional encoding with L octaves is the special case whose row
     3k+d is 2^(k-1) e_d, giving cos/sin(2^k pi x_d).
+  * hidden activation ReLU, or sin(omega z) on every hidden layer with
+    derivative omega cos(omega z) (appendix on activation functions: sin with
+    frequency 1.5 to 3 for smooth volumes; the frequency is read as a factor on
+    the pre-activation of each hidden layer, the head staying linear);
   * ReLU'(0) = 0; Adam with beta1 0.9, beta2 0.999, eps 1e-8 added outside
     the square root, no weight decay; lr_s = lr0 * 0.975^floor((s-1)/100).
   * per-sample squared error averaged over the batch (the subscript missing
@@ -25,9 +29,32 @@ import numpy as np
 
 
 # ----------------------------------------------------------------------------- architecture
-def layer_shapes(K, W, H, c):
+class Shapes(list):
+    """Weight shapes [(out, in)] of the layers, with the hidden activation:
+    omega = 0 for ReLU, omega > 0 for sin(omega z)."""
+    omega = 0.0
+
+
+class Params(list):
+    """Layer parameters [(W_l, b_l)], with the hidden activation as in Shapes."""
+    omega = 0.0
+
+
+def layer_shapes(K, W, H, c, omega=0.0):
     """Weight shapes [(out, in)] of an H x W MLP with K inputs and c outputs."""
-    return [(W, K)] + [(W, W)] * (H - 1) + [(c, W)]
+    s = Shapes([(W, K)] + [(W, W)] * (H - 1) + [(c, W)])
+    s.omega = float(omega)
+    return s
+
+
+def activation(z, omega):
+    """Hidden activation: ReLU (omega = 0) or sin(omega z)."""
+    return np.maximum(z, 0.0) if omega == 0 else np.sin(omega * z)
+
+
+def activation_grad(z, omega):
+    """Derivative of the hidden activation at z: 1[z > 0] or omega cos(omega z)."""
+    return (z > 0).astype(np.float64) if omega == 0 else omega * np.cos(omega * z)
 
 
 def param_count(K, W, H, c):
@@ -38,7 +65,8 @@ def param_count(K, W, H, c):
 def unflatten(theta, shapes):
     """Canonical flat layout W1, b1, W2, b2, ... with W_l row-major [out][in]."""
     theta = np.asarray(theta, dtype=np.float64)
-    params, o = [], 0
+    params, o = Params(), 0
+    params.omega = getattr(shapes, "omega", 0.0)
     for (n_out, n_in) in shapes:
         Wl = theta[o:o + n_out * n_in].reshape(n_out, n_in); o += n_out * n_in
         bl = theta[o:o + n_out]; o += n_out
@@ -79,14 +107,15 @@ def encode(x, B):
 
 # ----------------------------------------------------------------------------- forward
 def forward(params, z0):
-    """MLP forward: z_l = W_l h_{l-1} + b_l, h_l = ReLU(z_l), identity head.
+    """MLP forward: z_l = W_l h_{l-1} + b_l, h_l = act(z_l), identity head.
 
     Returns the output (n, c) and the cache [h_0, z_1, h_1, ..., z_H, h_H]."""
+    omega = getattr(params, "omega", 0.0)
     h = np.asarray(z0, np.float64)
     cache = [h]
     for Wl, bl in params[:-1]:
         z = h @ Wl.T + bl
-        h = np.maximum(z, 0.0)
+        h = activation(z, omega)
         cache += [z, h]
     Wo, bo = params[-1]
     return h @ Wo.T + bo, cache
@@ -152,10 +181,11 @@ def backward(params, cache, gy):
 
     For the head and each hidden layer l (top down):
       dW_l = sum_b g_l h_{l-1}^T,  db_l = sum_b g_l,
-      g_{l-1} = (W_l^T g_l) * 1[z_{l-1} > 0],
+      g_{l-1} = (W_l^T g_l) * act'(z_{l-1}),
     stopping at the mapped features (no gradient into gamma).
     Returns [(dW_l, db_l)] in layer order."""
     H = len(params) - 1
+    omega = getattr(params, "omega", 0.0)
     g = np.asarray(gy, np.float64)
     grads = [None] * (H + 1)
     for l in range(H, -1, -1):
@@ -164,7 +194,7 @@ def backward(params, cache, gy):
         grads[l] = (g.T @ h_in, g.sum(axis=0))
         if l > 0:
             z_prev = cache[2 * l - 1]
-            g = (g @ Wl) * (z_prev > 0)
+            g = (g @ Wl) * activation_grad(z_prev, omega)
     return grads
 
 

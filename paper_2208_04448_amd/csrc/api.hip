@@ -111,6 +111,9 @@ static NetView net_view(const Net& n) {
   v.bhead = n.bhead.p;
   v.benc = n.benc.p;
   v.nfreq = n.d.n_freq;
+  v.act_w = n.d.sin_freq;
+  v.act_rev64 = (double)n.d.sin_freq / (2.0 * 3.14159265358979323846);
+  v.act_rev = (float)v.act_rev64;
   return v;
 }
 
@@ -302,10 +305,13 @@ nvdb_status nvdb_model_create(const nvdb_model_desc* desc, nvdb_model** out) {
         n.s.W = d.width;
         n.s.H = d.hidden;
         n.s.C = d.n_out;
-        NVDB_REQUIRE(find_kernels(n.prec, d.width, d.hidden, n.s.KP, d.n_out, &n.ks), NVDB_E_UNSUPPORTED,
+        NVDB_REQUIRE(std::isfinite(d.sin_freq) && d.sin_freq >= 0.f && d.sin_freq <= 64.f, NVDB_E_INVALID,
+                     "sin frequency must be 0 (ReLU) or in (0, 64]");
+        const int act = d.sin_freq > 0.f ? ACT_SIN : ACT_RELU;
+        NVDB_REQUIRE(find_kernels(n.prec, d.width, d.hidden, n.s.KP, d.n_out, act, &n.ks), NVDB_E_UNSUPPORTED,
                      "no kernel for this network shape (width " + std::to_string(d.width) + ", hidden " +
                          std::to_string(d.hidden) + ", inputs " + std::to_string(n.s.KP) + ", outputs " +
-                         std::to_string(d.n_out) + ")");
+                         std::to_string(d.n_out) + (act == ACT_SIN ? ", sin activation" : "") + ")");
         if (n.prec == NVDB_BF16 && d.n_freq == 64 && n.ks.train_rows && !std::getenv("NVDB_TRAIN_CLASSIC"))
           n.ks.train = n.ks.train_rows;
         const int64_t P = n.s.nparams();
@@ -1842,7 +1848,6 @@ constexpr uint32_t ARCHIVE_VERSION = 1;
 constexpr uint32_t AR_L1_MASKS = 1u, AR_PATCHES = 2u, AR_L0_MASKS = 4u;
 
 int64_t pad4(int64_t n) { return (n + 3) & ~int64_t(3); }
-int64_t net_bytes(const NetShape& s, int32_t n_freq) { return 16 + 12 * (int64_t)n_freq + pad4(2 * s.nparams()); }
 
 struct Writer {
   uint8_t* buf;
@@ -2047,6 +2052,7 @@ nvdb_status nvdb_archive_write(const nvdb_model* m, const nvdb_tree* truth, cons
       const Net& N = m->nets[k];
       const int32_t desc[4] = {N.d.width, N.d.hidden, N.d.n_freq, N.d.n_out};
       w.put(desc, 16);
+      w.put(&N.d.sin_freq, 4);
       std::vector<float> b(4 * (size_t)(N.s.KP / 2));
       NVDB_HIP(hipMemcpy(b.data(), N.benc.p, b.size() * 4, hipMemcpyDeviceToHost));
       for (int i = 0; i < N.d.n_freq; ++i) w.put(&b[4 * i], 12);
@@ -2143,11 +2149,13 @@ nvdb_status nvdb_archive_decode(const uint8_t* buf, int64_t size, nvdb_tree** ou
       for (int k = 0; k < NVDB_MAX_NETS; ++k) {
         if (!(hd.nets_mask & (1u << k))) continue;
         int32_t desc[4];
+        float sin_freq;
         std::memcpy(desc, r.take(16), 16);
+        std::memcpy(&sin_freq, r.take(4), 4);
         NVDB_REQUIRE(desc[2] >= 1 && desc[2] <= 128 && desc[0] > 0 && desc[1] > 0 && desc[3] > 0, NVDB_E_INVALID,
                      "corrupt network shape");
         d.has_net[k] = 1;
-        d.net[k] = nvdb_net_desc{desc[0], desc[1], desc[2], desc[3]};
+        d.net[k] = nvdb_net_desc{desc[0], desc[1], desc[2], desc[3], sin_freq};
         blobs[k].B = r.take(12 * (int64_t)desc[2]);
         NetShape s{};
         s.K = 2 * desc[2];

@@ -81,7 +81,7 @@ struct TrainCfg {
   static __device__ __forceinline__ bool bias_owner(int a, int wi) { return OBW == 1 ? wi == 0 : a == wi; }
 };
 
-template <int PREC, int W, int H, int KP, int C>
+template <int PREC, int W, int H, int KP, int C, int ACT>
 __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) k_train(TrainLaunch L) {
   using P = PR<PREC>;
   using CF = TrainCfg<PREC, W, H, KP, C>;
@@ -172,6 +172,8 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
 
     // ================= forward
     uint32_t Hs[H][NB][SR];  // Hs[l] = a_{l+1} (S layout), l = 0..H-1
+    uint32_t Ds[ACT ? H : 1][NB][SR];  // sin activation: derivative factors of the layers
+    const ActC ac{nv.act_w, nv.act_rev, nv.act_rev64};
     {
       uint32_t X0[NIB0][SR];
       if constexpr (BF) {
@@ -189,14 +191,14 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
                                  &K};
       };
       if constexpr (CF::FWD_CHAIN) {
-        forward_chain_bf16<W, H, NIB0>(wf0, wfl, X0, Hs, sm_bias, K);
+        forward_chain_bf16<W, H, NIB0, ACT>(wf0, wfl, X0, Hs, Ds, sm_bias, K, ac);
       } else {
 #pragma unroll
         for (int ob = 0; ob < NB; ob += 2) {
           floatx16 a0 = bias_acc(sm_bias, K, ob), a1 = bias_acc(sm_bias, K, ob + 1);
           layer_block2<PREC, NIB0>(wf0, ob, X0, a0, a1);
-          store_relu<PREC>(a0, Hs[0][ob]);
-          store_relu<PREC>(a1, Hs[0][ob + 1]);
+          store_act<PREC, ACT>(a0, Hs[0][ob], ACT ? Ds[0][ob] : nullptr, ac);
+          store_act<PREC, ACT>(a1, Hs[0][ob + 1], ACT ? Ds[0][ob + 1] : nullptr, ac);
         }
         static_for<1, H>([&](auto lc) {
           constexpr int l = decltype(lc)::value;
@@ -205,8 +207,8 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
           for (int ob = 0; ob < NB; ob += 2) {
             floatx16 a0 = bias_acc(sm_bias + l * W, K, ob), a1 = bias_acc(sm_bias + l * W, K, ob + 1);
             layer_block2<PREC, NB>(wf, ob, Hs[l - 1], a0, a1);
-            store_relu<PREC>(a0, Hs[l][ob]);
-            store_relu<PREC>(a1, Hs[l][ob + 1]);
+            store_act<PREC, ACT>(a0, Hs[l][ob], ACT ? Ds[ACT ? l : 0][ob] : nullptr, ac);
+            store_act<PREC, ACT>(a1, Hs[l][ob + 1], ACT ? Ds[ACT ? l : 0][ob + 1] : nullptr, ac);
           }
         });
       }
@@ -230,7 +232,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
     const float Ls = loss_grad<C>(sp, smp, j, y, gy);
     if (h == 0) loss_acc += Ls;
 
-    // g_H = (Wh^T gy) * 1[a_H > 0]
+    // g_H = (Wh^T gy) * act'(z_H)
     uint32_t Gc[NB][SR];
 #pragma unroll
     for (int ob = 0; ob < NB; ++ob) {
@@ -246,7 +248,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
 #pragma unroll
         for (int e = 0; e < 4; ++e) g[4 * q + e] = v[e];
       }
-      store_masked<PREC>(g, Gc[ob], Hs[H - 1][ob]);
+      store_grad<PREC, ACT>(g, Gc[ob], Hs[H - 1][ob], Ds[ACT ? H - 1 : 0][ob]);
     }
     if constexpr (CF::HH_PRIVATE) {
       // the previous iteration's readers of this buffer finished before its last barrier
@@ -340,9 +342,15 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
             for (int b = 0; b < CF::IBWMAX; ++b) {
               if (b < IBWl) {
                 const int ib = wi * IBWl + b;
-                constexpr int NP = (l == 0) ? NIB0 / CF::XPANELS : NB;
-                if constexpr (BF) hb[b] = frag_tr(sl + ((l == 0) ? CF::xpanel(ib / NP) : CF::ROWS_BYTES), K, 16 * kk, ib % NP);
-                else hb[b] = ((const float*)(sl + CF::ROWS_BYTES))[(2 * kk + h) * CF::RB + 32 * ib + fl];
+                if constexpr (BF) {
+                  if constexpr (l == 0 && CF::XPANELS > 1) {
+                    constexpr int NP = NIB0 / CF::XPANELS;
+                    hb[b] = frag_tr(sl + CF::xpanel(ib / NP), K, 16 * kk, ib % NP);
+                  } else {
+                    hb[b] = frag_tr(sl + CF::ROWS_BYTES, K, 16 * kk, ib);
+                  }
+                }
+                if constexpr (!BF) hb[b] = ((const float*)(sl + CF::ROWS_BYTES))[(2 * kk + h) * CF::RB + 32 * ib + fl];
               }
             }
 #pragma unroll
@@ -454,7 +462,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
       }
 
       if constexpr (l > 0) {
-        // g_l = (W_l^T g_{l+1}) * 1[a_l > 0]
+        // g_l = (W_l^T g_{l+1}) * act'(z_l)
         WBwd<PREC, W> wb_p{wl + (size_t)(l - 1) * W * 256,
                            (const float*)nv.wrow + z + (size_t)W * KP + (size_t)(l - 1) * W * W, &K};
         const WBwdBuf<W> wb_b{raw_rsrc(nv.wtfrag, BF ? wtfrag_elems(nv.s) * 2 : 0), z + (l - 1) * W * W * 2,
@@ -465,8 +473,8 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
           floatx16 a0 = floatx16{}, a1 = floatx16{};
           if constexpr (BF && CF::DX_HBM) layer_block2<PREC, NB>(wb_b, ib, Gc, a0, a1);
           else layer_block2<PREC, NB>(wb_p, ib, Gc, a0, a1);
-          store_masked<PREC>(a0, Gn[ib], Hs[l - 1][ib]);
-          store_masked<PREC>(a1, Gn[ib + 1], Hs[l - 1][ib + 1]);
+          store_grad<PREC, ACT>(a0, Gn[ib], Hs[l - 1][ib], Ds[ACT ? l - 1 : 0][ib]);
+          store_grad<PREC, ACT>(a1, Gn[ib + 1], Hs[l - 1][ib + 1], Ds[ACT ? l - 1 : 0][ib + 1]);
         }
 #pragma unroll
         for (int ib = 0; ib < NB; ++ib)
@@ -574,7 +582,7 @@ struct InferCfg {
   static constexpr int LDS_BYTES = WL_BYTES + SMALL_FLOATS * 4;
 };
 
-template <int PREC, int W, int H, int KP, int C>
+template <int PREC, int W, int H, int KP, int C, int ACT>
 __global__ void __launch_bounds__(64 * INFER_WAVES, 1)
     __attribute__((amdgpu_waves_per_eu(INFER_WAVES / 4, INFER_WAVES / 4))) k_infer(InferLaunch I) {
   using P = PR<PREC>;
@@ -587,6 +595,7 @@ __global__ void __launch_bounds__(64 * INFER_WAVES, 1)
   SampleSpec sp = I.spec;
   if (sp.n_dev) sp.n = min(sp.n, (int64_t)*sp.n_dev);  // count known only on the device
   const int wave = wave_id();
+  const ActC ac{nv.act_w, nv.act_rev, nv.act_rev64};
 
   char* wl0 = smem;
   float* sm_bias0 = (float*)(smem + CF::WL_BYTES);
@@ -660,7 +669,7 @@ __global__ void __launch_bounds__(64 * INFER_WAVES, 1)
           }
         }
 #pragma unroll
-        for (int u = 0; u < NT; ++u) store_relu<PREC>(acc[u], Bn[u][ob]);
+        for (int u = 0; u < NT; ++u) store_act<PREC, ACT>(acc[u], Bn[u][ob], nullptr, ac);
       }
 #pragma unroll
       for (int u = 0; u < NT; ++u)
@@ -1182,37 +1191,54 @@ __global__ void k_sample(uint64_t sseed, uint32_t npop, int64_t n, uint32_t* out
 
 // ============================================================== host dispatch
 
-template <int PREC, int W, int H, int KP, int C>
+template <int PREC, int W, int H, int KP, int C, int ACT>
 KernelSet make_set() {
   static_assert(KP % 64 == 0, "the FP8 form takes k-steps of 64 features");
-  KernelSet k{k_train<PREC, W, H, KP, C>, k_infer<PREC, W, H, KP, C>,
+  KernelSet k{k_train<PREC, W, H, KP, C, ACT>, k_infer<PREC, W, H, KP, C, ACT>,
               TrainCfg<PREC, W, H, KP, C>::LDS_BYTES, InferCfg<PREC, W, H, KP, C>::LDS_BYTES,
-              k_infer_fp8<W, H, KP, C>, nullptr};
-  if constexpr (PREC == NVDB_BF16 && W == 128 && KP == 128 && C == 1 && (H == 3 || H == 4))
+              ACT == ACT_RELU ? k_infer_fp8<W, H, KP, C> : nullptr, nullptr};
+  if constexpr (PREC == NVDB_BF16 && W == 128 && KP == 128 && C == 1 && (H == 3 || H == 4) && ACT == ACT_RELU)
     k.train_rows = train_rows_kernel(H);
   return k;
 }
 
-// Shapes with compiled kernels: (W, H, KP, C).
+// Shapes with compiled kernels: (W, H, KP, C), ReLU.
 #define NVDB_FOR_SHAPES(X) \
   X(64, 3, 64, 1)          \
   X(64, 4, 128, 3)         \
   X(128, 4, 128, 1)        \
   X(128, 3, 128, 1)
 
-bool find_kernels(int prec, int W, int H, int KP, int C, KernelSet* out) {
-#define NVDB_MATCH(w, hh, kp, c)                                                      \
-  if (W == w && H == hh && KP == kp && C == c) {                                      \
-    *out = prec == NVDB_BF16 ? make_set<NVDB_BF16, w, hh, kp, c>() : make_set<NVDB_FP32, w, hh, kp, c>(); \
-    return true;                                                                      \
+bool find_kernels(int prec, int W, int H, int KP, int C, int act, KernelSet* out) {
+  if (act == ACT_RELU) {
+#define NVDB_MATCH(w, hh, kp, c)                                              \
+  if (W == w && H == hh && KP == kp && C == c) {                              \
+    *out = prec == NVDB_BF16 ? make_set<NVDB_BF16, w, hh, kp, c, ACT_RELU>()  \
+                             : make_set<NVDB_FP32, w, hh, kp, c, ACT_RELU>(); \
+    return true;                                                              \
   }
-  NVDB_FOR_SHAPES(NVDB_MATCH)
+    NVDB_FOR_SHAPES(NVDB_MATCH)
 #undef NVDB_MATCH
-  // Fourier features as many as the width (m = W = 128, K = 256), BF16 form only: the
-  // FP32 form's 256-float input rows do not fit the LDS next to its other buffers
-  if (prec == NVDB_BF16 && W == 128 && H == 3 && KP == 256 && C == 1) {
-    *out = make_set<NVDB_BF16, 128, 3, 256, 1>();
-    return true;
+    // Fourier features as many as the width (m = W = 128, K = 256), BF16 form only:
+    // the FP32 form's 256-float input rows do not fit the LDS next to its other buffers
+    if (prec == NVDB_BF16 && W == 128 && H == 3 && KP == 256 && C == 1) {
+      *out = make_set<NVDB_BF16, 128, 3, 256, 1, ACT_RELU>();
+      return true;
+    }
+    return false;
+  }
+  // sin activation: the small 3x64 network in both forms and the 3x128 network with
+  // m = 128 Fourier features in the BF16 form
+  if (act == ACT_SIN) {
+    if (W == 64 && H == 3 && KP == 64 && C == 1) {
+      *out = prec == NVDB_BF16 ? make_set<NVDB_BF16, 64, 3, 64, 1, ACT_SIN>()
+                               : make_set<NVDB_FP32, 64, 3, 64, 1, ACT_SIN>();
+      return true;
+    }
+    if (prec == NVDB_BF16 && W == 128 && H == 3 && KP == 256 && C == 1) {
+      *out = make_set<NVDB_BF16, 128, 3, 256, 1, ACT_SIN>();
+      return true;
+    }
   }
   return false;
 }

@@ -635,14 +635,71 @@ struct FwdSteps {
   }
 };
 
+// Hidden activation (App. on activation functions): ACT_RELU, or ACT_SIN,
+// h = sin(w z) with the derivative factor d = w cos(w z) kept for the backward
+// pass.  The hardware sine takes revolutions: the phase z w / (2 pi) (+ 1/4 for
+// the cosine) is reduced with fract first, formed in double precision in the
+// FP32 form.
+struct ActC {
+  float w;       // sin frequency
+  float rev;     // w / (2 pi)
+  double rev64;  // w / (2 pi), FP32 form
+};
+template <int PREC>
+__device__ __forceinline__ float act_phase(float z, const ActC& ac, float shift) {
+  if constexpr (PREC == NVDB_FP32) {
+    const double u = (double)z * ac.rev64 + (double)shift;
+    return (float)(u - floor(u));
+  } else {
+    return __builtin_amdgcn_fractf(fmaf(z, ac.rev, shift));
+  }
+}
+// h = act(a) into s (S layout); with ACT_SIN and d non-null also d = w cos(w a).
+template <int PREC, int ACT>
+__device__ __forceinline__ void store_act(floatx16 a, uint32_t* s, uint32_t* d, const ActC& ac) {
+  if constexpr (ACT == ACT_RELU) {
+    store_relu<PREC>(a, s);
+  } else {
+    floatx16 hv, dv;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      hv[i] = __builtin_amdgcn_sinf(act_phase<PREC>(a[i], ac, 0.f));
+      if (d) dv[i] = ac.w * __builtin_amdgcn_sinf(act_phase<PREC>(a[i], ac, 0.25f));
+    }
+    PR<PREC>::store(hv, s);
+    if (d) PR<PREC>::store(dv, d);
+  }
+}
+// Input gradient block: a times the activation's derivative, from the stored
+// activation (ReLU: a > 0) or the stored factor d (sin), stored in S layout.
+template <int PREC, int ACT>
+__device__ __forceinline__ void store_grad(floatx16 a, uint32_t* s, const uint32_t* act, const uint32_t* d) {
+  if constexpr (ACT == ACT_RELU) {
+    store_masked<PREC>(a, s, act);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if constexpr (PREC == NVDB_BF16) {
+        a[2 * i] *= bf16_lo(d[i]);
+        a[2 * i + 1] *= bf16_hi(d[i]);
+      } else {
+        a[2 * i] *= __uint_as_float(d[2 * i]);
+        a[2 * i + 1] *= __uint_as_float(d[2 * i + 1]);
+      }
+    }
+    PR<PREC>::store(a, s);
+  }
+}
+
 // All hidden layers of the BF16 forward pass in one software pipeline: weight
 // fragments (independent of the data) are fetched PF steps ahead through block
-// pairs and layers, and the bias/ReLU/convert epilogue of a block pair overlaps
-// the next pair's first products (two accumulator sets alternate).
-template <int W, int H, int NIB0, class F0, class FL>
+// pairs and layers, and the bias/activation/convert epilogue of a block pair
+// overlaps the next pair's first products (two accumulator sets alternate).
+// Ds receives the sin derivative factors (ACT_SIN).
+template <int W, int H, int NIB0, int ACT, class F0, class FL, int HD>
 __device__ __forceinline__ void forward_chain_bf16(const F0& wf0, const FL& wfl, const uint32_t (&X0)[NIB0][8],
-                                                   uint32_t (&Hs)[H][W / 32][8], const float* sm_bias,
-                                                   const LaneK& K) {
+                                                   uint32_t (&Hs)[H][W / 32][8], uint32_t (&Ds)[HD][W / 32][8],
+                                                   const float* sm_bias, const LaneK& K, const ActC& ac) {
   using P = PR<NVDB_BF16>;
   constexpr int NB = W / 32, KS = P::KS;
   using S = FwdSteps<NIB0, NB, H>;
@@ -685,13 +742,13 @@ __device__ __forceinline__ void forward_chain_bf16(const F0& wf0, const FL& wfl,
       constexpr int ge = g - S::DEFER;  // last step of the previous pair
       if constexpr (S::deferred(ge)) {
         constexpr int le = S::layer(ge), pe = S::pair(ge);
-        store_relu<NVDB_BF16>(acc[buf ^ 1][0], Hs[le][2 * pe]);
-        store_relu<NVDB_BF16>(acc[buf ^ 1][1], Hs[le][2 * pe + 1]);
+        store_act<NVDB_BF16, ACT>(acc[buf ^ 1][0], Hs[le][2 * pe], ACT ? Ds[ACT ? le : 0][2 * pe] : nullptr, ac);
+        store_act<NVDB_BF16, ACT>(acc[buf ^ 1][1], Hs[le][2 * pe + 1], ACT ? Ds[ACT ? le : 0][2 * pe + 1] : nullptr, ac);
       }
     }
     if constexpr (s == S::nsl(l) - 1 && !S::deferred(g)) {
-      store_relu<NVDB_BF16>(acc[buf][0], Hs[l][2 * p]);
-      store_relu<NVDB_BF16>(acc[buf][1], Hs[l][2 * p + 1]);
+      store_act<NVDB_BF16, ACT>(acc[buf][0], Hs[l][2 * p], ACT ? Ds[ACT ? l : 0][2 * p] : nullptr, ac);
+      store_act<NVDB_BF16, ACT>(acc[buf][1], Hs[l][2 * p + 1], ACT ? Ds[ACT ? l : 0][2 * p + 1] : nullptr, ac);
     }
   });
 }

@@ -165,6 +165,10 @@ struct NetView {
   const float* bhead;    // [C]
   const float* benc;     // feature-mapping matrix [KP/2][4] rows (bx, by, bz, 0), zero beyond n_freq
   int32_t nfreq;
+  // hidden activation sin(w z) when the kernel's activation is sin:
+  // w and w / (2 pi) in float and double
+  float act_w, act_rev;
+  double act_rev64;
 };
 
 // bf16 weight rows in LDS / HBM: 256 bytes per row (128 bf16), 8-byte chunks
@@ -259,7 +263,9 @@ __host__ __device__ inline int64_t fp8_weight_bytes(const NetShape& s) { return 
 // activations as LDS rows (H hidden layers), or null
 void (*train_rows_kernel(int H))(TrainLaunch);
 // mlp.hip
-bool find_kernels(int prec, int W, int H, int KP, int C, KernelSet* out);
+// hidden activation of a network's kernels
+enum : int { ACT_RELU = 0, ACT_SIN = 1 };
+bool find_kernels(int prec, int W, int H, int KP, int C, int act, KernelSet* out);
 void launch_quant_fp8(const NetShape& s, const float* theta, char* w8, float* w8inv, hipStream_t st);
 void launch_infer8(const KernelSet& ks, const InferLaunch& I, int grid, hipStream_t st);
 void launch_train(const KernelSet& ks, const TrainLaunch& L, int n_nets, hipStream_t st);

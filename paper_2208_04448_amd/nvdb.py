@@ -40,7 +40,8 @@ class TreeInfo(C.Structure):
 
 
 class NetDesc(C.Structure):
-    _fields_ = [("width", C.c_int32), ("hidden", C.c_int32), ("n_freq", C.c_int32), ("n_out", C.c_int32)]
+    _fields_ = [("width", C.c_int32), ("hidden", C.c_int32), ("n_freq", C.c_int32), ("n_out", C.c_int32),
+                ("sin_freq", C.c_float)]
 
 
 class ModelDesc(C.Structure):
@@ -262,12 +263,13 @@ class Model:
     """Handle of a set of NeuralVDB networks (regressor, level-0, level-1)."""
 
     def __init__(self, nets, precision=BF16, domain_lo=(0, 0, 0), domain_size=64, value_scale=1.0):
-        """nets: {net_id: (width, hidden, n_freq, n_out)}"""
+        """nets: {net_id: (width, hidden, n_freq, n_out[, sin_freq])}; sin_freq 0 (default) is ReLU."""
         d = ModelDesc()
         d.precision = precision
-        for k, (w, hh, m, c) in nets.items():
+        for k, desc in nets.items():
+            w, hh, m, c = desc[:4]
             d.has_net[k] = 1
-            d.net[k] = NetDesc(w, hh, m, c)
+            d.net[k] = NetDesc(w, hh, m, c, float(desc[4]) if len(desc) > 4 else 0.0)
         d.domain_lo = _i3(domain_lo)
         d.domain_size = int(domain_size)
         d.value_scale = float(value_scale)

@@ -50,13 +50,14 @@ def parse(buf, param_count):
         if not (hd["nets_mask"] >> k) & 1:
             continue
         W, H, nf, C = np.frombuffer(buf, np.int32, 4, pos).tolist()
-        pos += 16
+        sin_freq = float(np.frombuffer(buf, np.float32, 1, pos + 16)[0])
+        pos += 20
         B = np.frombuffer(buf, np.float32, 3 * nf, pos).reshape(nf, 3)
         pos += 12 * nf
         P = param_count(W, H, nf, C)
         codes = np.frombuffer(buf, np.uint16, P, pos)
         pos += (2 * P + 3) & ~3
-        nets[k] = dict(shape=(W, H, nf, C), B=B, codes=codes)
+        nets[k] = dict(shape=(W, H, nf, C), sin_freq=sin_freq, B=B, codes=codes)
     fp = np.frombuffer(buf, np.int32, 3 * hd["n_fp"], pos).reshape(-1, 3)
     pos += 12 * hd["n_fp"]
     fn = np.frombuffer(buf, np.int32, 3 * hd["n_fn"], pos).reshape(-1, 3)
@@ -73,7 +74,7 @@ def n_params(W, H, nf, C):
 
 def archive_size(n_l2, n_l1, explicit_l1, n_leaf, shapes, n_fp, n_fn):
     """Bytes of the image by the documented layout (n_leaf: leaf masks stored)."""
-    nets = sum(16 + 12 * nf + ((2 * n_params(W, H, nf, C) + 3) & ~3) for W, H, nf, C in shapes)
+    nets = sum(20 + 12 * nf + ((2 * n_params(W, H, nf, C) + 3) & ~3) for W, H, nf, C in shapes)
     return (120 + n_l2 * (12 + 4096) + n_l1 * (12 + (1024 if explicit_l1 else 0)) + 64 * n_leaf + nets
             + 12 * (n_fp + n_fn))
 
@@ -157,7 +158,7 @@ def test_archive_round_trip(gpu_lib, fitted, prec, store, mask, explicit, explic
         assert np.array_equal(a["leaf_mask"], ex["leaf_mask"])
     # networks: shapes, encodings exactly, parameters as round-to-nearest-even 16-bit codes
     for k, net in a["nets"].items():
-        assert net["shape"] == NETS[k]
+        assert net["shape"] == NETS[k] and net["sin_freq"] == 0.0
         assert np.array_equal(net["B"], ENC[k]().astype(np.float32))
         assert np.array_equal(net["codes"], codes16(m.get_params(k), S, gpu_lib))
     # patches: the difference between the truth and what the stored networks decode

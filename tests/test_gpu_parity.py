@@ -345,6 +345,129 @@ def test_ffm_features_as_many_as_width(gpu_lib, record, sphere):
     assert e.value.code == gpu_lib.E_UNSUPPORTED
 
 
+SIN_W = 1.5  # the appendix's suggested sin frequency
+# BF16 bounds of the sin networks: an activation's rounding error (or a flipped
+# bfloat16 code) reaches the output through the later hidden layers, each of which
+# can amplify it by up to w (the sine's slope) where ReLU passes it with slope <= 1,
+# so the ReLU bounds scale by w^(H-1) (measured 3.2e-3 forward against FP64 and
+# 1.4e-3 against the BF16 form, against 4.5e-3 and 2.25e-3 for H = 3).
+SIN_AMP = SIN_W ** 2
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_sin_activation_small(gpu_lib, record, sphere, prec):
+    """sin(1.5 z) on every hidden layer (3x64, PE-6): forward and element-wise
+    gradients against the FP64 oracle (and its BF16 form), a 10-step fit's losses
+    against the oracle drawing the same samples, the decode of every voxel; the
+    FP8 form is refused.  The sine is smooth, so no input is excluded near a kink."""
+    tr, ot = sphere
+    p = gpu_lib.FP32 if prec == "fp32" else gpu_lib.BF16
+    W_, H_, m_, c_ = 64, 3, 18, 1
+    shapes = mlp.layer_shapes(2 * m_, W_, H_, c_, omega=SIN_W)
+    th0 = workloads.init_params(2 * m_, W_, H_, c_, seed=17)
+    B = workloads.pe_matrix(6)
+    model = gpu_lib.Model({0: (W_, H_, m_, c_, SIN_W)}, precision=p, domain_size=64, value_scale=3.0)
+    model.set_params(0, th0)
+    model.set_encoding(0, B)
+    th, Bd = th0.astype(np.float64), B.astype(np.float64)
+    params = mlp.unflatten(th, shapes)
+    for n in (33, 4097):
+        x = np.random.default_rng(n).random((n, 3)).astype(np.float32)
+        y = model.forward_coords(0, torch.from_numpy(x).to(DEV)).cpu().numpy()
+        yo = mlp.predict(params, x.astype(np.float64), Bd)
+        err = float(np.max(np.abs(y - yo) / (1 + np.abs(yo))))
+        if p == gpu_lib.FP32:
+            record("forward_sin_fp32_n%d" % n, err=err)
+            assert err <= 1e-6, err
+        else:
+            yb, _ = bf16_form.forward_bf16(params, mlp.encode(x.astype(np.float64), Bd))
+            err_b = float(np.max(np.abs(y - yb) / (1 + np.abs(yb))))
+            record("forward_sin_bf16_n%d" % n, err=err, err_bf16_form=err_b)
+            assert err <= SIN_AMP * BF16_FWD_TOL and err_b <= SIN_AMP * BF16_FORM_FWD_TOL["pe"], (err, err_b)
+    n = 3000
+    rng = np.random.default_rng(21)
+    x = rng.random((n, 3)).astype(np.float32)
+    gy = rng.standard_normal((n, 1)).astype(np.float32)
+    model.reserve_dev(0, n)
+    g = model.backward_coords(0, torch.from_numpy(x).to(DEV), torch.from_numpy(gy).to(DEV)).cpu().numpy()
+    g = g.astype(np.float64)
+    go = F.param_grad(th, shapes, Bd, x.astype(np.float64), gy.astype(np.float64))
+    errs = tensor_errors(g, go, shapes)
+    if p == gpu_lib.FP32:
+        record("backward_sin_fp32", elem=max(errs))
+        assert max(errs) <= 3e-6, errs
+    else:
+        _, cb = bf16_form.forward_bf16(params, mlp.encode(x.astype(np.float64), Bd))
+        errs_b = tensor_errors(g, mlp.flatten(bf16_form.backward_bf16(params, cb, gy.astype(np.float64))), shapes)
+        record("backward_sin_bf16", elem=max(errs), elem_bf16_form=max(errs_b))
+        assert max(errs) <= BF16_RAND_GRAD_TOL and max(errs_b) <= SIN_AMP * BF16_FORM_GRAD_TOL["pe"], (errs, errs_b)
+    L = model.fit(tr, steps=10, batch=4096, nets_mask=1, seed=2, lr=1e-3)[0]
+    _, _, _, lo = F.train(th, shapes, Bd, ot, "regressor", (0, 0, 0), 64, T.SDF, 3.0, steps=10, batch=4096, seed=2,
+                          lr0=1e-3)
+    rel = np.abs(np.asarray(L[:10], np.float64) - np.asarray(lo)) / np.asarray(lo)
+    record("fit_sin_%s" % prec, rel_loss=float(rel.max()))
+    assert rel.max() <= (1e-5 if p == gpu_lib.FP32 else 2e-2), rel
+    thf = model.get_params(0).astype(np.float64)
+    vals, _ = model.decode(tr, values=True, masks=False)
+    vo = F.decode_values(thf, shapes, Bd, ot, (0, 0, 0), 64, T.SDF, 3.0)
+    d = np.abs(vals.cpu().numpy() - vo)
+    assert d.max() <= (3e-5 if p == gpu_lib.FP32 else 3.0 * SIN_AMP * BF16_FWD_TOL * (1 + np.abs(vo / 3.0)).max()), d.max()
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        model.decode(tr, values=True, masks=False, fp8=True)
+    assert e.value.code == gpu_lib.E_UNSUPPORTED
+
+
+def test_sin_activation_width_features(gpu_lib, record, sphere):
+    """The appendix's suggested starting point: 3x128, sin(1.5 z), as many Fourier
+    features as the width (m = 128), BF16: forward and gradients against the BF16
+    form, a 4-step fit's losses, the decode; FP32 and other sin shapes refused."""
+    tr, ot = sphere
+    W_, H_, m_ = 128, 3, 128
+    shapes = mlp.layer_shapes(2 * m_, W_, H_, 1, omega=SIN_W)
+    th0 = workloads.init_params(2 * m_, W_, H_, 1, seed=19)
+    B = workloads.ffm_matrix(m_, 5.0, seed=20)
+    model = gpu_lib.Model({0: (W_, H_, m_, 1, SIN_W)}, precision=gpu_lib.BF16, domain_size=64, value_scale=3.0)
+    model.set_params(0, th0)
+    model.set_encoding(0, B)
+    th, Bd = th0.astype(np.float64), B.astype(np.float64)
+    params = mlp.unflatten(th, shapes)
+    x = np.random.default_rng(4).random((4097, 3)).astype(np.float32)
+    y = model.forward_coords(0, torch.from_numpy(x).to(DEV)).cpu().numpy()
+    yb, _ = bf16_form.forward_bf16(params, mlp.encode(x.astype(np.float64), Bd))
+    yo = mlp.predict(params, x.astype(np.float64), Bd)
+    err, err_b = (float(np.max(np.abs(y - r) / (1 + np.abs(r)))) for r in (yo, yb))
+    record("forward_sin_bf16_3x128_m128", err=err, err_bf16_form=err_b)
+    assert err <= SIN_AMP * BF16_FWD_TOL and err_b <= SIN_AMP * BF16_FORM_FWD_TOL["ffm"], (err, err_b)
+    n = 3000
+    rng = np.random.default_rng(22)
+    xg = rng.random((n, 3)).astype(np.float32)
+    gy = rng.standard_normal((n, 1)).astype(np.float32)
+    model.reserve_dev(0, n)
+    g = model.backward_coords(0, torch.from_numpy(xg).to(DEV), torch.from_numpy(gy).to(DEV)).cpu().numpy()
+    _, cb = bf16_form.forward_bf16(params, mlp.encode(xg.astype(np.float64), Bd))
+    errs_b = tensor_errors(g.astype(np.float64), mlp.flatten(bf16_form.backward_bf16(params, cb, gy.astype(np.float64))),
+                           shapes)
+    record("backward_sin_bf16_3x128_m128", elem_bf16_form=max(errs_b))
+    assert max(errs_b) <= SIN_AMP * BF16_FORM_GRAD_TOL["ffm"], errs_b
+    L = model.fit(tr, steps=4, batch=4096, nets_mask=1, seed=2, lr=1e-3)[0]
+    _, _, _, lo = F.train(th, shapes, Bd, ot, "regressor", (0, 0, 0), 64, T.SDF, 3.0, steps=4, batch=4096, seed=2,
+                          lr0=1e-3)
+    rel = np.abs(np.asarray(L[:4], np.float64) - np.asarray(lo)) / np.asarray(lo)
+    record("fit_sin_bf16_3x128_m128", rel_loss=float(rel.max()))
+    assert rel.max() <= 2e-2, rel
+    vals, _ = model.decode(tr, values=True, masks=False)
+    vo = F.decode_values(model.get_params(0).astype(np.float64), shapes, Bd, ot, (0, 0, 0), 64, T.SDF, 3.0) / 3.0
+    assert np.max(np.abs(vals.cpu().numpy() / 3.0 - vo) / (1 + np.abs(vo))) <= SIN_AMP * BF16_FWD_TOL
+    for desc, prec in (((W_, H_, m_, 1, SIN_W), gpu_lib.FP32), ((128, 4, 64, 1, SIN_W), gpu_lib.BF16)):
+        with pytest.raises(gpu_lib.NvdbError) as e:
+            gpu_lib.Model({0: desc}, precision=prec, domain_size=64, value_scale=3.0)
+        assert e.value.code == gpu_lib.E_UNSUPPORTED
+    for bad in (-1.0, float("nan"), 100.0):
+        with pytest.raises(gpu_lib.NvdbError) as e:
+            gpu_lib.Model({0: (64, 3, 18, 1, bad)}, precision=gpu_lib.FP32, domain_size=64, value_scale=3.0)
+        assert e.value.code == gpu_lib.E_INVALID
+
+
 def test_backward_deterministic(gpu_lib):
     model, theta, B, shapes = model_for(gpu_lib, SHAPES[1], gpu_lib.BF16)
     x = torch.rand(50000, 3, device=DEV, generator=torch.Generator(DEV).manual_seed(3))

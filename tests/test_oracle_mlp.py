@@ -69,6 +69,31 @@ def test_forward_closed_forms():
     assert np.array_equal(y[:, 0], np.zeros(3))
 
 
+def test_forward_sin_special_values():
+    """sin(omega z) on every hidden layer, the head linear (omega = 1.5): one active
+    path y = 3 act(act(2 z0 + 1)) - 1 at inputs where the phases are known: a zero
+    pre-activation, omega z = pi / 2 (activation 1), omega z = pi (activation 0,
+    where cos would give -1 and an unscaled sine sin(z) would not vanish)."""
+    w = 1.5
+    shapes = mlp.layer_shapes(4, 3, 2, 2, omega=w)
+    params = mlp.unflatten(np.zeros(mlp.param_count(4, 3, 2, 2)), shapes)
+    assert params.omega == w
+    params[0][0][1, 2] = 2.0; params[0][1][1] = 1.0
+    params[1][0][0, 1] = 1.0
+    params[2][0][1, 0] = 3.0; params[2][1][1] = -1.0
+    z0 = np.zeros((3, 4))
+    z0[:, 2] = [-0.5, (math.pi / (2 * w) - 1) / 2, (math.pi / w - 1) / 2]
+    y, cache = mlp.forward(params, z0)
+    assert np.allclose(cache[2][:, 1], [0.0, 1.0, 0.0], atol=1e-15)
+    assert np.allclose(y[:, 1], [-1.0, 3 * math.sin(w * 1.0) - 1, -1.0], atol=1e-14)
+    assert np.allclose(y[:, 0], 0.0)   # the other output sees only zero weights and biases
+    # zero weights leave every hidden value at sin(omega b) of its bias
+    params = mlp.unflatten(np.zeros(mlp.param_count(4, 3, 2, 2)), shapes)
+    params[0][1][:] = [0.0, 1.0, -2.0]
+    _, cache = mlp.forward(params, z0)
+    assert np.allclose(cache[2][0], [0.0, math.sin(1.5), math.sin(-3.0)], atol=1e-15)
+
+
 def test_loss_special_values():
     assert math.isclose(mlp.loss_bce(np.zeros(5), np.array([0, 1, 1, 0, 1])), math.log(2))
     assert math.isclose(mlp.loss_ce(np.zeros((4, 3)), np.array([0, 1, 2, 2])), math.log(3))
@@ -94,9 +119,9 @@ def test_output_grad_finite_differences(kind, c):
             assert abs(fd - g[i, j]) < 1e-8
 
 
-def _fd_check(K, W, H, c, kind, h, seed):
+def _fd_check(K, W, H, c, kind, h, seed, omega=0.0):
     rng = np.random.default_rng(seed)
-    shapes = mlp.layer_shapes(K, W, H, c)
+    shapes = mlp.layer_shapes(K, W, H, c, omega=omega)
     theta = rng.standard_normal(mlp.param_count(K, W, H, c)) * 0.5
     z0 = rng.standard_normal((32, K))
     t = rng.standard_normal(32) if kind == "mse" else rng.integers(0, c if kind == "ce" else 2, 32)
@@ -132,6 +157,15 @@ def test_backward_finite_differences(K, W, H, c, kind):
     assert np.median(errs) < 1e-7 and np.max(errs) < 1e-4
     errs, kinks = _fd_check(K, W, H, c, kind, 1e-3, 12)
     assert np.median(errs) < 1e-5
+
+
+@pytest.mark.parametrize("omega", [1.5, 3.0])
+def test_backward_finite_differences_sin(omega):
+    """The sin activation is smooth: every sampled weight's central difference
+    matches the hand-derived gradient (omega cos(omega z) per hidden layer)."""
+    errs, kinks = _fd_check(12, 8, 3, 1, "mse", 1e-5, 13, omega=omega)
+    assert kinks == 0 and len(errs) == 64
+    assert np.median(errs) < 1e-7 and np.max(errs) < 1e-4
 
 
 def test_adam_first_step_and_constant_gradient():
