@@ -128,10 +128,15 @@ def main():
     if args.train_groups > 0:
         tuned_g, tune_ms = args.train_groups, {}
         bf.set_train_groups(tuned_g)
+        bf.train_kernel = nvdb.TRAIN_ROWS
     else:
         tuned_g, tune_ms = bf.autotune(tune_tree, nets_mask=3, batch=BATCH, reps=3)
+    kname = {nvdb.TRAIN_REGISTERS: "registers", nvdb.TRAIN_ROWS: "rows"}
+    dec_choice, dec_cands = bf.autotune_decode(tune_tree, nets_mask=3, reps=3)
     del tune_tree
-    print("autotune: G=%d %s" % (tuned_g, {g: round(t, 4) for g, t in tune_ms.items()}), file=sys.stderr, flush=True)
+    print("autotune: %s G=%d %s; decode %s" % (kname[bf.train_kernel], tuned_g,
+                                               {"%s/%d" % (kname[k], g): round(t, 4) for (k, g), t in tune_ms.items()},
+                                               dec_cands), file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         job(bf, args.fit_steps)
     torch.cuda.synchronize()
@@ -181,10 +186,17 @@ def main():
         "bf16": {"max_abs_err_voxels": rep["max_abs"], "rms_err_voxels": rep["rms"], "iou": rep["iou"],
                  "l0_fp": rep["fp"], "l0_fn": rep["fn"], "final_loss": [float(losses[0, -1]), float(losses[1, -1])]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_BF16_TFLOPS, "traffic": measured_traffic(),
-                     "kernel": "k_train_rows<4> (BF16 4x128, both networks per launch)",
+                     "frac": achieved / PEAK_BF16_TFLOPS,
+                     "traffic": measured_traffic() if bf.train_kernel == nvdb.TRAIN_ROWS else None,
+                     "kernel": ("k_train_rows<4>" if bf.train_kernel == nvdb.TRAIN_ROWS else "k_train<bf16,128,4,128,1>")
+                     + " (BF16 4x128, both networks per launch)",
                      "flops_per_launch": launch_flops, "avg_launch_ms": train_launch_s * 1e3},
-        "autotune": {"work_groups_per_network": tuned_g, "ms_per_step": {str(g): t for g, t in tune_ms.items()}},
+        "autotune": {"train_kernel": kname[bf.train_kernel], "work_groups_per_network": tuned_g,
+                     "ms_per_step": {"%s/%d" % (kname[k], g): t for (k, g), t in tune_ms.items()},
+                     "decode_shape": {str(k): dict(zip(("waves", "tiles_per_wave"),
+                                                       [c for c in dec_cands if c[0] == k][i][1:3]))
+                                      for k, i in dec_choice.items()},
+                     "decode_ms": {"%d/%dx%d" % (n_, w_, t_): ms_ for n_, w_, t_, ms_ in dec_cands}},
     }
     print("bf16 jobs: %s s" % ["%.3f" % t for t in times], file=sys.stderr, flush=True)
     # FP8 form of the decode with the same (BF16-trained) weights
@@ -342,7 +354,7 @@ def sequence_leg(n_frames, cap, tuned_g, full_width=False):
     warm = dict(steps=cap, batch=BATCH, seed=1, lr=1e-4)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    reps, _, fp = mdl.fit_sequence(trees, cold, warm, nets_mask=3, use_graph=True)
+    reps, Lseq, fp = mdl.fit_sequence(trees, cold, warm, nets_mask=3, use_graph=True)
     torch.cuda.synchronize()
     seq_s = time.perf_counter() - t
     steps = [int(max(r[0][:2])) for r in reps]
@@ -367,6 +379,29 @@ def sequence_leg(n_frames, cap, tuned_g, full_width=False):
     cold_s = time.perf_counter() - t
     v, mk = mdl.decode(trees[last])
     e = nvdb.errors(trees[last], v, mk)
+    # warm against cold (Sec. 3.6): for sampled frames, the steps a cold fit (initial
+    # weights, cold rate) needs until its batch loss, averaged over 100 steps, reaches
+    # the warm-started frame's final loss (the same average), per network; cold fits
+    # run in 250-step chunks up to three times the warm cap
+    c0 = cold["steps"] + warm["steps"]
+    warm_vs_cold = []
+    for f in sorted({max(1, n_frames // 4), max(1, n_frames // 2), last}):
+        seg = Lseq[:2, c0 + (f - 1) * cap: c0 + f * cap]
+        target = seg[:, -100:].mean(axis=1)
+        for k in (0, 1):
+            mdl.set_params(k, th0[k])
+            mdl.set_opt_state(k, np.zeros(P, np.float32), np.zeros(P, np.float32), 0)
+        reached = [None, None]
+        done = 0
+        while done < 3 * cap and None in reached:
+            Lc = mdl.fit(trees[f], steps=250, batch=BATCH, nets_mask=3, seed=11, lr=1e-3)
+            done += 250
+            for k in (0, 1):
+                if reached[k] is None and Lc[k, -100:].mean() <= target[k]:
+                    reached[k] = done
+        warm_vs_cold.append({"frame": f, "warm_steps": [int(reps[f][0][0]), int(reps[f][0][1])],
+                             "warm_final_loss": [float(t_) for t_ in target],
+                             "cold_steps_to_warm_loss": reached, "cold_steps_run": done})
     total_steps = sum(steps)
     return {"workload": "advected noisy water surface 1024x256x1024, %d frames, band +-3, wet region %s; regressor + "
                         "level-0 classifier 4x128, FFM m=64 sigma=10, BF16, 2^18 samples per network per step"
@@ -378,7 +413,9 @@ def sequence_leg(n_frames, cap, tuned_g, full_width=False):
             "warm_frames_hitting_cap": sum(1 for s_ in steps[1:] if s_ >= cap),
             "frames": frames,
             "last_frame_cold_2000": {"s": cold_s, "max_abs": e["max_abs"], "rms": e["rms"], "iou": e["iou"],
-                                     "l0_fp": e["fp"], "l0_fn": e["fn"]}}
+                                     "l0_fp": e["fp"], "l0_fn": e["fn"]},
+            "warm_vs_cold": warm_vs_cold,
+            "warm_vs_cold_note": "cold_steps_to_warm_loss null: not reached within cold_steps_run"}
 
 
 def cloud_leg(fit_steps, tuned_g):

@@ -243,16 +243,47 @@ nvdb_status nvdb_fit_experts(nvdb_model* const* models, const nvdb_tree* const* 
  * given G are deterministic; another G sums the same gradient in another order.
  * nvdb_model_set_train_groups sets G directly (0 restores the default, 256).
  * Synchronises `stream`.  Errors: E_INVALID, E_STATE as nvdb_fit. */
-#define NVDB_TUNE_MAX 16
+#define NVDB_TUNE_MAX 32
+/* Training kernels: activations kept in registers (every shape), or written once
+ * per layer as LDS rows with the weight gradients in the accumulation registers
+ * (the BF16 128-wide networks with 128 features and one output; the default there). */
+enum { NVDB_TRAIN_REGISTERS = 0, NVDB_TRAIN_ROWS = 1 };
 typedef struct {
   int32_t chosen_g;
+  int32_t chosen_kernel;             /* NVDB_TRAIN_*                         */
   int32_t n_candidates;
+  int32_t kernel[NVDB_TUNE_MAX];
   int32_t g[NVDB_TUNE_MAX];
   float ms_per_step[NVDB_TUNE_MAX];  /* train + reduce launches of one step */
 } nvdb_tune_report;
 nvdb_status nvdb_autotune(nvdb_model* model, const nvdb_tree* tree, int32_t nets_mask, int32_t batch, int32_t reps,
                           nvdb_tune_report* report, void* stream);
 nvdb_status nvdb_model_set_train_groups(nvdb_model* model, int32_t g);
+/* The training kernel of every network of the model (NVDB_TRAIN_ROWS applies to
+ * the networks that have that kernel; the others keep the register kernel).
+ * nvdb_autotune also chooses among the kernels (the candidates are kernel x G).
+ * Both compute the same gradient up to summation order. */
+nvdb_status nvdb_model_set_train_kernel(nvdb_model* model, int32_t kind);
+/* Decode tile shapes.  Each network's forward pass is compiled for a few
+ * (waves per work-group, 32-sample tiles per wave) shapes — BF16 (8, 2) the
+ * default, (8, 1), (4, 2), (4, 4); FP32 (8, 1) the default, (4, 1), (4, 2) —
+ * which give bit-identical outputs.  nvdb_autotune_decode times reps decodes of
+ * each network in nets_mask over its population of `tree` (all voxels, voxel slots
+ * of the leaves, or leaf slots of the level-1 nodes) for every shape and keeps the
+ * fastest for every later decode, query and forward call of that network.
+ * nvdb_model_set_decode_shape selects shape `index` (in the order above) directly.
+ * Synchronises `stream`.  Errors: E_INVALID, E_STATE. */
+typedef struct {
+  int32_t n_candidates;
+  int32_t net[NVDB_TUNE_MAX];
+  int32_t waves[NVDB_TUNE_MAX];
+  int32_t tiles[NVDB_TUNE_MAX];
+  float ms[NVDB_TUNE_MAX];      /* one decode of the network's population */
+  int32_t chosen[NVDB_MAX_NETS];  /* index of the chosen shape per network    */
+} nvdb_decode_tune_report;
+nvdb_status nvdb_autotune_decode(nvdb_model* model, const nvdb_tree* tree, int32_t nets_mask, int32_t reps,
+                                 nvdb_decode_tune_report* report, void* stream);
+nvdb_status nvdb_model_set_decode_shape(nvdb_model* model, int32_t net, int32_t index);
 
 /* Temporally coherent warm-start encoder for an animated sequence (Sec. 3.6).
  * Frame 0 is fitted from the model's current parameters with `cold` (the

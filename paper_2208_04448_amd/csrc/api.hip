@@ -830,13 +830,22 @@ nvdb_status nvdb_autotune(nvdb_model* m, const nvdb_tree* tree, int32_t nets_mas
                  "bad autotune arguments");
     hipStream_t st = (hipStream_t)stream;
     const std::vector<int> nets = fit_nets(m, tree, nets_mask);
-    const auto groups = kernel_groups(m, nets);
     const int tiles = (int)std::min<int64_t>(MAX_G, ((int64_t)batch + TRAIN_TILE - 1) / TRAIN_TILE);
     static const int cand_all[] = {32, 64, 128, 192, 256, 320, 384, 512};
-    std::vector<int> cands;
+    std::vector<int> gs;
     for (int g : cand_all)
-      if (g <= tiles) cands.push_back(g);
-    if (cands.empty() || cands.back() != tiles) cands.push_back(tiles);
+      if (g <= tiles) gs.push_back(g);
+    if (gs.empty() || gs.back() != tiles) gs.push_back(tiles);
+    // training kernels: activations in registers, and activation rows where a network has them
+    std::vector<int> kinds = {NVDB_TRAIN_REGISTERS};
+    for (int k : nets)
+      if (m->nets[k].ks.train_rows) {
+        kinds.push_back(NVDB_TRAIN_ROWS);
+        break;
+      }
+    std::vector<std::pair<int, int>> cands;  // (kernel, G)
+    for (int kd : kinds)
+      for (int g : gs) cands.push_back({kd, g});
     NVDB_REQUIRE((int)cands.size() <= NVDB_TUNE_MAX, NVDB_E_INVALID, "too many candidates");
     std::vector<DevBuf<float>> grads(NVDB_MAX_NETS);
     for (int k : nets) {
@@ -844,12 +853,22 @@ nvdb_status nvdb_autotune(nvdb_model* m, const nvdb_tree* tree, int32_t nets_mas
       grads[k].alloc(m->nets[k].s.nparams());
     }
     const int saved_g = m->train_g;
+    std::vector<void (*)(TrainLaunch)> saved_train(NVDB_MAX_NETS);
     std::vector<int64_t> saved_step(NVDB_MAX_NETS);
-    for (int k : nets) saved_step[k] = m->nets[k].step;
+    for (int k : nets) {
+      saved_step[k] = m->nets[k].step;
+      saved_train[k] = m->nets[k].ks.train;
+    }
+    auto use_kind = [&](int kd) {
+      for (int k : nets) {
+        KernelSet& ks = m->nets[k].ks;
+        ks.train = (kd == NVDB_TRAIN_ROWS && ks.train_rows) ? ks.train_rows : ks.train_classic;
+      }
+    };
     hipEvent_t e0, e1;
     NVDB_HIP(hipEventCreate(&e0));
     NVDB_HIP(hipEventCreate(&e1));
-    int best = cands[0];
+    size_t best = 0;
     float best_ms = 0.f;
     std::vector<float> times;
     try {
@@ -857,7 +876,9 @@ nvdb_status nvdb_autotune(nvdb_model* m, const nvdb_tree* tree, int32_t nets_mas
       StepHooks hk;
       for (int k : nets) hk.grad_out[k] = grads[k].p;
       for (size_t c = 0; c < cands.size(); ++c) {
-        m->train_g = cands[c];
+        use_kind(cands[c].first);
+        const auto groups = kernel_groups(m, nets);
+        m->train_g = cands[c].second;
         enqueue_step(m, tree, groups, ph, 0, hk, nullptr, st);  // warm-up
         NVDB_HIP(hipEventRecord(e0, st));
         for (int r = 0; r < reps; ++r) enqueue_step(m, tree, groups, ph, 0, hk, nullptr, st);
@@ -869,11 +890,12 @@ nvdb_status nvdb_autotune(nvdb_model* m, const nvdb_tree* tree, int32_t nets_mas
         times.push_back(ms);
         if (c == 0 || ms < best_ms) {
           best_ms = ms;
-          best = cands[c];
+          best = c;
         }
       }
     } catch (...) {
       m->train_g = saved_g;
+      for (int k : nets) m->nets[k].ks.train = saved_train[k];
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
       throw;
@@ -881,15 +903,31 @@ nvdb_status nvdb_autotune(nvdb_model* m, const nvdb_tree* tree, int32_t nets_mas
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     for (int k : nets) m->nets[k].step = saved_step[k];
-    m->train_g = best;
+    use_kind(cands[best].first);
+    m->train_g = cands[best].second;
     if (report) {
       std::memset(report, 0, sizeof(*report));
-      report->chosen_g = best;
+      report->chosen_g = cands[best].second;
+      report->chosen_kernel = cands[best].first;
       report->n_candidates = (int32_t)cands.size();
       for (size_t c = 0; c < cands.size(); ++c) {
-        report->g[c] = cands[c];
+        report->kernel[c] = cands[c].first;
+        report->g[c] = cands[c].second;
         report->ms_per_step[c] = times[c];
       }
+    }
+  });
+}
+
+nvdb_status nvdb_model_set_train_kernel(nvdb_model* m, int32_t kind) {
+  return guarded([&] {
+    NVDB_REQUIRE(m && (kind == NVDB_TRAIN_REGISTERS || kind == NVDB_TRAIN_ROWS), NVDB_E_INVALID,
+                 "unknown training kernel");
+    wait_model(m);
+    for (int k = 0; k < NVDB_MAX_NETS; ++k) {
+      if (!m->nets[k].present) continue;
+      KernelSet& ks = m->nets[k].ks;
+      ks.train = (kind == NVDB_TRAIN_ROWS && ks.train_rows) ? ks.train_rows : ks.train_classic;
     }
   });
 }
@@ -1067,7 +1105,7 @@ nvdb_status nvdb_fit_sequence(nvdb_model* m, const nvdb_tree* const* frames, int
 }
 
 // ------------------------------------------------------------------ decode
-static int infer_grid(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 512)); }
+static int infer8_grid(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 512)); }
 
 }  // extern "C"
 
@@ -1088,9 +1126,9 @@ static void run_infer(const nvdb_model* m, const Net& N, const Tree* tree, int s
     launch_quant_fp8(N.s, N.theta.p, N.w8.p, N.w8inv.p, st);
     I.w8 = N.w8.p;
     I.w8inv = N.w8inv.p;
-    launch_infer8(N.ks, I, infer_grid(n), st);
+    launch_infer8(N.ks, I, infer8_grid(n), st);
   } else {
-    launch_infer(N.ks, I, infer_grid(n), st);
+    launch_infer(N.ks, I, infer_grid(N.ks, n), st);
   }
 }
 
@@ -1115,6 +1153,82 @@ static void decode_impl(const nvdb_model* m, const nvdb_tree* tree, float* value
     run_infer(m, N, tree, SRC_LEAF_SLOTS, 512 * tree->n_leaf, I, fp8, st);
   }
 }
+
+extern "C" {
+
+nvdb_status nvdb_autotune_decode(nvdb_model* m, const nvdb_tree* tree, int32_t nets_mask, int32_t reps,
+                                 nvdb_decode_tune_report* report, void* stream) {
+  return guarded([&] {
+    NVDB_REQUIRE(m && tree && reps >= 1 && reps <= 1000, NVDB_E_INVALID, "bad autotune arguments");
+    hipStream_t st = (hipStream_t)stream;
+    const std::vector<int> nets = fit_nets(m, tree, nets_mask);
+    hipEvent_t e0, e1;
+    NVDB_HIP(hipEventCreate(&e0));
+    NVDB_HIP(hipEventCreate(&e1));
+    if (report) std::memset(report, 0, sizeof(*report));
+    int nc = 0;
+    try {
+      wait_model(m);
+      for (int k : nets) {
+        Net& N = m->nets[k];
+        int64_t n;
+        const int src = population_src(k, tree, &n);
+        DevBuf<float> y;
+        y.alloc(n * N.s.C);
+        const int saved = N.ks.infer_sel;
+        int best = 0;
+        float best_ms = 0.f;
+        for (int v = 0; v < N.ks.n_infer_v; ++v) {
+          N.ks.infer_sel = v;
+          InferLaunch I{};
+          I.out_kind = OUT_Y;
+          I.y = y.p;
+          run_infer(m, N, tree, src, n, I, false, st);  // warm-up
+          NVDB_HIP(hipEventRecord(e0, st));
+          for (int r = 0; r < reps; ++r) run_infer(m, N, tree, src, n, I, false, st);
+          NVDB_HIP(hipEventRecord(e1, st));
+          NVDB_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          NVDB_HIP(hipEventElapsedTime(&ms, e0, e1));
+          ms /= (float)reps;
+          if (v == 0 || ms < best_ms) {
+            best_ms = ms;
+            best = v;
+          }
+          if (report && nc < NVDB_TUNE_MAX) {
+            report->net[nc] = k;
+            report->waves[nc] = N.ks.infer_v[v].waves;
+            report->tiles[nc] = N.ks.infer_v[v].nt;
+            report->ms[nc] = ms;
+            ++nc;
+          }
+        }
+        (void)saved;
+        N.ks.infer_sel = best;
+        if (report) report->chosen[k] = best;
+      }
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (report) report->n_candidates = nc;
+  });
+}
+
+nvdb_status nvdb_model_set_decode_shape(nvdb_model* m, int32_t net, int32_t index) {
+  return guarded([&] {
+    NVDB_REQUIRE(m, NVDB_E_INVALID, "null model");
+    Net& N = net_of(m, net);
+    NVDB_REQUIRE(index >= 0 && index < N.ks.n_infer_v, NVDB_E_INVALID, "no such decode tile shape");
+    wait_model(m);
+    N.ks.infer_sel = index;
+  });
+}
+
+}  // extern "C"
 
 static void decode_l1_impl(const nvdb_model* m, const nvdb_tree* tree, uint8_t* classes_dev, bool fp8, hipStream_t st) {
   NVDB_REQUIRE(m && tree && classes_dev, NVDB_E_INVALID, "null argument");
@@ -1324,7 +1438,7 @@ nvdb_status nvdb_query(const nvdb_model* m, const nvdb_tree* tree, const float* 
       I.spec.n_dev = cnt.p;
       I.out_kind = OUT_Y;
       I.y = y.p;
-      launch_infer(N.ks, I, infer_grid(nb), st);
+      launch_infer(N.ks, I, infer_grid(N.ks, nb), st);
       query_scatter(y.p, hit_idx.p, nb, cnt.p, m->d.value_scale, values_dev + b0, st);
     }
     NVDB_HIP(hipStreamSynchronize(st));
@@ -1363,7 +1477,7 @@ nvdb_status nvdb_query_noalloc(const nvdb_model* m, const nvdb_tree* tree, const
       I.spec.n_dev = qs.cnt;
       I.out_kind = OUT_Y;
       I.y = qs.y;
-      launch_infer(N.ks, I, infer_grid(nb), st);
+      launch_infer(N.ks, I, infer_grid(N.ks, nb), st);
       query_scatter(qs.y, qs.hit_idx, nb, qs.cnt, m->d.value_scale, values_dev + b0, st);
     }
     mark(m, st);
@@ -1618,7 +1732,7 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
     I.spec.n = hc[k];
     I.out_kind = OUT_Y;
     I.y = y + hs[k];
-    launch_infer(N.ks, I, infer_grid(hc[k]), st);
+    launch_infer(N.ks, I, infer_grid(N.ks, hc[k]), st);
     query_scatter(y + hs[k], bslot + hs[k], hc[k], cnt + k, slots ? 1.f : experts[k]->d.value_scale, yslot, st);
   }
   moe_blend(*tree, slots, g, tab, yslot, slots ? nullptr : values_dev, slots ? mask_dev : nullptr, st);
@@ -1656,7 +1770,7 @@ static void forward_dev_impl(const nvdb_model* m, int32_t net, const Tree* tree,
   I.tree = tree_view(tree);
   I.out_kind = OUT_Y;
   I.y = y_dev;
-  launch_infer(N.ks, I, infer_grid(sp.n), st);
+  launch_infer(N.ks, I, infer_grid(N.ks, sp.n), st);
   mark(m, st);
 }
 

@@ -570,10 +570,12 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
 }
 
 // ============================================================== inference kernel
-template <int PREC, int W, int H, int KP, int C>
+// A decode tile shape: WV waves per work-group (one LDS copy of the weights), each
+// NTV 32-sample tiles sharing every weight fragment.
+template <int PREC, int W, int H, int KP, int C, int NTV = 1, int WV = INFER_WAVES>
 struct InferCfg {
-  static constexpr int NT = (PREC == NVDB_BF16) ? INFER_NT : 1;  // 32-sample tiles per wave sharing each weight fragment
-  static constexpr int WAVES = INFER_WAVES;          // waves per work-group (one LDS copy of the weights)
+  static constexpr int NT = NTV;
+  static constexpr int WAVES = WV;
   // Each 32-row block of the weight copy is followed by 64 pad bytes: a lane's reads of
   // two blocks 8192 bytes apart would hit the same banks when fetched together.
   static constexpr int BSTRIDE = 32 * 256 + 64;
@@ -582,11 +584,11 @@ struct InferCfg {
   static constexpr int LDS_BYTES = WL_BYTES + SMALL_FLOATS * 4;
 };
 
-template <int PREC, int W, int H, int KP, int C, int ACT>
-__global__ void __launch_bounds__(64 * INFER_WAVES, 1)
-    __attribute__((amdgpu_waves_per_eu(INFER_WAVES / 4, INFER_WAVES / 4))) k_infer(InferLaunch I) {
+template <int PREC, int W, int H, int KP, int C, int ACT, int NTV, int WV>
+__global__ void __launch_bounds__(64 * WV, 1) __attribute__((amdgpu_waves_per_eu(WV / 4, WV / 4)))
+k_infer(InferLaunch I) {
   using P = PR<PREC>;
-  using CF = InferCfg<PREC, W, H, KP, C>;
+  using CF = InferCfg<PREC, W, H, KP, C, NTV, WV>;
   constexpr int NB = W / 32, NIB0 = KP / 32, SR = P::SR, NT = CF::NT;
   constexpr int NA = NB > NIB0 ? NB : NIB0;
   constexpr bool BF = (PREC == NVDB_BF16);
@@ -1194,9 +1196,26 @@ __global__ void k_sample(uint64_t sseed, uint32_t npop, int64_t n, uint32_t* out
 template <int PREC, int W, int H, int KP, int C, int ACT>
 KernelSet make_set() {
   static_assert(KP % 64 == 0, "the FP8 form takes k-steps of 64 features");
-  KernelSet k{k_train<PREC, W, H, KP, C, ACT>, k_infer<PREC, W, H, KP, C, ACT>,
-              TrainCfg<PREC, W, H, KP, C>::LDS_BYTES, InferCfg<PREC, W, H, KP, C>::LDS_BYTES,
-              ACT == ACT_RELU ? k_infer_fp8<W, H, KP, C> : nullptr, nullptr};
+  KernelSet k{};
+  k.train = k.train_classic = k_train<PREC, W, H, KP, C, ACT>;
+  k.train_lds = TrainCfg<PREC, W, H, KP, C>::LDS_BYTES;
+  k.infer_lds = InferCfg<PREC, W, H, KP, C>::LDS_BYTES;
+  k.infer8 = ACT == ACT_RELU ? k_infer_fp8<W, H, KP, C> : nullptr;
+  // decode tile shapes (waves per work-group, tiles per wave), the default first:
+  // BF16 (8, 2), (8, 1), (4, 2), (4, 4); FP32 (8, 1), (4, 1), (4, 2)
+  if constexpr (PREC == NVDB_BF16) {
+    k.infer_v[0] = {k_infer<PREC, W, H, KP, C, ACT, 2, 8>, 8, 2};
+    k.infer_v[1] = {k_infer<PREC, W, H, KP, C, ACT, 1, 8>, 8, 1};
+    k.infer_v[2] = {k_infer<PREC, W, H, KP, C, ACT, 2, 4>, 4, 2};
+    k.infer_v[3] = {k_infer<PREC, W, H, KP, C, ACT, 4, 4>, 4, 4};
+    k.n_infer_v = 4;
+  } else {
+    k.infer_v[0] = {k_infer<PREC, W, H, KP, C, ACT, 1, 8>, 8, 1};
+    k.infer_v[1] = {k_infer<PREC, W, H, KP, C, ACT, 1, 4>, 4, 1};
+    k.infer_v[2] = {k_infer<PREC, W, H, KP, C, ACT, 2, 4>, 4, 2};
+    k.n_infer_v = 3;
+  }
+  k.infer_sel = 0;
   if constexpr (PREC == NVDB_BF16 && W == 128 && KP == 128 && C == 1 && (H == 3 || H == 4) && ACT == ACT_RELU)
     k.train_rows = train_rows_kernel(H);
   return k;
@@ -1247,8 +1266,16 @@ void launch_train(const KernelSet& ks, const TrainLaunch& L, int n_nets, hipStre
   hipLaunchKernelGGL(ks.train, dim3(L.G, n_nets), dim3(256), 0, st, L);
   NVDB_HIP(hipGetLastError());
 }
+int infer_grid(const KernelSet& ks, int64_t n) {
+  // half a pass of the grid per work-group (idle waves help small decodes), at most
+  // 4096 waves in flight
+  const InferVariant& v = ks.infer_v[ks.infer_sel];
+  const int64_t per_wg = 16 * (int64_t)v.nt * v.waves;
+  return (int)std::max<int64_t>(1, std::min<int64_t>((n + per_wg - 1) / per_wg, 4096 / v.waves));
+}
 void launch_infer(const KernelSet& ks, const InferLaunch& I, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(ks.infer, dim3(grid), dim3(64 * INFER_WAVES), 0, st, I);
+  const InferVariant& v = ks.infer_v[ks.infer_sel];
+  hipLaunchKernelGGL(v.fn, dim3(grid), dim3(64 * v.waves), 0, st, I);
   NVDB_HIP(hipGetLastError());
 }
 void launch_reduce_adam(const AdamLaunch& A, int64_t max_p, int n_nets, hipStream_t st) {

@@ -244,14 +244,23 @@ struct AdamNet {
 struct AdamLaunch {
   AdamNet nets[NVDB_MAX_NETS];
 };
+// One compiled decode tile shape.
+struct InferVariant {
+  void (*fn)(InferLaunch);
+  int waves;  // waves per work-group
+  int nt;     // 32-sample tiles per wave
+};
+constexpr int MAX_INFER_VARIANTS = 4;
 struct KernelSet {
-  void (*train)(TrainLaunch);
-  void (*infer)(InferLaunch);
-  int train_lds, infer_lds;
-  void (*infer8)(InferLaunch);  // FP8 form of the forward pass
+  void (*train)(TrainLaunch);          // the training kernel in use
+  void (*train_classic)(TrainLaunch);  // activations in registers
   // BF16 training kernel keeping activations as LDS rows (128-wide networks on 64
   // Fourier features, one output), or null
   void (*train_rows)(TrainLaunch);
+  int train_lds, infer_lds;
+  void (*infer8)(InferLaunch);  // FP8 form of the forward pass
+  InferVariant infer_v[MAX_INFER_VARIANTS];  // decode tile shapes, [0] the default
+  int n_infer_v, infer_sel;
 };
 // Bytes of the e4m3 weight fragments of all hidden layers (the FP8 form).
 // Elements of the bf16 fragment copies: all layers (forward), layers 1..H-1 (transposed).
@@ -269,6 +278,8 @@ bool find_kernels(int prec, int W, int H, int KP, int C, int act, KernelSet* out
 void launch_quant_fp8(const NetShape& s, const float* theta, char* w8, float* w8inv, hipStream_t st);
 void launch_infer8(const KernelSet& ks, const InferLaunch& I, int grid, hipStream_t st);
 void launch_train(const KernelSet& ks, const TrainLaunch& L, int n_nets, hipStream_t st);
+// work-groups of a decode launch of n samples with the selected tile shape
+int infer_grid(const KernelSet& ks, int64_t n);
 void launch_infer(const KernelSet& ks, const InferLaunch& I, int grid, hipStream_t st);
 void launch_reduce_adam(const AdamLaunch& A, int64_t max_p, int n_nets, hipStream_t st);
 void launch_write_shadow(const AdamNet& A, hipStream_t st);

@@ -68,9 +68,18 @@ class TopologyReport(C.Structure):
                 ("n_common", C.c_int64), ("max_abs", C.c_double), ("rms", C.c_double)]
 
 
+TUNE_MAX = 32
+TRAIN_REGISTERS, TRAIN_ROWS = 0, 1
+
+
 class TuneReport(C.Structure):
-    _fields_ = [("chosen_g", C.c_int32), ("n_candidates", C.c_int32), ("g", C.c_int32 * 16),
-                ("ms_per_step", C.c_float * 16)]
+    _fields_ = [("chosen_g", C.c_int32), ("chosen_kernel", C.c_int32), ("n_candidates", C.c_int32),
+                ("kernel", C.c_int32 * TUNE_MAX), ("g", C.c_int32 * TUNE_MAX), ("ms_per_step", C.c_float * TUNE_MAX)]
+
+
+class DecodeTuneReport(C.Structure):
+    _fields_ = [("n_candidates", C.c_int32), ("net", C.c_int32 * TUNE_MAX), ("waves", C.c_int32 * TUNE_MAX),
+                ("tiles", C.c_int32 * TUNE_MAX), ("ms", C.c_float * TUNE_MAX), ("chosen", C.c_int32 * 3)]
 
 
 class ErrorReport(C.Structure):
@@ -127,6 +136,9 @@ _SIGS = {
                                       _P, _P]),
     "nvdb_autotune": (C.c_int32, [_P, _P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(TuneReport), _P]),
     "nvdb_model_set_train_groups": (C.c_int32, [_P, C.c_int32]),
+    "nvdb_model_set_train_kernel": (C.c_int32, [_P, C.c_int32]),
+    "nvdb_autotune_decode": (C.c_int32, [_P, _P, C.c_int32, C.c_int32, C.POINTER(DecodeTuneReport), _P]),
+    "nvdb_model_set_decode_shape": (C.c_int32, [_P, C.c_int32, C.c_int32]),
     "nvdb_decode": (C.c_int32, [_P, _P, _P, _P, _P]),
     "nvdb_decode_l1": (C.c_int32, [_P, _P, _P, _P]),
     "nvdb_decode_fp8": (C.c_int32, [_P, _P, _P, _P, _P]),
@@ -344,11 +356,27 @@ class Model:
         return losses[:, :steps] if return_losses else None
 
     def autotune(self, tree, nets_mask, batch, reps=5):
-        """Pick the work-groups per network for training steps of `batch` samples;
-        returns (chosen G, {G: ms per step})."""
+        """Pick the training kernel and the work-groups per network for training steps
+        of `batch` samples; returns (chosen G, {(kernel, G): ms per step}); the chosen
+        kernel is in self.train_kernel."""
         r = TuneReport()
         _check(_lib.nvdb_autotune(self.h, tree.h, nets_mask, batch, reps, C.byref(r), _stream()))
-        return r.chosen_g, {r.g[i]: r.ms_per_step[i] for i in range(r.n_candidates)}
+        self.train_kernel = r.chosen_kernel
+        return r.chosen_g, {(r.kernel[i], r.g[i]): r.ms_per_step[i] for i in range(r.n_candidates)}
+
+    def set_train_kernel(self, kind):
+        _check(_lib.nvdb_model_set_train_kernel(self.h, int(kind)))
+
+    def autotune_decode(self, tree, nets_mask, reps=5):
+        """Pick each network's decode tile shape; returns ({net: chosen index},
+        [(net, waves, tiles, ms)])."""
+        r = DecodeTuneReport()
+        _check(_lib.nvdb_autotune_decode(self.h, tree.h, nets_mask, reps, C.byref(r), _stream()))
+        cand = [(r.net[i], r.waves[i], r.tiles[i], r.ms[i]) for i in range(r.n_candidates)]
+        return {k: r.chosen[k] for k in range(3) if (nets_mask >> k) & 1}, cand
+
+    def set_decode_shape(self, net, index):
+        _check(_lib.nvdb_model_set_decode_shape(self.h, int(net), int(index)))
 
     def set_train_groups(self, g):
         _check(_lib.nvdb_model_set_train_groups(self.h, int(g)))

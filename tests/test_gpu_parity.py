@@ -1044,8 +1044,10 @@ def test_autotune_leaves_state_and_fits_match(gpu_lib, sphere):
     m.fit(tr, steps=2, batch=4096, nets_mask=1, seed=1)
     before = (m.get_params(0), m.get_opt_state(0))
     g, times = m.autotune(tr, nets_mask=1, batch=1 << 14, reps=2)
-    assert g in times and set(times) <= {32, 64, 128, 192, 256, 320, 384, 512, 128}
-    assert times[g] == min(times.values()) and all(t > 0 for t in times.values())
+    assert m.train_kernel == gpu_lib.TRAIN_REGISTERS and (m.train_kernel, g) in times
+    assert {k for k, _ in times} == {gpu_lib.TRAIN_REGISTERS}
+    assert {gg for _, gg in times} <= {32, 64, 128, 192, 256, 320, 384, 512, 128}
+    assert times[(m.train_kernel, g)] == min(times.values()) and all(t > 0 for t in times.values())
     after = (m.get_params(0), m.get_opt_state(0))
     assert np.array_equal(before[0], after[0])
     assert all(np.array_equal(a, b) for a, b in zip(before[1][:2], after[1][:2])) and before[1][2] == after[1][2]
@@ -1061,6 +1063,60 @@ def test_autotune_leaves_state_and_fits_match(gpu_lib, sphere):
             res.setdefault(gg, []).append((L, m.get_params(0)))
         assert np.array_equal(res[gg][0][1], res[gg][1][1]) and np.array_equal(res[gg][0][0], res[gg][1][0])
         assert np.max(np.abs(res[gg][0][0] - lo) / lo) <= 1e-5
+
+
+def test_autotune_kernels_and_decode_shapes(gpu_lib, sphere):
+    """The autotuner's candidates cover both training kernels of the BF16 4x128
+    networks, and a fit with either kernel follows the oracle; every decode tile
+    shape gives bit-identical outputs (the per-sample arithmetic does not depend on
+    the tiling), in both precisions, and the decode autotuner keeps one of them."""
+    tr, ot = sphere
+    W_, H_, m_ = 128, 4, 64
+    shapes = mlp.layer_shapes(2 * m_, W_, H_, 1)
+    B = workloads.ffm_matrix(m_, 3.0, seed=5)
+    th0 = workloads.init_params(2 * m_, W_, H_, 1, seed=6)
+    m = gpu_lib.Model({0: (W_, H_, m_, 1), 1: (W_, H_, m_, 1)}, precision=gpu_lib.BF16, domain_size=64,
+                      value_scale=3.0)
+    for k in (0, 1):
+        m.set_params(k, th0)
+        m.set_encoding(k, B)
+    g, times = m.autotune(tr, nets_mask=3, batch=1 << 15, reps=2)
+    assert {k for k, _ in times} == {gpu_lib.TRAIN_REGISTERS, gpu_lib.TRAIN_ROWS}
+    assert times[(m.train_kernel, g)] == min(times.values())
+    _, _, _, lo = F.train(th0.astype(np.float64), shapes, B.astype(np.float64), ot, "regressor", (0, 0, 0), 64,
+                          T.SDF, 3.0, steps=3, batch=1 << 15, seed=4)
+    for kind in (gpu_lib.TRAIN_REGISTERS, gpu_lib.TRAIN_ROWS):
+        m.set_train_kernel(kind)
+        for k in (0, 1):
+            m.set_params(k, th0)
+            m.set_opt_state(k, np.zeros_like(th0), np.zeros_like(th0), 0)
+        L = m.fit(tr, steps=3, batch=1 << 15, nets_mask=3, seed=4)[0]
+        assert np.max(np.abs(L - lo) / lo) <= 2e-2, (kind, L, lo)
+    for prec, desc in ((gpu_lib.BF16, (W_, H_, m_, 1)), (gpu_lib.FP32, (64, 3, 18, 1))):
+        mm = gpu_lib.Model({0: desc, 1: desc}, precision=prec, domain_size=64, value_scale=3.0)
+        for k in (0, 1):
+            mm.set_params(k, workloads.init_params(2 * desc[2], desc[0], desc[1], 1, seed=7 + k))
+            mm.set_encoding(k, B if desc[2] == m_ else workloads.pe_matrix(6))
+        ref = None
+        n_shapes = 4 if prec == gpu_lib.BF16 else 3
+        for i in range(n_shapes):
+            for k in (0, 1):
+                mm.set_decode_shape(k, i)
+            v, mk = mm.decode(tr)
+            out = (v.cpu().numpy().view(np.uint32), mk.cpu().numpy())
+            if ref is None:
+                ref = out
+            assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), (prec, i)
+        with pytest.raises(gpu_lib.NvdbError) as e:
+            mm.set_decode_shape(0, n_shapes)
+        assert e.value.code == gpu_lib.E_INVALID
+        chosen, cands = mm.autotune_decode(tr, nets_mask=3, reps=2)
+        assert len(cands) == 2 * n_shapes and all(c[3] > 0 for c in cands)
+        for k in (0, 1):
+            mine = [c[3] for c in cands if c[0] == k]
+            assert mine[chosen[k]] == min(mine)
+        v, mk = mm.decode(tr)
+        assert np.array_equal(v.cpu().numpy().view(np.uint32), ref[0]) and np.array_equal(mk.cpu().numpy(), ref[1])
 
 
 # --------------------------------------------------------------------------- FP8 form of the decode
