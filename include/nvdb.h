@@ -220,11 +220,11 @@ nvdb_status nvdb_fit(nvdb_model* model, const nvdb_tree* tree, const nvdb_fit_de
 /* Fits of several independent models (the experts of a sparse domain
  * decomposition, Sec. 3.4: each subdomain's networks train on their own voxels
  * with no exchange), models[e] on trees[e], each exactly as nvdb_fit would run
- * it, with the same schedule (i.i.d. draws only).  The experts go round-robin
- * onto two internal streams (default priority) that start after the work
- * already on `stream`, and their steps are enqueued step by step across the
- * experts, so two experts' training launches share the GPU.  The call returns
- * when every fit is done.  loss_host, if not NULL, receives
+ * it, with the same schedule (i.i.d. draws only).  Per step, the networks that
+ * share a training kernel and a work-group count go into launches of up to 8
+ * networks (each sampling its own tree), and one optimiser launch updates up to
+ * 16 networks, all on `stream`; every network's result is bit-identical to its
+ * own nvdb_fit.  The call returns when every fit is done.  loss_host, if not NULL, receives
  * float[n][NVDB_MAX_NETS][steps].  fit->train_kernel_ms is ignored.  Errors:
  * E_INVALID (null arguments, n outside [1, 4096], a model listed twice, explicit
  * sample orders, bad schedule), otherwise those of nvdb_fit (on an error the

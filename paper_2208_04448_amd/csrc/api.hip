@@ -598,81 +598,90 @@ static void reserve_step(Net& N, int32_t batch, int32_t n_steps, int g) {
 // `groups` on `tree`: a gather per network, one fused train launch per group,
 // one reduce + Adam launch for all.  Workspace must be reserved beforehand.
 // `ev`, if non-null, holds two events per group around its train launch.
+// The record of network k of model m for one training step on `tree` (n samples).
+static void fill_train_net(nvdb_model* m, const Tree* tree, int k, const Phase& ph, int step, const StepHooks& hk,
+                           TrainNet& tn) {
+  Net& N = m->nets[k];
+  tn.net = net_view(N);
+  tn.tree = tree_view(tree);
+  base_spec(m, &tn.spec);
+  int64_t pop;
+  tn.spec.src = population_src(k, tree, &pop);
+  tn.spec.loss = k == NVDB_NET_REGRESSOR ? LOSS_MSE : (k == NVDB_NET_L0 ? LOSS_BCE : LOSS_CE);
+  tn.spec.npop = (uint32_t)pop;
+  int64_t n = ph.batch;
+  if (ph.idx && ph.idx->idx_dev[k]) {
+    const int64_t off = (int64_t)step * ph.batch;
+    n = std::min<int64_t>(ph.batch, ph.idx->idx_count[k] - off);
+    tn.spec.idx = ph.idx->idx_dev[k] + off;
+    tn.spec.bad_idx = m->errw.p;
+  } else {
+    tn.spec.step_seed = step_seed(ph.seed, k, N.step);
+  }
+  tn.spec.n = n;
+  tn.spec.inv_n = 1.f / (float)n;
+  tn.prev_loss = hk.prev_loss[k];
+  tn.stop_below = hk.stop_below[k];
+  // the BF16 kernels draw i.i.d. samples over voxels or leaf slots themselves;
+  // explicit index lists, the level-1 slots and the FP32 form use the gather kernel
+  tn.fused = m->d.precision == NVDB_BF16 && !tn.spec.idx &&
+             (tn.spec.src == SRC_VOXELS || tn.spec.src == SRC_LEAF_SLOTS);
+  tn.partial = N.partial.p;
+  tn.loss_partial = N.loss_partial.p;
+  tn.xt = N.xt.p;
+}
+
+// The optimiser record of network k after a training launch of G work-groups.
+static AdamNet fill_adam_net(nvdb_model* m, int k, const TrainNet& tn, int G, const Phase& ph, const StepHooks& hk) {
+  Net& N = m->nets[k];
+  NVDB_REQUIRE(N.partial.n >= (size_t)G * N.s.pstride() && N.xt.n >= (size_t)tn.spec.n, NVDB_E_STATE,
+               "training workspace not reserved");
+  const int64_t s = N.step + 1;
+  AdamNet a = adam_view(N);
+  a.partial = N.partial.p;
+  a.loss_partial = N.loss_partial.p;
+  a.G = G;
+  a.loss_out = hk.loss_out[k];
+  a.loss_scale = tn.spec.inv_n;
+  a.lr = (float)((double)ph.lr * std::pow((double)ph.lr_decay, (double)((s - 1) / ph.lr_interval)));
+  a.bc1 = (float)(1.0 - std::pow(0.9, (double)s));
+  a.bc2 = (float)(1.0 - std::pow(0.999, (double)s));
+  a.prev_loss = hk.prev_loss[k];
+  a.stop_below = hk.stop_below[k];
+  a.ran = hk.ran[k];
+  a.grad_out = hk.grad_out[k];
+  return a;
+}
+
+// One training step of the networks of `groups` (each group one launch of its kernel).
 static void enqueue_step(nvdb_model* m, const Tree* tree, const std::vector<std::vector<int>>& groups,
                          const Phase& ph, int step, const StepHooks& hk, hipEvent_t* ev, hipStream_t st) {
-  const TreeView tv = tree_view(tree);
   AdamLaunch AL{};
   int na = 0;
   int64_t maxP = 0;
   size_t evi = 0;
   for (auto& grp : groups) {
+    NVDB_REQUIRE(grp.size() <= (size_t)MAX_LAUNCH_NETS, NVDB_E_INVALID, "too many networks for one launch");
     TrainLaunch L{};
-    L.tree = tv;
     int G = 1;
-    int slot = 0;
-    for (int k : grp) {
-      Net& N = m->nets[k];
-      TrainNet& tn = L.nets[slot++];
-      tn.net = net_view(N);
-      base_spec(m, &tn.spec);
-      int64_t pop;
-      tn.spec.src = population_src(k, tree, &pop);
-      tn.spec.loss = k == NVDB_NET_REGRESSOR ? LOSS_MSE : (k == NVDB_NET_L0 ? LOSS_BCE : LOSS_CE);
-      tn.spec.npop = (uint32_t)pop;
-      int64_t n = ph.batch;
-      if (ph.idx && ph.idx->idx_dev[k]) {
-        const int64_t off = (int64_t)step * ph.batch;
-        n = std::min<int64_t>(ph.batch, ph.idx->idx_count[k] - off);
-        tn.spec.idx = ph.idx->idx_dev[k] + off;
-        tn.spec.bad_idx = m->errw.p;
-      } else {
-        tn.spec.step_seed = step_seed(ph.seed, k, N.step);
-      }
-      tn.spec.n = n;
-      tn.spec.inv_n = 1.f / (float)n;
-      tn.prev_loss = hk.prev_loss[k];
-      tn.stop_below = hk.stop_below[k];
-      G = std::max(G, train_grid(n, m->train_g > 0 ? m->train_g : DEFAULT_G));
+    for (size_t i = 0; i < grp.size(); ++i) {
+      fill_train_net(m, tree, grp[i], ph, step, hk, L.nets[i]);
+      G = std::max(G, train_grid(L.nets[i].spec.n, m->train_g > 0 ? m->train_g : DEFAULT_G));
     }
-    slot = 0;
     SampleSpec gspec[NVDB_MAX_NETS];
     floatx4* gout[NVDB_MAX_NETS];
     int ng = 0;
-    for (int k : grp) {
-      Net& N = m->nets[k];
-      NVDB_REQUIRE(N.partial.n >= (size_t)G * N.s.pstride() && N.xt.n >= (size_t)L.nets[slot].spec.n,
-                   NVDB_E_STATE, "training workspace not reserved");
-      TrainNet& tn = L.nets[slot++];
-      // the BF16 kernels draw i.i.d. samples over voxels or leaf slots themselves;
-      // explicit index lists, the level-1 slots and the FP32 form use the gather kernel
-      tn.fused = m->d.precision == NVDB_BF16 && !tn.spec.idx &&
-                 (tn.spec.src == SRC_VOXELS || tn.spec.src == SRC_LEAF_SLOTS);
-      if (!tn.fused) {
-        gspec[ng] = tn.spec;
-        gout[ng++] = N.xt.p;
+    for (size_t i = 0; i < grp.size(); ++i) {
+      const int k = grp[i];
+      if (!L.nets[i].fused) {
+        gspec[ng] = L.nets[i].spec;
+        gout[ng++] = m->nets[k].xt.p;
       }
-      tn.partial = N.partial.p;
-      tn.loss_partial = N.loss_partial.p;
-      tn.xt = N.xt.p;
-      const int64_t s = N.step + 1;
-      AdamNet a = adam_view(N);
-      a.partial = N.partial.p;
-      a.loss_partial = N.loss_partial.p;
-      a.G = G;
-      a.loss_out = hk.loss_out[k];
-      a.loss_scale = tn.spec.inv_n;
-      a.lr = (float)((double)ph.lr * std::pow((double)ph.lr_decay, (double)((s - 1) / ph.lr_interval)));
-      a.bc1 = (float)(1.0 - std::pow(0.9, (double)s));
-      a.bc2 = (float)(1.0 - std::pow(0.999, (double)s));
-      a.prev_loss = hk.prev_loss[k];
-      a.stop_below = hk.stop_below[k];
-      a.ran = hk.ran[k];
-      a.grad_out = hk.grad_out[k];
-      AL.nets[na++] = a;
-      maxP = std::max(maxP, N.s.nparams());
+      AL.nets[na++] = fill_adam_net(m, k, L.nets[i], G, ph, hk);
+      maxP = std::max(maxP, m->nets[k].s.nparams());
     }
     L.G = G;
-    if (ng > 0) launch_gather_multi(gspec, gout, ng, tv, st);
+    if (ng > 0) launch_gather_multi(gspec, gout, ng, tree_view(tree), st);
     if (ev) NVDB_HIP(hipEventRecord(ev[evi++], st));
     launch_train(m->nets[grp[0]].ks, L, (int)grp.size(), st);
     if (ev) NVDB_HIP(hipEventRecord(ev[evi++], st));
@@ -681,6 +690,53 @@ static void enqueue_step(nvdb_model* m, const Tree* tree, const std::vector<std:
   for (auto& grp : groups)
     for (int k : grp)
       if (!hk.grad_out[k]) m->nets[k].step += 1;
+}
+
+// One network of one model in a multi-model step.
+struct StepUnit {
+  nvdb_model* m;
+  const Tree* tree;
+  int k;
+  int G;
+};
+
+// One training step of many models' networks (the experts of a decomposition):
+// networks of one kernel and work-group count share launches of up to
+// MAX_LAUNCH_NETS networks, each on its own tree; the optimiser launches take up
+// to MAX_ADAM_NETS networks.  Per network the same arithmetic as enqueue_step.
+static void enqueue_step_units(const std::vector<std::vector<StepUnit>>& launches, const Phase& ph, int step,
+                               hipStream_t st) {
+  std::vector<std::pair<AdamNet, int64_t>> adam;
+  for (const auto& grp : launches) {
+    TrainLaunch L{};
+    const int G = grp[0].G;
+    for (size_t i = 0; i < grp.size(); ++i) {
+      const StepUnit& u = grp[i];
+      StepHooks hk;
+      hk.loss_out[u.k] = u.m->nets[u.k].losses.p + step;
+      fill_train_net(u.m, u.tree, u.k, ph, step, hk, L.nets[i]);
+      if (!L.nets[i].fused) {
+        SampleSpec sp = L.nets[i].spec;
+        floatx4* out = u.m->nets[u.k].xt.p;
+        launch_gather_multi(&sp, &out, 1, tree_view(u.tree), st);
+      }
+      adam.push_back({fill_adam_net(u.m, u.k, L.nets[i], G, ph, hk), u.m->nets[u.k].s.nparams()});
+    }
+    L.G = G;
+    launch_train(grp[0].m->nets[grp[0].k].ks, L, (int)grp.size(), st);
+  }
+  for (size_t a0 = 0; a0 < adam.size(); a0 += MAX_ADAM_NETS) {
+    AdamLaunch AL{};
+    int64_t maxP = 0;
+    const size_t na = std::min<size_t>(MAX_ADAM_NETS, adam.size() - a0);
+    for (size_t i = 0; i < na; ++i) {
+      AL.nets[i] = adam[a0 + i].first;
+      maxP = std::max(maxP, adam[a0 + i].second);
+    }
+    launch_reduce_adam(AL, maxP, (int)na, st);
+  }
+  for (const auto& grp : launches)
+    for (const StepUnit& u : grp) u.m->nets[u.k].step += 1;
 }
 
 extern "C" {
@@ -757,56 +813,33 @@ nvdb_status nvdb_fit_experts(nvdb_model* const* models, const nvdb_tree* const* 
     // every workspace first: a buffer grown while other experts' steps are queued
     // would free memory, and a free waits for the whole device
     std::vector<std::vector<int>> nets((size_t)n);
-    std::vector<std::vector<std::vector<int>>> groups((size_t)n);
     for (int e = 0; e < n; ++e) {
       nets[e] = fit_nets(models[e], trees[e], fit->nets_mask);
-      groups[e] = kernel_groups(models[e], nets[e]);
       for (int k : nets[e])
         reserve_step(models[e]->nets[k], fit->batch, fit->steps,
                      models[e]->train_g > 0 ? models[e]->train_g : DEFAULT_G);
     }
     const Phase ph{fit->batch, fit->seed, fit->lr, fit->lr_decay, fit->lr_interval, nullptr};
     hipStream_t st = (hipStream_t)stream;
-    // A one-network training launch at 128 work-groups (the count the autotuner
-    // picks for the 4x128 networks) holds half of the 256 compute units: two
-    // streams let two experts' steps run side by side.
-    // Steps are enqueued step-major across the experts, so that a full hardware
-    // queue on one stream never leaves the other without work.
-    constexpr int NS = 2;
-    hipStream_t s[NS] = {};
-    hipEvent_t after = nullptr;
-    nvdb_status bad = NVDB_OK;
-    std::string msg;
-    NVDB_HIP(hipEventCreateWithFlags(&after, hipEventDisableTiming));
-    NVDB_HIP(hipEventRecord(after, st));
-    for (int i = 0; i < NS && bad == NVDB_OK; ++i) {
-      if (hipStreamCreateWithFlags(&s[i], hipStreamNonBlocking) != hipSuccess ||
-          hipStreamWaitEvent(s[i], after, 0) != hipSuccess) {
-        bad = NVDB_E_DEVICE;
-        msg = "stream setup failed";
+    // networks of one kernel and work-group count share launches (each on its own
+    // tree), so a step of many small experts fills the GPU in one launch
+    std::vector<std::vector<StepUnit>> launches;
+    for (int e = 0; e < n; ++e)
+      for (int k : nets[e]) {
+        const StepUnit u{models[e], trees[e], k,
+                         train_grid(fit->batch, models[e]->train_g > 0 ? models[e]->train_g : DEFAULT_G)};
+        bool put = false;
+        for (auto& grp : launches)
+          if (grp.size() < (size_t)MAX_LAUNCH_NETS && grp[0].G == u.G &&
+              grp[0].m->nets[grp[0].k].ks.train == u.m->nets[u.k].ks.train) {
+            grp.push_back(u);
+            put = true;
+            break;
+          }
+        if (!put) launches.push_back({u});
       }
-    }
-    try {
-      for (int step = 0; step < fit->steps && bad == NVDB_OK; ++step)
-        for (int e = 0; e < n; ++e) {
-          StepHooks hk;
-          for (int k : nets[e]) hk.loss_out[k] = models[e]->nets[k].losses.p + step;
-          enqueue_step(models[e], trees[e], groups[e], ph, step, hk, nullptr, s[e % NS]);
-        }
-    } catch (const Error& x) {
-      bad = x.code;
-      msg = x.what();
-    }
-    for (int i = 0; i < NS; ++i)
-      if (s[i]) {
-        if (hipStreamSynchronize(s[i]) != hipSuccess && bad == NVDB_OK) {
-          bad = NVDB_E_DEVICE;
-          msg = "expert fit failed on the device";
-        }
-        (void)hipStreamDestroy(s[i]);
-      }
-    (void)hipEventDestroy(after);
-    if (bad != NVDB_OK) throw Error(bad, msg);
+    for (int step = 0; step < fit->steps; ++step) enqueue_step_units(launches, ph, step, st);
+    NVDB_HIP(hipStreamSynchronize(st));
     if (loss_host && fit->steps > 0) {
       std::vector<float> h((size_t)fit->steps);
       bool finite = true;
@@ -1784,16 +1817,16 @@ static void backward_dev_impl(nvdb_model* m, int32_t net, const Tree* tree, Samp
   const int G = train_grid(sp.n, N.dev_G);
   TrainLaunch L{};
   L.G = G;
-  L.tree = tree_view(tree);
   TrainNet& tn = L.nets[0];
   tn.net = net_view(N);
+  tn.tree = tree_view(tree);
   sp.loss = LOSS_EXTERNAL;
   sp.gy = gy_dev;
   sp.inv_n = 1.f;
   tn.spec = sp;
   tn.partial = N.dpart.p;
   tn.loss_partial = N.dlossp.p;
-  launch_gather(tn.spec, L.tree, N.dxt.p, st);
+  launch_gather(tn.spec, tn.tree, N.dxt.p, st);
   tn.xt = N.dxt.p;
   launch_train(N.ks, L, 1, st);
   AdamLaunch AL{};

@@ -148,13 +148,13 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
   NextSample nx{};
   {
     const int64_t j0 = (int64_t)blockIdx.x * 128 + wave * 32 + (lane_id() & 31);
-    next_stage1<BF>(TN, L.tree, j0, nx);
-    next_stage2<BF>(TN, L.tree, j0, nx);
+    next_stage1<BF>(TN, TN.tree, j0, nx);
+    next_stage2<BF>(TN, TN.tree, j0, nx);
   }
   for (int64_t it = blockIdx.x; it < n_iter; it += L.G) {
     const NextSample cur = nx;
     const int64_t jn = (it + L.G) * 128 + wave * 32 + (lane_id() & 31);
-    next_stage1<BF>(TN, L.tree, jn, nx);
+    next_stage1<BF>(TN, TN.tree, jn, nx);
     const LaneK K = lane_consts();
     const int h = K.h, fl = K.fl;
     const int z = opaque_zero();
@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
         });
       }
     }
-    next_stage2<BF>(TN, L.tree, jn, nx);  // the next tile's leaf origin (voxels)
+    next_stage2<BF>(TN, TN.tree, jn, nx);  // the next tile's leaf origin (voxels)
     // head (VALU): y_c = sum_f Wh[c][f] a_H[f] + bh[c]
     float y[C], gy[C];
 #pragma unroll

@@ -185,10 +185,11 @@ constexpr int ROW_ELEMS = 128;  // bf16 elements per stored row
 // ----------------------------------------------------------- launch records
 struct TrainNet {
   NetView net;
+  TreeView tree;        // the tree this network samples
   SampleSpec spec;
   const floatx4* xt;    // gathered samples of this step: (x, y, z, target or class)
   // nonzero: the kernel draws the i.i.d. samples itself (voxels or leaf slots) from
-  // the launch's tree instead of reading xt
+  // the network's tree instead of reading xt
   int32_t fused;
   float* partial;       // [G][P]
   float* loss_partial;  // [G]
@@ -197,9 +198,11 @@ struct TrainNet {
   const float* prev_loss;
   const float* stop_below;
 };
+// Networks of one kernel trained in one launch (gridDim.y), each on its own tree;
+// the experts of a domain decomposition share launches.
+constexpr int MAX_LAUNCH_NETS = 8;
 struct TrainLaunch {
-  TrainNet nets[NVDB_MAX_NETS];
-  TreeView tree;
+  TrainNet nets[MAX_LAUNCH_NETS];
   int32_t G;
 };
 enum InferOut : int32_t { OUT_Y = 0, OUT_VALUES = 1, OUT_MASK = 2, OUT_CLASS = 3 };
@@ -241,8 +244,9 @@ struct AdamNet {
   float* whead;
   float* bhead;
 };
+constexpr int MAX_ADAM_NETS = 16;
 struct AdamLaunch {
-  AdamNet nets[NVDB_MAX_NETS];
+  AdamNet nets[MAX_ADAM_NETS];
 };
 // One compiled decode tile shape.
 struct InferVariant {

@@ -209,13 +209,13 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
   NextSample nx{};
   {
     const int64_t j0 = (int64_t)blockIdx.x * 128 + wave * 32 + (lane_id() & 31);
-    next_stage1<true>(TN, L.tree, j0, nx);
-    next_stage2<true>(TN, L.tree, j0, nx);
+    next_stage1<true>(TN, TN.tree, j0, nx);
+    next_stage2<true>(TN, TN.tree, j0, nx);
   }
   for (int64_t it = blockIdx.x; it < n_iter; it += L.G) {
     const NextSample cur = nx;
     const int64_t jn = (it + L.G) * 128 + wave * 32 + (lane_id() & 31);
-    next_stage1<true>(TN, L.tree, jn, nx);
+    next_stage1<true>(TN, TN.tree, jn, nx);
     const LaneK K = lane_consts();
     const int h = K.h, fl = K.fl;
     const int z = opaque_zero();
@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
         wf[l] = WBuf{wf_rsrc, z + (l == 0 ? 0 : (W * KP + (l - 1) * W * W) * 2), vo, l == 0 ? NIB0 : NB};
       forward_rows<H>(wf, X0, Hl, hrows + wave * CF::ROWS, sm_bias, K);
     }
-    next_stage2<true>(TN, L.tree, jn, nx);  // the next tile's leaf origin (voxels)
+    next_stage2<true>(TN, TN.tree, jn, nx);  // the next tile's leaf origin (voxels)
 
     // ================= head (VALU): y = Wh a_H + bh, loss, g_H = Wh^T gy * 1[a_H > 0]
     float y[1], gy[1];

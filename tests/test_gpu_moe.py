@@ -185,7 +185,7 @@ def test_decode_moe_full_size_sampled(gpu_lib):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_fit_experts_equals_sequential_fits(gpu_lib, scene, prec):
-    """Experts fitted together (two streams) end bit-identical to the same fits
+    """Experts fitted together (shared launches) end bit-identical to the same fits
     run one after the other, with the same losses (the kernels are
     deterministic and the fits share nothing)."""
     tr, _ = scene
