@@ -1709,9 +1709,73 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
     table[(size_t)i] = k;
   }
   if (n == 0) return;
+  const size_t E = (size_t)n_experts;
+  // experts of one network shape decode in one grouped launch; the counts stay on
+  // the device (no host round trip), the pair buffers are sized for the most pairs
+  // possible (8 per item, each expert's run padded to whole chunks)
+  const KernelSet& ks0 = net_of(experts[0], net).ks;
+  bool grouped = ks0.infer_group != nullptr;
+  for (size_t k = 1; k < E && grouped; ++k) grouped = net_of(experts[k], net).ks.infer_group == ks0.infer_group;
+  if (grouped) {
+    const size_t CH = (size_t)ks0.group_chunk;
+    const size_t cap = 8 * (size_t)n + E * CH;
+    NVDB_REQUIRE(cap < (1ull << 32), NVDB_E_INVALID, "too many routed pairs for the grouped decode");
+    const size_t o_box = ((size_t)total * 4 + 255) & ~(size_t)255;
+    const size_t o_cnt = o_box + ((E * sizeof(MoeBox) + 255) & ~(size_t)255);
+    const size_t o_cs = o_cnt + (((E + 1) * 4 + 255) & ~(size_t)255);
+    const size_t o_start = o_cs + (((E + 1) * 4 + 255) & ~(size_t)255);
+    const size_t o_cur = o_start + ((E * 4 + 255) & ~(size_t)255);
+    const size_t o_nets = o_cur + ((E * 4 + 255) & ~(size_t)255);
+    MoeScratch& ws = moe_scratch();
+    std::lock_guard<std::mutex> lock(ws.mu);
+    StreamDrain drain{st};  // declared after the lock: runs before it is released
+    ws.small.ensure(o_nets + E * sizeof(GroupNet));
+    uint8_t* small = ws.small.p;
+    int32_t* tab = (int32_t*)small;
+    MoeBox* dbox = (MoeBox*)(small + o_box);
+    uint32_t* cnt = (uint32_t*)(small + o_cnt);
+    uint32_t* cs = (uint32_t*)(small + o_cs);
+    uint32_t* start = (uint32_t*)(small + o_start);
+    uint32_t* cursor = (uint32_t*)(small + o_cur);
+    GroupNet* gnets = (GroupNet*)(small + o_nets);
+    std::vector<GroupNet> hnets(E);
+    for (size_t k = 0; k < E; ++k) {
+      hnets[k].net = net_view(net_of(experts[k], net));
+      hnets[k].out_scale = slots ? 1.f : experts[k]->d.value_scale;
+    }
+    const size_t o_bs = (12 * cap + 255) & ~(size_t)255;
+    const size_t o_ys = o_bs + ((4 * cap + 255) & ~(size_t)255);
+    ws.big.ensure(o_ys + 32 * (size_t)n);
+    uint8_t* big = ws.big.p;
+    float* bx = (float*)big;
+    uint32_t* bslot = (uint32_t*)(big + o_bs);
+    float* yslot = (float*)(big + o_ys);
+    NVDB_HIP(hipMemcpyAsync(tab, table.data(), (size_t)total * 4, hipMemcpyHostToDevice, st));
+    NVDB_HIP(hipMemcpyAsync(dbox, box.data(), E * sizeof(MoeBox), hipMemcpyHostToDevice, st));
+    NVDB_HIP(hipMemcpyAsync(gnets, hnets.data(), E * sizeof(GroupNet), hipMemcpyHostToDevice, st));
+    NVDB_HIP(hipMemsetAsync(cnt, 0, (E + 1) * 4, st));
+    NVDB_HIP(hipMemsetAsync(cursor, 0, E * 4, st));
+    moe_count(*tree, slots, g, tab, n_experts, cnt, cnt + n_experts, st);
+    moe_plan(cnt, n_experts, (int)CH, cs, start, st);
+    moe_route(*tree, slots, g, tab, dbox, n_experts, start, cursor, bx, bslot, st);
+    InferGroupLaunch M{};
+    M.nets = gnets;
+    M.n_nets = n_experts;
+    M.chunk_start = cs;
+    M.count = cnt;
+    M.x = bx;
+    M.slot = bslot;
+    M.yslot = yslot;
+    launch_infer_group(ks0, M, st);
+    moe_blend(*tree, slots, g, tab, yslot, slots ? nullptr : values_dev, slots ? mask_dev : nullptr, st);
+    uint32_t uncovered = 0;
+    NVDB_HIP(hipMemcpyAsync(&uncovered, cnt + n_experts, 4, hipMemcpyDeviceToHost, st));
+    NVDB_HIP(hipStreamSynchronize(st));
+    NVDB_REQUIRE(uncovered == 0, NVDB_E_INVALID, "voxels that no expert's widened box holds");
+    return;
+  }
   // small arrays in one allocation: lookup table, boxes, counts (+ the
   // uncovered voxels), bucket starts, cursors
-  const size_t E = (size_t)n_experts;
   const size_t o_box = ((size_t)total * 4 + 255) & ~(size_t)255;
   const size_t o_cnt = o_box + ((E * sizeof(MoeBox) + 255) & ~(size_t)255);
   const size_t o_start = o_cnt + (((E + 1) * 4 + 255) & ~(size_t)255);

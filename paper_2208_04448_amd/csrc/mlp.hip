@@ -584,45 +584,45 @@ struct InferCfg {
   static constexpr int LDS_BYTES = WL_BYTES + SMALL_FLOATS * 4;
 };
 
+// The decode work of one work-group: one network's weights staged in LDS, then
+// passes of NT 32-sample tiles per wave.
 template <int PREC, int W, int H, int KP, int C, int ACT, int NTV, int WV>
-__global__ void __launch_bounds__(64 * WV, 1) __attribute__((amdgpu_waves_per_eu(WV / 4, WV / 4)))
-k_infer(InferLaunch I) {
+struct InferWG {
   using P = PR<PREC>;
   using CF = InferCfg<PREC, W, H, KP, C, NTV, WV>;
-  constexpr int NB = W / 32, NIB0 = KP / 32, SR = P::SR, NT = CF::NT;
-  constexpr int NA = NB > NIB0 ? NB : NIB0;
-  constexpr bool BF = (PREC == NVDB_BF16);
-  __shared__ __attribute__((aligned(16))) char smem[CF::LDS_BYTES];
-  const NetView& nv = I.net;
-  SampleSpec sp = I.spec;
-  if (sp.n_dev) sp.n = min(sp.n, (int64_t)*sp.n_dev);  // count known only on the device
-  const int wave = wave_id();
-  const ActC ac{nv.act_w, nv.act_rev, nv.act_rev64};
-
-  char* wl0 = smem;
-  float* sm_bias0 = (float*)(smem + CF::WL_BYTES);
-  float* sm_whead0 = sm_bias0 + H * W;
-  float* sm_bhead0 = sm_whead0 + C * W;
-  float* sm_benc0 = sm_bhead0 + 4;
-  if constexpr (BF) {
-    const u32x4* src = (const u32x4*)nv.wrow;
-    for (int i = threadIdx.x; i < H * W * 16; i += blockDim.x) {  // 16-byte pieces of the 256-byte rows
-      const int row = i >> 4, blk = row >> 5;
-      *(u32x4*)(wl0 + blk * CF::BSTRIDE + (row & 31) * 256 + (i & 15) * 16) = src[i];
+  static constexpr int NB = W / 32, NIB0 = KP / 32, SR = P::SR, NT = CF::NT;
+  static constexpr int NA = NB > NIB0 ? NB : NIB0;
+  static constexpr bool BF = (PREC == NVDB_BF16);
+  char* wl0;
+  float* sm_bias0;
+  float* sm_whead0;
+  float* sm_bhead0;
+  float* sm_benc0;
+  __device__ __forceinline__ explicit InferWG(char* smem)
+      : wl0(smem),
+        sm_bias0((float*)(smem + CF::WL_BYTES)),
+        sm_whead0(sm_bias0 + H * W),
+        sm_bhead0(sm_whead0 + C * W),
+        sm_benc0(sm_bhead0 + 4) {}
+  // Copies network nv's weights into LDS; every thread of the work-group takes part,
+  // and the caller synchronises before (if LDS was in use) and after.
+  __device__ __forceinline__ void stage(const NetView& nv) const {
+    if constexpr (BF) {
+      const u32x4* src = (const u32x4*)nv.wrow;
+      for (int i = threadIdx.x; i < H * W * 16; i += blockDim.x) {  // 16-byte pieces of the 256-byte rows
+        const int row = i >> 4, blk = row >> 5;
+        *(u32x4*)(wl0 + blk * CF::BSTRIDE + (row & 31) * 256 + (i & 15) * 16) = src[i];
+      }
     }
+    for (int i = threadIdx.x; i < H * W; i += blockDim.x) sm_bias0[i] = nv.bias[i];
+    for (int i = threadIdx.x; i < C * W; i += blockDim.x) sm_whead0[i] = nv.whead[i];
+    if (threadIdx.x < C) sm_bhead0[threadIdx.x] = nv.bhead[threadIdx.x];
+    for (int i = threadIdx.x; i < 4 * (KP / 2); i += blockDim.x) sm_benc0[i] = nv.benc[i];
   }
-  for (int i = threadIdx.x; i < H * W; i += blockDim.x) sm_bias0[i] = nv.bias[i];
-  for (int i = threadIdx.x; i < C * W; i += blockDim.x) sm_whead0[i] = nv.whead[i];
-  if (threadIdx.x < C) sm_bhead0[threadIdx.x] = nv.bhead[threadIdx.x];
-  for (int i = threadIdx.x; i < 4 * (KP / 2); i += blockDim.x) sm_benc0[i] = nv.benc[i];
-  __syncthreads();
-
-  PhaseA<NIB0> pa;
-  const bool fastenc = BF && 2 * nv.nfreq == 32 * NIB0;
-  if (fastenc) pa.load(sm_benc0);
-  const int64_t per_wave = 32 * NT;
-  const int64_t stride = (int64_t)gridDim.x * CF::WAVES * per_wave;
-  for (int64_t base = ((int64_t)blockIdx.x * CF::WAVES + wave) * per_wave; base < sp.n; base += stride) {
+  // One wave's tiles of samples base + 32 u (u < NT) of sp, written as I directs.
+  __device__ __forceinline__ void pass(const NetView& nv, const ActC& ac, const PhaseA<NIB0>& pa, bool fastenc,
+                                       const SampleSpec& sp, const TreeView& tv, const InferLaunch& I,
+                                       int64_t base) const {
     const LaneK K = lane_consts();
     const int h = K.h, fl = K.fl;
     const int z = opaque_zero();
@@ -634,7 +634,7 @@ k_infer(InferLaunch I) {
     uint32_t A[NT][NA][SR];
 #pragma unroll
     for (int u = 0; u < NT; ++u) {
-      const Smp smp = fetch_sample(sp, I.tree, base + 32 * u + fl, h == 0);
+      const Smp smp = fetch_sample(sp, tv, base + 32 * u + fl, h == 0);
       uint32_t X0[NIB0][SR];
       if constexpr (BF) {
         if (fastenc) encode_bf16_mfma<NIB0>(pa, smp, X0);
@@ -712,6 +712,8 @@ k_infer(InferLaunch I) {
         if (h == 0 && j < sp.n) {
           if (I.out_kind == OUT_VALUES) {
             I.y[j] = y[u][0] * I.out_scale;
+          } else if (I.out_kind == OUT_SCATTER) {
+            I.y[I.yidx[j]] = y[u][0] * I.out_scale;
           } else if (I.out_kind == OUT_CLASS) {
             int best = 0;
             float bv = y[u][0];
@@ -729,6 +731,73 @@ k_infer(InferLaunch I) {
         }
       }
     }
+  }
+};
+
+template <int PREC, int W, int H, int KP, int C, int ACT, int NTV, int WV>
+__global__ void __launch_bounds__(64 * WV, 1) __attribute__((amdgpu_waves_per_eu(WV / 4, WV / 4)))
+k_infer(InferLaunch I) {
+  using WG = InferWG<PREC, W, H, KP, C, ACT, NTV, WV>;
+  __shared__ __attribute__((aligned(16))) char smem[WG::CF::LDS_BYTES];
+  const NetView& nv = I.net;
+  SampleSpec sp = I.spec;
+  if (sp.n_dev) sp.n = min(sp.n, (int64_t)*sp.n_dev);  // count known only on the device
+  const ActC ac{nv.act_w, nv.act_rev, nv.act_rev64};
+  const WG wg(smem);
+  wg.stage(nv);
+  __syncthreads();
+  PhaseA<WG::NIB0> pa;
+  const bool fastenc = WG::BF && 2 * nv.nfreq == 32 * WG::NIB0;
+  if (fastenc) pa.load(wg.sm_benc0);
+  const int64_t per_wave = 32 * WG::NT;
+  const int64_t stride = (int64_t)gridDim.x * WV * per_wave;
+  for (int64_t base = ((int64_t)blockIdx.x * WV + wave_id()) * per_wave; base < sp.n; base += stride)
+    wg.pass(nv, ac, pa, fastenc, sp, I.tree, I, base);
+}
+
+// Decode of many networks of one shape in one launch (the experts of a domain
+// decomposition).  Their samples sit in one array, each network's run starting on
+// a chunk boundary (a chunk is one pass of a work-group, WV x NT x 32 samples);
+// work-group b takes the chunks [b n / G, (b + 1) n / G) of the n chunks and
+// restages the weights whenever its chunk belongs to another network.  Outputs
+// are scattered: yslot[yidx[s]] = y(s) * out_scale of the network.
+template <int PREC, int W, int H, int KP, int C, int ACT, int NTV, int WV>
+__global__ void __launch_bounds__(64 * WV, 1) __attribute__((amdgpu_waves_per_eu(WV / 4, WV / 4)))
+k_infer_group(InferGroupLaunch M) {
+  using WG = InferWG<PREC, W, H, KP, C, ACT, NTV, WV>;
+  __shared__ __attribute__((aligned(16))) char smem[WG::CF::LDS_BYTES];
+  constexpr int64_t CH = 32 * (int64_t)WG::NT * WV;
+  const WG wg(smem);
+  const uint32_t nc = M.chunk_start[M.n_nets];
+  const uint32_t c0 = (uint32_t)((uint64_t)blockIdx.x * nc / gridDim.x);
+  const uint32_t c1 = (uint32_t)((uint64_t)(blockIdx.x + 1) * nc / gridDim.x);
+  int cur = -1, k = 0;
+  PhaseA<WG::NIB0> pa;
+  bool fastenc = false;
+  for (uint32_t c = c0; c < c1; ++c) {
+    while (k + 1 < M.n_nets && M.chunk_start[k + 1] <= c) ++k;  // chunks are ordered by network
+    const NetView& nv = M.nets[k].net;
+    if (k != cur) {
+      if (cur >= 0) __syncthreads();
+      wg.stage(nv);
+      __syncthreads();
+      fastenc = WG::BF && 2 * nv.nfreq == 32 * WG::NIB0;
+      if (fastenc) pa.load(wg.sm_benc0);
+      cur = k;
+    }
+    const int64_t first = (int64_t)c * CH;  // sample offset of the chunk
+    SampleSpec sp{};
+    sp.src = SRC_COORDS;
+    sp.direct = 1;
+    sp.coords = M.x + 3 * first;
+    sp.n = min(CH, (int64_t)M.chunk_start[k] * CH + M.count[k] - first);
+    InferLaunch I{};
+    I.out_kind = OUT_SCATTER;
+    I.out_scale = M.nets[k].out_scale;
+    I.y = M.yslot;
+    I.yidx = M.slot + first;
+    const ActC ac{nv.act_w, nv.act_rev, nv.act_rev64};
+    wg.pass(nv, ac, pa, fastenc, sp, TreeView{}, I, (int64_t)wave_id() * 32 * WG::NT);
   }
 }
 
@@ -1204,12 +1273,18 @@ KernelSet make_set() {
   // decode tile shapes (waves per work-group, tiles per wave), the default first:
   // BF16 (8, 2), (8, 1), (4, 2), (4, 4); FP32 (8, 1), (4, 1), (4, 2)
   if constexpr (PREC == NVDB_BF16) {
+    k.infer_group = k_infer_group<PREC, W, H, KP, C, ACT, 2, 8>;
+    k.group_waves = 8;
+    k.group_chunk = 32 * 2 * 8;
     k.infer_v[0] = {k_infer<PREC, W, H, KP, C, ACT, 2, 8>, 8, 2};
     k.infer_v[1] = {k_infer<PREC, W, H, KP, C, ACT, 1, 8>, 8, 1};
     k.infer_v[2] = {k_infer<PREC, W, H, KP, C, ACT, 2, 4>, 4, 2};
     k.infer_v[3] = {k_infer<PREC, W, H, KP, C, ACT, 4, 4>, 4, 4};
     k.n_infer_v = 4;
   } else {
+    k.infer_group = k_infer_group<PREC, W, H, KP, C, ACT, 1, 8>;
+    k.group_waves = 8;
+    k.group_chunk = 32 * 1 * 8;
     k.infer_v[0] = {k_infer<PREC, W, H, KP, C, ACT, 1, 8>, 8, 1};
     k.infer_v[1] = {k_infer<PREC, W, H, KP, C, ACT, 1, 4>, 4, 1};
     k.infer_v[2] = {k_infer<PREC, W, H, KP, C, ACT, 2, 4>, 4, 2};
@@ -1272,6 +1347,11 @@ int infer_grid(const KernelSet& ks, int64_t n) {
   const InferVariant& v = ks.infer_v[ks.infer_sel];
   const int64_t per_wg = 16 * (int64_t)v.nt * v.waves;
   return (int)std::max<int64_t>(1, std::min<int64_t>((n + per_wg - 1) / per_wg, 4096 / v.waves));
+}
+void launch_infer_group(const KernelSet& ks, const InferGroupLaunch& M, hipStream_t st) {
+  // work-groups take contiguous chunk ranges; those past the chunk count exit
+  hipLaunchKernelGGL(ks.infer_group, dim3(4096 / ks.group_waves), dim3(64 * ks.group_waves), 0, st, M);
+  NVDB_HIP(hipGetLastError());
 }
 void launch_infer(const KernelSet& ks, const InferLaunch& I, int grid, hipStream_t st) {
   const InferVariant& v = ks.infer_v[ks.infer_sel];

@@ -375,6 +375,40 @@ void moe_route(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table
   NVDB_HIP(hipGetLastError());
 }
 
+namespace {
+// One work-group of 256 threads; n <= 4096 experts, each thread a contiguous run.
+__global__ void __launch_bounds__(256) k_moe_plan(const uint32_t* __restrict__ cnt, int n, int chunk,
+                                                  uint32_t* __restrict__ cs, uint32_t* __restrict__ start) {
+  __shared__ uint32_t part[256];
+  const int per = (n + 255) / 256, k0 = threadIdx.x * per, k1 = min(n, k0 + per);
+  uint32_t sum = 0;
+  for (int k = k0; k < k1; ++k) sum += (cnt[k] + (uint32_t)chunk - 1) / (uint32_t)chunk;
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {  // exclusive scan of the 256 partial sums
+    uint32_t run = 0;
+    for (int i = 0; i < 256; ++i) {
+      const uint32_t v = part[i];
+      part[i] = run;
+      run += v;
+    }
+    cs[n] = run;
+  }
+  __syncthreads();
+  uint32_t run = part[threadIdx.x];
+  for (int k = k0; k < k1; ++k) {
+    cs[k] = run;
+    start[k] = run * (uint32_t)chunk;
+    run += (cnt[k] + (uint32_t)chunk - 1) / (uint32_t)chunk;
+  }
+}
+}  // namespace
+
+void moe_plan(const uint32_t* cnt, int n, int chunk, uint32_t* cs, uint32_t* start, hipStream_t st) {
+  hipLaunchKernelGGL(k_moe_plan, dim3(1), dim3(256), 0, st, cnt, n, chunk, cs, start);
+  NVDB_HIP(hipGetLastError());
+}
+
 void moe_blend(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table, const float* yslot, float* values,
                uint64_t* mask, hipStream_t st) {
   hipLaunchKernelGGL(k_moe_blend, dim3(grid_of(items(t, slots))), dim3(256), 0, st, t.leaf_o.p, item_key(t, slots),

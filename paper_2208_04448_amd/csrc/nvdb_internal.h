@@ -205,14 +205,15 @@ struct TrainLaunch {
   TrainNet nets[MAX_LAUNCH_NETS];
   int32_t G;
 };
-enum InferOut : int32_t { OUT_Y = 0, OUT_VALUES = 1, OUT_MASK = 2, OUT_CLASS = 3 };
+enum InferOut : int32_t { OUT_Y = 0, OUT_VALUES = 1, OUT_MASK = 2, OUT_CLASS = 3, OUT_SCATTER = 4 };
 struct InferLaunch {
   NetView net;
   SampleSpec spec;  // spec.idx null, sample j is population index j (or coordinate j)
   TreeView tree;
   int32_t out_kind;
   float out_scale;
-  float* y;           // OUT_Y: [n][C]; OUT_VALUES: [n]
+  float* y;           // OUT_Y: [n][C]; OUT_VALUES: [n]; OUT_SCATTER: y[yidx[j]] = y_j * out_scale
+  const uint32_t* yidx;
   uint64_t* mask;     // OUT_MASK: [n/64]
   uint8_t* cls;       // OUT_CLASS: [n]
   // FP8 form only: e4m3 weight fragments of every hidden layer and 1/s_w per layer
@@ -244,6 +245,20 @@ struct AdamNet {
   float* whead;
   float* bhead;
 };
+// Grouped decode of many networks of one shape (the experts' forward passes).
+struct GroupNet {
+  NetView net;
+  float out_scale;
+};
+struct InferGroupLaunch {
+  const GroupNet* nets;         // [n_nets]
+  int32_t n_nets;
+  const uint32_t* chunk_start;  // [n_nets + 1]: first chunk of each network's samples, then the chunk count
+  const uint32_t* count;        // [n_nets] samples per network
+  const float* x;               // [chunks x chunk][3] normalised coordinates
+  const uint32_t* slot;         // [chunks x chunk] output index of each sample
+  float* yslot;
+};
 constexpr int MAX_ADAM_NETS = 16;
 struct AdamLaunch {
   AdamNet nets[MAX_ADAM_NETS];
@@ -265,6 +280,8 @@ struct KernelSet {
   void (*infer8)(InferLaunch);  // FP8 form of the forward pass
   InferVariant infer_v[MAX_INFER_VARIANTS];  // decode tile shapes, [0] the default
   int n_infer_v, infer_sel;
+  void (*infer_group)(InferGroupLaunch);     // grouped decode, default tile shape
+  int group_waves, group_chunk;              // its waves per work-group and samples per chunk
 };
 // Bytes of the e4m3 weight fragments of all hidden layers (the FP8 form).
 // Elements of the bf16 fragment copies: all layers (forward), layers 1..H-1 (transposed).
@@ -282,6 +299,7 @@ bool find_kernels(int prec, int W, int H, int KP, int C, int act, KernelSet* out
 void launch_quant_fp8(const NetShape& s, const float* theta, char* w8, float* w8inv, hipStream_t st);
 void launch_infer8(const KernelSet& ks, const InferLaunch& I, int grid, hipStream_t st);
 void launch_train(const KernelSet& ks, const TrainLaunch& L, int n_nets, hipStream_t st);
+void launch_infer_group(const KernelSet& ks, const InferGroupLaunch& M, hipStream_t st);
 // work-groups of a decode launch of n samples with the selected tile shape
 int infer_grid(const KernelSet& ks, int64_t n);
 void launch_infer(const KernelSet& ks, const InferLaunch& I, int grid, hipStream_t st);
@@ -342,6 +360,10 @@ void moe_count(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table
                uint32_t* uncovered, hipStream_t st);
 void moe_route(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table, const MoeBox* box, int n_exp,
                const uint32_t* start, uint32_t* cursor, float* bx, uint32_t* bslot, hipStream_t st);
+// chunk layout of the grouped decode from the per-expert counts: cs[k] first
+// chunk of expert k (runs padded to whole chunks of `chunk` samples), cs[n] the
+// chunk count, start[k] = cs[k] * chunk
+void moe_plan(const uint32_t* cnt, int n, int chunk, uint32_t* cs, uint32_t* start, hipStream_t st);
 void moe_blend(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table, const float* yslot, float* values,
                uint64_t* mask, hipStream_t st);
 void error_report(const Tree& t, const float* values, const uint64_t* pred_mask, nvdb_error_report* rep,
