@@ -1552,6 +1552,19 @@ static MoeGrid check_grid(const nvdb_subdomains* g) {
 struct MoeScratch {
   std::mutex mu;
   DevBuf<uint8_t> small, big;
+  // pinned host staging of the small arrays (uploaded with one asynchronous copy)
+  uint8_t* host = nullptr;
+  size_t host_cap = 0;
+  uint8_t* host_buf(size_t n) {
+    if (n > host_cap) {
+      if (host) NVDB_HIP(hipHostFree(host));
+      host = nullptr;
+      host_cap = 0;
+      NVDB_HIP(hipHostMalloc((void**)&host, n, hipHostMallocDefault));
+      host_cap = n;
+    }
+    return host;
+  }
 };
 static MoeScratch& moe_scratch() {
   static std::mutex m;
@@ -1738,11 +1751,18 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
     uint32_t* start = (uint32_t*)(small + o_start);
     uint32_t* cursor = (uint32_t*)(small + o_cur);
     GroupNet* gnets = (GroupNet*)(small + o_nets);
-    std::vector<GroupNet> hnets(E);
+    // the small arrays staged in pinned memory in their device layout, one upload
+    const size_t small_bytes = o_nets + E * sizeof(GroupNet);
+    uint8_t* hs = ws.host_buf(small_bytes + 256);
+    std::memcpy(hs, table.data(), (size_t)total * 4);
+    std::memcpy(hs + o_box, box.data(), E * sizeof(MoeBox));
     for (size_t k = 0; k < E; ++k) {
-      hnets[k].net = net_view(net_of(experts[k], net));
-      hnets[k].out_scale = slots ? 1.f : experts[k]->d.value_scale;
+      GroupNet gn{};
+      gn.net = net_view(net_of(experts[k], net));
+      gn.out_scale = slots ? 1.f : experts[k]->d.value_scale;
+      std::memcpy(hs + o_nets + k * sizeof(GroupNet), &gn, sizeof(GroupNet));
     }
+    uint32_t* uncovered = (uint32_t*)(hs + small_bytes);
     const size_t o_bs = (12 * cap + 255) & ~(size_t)255;
     const size_t o_ys = o_bs + ((4 * cap + 255) & ~(size_t)255);
     ws.big.ensure(o_ys + 32 * (size_t)n);
@@ -1750,9 +1770,7 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
     float* bx = (float*)big;
     uint32_t* bslot = (uint32_t*)(big + o_bs);
     float* yslot = (float*)(big + o_ys);
-    NVDB_HIP(hipMemcpyAsync(tab, table.data(), (size_t)total * 4, hipMemcpyHostToDevice, st));
-    NVDB_HIP(hipMemcpyAsync(dbox, box.data(), E * sizeof(MoeBox), hipMemcpyHostToDevice, st));
-    NVDB_HIP(hipMemcpyAsync(gnets, hnets.data(), E * sizeof(GroupNet), hipMemcpyHostToDevice, st));
+    NVDB_HIP(hipMemcpyAsync(small, hs, small_bytes, hipMemcpyHostToDevice, st));
     NVDB_HIP(hipMemsetAsync(cnt, 0, (E + 1) * 4, st));
     NVDB_HIP(hipMemsetAsync(cursor, 0, E * 4, st));
     moe_count(*tree, slots, g, tab, n_experts, cnt, cnt + n_experts, st);
@@ -1768,10 +1786,9 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
     M.yslot = yslot;
     launch_infer_group(ks0, M, st);
     moe_blend(*tree, slots, g, tab, yslot, slots ? nullptr : values_dev, slots ? mask_dev : nullptr, st);
-    uint32_t uncovered = 0;
-    NVDB_HIP(hipMemcpyAsync(&uncovered, cnt + n_experts, 4, hipMemcpyDeviceToHost, st));
+    NVDB_HIP(hipMemcpyAsync(uncovered, cnt + n_experts, 4, hipMemcpyDeviceToHost, st));
     NVDB_HIP(hipStreamSynchronize(st));
-    NVDB_REQUIRE(uncovered == 0, NVDB_E_INVALID, "voxels that no expert's widened box holds");
+    NVDB_REQUIRE(*uncovered == 0, NVDB_E_INVALID, "voxels that no expert's widened box holds");
     return;
   }
   // small arrays in one allocation: lookup table, boxes, counts (+ the
