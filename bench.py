@@ -518,6 +518,46 @@ def cloud_leg(fit_steps, tuned_g):
                          "decoded_fp": ra["fp"], "decoded_fn": ra["fn"], "decoded_rms_err": ra["rms"],
                          "decoded_max_abs_err": ra["max_abs"], "decoded_voxels_per_s": N / rd_s}
         del back, blob
+    # sparse domain decomposition in the paper's cell range (Sec. 3.4: 512 to 2048):
+    # 512^3 cells with an 8-voxel halo, one BF16 regressor per kept cell fitted as
+    # long as the single regressor, blended decode against the single decode
+    size, halo = 512, 8
+    cells = nvdb.subdomain_cells(tree, (0, 0, 0), size, halo)
+    experts, subs = [], []
+    for c in cells:
+        subs.append(tree.subdomain((0, 0, 0), size, halo, c))
+        lo, D = nvdb.subdomain_box((0, 0, 0), size, halo, c)
+        e = nvdb.Model({0: (W, H, M, C)}, precision=nvdb.BF16, domain_lo=lo, domain_size=D, value_scale=1.0)
+        e.set_encoding(0, workloads.ffm_matrix(M, 10.0, seed=51))
+        e.set_params(0, workloads.init_params(2 * M, W, H, C, seed=53))
+        e.set_train_groups(tuned_g)
+        experts.append(e)
+    pairs = sum(int(s_.info().n_voxels) for s_ in subs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nvdb.fit_experts(experts, subs, steps=fit_steps, batch=BATCH, nets_mask=1, seed=0, lr=1e-3, lr_decay=0.975,
+                     lr_interval=100)
+    torch.cuda.synchronize()
+    moe_fit_s = time.perf_counter() - t0
+    del subs
+    vm = nvdb.decode_moe(experts, cells, (0, 0, 0), size, halo, tree)
+    rm = nvdb.errors(tree, vm)
+    del vm
+    ts = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        vm = nvdb.decode_moe(experts, cells, (0, 0, 0), size, halo, tree)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+        del vm
+    moe_dec_s = sorted(ts)[1]
+    moe = {"subdomain_size": size, "halo": halo, "experts": len(cells), "routed_pairs_per_voxel": pairs / N,
+           "fit_s": moe_fit_s, "train_samples_per_s": len(cells) * fit_steps * BATCH / moe_fit_s,
+           "blend_decode_ms": moe_dec_s * 1e3, "blend_voxels_per_s": N / moe_dec_s,
+           "rms_err": rm["rms"], "max_abs_err": rm["max_abs"],
+           "single_network": {"rms_err": rep["rms"], "max_abs_err": rep["max_abs"], "decode_ms": dec_s * 1e3}}
+    del experts
     return {"workload": "fBm cloud 1024^3 (6 octaves, lacunarity 2, gain 0.5), active where density > 0.55; "
                         "voxel regressor 4x128 + level-1 classifier 4x64 (3 classes), FFM m=64 sigma=10, BF16; "
                         "%d steps x 2^18 samples per network" % fit_steps,
@@ -527,7 +567,7 @@ def cloud_leg(fit_steps, tuned_g):
             "l1_slots_per_s": 4096 * L1 / l1_s, "l1_decode_ms": l1_s * 1e3,
             "rms_err": rep["rms"], "max_abs_err": rep["max_abs"],
             "l1": {"n_slots": r1["n_slots"], "fp": r1["fp"], "fn": r1["fn"], "mismatch": r1["mismatch"]},
-            "topology_decode": topo, "archive": archive,
+            "topology_decode": topo, "archive": archive, "moe_512": moe,
             "fp8": {"decoded_voxels_per_s": N / dec8_s, "decode_ms": dec8_s * 1e3,
                     "decode_tflops": N * flops_fwd(2 * M, W, H, C) / dec8_s / 1e12,
                     "frac_of_fp8_peak": N * flops_fwd(2 * M, W, H, C) / dec8_s / 1e12 / 5000.0,

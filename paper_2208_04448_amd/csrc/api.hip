@@ -1731,18 +1731,18 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
   for (size_t k = 1; k < E && grouped; ++k) grouped = net_of(experts[k], net).ks.infer_group == ks0.infer_group;
   if (grouped) {
     const size_t CH = (size_t)ks0.group_chunk;
-    const size_t cap = 8 * (size_t)n + E * CH;
-    NVDB_REQUIRE(cap < (1ull << 32), NVDB_E_INVALID, "too many routed pairs for the grouped decode");
     const size_t o_box = ((size_t)total * 4 + 255) & ~(size_t)255;
     const size_t o_cnt = o_box + ((E * sizeof(MoeBox) + 255) & ~(size_t)255);
     const size_t o_cs = o_cnt + (((E + 1) * 4 + 255) & ~(size_t)255);
     const size_t o_start = o_cs + (((E + 1) * 4 + 255) & ~(size_t)255);
     const size_t o_cur = o_start + ((E * 4 + 255) & ~(size_t)255);
-    const size_t o_nets = o_cur + ((E * 4 + 255) & ~(size_t)255);
+    const size_t o_flag = o_cur + ((E * 4 + 255) & ~(size_t)255);
+    const size_t o_nets = o_flag + 256;
     MoeScratch& ws = moe_scratch();
     std::lock_guard<std::mutex> lock(ws.mu);
     StreamDrain drain{st};  // declared after the lock: runs before it is released
-    ws.small.ensure(o_nets + E * sizeof(GroupNet));
+    const size_t small_bytes = o_nets + E * sizeof(GroupNet);
+    ws.small.ensure(small_bytes);
     uint8_t* small = ws.small.p;
     int32_t* tab = (int32_t*)small;
     MoeBox* dbox = (MoeBox*)(small + o_box);
@@ -1750,9 +1750,9 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
     uint32_t* cs = (uint32_t*)(small + o_cs);
     uint32_t* start = (uint32_t*)(small + o_start);
     uint32_t* cursor = (uint32_t*)(small + o_cur);
+    uint32_t* flag = (uint32_t*)(small + o_flag);
     GroupNet* gnets = (GroupNet*)(small + o_nets);
     // the small arrays staged in pinned memory in their device layout, one upload
-    const size_t small_bytes = o_nets + E * sizeof(GroupNet);
     uint8_t* hs = ws.host_buf(small_bytes + 256);
     std::memcpy(hs, table.data(), (size_t)total * 4);
     std::memcpy(hs + o_box, box.data(), E * sizeof(MoeBox));
@@ -1762,34 +1762,48 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
       gn.out_scale = slots ? 1.f : experts[k]->d.value_scale;
       std::memcpy(hs + o_nets + k * sizeof(GroupNet), &gn, sizeof(GroupNet));
     }
-    uint32_t* uncovered = (uint32_t*)(hs + small_bytes);
-    const size_t o_bs = (12 * cap + 255) & ~(size_t)255;
-    const size_t o_ys = o_bs + ((4 * cap + 255) & ~(size_t)255);
-    ws.big.ensure(o_ys + 32 * (size_t)n);
-    uint8_t* big = ws.big.p;
-    float* bx = (float*)big;
-    uint32_t* bslot = (uint32_t*)(big + o_bs);
-    float* yslot = (float*)(big + o_ys);
-    NVDB_HIP(hipMemcpyAsync(small, hs, small_bytes, hipMemcpyHostToDevice, st));
-    NVDB_HIP(hipMemsetAsync(cnt, 0, (E + 1) * 4, st));
-    NVDB_HIP(hipMemsetAsync(cursor, 0, E * 4, st));
-    moe_count(*tree, slots, g, tab, n_experts, cnt, cnt + n_experts, st);
-    moe_plan(cnt, n_experts, (int)CH, cs, start, st);
-    moe_route(*tree, slots, g, tab, dbox, n_experts, start, cursor, bx, bslot, st);
-    InferGroupLaunch M{};
-    M.nets = gnets;
-    M.n_nets = n_experts;
-    M.chunk_start = cs;
-    M.count = cnt;
-    M.x = bx;
-    M.slot = bslot;
-    M.yslot = yslot;
-    launch_infer_group(ks0, M, st);
-    moe_blend(*tree, slots, g, tab, yslot, slots ? nullptr : values_dev, slots ? mask_dev : nullptr, st);
-    NVDB_HIP(hipMemcpyAsync(uncovered, cnt + n_experts, 4, hipMemcpyDeviceToHost, st));
-    NVDB_HIP(hipStreamSynchronize(st));
-    NVDB_REQUIRE(*uncovered == 0, NVDB_E_INVALID, "voxels that no expert's widened box holds");
-    return;
+    uint32_t* back = (uint32_t*)(hs + small_bytes);  // uncovered items, overflow flag
+    // pair buffers for two pairs per item (plus each run's padding to whole
+    // chunks); if the routing finds more, the exact size is read back and the
+    // decode runs again
+    size_t cap = 2 * (size_t)n + E * CH;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      NVDB_REQUIRE(cap < (1ull << 32), NVDB_E_INVALID, "too many routed pairs for the grouped decode");
+      const size_t o_bs = (12 * cap + 255) & ~(size_t)255;
+      const size_t o_ys = o_bs + ((4 * cap + 255) & ~(size_t)255);
+      ws.big.ensure(o_ys + 32 * (size_t)n);
+      uint8_t* big = ws.big.p;
+      float* bx = (float*)big;
+      uint32_t* bslot = (uint32_t*)(big + o_bs);
+      float* yslot = (float*)(big + o_ys);
+      NVDB_HIP(hipMemcpyAsync(small, hs, small_bytes, hipMemcpyHostToDevice, st));
+      NVDB_HIP(hipMemsetAsync(cnt, 0, (E + 1) * 4, st));
+      NVDB_HIP(hipMemsetAsync(cursor, 0, E * 4, st));
+      moe_count(*tree, slots, g, tab, n_experts, cnt, cnt + n_experts, st);
+      moe_plan(cnt, n_experts, (int)CH, cap, cs, start, flag, st);
+      moe_route(*tree, slots, g, tab, dbox, n_experts, start, cursor, bx, bslot, cap, st);
+      InferGroupLaunch M{};
+      M.nets = gnets;
+      M.n_nets = n_experts;
+      M.chunk_start = cs;
+      M.count = cnt;
+      M.x = bx;
+      M.slot = bslot;
+      M.yslot = yslot;
+      launch_infer_group(ks0, M, st);
+      moe_blend(*tree, slots, g, tab, yslot, slots ? nullptr : values_dev, slots ? mask_dev : nullptr, st);
+      NVDB_HIP(hipMemcpyAsync(back, cnt + n_experts, 4, hipMemcpyDeviceToHost, st));
+      NVDB_HIP(hipMemcpyAsync(back + 1, flag, 4, hipMemcpyDeviceToHost, st));
+      NVDB_HIP(hipStreamSynchronize(st));
+      NVDB_REQUIRE(back[0] == 0, NVDB_E_INVALID, "voxels that no expert's widened box holds");
+      if (back[1] == 0) return;
+      std::vector<uint32_t> hc(E);
+      NVDB_HIP(hipMemcpy(hc.data(), cnt, E * 4, hipMemcpyDeviceToHost));
+      size_t need = 0;
+      for (size_t k = 0; k < E; ++k) need += (hc[k] + CH - 1) / CH * CH;
+      cap = need;
+    }
+    NVDB_REQUIRE(false, NVDB_E_DEVICE, "the routed pair count changed between two passes");
   }
   // small arrays in one allocation: lookup table, boxes, counts (+ the
   // uncovered voxels), bucket starts, cursors
@@ -1833,7 +1847,7 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
   uint32_t* bslot = (uint32_t*)(big + o_bs);
   float* yslot = (float*)(big + o_ys);
   NVDB_HIP(hipMemcpyAsync(start, hs.data(), E * 4, hipMemcpyHostToDevice, st));
-  moe_route(*tree, slots, g, tab, dbox, n_experts, start, cursor, bx, bslot, st);
+  moe_route(*tree, slots, g, tab, dbox, n_experts, start, cursor, bx, bslot, pairs, st);
   for (size_t k = 0; k < E; ++k) {
     if (hc[k] == 0) continue;
     const Net& N = net_of(experts[k], net);

@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(256) k_moe_route(const int4* __restrict__ leaf
                                                    int64_t n, MoeGrid g, const int32_t* __restrict__ table,
                                                    const MoeBox* __restrict__ box, int n_exp,
                                                    const uint32_t* __restrict__ start, uint32_t* __restrict__ cursor,
-                                                   float* __restrict__ bx, uint32_t* __restrict__ bslot) {
+                                                   float* __restrict__ bx, uint32_t* __restrict__ bslot, uint64_t cap) {
   extern __shared__ uint32_t lds[];  // 3 n_exp words, sized at launch
   uint32_t* hist = lds;
   uint32_t* base = lds + n_exp;
@@ -280,6 +280,7 @@ __global__ void __launch_bounds__(256) k_moe_route(const int4* __restrict__ leaf
       const uint32_t pos = wave_hist_add(fill, k);
       if (k < 0) continue;
       const uint32_t s = base[k] + pos;
+      if (s >= cap) continue;  // the pair buffers were too small: the caller retries
       const MoeBox b = box[k];
       bx[3 * (size_t)s] = ((float)(p.x - b.lo[0]) + 0.5f) * b.inv_d;
       bx[3 * (size_t)s + 1] = ((float)(p.y - b.lo[1]) + 0.5f) * b.inv_d;
@@ -368,17 +369,20 @@ void moe_count(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table
 }
 
 void moe_route(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table, const MoeBox* box, int n_exp,
-               const uint32_t* start, uint32_t* cursor, float* bx, uint32_t* bslot, hipStream_t st) {
+               const uint32_t* start, uint32_t* cursor, float* bx, uint32_t* bslot, uint64_t cap, hipStream_t st) {
   hipLaunchKernelGGL(k_moe_route, dim3(route_grid(items(t, slots))), dim3(256), (size_t)n_exp * 12, st, t.leaf_o.p,
                      item_key(t, slots),
-                     items(t, slots), g, table, box, n_exp, start, cursor, bx, bslot);
+                     items(t, slots), g, table, box, n_exp, start, cursor, bx, bslot, cap);
   NVDB_HIP(hipGetLastError());
 }
 
 namespace {
 // One work-group of 256 threads; n <= 4096 experts, each thread a contiguous run.
-__global__ void __launch_bounds__(256) k_moe_plan(const uint32_t* __restrict__ cnt, int n, int chunk,
-                                                  uint32_t* __restrict__ cs, uint32_t* __restrict__ start) {
+// When the padded pairs exceed cap, flag[0] is set and the chunk count is 0 (the
+// grouped decode then does nothing and the caller retries with larger buffers).
+__global__ void __launch_bounds__(256) k_moe_plan(const uint32_t* __restrict__ cnt, int n, int chunk, uint64_t cap,
+                                                  uint32_t* __restrict__ cs, uint32_t* __restrict__ start,
+                                                  uint32_t* __restrict__ flag) {
   __shared__ uint32_t part[256];
   const int per = (n + 255) / 256, k0 = threadIdx.x * per, k1 = min(n, k0 + per);
   uint32_t sum = 0;
@@ -392,7 +396,9 @@ __global__ void __launch_bounds__(256) k_moe_plan(const uint32_t* __restrict__ c
       part[i] = run;
       run += v;
     }
-    cs[n] = run;
+    const bool over = (uint64_t)run * (uint64_t)chunk > cap;
+    cs[n] = over ? 0u : run;
+    flag[0] = over ? 1u : 0u;
   }
   __syncthreads();
   uint32_t run = part[threadIdx.x];
@@ -404,8 +410,9 @@ __global__ void __launch_bounds__(256) k_moe_plan(const uint32_t* __restrict__ c
 }
 }  // namespace
 
-void moe_plan(const uint32_t* cnt, int n, int chunk, uint32_t* cs, uint32_t* start, hipStream_t st) {
-  hipLaunchKernelGGL(k_moe_plan, dim3(1), dim3(256), 0, st, cnt, n, chunk, cs, start);
+void moe_plan(const uint32_t* cnt, int n, int chunk, uint64_t cap, uint32_t* cs, uint32_t* start, uint32_t* flag,
+              hipStream_t st) {
+  hipLaunchKernelGGL(k_moe_plan, dim3(1), dim3(256), 0, st, cnt, n, chunk, cap, cs, start, flag);
   NVDB_HIP(hipGetLastError());
 }
 

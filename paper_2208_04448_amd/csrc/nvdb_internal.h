@@ -359,11 +359,12 @@ int64_t moe_extract(const Tree& t, const int32_t lo[3], int32_t D, int32_t* ijk,
 void moe_count(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table, int n_exp, uint32_t* cnt,
                uint32_t* uncovered, hipStream_t st);
 void moe_route(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table, const MoeBox* box, int n_exp,
-               const uint32_t* start, uint32_t* cursor, float* bx, uint32_t* bslot, hipStream_t st);
+               const uint32_t* start, uint32_t* cursor, float* bx, uint32_t* bslot, uint64_t cap, hipStream_t st);
 // chunk layout of the grouped decode from the per-expert counts: cs[k] first
 // chunk of expert k (runs padded to whole chunks of `chunk` samples), cs[n] the
-// chunk count, start[k] = cs[k] * chunk
-void moe_plan(const uint32_t* cnt, int n, int chunk, uint32_t* cs, uint32_t* start, hipStream_t st);
+// chunk count, start[k] = cs[k] * chunk; pairs beyond cap set flag[0] (and cs[n] = 0)
+void moe_plan(const uint32_t* cnt, int n, int chunk, uint64_t cap, uint32_t* cs, uint32_t* start, uint32_t* flag,
+              hipStream_t st);
 void moe_blend(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table, const float* yslot, float* values,
                uint64_t* mask, hipStream_t st);
 void error_report(const Tree& t, const float* values, const uint64_t* pred_mask, nvdb_error_report* rep,

@@ -111,6 +111,24 @@ def test_decode_moe_offset_grid_and_ragged_counts(gpu_lib, scene):
     assert np.all(np.abs(got - want) <= 3e-5 * (1 + np.abs(want)))
 
 
+def test_decode_moe_many_pairs_per_voxel(gpu_lib, scene):
+    """Cells of edge 16 with an 8-voxel halo: every voxel lies in the overlap of
+    several widened boxes (more than two pairs per voxel on average), so the
+    grouped decode's first pair buffers overflow, the routing writes nothing past
+    them, and the decode runs again with buffers of the exact size; the result
+    matches the oracle's blend.  A second call reuses the grown buffers."""
+    tr, ot = scene
+    origin, size, halo = (0, 0, 0), 16, 8
+    cells = gpu_lib.subdomain_cells(tr, origin, size, halo)
+    models, ex = _experts(gpu_lib, cells, origin, size, halo, (64, 3, 18), gpu_lib.FP32)
+    n_exp = sum(moe.gate(ot["ijk"], c, origin, size, halo) > 0 for c in cells)
+    assert n_exp.mean() > 2.5
+    want = moe.decode_moe(ot["ijk"], ex, origin, size, halo)
+    for _ in range(2):
+        got = gpu_lib.decode_moe(models, cells, origin, size, halo, tr).cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(got - want) <= 3e-5 * (1 + np.abs(want)))
+
+
 def test_decode_moe_single_expert_equals_decode(gpu_lib):
     """One cell whose gate is 1 on every voxel: the blend returns the expert's
     own decode exactly."""
