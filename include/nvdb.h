@@ -443,9 +443,11 @@ nvdb_status nvdb_tree_subdomain(const nvdb_tree* tree, const nvdb_subdomains* gr
  * clamped tent: the product over the axes of min(t, size + 2 halo - t,
  * 2 halo) / (2 halo), t the distance of the voxel centre from the lower face of
  * the widened box.  Each expert computes in its own precision.  values_dev is
- * float32[N] in the tree's voxel order (as nvdb_decode).  Scratch (16 B per
- * routed pair plus 32 B per voxel, grown to the largest call) stays allocated on
- * each device until the process ends; calls on one device take turns on it.
+ * float32[N] in the tree's voxel order (as nvdb_decode).  Experts of one network
+ * shape run in one grouped launch.  Scratch (16 B per routed pair, sized for two
+ * pairs per voxel and grown to the exact count when a call routes more, plus 32 B
+ * per voxel, grown to the largest call) stays allocated on each device until the
+ * process ends; calls on one device take turns on it.
  * Synchronises `stream`.  Errors: E_INVALID (null arguments, n_experts outside [1, 4096],
  * two experts for one cell, experts spanning more than 2^24 cells, a tree of
  * 2^29 voxels or more, or a voxel that no expert's widened box holds: then
@@ -464,6 +466,22 @@ nvdb_status nvdb_decode_moe(const nvdb_model* const* experts, const int32_t* cel
 nvdb_status nvdb_decode_moe_mask(const nvdb_model* const* experts, const int32_t* cells, int32_t n_experts,
                                  const nvdb_subdomains* grid, const nvdb_tree* tree, uint64_t* mask_dev,
                                  void* stream);
+
+/* The same blend for the level-1 classes (the decomposition applies to every
+ * network of the hierarchy, Sec. 3.4): expert k's level-1 classifier runs at every
+ * leaf slot of the tree's level-1 nodes that its widened box holds, at
+ * x = (o - domain_lo + 4) / domain_size for the slot at origin o; the three
+ * logits are blended with the gates taken at the slot's centre o + 4, and the
+ * slot's class is the argmax of the blended logits (ties to the lowest class).
+ * classes_dev is uint8[n_l1][4096] (as nvdb_decode_l1).  The cell size, the halo
+ * and the grid origin must be multiples of 8 (a slot then lies wholly inside or
+ * outside every widened box), and the experts must share one network shape.
+ * Synchronisation, scratch (96 B per leaf slot in place of 32 B per voxel) and
+ * errors as nvdb_decode_moe_mask, E_UNSUPPORTED for experts of different shapes
+ * and E_STATE for an unset level-1 classifier. */
+nvdb_status nvdb_decode_moe_l1(const nvdb_model* const* experts, const int32_t* cells, int32_t n_experts,
+                               const nvdb_subdomains* grid, const nvdb_tree* tree, uint8_t* classes_dev,
+                               void* stream);
 
 /* Level-1 classifier report (Sec. 3.3.1, Sec. 4) over the 4096 leaf slots of
  * every level-1 node: classes_dev is uint8[n_l1][4096] as written by

@@ -78,6 +78,41 @@ def gate(ijk, cell, origin, S, h):
     return np.prod(g, axis=1) * in_widened_box(p, cell, origin, S, h)
 
 
+def gate_leaf_slot(o, cell, origin, S, h):
+    """Clamped tent G_k at the centres o + 4 of the leaf slots at origins o (zero
+    where the slot's 8^3 block is not wholly inside the widened box)."""
+    o = np.asarray(o, np.int64).reshape(-1, 3)
+    lo, D = widened_box(cell, origin, S, h)
+    t = o.astype(np.float64) + 4.0 - lo.astype(np.float64)
+    g = np.minimum(np.minimum(t, D - t), 2.0 * h) / (2.0 * h)
+    g = np.clip(g, 0.0, None)
+    inside = np.all((o >= lo) & (o + 8 <= lo + D), axis=1)
+    return np.prod(g, axis=1) * inside
+
+
+def decode_moe_l1(slot_origins, experts, origin, S, h):
+    """Blended level-1 classes at leaf slots (origins o): the experts' three logits
+    at x = (o - lo + 4) / D averaged with the gates at the slot centres, then the
+    argmax (ties to the lowest class).  Returns (classes, blended logits)."""
+    check_geometry(S, h)
+    o = np.asarray(slot_origins, np.int64).reshape(-1, 3)
+    num = np.zeros((len(o), 3))
+    den = np.zeros(len(o))
+    for e in experts:
+        g = gate_leaf_slot(o, e["cell"], origin, S, h)
+        sel = g > 0
+        if not sel.any():
+            continue
+        x = mlp.normalize_leaf_slot(o[sel], e["lo"], e["D"])
+        y = mlp.predict(mlp.unflatten(e["theta"], e["shapes"]), x, e["B"])
+        num[sel] += g[sel][:, None] * y
+        den[sel] += g[sel]
+    logits = np.full((len(o), 3), np.nan)
+    ok = den > 0
+    logits[ok] = num[ok] / den[ok][:, None]
+    return np.argmax(np.where(np.isnan(logits), -np.inf, logits), axis=1), logits
+
+
 def subdomain_voxels(ijk, values, cell, origin, S, h):
     """Voxels (coordinates, values) of the widened box of `cell`: the training
     set of its expert."""

@@ -1678,21 +1678,28 @@ nvdb_status nvdb_tree_subdomain(const nvdb_tree* tree, const nvdb_subdomains* gr
 
 }  // extern "C"
 
-// Blended decode over the active voxels (regressors, values) or over every voxel
-// slot of the leaves (level-0 classifiers, mask bits).
+// Blended decode over the active voxels (regressors, values), over every voxel
+// slot of the leaves (level-0 classifiers, mask bits) or over every leaf slot of
+// the level-1 nodes (level-1 classifiers, classes).
 static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cells, int32_t n_experts,
                             const nvdb_subdomains* grid, const nvdb_tree* tree, int net, float* values_dev,
-                            uint64_t* mask_dev, hipStream_t st) {
+                            uint64_t* mask_dev, uint8_t* cls_dev, hipStream_t st) {
   NVDB_REQUIRE(experts && cells && tree, NVDB_E_INVALID, "null argument");
   NVDB_REQUIRE(n_experts >= 1 && n_experts <= MOE_MAX_EXPERTS, NVDB_E_INVALID, "expert count outside [1, 4096]");
   const bool slots = net == NVDB_NET_L0;
-  const int64_t n = slots ? 512 * tree->n_leaf : tree->n_vox;
+  const int kind = net == NVDB_NET_REGRESSOR ? MOE_VOXELS : (net == NVDB_NET_L0 ? MOE_VOXEL_SLOTS : MOE_LEAF_SLOTS);
+  const int64_t n = kind == MOE_VOXELS ? tree->n_vox : (kind == MOE_VOXEL_SLOTS ? 512 * tree->n_leaf : 4096 * tree->n_l1);
+  const int C = kind == MOE_LEAF_SLOTS ? 3 : 1;
   NVDB_REQUIRE(n < (1ll << 29), NVDB_E_INVALID, "the blended decode takes fewer than 2^29 voxels or slots");
-  NVDB_REQUIRE(n == 0 || (slots ? mask_dev != nullptr : values_dev != nullptr), NVDB_E_INVALID, "null output");
+  NVDB_REQUIRE(n == 0 || (kind == MOE_VOXELS ? values_dev != nullptr
+                                             : (kind == MOE_VOXEL_SLOTS ? mask_dev != nullptr : cls_dev != nullptr)),
+               NVDB_E_INVALID, "null output");
   MoeGrid g = check_grid(grid);
-  if (slots)
+  if (kind != MOE_VOXELS)
     NVDB_REQUIRE(g.S % 8 == 0 && g.o[0] % 8 == 0 && g.o[1] % 8 == 0 && g.o[2] % 8 == 0, NVDB_E_INVALID,
-                 "the mask decode needs a cell size and grid origin that are multiples of 8");
+                 "the slot decodes need a cell size and grid origin that are multiples of 8");
+  if (kind == MOE_LEAF_SLOTS)
+    NVDB_REQUIRE(g.h % 8 == 0, NVDB_E_INVALID, "the level-1 decode needs a halo that is a multiple of 8");
   std::vector<MoeBox> box((size_t)n_experts);
   for (int k = 0; k < n_experts; ++k) {
     NVDB_REQUIRE(experts[k] != nullptr, NVDB_E_INVALID, "null expert");
@@ -1759,7 +1766,7 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
     for (size_t k = 0; k < E; ++k) {
       GroupNet gn{};
       gn.net = net_view(net_of(experts[k], net));
-      gn.out_scale = slots ? 1.f : experts[k]->d.value_scale;
+      gn.out_scale = kind == MOE_VOXELS ? experts[k]->d.value_scale : 1.f;
       std::memcpy(hs + o_nets + k * sizeof(GroupNet), &gn, sizeof(GroupNet));
     }
     uint32_t* back = (uint32_t*)(hs + small_bytes);  // uncovered items, overflow flag
@@ -1767,11 +1774,12 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
     // chunks); if the routing finds more, the exact size is read back and the
     // decode runs again
     size_t cap = 2 * (size_t)n + E * CH;
+    NVDB_REQUIRE(net_of(experts[0], net).s.C == C, NVDB_E_INVALID, "expert output count");
     for (int attempt = 0; attempt < 2; ++attempt) {
       NVDB_REQUIRE(cap < (1ull << 32), NVDB_E_INVALID, "too many routed pairs for the grouped decode");
       const size_t o_bs = (12 * cap + 255) & ~(size_t)255;
       const size_t o_ys = o_bs + ((4 * cap + 255) & ~(size_t)255);
-      ws.big.ensure(o_ys + 32 * (size_t)n);
+      ws.big.ensure(o_ys + 32 * (size_t)C * (size_t)n);
       uint8_t* big = ws.big.p;
       float* bx = (float*)big;
       uint32_t* bslot = (uint32_t*)(big + o_bs);
@@ -1779,9 +1787,9 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
       NVDB_HIP(hipMemcpyAsync(small, hs, small_bytes, hipMemcpyHostToDevice, st));
       NVDB_HIP(hipMemsetAsync(cnt, 0, (E + 1) * 4, st));
       NVDB_HIP(hipMemsetAsync(cursor, 0, E * 4, st));
-      moe_count(*tree, slots, g, tab, n_experts, cnt, cnt + n_experts, st);
+      moe_count(*tree, kind, g, tab, n_experts, cnt, cnt + n_experts, st);
       moe_plan(cnt, n_experts, (int)CH, cap, cs, start, flag, st);
-      moe_route(*tree, slots, g, tab, dbox, n_experts, start, cursor, bx, bslot, cap, st);
+      moe_route(*tree, kind, g, tab, dbox, n_experts, start, cursor, bx, bslot, cap, st);
       InferGroupLaunch M{};
       M.nets = gnets;
       M.n_nets = n_experts;
@@ -1791,7 +1799,8 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
       M.slot = bslot;
       M.yslot = yslot;
       launch_infer_group(ks0, M, st);
-      moe_blend(*tree, slots, g, tab, yslot, slots ? nullptr : values_dev, slots ? mask_dev : nullptr, st);
+      moe_blend(*tree, kind, g, tab, yslot, kind == MOE_VOXELS ? values_dev : nullptr,
+                kind == MOE_VOXEL_SLOTS ? mask_dev : nullptr, kind == MOE_LEAF_SLOTS ? cls_dev : nullptr, st);
       NVDB_HIP(hipMemcpyAsync(back, cnt + n_experts, 4, hipMemcpyDeviceToHost, st));
       NVDB_HIP(hipMemcpyAsync(back + 1, flag, 4, hipMemcpyDeviceToHost, st));
       NVDB_HIP(hipStreamSynchronize(st));
@@ -1805,6 +1814,8 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
     }
     NVDB_REQUIRE(false, NVDB_E_DEVICE, "the routed pair count changed between two passes");
   }
+  NVDB_REQUIRE(kind != MOE_LEAF_SLOTS, NVDB_E_UNSUPPORTED,
+               "the blended level-1 decode needs experts of one network shape");
   // small arrays in one allocation: lookup table, boxes, counts (+ the
   // uncovered voxels), bucket starts, cursors
   const size_t o_box = ((size_t)total * 4 + 255) & ~(size_t)255;
@@ -1825,7 +1836,7 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
   NVDB_HIP(hipMemcpyAsync(dbox, box.data(), E * sizeof(MoeBox), hipMemcpyHostToDevice, st));
   NVDB_HIP(hipMemsetAsync(cnt, 0, (E + 1) * 4, st));
   NVDB_HIP(hipMemsetAsync(cursor, 0, E * 4, st));
-  moe_count(*tree, slots, g, tab, n_experts, cnt, cnt + n_experts, st);
+  moe_count(*tree, kind, g, tab, n_experts, cnt, cnt + n_experts, st);
   std::vector<uint32_t> hc(E + 1);
   NVDB_HIP(hipMemcpyAsync(hc.data(), cnt, hc.size() * 4, hipMemcpyDeviceToHost, st));
   NVDB_HIP(hipStreamSynchronize(st));
@@ -1847,7 +1858,7 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
   uint32_t* bslot = (uint32_t*)(big + o_bs);
   float* yslot = (float*)(big + o_ys);
   NVDB_HIP(hipMemcpyAsync(start, hs.data(), E * 4, hipMemcpyHostToDevice, st));
-  moe_route(*tree, slots, g, tab, dbox, n_experts, start, cursor, bx, bslot, pairs, st);
+  moe_route(*tree, kind, g, tab, dbox, n_experts, start, cursor, bx, bslot, pairs, st);
   for (size_t k = 0; k < E; ++k) {
     if (hc[k] == 0) continue;
     const Net& N = net_of(experts[k], net);
@@ -1863,7 +1874,7 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
     launch_infer(N.ks, I, infer_grid(N.ks, hc[k]), st);
     query_scatter(y + hs[k], bslot + hs[k], hc[k], cnt + k, slots ? 1.f : experts[k]->d.value_scale, yslot, st);
   }
-  moe_blend(*tree, slots, g, tab, yslot, slots ? nullptr : values_dev, slots ? mask_dev : nullptr, st);
+  moe_blend(*tree, kind, g, tab, yslot, slots ? nullptr : values_dev, slots ? mask_dev : nullptr, nullptr, st);
   NVDB_HIP(hipStreamSynchronize(st));
 }
 
@@ -1872,7 +1883,7 @@ extern "C" {
 nvdb_status nvdb_decode_moe(const nvdb_model* const* experts, const int32_t* cells, int32_t n_experts,
                             const nvdb_subdomains* grid, const nvdb_tree* tree, float* values_dev, void* stream) {
   return guarded([&] {
-    decode_moe_impl(experts, cells, n_experts, grid, tree, NVDB_NET_REGRESSOR, values_dev, nullptr,
+    decode_moe_impl(experts, cells, n_experts, grid, tree, NVDB_NET_REGRESSOR, values_dev, nullptr, nullptr,
                     (hipStream_t)stream);
   });
 }
@@ -1881,7 +1892,17 @@ nvdb_status nvdb_decode_moe_mask(const nvdb_model* const* experts, const int32_t
                                  const nvdb_subdomains* grid, const nvdb_tree* tree, uint64_t* mask_dev,
                                  void* stream) {
   return guarded([&] {
-    decode_moe_impl(experts, cells, n_experts, grid, tree, NVDB_NET_L0, nullptr, mask_dev, (hipStream_t)stream);
+    decode_moe_impl(experts, cells, n_experts, grid, tree, NVDB_NET_L0, nullptr, mask_dev, nullptr,
+                    (hipStream_t)stream);
+  });
+}
+
+nvdb_status nvdb_decode_moe_l1(const nvdb_model* const* experts, const int32_t* cells, int32_t n_experts,
+                               const nvdb_subdomains* grid, const nvdb_tree* tree, uint8_t* classes_dev,
+                               void* stream) {
+  return guarded([&] {
+    decode_moe_impl(experts, cells, n_experts, grid, tree, NVDB_NET_L1, nullptr, nullptr, classes_dev,
+                    (hipStream_t)stream);
   });
 }
 

@@ -713,7 +713,8 @@ struct InferWG {
           if (I.out_kind == OUT_VALUES) {
             I.y[j] = y[u][0] * I.out_scale;
           } else if (I.out_kind == OUT_SCATTER) {
-            I.y[I.yidx[j]] = y[u][0] * I.out_scale;
+#pragma unroll
+            for (int c = 0; c < C; ++c) I.y[(size_t)I.yidx[j] * C + c] = y[u][c] * I.out_scale;
           } else if (I.out_kind == OUT_CLASS) {
             int best = 0;
             float bv = y[u][0];

@@ -24,6 +24,13 @@ namespace nvdb {
 
 namespace {
 
+// Where the items of a blended decode come from.
+struct ItemSrc {
+  const int4* org;      // leaf origins, or level-1 origins (leaf-slot items)
+  const uint32_t* key;  // voxel keys (voxel items), or null
+  int l1;               // 1: leaf slots of the level-1 nodes
+};
+
 // Floor division in 64 bits: p - o can leave the int32 range for far grid origins.
 __device__ __forceinline__ int64_t floor_div(int64_t a, int64_t s) { return a >= 0 ? a / s : -((-a + s - 1) / s); }
 
@@ -46,10 +53,11 @@ __device__ __forceinline__ AxisCells axis_cells(int p, int o, int S, int h) {
   return a;
 }
 
-// Tent of cell c along one axis at the centre of voxel p (p in the widened box):
-// twice the distance to the lower face is a = 2 (p - (o + cS - h)) + 1.
-__device__ __forceinline__ float tent(int p, int c, int o, int S, int h) {
-  const int64_t a = 2 * ((int64_t)p - ((int64_t)o + (int64_t)c * S - h)) + 1;
+// Tent of cell c along one axis at the centre of the item at p (p in the widened
+// box): twice the distance to the lower face is a = 2 (p - (o + cS - h)) + half2,
+// half2 = 1 for a voxel (centre p + 1/2), 8 for a leaf slot (centre p + 4).
+__device__ __forceinline__ float tent(int p, int c, int o, int S, int h, int half2) {
+  const int64_t a = 2 * ((int64_t)p - ((int64_t)o + (int64_t)c * S - h)) + half2;
   const int m = (int)min(min(a, (int64_t)2 * (S + 2 * h) - a), (int64_t)4 * h);
   return (float)m / (float)(4 * h);
 }
@@ -64,7 +72,8 @@ __device__ __forceinline__ int expert_at(const MoeGrid& g, const int32_t* __rest
 // Calls f(slot j, expert k, gate) for every expert whose widened box holds p,
 // in the fixed order j = (ix << 2) | (iy << 1) | iz.
 template <class F>
-__device__ __forceinline__ void for_each_expert(const MoeGrid& g, const int32_t* __restrict__ table, int3 p, F&& f) {
+__device__ __forceinline__ void for_each_expert(const MoeGrid& g, const int32_t* __restrict__ table, int3 p, int half2,
+                                                F&& f) {
   const AxisCells ax = axis_cells(p.x, g.o[0], g.S, g.h);
   const AxisCells ay = axis_cells(p.y, g.o[1], g.S, g.h);
   const AxisCells az = axis_cells(p.z, g.o[2], g.S, g.h);
@@ -74,8 +83,8 @@ __device__ __forceinline__ void for_each_expert(const MoeGrid& g, const int32_t*
         const int cx = ax.base + ix, cy = ay.base + iy, cz = az.base + iz;
         const int k = expert_at(g, table, cx, cy, cz);
         if (k < 0) continue;
-        const float w = tent(p.x, cx, g.o[0], g.S, g.h) * tent(p.y, cy, g.o[1], g.S, g.h) *
-                        tent(p.z, cz, g.o[2], g.S, g.h);
+        const float w = tent(p.x, cx, g.o[0], g.S, g.h, half2) * tent(p.y, cy, g.o[1], g.S, g.h, half2) *
+                        tent(p.z, cz, g.o[2], g.S, g.h, half2);
         f((ix << 2) | (iy << 1) | iz, k, w);
       }
 }
@@ -187,20 +196,25 @@ __global__ void __launch_bounds__(256) k_moe_extract(const int4* __restrict__ le
   }
 }
 
-// Item i is voxel i (key[i] = leaf << 9 | n0) or, with key null, voxel slot i
-// of the leaves (i = leaf << 9 | n0 itself).
-__device__ __forceinline__ int3 item_of(const int4* __restrict__ leaf_o, const uint32_t* __restrict__ key, int64_t i) {
-  return voxel_of(leaf_o, key ? key[i] : (uint32_t)i);
+// Item i is voxel i (key[i] = leaf << 9 | n0), or, with key null, voxel slot i of
+// the leaves (i = leaf << 9 | n0 itself), or (l1) leaf slot i & 4095 of level-1
+// node i >> 12, positioned at the slot's origin.
+__device__ __forceinline__ int3 item_of(const ItemSrc& s, int64_t i) {
+  if (s.l1) {
+    const int4 o = s.org[i >> 12];
+    const int n1 = (int)(i & 4095);
+    return make_int3(o.x + 8 * (n1 >> 8), o.y + 8 * ((n1 >> 4) & 15), o.z + 8 * (n1 & 15));
+  }
+  return voxel_of(s.org, s.key ? s.key[i] : (uint32_t)i);
 }
 
 // Candidate cells of item i (none past n).
-__device__ __forceinline__ void voxel_cells(const int4* __restrict__ leaf_o, const uint32_t* __restrict__ key,
-                                            int64_t i, int64_t n, const MoeGrid& g, int3& p, AxisCells& ax,
-                                            AxisCells& ay, AxisCells& az) {
+__device__ __forceinline__ void voxel_cells(const ItemSrc& src, int64_t i, int64_t n, const MoeGrid& g, int3& p,
+                                            AxisCells& ax, AxisCells& ay, AxisCells& az) {
   p = make_int3(0, 0, 0);
   ax = ay = az = AxisCells{0, 0};
   if (i < n) {
-    p = item_of(leaf_o, key, i);
+    p = item_of(src, i);
     ax = axis_cells(p.x, g.o[0], g.S, g.h);
     ay = axis_cells(p.y, g.o[1], g.S, g.h);
     az = axis_cells(p.z, g.o[2], g.S, g.h);
@@ -211,8 +225,7 @@ __device__ __forceinline__ void voxel_cells(const int4* __restrict__ leaf_o, con
 // covers.  Each block walks several 256-voxel tiles (block-uniform trip count)
 // into an LDS histogram (wave-aggregated adds), then adds it to the global
 // counts with one atomic per (block, expert).
-__global__ void __launch_bounds__(256) k_moe_count(const int4* __restrict__ leaf_o, const uint32_t* __restrict__ key,
-                                                   int64_t n, MoeGrid g, const int32_t* __restrict__ table,
+__global__ void __launch_bounds__(256) k_moe_count(ItemSrc src, int64_t n, MoeGrid g, const int32_t* __restrict__ table,
                                                    int n_exp, uint32_t* __restrict__ cnt,
                                                    uint32_t* __restrict__ uncovered) {
   extern __shared__ uint32_t lds[];  // n_exp counters, sized at launch
@@ -225,7 +238,7 @@ __global__ void __launch_bounds__(256) k_moe_count(const int4* __restrict__ leaf
     const int64_t i = t0 + threadIdx.x;
     int3 p;
     AxisCells ax, ay, az;
-    voxel_cells(leaf_o, key, i, n, g, p, ax, ay, az);
+    voxel_cells(src, i, n, g, p, ax, ay, az);
     bool covered = false;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -247,8 +260,7 @@ __global__ void __launch_bounds__(256) k_moe_count(const int4* __restrict__ leaf
 // expert, reserves one range per expert after `start[k]` with one atomic, then
 // walks its tiles again and fills the ranges (positions from fresh LDS
 // counters: any order within a range will do).
-__global__ void __launch_bounds__(256) k_moe_route(const int4* __restrict__ leaf_o, const uint32_t* __restrict__ key,
-                                                   int64_t n, MoeGrid g, const int32_t* __restrict__ table,
+__global__ void __launch_bounds__(256) k_moe_route(ItemSrc src, int64_t n, MoeGrid g, const int32_t* __restrict__ table,
                                                    const MoeBox* __restrict__ box, int n_exp,
                                                    const uint32_t* __restrict__ start, uint32_t* __restrict__ cursor,
                                                    float* __restrict__ bx, uint32_t* __restrict__ bslot, uint64_t cap) {
@@ -262,7 +274,7 @@ __global__ void __launch_bounds__(256) k_moe_route(const int4* __restrict__ leaf
   for (int64_t t0 = (int64_t)blockIdx.x * 256; t0 < n; t0 += stride) {
     int3 p;
     AxisCells ax, ay, az;
-    voxel_cells(leaf_o, key, t0 + threadIdx.x, n, g, p, ax, ay, az);
+    voxel_cells(src, t0 + threadIdx.x, n, g, p, ax, ay, az);
 #pragma unroll
     for (int j = 0; j < 8; ++j) (void)wave_hist_add(hist, slot_expert(g, table, ax, ay, az, j));
   }
@@ -273,7 +285,8 @@ __global__ void __launch_bounds__(256) k_moe_route(const int4* __restrict__ leaf
     const int64_t i = t0 + threadIdx.x;
     int3 p;
     AxisCells ax, ay, az;
-    voxel_cells(leaf_o, key, i, n, g, p, ax, ay, az);
+    voxel_cells(src, i, n, g, p, ax, ay, az);
+    const float half = src.l1 ? 4.f : 0.5f;  // the item's centre
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int k = slot_expert(g, table, ax, ay, az, j);
@@ -282,9 +295,9 @@ __global__ void __launch_bounds__(256) k_moe_route(const int4* __restrict__ leaf
       const uint32_t s = base[k] + pos;
       if (s >= cap) continue;  // the pair buffers were too small: the caller retries
       const MoeBox b = box[k];
-      bx[3 * (size_t)s] = ((float)(p.x - b.lo[0]) + 0.5f) * b.inv_d;
-      bx[3 * (size_t)s + 1] = ((float)(p.y - b.lo[1]) + 0.5f) * b.inv_d;
-      bx[3 * (size_t)s + 2] = ((float)(p.z - b.lo[2]) + 0.5f) * b.inv_d;
+      bx[3 * (size_t)s] = ((float)(p.x - b.lo[0]) + half) * b.inv_d;
+      bx[3 * (size_t)s + 1] = ((float)(p.y - b.lo[1]) + half) * b.inv_d;
+      bx[3 * (size_t)s + 2] = ((float)(p.z - b.lo[2]) + half) * b.inv_d;
       bslot[s] = (uint32_t)(8 * i + j);
     }
   }
@@ -292,17 +305,33 @@ __global__ void __launch_bounds__(256) k_moe_route(const int4* __restrict__ leaf
 
 // Gate-weighted average of the expert outputs held in the item's 8 slots: a
 // value per voxel, or (mask non-null) the bit "blended logit > 0" per voxel slot,
-// packed 64 to a word by the wave that computed them.
-__global__ void __launch_bounds__(256) k_moe_blend(const int4* __restrict__ leaf_o, const uint32_t* __restrict__ key,
-                                                   int64_t n, MoeGrid g, const int32_t* __restrict__ table,
+// packed 64 to a word by the wave that computed them, or (cls non-null, leaf-slot
+// items) the class of the three blended logits (argmax, ties to the lowest).
+__global__ void __launch_bounds__(256) k_moe_blend(ItemSrc src, int64_t n, MoeGrid g,
+                                                   const int32_t* __restrict__ table,
                                                    const float* __restrict__ yslot, float* __restrict__ values,
-                                                   uint64_t* __restrict__ mask) {
+                                                   uint64_t* __restrict__ mask, uint8_t* __restrict__ cls) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   float v = 0.f;
+  if (i < n && cls) {
+    const int3 p = item_of(src, i);
+    float num[3] = {0.f, 0.f, 0.f}, den = 0.f;
+    for_each_expert(g, table, p, 8, [&](int j, int, float w) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) num[c] += w * yslot[3 * (8 * i + j) + c];
+      den += w;
+    });
+    int best = 0;
+#pragma unroll
+    for (int c = 1; c < 3; ++c)
+      if (num[c] / den > num[best] / den) best = c;
+    cls[i] = den > 0.f ? (uint8_t)best : (uint8_t)255;
+    return;
+  }
   if (i < n) {
-    const int3 p = item_of(leaf_o, key, i);
+    const int3 p = item_of(src, i);
     float num = 0.f, den = 0.f;
-    for_each_expert(g, table, p, [&](int j, int, float w) {
+    for_each_expert(g, table, p, 1, [&](int j, int, float w) {
       num += w * yslot[8 * i + j];
       den += w;
     });
@@ -357,22 +386,25 @@ int64_t moe_extract(const Tree& t, const int32_t lo[3], int32_t D, int32_t* ijk,
   return (int64_t)c;
 }
 
-static int64_t items(const Tree& t, bool slots) { return slots ? 512 * t.n_leaf : t.n_vox; }
-static const uint32_t* item_key(const Tree& t, bool slots) { return slots ? nullptr : t.vox_key.p; }
+static int64_t items(const Tree& t, int kind) {
+  return kind == MOE_VOXELS ? t.n_vox : (kind == MOE_VOXEL_SLOTS ? 512 * t.n_leaf : 4096 * t.n_l1);
+}
+static ItemSrc item_src(const Tree& t, int kind) {
+  if (kind == MOE_LEAF_SLOTS) return ItemSrc{t.l1_o.p, nullptr, 1};
+  return ItemSrc{t.leaf_o.p, kind == MOE_VOXELS ? t.vox_key.p : nullptr, 0};
+}
 
-void moe_count(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table, int n_exp, uint32_t* cnt,
+void moe_count(const Tree& t, int kind, const MoeGrid& g, const int32_t* table, int n_exp, uint32_t* cnt,
                uint32_t* uncovered, hipStream_t st) {
-  hipLaunchKernelGGL(k_moe_count, dim3(route_grid(items(t, slots))), dim3(256), (size_t)n_exp * 4, st, t.leaf_o.p,
-                     item_key(t, slots),
-                     items(t, slots), g, table, n_exp, cnt, uncovered);
+  hipLaunchKernelGGL(k_moe_count, dim3(route_grid(items(t, kind))), dim3(256), (size_t)n_exp * 4, st,
+                     item_src(t, kind), items(t, kind), g, table, n_exp, cnt, uncovered);
   NVDB_HIP(hipGetLastError());
 }
 
-void moe_route(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table, const MoeBox* box, int n_exp,
+void moe_route(const Tree& t, int kind, const MoeGrid& g, const int32_t* table, const MoeBox* box, int n_exp,
                const uint32_t* start, uint32_t* cursor, float* bx, uint32_t* bslot, uint64_t cap, hipStream_t st) {
-  hipLaunchKernelGGL(k_moe_route, dim3(route_grid(items(t, slots))), dim3(256), (size_t)n_exp * 12, st, t.leaf_o.p,
-                     item_key(t, slots),
-                     items(t, slots), g, table, box, n_exp, start, cursor, bx, bslot, cap);
+  hipLaunchKernelGGL(k_moe_route, dim3(route_grid(items(t, kind))), dim3(256), (size_t)n_exp * 12, st,
+                     item_src(t, kind), items(t, kind), g, table, box, n_exp, start, cursor, bx, bslot, cap);
   NVDB_HIP(hipGetLastError());
 }
 
@@ -416,10 +448,10 @@ void moe_plan(const uint32_t* cnt, int n, int chunk, uint64_t cap, uint32_t* cs,
   NVDB_HIP(hipGetLastError());
 }
 
-void moe_blend(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table, const float* yslot, float* values,
-               uint64_t* mask, hipStream_t st) {
-  hipLaunchKernelGGL(k_moe_blend, dim3(grid_of(items(t, slots))), dim3(256), 0, st, t.leaf_o.p, item_key(t, slots),
-                     items(t, slots), g, table, yslot, values, mask);
+void moe_blend(const Tree& t, int kind, const MoeGrid& g, const int32_t* table, const float* yslot, float* values,
+               uint64_t* mask, uint8_t* cls, hipStream_t st) {
+  hipLaunchKernelGGL(k_moe_blend, dim3(grid_of(items(t, kind))), dim3(256), 0, st, item_src(t, kind), items(t, kind), g,
+                     table, yslot, values, mask, cls);
   NVDB_HIP(hipGetLastError());
 }
 

@@ -356,17 +356,20 @@ void moe_mark_cells(const Tree& t, const MoeGrid& g, uint8_t* flag, hipStream_t 
 int64_t moe_extract(const Tree& t, const int32_t lo[3], int32_t D, int32_t* ijk, float* v, uint32_t* count,
                     hipStream_t st);
 // routing and blend over the active voxels, or (slots) over every voxel slot of the leaves
-void moe_count(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table, int n_exp, uint32_t* cnt,
+// items of a blended decode: the voxels, the voxel slots of the leaves, or the
+// leaf slots of the level-1 nodes
+enum : int { MOE_VOXELS = 0, MOE_VOXEL_SLOTS = 1, MOE_LEAF_SLOTS = 2 };
+void moe_count(const Tree& t, int kind, const MoeGrid& g, const int32_t* table, int n_exp, uint32_t* cnt,
                uint32_t* uncovered, hipStream_t st);
-void moe_route(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table, const MoeBox* box, int n_exp,
+void moe_route(const Tree& t, int kind, const MoeGrid& g, const int32_t* table, const MoeBox* box, int n_exp,
                const uint32_t* start, uint32_t* cursor, float* bx, uint32_t* bslot, uint64_t cap, hipStream_t st);
 // chunk layout of the grouped decode from the per-expert counts: cs[k] first
 // chunk of expert k (runs padded to whole chunks of `chunk` samples), cs[n] the
 // chunk count, start[k] = cs[k] * chunk; pairs beyond cap set flag[0] (and cs[n] = 0)
 void moe_plan(const uint32_t* cnt, int n, int chunk, uint64_t cap, uint32_t* cs, uint32_t* start, uint32_t* flag,
               hipStream_t st);
-void moe_blend(const Tree& t, bool slots, const MoeGrid& g, const int32_t* table, const float* yslot, float* values,
-               uint64_t* mask, hipStream_t st);
+void moe_blend(const Tree& t, int kind, const MoeGrid& g, const int32_t* table, const float* yslot, float* values,
+               uint64_t* mask, uint8_t* cls, hipStream_t st);
 void error_report(const Tree& t, const float* values, const uint64_t* pred_mask, nvdb_error_report* rep,
                   hipStream_t st);
 void error_report_l1(const Tree& t, const uint8_t* classes, nvdb_l1_report* rep, hipStream_t st);

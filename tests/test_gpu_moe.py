@@ -283,3 +283,52 @@ def test_moe_empty_and_single_voxel(gpu_lib):
     got = gpu_lib.decode_moe(models, cells, origin, size, halo, one).cpu().numpy().astype(np.float64)
     want = moe.decode_moe(ijk, ex, origin, size, halo)
     assert np.all(np.abs(got - want) <= 3e-5 * (1 + np.abs(want)))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_decode_moe_l1_matches_oracle(gpu_lib, scene, prec):
+    """Blended level-1 classes: every leaf slot of the level-1 node, the experts'
+    three logits blended with the gates at the slot centres, argmax against the
+    oracle's blend (slots whose two largest blended logits lie within the forward
+    tolerance may go either way).  A halo that is not a multiple of 8 and experts
+    of different shapes are refused."""
+    tr, ot = scene
+    origin, size, halo = (0, 0, 0), 64, 8
+    p = gpu_lib.FP32 if prec == "fp32" else gpu_lib.BF16
+    cells = gpu_lib.subdomain_cells(tr, origin, size, halo)
+    assert len(cells) == 8
+    W_, H_, m_ = 64, 4, 64
+    shapes = mlp.layer_shapes(2 * m_, W_, H_, 3)
+    models, ex = [], []
+    for k, c in enumerate(cells):
+        lo, D = gpu_lib.subdomain_box(origin, size, halo, c)
+        theta = workloads.init_params(2 * m_, W_, H_, 3, seed=300 + k)
+        theta[-(3 * W_ + 3):] *= 20.0  # logits of order 1
+        B = workloads.ffm_matrix(m_, 3.0, seed=400 + k)
+        mdl = gpu_lib.Model({2: (W_, H_, m_, 3)}, precision=p, domain_lo=lo, domain_size=D, value_scale=3.0)
+        mdl.set_params(2, theta)
+        mdl.set_encoding(2, B)
+        models.append(mdl)
+        ex.append(dict(cell=c, theta=theta.astype(np.float64), shapes=shapes, B=B.astype(np.float64), lo=lo, D=D,
+                       scale=1.0))
+    got = gpu_lib.decode_moe_l1(models, cells, origin, size, halo, tr).cpu().numpy().reshape(-1)
+    n = 4096 * len(ot["l1_origin"])
+    slots = ot["l1_origin"][np.arange(n) >> 12].astype(np.int64) + T.n1_to_offset(np.arange(n) & 4095)
+    cls, lg = moe.decode_moe_l1(slots, ex, origin, size, halo)
+    srt = np.sort(lg, axis=1)
+    tie = (srt[:, -1] - srt[:, -2]) <= (1e-4 if p == gpu_lib.FP32 else 6e-2)
+    assert tie.mean() < 0.1
+    n_exp = sum(moe.gate_leaf_slot(slots, c, origin, size, halo) > 0 for c in cells)
+    assert (n_exp == 8).sum() > 0  # slots blended from eight experts are exercised
+    assert np.all((got == cls) | tie), int(((got != cls) & ~tie).sum())
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        gpu_lib.decode_moe_l1(models, cells, origin, size, 4, tr)
+    assert e.value.code == gpu_lib.E_INVALID
+    other = gpu_lib.Model({2: (64, 4, 64, 3), 0: (64, 3, 18, 1)}, precision=gpu_lib.FP32, domain_size=80)
+    other.set_params(2, workloads.init_params(128, 64, 4, 3, seed=9))
+    other.set_encoding(2, workloads.ffm_matrix(64, 3.0, seed=9))
+    mixed = [other] + models[1:] if p == gpu_lib.BF16 else models
+    if p == gpu_lib.BF16:  # an FP32 expert among BF16 experts: different kernels
+        with pytest.raises(gpu_lib.NvdbError) as e:
+            gpu_lib.decode_moe_l1(mixed, cells, origin, size, halo, tr)
+        assert e.value.code == gpu_lib.E_UNSUPPORTED

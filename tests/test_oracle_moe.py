@@ -147,3 +147,67 @@ def test_geometry_checks():
     with pytest.raises(ValueError):
         moe.check_geometry(16, 0)
     moe.check_geometry(16, 8)
+
+
+def const3_expert(cell, logits, origin, S, h, K=8, W=16, H=2):
+    """A level-1 expert whose three logits are constant: weights zero, head biases."""
+    shapes = mlp.layer_shapes(K, W, H, 3)
+    theta = np.zeros(mlp.param_count(K, W, H, 3))
+    theta[-3:] = logits
+    lo, D = moe.widened_box(cell, origin, S, h)
+    return dict(cell=cell, theta=theta, shapes=shapes, B=np.zeros((K // 2, 3)), lo=lo, D=D, scale=1.0)
+
+
+def test_leaf_slot_gate_closed_form():
+    # S = 32, h = 8, cell 0 at origin 0: widened box [-8, 40), edge 48.  Slots at
+    # x origins -8, 0, ..., 32 have centres -4, 4, ..., 36 (t = 4, 12, ..., 44 from
+    # the lower face): gates 4/16, 12/16, 1, 1, 12/16, 4/16 along x; slots whose
+    # block leaves the box get 0; the 3-D gate is the product over the axes.
+    S, h = 32, 8
+    xs = np.arange(-16, 48, 8)
+    o = np.stack([xs, np.full_like(xs, 8), np.full_like(xs, 16)], 1)
+    g = moe.gate_leaf_slot(o, (0, 0, 0), (0, 0, 0), S, h)
+    want = {-16: 0.0, -8: 0.25, 0: 0.75, 8: 1.0, 16: 1.0, 24: 0.75, 32: 0.25, 40: 0.0}
+    assert np.array_equal(g, np.array([want[x] for x in xs]))
+    assert moe.gate_leaf_slot(np.array([[-8, -8, 32]]), (0, 0, 0), (0, 0, 0), S, h)[0] == 0.25 ** 3
+    # neighbours' gates sum to 1 on every slot of cell 0's widened box (all 27 cells kept)
+    cells = list(itertools.product((-1, 0, 1), repeat=3))
+    ax = np.arange(-8, 40, 8)
+    o = np.stack(np.meshgrid(ax, ax, ax, indexing="ij"), -1).reshape(-1, 3)
+    gs = np.stack([moe.gate_leaf_slot(o, c, (0, 0, 0), S, h) for c in cells])
+    assert np.array_equal(gs.sum(0), np.ones(len(o)))
+
+
+def test_level1_blend_of_constant_experts():
+    # two cells along x: expert 0 says class 0 (logits 1, 0, 0), expert 1 class 2
+    # (logits 0, 0, 2).  Blended logits (1 - w, 0, 2 w) with w expert 1's share:
+    # class 2 wherever 2 w > 1 - w, i.e. w > 1/3; slot centres in the overlap
+    # [S - h, S + h) = [24, 40) are 28 and 36, with w = 0.25 and 0.75.
+    S, h, org = 32, 8, (0, 0, 0)
+    ex = [const3_expert((0, 0, 0), [1.0, 0.0, 0.0], org, S, h), const3_expert((1, 0, 0), [0.0, 0.0, 2.0], org, S, h)]
+    xs = np.arange(0, 64, 8)
+    o = np.stack([xs, np.full_like(xs, 8), np.full_like(xs, 8)], 1)
+    cls, lg = moe.decode_moe_l1(o, ex, org, S, h)
+    assert cls.tolist() == [0, 0, 0, 0, 2, 2, 2, 2]
+    assert np.allclose(lg[3], [0.75, 0.0, 0.5]) and np.allclose(lg[4], [0.25, 0.0, 1.5])
+
+
+def test_level1_single_expert_is_the_plain_decode():
+    v = workloads.sphere_sdf().numpy()
+    tr = T.build(*T.active_set_dense(v, (0, 0, 0), T.SDF, 3.0))
+    S, h, o = 64, 8, (0, 0, 0)
+    K, W, H = 36, 64, 3
+    shapes = mlp.layer_shapes(K, W, H, 3)
+    theta = workloads.init_params(K, W, H, 3, seed=5).astype(np.float64)
+    B = mlp.pe_matrix(6)
+    lo, D = moe.widened_box((0, 0, 0), o, S, h)
+    e = dict(cell=(0, 0, 0), theta=theta, shapes=shapes, B=B, lo=lo, D=D, scale=1.0)
+    slots = tr["l1_origin"][np.arange(4096 * len(tr["l1_origin"])) >> 12] + T.n1_to_offset(np.arange(4096 * len(tr["l1_origin"])) & 4095)
+    cls, lg = moe.decode_moe_l1(slots, [e], o, S, h)
+    want = F.decode_l1(theta, shapes, B, tr, lo, D)
+    # the level-1 node spans [0, 128)^3; the cell's widened box [-8, 72)^3 holds the
+    # slots with origins up to 64 (9^3 of them), where the blend is the expert itself
+    inside = np.all(slots + 8 <= 72, axis=1)
+    assert inside.sum() == 729 and np.all(np.isnan(lg[~inside]))
+    assert np.allclose(lg[inside], want[inside], rtol=0, atol=1e-12)
+    assert np.array_equal(cls[inside], F.l1_classes(want[inside]))
