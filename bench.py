@@ -299,6 +299,12 @@ def main():
     if not args.skip_sequence:
         print("sequence leg ...", file=sys.stderr, flush=True)
         out["sequence"] = sequence_leg(args.seq_frames, args.seq_cap, tuned_g, args.seq_full_width)
+        # the same sequence refined at the cold rate (Sec. 3.6 allows the same or a
+        # smaller rate for the refinement): warm against cold only
+        same = sequence_leg(args.seq_frames, args.seq_cap, tuned_g, args.seq_full_width, warm_lr=1e-3)
+        out["sequence"]["warm_at_cold_rate"] = {k: same[k] for k in ("warm", "sequence_s", "warm_frames_hitting_cap",
+                                                                     "warm_vs_cold")}
+        out["sequence"]["warm_at_cold_rate"]["last_frame_rms"] = same["frames"][-1]["rms"]
         torch.cuda.empty_cache()
     if not args.skip_cloud:
         print("cloud leg ...", file=sys.stderr, flush=True)
@@ -323,7 +329,7 @@ def measured_traffic():
     return rec["traffic_bytes_per_launch"]
 
 
-def sequence_leg(n_frames, cap, tuned_g, full_width=False):
+def sequence_leg(n_frames, cap, tuned_g, full_width=False, warm_lr=1e-4):
     """Warm-started fit of an animated sequence: frame 0 cold (2000 steps, lr 1e-3)
     then refit at 1e-4, later frames warm-started at 1e-4 until the batch loss is
     below frame 0's final loss (at most `cap` steps); then the last frame fitted
@@ -351,7 +357,7 @@ def sequence_leg(n_frames, cap, tuned_g, full_width=False):
         mdl.set_encoding(k, workloads.ffm_matrix(M, 10.0, seed=41 + k))
         mdl.set_params(k, th0[k])
     cold = dict(steps=2000, batch=BATCH, seed=0, lr=1e-3)
-    warm = dict(steps=cap, batch=BATCH, seed=1, lr=1e-4)
+    warm = dict(steps=cap, batch=BATCH, seed=1, lr=warm_lr)
     torch.cuda.synchronize()
     t = time.perf_counter()
     reps, Lseq, fp = mdl.fit_sequence(trees, cold, warm, nets_mask=3, use_graph=True)
@@ -407,7 +413,7 @@ def sequence_leg(n_frames, cap, tuned_g, full_width=False):
                         "level-0 classifier 4x128, FFM m=64 sigma=10, BF16, 2^18 samples per network per step"
                         % (n_frames, "at full width" if full_width else "growing from x < 288 to full width"),
             "frame_voxels_min_max": [min(counts), max(counts)], "frames_generated_s": gen_s,
-            "cold": {"steps": 2000, "lr": 1e-3}, "warm": {"cap": cap, "lr": 1e-4},
+            "cold": {"steps": 2000, "lr": 1e-3}, "warm": {"cap": cap, "lr": warm_lr},
             "sequence_s": seq_s, "steps_total": total_steps,
             "train_samples_per_s": 2 * BATCH * total_steps / seq_s,
             "warm_frames_hitting_cap": sum(1 for s_ in steps[1:] if s_ >= cap),
