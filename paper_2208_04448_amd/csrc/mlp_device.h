@@ -122,20 +122,36 @@ __device__ __forceinline__ uint32_t relu_pk(uint32_t w) {
   v = __builtin_elementwise_max(v, short2v{0, 0});
   return __builtin_bit_cast(uint32_t, v);
 }
-// Zero the halves of g whose matching half of a (a ReLU output, so >= +0) is zero:
-// t = min(a, 1) per 16-bit half is 1 where a > 0 and 0 where a == 0, and the
-// 16-bit product g * t keeps or clears each half: two packed 16-bit integer
-// instructions, written as inline assembly because the optimiser turns the
-// product by {0, 1} into per-half compares and selects.  The compiler does not
-// count inline assembly as a vector-ALU write when it pads matrix-core operand
-// reads, so the trailing s_nop supplies the two wait states a matrix product
-// reading the result right away would need.
-__device__ __forceinline__ uint32_t mask_pk(uint32_t g, uint32_t a) {
-  uint32_t r;
-  asm("v_pk_min_u16 %0, %1, %2\n\tv_pk_mul_lo_u16 %0, %3, %0\n\ts_nop 1"
-      : "=&v"(r)
-      : "v"(a), "s"(0x00010001u), "v"(g));
-  return r;
+// Zero the halves of the 8 words g whose matching half of a (a ReLU output, so
+// >= +0) is zero: t = min(a, 1) per 16-bit half is 1 where a > 0 and 0 where
+// a == 0, and the 16-bit product g * t keeps or clears each half.  The products
+// are inline assembly because the optimiser turns a product by {0, 1}, and the
+// minimum too, into per-half compares and selects.  The compiler does not count inline assembly as
+// a vector-ALU write when it pads matrix-core operand reads, so one trailing s_nop
+// supplies the two wait states a matrix product reading the last word right away
+// would need (the earlier words are followed by the later products).
+__device__ __forceinline__ void mask_pk8(uint32_t (&g)[8], const uint32_t* a) {
+  uint32_t t[8];
+  asm("v_pk_min_u16 %8, %16, %24\n\t"
+      "v_pk_min_u16 %9, %17, %24\n\t"
+      "v_pk_min_u16 %10, %18, %24\n\t"
+      "v_pk_min_u16 %11, %19, %24\n\t"
+      "v_pk_min_u16 %12, %20, %24\n\t"
+      "v_pk_min_u16 %13, %21, %24\n\t"
+      "v_pk_min_u16 %14, %22, %24\n\t"
+      "v_pk_min_u16 %15, %23, %24\n\t"
+      "v_pk_mul_lo_u16 %0, %0, %8\n\t"
+      "v_pk_mul_lo_u16 %1, %1, %9\n\t"
+      "v_pk_mul_lo_u16 %2, %2, %10\n\t"
+      "v_pk_mul_lo_u16 %3, %3, %11\n\t"
+      "v_pk_mul_lo_u16 %4, %4, %12\n\t"
+      "v_pk_mul_lo_u16 %5, %5, %13\n\t"
+      "v_pk_mul_lo_u16 %6, %6, %14\n\t"
+      "v_pk_mul_lo_u16 %7, %7, %15\n\t"
+      "s_nop 1"
+      : "+v"(g[0]), "+v"(g[1]), "+v"(g[2]), "+v"(g[3]), "+v"(g[4]), "+v"(g[5]), "+v"(g[6]), "+v"(g[7]),
+        "=&v"(t[0]), "=&v"(t[1]), "=&v"(t[2]), "=&v"(t[3]), "=&v"(t[4]), "=&v"(t[5]), "=&v"(t[6]), "=&v"(t[7])
+      : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]), "v"(a[6]), "v"(a[7]), "s"(0x00010001u));
 }
 template <int PREC>
 __device__ __forceinline__ void store_relu(floatx16 a, uint32_t* s) {
@@ -152,9 +168,11 @@ __device__ __forceinline__ void store_relu(floatx16 a, uint32_t* s) {
 template <int PREC>
 __device__ __forceinline__ void store_masked(floatx16 a, uint32_t* s, const uint32_t* act) {
   if constexpr (PREC == NVDB_BF16) {
-    PR<PREC>::store(a, s);
+    uint32_t w[8];
+    PR<PREC>::store(a, w);
+    mask_pk8(w, act);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) s[i] = mask_pk(s[i], act[i]);
+    for (int i = 0; i < 8; ++i) s[i] = w[i];
   } else {
 #pragma unroll
     for (int i = 0; i < 16; ++i) s[i] = __uint_as_float(act[i]) > 0.f ? __float_as_uint(a[i]) : 0u;

@@ -63,9 +63,12 @@ struct WBuf {
   int soff;  // byte offset of the layer (uniform)
   int voff;  // lane * 16
   int nib;   // input blocks of the layer (forward) or output blocks (backward)
+  // The fragment's offset splits into a 4 KiB page (scalar offset, shared by the page's
+  // four fragments) and its place in the page (the instruction's immediate offset).
   __device__ __forceinline__ bf16x8 operator()(int b, int t, int kk) const {
-    return __builtin_bit_cast(
-        bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff, soff + ((b * nib + t) * 2 + kk) * 1024, 0));
+    const int f = (b * nib + t) * 2 + kk;
+    return __builtin_bit_cast(bf16x8,
+                              __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff + (f & 3) * 1024, soff + (f >> 2) * 4096, 0));
   }
 };
 
@@ -204,8 +207,6 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
   float* partial = TN.partial + (size_t)blockIdx.x * nv.s.pstride();
   const __amdgpu_buffer_rsrc_t wf_rsrc = raw_rsrc(nv.wfrag, wfrag_elems(nv.s) * 2);
   const __amdgpu_buffer_rsrc_t wt_rsrc = raw_rsrc(nv.wtfrag, wtfrag_elems(nv.s) * 2);
-  PhaseA<NIB0> pa;
-  pa.load(sm_benc0);
   NextSample nx{};
   {
     const int64_t j0 = (int64_t)blockIdx.x * 128 + wave * 32 + (lane_id() & 31);
@@ -233,6 +234,10 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
     // ================= forward: rows of a_1 .. a_{H-1} to LDS, a_H in registers
     uint32_t Hl[NB][8];
     {
+      // the encoding's frequency rows are read from LDS where they are used (held in
+      // registers across the iteration they would be spilled)
+      PhaseA<NIB0> pa;
+      pa.load(sm_benc0 + z);
       uint32_t X0[NIB0][8];
       encode_bf16_mfma<NIB0>(pa, smp, X0);
       WBuf wf[H];
@@ -273,6 +278,21 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
       store_masked<NVDB_BF16>(g, Gc[ob], Hl[ob]);
     }
 
+    // Transposed weight fragments of the input-gradient products run as one pipeline
+    // over the backward stages: the first ones of a stage are requested during the
+    // stage before it (those of layer H-1 before its stage's barrier), so no stage
+    // starts on a load.
+    constexpr int DPF = ROWS_DX_PF;
+    static_assert(16 % DPF == 0, "step q of every stage uses slot q mod DPF");
+    bf16x8 dfa[DPF], dfb[DPF];
+    // step q = 0..15 of layer l: input blocks 2p, 2p+1 (p = q / 8), k-step q % 8 of g_l
+    auto dxfetch = [&](int l, int q, bf16x8& x, bf16x8& y2) {
+      const WBuf wt{wt_rsrc, z + (l - 1) * W * W * 2, vo, NB};
+      const int pp = q >> 3, ss = q & 7;
+      x = wt(2 * pp, ss >> 1, ss & 1);
+      y2 = wt(2 * pp + 1, ss >> 1, ss & 1);
+    };
+
     // ================= head weight gradient: a_H rows and gy of the work-group's samples
     {
       char* own = grows + wave * CF::ROWS;
@@ -309,9 +329,15 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
       char* arows = hrows + (l == 0 ? H - 2 : l - 1) * CF::LROWS;
       write_rows_bf16<NB>(grows + wave * CF::ROWS, K, Gc);
       if constexpr (l == 0) {
+        PhaseA<NIB0> pa;
+        pa.load(sm_benc0 + z);
         uint32_t X0[NIB0][8];
         encode_bf16_mfma<NIB0>(pa, smp, X0);
         write_rows_bf16<NIB0>(arows + wave * CF::ROWS, K, X0);
+      }
+      if constexpr (l == H - 1) {
+#pragma unroll
+        for (int q = 0; q < DPF; ++q) dxfetch(H - 1, q, dfa[q], dfb[q]);
       }
       __syncthreads();
       // dW_l: 8 steps (slot sl of the four waves' rows, k-step kk of its 32 samples),
@@ -319,39 +345,31 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
       // Gn = (W_l^T g_l) * 1[a_l > 0], two block pairs of 8 steps
       constexpr int NDW = 8;
       bf16x8 ga[2][2], hb[2][2];
+      // A[0] is the wave's own output block 2 wo + wi (whose bias gradient it sums),
+      // A[1] the other block of the pair
       auto dw_load = [&](int st, bf16x8 (&A)[2], bf16x8 (&Bv)[2]) {
         const int sl = st >> 1, kk = st & 1;
-        A[0] = frag_tr(grows + sl * CF::ROWS, K, 16 * kk, 2 * wo);
-        A[1] = frag_tr(grows + sl * CF::ROWS, K, 16 * kk, 2 * wo + 1);
+        A[0] = frag_tr(grows + sl * CF::ROWS, K, 16 * kk, 2 * wo + wi);
+        A[1] = frag_tr(grows + sl * CF::ROWS, K, 16 * kk, 2 * wo + (wi ^ 1));
         Bv[0] = frag_tr(arows + sl * CF::ROWS, K, 16 * kk, 2 * wi);
         Bv[1] = frag_tr(arows + sl * CF::ROWS, K, 16 * kk, 2 * wi + 1);
       };
       auto dw_step = [&](const bf16x8 (&A)[2], const bf16x8 (&Bv)[2]) {
-        dbias[l][0] = frag_sum(wi ? A[1] : A[0], dbias[l][0]);
+        dbias[l][0] = frag_sum(A[0], dbias[l][0]);
         mfma_dw4(dacc[l][0][0], dacc[l][0][1], dacc[l][1][0], dacc[l][1][1], A[0], A[1], Bv[0], Bv[1]);
       };
       dw_load(0, ga[0], hb[0]);
       if constexpr (l > 0) {
-        const WBuf wt{wt_rsrc, z + (l - 1) * W * W * 2, vo, NB};
         const char* own_a = arows + wave * CF::ROWS;
         uint32_t Gn[NB][8];
-        constexpr int PF = ROWS_DX_PF;
-        bf16x8 fa[PF], fb[PF];
-        // steps q = 0..15: pair p = q / 8 (input blocks 2p, 2p+1), k-step s = q % 8 of Gc
-        auto wfetch = [&](int q, bf16x8& x, bf16x8& y2) {
-          const int pp = q >> 3, ss = q & 7;
-          x = wt(2 * pp, ss >> 1, ss & 1);
-          y2 = wt(2 * pp + 1, ss >> 1, ss & 1);
-        };
-#pragma unroll
-        for (int q = 0; q < PF; ++q) wfetch(q, fa[q], fb[q]);
         floatx16 a0 = floatx16{}, a1 = floatx16{};
         uint32_t m0[8], m1[8];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
           const int pp = q >> 3, ss = q & 7;
-          const bf16x8 w0 = fa[q % PF], w1 = fb[q % PF];
-          if (q + PF < 16) wfetch(q + PF, fa[q % PF], fb[q % PF]);
+          const bf16x8 w0 = dfa[q % DPF], w1 = dfb[q % DPF];
+          if (q + DPF < 16) dxfetch(l, q + DPF, dfa[q % DPF], dfb[q % DPF]);
+          else if (l > 1) dxfetch(l - 1, q + DPF - 16, dfa[q % DPF], dfb[q % DPF]);  // the next stage's first
           const bf16x8 bg = P::sfrag(Gc[ss >> 1], ss & 1);
           a0 = P::mma(w0, bg, a0);
           a1 = P::mma(w1, bg, a1);
@@ -400,7 +418,7 @@ __global__ void __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        const int ob = 2 * wo + a, ib = 2 * wi + b, i = 32 * ib + fl;
+        const int ob = 2 * wo + (a ^ wi), ib = 2 * wi + b, i = 32 * ib + fl;
         if (i < win) {
 #pragma unroll
           for (int r = 0; r < 16; ++r) partial[nv.s.woff(l) + (size_t)sfeat(ob, r, h) * win + i] = dacc[l][a][b][r];
