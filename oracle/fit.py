@@ -6,7 +6,9 @@ Encoding trains each network on its own samples (Sec. 3.2.1, 3.3.1):
   * level-0 mask classifier: every voxel slot of the existing leaves
     ("performed within level-1's children nodes"), label = active bit;
   * level-1 node classifier: every leaf slot of the existing level-1 nodes at
-    the leaf centre, label = child (0) / active tile (1) / inactive tile (2).
+    the leaf centre, label = child (0) / active tile (1) / inactive tile (2);
+  * tile value regressor: the active tiles at their leaf-slot centres, target
+    scaled as the voxel regressor's (Sec. 3.3.1).
 Decoding (Sec. 3.5, offline sequential access) evaluates the networks over all
 slots: mask bit = logit > 0, node class = argmax with ties to the lowest index,
 value = y * band (SDF) or y (fog).  The error report follows the quality
@@ -17,8 +19,9 @@ import numpy as np
 
 from . import fp8 as fp8_form, mlp, sampler, tree as T
 
-NET_STREAM = {"regressor": sampler.STREAM_REGRESSOR, "l0": sampler.STREAM_L0, "l1": sampler.STREAM_L1}
-NET_LOSS = {"regressor": "mse", "l0": "bce", "l1": "ce"}
+NET_STREAM = {"regressor": sampler.STREAM_REGRESSOR, "l0": sampler.STREAM_L0, "l1": sampler.STREAM_L1,
+              "tile": sampler.STREAM_TILE}
+NET_LOSS = {"regressor": "mse", "l0": "bce", "l1": "ce", "tile": "mse"}
 
 
 def population(tr, net):
@@ -28,6 +31,8 @@ def population(tr, net):
         return 512 * len(tr["leaf_origin"])
     if net == "l1":
         return 4096 * len(tr["l1_origin"])
+    if net == "tile":
+        return len(tr["tile_value"])
     raise ValueError(net)
 
 
@@ -50,6 +55,11 @@ def net_inputs(tr, net, idx, lo, D, kind, band):
         child = T.mask_bits(tr["l1_child"], node, n1)
         active = T.mask_bits(tr["l1_active"], node, n1)
         t = np.where(child == 1, 0, np.where(active == 1, 1, 2))
+    elif net == "tile":
+        o = tr["l1_origin"][tr["tile_l1"][idx]].astype(np.int64) + T.n1_to_offset(tr["tile_n1"][idx])
+        x = mlp.normalize_leaf_slot(o, lo, D)
+        v = tr["tile_value"][idx]
+        t = v / band if kind == T.SDF else v
     else:
         raise ValueError(net)
     return x, t
@@ -159,6 +169,20 @@ def decode_l1(theta, shapes, B, tr, lo, D, slots=None, fp8=False):
     return _batched_predict(theta, shapes, B, x, fp8=fp8)
 
 
+def decode_tiles(theta, shapes, B, tr, lo, D, kind, band, fp8=False):
+    """Tile value regressor at every active tile of the tree, in value units."""
+    x, _ = net_inputs(tr, "tile", np.arange(len(tr["tile_value"])), lo, D, kind, band)
+    y = _batched_predict(theta, shapes, B, x, fp8=fp8)[:, 0]
+    return y * band if kind == T.SDF else y
+
+
+def errors_tiles(tr, that):
+    """max |t^ - t| and RMS over the active tiles of the tree (value units)."""
+    d = np.asarray(that, np.float64) - tr["tile_value"]
+    return dict(n=len(d), max_abs=float(np.max(np.abs(d))) if len(d) else 0.0,
+                rms=float(np.sqrt(np.mean(d * d))) if len(d) else 0.0)
+
+
 def mask_from_logits(logits, n_leaves):
     """Predicted leaf masks (L, 8) uint64 from slot logits in leaf-major order."""
     bits = (np.asarray(logits).reshape(n_leaves, 512) > 0)
@@ -185,24 +209,33 @@ def errors_l1(tr, classes):
                 mismatch=int(np.sum(c != truth)))
 
 
-def topology_from_decisions(tr, classes, active_fn, value_fn):
+def topology_from_decisions(tr, classes, active_fn, value_fn, tile_fn=None):
     """Lower tree levels rebuilt from per-slot decisions (Sec. 3.3, 3.5).
 
-    classes: level-1 class of every leaf slot of tr's level-1 nodes (0 = leaf);
-    active_fn(p) -> bool per voxel coordinate of the predicted leaves' slots;
-    value_fn(p, active) -> values of the active voxels.  Returns the predicted
-    leaf origins, voxel coordinates and values in canonical order."""
-    slots = np.nonzero(np.asarray(classes).reshape(-1) == 0)[0]
+    classes: level-1 class of every leaf slot of tr's level-1 nodes (0 = leaf,
+    1 = active tile); active_fn(p) -> bool per voxel coordinate of the predicted
+    leaves' slots; value_fn(p, active) -> values of the active voxels;
+    tile_fn(o) -> values of the predicted active tiles at leaf origins o (the top-
+    down traversal of Sec. 3.3.1: an active tile takes the tile regressor's value
+    and has no leaf below it).  Returns the predicted leaf origins, voxel
+    coordinates and values in canonical order, and the predicted tiles as keys
+    (level-1 node << 12 | n1), origins and values (empty without tile_fn)."""
+    flat = np.asarray(classes).reshape(-1)
+    tslots = np.nonzero(flat == 1)[0] if tile_fn is not None else np.zeros(0, np.int64)
+    tile_o = tr["l1_origin"][tslots >> 12].astype(np.int64) + T.n1_to_offset(tslots & 4095)
+    tile_v = np.asarray(tile_fn(tile_o), np.float64) if len(tslots) else np.zeros(0)
+    slots = np.nonzero(flat == 0)[0]
     node, n1 = slots >> 12, slots & 4095
     leaf_o = tr["l1_origin"][node].astype(np.int64) + T.n1_to_offset(n1)
     p = (leaf_o[:, None, :] + T.n0_to_offset(np.arange(512))[None, :, :]).reshape(-1, 3)
     act = np.asarray(active_fn(p), bool) if len(p) else np.zeros(0, bool)
     ijk = p[act]
     values = np.asarray(value_fn(p, act), np.float64) if len(ijk) else np.zeros(0)
-    return dict(leaf_origin=leaf_o, ijk=ijk, values=values)
+    return dict(leaf_origin=leaf_o, ijk=ijk, values=values, tile_key=tslots.astype(np.int64), tile_origin=tile_o,
+                tile_value=tile_v)
 
 
-def topology_from_values(tr, classes, kind, thr, value_fn, active_fn=None):
+def topology_from_values(tr, classes, kind, thr, value_fn, active_fn=None, tile_fn=None):
     """Decided topology of the lower levels (Sec. 3.3, 3.5) from per-voxel functions.
 
     classes: level-1 class of every leaf slot of tr's level-1 nodes (0 = leaf).
@@ -210,12 +243,13 @@ def topology_from_values(tr, classes, kind, thr, value_fn, active_fn=None):
     (the level-0 classifier's decision); without one, where the value the
     regressor gives it passes the volume's own active rule: |v| <= band for a
     level set (closed interval, Sec. 3.2.1), v > threshold for fog.  value_fn(p)
-    gives the values in value units.  Returns leaf origins, voxel coordinates and
-    values in canonical order."""
+    gives the values in value units; tile_fn as in topology_from_decisions.
+    Returns leaf origins, voxel coordinates and values in canonical order, and the
+    predicted tiles."""
     if active_fn is not None:
         def values(p, act):
             return value_fn(p[act])
-        return topology_from_decisions(tr, classes, active_fn, values)
+        return topology_from_decisions(tr, classes, active_fn, values, tile_fn)
     cache = {}
 
     def active(p):
@@ -225,15 +259,20 @@ def topology_from_values(tr, classes, kind, thr, value_fn, active_fn=None):
 
     def values(p, act):
         return cache["v"][act]
-    return topology_from_decisions(tr, classes, active, values)
+    return topology_from_decisions(tr, classes, active, values, tile_fn)
 
 
-def decode_topology(tr, lo, D, kind, thr, value_scale, l1, reg, l0=None, fp8=False):
+def decode_topology(tr, lo, D, kind, thr, value_scale, l1, reg, l0=None, fp8=False, tile=None):
     """Full decode with the networks: level-1 classes at every leaf slot, then the
     level-0 classifier (logit > 0) or, without one, the regressor's value tested
     with the volume's active rule (topology_from_values), then the regressor's
-    values.  l1, reg, l0: (theta, shapes, B)."""
+    values; with a tile value regressor, every slot classified as an active tile
+    takes its value at the slot's leaf centre.  l1, reg, l0, tile: (theta, shapes, B)."""
     cls = l1_classes(decode_l1(*l1, tr, lo, D, fp8=fp8))
+    tile_fn = None
+    if tile is not None:
+        def tile_fn(o):
+            return _batched_predict(*tile, mlp.normalize_leaf_slot(o, lo, D), fp8=fp8)[:, 0] * value_scale
 
     def reg_values(p):
         return _batched_predict(*reg, mlp.normalize_voxel(p, lo, D), fp8=fp8)[:, 0] * value_scale
@@ -242,7 +281,7 @@ def decode_topology(tr, lo, D, kind, thr, value_scale, l1, reg, l0=None, fp8=Fal
     if l0 is not None:
         def active(p):
             return _batched_predict(*l0, mlp.normalize_voxel(p, lo, D), fp8=fp8)[:, 0] > 0
-    return topology_from_values(tr, cls, kind, thr, reg_values, active)
+    return topology_from_values(tr, cls, kind, thr, reg_values, active, tile_fn)
 
 
 def _voxel_keys(ijk):

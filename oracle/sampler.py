@@ -23,7 +23,7 @@ GOLDEN = 0x9E3779B97F4A7C15
 M1 = 0xBF58476D1CE4E5B9
 M2 = 0x94D049BB133111EB
 
-STREAM_REGRESSOR, STREAM_L0, STREAM_L1 = 0, 1, 2
+STREAM_REGRESSOR, STREAM_L0, STREAM_L1, STREAM_TILE = 0, 1, 2, 3
 
 
 def mix_int(z):

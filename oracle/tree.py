@@ -155,7 +155,46 @@ def build(ijk, values):
     return dict(ijk=ijk, values=values, vox_leaf=vox_leaf, vox_n0=d["n0"],
                 leaf_origin=leaf_origin, leaf_mask=leaf_mask, leaf_off=leaf_off, leaf_l1=leaf_l1,
                 l1_origin=l1_origin, l1_child=l1_child, l1_active=np.zeros_like(l1_child), l1_l2=l1_l2,
-                l2_origin=l2_origin, l2_child=l2_child, l2_active=np.zeros_like(l2_child))
+                l2_origin=l2_origin, l2_child=l2_child, l2_active=np.zeros_like(l2_child),
+                tile_l1=np.zeros(0, np.int64), tile_n1=np.zeros(0, np.int64),
+                tile_origin=np.zeros((0, 3), np.int32), tile_value=np.zeros(0, np.float64))
+
+
+def prune_tiles(tr):
+    """Replace every leaf whose 512 voxels are all active and share one value by an
+    active tile of its level-1 node (a constant leaf-sized region that carries one
+    value and no leaf node: the active tiles of Sec. 3.3.1, whose values the tile
+    value regressor encodes).  The level-1 and upper nodes stay as they are; the
+    tile's child bit is cleared and its active-tile bit set.  Tiles keep the
+    canonical order of the leaves they replace, i.e. (level-1 node, n1)."""
+    L = len(tr["leaf_origin"])
+    full = np.all(tr["leaf_mask"] == np.uint64(0xFFFFFFFFFFFFFFFF), axis=1) if L else np.zeros(0, bool)
+    const = np.zeros(L, bool)
+    for i in np.nonzero(full)[0]:
+        v = tr["values"][tr["leaf_off"][i]:tr["leaf_off"][i + 1]]
+        const[i] = bool(np.all(v == v[0]))
+    tile = full & const
+    keep = ~tile
+    vox_keep = keep[tr["vox_leaf"]] if len(tr["values"]) else np.zeros(0, bool)
+    new_index = np.cumsum(keep) - 1
+    leaf_n1 = decompose(tr["leaf_origin"])["n1"] if L else np.zeros(0, np.int64)
+    l1_child = tr["l1_child"].copy()
+    l1_active = tr["l1_active"].copy()
+    for i in np.nonzero(tile)[0]:
+        node, n1 = int(tr["leaf_l1"][i]), int(leaf_n1[i])
+        l1_child[node, n1 >> 6] &= ~(np.uint64(1) << np.uint64(n1 & 63))
+        l1_active[node, n1 >> 6] |= np.uint64(1) << np.uint64(n1 & 63)
+    counts = np.diff(tr["leaf_off"])[keep]
+    out = dict(tr)
+    out.update(ijk=tr["ijk"][vox_keep], values=tr["values"][vox_keep],
+               vox_leaf=new_index[tr["vox_leaf"][vox_keep]], vox_n0=tr["vox_n0"][vox_keep],
+               leaf_origin=tr["leaf_origin"][keep], leaf_mask=tr["leaf_mask"][keep],
+               leaf_off=np.concatenate([[0], np.cumsum(counts)]).astype(np.int64), leaf_l1=tr["leaf_l1"][keep],
+               l1_child=l1_child, l1_active=l1_active,
+               tile_l1=tr["leaf_l1"][tile].astype(np.int64), tile_n1=leaf_n1[tile].astype(np.int64),
+               tile_origin=tr["leaf_origin"][tile],
+               tile_value=np.array([tr["values"][tr["leaf_off"][i]] for i in np.nonzero(tile)[0]], np.float64))
+    return out
 
 
 def mask_bits(words, row, n):

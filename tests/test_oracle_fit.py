@@ -342,3 +342,62 @@ def test_topology_active_rule_rebuilds_truth_fog():
     cls[first_leaf] = 2
     out2 = F.topology_from_values(tr, cls, T.FOG, 0.5, lookup)
     assert len(out2["ijk"]) == len(tr["ijk"]) - int(np.sum(tr["vox_leaf"] == 0))
+
+
+# ---------------------------------------------------------------- active tiles (Sec. 3.3.1)
+@pytest.fixture(scope="module")
+def fog_tiles():
+    v = workloads.saturated_fog().numpy()
+    ijk, vals = T.active_set_dense(v, (0, 0, 0), T.FOG, 0.05)
+    return T.prune_tiles(T.build(ijk, vals))
+
+
+def test_tile_samples_are_the_active_tile_slots(fog_tiles):
+    """The tile regressor's samples are the level-1 slots whose ternary class is
+    'active tile', at the same leaf centres the level-1 classifier sees, with the
+    tile value (fog: unscaled) as target."""
+    tr = fog_tiles
+    nt = F.population(tr, "tile")
+    assert nt == len(tr["tile_value"]) >= 4
+    key = tr["tile_l1"] * 4096 + tr["tile_n1"]
+    x1, c1 = F.net_inputs(tr, "l1", key, (0, 0, 0), 64, T.FOG, 0.05)
+    xt, tt = F.net_inputs(tr, "tile", np.arange(nt), (0, 0, 0), 64, T.FOG, 0.05)
+    assert np.array_equal(x1, xt) and np.all(c1 == 1)
+    assert np.all(tt == 1.0) and np.array_equal(tt, tr["tile_value"])
+    assert np.allclose(xt, (tr["tile_origin"] + 4) / 64)
+    _, call = F.net_inputs(tr, "l1", np.arange(F.population(tr, "l1")), (0, 0, 0), 64, T.FOG, 0.05)
+    assert (call == 1).sum() == nt and (call == 0).sum() == len(tr["leaf_origin"])
+
+
+def test_topology_with_tiles_from_true_decisions(fog_tiles):
+    """The top-down decode with the true ternary classes, masks, values and tile
+    values rebuilds the voxels and the tiles exactly; a tile predicted inactive
+    is missing from the result, and planted tile errors are measured exactly."""
+    tr = fog_tiles
+    n = 4096 * len(tr["l1_origin"])
+    _, cls = F.net_inputs(tr, "l1", np.arange(n), (0, 0, 0), 64, T.FOG, 0.05)
+    keys = set(map(tuple, tr["ijk"].tolist()))
+    lut = {k: v for k, v in zip(map(tuple, tr["ijk"].tolist()), tr["values"])}
+    tlut = {tuple(o): v for o, v in zip(tr["tile_origin"].tolist(), tr["tile_value"])}
+    active = lambda p: np.array([tuple(q) in keys for q in p.tolist()])
+    values = lambda p, a: np.array([lut[tuple(q)] for q in p[a].tolist()])
+    tiles = lambda o: np.array([tlut[tuple(q)] for q in o.tolist()])
+    pred = F.topology_from_decisions(tr, cls, active, values, tiles)
+    assert np.array_equal(pred["ijk"], tr["ijk"]) and np.array_equal(pred["values"], tr["values"])
+    assert np.array_equal(pred["tile_key"], tr["tile_l1"] * 4096 + tr["tile_n1"])
+    assert np.array_equal(pred["tile_origin"], tr["tile_origin"])
+    assert np.array_equal(pred["tile_value"], tr["tile_value"])
+    # without a tile regressor no tiles come out
+    assert len(F.topology_from_decisions(tr, cls, active, values)["tile_key"]) == 0
+    # the first tile predicted as an inactive tile
+    cls2 = cls.copy()
+    cls2[pred["tile_key"][0]] = 2
+    pred2 = F.topology_from_decisions(tr, cls2, active, values, tiles)
+    assert np.array_equal(pred2["tile_key"], pred["tile_key"][1:])
+    # planted tile value errors
+    that = tr["tile_value"].copy()
+    that[1] += 0.25
+    that[2] -= 0.125
+    rep = F.errors_tiles(tr, that)
+    assert rep["n"] == len(that) and rep["max_abs"] == 0.25
+    assert np.isclose(rep["rms"], np.sqrt((0.0625 + 0.015625) / len(that)))

@@ -170,3 +170,82 @@ def test_active_set_sparse_rule_and_order():
         pts = np.array([[i + org[0], j + org[1], k + org[2]] for i in range(6) for j in range(5) for k in range(7)])
         got, _ = T.active_set_sparse(pts, grid.reshape(-1), kind, thr)
         assert set(map(tuple, got.tolist())) == ref
+
+
+# ---------------------------------------------------------------- active tiles (Sec. 3.3.1)
+def _block(origin, value=0.75):
+    o = np.asarray(origin, np.int64)
+    off = np.stack(np.meshgrid(np.arange(8), np.arange(8), np.arange(8), indexing="ij"), -1).reshape(-1, 3)
+    return o + off, np.full(512, value, np.float64)
+
+
+def _tile_case():
+    """Four leaf-sized blocks: A (0,0,0) full and constant; B (8,0,0) full with one
+    voxel of another value; C (16,0,0) constant with one voxel missing; D (0,128,0),
+    in a second level-1 node, full and constant."""
+    a, va = _block((0, 0, 0), 0.75)
+    b, vb = _block((8, 0, 0), 0.75)
+    vb[100] = 0.5
+    c, vc = _block((16, 0, 0), 0.75)
+    c, vc = c[1:], vc[1:]
+    d, vd = _block((0, 128, 0), 1.0)
+    return np.concatenate([a, b, c, d]).astype(np.int32), np.concatenate([va, vb, vc, vd])
+
+
+def test_prune_tiles_hand_case():
+    ijk, v = _tile_case()
+    tr = T.prune_tiles(T.build(ijk, v))
+    # two tiles (A, D) in canonical order, two leaves (B, C) left
+    assert tr["tile_origin"].tolist() == [[0, 0, 0], [0, 128, 0]]
+    assert tr["tile_value"].tolist() == [0.75, 1.0]
+    assert tr["tile_n1"].tolist() == [0, 0]
+    assert tr["tile_l1"].tolist() == [0, 1]
+    assert tr["leaf_origin"].tolist() == [[8, 0, 0], [16, 0, 0]]
+    assert len(tr["values"]) == 512 + 511 and tr["leaf_off"].tolist() == [0, 512, 1023]
+    assert tr["vox_leaf"].tolist() == [0] * 512 + [1] * 511
+    # level-1 node 0 (origin 0): children at n1 = 1 << 8 (x = 8) and 2 << 8 (x = 16), tile at n1 = 0;
+    # node 1 (origin (0,128,0)): no child, a tile at n1 = 0
+    assert tr["l1_origin"].tolist() == [[0, 0, 0], [0, 128, 0]]
+    child = {(int(n), int(b)) for n in range(2) for b in range(4096) if T.mask_bits(tr["l1_child"], n, b)}
+    active = {(int(n), int(b)) for n in range(2) for b in range(4096) if T.mask_bits(tr["l1_active"], n, b)}
+    assert child == {(0, 256), (0, 512)}
+    assert active == {(0, 0), (1, 0)}
+    # a tree without constant full leaves is unchanged
+    tr0 = T.build(ijk[512:512 + 1023], v[512:512 + 1023])
+    tp = T.prune_tiles(tr0)
+    assert len(tp["tile_value"]) == 0 and np.array_equal(tp["values"], tr0["values"])
+    assert np.array_equal(tp["l1_child"], tr0["l1_child"])
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_prune_tiles_is_lossless(seed):
+    """Expanding every tile back into its 512 voxels gives the original active set
+    and values exactly, and no kept leaf is full and constant."""
+    rng = np.random.default_rng(seed)
+    ijk = random_sparse(rng, 3000, 60)
+    vals = rng.choice([0.25, 0.5], size=len(ijk))
+    blocks = [_block(tuple(int(c) for c in 8 * rng.integers(-8, 8, 3)), float(rng.choice([0.25, 1.0])))
+              for _ in range(6)]
+    pts = {tuple(p): float(x) for p, x in zip(ijk.tolist(), vals)}
+    for bi, bv in blocks:
+        for p, x in zip(bi.tolist(), bv):
+            pts[tuple(p)] = x
+    keys = sorted(pts)
+    ijk = np.array(keys, np.int32)
+    v = np.array([pts[k] for k in keys])
+    tr = T.prune_tiles(T.build(ijk, v))
+    assert len(tr["tile_value"]) >= 1
+    back = {tuple(p): float(x) for p, x in zip(tr["ijk"].tolist(), tr["values"])}
+    for o, x in zip(tr["tile_origin"], tr["tile_value"]):
+        bi, bv = _block(o, x)
+        for p in bi.tolist():
+            assert tuple(p) not in back
+            back[tuple(p)] = x
+    assert back == pts
+    for i in range(len(tr["leaf_origin"])):
+        seg = tr["values"][tr["leaf_off"][i]:tr["leaf_off"][i + 1]]
+        assert not (len(seg) == 512 and np.all(seg == seg[0]))
+    # every tile sits at an active-tile bit, no child bit there
+    for n, b in zip(tr["tile_l1"], tr["tile_n1"]):
+        assert T.mask_bits(tr["l1_active"], n, b) == 1 and T.mask_bits(tr["l1_child"], n, b) == 0
+    assert int(T.popcount64(tr["l1_active"]).sum()) == len(tr["tile_value"])

@@ -8,5 +8,5 @@ procedural volumes here stand in for its scanned level sets, density clouds
 and simulated sequences.
 """
 from .volumes import (sphere_sdf, two_spheres_sdf, noise_sphere_sdf, fbm_cloud, water_frame,  # noqa: F401
-                      gradient_noise, fbm)
+                      saturated_fog, gradient_noise, fbm)
 from .params import init_params, ffm_matrix, pe_matrix, epoch_permutation, net_shapes  # noqa: F401

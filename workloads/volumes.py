@@ -113,6 +113,21 @@ def fbm_cloud(n=1024, octaves=6, scale=256.0, seed=7, device="cpu", chunk=16):
     return out
 
 
+def saturated_fog(n=64, center=(32.0, 32.0, 32.0), radius=24.0, gain=3.0, amplitude=0.3, scale=16.0, seed=5,
+                  device="cpu", chunk=32):
+    """Density clamp(gain (1 - |p - c| / R) + amplitude fbm(p / scale), 0, 1) on an n^3
+    lattice (fog volume): a noisy ball whose core saturates at exactly 1, so the
+    leaves inside the core are constant."""
+    out = torch.empty((n, n, n), dtype=torch.float32, device=device)
+    for x0 in range(0, n, chunk):
+        nx = min(chunk, n - x0)
+        x, y, z = _grid((nx, n, n), device, (x0, 0, 0))
+        p = torch.stack([x, y, z], -1)
+        d = torch.sqrt((x - center[0]) ** 2 + (y - center[1]) ** 2 + (z - center[2]) ** 2)
+        out[x0:x0 + nx] = (gain * (1.0 - d / radius) + amplitude * fbm(p / scale, 3, seed)).clamp(0.0, 1.0)
+    return out
+
+
 def water_frame(t, nx=1024, ny=256, nz=1024, speed=8.0, base=128.0, amp=24.0, scale=128.0,
                 wet0=288.0, wet1=1024.0, n_frames=16, seed=3, device="cpu", outside=100.0):
     """Frame t of an advected noisy water surface, as a signed distance in voxel units.
