@@ -161,18 +161,18 @@ def build(ijk, values):
 
 
 def prune_tiles(tr):
-    """Replace every leaf whose 512 voxels are all active and share one value by an
-    active tile of its level-1 node (a constant leaf-sized region that carries one
-    value and no leaf node: the active tiles of Sec. 3.3.1, whose values the tile
-    value regressor encodes).  The level-1 and upper nodes stay as they are; the
+    """Replace every leaf whose 512 voxels are all active and share one value (bit for
+    bit) by an active tile of its level-1 node (a constant leaf-sized region that
+    carries one value and no leaf node: the active tiles of Sec. 3.3.1, whose values
+    the tile value regressor encodes).  The level-1 and upper nodes stay as they are; the
     tile's child bit is cleared and its active-tile bit set.  Tiles keep the
     canonical order of the leaves they replace, i.e. (level-1 node, n1)."""
     L = len(tr["leaf_origin"])
     full = np.all(tr["leaf_mask"] == np.uint64(0xFFFFFFFFFFFFFFFF), axis=1) if L else np.zeros(0, bool)
     const = np.zeros(L, bool)
-    for i in np.nonzero(full)[0]:
+    for i in np.nonzero(full)[0]:   # one value: identical bit for bit (+0 and -0 differ)
         v = tr["values"][tr["leaf_off"][i]:tr["leaf_off"][i + 1]]
-        const[i] = bool(np.all(v == v[0]))
+        const[i] = bool(np.all(v == v[0]) and np.all(np.signbit(v) == np.signbit(v[0])))
     tile = full & const
     keep = ~tile
     vox_keep = keep[tr["vox_leaf"]] if len(tr["values"]) else np.zeros(0, bool)

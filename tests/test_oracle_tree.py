@@ -210,6 +210,13 @@ def test_prune_tiles_hand_case():
     active = {(int(n), int(b)) for n in range(2) for b in range(4096) if T.mask_bits(tr["l1_active"], n, b)}
     assert child == {(0, 256), (0, 512)}
     assert active == {(0, 0), (1, 0)}
+    # +0 and -0 are different values: such a leaf stays a leaf
+    e, ve = _block((0, 0, 256), 0.0)
+    ve[7] = -0.0
+    te = T.prune_tiles(T.build(e.astype(np.int32), ve))
+    assert len(te["tile_value"]) == 0 and len(te["leaf_origin"]) == 1
+    te = T.prune_tiles(T.build(e.astype(np.int32), np.zeros(512)))
+    assert len(te["tile_value"]) == 1 and len(te["leaf_origin"]) == 0 and len(te["values"]) == 0
     # a tree without constant full leaves is unchanged
     tr0 = T.build(ijk[512:512 + 1023], v[512:512 + 1023])
     tp = T.prune_tiles(tr0)
