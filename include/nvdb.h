@@ -44,7 +44,7 @@ enum {
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* nvdb_last_error(void);
-/* ABI version of this header (increments on incompatible changes). */
+/* ABI version of this header (increments on incompatible changes): 2. */
 int32_t nvdb_abi_version(void);
 
 typedef struct nvdb_tree nvdb_tree;
@@ -67,6 +67,7 @@ typedef struct {
   int32_t grid_origin[3];   /* index-space origin of the source grid        */
   int32_t grid_dims[3];     /* extent of the source grid                    */
   int64_t bytes_l2, bytes_l1, bytes_leaf_masks, bytes_voxels; /* Tab. memory_cost accounting */
+  int64_t n_tiles;          /* active tiles at level 1 (nvdb_tree_prune_tiles) */
 } nvdb_tree_info;
 
 /* Build the [Hash,5,4,3] tree (Sec. 3.1) of a dense grid resident in HBM.
@@ -98,6 +99,21 @@ nvdb_status nvdb_tree_build_sparse(const int32_t* ijk_dev, const float* values_d
                                    const nvdb_active_rule* rule, void* stream, nvdb_tree** out);
 /* Counts, bounding grid and byte accounting of a tree. */
 nvdb_status nvdb_tree_get_info(const nvdb_tree* tree, nvdb_tree_info* info);
+/* Active tiles (Sec. 3.3.1: the level-1 entries that hold one value for a whole
+ * leaf-sized region, whose values the tile value regressor encodes).  Returns a
+ * new tree (free with nvdb_tree_free) in which every leaf of `in` whose 512
+ * voxels are all active and bit-equal is replaced by an active tile of its
+ * level-1 node: the leaf and its voxels leave the leaf and voxel arrays (the
+ * rest keep their canonical order), the tile's child bit is cleared and its
+ * active-tile bit set; level-1 and upper nodes are unchanged.  Tiles are kept in
+ * canonical order, (level-1 node, n1); a tree without full constant leaves yields
+ * a copy without tiles.  Synchronises `stream`.  Errors: E_INVALID (null
+ * argument, a tree that already has tiles, 2^20 or more level-1 nodes). */
+nvdb_status nvdb_tree_prune_tiles(const nvdb_tree* in, void* stream, nvdb_tree** out);
+/* The active tiles of a tree to host buffers (any may be NULL): tile_key
+ * uint32[T] = level-1 node index << 12 | n1, tile_value float32[T], l1_active
+ * uint64[n_l1][64] (bit n1 of node k in word n1>>6 at n1&63). */
+nvdb_status nvdb_tree_export_tiles(const nvdb_tree* tree, uint32_t* tile_key, float* tile_value, uint64_t* l1_active);
 /* Copy the canonical arrays to host buffers (any may be NULL):
  * leaf_origin int32[L][3], leaf_mask uint64[L][8], leaf_off uint32[L+1]
  * (exclusive prefix of active counts), values float32[N] (leaf-major, n0
@@ -113,10 +129,11 @@ void nvdb_tree_free(nvdb_tree* tree);
 
 /* ----------------------------------------------------------------- models */
 /* Networks of a NeuralVDB (Sec. 3.2, 3.3.1): the voxel-value regressor
- * (MSE, eq. mse), the level-0 active-mask classifier (binary cross-entropy)
- * and the level-1 node classifier (three-class cross-entropy: child, active
- * tile, inactive tile). */
-enum { NVDB_NET_REGRESSOR = 0, NVDB_NET_L0 = 1, NVDB_NET_L1 = 2, NVDB_MAX_NETS = 3 };
+ * (MSE, eq. mse), the level-0 active-mask classifier (binary cross-entropy),
+ * the level-1 node classifier (three-class cross-entropy: child, active tile,
+ * inactive tile) and the tile value regressor (MSE over the active tiles at
+ * their leaf-slot centres, target scaled as the voxel regressor's). */
+enum { NVDB_NET_REGRESSOR = 0, NVDB_NET_L0 = 1, NVDB_NET_L1 = 2, NVDB_NET_TILE = 3, NVDB_MAX_NETS = 4 };
 /* Arithmetic of the matrix products: FP32 (fp32 MFMA), or BF16 operands with
  * FP32 accumulation.  Master weights, moments and losses are FP32 in both. */
 enum { NVDB_FP32 = 0, NVDB_BF16 = 1 };
@@ -345,6 +362,12 @@ nvdb_status nvdb_decode_l1(const nvdb_model* model, const nvdb_tree* tree, uint8
 nvdb_status nvdb_decode_fp8(const nvdb_model* model, const nvdb_tree* tree, float* values_dev, uint64_t* pred_mask_dev,
                             void* stream);
 nvdb_status nvdb_decode_l1_fp8(const nvdb_model* model, const nvdb_tree* tree, uint8_t* classes_dev, void* stream);
+/* Tile value regressor at every active tile of the tree (leaf-slot centres, in
+ * the tree's tile order): tile_values_dev float32[T] receives y * value_scale.
+ * fp8 != 0 runs the FP8 form.  Asynchronous.  Errors: E_INVALID (no tile
+ * regressor in the model), E_STATE (its parameters or encoding unset). */
+nvdb_status nvdb_decode_tiles(const nvdb_model* model, const nvdb_tree* tree, int32_t fp8, float* tile_values_dev,
+                              void* stream);
 
 /* Error report (Sec. 4): max |v^ - v| and RMS over the true active voxels in
  * value units; IoU of the interiors {v <= 0} over the active set (level sets);
@@ -359,6 +382,10 @@ typedef struct {
 } nvdb_error_report;
 nvdb_status nvdb_errors(const nvdb_tree* tree, const float* values_dev, const uint64_t* pred_mask_dev,
                         nvdb_error_report* out, void* stream);
+/* max |t^ - t| and RMS over the active tiles of the tree (value units) into
+ * out->n, max_abs, rms (iou -1, fp = fn = 0).  Synchronises `stream`. */
+nvdb_status nvdb_errors_tiles(const nvdb_tree* tree, const float* tile_values_dev, nvdb_error_report* out,
+                              void* stream);
 /* Full decode of the lower tree levels (Sec. 3.3, 3.5): the level-1 classifier
  * predicts, for every leaf slot of the level-1 nodes of `upper` (whose upper
  * levels are stored explicitly), which slots hold a leaf (a model without the
@@ -371,7 +398,10 @@ nvdb_status nvdb_errors(const nvdb_tree* tree, const float* values_dev, const ui
  * voxel its value.  The result is a new tree (free with nvdb_tree_free) with
  * the predicted leaves in canonical order, their masks, voxel values and the
  * predicted level-1 child / tile masks; it keeps every level-1 node of
- * `upper`.  fp8 != 0 runs the networks in the FP8 form.  Synchronises `stream`.
+ * `upper`.  With a tile value regressor in the model, every slot of the
+ * active-tile class becomes an active tile of the result, in canonical order,
+ * valued by that regressor at the slot's leaf centre (the top-down traversal of
+ * Sec. 3.3.1); without one the result holds the active-tile bits but no tiles.  fp8 != 0 runs the networks in the FP8 form.  Synchronises `stream`.
  * Errors: E_STATE (a needed network missing or unset), E_INVALID. */
 nvdb_status nvdb_decode_topology(const nvdb_model* model, const nvdb_tree* upper, int32_t fp8, nvdb_tree** out,
                                  void* stream);

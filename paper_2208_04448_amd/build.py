@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnvdb.so")
-SOURCES = ["mlp.hip", "train_rows.hip", "tree.hip", "sparse.hip", "query.hip", "moe.hip", "archive.hip", "api.hip"]
+SOURCES = ["mlp.hip", "train_rows.hip", "tree.hip", "sparse.hip", "query.hip", "moe.hip", "archive.hip", "tiles.hip",
+           "api.hip"]
 # Per-source code generation: the activation-rows training kernel puts matrix-product
 # results in general-purpose vector registers (its weight gradients are pinned to the
 # accumulation registers by operand constraints).

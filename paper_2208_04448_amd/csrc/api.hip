@@ -92,6 +92,8 @@ static TreeView tree_view(const Tree* t) {
   v.leaf_o = t->leaf_o.p;
   v.leaf_mask = t->leaf_mask.p;
   v.vox_key = t->vox_key.p;
+  v.tile_key = t->tile_key.p;
+  v.tile_val = t->tile_val.p;
   v.values = t->values.p;
   v.l1_o = t->l1_o.p;
   v.l1_child = t->l1_child.p;
@@ -175,7 +177,7 @@ static void ensure_partials(Net& n, int G) {
 extern "C" {
 
 const char* nvdb_last_error(void) { return g_err.c_str(); }
-int32_t nvdb_abi_version(void) { return 1; }
+int32_t nvdb_abi_version(void) { return 2; }
 
 // ------------------------------------------------------------------ trees
 nvdb_status nvdb_tree_build_dense(const float* grid_dev, const int32_t dims[3], const int32_t origin[3],
@@ -215,6 +217,28 @@ nvdb_status nvdb_tree_get_info(const nvdb_tree* t, nvdb_tree_info* info) {
     info->bytes_l1 = t->n_l1 * (2 * (4096 / 8) + 4096 * 4 + 12);
     info->bytes_leaf_masks = t->n_leaf * (512 / 8 + 12);
     info->bytes_voxels = t->n_leaf * 512 * 4;
+    info->n_tiles = t->n_tile;
+  });
+}
+
+nvdb_status nvdb_tree_prune_tiles(const nvdb_tree* in, void* stream, nvdb_tree** out) {
+  return guarded([&] {
+    NVDB_REQUIRE(in && out, NVDB_E_INVALID, "null argument");
+    *out = nullptr;
+    Tree* t = prune_tiles(*in, (hipStream_t)stream);
+    *out = static_cast<nvdb_tree*>(t);
+  });
+}
+
+nvdb_status nvdb_tree_export_tiles(const nvdb_tree* t, uint32_t* tile_key, float* tile_value, uint64_t* l1_active) {
+  return guarded([&] {
+    NVDB_REQUIRE(t, NVDB_E_INVALID, "null tree");
+    if (tile_key && t->n_tile)
+      NVDB_HIP(hipMemcpy(tile_key, t->tile_key.p, t->n_tile * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (tile_value && t->n_tile)
+      NVDB_HIP(hipMemcpy(tile_value, t->tile_val.p, t->n_tile * sizeof(float), hipMemcpyDeviceToHost));
+    if (l1_active && t->n_l1)
+      NVDB_HIP(hipMemcpy(l1_active, t->l1_active.p, t->n_l1 * 64 * sizeof(uint64_t), hipMemcpyDeviceToHost));
   });
 }
 
@@ -517,6 +541,10 @@ static int population_src(int net, const Tree* t, int64_t* pop) {
     *pop = 512 * t->n_leaf;
     return SRC_LEAF_SLOTS;
   }
+  if (net == NVDB_NET_TILE) {
+    *pop = t->n_tile;
+    return SRC_TILES;
+  }
   *pop = 4096 * t->n_l1;
   return SRC_L1_SLOTS;
 }
@@ -607,7 +635,7 @@ static void fill_train_net(nvdb_model* m, const Tree* tree, int k, const Phase& 
   base_spec(m, &tn.spec);
   int64_t pop;
   tn.spec.src = population_src(k, tree, &pop);
-  tn.spec.loss = k == NVDB_NET_REGRESSOR ? LOSS_MSE : (k == NVDB_NET_L0 ? LOSS_BCE : LOSS_CE);
+  tn.spec.loss = (k == NVDB_NET_REGRESSOR || k == NVDB_NET_TILE) ? LOSS_MSE : (k == NVDB_NET_L0 ? LOSS_BCE : LOSS_CE);
   tn.spec.npop = (uint32_t)pop;
   int64_t n = ph.batch;
   if (ph.idx && ph.idx->idx_dev[k]) {
@@ -1274,7 +1302,38 @@ static void decode_l1_impl(const nvdb_model* m, const nvdb_tree* tree, uint8_t* 
   run_infer(m, N, tree, SRC_L1_SLOTS, 4096 * tree->n_l1, I, fp8, st);
 }
 
+// The tile value regressor at every active tile of `tree`, in value units.
+static void decode_tiles_impl(const nvdb_model* m, const nvdb_tree* tree, float* values_dev, bool fp8,
+                              hipStream_t st) {
+  NVDB_REQUIRE(m && tree, NVDB_E_INVALID, "null argument");
+  const Net& N = net_of(m, NVDB_NET_TILE);
+  NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "tile value regressor parameters or encoding not set");
+  if (tree->n_tile == 0) return;
+  NVDB_REQUIRE(values_dev, NVDB_E_INVALID, "null argument");
+  InferLaunch I{};
+  I.out_kind = OUT_VALUES;
+  I.out_scale = m->d.value_scale;
+  I.y = values_dev;
+  run_infer(m, N, tree, SRC_TILES, tree->n_tile, I, fp8, st);
+}
+
 extern "C" {
+
+nvdb_status nvdb_decode_tiles(const nvdb_model* m, const nvdb_tree* tree, int32_t fp8, float* tile_values_dev,
+                              void* stream) {
+  return guarded([&] {
+    decode_tiles_impl(m, tree, tile_values_dev, fp8 != 0, (hipStream_t)stream);
+    mark(m, (hipStream_t)stream);
+  });
+}
+
+nvdb_status nvdb_errors_tiles(const nvdb_tree* tree, const float* tile_values_dev, nvdb_error_report* out,
+                              void* stream) {
+  return guarded([&] {
+    NVDB_REQUIRE(tree && out && (tile_values_dev || tree->n_tile == 0), NVDB_E_INVALID, "null argument");
+    error_report_tiles(*tree, tile_values_dev, out, (hipStream_t)stream);
+  });
+}
 
 nvdb_status nvdb_decode(const nvdb_model* m, const nvdb_tree* tree, float* values_dev, uint64_t* pred_mask_dev,
                         void* stream) {
@@ -1367,6 +1426,13 @@ static nvdb_tree* decode_topology_impl(const nvdb_model* m, const nvdb_tree* upp
       t->leaf_mask.alloc(std::max<int64_t>(t->n_leaf, 1) * 8);
       t->leaf_off.alloc(t->n_leaf + 1);
       if (n_slots > 0) pred_leaves(cls.p, prefix.p, t->l1_o.p, n_slots, t->leaf_o.p, t->l1_child.p, t->l1_active.p, st);
+      // active tiles: the slots of the active-tile class, valued by the tile regressor
+      const Net& TR = m->nets[NVDB_NET_TILE];
+      if (TR.present) {
+        NVDB_REQUIRE(TR.params_set && TR.enc_set, NVDB_E_STATE, "tile value regressor parameters or encoding not set");
+        tiles_from_classes(cls.p, n_slots, t, st);
+        decode_tiles_impl(m, t, t->tile_val.p, use_fp8, st);
+      }
       // level 0: voxel masks
       DevBuf<float> slot_y;
       if (masks_given) {

@@ -241,17 +241,23 @@ __device__ __forceinline__ Smp fetch_sample(const SampleSpec& sp, const TreeView
     py = o.y + (int)((n0 >> 3) & 7u);
     pz = o.z + (int)(n0 & 7u);
     if (!sp.direct) s.t = (float)((tv.leaf_mask[(size_t)leaf * 8 + (n0 >> 6)] >> (n0 & 63u)) & 1ull);
-  } else {  // SRC_L1_SLOTS: leaf centres of every slot of the level-1 nodes
-    uint32_t node = g >> 12, n1 = g & 4095u;
+  } else {  // SRC_L1_SLOTS (every slot of the level-1 nodes) or SRC_TILES: leaf centres
+    const bool tile = sp.src == SRC_TILES;
+    const uint32_t key = tile ? tv.tile_key[g] : g;
+    uint32_t node = key >> 12, n1 = key & 4095u;
     int4 o = tv.l1_o[node];
     px = o.x + 8 * (int)(n1 >> 8);
     py = o.y + 8 * (int)((n1 >> 4) & 15u);
     pz = o.z + 8 * (int)(n1 & 15u);
     half = 4.f;
     if (!sp.direct) {
-      const uint64_t c = (tv.l1_child[(size_t)node * 64 + (n1 >> 6)] >> (n1 & 63u)) & 1ull;
-      const uint64_t a = (tv.l1_active[(size_t)node * 64 + (n1 >> 6)] >> (n1 & 63u)) & 1ull;
-      s.cls = c ? 0 : (a ? 1 : 2);
+      if (tile) {
+        s.t = tv.tile_val[g] * sp.tscale;
+      } else {
+        const uint64_t c = (tv.l1_child[(size_t)node * 64 + (n1 >> 6)] >> (n1 & 63u)) & 1ull;
+        const uint64_t a = (tv.l1_active[(size_t)node * 64 + (n1 >> 6)] >> (n1 & 63u)) & 1ull;
+        s.cls = c ? 0 : (a ? 1 : 2);
+      }
     }
   }
   s.x[0] = ((float)(px - sp.lo[0]) + half) * sp.inv_d;

@@ -77,12 +77,15 @@ struct Tree {
   DevBuf<uint32_t> vox_key;    // [N] leaf << 9 | n0
   DevBuf<int4> l1_o;           // [n_l1]
   DevBuf<uint64_t> l1_child;   // [n_l1][64]
-  DevBuf<uint64_t> l1_active;  // [n_l1][64] (all zero for trees built from voxels)
+  DevBuf<uint64_t> l1_active;  // [n_l1][64] (zero unless the tree has active tiles)
   std::vector<int32_t> l2_origin;  // host, [n_l2][3]
+  int64_t n_tile = 0;          // active tiles (prune_tiles, or a decoded topology)
+  DevBuf<uint32_t> tile_key;   // [n_tile] level-1 node << 12 | n1, canonical order
+  DevBuf<float> tile_val;      // [n_tile]
 };
 
 // ------------------------------------------------------------- sampling
-enum SampleSource : int32_t { SRC_VOXELS = 0, SRC_LEAF_SLOTS = 1, SRC_L1_SLOTS = 2, SRC_COORDS = 3 };
+enum SampleSource : int32_t { SRC_VOXELS = 0, SRC_LEAF_SLOTS = 1, SRC_L1_SLOTS = 2, SRC_COORDS = 3, SRC_TILES = 4 };
 enum LossKind : int32_t { LOSS_MSE = 0, LOSS_BCE = 1, LOSS_CE = 2, LOSS_EXTERNAL = 3 };
 
 constexpr uint64_t SM_GOLDEN = 0x9E3779B97F4A7C15ull;
@@ -112,6 +115,8 @@ struct TreeView {
   const int4* l1_o;
   const uint64_t* l1_child;
   const uint64_t* l1_active;
+  const uint32_t* tile_key;  // active tiles: level-1 node << 12 | n1
+  const float* tile_val;
 };
 
 struct SampleSpec {
@@ -374,6 +379,12 @@ void error_report(const Tree& t, const float* values, const uint64_t* pred_mask,
                   hipStream_t st);
 void error_report_l1(const Tree& t, const uint8_t* classes, nvdb_l1_report* rep, hipStream_t st);
 uint64_t scan_u64(const uint64_t* in, int64_t n, uint64_t* out, hipStream_t st);  // exclusive; returns the total
+// Active tiles (tiles.hip): the pruned copy of a tree; the predicted tiles of a
+// decoded topology (class-1 slots of cls, n_slots = 4096 n_l1) into t->tile_key;
+// the error report over a tree's tiles.
+Tree* prune_tiles(const Tree& in, hipStream_t st);
+void tiles_from_classes(const uint8_t* cls, int64_t n_slots, Tree* t, hipStream_t st);
+void error_report_tiles(const Tree& t, const float* pred, nvdb_error_report* rep, hipStream_t st);
 void pred_flags(const uint8_t* cls, int64_t n, uint64_t* flag, hipStream_t st);
 void pred_leaves(const uint8_t* cls, const uint64_t* prefix, const int4* l1_o, int64_t n, int4* leaf_o, uint64_t* child,
                  uint64_t* active, hipStream_t st);

@@ -457,6 +457,31 @@ void error_report(const Tree& t, const float* values, const uint64_t* pred_mask,
   rep->fn = (int64_t)fn;
 }
 
+// The same maxima and RMS over the active tiles of a tree (no IoU, no masks).
+void error_report_tiles(const Tree& t, const float* pred, nvdb_error_report* rep, hipStream_t st) {
+  const int nblk = 64;
+  DevBuf<ErrPartial> part;
+  part.alloc(nblk);
+  NVDB_HIP(hipMemsetAsync(part.p, 0, nblk * sizeof(ErrPartial), st));
+  std::vector<ErrPartial> h(nblk);
+  if (t.n_tile > 0) {
+    hipLaunchKernelGGL(k_err_values, dim3(nblk), dim3(256), 0, st, t.tile_val.p, pred, t.n_tile, (int)NVDB_FOG, part.p);
+    NVDB_HIP(hipGetLastError());
+  }
+  NVDB_HIP(hipMemcpyAsync(h.data(), part.p, nblk * sizeof(ErrPartial), hipMemcpyDeviceToHost, st));
+  NVDB_HIP(hipStreamSynchronize(st));
+  double sq = 0.0, mx = 0.0;
+  for (int i = 0; i < nblk; ++i) {
+    sq += h[i].sq;
+    mx = std::max(mx, (double)h[i].max_abs);
+  }
+  rep->n = t.n_tile;
+  rep->max_abs = mx;
+  rep->rms = t.n_tile > 0 ? std::sqrt(sq / (double)t.n_tile) : 0.0;
+  rep->iou = -1.0;
+  rep->fp = rep->fn = 0;
+}
+
 // ----------------------------------------------------------------- predicted topology
 uint64_t scan_u64(const uint64_t* in, int64_t n, uint64_t* out, hipStream_t st) {
   if (n == 0) return 0;

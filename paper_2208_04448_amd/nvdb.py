@@ -17,7 +17,7 @@ _lib = C.CDLL(LIB_PATH)
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_NUMERIC, E_STATE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 SDF, FOG = 0, 1
-NET_REGRESSOR, NET_L0, NET_L1, MAX_NETS = 0, 1, 2, 3
+NET_REGRESSOR, NET_L0, NET_L1, NET_TILE, MAX_NETS = 0, 1, 2, 3, 4
 FP32, BF16 = 0, 1
 STORE_F16, STORE_BF16 = 0, 1
 
@@ -36,7 +36,7 @@ class TreeInfo(C.Structure):
     _fields_ = [("n_voxels", C.c_int64), ("n_leaves", C.c_int64), ("n_l1", C.c_int64), ("n_l2", C.c_int64),
                 ("grid_origin", C.c_int32 * 3), ("grid_dims", C.c_int32 * 3),
                 ("bytes_l2", C.c_int64), ("bytes_l1", C.c_int64), ("bytes_leaf_masks", C.c_int64),
-                ("bytes_voxels", C.c_int64)]
+                ("bytes_voxels", C.c_int64), ("n_tiles", C.c_int64)]
 
 
 class NetDesc(C.Structure):
@@ -45,18 +45,18 @@ class NetDesc(C.Structure):
 
 
 class ModelDesc(C.Structure):
-    _fields_ = [("precision", C.c_int32), ("has_net", C.c_int32 * 3), ("net", NetDesc * 3),
+    _fields_ = [("precision", C.c_int32), ("has_net", C.c_int32 * MAX_NETS), ("net", NetDesc * MAX_NETS),
                 ("domain_lo", C.c_int32 * 3), ("domain_size", C.c_int32), ("value_scale", C.c_float)]
 
 
 class FitDesc(C.Structure):
     _fields_ = [("steps", C.c_int32), ("batch", C.c_int32), ("seed", C.c_uint64), ("lr", C.c_float),
                 ("lr_decay", C.c_float), ("lr_interval", C.c_int32), ("nets_mask", C.c_int32),
-                ("idx_dev", C.c_void_p * 3), ("idx_count", C.c_int64 * 3), ("train_kernel_ms", C.c_void_p)]
+                ("idx_dev", C.c_void_p * MAX_NETS), ("idx_count", C.c_int64 * MAX_NETS), ("train_kernel_ms", C.c_void_p)]
 
 
 class FrameReport(C.Structure):
-    _fields_ = [("steps_run", C.c_int32 * 3), ("final_loss", C.c_float * 3)]
+    _fields_ = [("steps_run", C.c_int32 * MAX_NETS), ("final_loss", C.c_float * MAX_NETS)]
 
 
 class L1Report(C.Structure):
@@ -79,7 +79,7 @@ class TuneReport(C.Structure):
 
 class DecodeTuneReport(C.Structure):
     _fields_ = [("n_candidates", C.c_int32), ("net", C.c_int32 * TUNE_MAX), ("waves", C.c_int32 * TUNE_MAX),
-                ("tiles", C.c_int32 * TUNE_MAX), ("ms", C.c_float * TUNE_MAX), ("chosen", C.c_int32 * 3)]
+                ("tiles", C.c_int32 * TUNE_MAX), ("ms", C.c_float * TUNE_MAX), ("chosen", C.c_int32 * MAX_NETS)]
 
 
 class ErrorReport(C.Structure):
@@ -110,6 +110,10 @@ _SIGS = {
                                           C.POINTER(_P)]),
     "nvdb_tree_build_sparse": (C.c_int32, [_P, _P, C.c_int64, C.POINTER(ActiveRule), _P, C.POINTER(_P)]),
     "nvdb_tree_get_info": (C.c_int32, [_P, C.POINTER(TreeInfo)]),
+    "nvdb_tree_prune_tiles": (C.c_int32, [_P, _P, C.POINTER(_P)]),
+    "nvdb_tree_export_tiles": (C.c_int32, [_P, _P, _P, _P]),
+    "nvdb_decode_tiles": (C.c_int32, [_P, _P, C.c_int32, _P, _P]),
+    "nvdb_errors_tiles": (C.c_int32, [_P, _P, C.POINTER(ErrorReport), _P]),
     "nvdb_query": (C.c_int32, [_P, _P, _P, C.c_int64, C.c_float, C.c_int64, _P, _P, _P]),
     "nvdb_topology_patches": (C.c_int32, [_P, _P, _P, C.c_int64, _P, C.c_int64, C.POINTER(C.c_int64),
                                           C.POINTER(C.c_int64), _P]),
@@ -254,6 +258,24 @@ class Tree:
         _check(_lib.nvdb_tree_get_info(self.h, C.byref(i)))
         return i
 
+    def prune_tiles(self):
+        """New tree with every full, constant leaf replaced by an active tile of its level-1 node."""
+        h = C.c_void_p()
+        _check(_lib.nvdb_tree_prune_tiles(self.h, _stream(), C.byref(h)))
+        t = Tree.__new__(Tree)
+        t.h = h
+        t.kind = self.kind
+        return t
+
+    def export_tiles(self):
+        """Active tiles: keys uint32 [T] (level-1 node << 12 | n1), values float32 [T],
+        level-1 active-tile masks uint64 [n_l1, 64]."""
+        i = self.info()
+        k, v = np.zeros(i.n_tiles, np.uint32), np.zeros(i.n_tiles, np.float32)
+        a = np.zeros((i.n_l1, 64), np.uint64)
+        _check(_lib.nvdb_tree_export_tiles(self.h, *[o.ctypes.data_as(C.c_void_p) for o in (k, v, a)]))
+        return k, v, a
+
     def export(self):
         i = self.info()
         L, N, L1 = i.n_leaves, i.n_voxels, i.n_l1
@@ -273,7 +295,7 @@ class Tree:
 
 # ---------------------------------------------------------------------------- models
 class Model:
-    """Handle of a set of NeuralVDB networks (regressor, level-0, level-1)."""
+    """Handle of a set of NeuralVDB networks (regressor, level-0, level-1, tile values)."""
 
     def __init__(self, nets, precision=BF16, domain_lo=(0, 0, 0), domain_size=64, value_scale=1.0):
         """nets: {net_id: (width, hidden, n_freq, n_out[, sin_freq])}; sin_freq 0 (default) is ReLU."""
@@ -374,7 +396,7 @@ class Model:
         r = DecodeTuneReport()
         _check(_lib.nvdb_autotune_decode(self.h, tree.h, nets_mask, reps, C.byref(r), _stream()))
         cand = [(r.net[i], r.waves[i], r.tiles[i], r.ms[i]) for i in range(r.n_candidates)]
-        return {k: r.chosen[k] for k in range(3) if (nets_mask >> k) & 1}, cand
+        return {k: r.chosen[k] for k in range(MAX_NETS) if (nets_mask >> k) & 1}, cand
 
     def set_decode_shape(self, net, index):
         _check(_lib.nvdb_model_set_decode_shape(self.h, int(net), int(index)))
@@ -425,6 +447,13 @@ class Model:
         out = torch.empty((i.n_l1, 4096), dtype=torch.uint8, device="cuda")
         f = _lib.nvdb_decode_l1_fp8 if fp8 else _lib.nvdb_decode_l1
         _check(f(self.h, tree.h, _ptr(out), _stream()))
+        return out
+
+    def decode_tiles(self, tree, fp8=False):
+        """Tile value regressor at every active tile of `tree` (value units, device float32 [T])."""
+        import torch
+        out = torch.empty(tree.info().n_tiles, dtype=torch.float32, device="cuda")
+        _check(_lib.nvdb_decode_tiles(self.h, tree.h, int(bool(fp8)), _ptr(out), _stream()))
         return out
 
     def decode_topology(self, upper, fp8=False):
@@ -529,6 +558,12 @@ def errors(tree, values, pred_mask=None):
     r = ErrorReport()
     _check(_lib.nvdb_errors(tree.h, _ptr(values), _ptr(pred_mask), C.byref(r), _stream()))
     return dict(n=r.n, max_abs=r.max_abs, rms=r.rms, iou=r.iou, fp=r.fp, fn=r.fn)
+
+
+def errors_tiles(tree, tile_values):
+    r = ErrorReport()
+    _check(_lib.nvdb_errors_tiles(tree.h, _ptr(tile_values), C.byref(r), _stream()))
+    return dict(n=r.n, max_abs=r.max_abs, rms=r.rms)
 
 
 def errors_l1(tree, classes):

@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol(nvdb):
 
 
 def test_version_and_error_string(nvdb):
-    assert nvdb._lib.nvdb_abi_version() == 1
+    assert nvdb._lib.nvdb_abi_version() == 2
     d = nvdb.ModelDesc()
     d.precision = 9
     h = C.c_void_p()

@@ -1,0 +1,200 @@
+"""GPU parity of the active tiles and the tile value regressor (Sec. 3.3.1)
+against the oracle: pruning bit for bit, training losses, tile decode, the tile
+error report and the top-down decode with tiles.  Tolerances as in
+test_gpu_parity (FP32 losses 1e-5 relative, BF16 2e-2; FP32 forward
+1e-6 (1 + |y|), BF16 forward 2e-3 (1 + |y|); FP8 3e-2)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import fit as F, mlp, tree as T
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+THR = 0.05
+
+
+def _fog(n):
+    c = n / 2.0
+    return workloads.saturated_fog(n=n, center=(c, c + 3.0, c - 2.0), radius=0.44 * n, scale=n / 4.0)
+
+
+def _pair(gpu_lib, v, origin=(0, 0, 0)):
+    tr = gpu_lib.Tree(v.to(DEV), origin, T.FOG, THR).prune_tiles()
+    ot = T.prune_tiles(T.build(*T.active_set_dense(v.numpy(), origin, T.FOG, THR)))
+    return tr, ot
+
+
+def _assert_same(tr, ot):
+    ex, i = tr.export(), tr.info()
+    assert (i.n_voxels, i.n_leaves, i.n_l1, i.n_tiles) == (len(ot["values"]), len(ot["leaf_origin"]),
+                                                           len(ot["l1_origin"]), len(ot["tile_value"]))
+    assert np.array_equal(ex["leaf_origin"], ot["leaf_origin"])
+    assert np.array_equal(ex["leaf_mask"], ot["leaf_mask"])
+    assert np.array_equal(ex["leaf_off"].astype(np.int64), ot["leaf_off"])
+    assert np.array_equal(ex["values"].astype(np.float64), ot["values"])
+    assert np.array_equal(ex["l1_child"], ot["l1_child"])
+    k, val, act = tr.export_tiles()
+    assert np.array_equal(k.astype(np.int64), ot["tile_l1"] * 4096 + ot["tile_n1"])
+    assert np.array_equal(val.astype(np.float64), ot["tile_value"])
+    assert np.array_equal(act, ot["l1_active"])
+
+
+@pytest.fixture(scope="module")
+def fog(gpu_lib):
+    return _pair(gpu_lib, _fog(128))
+
+
+@pytest.fixture(scope="module")
+def terraces(gpu_lib):
+    """Fog rounded down to quarters: active tiles of three different values."""
+    v = workloads.saturated_fog(n=128, center=(64.0, 67.0, 62.0), radius=56.3, scale=32.0, levels=4, gain=1.1,
+                                amplitude=0.05)
+    return _pair(gpu_lib, v)
+
+
+def test_prune_tiles_matches_oracle(gpu_lib, fog):
+    tr, ot = fog
+    print("fog 128^3: %d voxels, %d leaves, %d tiles" % (len(ot["values"]), len(ot["leaf_origin"]),
+                                                        len(ot["tile_value"])))
+    assert len(ot["tile_value"]) >= 100
+    _assert_same(tr, ot)
+
+
+def test_prune_tiles_ragged_negative_origin(gpu_lib):
+    """A ragged grid at a negative origin spanning several level-1 and level-2 nodes."""
+    v = _fog(150)[:, 7:141, 3:].contiguous()
+    tr, ot = _pair(gpu_lib, v, origin=(-4100, 60, -97))
+    assert len(ot["tile_value"]) > 0 and len(ot["l2_origin"]) > 1
+    _assert_same(tr, ot)
+
+
+def test_prune_tiles_hand_and_edge_cases(gpu_lib):
+    """The hand-counted case of the oracle pins (two tiles, one in a level-1 node
+    left without leaves), a leaf of +0 and -0 values that stays a leaf, a tree
+    without tiles, the empty tree, and a second pruning (refused)."""
+    def block(o, value):
+        off = np.stack(np.meshgrid(*[np.arange(8)] * 3, indexing="ij"), -1).reshape(-1, 3)
+        return np.asarray(o) + off, np.full(512, value)
+    parts = [block((0, 0, 0), 0.75), block((8, 0, 0), 0.75), block((16, 0, 0), 0.75), block((0, 128, 0), 1.0),
+             block((0, 0, 256), 0.0)]
+    parts[1][1][100] = 0.5
+    parts[2] = (parts[2][0][1:], parts[2][1][1:])
+    parts[4][1][7] = -0.0
+    ijk = np.concatenate([p[0] for p in parts]).astype(np.int32)
+    val = np.concatenate([p[1] for p in parts]).astype(np.float32)
+    sdf_rule = (T.SDF, 10.0)   # every listed voxel is active (|v| <= 10)
+    tr = gpu_lib.Tree.from_sparse(torch.from_numpy(ijk).to(DEV), torch.from_numpy(val).to(DEV), *sdf_rule)
+    tp = tr.prune_tiles()
+    ot = T.prune_tiles(T.build(ijk, val.astype(np.float64)))
+    assert len(ot["tile_value"]) == 2
+    _assert_same(tp, ot)
+    with pytest.raises(gpu_lib.NvdbError):
+        tp.prune_tiles()
+    # a tree without constant full leaves: the same arrays, no tiles
+    v = workloads.sphere_sdf(n=40, center=(20.0, 21.0, 19.0), radius=12.0)
+    t0 = gpu_lib.Tree(v.to(DEV), (0, 0, 0), T.SDF, 2.0)
+    p0 = t0.prune_tiles()
+    assert p0.info().n_tiles == 0
+    a, b = t0.export(), p0.export()
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    # the empty tree
+    e = gpu_lib.Tree(torch.full((9, 10, 11), 50.0, device=DEV), (0, 0, 0), T.SDF, 3.0).prune_tiles()
+    i = e.info()
+    assert (i.n_voxels, i.n_leaves, i.n_tiles) == (0, 0, 0)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_tile_regressor_fit_decode_errors(gpu_lib, terraces, prec):
+    """Tile value regressor (3x64, positional encoding): i.i.d. SplitMix64 batches
+    over the tiles (three tile values), losses of 6 steps against the oracle
+    drawing the same indices; then the decode at every tile and the tile error
+    report."""
+    tr, ot = terraces
+    assert len(np.unique(ot["tile_value"])) >= 3
+    W, H, m, c = 64, 3, 18, 1
+    shapes = mlp.layer_shapes(2 * m, W, H, c)
+    B = workloads.pe_matrix(6)
+    th0 = workloads.init_params(2 * m, W, H, c, seed=31)
+    p = gpu_lib.FP32 if prec == "fp32" else gpu_lib.BF16
+    model = gpu_lib.Model({3: (W, H, m, c)}, precision=p, domain_size=128, value_scale=1.0)
+    model.set_params(3, th0)
+    model.set_encoding(3, B)
+    L = model.fit(tr, steps=6, batch=2048, nets_mask=8, seed=13)[3]
+    _, _, _, lo = F.train(th0.astype(np.float64), shapes, B.astype(np.float64), ot, "tile", (0, 0, 0), 128, T.FOG,
+                          THR, steps=6, batch=2048, seed=13)
+    rel = np.abs(L - lo) / lo
+    assert rel[0] <= (1e-6 if p == gpu_lib.FP32 else 2e-2), (L, lo)
+    assert np.max(rel) <= (1e-5 if p == gpu_lib.FP32 else 2e-2), (L, lo)
+    th = model.get_params(3).astype(np.float64)
+    got = model.decode_tiles(tr).cpu().numpy()
+    want = F.decode_tiles(th, shapes, B.astype(np.float64), ot, (0, 0, 0), 128, T.FOG, THR)
+    tol = 1e-6 if p == gpu_lib.FP32 else 2e-3
+    assert np.all(np.abs(got - want) <= tol * (1 + np.abs(want))), np.abs(got - want).max()
+    rep = gpu_lib.errors_tiles(tr, model.decode_tiles(tr))
+    orep = F.errors_tiles(ot, got.astype(np.float64))
+    assert rep["n"] == orep["n"] == len(ot["tile_value"])
+    assert abs(rep["max_abs"] - orep["max_abs"]) <= 1e-6 and abs(rep["rms"] - orep["rms"]) <= 1e-9 * max(1, orep["rms"])
+    if p == gpu_lib.BF16:
+        g8 = model.decode_tiles(tr, fp8=True).cpu().numpy()
+        w8 = F.decode_tiles(th, shapes, B.astype(np.float64), ot, (0, 0, 0), 128, T.FOG, THR, fp8=True)
+        assert np.abs(g8 - w8).max() <= 3e-2
+
+
+def test_tile_regressor_errors(gpu_lib, fog):
+    tr, _ = fog
+    m = gpu_lib.Model({0: (64, 3, 18, 1)}, precision=gpu_lib.FP32, domain_size=128, value_scale=1.0)
+    with pytest.raises(gpu_lib.NvdbError):
+        m.decode_tiles(tr)                      # no tile regressor in the model
+    m2 = gpu_lib.Model({3: (64, 3, 18, 1)}, precision=gpu_lib.FP32, domain_size=128, value_scale=1.0)
+    with pytest.raises(gpu_lib.NvdbError):
+        m2.decode_tiles(tr)                     # parameters not set
+    m2.set_params(3, workloads.init_params(36, 64, 3, 1, seed=2))
+    m2.set_encoding(3, workloads.pe_matrix(6))
+    t0 = gpu_lib.Tree(_fog(64).to(DEV), (0, 0, 0), T.FOG, THR)   # not pruned: no tiles to train on
+    with pytest.raises(gpu_lib.NvdbError):
+        m2.fit(t0, steps=1, batch=64, nets_mask=8, seed=1)
+    assert m2.decode_tiles(t0).numel() == 0
+
+
+def test_decode_topology_with_tiles(gpu_lib, fog):
+    """Top-down decode (Sec. 3.3.1): level-1 classes -> active tiles valued by the
+    tile regressor, leaves -> level-0 classifier -> voxel values; FP32 against the
+    oracle's decode with the same weights.  Tile slots may differ only where the
+    level-1 logits are within rounding of a tie; values at the common tiles agree
+    to FP32 forward accuracy."""
+    tr, ot = fog
+    nets = {2: (64, 4, 64, 3), 0: (64, 3, 18, 1), 1: (64, 3, 18, 1), 3: (64, 3, 18, 1)}
+    m = gpu_lib.Model(nets, precision=gpu_lib.FP32, domain_size=128, value_scale=1.0)
+    Bs = {2: workloads.ffm_matrix(64, 2.0, seed=4), 0: workloads.pe_matrix(6), 1: workloads.pe_matrix(6),
+          3: workloads.pe_matrix(6)}
+    for k, (W_, H_, m_, c_) in nets.items():
+        m.set_params(k, workloads.init_params(2 * m_, W_, H_, c_, seed=50 + k))
+        m.set_encoding(k, Bs[k])
+    m.fit(tr, steps=200, batch=4096, nets_mask=15, seed=1, lr=3e-3)
+    pred = m.decode_topology(tr)
+    keys, vals, act = pred.export_tiles()
+
+    def net(k):
+        W_, H_, m_, c_ = nets[k]
+        return (m.get_params(k).astype(np.float64), mlp.layer_shapes(2 * m_, W_, H_, c_), Bs[k].astype(np.float64))
+    o = F.decode_topology(ot, (0, 0, 0), 128, T.FOG, THR, 1.0, net(2), net(0), net(1), tile=net(3))
+    lg = F.decode_l1(*net(2), ot, (0, 0, 0), 128)
+    srt = np.sort(lg, axis=1)
+    tie = (srt[:, -1] - srt[:, -2]) <= 1e-4
+    diff = np.setxor1d(keys.astype(np.int64), o["tile_key"])
+    assert np.all(tie[diff]), len(diff)
+    assert len(keys) > 0
+    common, ig, io = np.intersect1d(keys.astype(np.int64), o["tile_key"], return_indices=True)
+    d = np.abs(vals[ig] - o["tile_value"][io])
+    assert d.max() <= 1e-5 * (1 + np.abs(o["tile_value"][io]).max()), d.max()
+    # the active-tile bits of the result are its tiles
+    assert int(T.popcount64(act).sum()) == len(keys)
+    # the tile error of the decoded values against the truth at the correctly placed tiles
+    truth = dict(zip((ot["tile_l1"] * 4096 + ot["tile_n1"]).tolist(), ot["tile_value"]))
+    hit = [i for i, k in enumerate(keys.tolist()) if k in truth]
+    err = np.abs(vals[hit] - np.array([truth[keys[i]] for i in hit]))
+    print("tiles: %d predicted, %d true, %d placed right; max err %.3g rms %.3g"
+          % (len(keys), len(truth), len(hit), err.max(), np.sqrt(np.mean(err ** 2))))

@@ -114,10 +114,11 @@ def fbm_cloud(n=1024, octaves=6, scale=256.0, seed=7, device="cpu", chunk=16):
 
 
 def saturated_fog(n=64, center=(32.0, 32.0, 32.0), radius=24.0, gain=3.0, amplitude=0.3, scale=16.0, seed=5,
-                  device="cpu", chunk=32):
+                  device="cpu", chunk=32, levels=0):
     """Density clamp(gain (1 - |p - c| / R) + amplitude fbm(p / scale), 0, 1) on an n^3
     lattice (fog volume): a noisy ball whose core saturates at exactly 1, so the
-    leaves inside the core are constant."""
+    leaves inside the core are constant.  levels > 0 rounds the density down to a
+    multiple of 1 / levels (terraces of constant density)."""
     out = torch.empty((n, n, n), dtype=torch.float32, device=device)
     for x0 in range(0, n, chunk):
         nx = min(chunk, n - x0)
@@ -125,6 +126,8 @@ def saturated_fog(n=64, center=(32.0, 32.0, 32.0), radius=24.0, gain=3.0, amplit
         p = torch.stack([x, y, z], -1)
         d = torch.sqrt((x - center[0]) ** 2 + (y - center[1]) ** 2 + (z - center[2]) ** 2)
         out[x0:x0 + nx] = (gain * (1.0 - d / radius) + amplitude * fbm(p / scale, 3, seed)).clamp(0.0, 1.0)
+    if levels > 0:
+        out = torch.floor(out * levels) / levels
     return out
 
 
