@@ -63,6 +63,7 @@ def main():
     ap.add_argument("--skip-small", action="store_true")
     ap.add_argument("--skip-query", action="store_true")
     ap.add_argument("--skip-moe", action="store_true")
+    ap.add_argument("--skip-tiles", action="store_true")
     ap.add_argument("--seq-frames", type=int, default=16)
     ap.add_argument("--seq-cap", type=int, default=2000)
     ap.add_argument("--seq-full-width", action="store_true",
@@ -310,8 +311,84 @@ def main():
         print("cloud leg ...", file=sys.stderr, flush=True)
         out["cloud"] = cloud_leg(args.fit_steps, tuned_g)
         torch.cuda.empty_cache()
+    if not args.skip_tiles:
+        print("active-tiles leg ...", file=sys.stderr, flush=True)
+        out["tiles"] = tiles_leg(args.fit_steps // 2)
+        torch.cuda.empty_cache()
 
     print(json.dumps(out), flush=True)
+
+
+def tiles_leg(fit_steps, n=256, thr=0.05):
+    """Fog with a saturated core (Sec. 3.3.1): leaves of constant density become active
+    tiles; the level-1 classifier is ternary (leaf / active tile / inactive) and the tile
+    value regressor encodes the tile values.  All four networks train together, then the
+    lower levels are decoded top-down from the level-1 nodes."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2208_04448_amd import nvdb
+    c = n / 2.0
+    grid = workloads.saturated_fog(n=n, center=(c, c + 3.0, c - 2.0), radius=0.44 * n, scale=n / 4.0, device="cuda")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    full = nvdb.Tree(grid, (0, 0, 0), nvdb.FOG, thr)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t
+    t = time.perf_counter()
+    tree = full.prune_tiles()
+    torch.cuda.synchronize()
+    t_prune = time.perf_counter() - t
+    fi, info = full.info(), tree.info()
+    del full, grid
+    nets = {0: (W, H, M, C), 1: (W, H, M, C), 2: (64, 4, 64, 3), 3: (64, 3, 32, 1)}
+    mdl = nvdb.Model(nets, precision=nvdb.BF16, domain_lo=(0, 0, 0), domain_size=n, value_scale=1.0)
+    sig = {0: 10.0, 1: 10.0, 2: 2.0, 3: 2.0}
+    for k, (w_, h_, m_, c_) in nets.items():
+        mdl.set_encoding(k, workloads.ffm_matrix(m_, sig[k], seed=60 + k))
+        mdl.set_params(k, workloads.init_params(2 * m_, w_, h_, c_, seed=70 + k))
+    mdl.set_train_groups(128)
+    batch = 1 << 16
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    losses = mdl.fit(tree, steps=fit_steps, batch=batch, nets_mask=15, seed=0, lr=1e-3, lr_decay=0.975,
+                     lr_interval=100)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t
+    vt = mdl.decode_tiles(tree)
+    tile_err = nvdb.errors_tiles(tree, vt)
+    l1 = nvdb.errors_l1(tree, mdl.decode_l1(tree))
+    mdl.decode_topology(tree)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    pred = mdl.decode_topology(tree)
+    torch.cuda.synchronize()
+    t_dec = time.perf_counter() - t
+    topo = nvdb.errors_topology(tree, pred)
+    kt, vt_true, _ = tree.export_tiles()
+    kp, vp, _ = pred.export_tiles()
+    common, it, ip = np.intersect1d(kt, kp, return_indices=True)
+    d = vp[ip].astype(np.float64) - vt_true[it]
+    pi = pred.info()
+    return {"workload": "fog %d^3, density clamp(3 (1 - r/R) + 0.3 fbm, 0, 1), R = %.1f, threshold %.2f; leaves of "
+                        "one density pruned to active tiles" % (n, 0.44 * n, thr),
+            "n_voxels_before_pruning": fi.n_voxels, "n_leaves_before_pruning": fi.n_leaves,
+            "n_voxels": info.n_voxels, "n_leaves": info.n_leaves, "n_tiles": info.n_tiles, "n_l1": info.n_l1,
+            "build_ms": t_build * 1e3, "prune_ms": t_prune * 1e3,
+            "networks": {"regressor": "4x128 m=64", "l0": "4x128 m=64", "l1": "4x64 m=64, 3 classes",
+                         "tile": "3x64 m=32"},
+            "fit_steps": fit_steps, "batch": batch, "fit_s": t_fit,
+            "train_samples_per_s": 4 * batch * fit_steps / t_fit,
+            "final_loss": [float(losses[k, -1]) for k in range(4)],
+            "tile_err_true_topology": tile_err, "l1_report": l1,
+            "decode_topology_ms": t_dec * 1e3,
+            "decoded": {"n_voxels": pi.n_voxels, "n_leaves": pi.n_leaves, "n_tiles": pi.n_tiles,
+                        "tiles_placed_right": int(len(common)), "tiles_fp": int(len(kp) - len(common)),
+                        "tiles_fn": int(len(kt) - len(common)),
+                        "tile_max_abs": float(np.abs(d).max()) if len(d) else 0.0,
+                        "tile_rms": float(np.sqrt(np.mean(d * d))) if len(d) else 0.0,
+                        "voxels": topo}}
 
 
 def measured_traffic():

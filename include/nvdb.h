@@ -579,8 +579,12 @@ nvdb_status nvdb_query_noalloc(const nvdb_model* model, const nvdb_tree* tree, c
  * 16-bit networks, in the model's arithmetic, from the stored upper levels)
  * and lists where it differs from `truth`, so the reader restores the true
  * active set exactly.  cap 0 with buf NULL returns the size only.
+ * A truth with active tiles is archived with its level-1 and leaf masks stored
+ * (no patches): the reader's top-down decode then places the tiles exactly and
+ * values them with the tile value regressor, which the archive must hold.
  * Synchronises `stream`.  Errors: E_INVALID (bad description, buffer smaller
- * than *size), E_STATE (a network missing or unset).
+ * than *size), E_STATE (a network missing or unset), E_UNSUPPORTED (patches
+ * requested for a truth with active tiles).
  * nvdb_archive_decode: the tree decoded from an archive: the lower levels by
  * inference from the stored upper levels (nvdb_decode_topology), the patches
  * applied, values from the regressor at every voxel.  The caller frees the tree.

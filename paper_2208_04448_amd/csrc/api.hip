@@ -2256,6 +2256,9 @@ nvdb_status nvdb_archive_write(const nvdb_model* m, const nvdb_tree* truth, cons
                  "level-1 nodes are stored either as masks or as the level-1 classifier");
     NVDB_REQUIRE(!ad->explicit_l0 || (ad->explicit_l1 && !(mask & (1 << NVDB_NET_L0)) && !ad->patches),
                  NVDB_E_INVALID, "stored leaf masks need stored level-1 masks, no level-0 classifier and no patches");
+    // voxel patches rebuild the reader's tree from voxels, which holds no tiles
+    NVDB_REQUIRE(!(ad->patches && truth->n_tile > 0), NVDB_E_UNSUPPORTED,
+                 "voxel patches of a tree with active tiles (store the leaf masks instead)");
     for (int k = 0; k < NVDB_MAX_NETS; ++k)
       if (mask & (1 << k)) {
         const Net& N = net_of(m, k);

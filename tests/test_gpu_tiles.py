@@ -198,3 +198,36 @@ def test_decode_topology_with_tiles(gpu_lib, fog):
     err = np.abs(vals[hit] - np.array([truth[keys[i]] for i in hit]))
     print("tiles: %d predicted, %d true, %d placed right; max err %.3g rms %.3g"
           % (len(keys), len(truth), len(hit), err.max(), np.sqrt(np.mean(err ** 2))))
+
+
+def test_archive_with_tiles(gpu_lib, fog):
+    """An archive of a tree with active tiles stores the level-1 and leaf masks and
+    the tile value regressor; its decode places every tile and leaf exactly and
+    values the tiles with the stored (16-bit) regressor.  Voxel patches, which
+    would rebuild the tree from voxels, are refused for such a tree."""
+    tr, ot = fog
+    nets = {0: (64, 3, 18, 1), 3: (64, 3, 18, 1)}
+    m = gpu_lib.Model(nets, precision=gpu_lib.BF16, domain_size=128, value_scale=1.0)
+    for k, (W_, H_, m_, c_) in nets.items():
+        m.set_params(k, workloads.init_params(2 * m_, W_, H_, c_, seed=80 + k))
+        m.set_encoding(k, workloads.pe_matrix(6))
+    m.fit(tr, steps=50, batch=2048, nets_mask=9, seed=3)
+    with pytest.raises(gpu_lib.NvdbError):
+        gpu_lib.archive_write(m, tr, 9, gpu_lib.STORE_F16, explicit_l1=True, patches=True)
+    buf = gpu_lib.archive_write(m, tr, 9, gpu_lib.STORE_F16, explicit_l1=True, explicit_l0=True)
+    dt, info = gpu_lib.archive_decode(buf)
+    assert info.nets_mask == 9
+    de, ex = dt.export(), tr.export()
+    for key in ("leaf_origin", "leaf_mask", "leaf_off", "l1_origin", "l1_child"):
+        assert np.array_equal(de[key], ex[key]), key
+    k_d, v_d, a_d = dt.export_tiles()
+    k_t, _, a_t = tr.export_tiles()
+    assert np.array_equal(k_d, k_t) and np.array_equal(a_d, a_t) and len(k_t) == len(ot["tile_value"])
+    # the stored networks: both rounded to binary16, as the reader holds them
+    r = gpu_lib.Model(nets, precision=gpu_lib.BF16, domain_size=128, value_scale=1.0)
+    for k in nets:
+        r.set_params16(k, gpu_lib.STORE_F16, m.get_params16(k, gpu_lib.STORE_F16))
+        r.set_encoding(k, workloads.pe_matrix(6))
+    assert np.array_equal(v_d, r.decode_tiles(tr).cpu().numpy())
+    want, _ = r.decode(tr, values=True, masks=False)
+    assert np.array_equal(de["values"], want.cpu().numpy())
