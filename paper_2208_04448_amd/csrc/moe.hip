@@ -303,6 +303,112 @@ __global__ void __launch_bounds__(256) k_moe_route(ItemSrc src, int64_t n, MoeGr
   }
 }
 
+// The same two passes for voxel and voxel-slot items when the cell grid is
+// leaf-aligned (origin, edge and halo multiples of 8): every item of a leaf then
+// meets the same experts, so the experts are found once per leaf and its m items
+// (its active voxels, or its 512 slots) are counted and reserved together.
+__device__ __forceinline__ void leaf_cells(const int4& o, const MoeGrid& g, AxisCells& ax, AxisCells& ay,
+                                           AxisCells& az) {
+  ax = axis_cells(o.x, g.o[0], g.S, g.h);
+  ay = axis_cells(o.y, g.o[1], g.S, g.h);
+  az = axis_cells(o.z, g.o[2], g.S, g.h);
+}
+__device__ __forceinline__ uint32_t leaf_items(const uint32_t* __restrict__ leaf_off, int64_t l) {
+  return leaf_off ? leaf_off[l + 1] - leaf_off[l] : 512u;
+}
+
+__global__ void __launch_bounds__(256) k_moe_count_leaf(const int4* __restrict__ leaf_o,
+                                                        const uint32_t* __restrict__ leaf_off, int64_t n_leaf,
+                                                        MoeGrid g, const int32_t* __restrict__ table, int n_exp,
+                                                        uint32_t* __restrict__ cnt, uint32_t* __restrict__ uncovered) {
+  extern __shared__ uint32_t lds[];  // n_exp counters
+  __shared__ uint32_t unc;
+  for (int k = threadIdx.x; k < n_exp; k += blockDim.x) lds[k] = 0u;
+  if (threadIdx.x == 0) unc = 0u;
+  __syncthreads();
+  for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n_leaf; l += (int64_t)gridDim.x * blockDim.x) {
+    AxisCells ax, ay, az;
+    leaf_cells(leaf_o[l], g, ax, ay, az);
+    const uint32_t m = leaf_items(leaf_off, l);
+    bool covered = false;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = slot_expert(g, table, ax, ay, az, j);
+      if (k >= 0) {
+        atomicAdd(&lds[k], m);
+        covered = true;
+      }
+    }
+    if (!covered && m) atomicAdd(&unc, m);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < n_exp; k += blockDim.x)
+    if (lds[k]) atomicAdd(&cnt[k], lds[k]);
+  if (threadIdx.x == 0 && unc) atomicAdd(uncovered, unc);
+}
+
+// One wave per leaf: walk 1 sums the block's items per expert, one global atomic
+// per (block, expert) reserves its ranges, walk 2 gives each (leaf, expert) a run
+// of m consecutive places in the range and the lanes fill it.
+__global__ void __launch_bounds__(256) k_moe_route_leaf(const int4* __restrict__ leaf_o,
+                                                        const uint32_t* __restrict__ leaf_off,
+                                                        const uint32_t* __restrict__ key, int64_t n_leaf, MoeGrid g,
+                                                        const int32_t* __restrict__ table,
+                                                        const MoeBox* __restrict__ box, int n_exp,
+                                                        const uint32_t* __restrict__ start,
+                                                        uint32_t* __restrict__ cursor, float* __restrict__ bx,
+                                                        uint32_t* __restrict__ bslot, uint64_t cap) {
+  extern __shared__ uint32_t lds[];  // 3 n_exp words
+  uint32_t* hist = lds;
+  uint32_t* base = lds + n_exp;
+  uint32_t* fill = lds + 2 * n_exp;
+  for (int k = threadIdx.x; k < n_exp; k += blockDim.x) hist[k] = fill[k] = 0u;
+  __syncthreads();
+  const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63u);
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  for (int64_t l = (int64_t)blockIdx.x * 4 + wave; l < n_leaf; l += stride) {
+    if (lane != 0) continue;
+    AxisCells ax, ay, az;
+    leaf_cells(leaf_o[l], g, ax, ay, az);
+    const uint32_t m = leaf_items(leaf_off, l);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = slot_expert(g, table, ax, ay, az, j);
+      if (k >= 0 && m) atomicAdd(&hist[k], m);
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < n_exp; k += blockDim.x) base[k] = hist[k] ? start[k] + atomicAdd(&cursor[k], hist[k]) : 0u;
+  __syncthreads();
+  for (int64_t l = (int64_t)blockIdx.x * 4 + wave; l < n_leaf; l += stride) {
+    const int4 o = leaf_o[l];
+    AxisCells ax, ay, az;
+    leaf_cells(o, g, ax, ay, az);
+    const uint32_t m = leaf_items(leaf_off, l);
+    const uint32_t i0 = leaf_off ? leaf_off[l] : (uint32_t)(l * 512);
+#pragma unroll 1
+    for (int j = 0; j < 8; ++j) {
+      const int k = slot_expert(g, table, ax, ay, az, j);  // wave-uniform
+      if (k < 0 || m == 0) continue;
+      uint32_t run = 0;
+      if (lane == 0) run = atomicAdd(&fill[k], m);
+      run = __shfl(run, 0);
+      const MoeBox b = box[k];
+      for (uint32_t r = lane; r < m; r += 64) {
+        const uint32_t i = i0 + r;
+        const uint32_t n0 = key ? (key[i] & 511u) : r;
+        const uint64_t s = (uint64_t)base[k] + run + r;
+        if (s >= cap) continue;  // the pair buffers were too small: the caller retries
+        const int px = o.x + (int)(n0 >> 6), py = o.y + (int)((n0 >> 3) & 7u), pz = o.z + (int)(n0 & 7u);
+        bx[3 * s] = ((float)(px - b.lo[0]) + 0.5f) * b.inv_d;
+        bx[3 * s + 1] = ((float)(py - b.lo[1]) + 0.5f) * b.inv_d;
+        bx[3 * s + 2] = ((float)(pz - b.lo[2]) + 0.5f) * b.inv_d;
+        bslot[s] = 8u * i + (uint32_t)j;
+      }
+    }
+  }
+}
+
 // Gate-weighted average of the expert outputs held in the item's 8 slots: a
 // value per voxel, or (mask non-null) the bit "blended logit > 0" per voxel slot,
 // packed 64 to a word by the wave that computed them, or (cls non-null, leaf-slot
@@ -394,17 +500,39 @@ static ItemSrc item_src(const Tree& t, int kind) {
   return ItemSrc{t.leaf_o.p, kind == MOE_VOXELS ? t.vox_key.p : nullptr, 0};
 }
 
+// Voxel and voxel-slot items of a leaf-aligned grid are routed per leaf.
+static bool per_leaf(const MoeGrid& g, int kind) {
+  return kind != MOE_LEAF_SLOTS && ((g.o[0] | g.o[1] | g.o[2] | g.S | g.h) & 7) == 0;
+}
+static unsigned leaf_grid(int64_t n_leaf, int per_block, int64_t max_blocks) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(max_blocks, (n_leaf + per_block - 1) / per_block));
+}
+
 void moe_count(const Tree& t, int kind, const MoeGrid& g, const int32_t* table, int n_exp, uint32_t* cnt,
                uint32_t* uncovered, hipStream_t st) {
-  hipLaunchKernelGGL(k_moe_count, dim3(route_grid(items(t, kind))), dim3(256), (size_t)n_exp * 4, st,
-                     item_src(t, kind), items(t, kind), g, table, n_exp, cnt, uncovered);
+  if (per_leaf(g, kind)) {
+    if (t.n_leaf == 0) return;
+    hipLaunchKernelGGL(k_moe_count_leaf, dim3(leaf_grid(t.n_leaf, 256, 1024)), dim3(256), (size_t)n_exp * 4, st, t.leaf_o.p,
+                       kind == MOE_VOXELS ? t.leaf_off.p : nullptr, t.n_leaf, g, table, n_exp, cnt, uncovered);
+  } else {
+    hipLaunchKernelGGL(k_moe_count, dim3(route_grid(items(t, kind))), dim3(256), (size_t)n_exp * 4, st,
+                       item_src(t, kind), items(t, kind), g, table, n_exp, cnt, uncovered);
+  }
   NVDB_HIP(hipGetLastError());
 }
 
 void moe_route(const Tree& t, int kind, const MoeGrid& g, const int32_t* table, const MoeBox* box, int n_exp,
                const uint32_t* start, uint32_t* cursor, float* bx, uint32_t* bslot, uint64_t cap, hipStream_t st) {
-  hipLaunchKernelGGL(k_moe_route, dim3(route_grid(items(t, kind))), dim3(256), (size_t)n_exp * 12, st,
-                     item_src(t, kind), items(t, kind), g, table, box, n_exp, start, cursor, bx, bslot, cap);
+  if (per_leaf(g, kind)) {
+    if (t.n_leaf == 0) return;
+    const bool vox = kind == MOE_VOXELS;
+    hipLaunchKernelGGL(k_moe_route_leaf, dim3(leaf_grid(t.n_leaf, 4, 1024)), dim3(256), (size_t)n_exp * 12, st, t.leaf_o.p,
+                       vox ? t.leaf_off.p : nullptr, vox ? t.vox_key.p : nullptr, t.n_leaf, g, table, box, n_exp,
+                       start, cursor, bx, bslot, cap);
+  } else {
+    hipLaunchKernelGGL(k_moe_route, dim3(route_grid(items(t, kind))), dim3(256), (size_t)n_exp * 12, st,
+                       item_src(t, kind), items(t, kind), g, table, box, n_exp, start, cursor, bx, bslot, cap);
+  }
   NVDB_HIP(hipGetLastError());
 }
 
