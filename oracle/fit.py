@@ -334,12 +334,30 @@ def query_hits(tr, q):
     return np.array([bool(ok[i]) and tuple(p[i]) in active for i in range(len(q))], dtype=bool)
 
 
-def query_values(theta, shapes, B, tr, lo, D, kind, band, q, background):
+def query_tiles(tr, q):
+    """Random access through the level-1 nodes (Sec. 3.3.1, 3.5): the active tile a
+    query position falls in -- the tile whose leaf-sized region holds its voxel
+    floor(q) -- as an index into the tree's tiles, or -1 (no level-1 node there, or
+    the slot is a leaf or an inactive tile).  A voxel inside an existing leaf is
+    never in a tile."""
+    q = np.asarray(q, np.float64).reshape(-1, 3)
+    ok = np.all(np.isfinite(q), axis=1) & np.all(np.abs(q) < 2.0 ** 31 - 2, axis=1)
+    where = {tuple(o): t for t, o in enumerate(np.asarray(tr["tile_origin"], np.int64).tolist())}
+    out = np.full(len(q), -1, np.int64)
+    for i in np.nonzero(ok)[0]:
+        o = tuple(int(c) & ~7 for c in np.floor(q[i]).astype(np.int64))
+        out[i] = where.get(o, -1)
+    return out
+
+
+def query_values(theta, shapes, B, tr, lo, D, kind, band, q, background, tile=None):
     """Online random access of the [Hash,5,4,NN(3)] configuration (Sec. 3.5): a hit
     gets the regressor's value at its own position, normalised like the voxel
     centres, x = (q - lo) / D (so q = p + 1/2 reproduces the decode of voxel p),
-    scaled back to value units; every other query gets `background` (the volumes
-    here hold no active tiles).  Returns (values, hits)."""
+    scaled back to value units; with a tile value regressor `tile` = (theta,
+    shapes, B), a query in an active tile gets that regressor's value at the
+    tile's leaf-slot centre (the tile's one value, as the tile decode gives it);
+    every other query gets `background`.  Returns (values, hits) (hits: voxel hits)."""
     q = np.asarray(q, np.float64).reshape(-1, 3)
     hits = query_hits(tr, q)
     vals = np.full(len(q), float(background))
@@ -347,6 +365,12 @@ def query_values(theta, shapes, B, tr, lo, D, kind, band, q, background):
         x = (q[hits] - np.asarray(lo, np.float64)) / float(D)
         y = _batched_predict(theta, shapes, B, x)[:, 0]
         vals[hits] = y * band if kind == T.SDF else y
+    if tile is not None:
+        t = query_tiles(tr, q)
+        sel = t >= 0
+        if sel.any():
+            vt = decode_tiles(*tile, tr, lo, D, kind, band)
+            vals[sel] = vt[t[sel]]
     return vals, hits
 
 

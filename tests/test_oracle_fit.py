@@ -401,3 +401,37 @@ def test_topology_with_tiles_from_true_decisions(fog_tiles):
     rep = F.errors_tiles(tr, that)
     assert rep["n"] == len(that) and rep["max_abs"] == 0.25
     assert np.isclose(rep["rms"], np.sqrt((0.0625 + 0.015625) / len(that)))
+
+
+def test_query_tiles_pins(fog_tiles):
+    """Random access through the tiles: queries anywhere inside an active tile's
+    8^3 region find it (brute force over the tile origins), queries in leaves,
+    outside the level-1 nodes or non-finite find none; with a tile regressor such
+    queries return the tile decode's value, every voxel hit the regressor's."""
+    tr = fog_tiles
+    rng = np.random.default_rng(5)
+    t_pick = rng.integers(0, len(tr["tile_value"]), 200)
+    q_in = tr["tile_origin"][t_pick] + rng.uniform(0.0, 8.0, (200, 3))
+    q_rand = rng.uniform(-10.0, 80.0, (2000, 3))
+    q = np.concatenate([q_in, q_rand, [[np.nan, 1, 1], [1e12, 0, 0]]])
+    got = F.query_tiles(tr, q)
+    assert np.array_equal(got[:200], t_pick)
+    origins = [tuple(o) for o in tr["tile_origin"].tolist()]
+    for i in range(200, len(q)):
+        if not np.all(np.isfinite(q[i])) or np.any(np.abs(q[i]) >= 2.0 ** 31 - 2):
+            assert got[i] == -1
+            continue
+        o = tuple(int(c) & ~7 for c in np.floor(q[i]))
+        assert got[i] == (origins.index(o) if o in origins else -1)
+    hits = F.query_hits(tr, q)
+    assert not np.any(hits & (got >= 0)) and hits.sum() > 0 and (got >= 0).sum() > 200
+    shapes = mlp.layer_shapes(36, 16, 2, 1)
+    th = np.random.default_rng(0).uniform(-0.5, 0.5, mlp.param_count(36, 16, 2, 1))
+    tt = np.random.default_rng(1).uniform(-0.5, 0.5, mlp.param_count(36, 16, 2, 1))
+    B = mlp.pe_matrix(6)
+    v, h = F.query_values(th, shapes, B, tr, (0, 0, 0), 64, T.FOG, 0.05, q, background=-1.0,
+                          tile=(tt, shapes, B))
+    vt = F.decode_tiles(tt, shapes, B, tr, (0, 0, 0), 64, T.FOG, 0.05)
+    assert np.array_equal(v[got >= 0], vt[got[got >= 0]])
+    v0, _ = F.query_values(th, shapes, B, tr, (0, 0, 0), 64, T.FOG, 0.05, q, background=-1.0)
+    assert np.array_equal(v[~(got >= 0)], v0[~(got >= 0)]) and np.all(v0[got >= 0] == -1.0)
