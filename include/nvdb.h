@@ -531,13 +531,17 @@ nvdb_status nvdb_errors_l1(const nvdb_tree* tree, const uint8_t* classes_dev, nv
  * floor(q) is a hit when the voxel's leaf exists and its active mask holds it;
  * hits get the regressor's value at q, normalised like the voxel centres
  * ((q - domain_lo) / domain_size) and scaled back by value_scale, so a query at
- * a voxel centre returns that voxel's decoded value; every other query
- * (including non-finite positions) gets `background` (the trees built here
- * hold no active tiles).  The regressor runs only on the hits.  Queries are
- * processed in batches of `batch` (0: all at once).  hits_dev (uint8[n], may
- * be NULL) receives 1 for regressor queries.  Device buffers; synchronises
- * `stream`.  Errors: E_INVALID (bad buffers or sizes, n >= 2^31, non-finite
- * background), E_STATE (regressor missing or unset). */
+ * a voxel centre returns that voxel's decoded value.  When the tree has active
+ * tiles (nvdb_tree_prune_tiles) and the model holds the tile value regressor, a
+ * query whose voxel lies in an active tile's region gets that regressor's value
+ * at the tile's leaf-slot centre (the tile's one value, bit-equal to
+ * nvdb_decode_tiles).  Every other query (including non-finite positions) gets
+ * `background`.  The networks run only on their hits.  Queries are processed in
+ * batches of `batch` (0: all at once).  hits_dev (uint8[n], may be NULL)
+ * receives 1 for regressor queries, 2 for tile queries, 0 otherwise.  Device
+ * buffers; synchronises `stream`.  Errors: E_INVALID (bad buffers or sizes,
+ * n >= 2^31, non-finite background), E_STATE (regressor, or the tile regressor
+ * a tree with tiles needs, missing or unset). */
 nvdb_status nvdb_query(const nvdb_model* model, const nvdb_tree* tree, const float* q_dev, int64_t n, float background,
                        int64_t batch, float* values_dev, uint8_t* hits_dev, void* stream);
 
@@ -550,7 +554,9 @@ nvdb_status nvdb_query(const nvdb_model* model, const nvdb_tree* tree, const flo
  * is E_INVALID.  Asynchronous on `stream` (no synchronisation).  Every call on
  * one GPU shares that GPU's scratch: calls that overlap on one GPU (other
  * streams, other threads) race and must be serialised by the caller; calls on
- * one stream are ordered.  Errors as nvdb_query, E_DEVICE if the scratch's
+ * one stream are ordered.  The scratch holds the voxel hits only: a tree with
+ * active tiles queried with a model holding the tile regressor is E_UNSUPPORTED
+ * here (nvdb_query serves it).  Errors as nvdb_query, E_DEVICE if the scratch's
  * device address cannot be obtained. */
 nvdb_status nvdb_query_noalloc(const nvdb_model* model, const nvdb_tree* tree, const float* q_dev, int64_t n,
                                float background, int64_t batch, float* values_dev, uint8_t* hits_dev, void* stream);

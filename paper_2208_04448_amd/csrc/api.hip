@@ -1510,21 +1510,47 @@ nvdb_status nvdb_query(const nvdb_model* m, const nvdb_tree* tree, const float* 
     NVDB_REQUIRE(std::isfinite(background), NVDB_E_INVALID, "background must be finite");
     const Net& N = net_of(m, NVDB_NET_REGRESSOR);
     NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "regressor parameters or encoding not set");
+    // active tiles are looked up when the tree has them and the model holds the tile regressor
+    const Net& TN = m->nets[NVDB_NET_TILE];
+    const bool tiles = tree->n_tile > 0 && TN.present;
+    if (tiles) NVDB_REQUIRE(TN.params_set && TN.enc_set, NVDB_E_STATE, "tile value regressor parameters or encoding not set");
     if (n == 0) return;
     hipStream_t st = (hipStream_t)stream;
     const int64_t bs = batch > 0 ? std::min<int64_t>(batch, n) : n;
-    DevBuf<float> hit_x, y;
-    DevBuf<uint32_t> hit_idx, cnt;
+    DevBuf<float> hit_x, y, tile_x, tile_y;
+    DevBuf<uint32_t> hit_idx, cnt, tile_idx;
     hit_x.alloc(3 * (size_t)bs);
     y.alloc((size_t)bs);
     hit_idx.alloc((size_t)bs);
-    cnt.alloc(1);
+    cnt.alloc(2);
+    QueryTiles qt{};
+    if (tiles) {
+      tile_x.alloc(3 * (size_t)bs);
+      tile_y.alloc((size_t)bs);
+      tile_idx.alloc((size_t)bs);
+      qt = QueryTiles{tree->l1_o.p, tree->l1_active.p, tree->n_l1, tile_x.p, tile_idx.p, cnt.p + 1};
+    }
     const float inv_d = 1.f / (float)m->d.domain_size;
     for (int64_t b0 = 0; b0 < n; b0 += bs) {
       const int64_t nb = std::min(bs, n - b0);
       query_zero_count(cnt.p, st);
+      if (tiles) query_zero_count(cnt.p + 1, st);
       query_classify(q_dev + 3 * b0, nb, *tree, background, m->d.domain_lo, inv_d, values_dev + b0,
-                     hits_dev ? hits_dev + b0 : nullptr, hit_x.p, hit_idx.p, cnt.p, st);
+                     hits_dev ? hits_dev + b0 : nullptr, hit_x.p, hit_idx.p, cnt.p, qt, st);
+      if (tiles) {  // the tile regressor over the batch's tile hits (count read on the device)
+        InferLaunch T{};
+        T.net = net_view(TN);
+        base_spec(m, &T.spec);
+        T.spec.src = SRC_COORDS;
+        T.spec.direct = 1;
+        T.spec.coords = tile_x.p;
+        T.spec.n = nb;
+        T.spec.n_dev = cnt.p + 1;
+        T.out_kind = OUT_Y;
+        T.y = tile_y.p;
+        launch_infer(TN.ks, T, infer_grid(TN.ks, nb), st);
+        query_scatter(tile_y.p, tile_idx.p, nb, cnt.p + 1, m->d.value_scale, values_dev + b0, st);
+      }
       // the regressor over the batch's hits: launched for nb samples, it reads the
       // hit count on the device (waves past it exit at once)
       InferLaunch I{};
@@ -1555,6 +1581,8 @@ nvdb_status nvdb_query_noalloc(const nvdb_model* m, const nvdb_tree* tree, const
     NVDB_REQUIRE(std::isfinite(background), NVDB_E_INVALID, "background must be finite");
     const Net& N = net_of(m, NVDB_NET_REGRESSOR);
     NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "regressor parameters or encoding not set");
+    NVDB_REQUIRE(!(tree->n_tile > 0 && m->nets[NVDB_NET_TILE].present), NVDB_E_UNSUPPORTED,
+                 "active tiles need nvdb_query (the static scratch holds the voxel hits only)");
     if (n == 0) return;
     hipStream_t st = (hipStream_t)stream;
     const QueryScratch qs = query_noalloc_scratch();
@@ -1565,7 +1593,7 @@ nvdb_status nvdb_query_noalloc(const nvdb_model* m, const nvdb_tree* tree, const
       const int64_t nb = std::min(bs, n - b0);
       query_zero_count(qs.cnt, st);
       query_classify(q_dev + 3 * b0, nb, *tree, background, m->d.domain_lo, inv_d, values_dev + b0,
-                     hits_dev ? hits_dev + b0 : nullptr, qs.hit_x, qs.hit_idx, qs.cnt, st);
+                     hits_dev ? hits_dev + b0 : nullptr, qs.hit_x, qs.hit_idx, qs.cnt, QueryTiles{}, st);
       InferLaunch I{};
       I.net = net_view(N);
       base_spec(m, &I.spec);

@@ -318,8 +318,20 @@ void launch_fill(float* p, int64_t n, float v, hipStream_t st);
 Tree* build_tree_dense(const float* grid, const int32_t dims[3], const int32_t origin[3], const nvdb_active_rule& rule,
                        hipStream_t st);
 // query.hip
+// Active tiles of a random access: the tree's level-1 origins and active-tile
+// masks (n_l1 = 0: tiles are not looked up), and the compacted tile hits (the
+// tile's normalised leaf-slot centre, the query index, the count).
+struct QueryTiles {
+  const int4* l1_o;
+  const uint64_t* l1_active;
+  int64_t n_l1;
+  float* x;
+  uint32_t* idx;
+  uint32_t* n_hits;
+};
 void query_classify(const float* q, int64_t n, const Tree& tree, float background, const int32_t lo[3], float inv_d,
-                    float* values, uint8_t* hits, float* hit_x, uint32_t* hit_idx, uint32_t* n_hits, hipStream_t st);
+                    float* values, uint8_t* hits, float* hit_x, uint32_t* hit_idx, uint32_t* n_hits,
+                    const QueryTiles& tiles, hipStream_t st);
 void query_scatter(const float* y, const uint32_t* idx, int64_t n, const uint32_t* n_hits, float scale, float* values,
                    hipStream_t st);
 void query_zero_count(uint32_t* c, hipStream_t st);

@@ -5,7 +5,11 @@
 // canonical order: level-2 origin, then n2, then n1) and the leaf's active mask
 // holds it.  Hits are compacted and only they run through the regressor (whose
 // launch reads the hit count on the device, so batches need no host round trip);
-// every other query gets the background value.  The same leaf lookup lists the
+// every other query gets the background value.  With a tile value regressor, a
+// query whose voxel lies in an active tile of a level-1 node (binary search over the
+// level-1 origins, then the node's active-tile bit) is a tile hit: tile hits are
+// compacted with the tile's leaf-slot centre, the tile regressor runs over them and
+// they get its value, the tile's one value.  The same leaf lookup lists the
 // patches of a decoded topology (voxels it adds or misses).
 #include <algorithm>
 #include <cmath>
@@ -54,25 +58,47 @@ namespace {
 // Per query: hit test; misses get the background, hits are appended (in any
 // order: each value depends only on its own query) with their normalised
 // position and query index.
-__global__ void __launch_bounds__(256) k_query_classify(const float* __restrict__ q, int64_t n, QueryTree t, float bg,
-                                                        int lo0, int lo1, int lo2, float inv_d, float* __restrict__ values,
+__global__ void __launch_bounds__(256) k_query_classify(const float* __restrict__ q, int64_t n, QueryTree t,
+                                                        QueryTiles tl, float bg, int lo0, int lo1, int lo2,
+                                                        float inv_d, float* __restrict__ values,
                                                         uint8_t* __restrict__ hits, float* __restrict__ hit_x,
                                                         uint32_t* __restrict__ hit_idx, uint32_t* n_hits) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float qx = q[3 * i], qy = q[3 * i + 1], qz = q[3 * i + 2];
   const float lim = 2147483648.f;  // 2^31: every float below it floors into int32
-  bool hit = isfinite(qx) && isfinite(qy) && isfinite(qz) && fabsf(qx) < lim && fabsf(qy) < lim && fabsf(qz) < lim;
-  if (hit) {
-    const int px = (int)floorf(qx), py = (int)floorf(qy), pz = (int)floorf(qz);
+  const bool ok = isfinite(qx) && isfinite(qy) && isfinite(qz) && fabsf(qx) < lim && fabsf(qy) < lim && fabsf(qz) < lim;
+  bool hit = false, in_tile = false;
+  int px = 0, py = 0, pz = 0;
+  if (ok) {
+    px = (int)floorf(qx);
+    py = (int)floorf(qy);
+    pz = (int)floorf(qz);
     const int64_t a = find_leaf(t, make_int4(px & ~7, py & ~7, pz & ~7, 0));
-    hit = false;
     if (a >= 0) {
       const uint32_t n0 = (uint32_t)(((px & 7) << 6) | ((py & 7) << 3) | (pz & 7));
       hit = (t.leaf_mask[a * 8 + (n0 >> 6)] >> (n0 & 63u)) & 1ull;
+    } else if (tl.n_l1 > 0) {
+      const int4 o1 = make_int4(px & ~127, py & ~127, pz & ~127, 0);
+      const int64_t k = lower_l1(tl.l1_o, tl.n_l1, o1);
+      if (k < tl.n_l1) {
+        const int4 f = tl.l1_o[k];
+        if (f.x == o1.x && f.y == o1.y && f.z == o1.z) {
+          const uint32_t n1 = (uint32_t)((((px >> 3) & 15) << 8) | (((py >> 3) & 15) << 4) | ((pz >> 3) & 15));
+          in_tile = (tl.l1_active[k * 64 + (n1 >> 6)] >> (n1 & 63u)) & 1ull;
+        }
+      }
     }
   }
-  if (hits) hits[i] = hit ? 1 : 0;
+  if (hits) hits[i] = hit ? 1 : (in_tile ? 2 : 0);
+  if (in_tile) {  // the tile's leaf-slot centre, normalised as the tile decode does it
+    const uint32_t s = atomicAdd(tl.n_hits, 1u);
+    tl.x[3 * (size_t)s] = ((float)((px & ~7) - lo0) + 4.f) * inv_d;
+    tl.x[3 * (size_t)s + 1] = ((float)((py & ~7) - lo1) + 4.f) * inv_d;
+    tl.x[3 * (size_t)s + 2] = ((float)((pz & ~7) - lo2) + 4.f) * inv_d;
+    tl.idx[s] = (uint32_t)i;
+    return;
+  }
   if (!hit) {
     values[i] = bg;
     return;
@@ -145,11 +171,12 @@ int64_t topology_patches(const Tree& a, const Tree& b, int32_t* out, int64_t cap
 }
 
 void query_classify(const float* q, int64_t n, const Tree& tree, float background, const int32_t lo[3], float inv_d,
-                    float* values, uint8_t* hits, float* hit_x, uint32_t* hit_idx, uint32_t* n_hits, hipStream_t st) {
+                    float* values, uint8_t* hits, float* hit_x, uint32_t* hit_idx, uint32_t* n_hits,
+                    const QueryTiles& tiles, hipStream_t st) {
   if (n <= 0) return;
   QueryTree t{tree.leaf_o.p, tree.leaf_mask.p, tree.n_leaf};
-  hipLaunchKernelGGL(k_query_classify, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, q, n, t, background, lo[0],
-                     lo[1], lo[2], inv_d, values, hits, hit_x, hit_idx, n_hits);
+  hipLaunchKernelGGL(k_query_classify, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, q, n, t, tiles, background,
+                     lo[0], lo[1], lo[2], inv_d, values, hits, hit_x, hit_idx, n_hits);
   NVDB_HIP(hipGetLastError());
 }
 

@@ -8,30 +8,9 @@
 #include <memory>
 
 #include "nvdb_internal.h"
+#include "tree_device.h"
 
 namespace nvdb {
-
-// Canonical order of level-1 nodes: level-2 origin (x, y, z), then the slot n2.
-__device__ inline bool l1_before(int4 a, int4 b) {
-  const int ax = a.x & ~4095, ay = a.y & ~4095, az = a.z & ~4095;
-  const int bx = b.x & ~4095, by = b.y & ~4095, bz = b.z & ~4095;
-  if (ax != bx) return ax < bx;
-  if (ay != by) return ay < by;
-  if (az != bz) return az < bz;
-  const int na = (((a.x >> 7) & 31) << 10) | (((a.y >> 7) & 31) << 5) | ((a.z >> 7) & 31);
-  const int nb = (((b.x >> 7) & 31) << 10) | (((b.y >> 7) & 31) << 5) | ((b.z >> 7) & 31);
-  return na < nb;
-}
-// Index of the level-1 node with origin o among the n canonical origins.
-__device__ inline int64_t find_l1(const int4* l1_o, int64_t n, int4 o) {
-  int64_t lo = 0, hi = n;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (l1_before(l1_o[mid], o)) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
 
 // One wave per leaf: tile[i] = 1 iff its mask is full and its 512 values share one
 // bit pattern (a full leaf's values are contiguous at off[i]); keep[i] = 1 - tile[i].
@@ -70,7 +49,7 @@ __global__ void k_prune_leaves(const int4* leaf_o, const uint64_t* mask, const u
   const int4 o = leaf_o[i];
   if (tile[i]) {
     const int4 lo = make_int4(o.x & ~127, o.y & ~127, o.z & ~127, 0);
-    const int64_t node = find_l1(l1_o, n_l1, lo);
+    const int64_t node = lower_l1(l1_o, n_l1, lo);
     const uint32_t n1 = (uint32_t)((((o.x >> 3) & 15) << 8) | (((o.y >> 3) & 15) << 4) | ((o.z >> 3) & 15));
     const uint64_t t = pre_tile[i];
     tile_key[t] = ((uint32_t)node << 12) | n1;

@@ -26,6 +26,29 @@ struct QueryTree {
   int64_t n_leaf;
 };
 
+// Canonical order of level-1 nodes: level-2 origin (x, y, z), then the slot n2.
+__device__ __forceinline__ bool l1_before(int4 a, int4 b) {
+  const int ax = a.x & ~4095, ay = a.y & ~4095, az = a.z & ~4095;
+  const int bx = b.x & ~4095, by = b.y & ~4095, bz = b.z & ~4095;
+  if (ax != bx) return ax < bx;
+  if (ay != by) return ay < by;
+  if (az != bz) return az < bz;
+  const int na = (((a.x >> 7) & 31) << 10) | (((a.y >> 7) & 31) << 5) | ((a.z >> 7) & 31);
+  const int nb = (((b.x >> 7) & 31) << 10) | (((b.y >> 7) & 31) << 5) | ((b.z >> 7) & 31);
+  return na < nb;
+}
+// First index among the n canonical level-1 origins that is not before o (o itself
+// when that node exists).
+__device__ __forceinline__ int64_t lower_l1(const int4* l1_o, int64_t n, int4 o) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (l1_before(l1_o[mid], o)) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // Index of the leaf of t with origin o, or -1.
 __device__ __forceinline__ int64_t find_leaf(const QueryTree& t, const int4& o) {
   int64_t a = 0, b = t.n_leaf;

@@ -231,3 +231,48 @@ def test_archive_with_tiles(gpu_lib, fog):
     assert np.array_equal(v_d, r.decode_tiles(tr).cpu().numpy())
     want, _ = r.decode(tr, values=True, masks=False)
     assert np.array_equal(de["values"], want.cpu().numpy())
+
+
+@pytest.mark.parametrize("batch", [0, 1000])
+def test_query_with_tiles(gpu_lib, fog, batch):
+    """Random access through the tiles (Sec. 3.3.1, 3.5): voxel hits get the
+    regressor at the query position, queries inside an active tile get the tile
+    regressor's value (bit-equal to the library's tile decode), the rest the
+    background; hit flags 1 / 2 / 0; FP32 against the oracle.  The allocation-free
+    variant, whose scratch holds voxel hits only, refuses such a tree."""
+    tr, ot = fog
+    nets = {0: (64, 3, 18, 1), 3: (64, 3, 18, 1)}
+    m = gpu_lib.Model(nets, precision=gpu_lib.FP32, domain_size=128, value_scale=1.0)
+    th = {k: workloads.init_params(36, 64, 3, 1, seed=90 + k) for k in nets}
+    B = workloads.pe_matrix(6)
+    for k in nets:
+        m.set_params(k, th[k])
+        m.set_encoding(k, B)
+    rng = np.random.default_rng(11)
+    t_pick = rng.integers(0, len(ot["tile_value"]), 300)
+    q = np.concatenate([ot["tile_origin"][t_pick] + rng.uniform(0.0, 8.0, (300, 3)),
+                        ot["ijk"][rng.integers(0, len(ot["ijk"]), 300)] + rng.uniform(0.0, 1.0, (300, 3)),
+                        rng.uniform(-20.0, 150.0, (3000, 3)), [[np.nan, 1, 1], [1e12, 0, 0]]]).astype(np.float32)
+    v, h = m.query(tr, torch.from_numpy(q).to(DEV), background=-1.0, batch=batch, return_hits=True)
+    v, h = v.cpu().numpy(), h.cpu().numpy()
+    shapes = mlp.layer_shapes(36, 64, 3, 1)
+    want, whits = F.query_values(th[0].astype(np.float64), shapes, B.astype(np.float64), ot, (0, 0, 0), 128, T.FOG,
+                                 THR, q.astype(np.float64), background=-1.0,
+                                 tile=(th[3].astype(np.float64), shapes, B.astype(np.float64)))
+    tq = F.query_tiles(ot, q.astype(np.float64))
+    assert np.array_equal(h == 1, whits) and np.array_equal(h == 2, tq >= 0)
+    assert np.all(h[:300] == 2) and np.all(h[300:600] == 1)
+    assert np.all(np.abs(v - want) <= 1e-6 * (1 + np.abs(want))), np.abs(v - want).max()
+    dec = m.decode_tiles(tr).cpu().numpy()
+    assert np.array_equal(v[h == 2], dec[tq[h == 2]])
+    assert np.all(v[h == 0] == -1.0)
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        m.query_noalloc(tr, torch.from_numpy(q).to(DEV), background=-1.0)
+    assert e.value.code == gpu_lib.E_UNSUPPORTED
+    # a model without the tile regressor treats the tiles as misses
+    r = gpu_lib.Model({0: nets[0]}, precision=gpu_lib.FP32, domain_size=128, value_scale=1.0)
+    r.set_params(0, th[0])
+    r.set_encoding(0, B)
+    v0, h0 = r.query(tr, torch.from_numpy(q).to(DEV), background=-1.0, batch=batch, return_hits=True)
+    h0 = h0.cpu().numpy()
+    assert np.array_equal(h0, np.where(h == 1, 1, 0)) and np.all(v0.cpu().numpy()[h == 2] == -1.0)
