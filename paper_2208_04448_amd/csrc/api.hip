@@ -56,8 +56,12 @@ struct nvdb_model {
   hipEvent_t done = nullptr;
   // [0]: explicit sample indices found at or beyond their population size
   nvdb::DevBuf<unsigned long long> errw;
+  // events of the optional per-launch timing of nvdb_fit, created once and reused
+  // (creating thousands per call would leave the device idle before every fit)
+  std::vector<hipEvent_t> timing;
   ~nvdb_model() {
     if (done) (void)hipEventDestroy(done);
+    for (auto e : timing) (void)hipEventDestroy(e);
   }
 };
 
@@ -784,29 +788,31 @@ nvdb_status nvdb_fit(nvdb_model* m, const nvdb_tree* tree, const nvdb_fit_desc* 
     const Phase ph{fit->batch, fit->seed, fit->lr, fit->lr_decay, fit->lr_interval, fit};
 
     // optional timing of the training-kernel launches with HIP events on `stream`
-    std::vector<hipEvent_t> ev;
-    if (fit->train_kernel_ms) {
-      ev.resize(2 * (size_t)fit->steps * groups.size());
-      for (auto& e : ev) NVDB_HIP(hipEventCreate(&e));
+    const size_t n_ev = fit->train_kernel_ms ? 2 * (size_t)fit->steps * groups.size() : 0;
+    if (n_ev) NVDB_HIP(hipStreamSynchronize(st));  // earlier timed fits may still use the cached events
+    while (m->timing.size() < n_ev) {
+      hipEvent_t e = nullptr;
+      NVDB_HIP(hipEventCreate(&e));
+      m->timing.push_back(e);
     }
+    hipEvent_t* ev = n_ev ? m->timing.data() : nullptr;
     for (int step = 0; step < fit->steps; ++step) {
       StepHooks hk;
       for (int k : nets) hk.loss_out[k] = m->nets[k].losses.p + step;
-      enqueue_step(m, tree, groups, ph, step, hk, ev.empty() ? nullptr : ev.data() + 2 * groups.size() * step, st);
+      enqueue_step(m, tree, groups, ph, step, hk, ev ? ev + 2 * groups.size() * step : nullptr, st);
     }
     mark(m, st);
     bool lists = false;
     for (int k : nets) lists = lists || fit->idx_dev[k] != nullptr;
     if (lists) NVDB_REQUIRE(take_bad_indices(m) == 0, NVDB_E_INVALID, "sample index at or beyond its population size");
-    if (!ev.empty()) {
-      NVDB_HIP(hipEventSynchronize(ev.back()));
+    if (n_ev) {
+      NVDB_HIP(hipEventSynchronize(ev[n_ev - 1]));
       double tot = 0.0;
-      for (size_t i = 0; i + 1 < ev.size(); i += 2) {
+      for (size_t i = 0; i + 1 < n_ev; i += 2) {
         float ms = 0.f;
         NVDB_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
         tot += ms;
       }
-      for (auto& e : ev) (void)hipEventDestroy(e);
       *fit->train_kernel_ms = (float)tot;
     }
     if (loss_host) {
