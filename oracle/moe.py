@@ -113,6 +113,31 @@ def decode_moe_l1(slot_origins, experts, origin, S, h):
     return np.argmax(np.where(np.isnan(logits), -np.inf, logits), axis=1), logits
 
 
+def decode_moe_tiles(tile_origins, experts, origin, S, h):
+    """Blended values of active tiles (Sec. 3.3.1 tile values under the
+    decomposition of Sec. 3.4): each expert's tile value regressor at the tile's
+    leaf-slot centre, x = (o - lo + 4) / D, scaled by the expert's value scale and
+    averaged with the gates at the slot centres (those of decode_moe_l1).  Tiles
+    that no gate covers get NaN."""
+    check_geometry(S, h)
+    o = np.asarray(tile_origins, np.int64).reshape(-1, 3)
+    num = np.zeros(len(o))
+    den = np.zeros(len(o))
+    for e in experts:
+        g = gate_leaf_slot(o, e["cell"], origin, S, h)
+        sel = g > 0
+        if not sel.any():
+            continue
+        x = mlp.normalize_leaf_slot(o[sel], e["lo"], e["D"])
+        y = mlp.predict(mlp.unflatten(e["theta"], e["shapes"]), x, e["B"])[:, 0]
+        num[sel] += g[sel] * y * float(e["scale"])
+        den[sel] += g[sel]
+    out = np.full(len(o), np.nan)
+    ok = den > 0
+    out[ok] = num[ok] / den[ok]
+    return out
+
+
 def subdomain_voxels(ijk, values, cell, origin, S, h):
     """Voxels (coordinates, values) of the widened box of `cell`: the training
     set of its expert."""

@@ -2,7 +2,8 @@
 values in closed form, partition of unity, the eight-expert bound, kept cells
 by brute force, subdomain sizes of a dense block, the blend of constant
 experts (linear interpolation across the overlap), and the single-expert case
-reducing to the plain decode."""
+reducing to the plain decode, for voxel values, level-1 classes and active-tile
+values."""
 import itertools
 
 import numpy as np
@@ -211,3 +212,41 @@ def test_level1_single_expert_is_the_plain_decode():
     assert inside.sum() == 729 and np.all(np.isnan(lg[~inside]))
     assert np.allclose(lg[inside], want[inside], rtol=0, atol=1e-12)
     assert np.array_equal(cls[inside], F.l1_classes(want[inside]))
+
+
+def test_tiles_single_expert_is_the_plain_tile_decode():
+    # the pruned fog's active tiles all lie in the one cell's widened box [-8, 72)^3,
+    # so the blend is the expert itself: the plain tile decode of Sec. 3.3.1
+    v = workloads.saturated_fog().numpy()
+    tr = T.prune_tiles(T.build(*T.active_set_dense(v, (0, 0, 0), T.FOG, 0.05)))
+    assert len(tr["tile_value"]) >= 4
+    S, h, o = 64, 8, (0, 0, 0)
+    K, W, H = 36, 64, 3
+    shapes = mlp.layer_shapes(K, W, H, 1)
+    theta = workloads.init_params(K, W, H, 1, seed=9).astype(np.float64)
+    B = mlp.pe_matrix(6)
+    lo, D = moe.widened_box((0, 0, 0), o, S, h)
+    e = dict(cell=(0, 0, 0), theta=theta, shapes=shapes, B=B, lo=lo, D=D, scale=1.0)
+    got = moe.decode_moe_tiles(tr["tile_origin"], [e], o, S, h)
+    want = F.decode_tiles(theta, shapes, B, tr, lo, D, T.FOG, 0.05)
+    assert np.allclose(got, want, rtol=0, atol=1e-12)
+    # a value scale multiplies the output; a tile outside every box gets NaN
+    e2 = dict(e, scale=2.5)
+    assert np.allclose(moe.decode_moe_tiles(tr["tile_origin"], [e2], o, S, h), 2.5 * want, rtol=0, atol=1e-12)
+    assert np.isnan(moe.decode_moe_tiles([[80, 0, 0]], [e], o, S, h)).all()
+
+
+def test_tiles_blend_of_constant_experts():
+    # two cells along x with constant outputs 1 and 3 (value scales 1 and 2, so
+    # 1 and 6 in value units): the blend interpolates linearly across the overlap
+    # [24, 40), slot centres 28 and 36 with expert 1's share 0.25 and 0.75
+    S, h, org = 32, 8, (0, 0, 0)
+    e0 = const_expert((0, 0, 0), 1.0, org, S, h)
+    e1 = dict(const_expert((1, 0, 0), 3.0, org, S, h), scale=2.0)
+    xs = np.arange(0, 64, 8)
+    o = np.stack([xs, np.full_like(xs, 8), np.full_like(xs, 8)], 1)
+    got = moe.decode_moe_tiles(o, [e0, e1], org, S, h)
+    assert np.allclose(got, [1, 1, 1, 2.25, 4.75, 6, 6, 6], rtol=0, atol=1e-12)
+    # the same gates as the level-1 blend: tile value = sum g c / sum g
+    g = np.stack([moe.gate_leaf_slot(o, e["cell"], org, S, h) for e in (e0, e1)])
+    assert np.allclose(got, (g[0] * 1.0 + g[1] * 6.0) / g.sum(0), rtol=0, atol=1e-12)
