@@ -440,8 +440,9 @@ typedef struct {
   int32_t halo;
 } nvdb_subdomains;
 
-/* The cells whose core holds an active voxel of `tree` (the others are
- * dropped, as the paper drops empty subdomains), ascending in (cx, cy, cz):
+/* The cells whose core holds an active voxel of `tree`, or meets the 8^3 region
+ * of one of its active tiles (the others are dropped, as the paper drops empty
+ * subdomains), ascending in (cx, cy, cz):
  * the first min(n, cap) go to cells int32[cap][3] (host), the count n to
  * *n_cells.  Synchronises `stream`.  Errors: E_INVALID (null arguments, bad
  * grid, a tree spanning more than 2^24 candidate cells). */
@@ -512,6 +513,20 @@ nvdb_status nvdb_decode_moe_mask(const nvdb_model* const* experts, const int32_t
 nvdb_status nvdb_decode_moe_l1(const nvdb_model* const* experts, const int32_t* cells, int32_t n_experts,
                                const nvdb_subdomains* grid, const nvdb_tree* tree, uint8_t* classes_dev,
                                void* stream);
+
+/* The same blend for the values of active tiles (Sec. 3.3.1 tiles under the
+ * decomposition of Sec. 3.4): expert k's tile value regressor runs at every
+ * active tile of the tree that its widened box holds, at x = (o - domain_lo + 4)
+ * / domain_size for the tile at leaf-slot origin o, times the expert's value
+ * scale; the values are blended with the gates taken at the tile's centre o + 4
+ * (the gates of nvdb_decode_moe_l1).  tile_values_dev is float[n_tiles] in the
+ * tree's tile order (as nvdb_decode_tiles).  The cell size, the halo and the grid
+ * origin must be multiples of 8.  Synchronisation, scratch (32 B per tile) and
+ * errors as nvdb_decode_moe, E_STATE for an unset tile value regressor; a tree
+ * without tiles returns at once. */
+nvdb_status nvdb_decode_moe_tiles(const nvdb_model* const* experts, const int32_t* cells, int32_t n_experts,
+                                  const nvdb_subdomains* grid, const nvdb_tree* tree, float* tile_values_dev,
+                                  void* stream);
 
 /* Level-1 classifier report (Sec. 3.3.1, Sec. 4) over the 4096 leaf slots of
  * every level-1 node: classes_dev is uint8[n_l1][4096] as written by

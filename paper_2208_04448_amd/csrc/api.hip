@@ -1696,10 +1696,22 @@ nvdb_status nvdb_subdomain_cells(const nvdb_tree* tree, const nvdb_subdomains* g
     NVDB_REQUIRE(cap >= 0 && (cap == 0 || cells), NVDB_E_INVALID, "bad cell buffer");
     MoeGrid g = check_grid(grid);
     *n_cells = 0;
-    if (tree->n_vox == 0) return;
+    if (tree->n_vox == 0 && tree->n_tile == 0) return;
     hipStream_t st = (hipStream_t)stream;
-    int32_t lo[3], hi[3];
-    leaf_bbox(*tree, lo, hi, st);
+    int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+    if (tree->n_leaf > 0) leaf_bbox(*tree, lo, hi, st);
+    if (tree->n_tile > 0) {  // the active tiles lie in the level-1 nodes
+      std::vector<int4> l1((size_t)tree->n_l1);
+      NVDB_HIP(hipMemcpyAsync(l1.data(), tree->l1_o.p, l1.size() * sizeof(int4), hipMemcpyDeviceToHost, st));
+      NVDB_HIP(hipStreamSynchronize(st));
+      for (const int4& o : l1) {
+        const int32_t c[3] = {o.x, o.y, o.z};
+        for (int d = 0; d < 3; ++d) {
+          lo[d] = std::min(lo[d], c[d]);
+          hi[d] = std::max(hi[d], c[d] + 128);
+        }
+      }
+    }
     for (int d = 0; d < 3; ++d) {
       const int64_t a = floor_div64((int64_t)lo[d] - g.o[d], g.S), b = floor_div64((int64_t)hi[d] - 1 - g.o[d], g.S);
       NVDB_REQUIRE(b - a + 1 <= MOE_MAX_RANGE, NVDB_E_INVALID, "the tree spans more than 2^24 cells");
@@ -1779,27 +1791,35 @@ nvdb_status nvdb_tree_subdomain(const nvdb_tree* tree, const nvdb_subdomains* gr
 }  // extern "C"
 
 // Blended decode over the active voxels (regressors, values), over every voxel
-// slot of the leaves (level-0 classifiers, mask bits) or over every leaf slot of
-// the level-1 nodes (level-1 classifiers, classes).
+// slot of the leaves (level-0 classifiers, mask bits), over every leaf slot of
+// the level-1 nodes (level-1 classifiers, classes) or over the active tiles (tile
+// value regressors, values).
 static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cells, int32_t n_experts,
                             const nvdb_subdomains* grid, const nvdb_tree* tree, int net, float* values_dev,
                             uint64_t* mask_dev, uint8_t* cls_dev, hipStream_t st) {
   NVDB_REQUIRE(experts && cells && tree, NVDB_E_INVALID, "null argument");
   NVDB_REQUIRE(n_experts >= 1 && n_experts <= MOE_MAX_EXPERTS, NVDB_E_INVALID, "expert count outside [1, 4096]");
   const bool slots = net == NVDB_NET_L0;
-  const int kind = net == NVDB_NET_REGRESSOR ? MOE_VOXELS : (net == NVDB_NET_L0 ? MOE_VOXEL_SLOTS : MOE_LEAF_SLOTS);
-  const int64_t n = kind == MOE_VOXELS ? tree->n_vox : (kind == MOE_VOXEL_SLOTS ? 512 * tree->n_leaf : 4096 * tree->n_l1);
+  const int kind = net == NVDB_NET_REGRESSOR ? MOE_VOXELS
+                   : net == NVDB_NET_L0      ? MOE_VOXEL_SLOTS
+                   : net == NVDB_NET_L1      ? MOE_LEAF_SLOTS
+                                             : MOE_TILES;
+  const bool valued = kind == MOE_VOXELS || kind == MOE_TILES;  // value outputs, in value units
+  const int64_t n = kind == MOE_VOXELS        ? tree->n_vox
+                    : kind == MOE_VOXEL_SLOTS ? 512 * tree->n_leaf
+                    : kind == MOE_LEAF_SLOTS  ? 4096 * tree->n_l1
+                                              : tree->n_tile;
   const int C = kind == MOE_LEAF_SLOTS ? 3 : 1;
   NVDB_REQUIRE(n < (1ll << 29), NVDB_E_INVALID, "the blended decode takes fewer than 2^29 voxels or slots");
-  NVDB_REQUIRE(n == 0 || (kind == MOE_VOXELS ? values_dev != nullptr
-                                             : (kind == MOE_VOXEL_SLOTS ? mask_dev != nullptr : cls_dev != nullptr)),
+  NVDB_REQUIRE(n == 0 || (valued ? values_dev != nullptr
+                                 : (kind == MOE_VOXEL_SLOTS ? mask_dev != nullptr : cls_dev != nullptr)),
                NVDB_E_INVALID, "null output");
   MoeGrid g = check_grid(grid);
   if (kind != MOE_VOXELS)
     NVDB_REQUIRE(g.S % 8 == 0 && g.o[0] % 8 == 0 && g.o[1] % 8 == 0 && g.o[2] % 8 == 0, NVDB_E_INVALID,
                  "the slot decodes need a cell size and grid origin that are multiples of 8");
-  if (kind == MOE_LEAF_SLOTS)
-    NVDB_REQUIRE(g.h % 8 == 0, NVDB_E_INVALID, "the level-1 decode needs a halo that is a multiple of 8");
+  if (kind == MOE_LEAF_SLOTS || kind == MOE_TILES)
+    NVDB_REQUIRE(g.h % 8 == 0, NVDB_E_INVALID, "the level-1 and tile decodes need a halo that is a multiple of 8");
   std::vector<MoeBox> box((size_t)n_experts);
   for (int k = 0; k < n_experts; ++k) {
     NVDB_REQUIRE(experts[k] != nullptr, NVDB_E_INVALID, "null expert");
@@ -1866,7 +1886,7 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
     for (size_t k = 0; k < E; ++k) {
       GroupNet gn{};
       gn.net = net_view(net_of(experts[k], net));
-      gn.out_scale = kind == MOE_VOXELS ? experts[k]->d.value_scale : 1.f;
+      gn.out_scale = valued ? experts[k]->d.value_scale : 1.f;
       std::memcpy(hs + o_nets + k * sizeof(GroupNet), &gn, sizeof(GroupNet));
     }
     uint32_t* back = (uint32_t*)(hs + small_bytes);  // uncovered items, overflow flag
@@ -1899,7 +1919,7 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
       M.slot = bslot;
       M.yslot = yslot;
       launch_infer_group(ks0, M, st);
-      moe_blend(*tree, kind, g, tab, yslot, kind == MOE_VOXELS ? values_dev : nullptr,
+      moe_blend(*tree, kind, g, tab, yslot, valued ? values_dev : nullptr,
                 kind == MOE_VOXEL_SLOTS ? mask_dev : nullptr, kind == MOE_LEAF_SLOTS ? cls_dev : nullptr, st);
       NVDB_HIP(hipMemcpyAsync(back, cnt + n_experts, 4, hipMemcpyDeviceToHost, st));
       NVDB_HIP(hipMemcpyAsync(back + 1, flag, 4, hipMemcpyDeviceToHost, st));
@@ -2002,6 +2022,15 @@ nvdb_status nvdb_decode_moe_l1(const nvdb_model* const* experts, const int32_t* 
                                void* stream) {
   return guarded([&] {
     decode_moe_impl(experts, cells, n_experts, grid, tree, NVDB_NET_L1, nullptr, nullptr, classes_dev,
+                    (hipStream_t)stream);
+  });
+}
+
+nvdb_status nvdb_decode_moe_tiles(const nvdb_model* const* experts, const int32_t* cells, int32_t n_experts,
+                                  const nvdb_subdomains* grid, const nvdb_tree* tree, float* tile_values_dev,
+                                  void* stream) {
+  return guarded([&] {
+    decode_moe_impl(experts, cells, n_experts, grid, tree, NVDB_NET_TILE, tile_values_dev, nullptr, nullptr,
                     (hipStream_t)stream);
   });
 }

@@ -27,7 +27,7 @@ namespace {
 // Where the items of a blended decode come from.
 struct ItemSrc {
   const int4* org;      // leaf origins, or level-1 origins (leaf-slot items)
-  const uint32_t* key;  // voxel keys (voxel items), or null
+  const uint32_t* key;  // voxel keys (voxel items), active-tile keys (l1), or null
   int l1;               // 1: leaf slots of the level-1 nodes
 };
 
@@ -159,6 +159,27 @@ __global__ void __launch_bounds__(256) k_moe_mark(const int4* __restrict__ leaf_
     flag[(ix * g.cdim[1] + iy) * g.cdim[2] + iz] = 1;
 }
 
+// Per active tile: every cell whose core meets the tile's 8^3 region (a tile
+// straddles several cores when the grid is not aligned to 8).
+__global__ void __launch_bounds__(256) k_moe_mark_tiles(const int4* __restrict__ l1_o,
+                                                        const uint32_t* __restrict__ tkey, int64_t n, MoeGrid g,
+                                                        uint8_t* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t k = tkey[i], n1 = k & 4095u;
+  const int4 o = l1_o[k >> 12];
+  const int p[3] = {o.x + 8 * (int)(n1 >> 8), o.y + 8 * (int)((n1 >> 4) & 15u), o.z + 8 * (int)(n1 & 15u)};
+  int64_t a[3], b[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    a[d] = max(floor_div((int64_t)p[d] - g.o[d], g.S) - g.clo[d], (int64_t)0);
+    b[d] = min(floor_div((int64_t)p[d] + 7 - g.o[d], g.S) - g.clo[d], (int64_t)g.cdim[d] - 1);
+  }
+  for (int64_t ix = a[0]; ix <= b[0]; ++ix)
+    for (int64_t iy = a[1]; iy <= b[1]; ++iy)
+      for (int64_t iz = a[2]; iz <= b[2]; ++iz) flag[(ix * g.cdim[1] + iy) * g.cdim[2] + iz] = 1;
+}
+
 // Voxels inside a widened box [lo, lo + D)^3, appended (one global atomic per
 // block).
 __global__ void __launch_bounds__(256) k_moe_extract(const int4* __restrict__ leaf_o, const uint32_t* __restrict__ key,
@@ -197,12 +218,14 @@ __global__ void __launch_bounds__(256) k_moe_extract(const int4* __restrict__ le
 }
 
 // Item i is voxel i (key[i] = leaf << 9 | n0), or, with key null, voxel slot i of
-// the leaves (i = leaf << 9 | n0 itself), or (l1) leaf slot i & 4095 of level-1
-// node i >> 12, positioned at the slot's origin.
+// the leaves (i = leaf << 9 | n0 itself), or (l1) leaf slot k & 4095 of level-1
+// node k >> 12, positioned at the slot's origin, with k = i, or k = key[i] for the
+// active tiles.
 __device__ __forceinline__ int3 item_of(const ItemSrc& s, int64_t i) {
   if (s.l1) {
-    const int4 o = s.org[i >> 12];
-    const int n1 = (int)(i & 4095);
+    const int64_t k = s.key ? (int64_t)s.key[i] : i;
+    const int4 o = s.org[k >> 12];
+    const int n1 = (int)(k & 4095);
     return make_int3(o.x + 8 * (n1 >> 8), o.y + 8 * ((n1 >> 4) & 15), o.z + 8 * (n1 & 15));
   }
   return voxel_of(s.org, s.key ? s.key[i] : (uint32_t)i);
@@ -410,9 +433,10 @@ __global__ void __launch_bounds__(256) k_moe_route_leaf(const int4* __restrict__
 }
 
 // Gate-weighted average of the expert outputs held in the item's 8 slots: a
-// value per voxel, or (mask non-null) the bit "blended logit > 0" per voxel slot,
-// packed 64 to a word by the wave that computed them, or (cls non-null, leaf-slot
-// items) the class of the three blended logits (argmax, ties to the lowest).
+// value per voxel (or per active tile, gated at the tile's centre), or (mask
+// non-null) the bit "blended logit > 0" per voxel slot, packed 64 to a word by the
+// wave that computed them, or (cls non-null, leaf-slot items) the class of the
+// three blended logits (argmax, ties to the lowest).
 __global__ void __launch_bounds__(256) k_moe_blend(ItemSrc src, int64_t n, MoeGrid g,
                                                    const int32_t* __restrict__ table,
                                                    const float* __restrict__ yslot, float* __restrict__ values,
@@ -437,7 +461,7 @@ __global__ void __launch_bounds__(256) k_moe_blend(ItemSrc src, int64_t n, MoeGr
   if (i < n) {
     const int3 p = item_of(src, i);
     float num = 0.f, den = 0.f;
-    for_each_expert(g, table, p, 1, [&](int j, int, float w) {
+    for_each_expert(g, table, p, src.l1 ? 8 : 1, [&](int j, int, float w) {
       num += w * yslot[8 * i + j];
       den += w;
     });
@@ -473,9 +497,16 @@ void leaf_bbox(const Tree& t, int32_t lo[3], int32_t hi[3], hipStream_t st) {
 }
 
 void moe_mark_cells(const Tree& t, const MoeGrid& g, uint8_t* flag, hipStream_t st) {
-  if (t.n_vox == 0) return;
-  hipLaunchKernelGGL(k_moe_mark, dim3(grid_of(t.n_vox)), dim3(256), 0, st, t.leaf_o.p, t.vox_key.p, t.n_vox, g, flag);
-  NVDB_HIP(hipGetLastError());
+  if (t.n_vox > 0) {
+    hipLaunchKernelGGL(k_moe_mark, dim3(grid_of(t.n_vox)), dim3(256), 0, st, t.leaf_o.p, t.vox_key.p, t.n_vox, g,
+                       flag);
+    NVDB_HIP(hipGetLastError());
+  }
+  if (t.n_tile > 0) {
+    hipLaunchKernelGGL(k_moe_mark_tiles, dim3(grid_of(t.n_tile)), dim3(256), 0, st, t.l1_o.p, t.tile_key.p, t.n_tile,
+                       g, flag);
+    NVDB_HIP(hipGetLastError());
+  }
 }
 
 int64_t moe_extract(const Tree& t, const int32_t lo[3], int32_t D, int32_t* ijk, float* v, uint32_t* count,
@@ -493,16 +524,18 @@ int64_t moe_extract(const Tree& t, const int32_t lo[3], int32_t D, int32_t* ijk,
 }
 
 static int64_t items(const Tree& t, int kind) {
+  if (kind == MOE_TILES) return t.n_tile;
   return kind == MOE_VOXELS ? t.n_vox : (kind == MOE_VOXEL_SLOTS ? 512 * t.n_leaf : 4096 * t.n_l1);
 }
 static ItemSrc item_src(const Tree& t, int kind) {
   if (kind == MOE_LEAF_SLOTS) return ItemSrc{t.l1_o.p, nullptr, 1};
+  if (kind == MOE_TILES) return ItemSrc{t.l1_o.p, t.tile_key.p, 1};
   return ItemSrc{t.leaf_o.p, kind == MOE_VOXELS ? t.vox_key.p : nullptr, 0};
 }
 
 // Voxel and voxel-slot items of a leaf-aligned grid are routed per leaf.
 static bool per_leaf(const MoeGrid& g, int kind) {
-  return kind != MOE_LEAF_SLOTS && ((g.o[0] | g.o[1] | g.o[2] | g.S | g.h) & 7) == 0;
+  return (kind == MOE_VOXELS || kind == MOE_VOXEL_SLOTS) && ((g.o[0] | g.o[1] | g.o[2] | g.S | g.h) & 7) == 0;
 }
 static unsigned leaf_grid(int64_t n_leaf, int per_block, int64_t max_blocks) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(max_blocks, (n_leaf + per_block - 1) / per_block));

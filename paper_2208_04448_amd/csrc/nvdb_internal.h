@@ -375,7 +375,7 @@ int64_t moe_extract(const Tree& t, const int32_t lo[3], int32_t D, int32_t* ijk,
 // routing and blend over the active voxels, or (slots) over every voxel slot of the leaves
 // items of a blended decode: the voxels, the voxel slots of the leaves, or the
 // leaf slots of the level-1 nodes
-enum : int { MOE_VOXELS = 0, MOE_VOXEL_SLOTS = 1, MOE_LEAF_SLOTS = 2 };
+enum : int { MOE_VOXELS = 0, MOE_VOXEL_SLOTS = 1, MOE_LEAF_SLOTS = 2, MOE_TILES = 3 };
 void moe_count(const Tree& t, int kind, const MoeGrid& g, const int32_t* table, int n_exp, uint32_t* cnt,
                uint32_t* uncovered, hipStream_t st);
 void moe_route(const Tree& t, int kind, const MoeGrid& g, const int32_t* table, const MoeBox* box, int n_exp,

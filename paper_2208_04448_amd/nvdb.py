@@ -123,6 +123,7 @@ _SIGS = {
     "nvdb_decode_moe": (C.c_int32, [C.POINTER(_P), _P, C.c_int32, C.POINTER(Subdomains), _P, _P, _P]),
     "nvdb_decode_moe_mask": (C.c_int32, [C.POINTER(_P), _P, C.c_int32, C.POINTER(Subdomains), _P, _P, _P]),
     "nvdb_decode_moe_l1": (C.c_int32, [C.POINTER(_P), _P, C.c_int32, C.POINTER(Subdomains), _P, _P, _P]),
+    "nvdb_decode_moe_tiles": (C.c_int32, [C.POINTER(_P), _P, C.c_int32, C.POINTER(Subdomains), _P, _P, _P]),
     "nvdb_tree_export": (C.c_int32, [_P, _P, _P, _P, _P, _P, _P]),
     "nvdb_tree_free": (None, [_P]),
     "nvdb_model_create": (C.c_int32, [C.POINTER(ModelDesc), C.POINTER(_P)]),
@@ -679,6 +680,19 @@ def decode_moe_l1(experts, cells, origin, size, halo, tree):
     out = torch.empty((tree.info().n_l1, 4096), dtype=torch.uint8, device="cuda")
     _check(_lib.nvdb_decode_moe_l1(hs, cells.ctypes.data_as(C.c_void_p), len(experts), C.byref(g), tree.h,
                                    _ptr(out), _stream()))
+    return out
+
+
+def decode_moe_tiles(experts, cells, origin, size, halo, tree):
+    """Blended active-tile values (float32 [n_tiles], device) of the experts' tile value regressors."""
+    import torch
+    cells = np.ascontiguousarray(np.asarray(cells, np.int32).reshape(-1, 3))
+    assert len(cells) == len(experts)
+    hs = (_P * len(experts))(*[e.h for e in experts])
+    g = Subdomains(_i3(origin), int(size), int(halo))
+    out = torch.empty(tree.info().n_tiles, dtype=torch.float32, device="cuda")
+    _check(_lib.nvdb_decode_moe_tiles(hs, cells.ctypes.data_as(C.c_void_p), len(experts), C.byref(g), tree.h,
+                                      _ptr(out), _stream()))
     return out
 
 

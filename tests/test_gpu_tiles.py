@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import workloads
-from oracle import fit as F, mlp, tree as T
+from oracle import fit as F, mlp, moe, tree as T
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -276,3 +276,55 @@ def test_query_with_tiles(gpu_lib, fog, batch):
     v0, h0 = r.query(tr, torch.from_numpy(q).to(DEV), background=-1.0, batch=batch, return_hits=True)
     h0 = h0.cpu().numpy()
     assert np.array_equal(h0, np.where(h == 1, 1, 0)) and np.all(v0.cpu().numpy()[h == 2] == -1.0)
+
+
+def _tile_voxels(ot):
+    off = np.stack(np.meshgrid(*[np.arange(8)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    return (ot["tile_origin"][:, None, :] + off[None]).reshape(-1, 3)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_decode_moe_tiles_matches_oracle(gpu_lib, fog, prec):
+    """Blended active-tile values under the sparse domain decomposition (Sec.
+    3.3.1 tiles, Sec. 3.4 gates): the kept cells count the tiles' voxels, each
+    expert's tile value regressor (own box, value scale 1.5) runs at the tiles in
+    its widened box, blended with the gates at the tile centres, against the
+    oracle's blend; a halo that is not a multiple of 8 is refused and a tree
+    without tiles decodes to nothing."""
+    tr, ot = fog
+    origin, size, halo = (0, 0, 0), 48, 8
+    cells = gpu_lib.subdomain_cells(tr, origin, size, halo)
+    want_cells = moe.kept_cells(np.concatenate([ot["ijk"], _tile_voxels(ot)]), origin, size)
+    assert np.array_equal(cells, want_cells.astype(np.int32))
+    W, H, m = 64, 3, 18
+    shapes = mlp.layer_shapes(2 * m, W, H, 1)
+    B = workloads.pe_matrix(6)
+    p = gpu_lib.FP32 if prec == "fp32" else gpu_lib.BF16
+    models, ex = [], []
+    for k, c in enumerate(cells):
+        lo, D = gpu_lib.subdomain_box(origin, size, halo, c)
+        theta = workloads.init_params(2 * m, W, H, 1, seed=500 + k)
+        mdl = gpu_lib.Model({3: (W, H, m, 1)}, precision=p, domain_lo=lo, domain_size=D, value_scale=1.5)
+        mdl.set_params(3, theta)
+        mdl.set_encoding(3, B)
+        models.append(mdl)
+        ex.append(dict(cell=c, theta=theta.astype(np.float64), shapes=shapes, B=B.astype(np.float64), lo=lo, D=D,
+                       scale=1.5))
+    got = gpu_lib.decode_moe_tiles(models, cells, origin, size, halo, tr).cpu().numpy().astype(np.float64)
+    want = moe.decode_moe_tiles(ot["tile_origin"], ex, origin, size, halo)
+    n_exp = sum(moe.gate_leaf_slot(ot["tile_origin"], c, origin, size, halo) > 0 for c in cells)
+    assert np.all(n_exp >= 1) and (n_exp >= 2).sum() > 0  # tiles blended from several experts
+    tol = 3e-5 if p == gpu_lib.FP32 else 3e-3
+    assert np.all(np.abs(got - want) <= tol * (1 + np.abs(want))), np.abs(got - want).max()
+    if p == gpu_lib.BF16:  # an FP32 expert among BF16 ones: one decode launch per expert
+        m0 = gpu_lib.Model({3: (W, H, m, 1)}, precision=gpu_lib.FP32, domain_lo=ex[0]["lo"], domain_size=ex[0]["D"],
+                           value_scale=1.5)
+        m0.set_params(3, ex[0]["theta"].astype(np.float32))
+        m0.set_encoding(3, B)
+        mixed = gpu_lib.decode_moe_tiles([m0] + models[1:], cells, origin, size, halo, tr).cpu().numpy()
+        assert np.all(np.abs(mixed - want) <= tol * (1 + np.abs(want))), np.abs(mixed - want).max()
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        gpu_lib.decode_moe_tiles(models, cells, origin, size, 4, tr)
+    assert e.value.code == gpu_lib.E_INVALID
+    plain = gpu_lib.Tree(_fog(64).to(DEV), (0, 0, 0), T.FOG, THR)
+    assert gpu_lib.decode_moe_tiles(models, cells, origin, size, halo, plain).numel() == 0
