@@ -12,7 +12,10 @@
 // The blended decode routes every (voxel, expert) pair into a per-expert bucket
 // of normalised coordinates, runs each expert's forward pass over its bucket,
 // scatters the outputs into eight slots per voxel, and blends the slots in a
-// fixed order (deterministic: bucket order never reaches the sums).
+// fixed order (deterministic: bucket order never reaches the sums).  Slot j of
+// item i sits at j n + i: eight planes of n slots, so that one expert's outputs
+// for consecutive items land side by side and the blend reads each plane
+// coalesced.
 #include <algorithm>
 #include <cfloat>
 #include <climits>
@@ -279,7 +282,7 @@ __global__ void __launch_bounds__(256) k_moe_count(ItemSrc src, int64_t n, MoeGr
 }
 
 // Pass 2: writes each pair into its expert's bucket: the expert's normalised
-// coordinates and the voxel's slot 8 i + j.  A block counts its pairs per
+// coordinates and the item's slot j n + i.  A block counts its pairs per
 // expert, reserves one range per expert after `start[k]` with one atomic, then
 // walks its tiles again and fills the ranges (positions from fresh LDS
 // counters: any order within a range will do).
@@ -321,7 +324,7 @@ __global__ void __launch_bounds__(256) k_moe_route(ItemSrc src, int64_t n, MoeGr
       bx[3 * (size_t)s] = ((float)(p.x - b.lo[0]) + half) * b.inv_d;
       bx[3 * (size_t)s + 1] = ((float)(p.y - b.lo[1]) + half) * b.inv_d;
       bx[3 * (size_t)s + 2] = ((float)(p.z - b.lo[2]) + half) * b.inv_d;
-      bslot[s] = (uint32_t)(8 * i + j);
+      bslot[s] = (uint32_t)j * (uint32_t)n + (uint32_t)i;
     }
   }
 }
@@ -380,7 +383,8 @@ __global__ void __launch_bounds__(256) k_moe_route_leaf(const int4* __restrict__
                                                         const MoeBox* __restrict__ box, int n_exp,
                                                         const uint32_t* __restrict__ start,
                                                         uint32_t* __restrict__ cursor, float* __restrict__ bx,
-                                                        uint32_t* __restrict__ bslot, uint64_t cap) {
+                                                        uint32_t* __restrict__ bslot, uint32_t n_items,
+                                                        uint64_t cap) {
   extern __shared__ uint32_t lds[];  // 3 n_exp words
   uint32_t* hist = lds;
   uint32_t* base = lds + n_exp;
@@ -426,7 +430,7 @@ __global__ void __launch_bounds__(256) k_moe_route_leaf(const int4* __restrict__
         bx[3 * s] = ((float)(px - b.lo[0]) + 0.5f) * b.inv_d;
         bx[3 * s + 1] = ((float)(py - b.lo[1]) + 0.5f) * b.inv_d;
         bx[3 * s + 2] = ((float)(pz - b.lo[2]) + 0.5f) * b.inv_d;
-        bslot[s] = 8u * i + (uint32_t)j;
+        bslot[s] = (uint32_t)j * n_items + i;
       }
     }
   }
@@ -448,7 +452,7 @@ __global__ void __launch_bounds__(256) k_moe_blend(ItemSrc src, int64_t n, MoeGr
     float num[3] = {0.f, 0.f, 0.f}, den = 0.f;
     for_each_expert(g, table, p, 8, [&](int j, int, float w) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) num[c] += w * yslot[3 * (8 * i + j) + c];
+      for (int c = 0; c < 3; ++c) num[c] += w * yslot[3 * ((size_t)j * n + i) + c];
       den += w;
     });
     int best = 0;
@@ -462,7 +466,7 @@ __global__ void __launch_bounds__(256) k_moe_blend(ItemSrc src, int64_t n, MoeGr
     const int3 p = item_of(src, i);
     float num = 0.f, den = 0.f;
     for_each_expert(g, table, p, src.l1 ? 8 : 1, [&](int j, int, float w) {
-      num += w * yslot[8 * i + j];
+      num += w * yslot[(size_t)j * n + i];
       den += w;
     });
     v = den > 0.f ? num / den : __builtin_nanf("");
@@ -561,7 +565,7 @@ void moe_route(const Tree& t, int kind, const MoeGrid& g, const int32_t* table, 
     const bool vox = kind == MOE_VOXELS;
     hipLaunchKernelGGL(k_moe_route_leaf, dim3(leaf_grid(t.n_leaf, 4, 1024)), dim3(256), (size_t)n_exp * 12, st, t.leaf_o.p,
                        vox ? t.leaf_off.p : nullptr, vox ? t.vox_key.p : nullptr, t.n_leaf, g, table, box, n_exp,
-                       start, cursor, bx, bslot, cap);
+                       start, cursor, bx, bslot, (uint32_t)items(t, kind), cap);
   } else {
     hipLaunchKernelGGL(k_moe_route, dim3(route_grid(items(t, kind))), dim3(256), (size_t)n_exp * 12, st,
                        item_src(t, kind), items(t, kind), g, table, box, n_exp, start, cursor, bx, bslot, cap);
