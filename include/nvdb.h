@@ -562,17 +562,16 @@ nvdb_status nvdb_query(const nvdb_model* model, const nvdb_tree* tree, const flo
 
 /* nvdb_query without any device allocation, for callers that cannot allocate
  * (code under HIP graph capture, serving loops that forbid hipMalloc): the same
- * values and hit flags as nvdb_query, computed by the same kernels, with the
- * per-batch scratch (1.25 MiB: positions, outputs and indices of one batch of
- * at most 65536 queries, and the hit counter) in a static device array that each
- * GPU holds until the process ends.  batch 0 means 65536; a batch above 65536
- * is E_INVALID.  Asynchronous on `stream` (no synchronisation).  Every call on
- * one GPU shares that GPU's scratch: calls that overlap on one GPU (other
- * streams, other threads) race and must be serialised by the caller; calls on
- * one stream are ordered.  The scratch holds the voxel hits only: a tree with
- * active tiles queried with a model holding the tile regressor is E_UNSUPPORTED
- * here (nvdb_query serves it).  Errors as nvdb_query, E_DEVICE if the scratch's
- * device address cannot be obtained. */
+ * values and hit flags as nvdb_query, active tiles included, computed by the
+ * same kernels, with the per-batch scratch (2.5 MiB: positions, outputs and
+ * indices of the voxel hits and of the tile hits of one batch of at most 65536
+ * queries, and the two hit counters) in a static device array that each GPU
+ * holds until the process ends.  batch 0 means 65536; a batch above 65536 is
+ * E_INVALID.  Asynchronous on `stream` (no synchronisation).  Every call on one
+ * GPU shares that GPU's scratch: calls that overlap on one GPU (other streams,
+ * other threads) race and must be serialised by the caller; calls on one stream
+ * are ordered.  Errors as nvdb_query, E_DEVICE if the scratch's device address
+ * cannot be obtained. */
 nvdb_status nvdb_query_noalloc(const nvdb_model* model, const nvdb_tree* tree, const float* q_dev, int64_t n,
                                float background, int64_t batch, float* values_dev, uint8_t* hits_dev, void* stream);
 

@@ -1587,19 +1587,37 @@ nvdb_status nvdb_query_noalloc(const nvdb_model* m, const nvdb_tree* tree, const
     NVDB_REQUIRE(std::isfinite(background), NVDB_E_INVALID, "background must be finite");
     const Net& N = net_of(m, NVDB_NET_REGRESSOR);
     NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "regressor parameters or encoding not set");
-    NVDB_REQUIRE(!(tree->n_tile > 0 && m->nets[NVDB_NET_TILE].present), NVDB_E_UNSUPPORTED,
-                 "active tiles need nvdb_query (the static scratch holds the voxel hits only)");
+    const Net& TN = m->nets[NVDB_NET_TILE];
+    const bool tiles = tree->n_tile > 0 && TN.present;
+    if (tiles) NVDB_REQUIRE(TN.params_set && TN.enc_set, NVDB_E_STATE, "tile value regressor parameters or encoding not set");
     if (n == 0) return;
     hipStream_t st = (hipStream_t)stream;
     const QueryScratch qs = query_noalloc_scratch();
     const int64_t bs = std::min<int64_t>(batch > 0 ? batch : QUERY_NOALLOC_MAX_BATCH, n);
     const float inv_d = 1.f / (float)m->d.domain_size;
+    const QueryTiles qt =
+        tiles ? QueryTiles{tree->l1_o.p, tree->l1_active.p, tree->n_l1, qs.tile_x, qs.tile_idx, qs.cnt + 1} : QueryTiles{};
     // batches run one after the other on `stream` and reuse the same scratch
     for (int64_t b0 = 0; b0 < n; b0 += bs) {
       const int64_t nb = std::min(bs, n - b0);
       query_zero_count(qs.cnt, st);
+      if (tiles) query_zero_count(qs.cnt + 1, st);
       query_classify(q_dev + 3 * b0, nb, *tree, background, m->d.domain_lo, inv_d, values_dev + b0,
-                     hits_dev ? hits_dev + b0 : nullptr, qs.hit_x, qs.hit_idx, qs.cnt, QueryTiles{}, st);
+                     hits_dev ? hits_dev + b0 : nullptr, qs.hit_x, qs.hit_idx, qs.cnt, qt, st);
+      if (tiles) {  // as in nvdb_query: the tile regressor over the batch's tile hits
+        InferLaunch T{};
+        T.net = net_view(TN);
+        base_spec(m, &T.spec);
+        T.spec.src = SRC_COORDS;
+        T.spec.direct = 1;
+        T.spec.coords = qs.tile_x;
+        T.spec.n = nb;
+        T.spec.n_dev = qs.cnt + 1;
+        T.out_kind = OUT_Y;
+        T.y = qs.tile_y;
+        launch_infer(TN.ks, T, infer_grid(TN.ks, nb), st);
+        query_scatter(qs.tile_y, qs.tile_idx, nb, qs.cnt + 1, m->d.value_scale, values_dev + b0, st);
+      }
       InferLaunch I{};
       I.net = net_view(N);
       base_spec(m, &I.spec);

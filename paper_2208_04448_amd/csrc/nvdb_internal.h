@@ -339,10 +339,13 @@ void query_zero_count(uint32_t* c, hipStream_t st);
 // the current device (looked up once per device).
 constexpr int64_t QUERY_NOALLOC_MAX_BATCH = 1 << 16;
 struct QueryScratch {
-  float* hit_x;       // [max batch][3]
-  float* y;           // [max batch]
-  uint32_t* hit_idx;  // [max batch]
-  uint32_t* cnt;      // [1]
+  float* hit_x;        // [max batch][3]
+  float* y;            // [max batch]
+  uint32_t* hit_idx;   // [max batch]
+  float* tile_x;       // [max batch][3]
+  float* tile_y;       // [max batch]
+  uint32_t* tile_idx;  // [max batch]
+  uint32_t* cnt;       // [2]: voxel hits, tile hits
 };
 QueryScratch query_noalloc_scratch();
 // voxels of a that b lacks, canonical order, at most cap written to out [cap][3]; returns the count

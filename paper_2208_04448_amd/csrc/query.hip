@@ -24,13 +24,17 @@ namespace nvdb {
 // Scratch of the allocation-free random access (nvdb_query_noalloc), one copy
 // per GPU for the life of the process: per query of a batch of at most
 // QUERY_NOALLOC_MAX_BATCH its normalised position (3 floats), regressor output
-// and query index, then the hit counter.  In host code `scratch` names a host
-// stand-in, never the device memory: kernels get the address that
-// hipGetSymbolAddress returns for the current device.
+// and query index, the same three for the tile hits, then the voxel-hit and
+// tile-hit counters.  In host code `scratch` names a host stand-in, never the
+// device memory: kernels get the address that hipGetSymbolAddress returns for
+// the current device.
 constexpr size_t QS_X = 0;
 constexpr size_t QS_Y = QS_X + 12 * (size_t)QUERY_NOALLOC_MAX_BATCH;
 constexpr size_t QS_IDX = QS_Y + 4 * (size_t)QUERY_NOALLOC_MAX_BATCH;
-constexpr size_t QS_CNT = QS_IDX + 4 * (size_t)QUERY_NOALLOC_MAX_BATCH;
+constexpr size_t QS_TX = QS_IDX + 4 * (size_t)QUERY_NOALLOC_MAX_BATCH;
+constexpr size_t QS_TY = QS_TX + 12 * (size_t)QUERY_NOALLOC_MAX_BATCH;
+constexpr size_t QS_TIDX = QS_TY + 4 * (size_t)QUERY_NOALLOC_MAX_BATCH;
+constexpr size_t QS_CNT = QS_TIDX + 4 * (size_t)QUERY_NOALLOC_MAX_BATCH;
 constexpr size_t QS_BYTES = QS_CNT + 256;
 static __device__ __align__(256) char scratch[QS_BYTES];
 
@@ -50,7 +54,8 @@ QueryScratch query_noalloc_scratch() {
     }
     p = (char*)a;
   }
-  return QueryScratch{(float*)(p + QS_X), (float*)(p + QS_Y), (uint32_t*)(p + QS_IDX), (uint32_t*)(p + QS_CNT)};
+  return QueryScratch{(float*)(p + QS_X),  (float*)(p + QS_Y),  (uint32_t*)(p + QS_IDX), (float*)(p + QS_TX),
+                      (float*)(p + QS_TY), (uint32_t*)(p + QS_TIDX), (uint32_t*)(p + QS_CNT)};
 }
 
 namespace {

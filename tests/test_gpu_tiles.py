@@ -238,8 +238,7 @@ def test_query_with_tiles(gpu_lib, fog, batch):
     """Random access through the tiles (Sec. 3.3.1, 3.5): voxel hits get the
     regressor at the query position, queries inside an active tile get the tile
     regressor's value (bit-equal to the library's tile decode), the rest the
-    background; hit flags 1 / 2 / 0; FP32 against the oracle.  The allocation-free
-    variant, whose scratch holds voxel hits only, refuses such a tree."""
+    background; hit flags 1 / 2 / 0; FP32 against the oracle."""
     tr, ot = fog
     nets = {0: (64, 3, 18, 1), 3: (64, 3, 18, 1)}
     m = gpu_lib.Model(nets, precision=gpu_lib.FP32, domain_size=128, value_scale=1.0)
@@ -266,9 +265,6 @@ def test_query_with_tiles(gpu_lib, fog, batch):
     dec = m.decode_tiles(tr).cpu().numpy()
     assert np.array_equal(v[h == 2], dec[tq[h == 2]])
     assert np.all(v[h == 0] == -1.0)
-    with pytest.raises(gpu_lib.NvdbError) as e:
-        m.query_noalloc(tr, torch.from_numpy(q).to(DEV), background=-1.0)
-    assert e.value.code == gpu_lib.E_UNSUPPORTED
     # a model without the tile regressor treats the tiles as misses
     r = gpu_lib.Model({0: nets[0]}, precision=gpu_lib.FP32, domain_size=128, value_scale=1.0)
     r.set_params(0, th[0])
