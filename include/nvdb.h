@@ -506,10 +506,10 @@ nvdb_status nvdb_decode_moe_mask(const nvdb_model* const* experts, const int32_t
  * slot's class is the argmax of the blended logits (ties to the lowest class).
  * classes_dev is uint8[n_l1][4096] (as nvdb_decode_l1).  The cell size, the halo
  * and the grid origin must be multiples of 8 (a slot then lies wholly inside or
- * outside every widened box), and the experts must share one network shape.
- * Synchronisation, scratch (96 B per leaf slot in place of 32 B per voxel) and
- * errors as nvdb_decode_moe_mask, E_UNSUPPORTED for experts of different shapes
- * and E_STATE for an unset level-1 classifier. */
+ * outside every widened box).  Experts of one network shape and precision share
+ * one grouped launch; otherwise each expert runs its own.  Synchronisation,
+ * scratch (96 B per leaf slot in place of 32 B per voxel) and errors as
+ * nvdb_decode_moe_mask, E_STATE for an unset level-1 classifier. */
 nvdb_status nvdb_decode_moe_l1(const nvdb_model* const* experts, const int32_t* cells, int32_t n_experts,
                                const nvdb_subdomains* grid, const nvdb_tree* tree, uint8_t* classes_dev,
                                void* stream);

@@ -1843,6 +1843,7 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
     NVDB_REQUIRE(experts[k] != nullptr, NVDB_E_INVALID, "null expert");
     const Net& N = net_of(experts[k], net);
     NVDB_REQUIRE(N.params_set && N.enc_set, NVDB_E_STATE, "expert network parameters or encoding not set");
+    NVDB_REQUIRE(N.s.C == C, NVDB_E_INVALID, "expert output count");
     for (int d = 0; d < 3; ++d) box[k].lo[d] = experts[k]->d.domain_lo[d];
     box[k].inv_d = 1.f / (float)experts[k]->d.domain_size;
   }
@@ -1952,8 +1953,6 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
     }
     NVDB_REQUIRE(false, NVDB_E_DEVICE, "the routed pair count changed between two passes");
   }
-  NVDB_REQUIRE(kind != MOE_LEAF_SLOTS, NVDB_E_UNSUPPORTED,
-               "the blended level-1 decode needs experts of one network shape");
   // small arrays in one allocation: lookup table, boxes, counts (+ the
   // uncovered voxels), bucket starts, cursors
   const size_t o_box = ((size_t)total * 4 + 255) & ~(size_t)255;
@@ -1985,11 +1984,11 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
     hs[k] = (uint32_t)pairs;
     pairs += hc[k];
   }
-  // per-pair coordinates, outputs and slots, and eight slots per voxel, in one allocation
+  // per-pair coordinates, outputs (C each) and slots, and eight slots per item, in one allocation
   const size_t o_y = (12 * pairs + 255) & ~(size_t)255;
-  const size_t o_bs = o_y + ((4 * pairs + 255) & ~(size_t)255);
+  const size_t o_bs = o_y + ((4 * (size_t)C * pairs + 255) & ~(size_t)255);
   const size_t o_ys = o_bs + ((4 * pairs + 255) & ~(size_t)255);
-  ws.big.ensure(o_ys + 32 * (size_t)n);
+  ws.big.ensure(o_ys + 32 * (size_t)C * (size_t)n);
   uint8_t* big = ws.big.p;
   float* bx = (float*)big;
   float* y = (float*)(big + o_y);
@@ -2008,11 +2007,13 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
     I.spec.coords = bx + 3 * (size_t)hs[k];
     I.spec.n = hc[k];
     I.out_kind = OUT_Y;
-    I.y = y + hs[k];
+    I.y = y + (size_t)C * hs[k];
     launch_infer(N.ks, I, infer_grid(N.ks, hc[k]), st);
-    query_scatter(y + hs[k], bslot + hs[k], hc[k], cnt + k, slots ? 1.f : experts[k]->d.value_scale, yslot, st);
+    query_scatter(y + (size_t)C * hs[k], bslot + hs[k], hc[k], cnt + k, valued ? experts[k]->d.value_scale : 1.f,
+                  yslot, st, C);
   }
-  moe_blend(*tree, kind, g, tab, yslot, slots ? nullptr : values_dev, slots ? mask_dev : nullptr, nullptr, st);
+  moe_blend(*tree, kind, g, tab, yslot, valued ? values_dev : nullptr, slots ? mask_dev : nullptr,
+            kind == MOE_LEAF_SLOTS ? cls_dev : nullptr, st);
   NVDB_HIP(hipStreamSynchronize(st));
 }
 

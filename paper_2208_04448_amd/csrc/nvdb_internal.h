@@ -332,8 +332,9 @@ struct QueryTiles {
 void query_classify(const float* q, int64_t n, const Tree& tree, float background, const int32_t lo[3], float inv_d,
                     float* values, uint8_t* hits, float* hit_x, uint32_t* hit_idx, uint32_t* n_hits,
                     const QueryTiles& tiles, hipStream_t st);
+// values[idx[h] C + c] = y[h C + c] * scale for the first min(n, *n_hits) rows h
 void query_scatter(const float* y, const uint32_t* idx, int64_t n, const uint32_t* n_hits, float scale, float* values,
-                   hipStream_t st);
+                   hipStream_t st, int C = 1);
 void query_zero_count(uint32_t* c, hipStream_t st);
 // Device addresses of the static scratch of the allocation-free random access on
 // the current device (looked up once per device).

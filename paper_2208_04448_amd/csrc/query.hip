@@ -117,9 +117,11 @@ __global__ void __launch_bounds__(256) k_query_classify(const float* __restrict_
 
 __global__ void __launch_bounds__(256) k_query_scatter(const float* __restrict__ y, const uint32_t* __restrict__ idx,
                                                        int64_t n, const uint32_t* n_hits, float scale,
-                                                       float* __restrict__ values) {
+                                                       float* __restrict__ values, int C) {
   const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (h < n && h < (int64_t)*n_hits) values[idx[h]] = y[h] * scale;
+  if (h >= n || h >= (int64_t)*n_hits) return;
+  const size_t d = (size_t)idx[h] * C;
+  for (int c = 0; c < C; ++c) values[d + c] = y[(size_t)h * C + c] * scale;
 }
 __global__ void k_query_zero(uint32_t* c) { *c = 0u; }
 
@@ -186,10 +188,10 @@ void query_classify(const float* q, int64_t n, const Tree& tree, float backgroun
 }
 
 void query_scatter(const float* y, const uint32_t* idx, int64_t n, const uint32_t* n_hits, float scale, float* values,
-                   hipStream_t st) {
+                   hipStream_t st, int C) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_query_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, y, idx, n, n_hits, scale,
-                     values);
+                     values, C);
   NVDB_HIP(hipGetLastError());
 }
 void query_zero_count(uint32_t* c, hipStream_t st) {
