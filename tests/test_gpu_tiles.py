@@ -292,6 +292,12 @@ def test_decode_moe_tiles_matches_oracle(gpu_lib, fog, prec):
     cells = gpu_lib.subdomain_cells(tr, origin, size, halo)
     want_cells = moe.kept_cells(np.concatenate([ot["ijk"], _tile_voxels(ot)]), origin, size)
     assert np.array_equal(cells, want_cells.astype(np.int32))
+    # an offset grid of 10-voxel cells: tiles straddle up to eight cores, and cells
+    # meeting only tile regions are kept
+    tv = _tile_voxels(ot)
+    off = gpu_lib.subdomain_cells(tr, (3, -5, 2), 10, 4)
+    assert np.array_equal(off, moe.kept_cells(np.concatenate([ot["ijk"], tv]), (3, -5, 2), 10).astype(np.int32))
+    assert len(off) > len(moe.kept_cells(ot["ijk"], (3, -5, 2), 10))
     W, H, m = 64, 3, 18
     shapes = mlp.layer_shapes(2 * m, W, H, 1)
     B = workloads.pe_matrix(6)
