@@ -459,6 +459,10 @@ nvdb_status nvdb_subdomain_box(const nvdb_subdomains* grid, const int32_t cell[3
 /* Training set of the expert of `cell`: the active voxels of `tree` inside the
  * cell's widened box, with their values, as a new tree (its arrays are those
  * of a tree built from that voxel list; it records the source's active rule).
+ * The voxels of the source's active tiles count as active voxels of the tile's
+ * value; for a source with active tiles the new tree is then pruned as by
+ * nvdb_tree_prune_tiles, so that the tiles wholly inside the box are its active
+ * tiles (a tile cut by the box leaves a leaf of the voxels inside).
  * An expert's model takes domain_lo = the widened box's lower corner and
  * domain_size = size + 2 halo (coordinates normalised to the subdomain's box).
  * The caller frees the result with nvdb_tree_free.  Synchronises `stream`.

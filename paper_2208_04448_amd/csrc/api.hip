@@ -8,6 +8,7 @@
 #include <limits>
 #include <map>
 #include <mutex>
+#include <memory>
 #include <new>
 #include <string>
 
@@ -1793,16 +1794,20 @@ nvdb_status nvdb_tree_subdomain(const nvdb_tree* tree, const nvdb_subdomains* gr
     DevBuf<int32_t> ijk;
     DevBuf<float> v;
     DevBuf<uint32_t> count;
-    ijk.alloc(3 * (size_t)tree->n_vox);
-    v.alloc((size_t)tree->n_vox);
+    const int64_t cap = std::max<int64_t>(tree->n_vox + 512 * tree->n_tile, 1);
+    ijk.alloc(3 * (size_t)cap);
+    v.alloc((size_t)cap);
     count.alloc(1);
     const int64_t n = moe_extract(*tree, lo, g.S + 2 * g.h, ijk.p, v.p, count.p, st);
     // every voxel of the source is kept: a band no finite value exceeds
     const nvdb_active_rule keep{NVDB_SDF, FLT_MAX};
-    Tree* t = build_tree_sparse(ijk.p, v.p, n, keep, st);
+    std::unique_ptr<Tree> t(build_tree_sparse(ijk.p, v.p, n, keep, st));
     t->kind = tree->kind;
     t->thr = tree->thr;
-    *out = static_cast<nvdb_tree*>(t);
+    // a source with active tiles: the tiles wholly inside the box become tiles again
+    // (the source's leaves are never full and of one value, so no other leaf is pruned)
+    if (tree->n_tile > 0) t.reset(prune_tiles(*t, st));
+    *out = static_cast<nvdb_tree*>(t.release());
   });
 }
 

@@ -184,18 +184,28 @@ __global__ void __launch_bounds__(256) k_moe_mark_tiles(const int4* __restrict__
 }
 
 // Voxels inside a widened box [lo, lo + D)^3, appended (one global atomic per
-// block).
+// block): with `tiles` false item i is voxel i (origins leaf_o, keys key, values
+// val); with `tiles` true it is voxel i & 511 of active tile i >> 9 (level-1
+// origins leaf_o, tile keys key, tile values val), every voxel of a tile holding
+// the tile's value.
 __global__ void __launch_bounds__(256) k_moe_extract(const int4* __restrict__ leaf_o, const uint32_t* __restrict__ key,
-                                                     const float* __restrict__ val, int64_t n, int lx, int ly, int lz,
-                                                     int D, int32_t* __restrict__ ijk, float* __restrict__ v,
-                                                     uint32_t* __restrict__ count) {
+                                                     const float* __restrict__ val, int64_t n, bool tiles, int lx,
+                                                     int ly, int lz, int D, int32_t* __restrict__ ijk,
+                                                     float* __restrict__ v, uint32_t* __restrict__ count) {
   __shared__ uint32_t wcount[4], wbase[4];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int w = (int)(threadIdx.x >> 6);
   bool in = false;
   int3 p = make_int3(0, 0, 0);
   if (i < n) {
-    p = voxel_of(leaf_o, key[i]);
+    if (tiles) {
+      const uint32_t k = key[i >> 9], n1 = k & 4095u, n0 = (uint32_t)(i & 511);
+      const int4 o = leaf_o[k >> 12];
+      p = make_int3(o.x + 8 * (int)(n1 >> 8) + (int)(n0 >> 6), o.y + 8 * (int)((n1 >> 4) & 15u) + (int)((n0 >> 3) & 7u),
+                    o.z + 8 * (int)(n1 & 15u) + (int)(n0 & 7u));
+    } else {
+      p = voxel_of(leaf_o, key[i]);
+    }
     in = (int64_t)p.x - lx >= 0 && (int64_t)p.x - lx < D && (int64_t)p.y - ly >= 0 && (int64_t)p.y - ly < D &&
          (int64_t)p.z - lz >= 0 && (int64_t)p.z - lz < D;
   }
@@ -216,7 +226,7 @@ __global__ void __launch_bounds__(256) k_moe_extract(const int4* __restrict__ le
     ijk[3 * (size_t)s] = p.x;
     ijk[3 * (size_t)s + 1] = p.y;
     ijk[3 * (size_t)s + 2] = p.z;
-    v[s] = val[i];
+    v[s] = val[tiles ? i >> 9 : i];
   }
 }
 
@@ -518,7 +528,12 @@ int64_t moe_extract(const Tree& t, const int32_t lo[3], int32_t D, int32_t* ijk,
   NVDB_HIP(hipMemsetAsync(count, 0, sizeof(uint32_t), st));
   if (t.n_vox > 0) {
     hipLaunchKernelGGL(k_moe_extract, dim3(grid_of(t.n_vox)), dim3(256), 0, st, t.leaf_o.p, t.vox_key.p, t.values.p,
-                       t.n_vox, lo[0], lo[1], lo[2], D, ijk, v, count);
+                       t.n_vox, false, lo[0], lo[1], lo[2], D, ijk, v, count);
+    NVDB_HIP(hipGetLastError());
+  }
+  if (t.n_tile > 0) {  // the voxels of the active tiles, appended after the others
+    hipLaunchKernelGGL(k_moe_extract, dim3(grid_of(512 * t.n_tile)), dim3(256), 0, st, t.l1_o.p, t.tile_key.p,
+                       t.tile_val.p, 512 * t.n_tile, true, lo[0], lo[1], lo[2], D, ijk, v, count);
     NVDB_HIP(hipGetLastError());
   }
   uint32_t c = 0;

@@ -373,7 +373,8 @@ struct MoeBox {  // an expert's normalisation box: x = (p - lo + 1/2) * inv_d
 constexpr int MOE_MAX_EXPERTS = 4096;
 void leaf_bbox(const Tree& t, int32_t lo[3], int32_t hi[3], hipStream_t st);  // synchronises; hi exclusive
 void moe_mark_cells(const Tree& t, const MoeGrid& g, uint8_t* flag, hipStream_t st);
-// voxels of t inside [lo, lo + D)^3 into ijk [n][3], v [n] (any order); synchronises, returns the count
+// voxels of t inside [lo, lo + D)^3, those of its active tiles included, into ijk [n][3], v [n]
+// (any order; room for n_vox + 512 n_tile); synchronises, returns the count
 int64_t moe_extract(const Tree& t, const int32_t lo[3], int32_t D, int32_t* ijk, float* v, uint32_t* count,
                     hipStream_t st);
 // routing and blend over the active voxels, or (slots) over every voxel slot of the leaves

@@ -330,3 +330,30 @@ def test_decode_moe_tiles_matches_oracle(gpu_lib, fog, prec):
     assert e.value.code == gpu_lib.E_INVALID
     plain = gpu_lib.Tree(_fog(64).to(DEV), (0, 0, 0), T.FOG, THR)
     assert gpu_lib.decode_moe_tiles(models, cells, origin, size, halo, plain).numel() == 0
+
+
+@pytest.mark.parametrize("grid", [((0, 0, 0), 48, 8), ((3, -5, 2), 40, 8)], ids=["aligned", "offset"])
+def test_tree_subdomain_with_tiles(gpu_lib, fog, grid):
+    """Expert training sets of a tree with active tiles (Sec. 3.4 over the tiles of
+    Sec. 3.3.1): the voxels and tile voxels inside a cell's widened box, built and
+    pruned, against the oracle's build of the same voxels and its pruning, for
+    every kept cell; on the offset grid the boxes cut tiles, which come back as
+    leaves of the voxels inside."""
+    tr, ot = fog
+    origin, size, halo = grid
+    tv = _tile_voxels(ot)
+    all_ijk = np.concatenate([ot["ijk"], tv])
+    all_val = np.concatenate([ot["values"], np.repeat(ot["tile_value"], 512)])
+    cells = gpu_lib.subdomain_cells(tr, origin, size, halo)
+    n_tiles = n_cut = 0
+    for c in cells:
+        sel = moe.in_widened_box(all_ijk, c, origin, size, halo)
+        want = T.prune_tiles(T.build(all_ijk[sel], all_val[sel]))
+        sub = tr.subdomain(origin, size, halo, c)
+        _assert_same(sub, want)
+        n_tiles += len(want["tile_value"])
+        tin = moe.in_widened_box(tv, c, origin, size, halo).reshape(-1, 512).sum(1)
+        n_cut += int(((tin > 0) & (tin < 512)).sum())
+    assert n_tiles > len(ot["tile_value"])  # tiles in the overlaps belong to several experts
+    if origin != (0, 0, 0):
+        assert n_cut > 0
