@@ -371,6 +371,7 @@ def tiles_leg(fit_steps, n=256, thr=0.05):
     common, it, ip = np.intersect1d(kt, kp, return_indices=True)
     d = vp[ip].astype(np.float64) - vt_true[it]
     pi = pred.info()
+    moe = tiles_moe(tree, n, fit_steps)
     return {"workload": "fog %d^3, density clamp(3 (1 - r/R) + 0.3 fbm, 0, 1), R = %.1f, threshold %.2f; leaves of "
                         "one density pruned to active tiles" % (n, 0.44 * n, thr),
             "n_voxels_before_pruning": fi.n_voxels, "n_leaves_before_pruning": fi.n_leaves,
@@ -388,7 +389,51 @@ def tiles_leg(fit_steps, n=256, thr=0.05):
                         "tiles_fn": int(len(kt) - len(common)),
                         "tile_max_abs": float(np.abs(d).max()) if len(d) else 0.0,
                         "tile_rms": float(np.sqrt(np.mean(d * d))) if len(d) else 0.0,
-                        "voxels": topo}}
+                        "voxels": topo},
+            "moe_tiles": moe}
+
+
+def tiles_moe(tree, n, fit_steps, S=128, h=8):
+    """The tile values under the sparse domain decomposition (Sec. 3.4): cells of
+    edge S with an h-voxel halo; the experts whose widened box holds tiles (a tile's
+    gates vanish outside the boxes that hold it, so the others take no part) each
+    fit a tile value regressor on their own tiles, all in shared launches; then the
+    blended decode of every tile and its error."""
+    import torch
+
+    import workloads
+    from paper_2208_04448_amd import nvdb
+    origin = (0, 0, 0)
+    cells = nvdb.subdomain_cells(tree, origin, S, h)
+    experts, subs, used = [], [], []
+    for c in cells:
+        sub = tree.subdomain(origin, S, h, c)
+        if sub.info().n_tiles == 0:
+            continue
+        lo, D = nvdb.subdomain_box(origin, S, h, c)
+        m = nvdb.Model({3: (64, 3, 32, 1)}, precision=nvdb.BF16, domain_lo=lo, domain_size=D, value_scale=1.0)
+        m.set_encoding(3, workloads.ffm_matrix(32, 2.0, seed=63))
+        m.set_params(3, workloads.init_params(64, 64, 3, 1, seed=73))
+        experts.append(m)
+        subs.append(sub)
+        used.append(c)
+    batch = 1 << 14
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    nvdb.fit_experts(experts, subs, steps=fit_steps, batch=batch, nets_mask=8, seed=0, lr=1e-3, lr_decay=0.975,
+                     lr_interval=100)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t
+    v = nvdb.decode_moe_tiles(experts, used, origin, S, h, tree)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(3):
+        v = nvdb.decode_moe_tiles(experts, used, origin, S, h, tree)
+    torch.cuda.synchronize()
+    t_dec = (time.perf_counter() - t) / 3
+    return {"cells": "%d^3 cells, halo %d: %d kept, %d with tiles" % (S, h, len(cells), len(experts)),
+            "expert_tiles": [s_.info().n_tiles for s_ in subs], "fit_steps": fit_steps, "batch": batch,
+            "fit_s": t_fit, "blended_decode_ms": t_dec * 1e3, "tile_err": nvdb.errors_tiles(tree, v)}
 
 
 def measured_traffic():
