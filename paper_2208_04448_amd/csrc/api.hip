@@ -1913,7 +1913,10 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
       gn.out_scale = valued ? experts[k]->d.value_scale : 1.f;
       std::memcpy(hs + o_nets + k * sizeof(GroupNet), &gn, sizeof(GroupNet));
     }
-    uint32_t* back = (uint32_t*)(hs + small_bytes);  // uncovered items, overflow flag
+    // the counters and cursors start at zero: the upload clears them
+    std::memset(hs + o_cnt, 0, (E + 1) * 4);
+    std::memset(hs + o_cur, 0, E * 4);
+    uint32_t* back = (uint32_t*)(hs + small_bytes);  // overflow flag, uncovered items
     // pair buffers for two pairs per item (plus each run's padding to whole
     // chunks); if the routing finds more, the exact size is read back and the
     // decode runs again
@@ -1929,8 +1932,6 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
       uint32_t* bslot = (uint32_t*)(big + o_bs);
       float* yslot = (float*)(big + o_ys);
       NVDB_HIP(hipMemcpyAsync(small, hs, small_bytes, hipMemcpyHostToDevice, st));
-      NVDB_HIP(hipMemsetAsync(cnt, 0, (E + 1) * 4, st));
-      NVDB_HIP(hipMemsetAsync(cursor, 0, E * 4, st));
       moe_count(*tree, kind, g, tab, n_experts, cnt, cnt + n_experts, st);
       moe_plan(cnt, n_experts, (int)CH, cap, cs, start, flag, st);
       moe_route(*tree, kind, g, tab, dbox, n_experts, start, cursor, bx, bslot, cap, st);
@@ -1945,11 +1946,10 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
       launch_infer_group(ks0, M, st);
       moe_blend(*tree, kind, g, tab, yslot, valued ? values_dev : nullptr,
                 kind == MOE_VOXEL_SLOTS ? mask_dev : nullptr, kind == MOE_LEAF_SLOTS ? cls_dev : nullptr, st);
-      NVDB_HIP(hipMemcpyAsync(back, cnt + n_experts, 4, hipMemcpyDeviceToHost, st));
-      NVDB_HIP(hipMemcpyAsync(back + 1, flag, 4, hipMemcpyDeviceToHost, st));
+      NVDB_HIP(hipMemcpyAsync(back, flag, 8, hipMemcpyDeviceToHost, st));
       NVDB_HIP(hipStreamSynchronize(st));
-      NVDB_REQUIRE(back[0] == 0, NVDB_E_INVALID, "voxels that no expert's widened box holds");
-      if (back[1] == 0) return;
+      NVDB_REQUIRE(back[1] == 0, NVDB_E_INVALID, "voxels that no expert's widened box holds");
+      if (back[0] == 0) return;
       std::vector<uint32_t> hc(E);
       NVDB_HIP(hipMemcpy(hc.data(), cnt, E * 4, hipMemcpyDeviceToHost));
       size_t need = 0;

@@ -592,6 +592,8 @@ namespace {
 // One work-group of 256 threads; n <= 4096 experts, each thread a contiguous run.
 // When the padded pairs exceed cap, flag[0] is set and the chunk count is 0 (the
 // grouped decode then does nothing and the caller retries with larger buffers).
+// flag[1] receives cnt[n], the count of items no expert holds, so that one copy
+// brings both back.
 __global__ void __launch_bounds__(256) k_moe_plan(const uint32_t* __restrict__ cnt, int n, int chunk, uint64_t cap,
                                                   uint32_t* __restrict__ cs, uint32_t* __restrict__ start,
                                                   uint32_t* __restrict__ flag) {
@@ -611,6 +613,7 @@ __global__ void __launch_bounds__(256) k_moe_plan(const uint32_t* __restrict__ c
     const bool over = (uint64_t)run * (uint64_t)chunk > cap;
     cs[n] = over ? 0u : run;
     flag[0] = over ? 1u : 0u;
+    flag[1] = cnt[n];
   }
   __syncthreads();
   uint32_t run = part[threadIdx.x];

@@ -387,7 +387,8 @@ void moe_route(const Tree& t, int kind, const MoeGrid& g, const int32_t* table, 
                const uint32_t* start, uint32_t* cursor, float* bx, uint32_t* bslot, uint64_t cap, hipStream_t st);
 // chunk layout of the grouped decode from the per-expert counts: cs[k] first
 // chunk of expert k (runs padded to whole chunks of `chunk` samples), cs[n] the
-// chunk count, start[k] = cs[k] * chunk; pairs beyond cap set flag[0] (and cs[n] = 0)
+// chunk count, start[k] = cs[k] * chunk; pairs beyond cap set flag[0] (and cs[n] = 0);
+// flag[1] = cnt[n] (the items no expert holds)
 void moe_plan(const uint32_t* cnt, int n, int chunk, uint64_t cap, uint32_t* cs, uint32_t* start, uint32_t* flag,
               hipStream_t st);
 void moe_blend(const Tree& t, int kind, const MoeGrid& g, const int32_t* table, const float* yslot, float* values,
