@@ -1350,8 +1350,9 @@ int infer_grid(const KernelSet& ks, int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>((n + per_wg - 1) / per_wg, 4096 / v.waves));
 }
 void launch_infer_group(const KernelSet& ks, const InferGroupLaunch& M, hipStream_t st) {
-  // work-groups take contiguous chunk ranges; those past the chunk count exit
-  hipLaunchKernelGGL(ks.infer_group, dim3(4096 / ks.group_waves), dim3(64 * ks.group_waves), 0, st, M);
+  // one 8-wave work-group per compute unit, each taking a contiguous chunk range
+  // (staging the weights once per network it meets); those past the chunk count exit
+  hipLaunchKernelGGL(ks.infer_group, dim3(2048 / ks.group_waves), dim3(64 * ks.group_waves), 0, st, M);
   NVDB_HIP(hipGetLastError());
 }
 void launch_infer(const KernelSet& ks, const InferLaunch& I, int grid, hipStream_t st) {
