@@ -1948,7 +1948,7 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
                 kind == MOE_VOXEL_SLOTS ? mask_dev : nullptr, kind == MOE_LEAF_SLOTS ? cls_dev : nullptr, st);
       NVDB_HIP(hipMemcpyAsync(back, flag, 8, hipMemcpyDeviceToHost, st));
       NVDB_HIP(hipStreamSynchronize(st));
-      NVDB_REQUIRE(back[1] == 0, NVDB_E_INVALID, "voxels that no expert's widened box holds");
+      NVDB_REQUIRE(back[1] == 0, NVDB_E_INVALID, "items (voxels, slots or tiles) that no expert's widened box holds");
       if (back[0] == 0) return;
       std::vector<uint32_t> hc(E);
       NVDB_HIP(hipMemcpy(hc.data(), cnt, E * 4, hipMemcpyDeviceToHost));
@@ -1982,7 +1982,7 @@ static void decode_moe_impl(const nvdb_model* const* experts, const int32_t* cel
   std::vector<uint32_t> hc(E + 1);
   NVDB_HIP(hipMemcpyAsync(hc.data(), cnt, hc.size() * 4, hipMemcpyDeviceToHost, st));
   NVDB_HIP(hipStreamSynchronize(st));
-  NVDB_REQUIRE(hc[E] == 0, NVDB_E_INVALID, "voxels that no expert's widened box holds");
+  NVDB_REQUIRE(hc[E] == 0, NVDB_E_INVALID, "items (voxels, slots or tiles) that no expert's widened box holds");
   std::vector<uint32_t> hs(E);
   uint64_t pairs = 0;
   for (size_t k = 0; k < E; ++k) {

@@ -285,8 +285,8 @@ def test_decode_moe_tiles_matches_oracle(gpu_lib, fog, prec):
     3.3.1 tiles, Sec. 3.4 gates): the kept cells count the tiles' voxels, each
     expert's tile value regressor (own box, value scale 1.5) runs at the tiles in
     its widened box, blended with the gates at the tile centres, against the
-    oracle's blend; a halo that is not a multiple of 8 is refused and a tree
-    without tiles decodes to nothing."""
+    oracle's blend; a halo that is not a multiple of 8 and tiles that no expert
+    holds are refused, and a tree without tiles decodes to nothing."""
     tr, ot = fog
     origin, size, halo = (0, 0, 0), 48, 8
     cells = gpu_lib.subdomain_cells(tr, origin, size, halo)
@@ -327,6 +327,12 @@ def test_decode_moe_tiles_matches_oracle(gpu_lib, fog, prec):
         assert np.all(np.abs(mixed - want) <= tol * (1 + np.abs(want))), np.abs(mixed - want).max()
     with pytest.raises(gpu_lib.NvdbError) as e:
         gpu_lib.decode_moe_tiles(models, cells, origin, size, 4, tr)
+    assert e.value.code == gpu_lib.E_INVALID
+    # without the centre cell's expert the tiles deep in its core have no expert
+    keep = [i for i, c in enumerate(cells) if tuple(c) != (1, 1, 1)]
+    assert len(keep) == len(cells) - 1
+    with pytest.raises(gpu_lib.NvdbError) as e:
+        gpu_lib.decode_moe_tiles([models[i] for i in keep], cells[keep], origin, size, halo, tr)
     assert e.value.code == gpu_lib.E_INVALID
     plain = gpu_lib.Tree(_fog(64).to(DEV), (0, 0, 0), T.FOG, THR)
     assert gpu_lib.decode_moe_tiles(models, cells, origin, size, halo, plain).numel() == 0
