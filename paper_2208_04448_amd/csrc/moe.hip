@@ -488,6 +488,48 @@ __global__ void __launch_bounds__(256) k_moe_blend(ItemSrc src, int64_t n, MoeGr
   }
 }
 
+// The mask blend per leaf of a leaf-aligned grid: one wave per leaf, whose 512
+// voxel slots i = 512 l + r all lie in the same widened boxes, so the leaf's
+// experts are looked up once; each lane blends slots r = lane, lane + 64, ... with
+// k_moe_blend's order and arithmetic (j ascending, gate = product of the three
+// tents at the voxel centre) and the wave packs each 64 bits into a mask word.
+// (For the voxels of a level set, about 180 per leaf, one thread per voxel is
+// faster: the wave's passes over a leaf would chain their loads.)
+__global__ void __launch_bounds__(256) k_moe_blend_slots_leaf(const int4* __restrict__ leaf_o, int64_t n_leaf,
+                                                              MoeGrid g, const int32_t* __restrict__ table,
+                                                              const float* __restrict__ yslot,
+                                                              uint64_t* __restrict__ mask) {
+  const int64_t l = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint32_t lane = threadIdx.x & 63u;
+  if (l >= n_leaf) return;  // uniform per wave
+  const size_t n = 512 * (size_t)n_leaf;
+  const int4 o = leaf_o[l];
+  AxisCells ax, ay, az;
+  leaf_cells(o, g, ax, ay, az);
+  int kj[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) kj[j] = slot_expert(g, table, ax, ay, az, j);
+#pragma unroll 1
+  for (uint32_t r0 = 0; r0 < 512; r0 += 64) {
+    const uint32_t r = r0 + lane;
+    const size_t i = 512 * (size_t)l + r;
+    const int px = o.x + (int)(r >> 6), py = o.y + (int)((r >> 3) & 7u), pz = o.z + (int)(r & 7u);
+    float num = 0.f, den = 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (kj[j] < 0) continue;
+      const float w = tent(px, ax.base + (j >> 2), g.o[0], g.S, g.h, 1) *
+                      tent(py, ay.base + ((j >> 1) & 1), g.o[1], g.S, g.h, 1) *
+                      tent(pz, az.base + (j & 1), g.o[2], g.S, g.h, 1);
+      num += w * yslot[(size_t)j * n + i];
+      den += w;
+    }
+    const float v = den > 0.f ? num / den : __builtin_nanf("");
+    const uint64_t bits = __ballot(v > 0.f);
+    if (lane == 0) mask[(size_t)l * 8 + (r0 >> 6)] = bits;
+  }
+}
+
 unsigned grid_of(int64_t n) { return (unsigned)((n + 255) / 256); }
 // the routing passes: at most four blocks per compute unit, each walking several tiles
 unsigned route_grid(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 1024); }
@@ -633,8 +675,14 @@ void moe_plan(const uint32_t* cnt, int n, int chunk, uint64_t cap, uint32_t* cs,
 
 void moe_blend(const Tree& t, int kind, const MoeGrid& g, const int32_t* table, const float* yslot, float* values,
                uint64_t* mask, uint8_t* cls, hipStream_t st) {
-  hipLaunchKernelGGL(k_moe_blend, dim3(grid_of(items(t, kind))), dim3(256), 0, st, item_src(t, kind), items(t, kind), g,
-                     table, yslot, values, mask, cls);
+  if (kind == MOE_VOXEL_SLOTS && per_leaf(g, kind)) {
+    if (t.n_leaf == 0) return;
+    hipLaunchKernelGGL(k_moe_blend_slots_leaf, dim3((unsigned)((t.n_leaf + 3) / 4)), dim3(256), 0, st, t.leaf_o.p,
+                       t.n_leaf, g, table, yslot, mask);
+  } else {
+    hipLaunchKernelGGL(k_moe_blend, dim3(grid_of(items(t, kind))), dim3(256), 0, st, item_src(t, kind), items(t, kind),
+                       g, table, yslot, values, mask, cls);
+  }
   NVDB_HIP(hipGetLastError());
 }
 
