@@ -363,3 +363,46 @@ def test_tree_subdomain_with_tiles(gpu_lib, fog, grid):
     assert n_tiles > len(ot["tile_value"])  # tiles in the overlaps belong to several experts
     if origin != (0, 0, 0):
         assert n_cut > 0
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_fit_tile_experts_equals_sequential_fits(gpu_lib, fog, prec):
+    """Tile value regressors of the experts of a tree with active tiles (Sec. 3.3.1
+    under Sec. 3.4), fitted together in shared launches, end bit-identical to the
+    same fits run one after the other, with the same losses; then their blended
+    decode equals the oracle's blend of the fitted parameters."""
+    tr, ot = fog
+    origin, size, halo = (0, 0, 0), 64, 8
+    cells = gpu_lib.subdomain_cells(tr, origin, size, halo)
+    subs = [tr.subdomain(origin, size, halo, c) for c in cells]
+    keep = [i for i, s_ in enumerate(subs) if s_.info().n_tiles > 0]
+    assert len(keep) == len(cells) == 8
+    p = gpu_lib.FP32 if prec == "fp32" else gpu_lib.BF16
+    W, H, m = 64, 3, 18
+    B = workloads.pe_matrix(6)
+
+    def experts():
+        out = []
+        for k, c in enumerate(cells):
+            lo, D = gpu_lib.subdomain_box(origin, size, halo, c)
+            md = gpu_lib.Model({3: (W, H, m, 1)}, precision=p, domain_lo=lo, domain_size=D, value_scale=1.0)
+            md.set_params(3, workloads.init_params(2 * m, W, H, 1, seed=700 + k))
+            md.set_encoding(3, B)
+            out.append(md)
+        return out
+    a, b = experts(), experts()
+    la = np.stack([md.fit(t, steps=20, batch=2048, nets_mask=8, seed=5)[3] for md, t in zip(a, subs)])
+    lb = gpu_lib.fit_experts(b, subs, steps=20, batch=2048, nets_mask=8, seed=5, return_losses=True)[:, 3]
+    for ma, mb in zip(a, b):
+        assert np.array_equal(ma.get_params(3).view(np.uint32), mb.get_params(3).view(np.uint32))
+    assert np.array_equal(la, lb) and np.all(np.isfinite(lb))
+    shapes = mlp.layer_shapes(2 * m, W, H, 1)
+    ex = []
+    for c, md in zip(cells, b):
+        lo, D = gpu_lib.subdomain_box(origin, size, halo, c)
+        ex.append(dict(cell=c, theta=md.get_params(3).astype(np.float64), shapes=shapes, B=B.astype(np.float64),
+                       lo=lo, D=D, scale=1.0))
+    got = gpu_lib.decode_moe_tiles(b, cells, origin, size, halo, tr).cpu().numpy().astype(np.float64)
+    want = moe.decode_moe_tiles(ot["tile_origin"], ex, origin, size, halo)
+    tol = 3e-5 if p == gpu_lib.FP32 else 3e-3
+    assert np.all(np.abs(got - want) <= tol * (1 + np.abs(want))), np.abs(got - want).max()
